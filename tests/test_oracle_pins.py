@@ -1,0 +1,248 @@
+"""Pins of the classical-Ewald oracle against values fixed by the mathematics.
+
+Each test targets a different part of the oracle so that a plausible mistake
+(a dropped term, a wrong sign or factor, a transposed operand) fails one of
+them:
+
+* rock-salt / CsCl Madelung constants: charge path, the 1/2 convention,
+  real + reciprocal + self terms;
+* one charge in a cubic box: the neutralising background term;
+* one dipole per cubic cell: dipole operator sign and the tin-foil boundary;
+* independence of the splitting parameter: consistency of the real,
+  reciprocal and self terms for dipoles and quadrupoles;
+* dipoles and quadrupoles as limits of charge clusters: the normalisation of
+  mu . grad and Theta : grad grad (no 1/2 or 1/3 factor);
+* brute-force cube sums on tiny cells: the summation convention of eq. (1);
+* finite differences: forces -dE/dx and fields dE/dmu;
+* derivative tensors: rank n+1 equals the gradient of rank n.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import brute
+
+EPS = 1e-14
+
+
+def _rand_system(seed, n=24, edge=9.0, neutral=True, with_mu=True, with_theta=True):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(-0.5 * edge, 0.5 * edge, (n, 3))
+    q = rng.normal(size=n)
+    if neutral:
+        q -= q.mean()
+    mu = 0.3 * rng.normal(size=(n, 3)) if with_mu else None
+    th = synth.random_traceless_theta(rng, n, 0.2) if with_theta else None
+    return pos, q, mu, th, edge
+
+
+@pytest.mark.parametrize("ncell", [1, 2])
+def test_nacl_madelung(oracle_lib, ncell):
+    # conventional cell of edge a = 2 (nearest-neighbour distance 1) holds 4 ion pairs:
+    # E = -4 n^3 M, M = 1.747564594633 (rock salt)
+    d = synth.nacl_conventional(ncell, 2.0)
+    e = oracle_lib.ewald(d["pos"], d["q"], edge=d["edge"], eps=EPS, grad=False)["energy"]
+    assert e == pytest.approx(-4 * ncell ** 3 * 1.747564594633, rel=1e-11)
+
+
+def test_cscl_madelung(oracle_lib):
+    # CsCl: ions at the corner and body centre of a cube of edge a; nearest distance a sqrt(3)/2;
+    # E per ion pair = -M / r0 with M = 1.762674773
+    a = 2.0
+    pos = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]]) * a - 0.3
+    q = np.array([1.0, -1.0])
+    e = oracle_lib.ewald(pos, q, edge=a, eps=EPS, grad=False)["energy"]
+    r0 = a * math.sqrt(3) / 2
+    assert e == pytest.approx(-1.762674773 / r0, rel=1e-9)
+
+
+def test_single_charge_background(oracle_lib):
+    # simple-cubic lattice of unit charges in a neutralising background:
+    # E = q^2 xi_sc / (2 L) with xi_sc = -2.837297479
+    for edge in (10.0, 3.7):
+        for alpha in (0.3, 0.8):
+            e = oracle_lib.ewald(np.zeros((1, 3)), np.ones(1), edge=edge, eps=EPS, alpha=alpha / edge * 10,
+                                 grad=False)["energy"]
+            assert e == pytest.approx(-2.837297479 / (2 * edge), rel=1e-9)
+
+
+def test_dipole_lattice(oracle_lib):
+    # one dipole per cubic cell, tin-foil boundary: E = -2 pi |mu|^2 / (3 V)
+    mu = np.array([[0.3, -0.2, 0.5]])
+    edge = 7.0
+    e = oracle_lib.ewald(np.zeros((1, 3)), np.zeros(1), mu=mu, edge=edge, eps=EPS, grad=False)["energy"]
+    assert e == pytest.approx(-2 * math.pi * np.sum(mu ** 2) / (3 * edge ** 3), rel=1e-11)
+
+
+@pytest.mark.parametrize("neutral", [True, False])
+def test_alpha_independence(oracle_lib, neutral):
+    pos, q, mu, th, edge = _rand_system(11, neutral=neutral)
+    es = []
+    for a in (0.35, 0.5, 0.75):
+        o = oracle_lib.ewald(pos, q, mu, th, edge=edge, eps=EPS, alpha=a, grad=False)
+        es.append(o["energy"])
+    es = np.array(es)
+    assert np.max(np.abs(es - es[0])) <= 1e-12 * abs(es[0])
+
+
+def test_translation_invariance(oracle_lib):
+    pos, q, mu, th, edge = _rand_system(12)
+    e0 = oracle_lib.ewald(pos, q, mu, th, edge=edge, eps=EPS, grad=False)["energy"]
+    shift = np.array([1.234, -3.21, 7.7])
+    e1 = oracle_lib.ewald(pos + shift, q, mu, th, edge=edge, eps=EPS, grad=False)["energy"]
+    assert e1 == pytest.approx(e0, rel=1e-13)
+
+
+def _subtract_intra(posc, qc, groups):
+    e = 0.0
+    for g in groups:
+        for a in range(len(g)):
+            for b in range(a + 1, len(g)):
+                i, j = g[a], g[b]
+                e += qc[i] * qc[j] / np.linalg.norm(posc[i] - posc[j])
+    return e
+
+
+def _dipole_clusters(pos, q, mu, d):
+    P, Q, groups = [], [], []
+    for i in range(len(q)):
+        g = [len(Q)]
+        P.append(pos[i]); Q.append(q[i])
+        m = np.linalg.norm(mu[i])
+        u = mu[i] / m
+        for s in (+1, -1):
+            g.append(len(Q))
+            P.append(pos[i] + s * 0.5 * d * u)
+            Q.append(s * m / d)
+        groups.append(g)
+    return np.array(P), np.array(Q), groups
+
+
+def _quad_clusters(pos, q, th, d):
+    P, Q, groups = [], [], []
+    for i in range(len(q)):
+        T = np.array([[th[i, 0], th[i, 1], th[i, 2]],
+                      [th[i, 1], th[i, 3], th[i, 4]],
+                      [th[i, 2], th[i, 4], th[i, 5]]])
+        lam, vec = np.linalg.eigh(T)
+        g = [len(Q)]
+        P.append(pos[i]); Q.append(q[i])
+        for k in range(3):
+            for s in (+1, -1):
+                g.append(len(Q))
+                P.append(pos[i] + s * d * vec[:, k])
+                Q.append(lam[k] / d ** 2)
+        groups.append(g)
+    return np.array(P), np.array(Q), groups
+
+
+def _richardson(f, d, levels=2):
+    # E(d) = E0 + c1 d^2 + c2 d^4 + ...: eliminate the first levels-1 even powers
+    vals = [f(d / 2 ** k) for k in range(levels)]
+    for j in range(1, levels):
+        vals = [(4 ** j * vals[k + 1] - vals[k]) / (4 ** j - 1) for k in range(len(vals) - 1)]
+    return vals[0]
+
+
+def test_dipole_is_charge_pair_limit(oracle_lib):
+    pos, q, mu, _, edge = _rand_system(13, n=6, with_theta=False)
+    ref = oracle_lib.ewald(pos, q, mu, None, edge=edge, eps=EPS, grad=False)["energy"]
+
+    def e_of(d):
+        P, Q, groups = _dipole_clusters(pos, q, mu, d)
+        e = oracle_lib.ewald(P, Q, edge=edge, eps=EPS, alpha=0.5, grad=False)["energy"]
+        return e - _subtract_intra(P, Q, groups)
+
+    est = _richardson(e_of, 0.02)
+    assert est == pytest.approx(ref, rel=2e-8)
+
+
+def test_quadrupole_is_charge_cluster_limit(oracle_lib):
+    pos, q, _, th, edge = _rand_system(14, n=5, with_mu=False)
+    ref = oracle_lib.ewald(pos, q, None, th, edge=edge, eps=EPS, grad=False)["energy"]
+
+    def e_of(d):
+        P, Q, groups = _quad_clusters(pos, q, th, d)
+        e = oracle_lib.ewald(P, Q, edge=edge, eps=EPS, alpha=0.5, grad=False)["energy"]
+        return e - _subtract_intra(P, Q, groups)
+
+    # a wrong normalisation (a 1/2 or 1/3 factor) would be an O(1) error
+    est = _richardson(e_of, 0.08, levels=3)
+    assert est == pytest.approx(ref, rel=1e-6)
+
+
+def test_brute_cube_sum_neutral_symmetric(oracle_lib):
+    # inversion-symmetric neutral cell: zero dipole, cube limit = tin-foil value
+    rng = np.random.default_rng(5)
+    h = rng.uniform(-2, 2, (3, 3))
+    qh = np.array([1.0, -0.6, -0.4])
+    pos = np.concatenate([h, -h])
+    q = np.concatenate([qh, qh])
+    e = oracle_lib.ewald(pos, q, edge=5.0, eps=EPS, grad=False)["energy"]
+    assert brute.cube_limit(pos, q, 5.0) == pytest.approx(e, rel=1e-10)
+
+
+def test_brute_cube_sum_with_dipole_moment(oracle_lib):
+    rng = np.random.default_rng(6)
+    pos = rng.uniform(-2, 2, (4, 3))
+    q = np.array([1.0, -1.0, 0.5, -0.5])
+    M = (q[:, None] * pos).sum(0)
+    edge = 5.0
+    e = oracle_lib.ewald(pos, q, edge=edge, eps=EPS, grad=False)["energy"]
+    cube = brute.cube_limit(pos, q, edge)
+    assert cube == pytest.approx(e + 2 * math.pi * np.sum(M ** 2) / (3 * edge ** 3), rel=1e-10)
+
+
+def test_forces_fields_finite_difference(oracle_lib):
+    pos, q, mu, th, edge = _rand_system(15, n=16)
+    o = oracle_lib.ewald(pos, q, mu, th, edge=edge, eps=EPS, alpha=0.45)
+    h = 1e-5
+    for i in (0, 7):
+        for d in range(3):
+            p1, p2 = pos.copy(), pos.copy()
+            p1[i, d] += h
+            p2[i, d] -= h
+            e1 = oracle_lib.ewald(p1, q, mu, th, edge=edge, eps=EPS, alpha=0.45, grad=False)["energy"]
+            e2 = oracle_lib.ewald(p2, q, mu, th, edge=edge, eps=EPS, alpha=0.45, grad=False)["energy"]
+            assert -(e1 - e2) / (2 * h) == pytest.approx(o["forces"][i, d], rel=1e-7, abs=1e-9)
+            m1, m2 = mu.copy(), mu.copy()
+            m1[i, d] += h
+            m2[i, d] -= h
+            e1 = oracle_lib.ewald(pos, q, m1, th, edge=edge, eps=EPS, alpha=0.45, grad=False)["energy"]
+            e2 = oracle_lib.ewald(pos, q, m2, th, edge=edge, eps=EPS, alpha=0.45, grad=False)["energy"]
+            assert (e1 - e2) / (2 * h) == pytest.approx(o["dEdmu"][i, d], rel=1e-7, abs=1e-9)
+
+
+def test_sites_match_full(oracle_lib):
+    pos, q, mu, th, edge = _rand_system(16, n=30)
+    full = oracle_lib.ewald(pos, q, mu, th, edge=edge, eps=EPS)
+    sel = np.array([3, 17, 29])
+    part = oracle_lib.ewald_sites(pos, q, mu, th, edge, sel, eps=EPS)
+    np.testing.assert_allclose(part["forces"], full["forces"][sel], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(part["dEdmu"], full["dEdmu"][sel], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_derivative_tensors(oracle_lib, n):
+    r = np.array([0.7, -0.4, 1.1])
+    a = 0.6
+    h = 1e-5
+    Tn = oracle_lib.dtensor(r, a, n)
+    for e in range(3):
+        rp, rm = r.copy(), r.copy()
+        rp[e] += h
+        rm[e] -= h
+        fd = (oracle_lib.dtensor(rp, a, n - 1) - oracle_lib.dtensor(rm, a, n - 1)) / (2 * h)
+        np.testing.assert_allclose(Tn[..., e], fd, rtol=1e-6, atol=1e-8)
+    # symmetric in all indices
+    if n >= 2:
+        np.testing.assert_allclose(Tn, np.swapaxes(Tn, 0, 1), rtol=1e-14, atol=1e-15)
+    # traceless away from the origin for the pure 1/r part is not expected for erfc; check the
+    # zero-alpha limit instead: T_ab of 1/r is (3 r_a r_b - r^2 delta_ab)/r^5
+    if n == 2:
+        T = oracle_lib.dtensor(r, 1e-9, 2)
+        r2 = r @ r
+        ref = (3 * np.outer(r, r) - r2 * np.eye(3)) / r2 ** 2.5
+        np.testing.assert_allclose(T, ref, rtol=1e-7)
