@@ -1,0 +1,172 @@
+/*
+ * ankh.h - C ABI of the MI355X interpolated-Ewald library (ANKH-FMM hot path).
+ *
+ * The library evaluates the periodic electrostatic energy of point charges,
+ * dipoles and quadrupoles in a cubic box,
+ *
+ *     E = 1/2 sum_t sum_x sum_y D_x D_y 1/|x - y + t|,
+ *     D_u = q_u + mu_u . grad + Theta_u : grad grad,            (paper, eq. 1)
+ *
+ * (the x = y, t = 0 term omitted, tin-foil boundary), by the interpolated
+ * Ewald strategy of the paper's ANKH-FMM section: with a small splitting
+ * parameter xi the reciprocal Ewald term is negligible and the real-space
+ * kernel H = erfc(xi r)/r (eq. for H) is summed over a truncated cube of
+ * images.  That sum is split over the leaves of a perfect octree into a near
+ * field (direct pair sums between adjacent leaves) and a far field handled by
+ * Chebyshev interpolation: modified charges at the leaves (Alg. 2), upward
+ * M2M, M2L over the interaction lists of every level (cells of the adjacent
+ * images included), one root operator for all farther images (periodicity
+ * section), then the self energy (eq. for E_self) and, for non-neutral
+ * cells, the neutralising background.  Forces and fields come from the
+ * adjoint of the same approximation (L2L, L2P, pair gradients).
+ *
+ * Units: Angstrom and elementary charge, Coulomb constant 1 (eq. 1 carries no
+ * prefactor); energies in e^2/Angstrom.
+ *
+ * Memory: every array argument of ankh_energy / ankh_energy_forces is a
+ * DEVICE pointer (HIP global memory, e.g. a PyTorch ROCm tensor), row-major
+ * float64, owned by the caller and never modified.  The plan owns all its
+ * internal buffers (sorted particle data, multipole and local expansions,
+ * operator tables) and frees them in ankh_destroy.
+ *
+ * Streams: all work of a plan is enqueued on the HIP stream given to
+ * ankh_plan (NULL = the default stream) and is asynchronous; outputs are
+ * valid after that stream is synchronised or after ankh_sync.  A plan is not
+ * thread-safe; use one plan per stream.
+ *
+ * Errors: host-checkable errors return at once with outputs untouched.
+ * Device-detected input errors (non-finite positions or moments, Theta not
+ * traceless) are latched in the plan and returned by ankh_sync.  No C++
+ * exception crosses this interface.
+ */
+#ifndef ANKH_H
+#define ANKH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ankh_plan_s *ankh_plan_t;
+
+typedef enum {
+    ANKH_OK = 0,
+    ANKH_ERR_INVALID_ARG = 1,          /* null pointer, n mismatch, box_radius <= 0, accuracy out of range ... */
+    ANKH_ERR_NONFINITE_INPUT = 2,      /* latched: NaN/Inf in positions or moments */
+    ANKH_ERR_THETA_NOT_TRACELESS = 3,  /* latched: |trace Theta| > 1e-6 (max |Theta_ii| + 1) */
+    ANKH_ERR_LEAF_OVERFLOW = 4,        /* reserved: no kernel has a per-leaf capacity limit */
+    ANKH_ERR_ACCURACY_UNREACHABLE = 5, /* plan: accuracy below what the precision mode can reach */
+    ANKH_ERR_OUT_OF_MEMORY = 6,        /* plan: device allocation failed */
+    ANKH_ERR_HIP = 7                   /* a HIP runtime call failed */
+} ankh_status;
+
+typedef enum {
+    ANKH_FP64 = 0,  /* every stage in float64 */
+    ANKH_MIXED = 1  /* near-field pair terms and the far-field contraction in float32;
+                       pair separations, self/background terms, moments, and every
+                       reduction in float64 */
+} ankh_precision;
+
+/* Optional overrides of the planner's choices: depth < 0 and any other field <= 0 mean "auto". */
+typedef struct {
+    int32_t depth;   /* octree depth E (leaves per axis 2^E), 0..7; NEGATIVE = auto (0 forces depth 0) */
+    int32_t order;   /* Chebyshev interpolation order L per axis, 2..10 */
+    int32_t images;  /* image radius p: images I with |I|_inf <= p are summed */
+    double xi;       /* Ewald splitting parameter (1/Angstrom) */
+} ankh_overrides;
+
+typedef struct {
+    int64_t n_atoms;
+    int32_t depth, order, images, max_order, precision;
+    double xi, box_radius, rel_accuracy;
+    double plan_ms;            /* wall time of ankh_plan (operator tables included) */
+    int64_t workspace_bytes;   /* device memory owned by the plan */
+    double m2l_flops;          /* algorithmic M2L flops per evaluation (2 * 189 * n_u^2 per cell) */
+    int64_t near_pairs;        /* ordered near-field pairs of the last evaluation (-1 if unknown) */
+    /* per-stage device time of the last evaluation in ms (hipEvent), valid when
+       timing is enabled with ankh_set_timing; -1 otherwise.
+       Stages: 0 bin+sort, 1 gather, 2 p2m, 3 m2m, 4 m2l, 5 periodic root,
+               6 l2l, 7 l2p, 8 p2p, 9 reduce + unpermute */
+    double stage_ms[10];
+} ankh_plan_stats;
+
+/*
+ * ankh_plan: choose parameters and precompute the operator tables for a box.
+ *   out           receives the plan handle (host pointer, not NULL).
+ *   n_atoms       number of atoms of every later call (>= 1).
+ *   box_radius    r_B, half the cubic box edge (Angstrom, > 0); the box is
+ *                 [-r_B, r_B)^3 and positions anywhere are wrapped into it.
+ *   rel_accuracy  target relative accuracy of the energy, in [1e-12, 1e-2]:
+ *                 sets xi (reciprocal term below the target), the image
+ *                 radius p and the interpolation order L (convergence in L
+ *                 is geometric, numerical-results section).
+ *   max_order     0 charges, 1 + dipoles, 2 + quadrupoles; later calls may
+ *                 pass NULL for the moments above this order.
+ *   precision     an ankh_precision value.
+ *   ov            NULL or overrides of depth / order / images / xi.
+ *   hip_stream    hipStream_t (as void *) all work is enqueued on; NULL = default.
+ * Precompute (the M2L matrices of every level and the root operator of the
+ * far images, which depend only on the box, as the periodicity section notes)
+ * runs on the device, synchronously.
+ */
+ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, double rel_accuracy,
+                      int32_t max_order, int32_t precision, const ankh_overrides *ov, void *hip_stream);
+
+/*
+ * ankh_energy: the energy only (paper, Alg. 3).
+ *   pos    [n][3]  positions (device, float64).
+ *   q      [n]     charges.
+ *   mu     [n][3]  dipoles, or NULL (treated as 0); required if max_order >= 1 was planned
+ *                  and ignored (must be NULL) if max_order == 0.
+ *   theta  [n][6]  traceless symmetric quadrupoles as (xx, xy, xz, yy, yz, zz), used
+ *                  literally in Theta : grad grad (no 1/2 or 1/3 factor), or NULL.
+ *   energy [1]     device output.
+ */
+ankh_status ankh_energy(ankh_plan_t plan, const double *pos, const double *q, const double *mu,
+                        const double *theta, double *energy);
+
+/*
+ * ankh_energy_forces: energy, forces F_i = -dE/dx_i and fields dE/dmu_i of the
+ * same approximation (the exact gradient of the approximate energy).
+ *   forces [n][3]  device output, not NULL.
+ *   dE_dmu [n][3]  device output or NULL; zeros when no dipoles are passed.
+ */
+ankh_status ankh_energy_forces(ankh_plan_t plan, const double *pos, const double *q, const double *mu,
+                               const double *theta, double *energy, double *forces, double *dE_dmu);
+
+/* Waits for the plan's stream; returns the first latched device-side input error, then clears it. */
+ankh_status ankh_sync(ankh_plan_t plan);
+
+/* Copies the plan's parameters and statistics (synchronises the plan's stream). */
+ankh_status ankh_get_stats(ankh_plan_t plan, ankh_plan_stats *out);
+
+/* Enables (1) or disables (0) per-stage hipEvent timing of later evaluations. */
+ankh_status ankh_set_timing(ankh_plan_t plan, int32_t enable);
+
+/*
+ * Energy terms of the last evaluation, copied to host memory (synchronises):
+ * out[0] near field, [1] far field of the octree levels, [2] far periodic
+ * images (root operator), [3] self, [4] background, [5] total, [6] total charge.
+ */
+ankh_status ankh_last_terms(ankh_plan_t plan, double *out_host);
+
+/*
+ * Copies the leaf-level modified charges of the last evaluation to host
+ * memory: out_host receives 8^E * L^3 doubles, leaf (i, j, k) at row
+ * (i * 2^E + j) * 2^E + k, node (a, b, c) at column (a * L + b) * L + c.
+ * `count` is the capacity of out_host in doubles.
+ */
+ankh_status ankh_leaf_multipoles(ankh_plan_t plan, double *out_host, int64_t count);
+
+/* Frees the plan (waits for its stream first). NULL is ignored. */
+void ankh_destroy(ankh_plan_t plan);
+
+/* Static description of a status code. */
+const char *ankh_status_string(ankh_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ANKH_H */

@@ -48,6 +48,9 @@ def lib():
         L.oracle_ewald_sites.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int64, i64p,
                                          dp, dp]
+        L.oracle_near_field.restype = ctypes.c_int
+        L.oracle_near_field.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int, ctypes.c_int, dp, dp, dp]
         L.oracle_dtensor.restype = ctypes.c_int
         L.oracle_dtensor.argtypes = [dp, ctypes.c_double, ctypes.c_int, dp]
         _lib = L

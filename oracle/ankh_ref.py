@@ -1,0 +1,323 @@
+"""Plain NumPy transcription of the ANKH-FMM evaluation (test infrastructure only).
+
+Follows the paper's steps in its order and notation, with no blocking or
+fusion: tree (perfect octree of depth E), modified charges Q_s by Alg. 2
+(Chebyshev basis S = H T, derivatives S^(n) = H D^n T), upward M2M, far field
+by M2L over the interaction lists of every level including the cells of the
+adjacent periodic images, far periodic images through one root operator,
+near field by direct pair sums over adjacent leaves, self energy and the
+neutralising background.  Forces and fields follow from the adjoint
+(L2L = M2M^T, L2P = P2M^T, gradients of the pair terms).
+
+Readings of the paper taken here (each also listed in the design notes):
+* Chebyshev nodes r_k = cos((2k+1) pi / (2L)), k = 0..L-1 (the printed node
+  formula lacks pi and mixes index bases).
+* The differentiation matrix D with T' = D T is strictly lower triangular:
+  T'_n = 2n sum_{j<n, n-j odd} T_j / c_j, c_0 = 2, c_j = 1 otherwise.
+* S^(n)(y) = (2/w)^n H D^n T(y_hat), y_hat = (y - ctr)/(w/2); the loop of
+  Alg. 2 takes S^(0) = H T before the first application of D.
+* Theta enters D_y = q + mu.grad + Theta:grad grad literally; off-diagonal
+  terms therefore appear twice (as Alg. 2 does).
+* The root (far image) operator C_per = sum over images I in Z_p with
+  |I|_inf >= 2 of the root-to-image M2L matrix, built directly on the root's
+  Chebyshev grid (the equispaced grid and FFT of the periodicity section only
+  accelerate the same sum).
+* E_rec is dropped (small xi); the background -pi Q^2/(2 V xi^2) is added for
+  non-neutral cells.
+
+The near-field pair sums use the pinned pair routine of `ewald.c`
+(`oracle_near_field`).  Parameters (depth E, order L, xi, image radius p) are
+inputs: this module chooses nothing.
+"""
+from __future__ import annotations
+
+import ctypes
+import itertools
+import math
+
+import numpy as np
+from scipy.special import erfc
+
+from . import lib as _oracle_lib, _p, _c64
+
+
+# ---- 1D Chebyshev tools (ANKH-FMM numerical differentiation section) --------
+
+def cheb_nodes(L: int) -> np.ndarray:
+    k = np.arange(L)
+    return np.cos((2 * k + 1) * np.pi / (2 * L))
+
+
+def cheb_T(x, L: int) -> np.ndarray:
+    """T_0..T_{L-1} at x by the three-term recurrence; shape x.shape + (L,)."""
+    x = np.asarray(x, dtype=np.float64)
+    T = np.empty(x.shape + (L,))
+    T[..., 0] = 1.0
+    if L > 1:
+        T[..., 1] = x
+    for m in range(2, L):
+        T[..., m] = 2 * x * T[..., m - 1] - T[..., m - 2]
+    return T
+
+
+def cheb_H(L: int) -> np.ndarray:
+    """H[k, m] = (1/L) (1 if m = 0 else 2 T_m(r_k)), so that S(x) = H T(x)."""
+    Tr = cheb_T(cheb_nodes(L), L)
+    H = 2.0 * Tr / L
+    H[:, 0] = 1.0 / L
+    return H
+
+
+def cheb_D(L: int) -> np.ndarray:
+    """T'(x) = D T(x)."""
+    D = np.zeros((L, L))
+    for n in range(1, L):
+        for j in range(n):
+            if (n - j) % 2 == 1:
+                D[n, j] = 2.0 * n / (2.0 if j == 0 else 1.0)
+    return D
+
+
+def lagrange_derivs(xhat, L: int, nmax: int, h: float) -> np.ndarray:
+    """S^(n)_k at scaled coordinates xhat for n = 0..nmax, with physical
+    scaling (1/h)^n; shape xhat.shape + (nmax+1, L)."""
+    H, D = cheb_H(L), cheb_D(L)
+    T = cheb_T(xhat, L)
+    out = np.empty(np.shape(xhat) + (nmax + 1, L))
+    Tn = T
+    for n in range(nmax + 1):
+        out[..., n, :] = (Tn @ H.T) / h ** n
+        Tn = Tn @ D.T
+    return out
+
+
+# ---- kernel ------------------------------------------------------------------
+
+def kernel_H(r, xi: float) -> np.ndarray:
+    r = np.asarray(r, dtype=np.float64)
+    return erfc(xi * r) / r
+
+
+# ---- tree --------------------------------------------------------------------
+
+def wrap(pos, edge):
+    r = 0.5 * edge
+    out = pos - edge * np.floor((pos + r) / edge)
+    out[out >= r] -= edge
+    return out
+
+
+def leaf_index(pos_wrapped, edge, depth):
+    n = 1 << depth
+    w = edge / n
+    ijk = np.floor((pos_wrapped + 0.5 * edge) / w).astype(np.int64)
+    return np.clip(ijk, 0, n - 1)
+
+
+# ---- operators ---------------------------------------------------------------
+
+def nodes3d(L: int) -> np.ndarray:
+    r = cheb_nodes(L)
+    g = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1)
+    return g.reshape(-1, 3)
+
+
+def m2m_1d(L: int):
+    """V[b][a, i] = S_a(child node i in parent coordinates), b = 0 low, 1 high child."""
+    r = cheb_nodes(L)
+    H = cheb_H(L)
+    lo = cheb_T((r - 1) / 2, L) @ H.T     # [i, a]
+    hi = cheb_T((r + 1) / 2, L) @ H.T
+    return [lo.T.copy(), hi.T.copy()]
+
+
+def interaction_offsets():
+    return [d for d in itertools.product(range(-3, 4), repeat=3) if max(abs(c) for c in d) >= 2]
+
+
+def m2l_matrix(d, w: float, L: int, xi: float) -> np.ndarray:
+    """C[t, s]_{kl} = H(x_k^t, y_l^s) for the source cell at offset d (cells of width w)."""
+    g = nodes3d(L)
+    diff = 0.5 * w * (g[:, None, :] - g[None, :, :]) - w * np.asarray(d, dtype=np.float64)
+    return kernel_H(np.sqrt(np.sum(diff * diff, axis=-1)), xi)
+
+
+def periodic_root_matrix(edge: float, L: int, xi: float, p: int) -> np.ndarray:
+    """sum over images I in Z_p with |I|_inf >= 2 of H(x_k - x_l - edge I) on the root grid."""
+    g = nodes3d(L) * (0.5 * edge)
+    base = g[:, None, :] - g[None, :, :]
+    C = np.zeros((len(g), len(g)))
+    for I in itertools.product(range(-p, p + 1), repeat=3):
+        if max(abs(c) for c in I) < 2:
+            continue
+        diff = base - edge * np.asarray(I, dtype=np.float64)
+        C += kernel_H(np.sqrt(np.sum(diff * diff, axis=-1)), xi)
+    return C
+
+
+def _valid_mask(n, d):
+    idx = np.arange(n)
+    masks = []
+    for c in d:
+        even = idx % 2 == 0
+        m = np.ones(n, dtype=bool)
+        if c == 3:
+            m = even
+        elif c == -3:
+            m = ~even
+        masks.append(m)
+    return masks[0][:, None, None] & masks[1][None, :, None] & masks[2][None, None, :]
+
+
+# ---- evaluation --------------------------------------------------------------
+
+def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, p: int,
+             grad: bool = True, nthreads: int = 0, keep: bool = False) -> dict:
+    pos = wrap(_c64(pos, (-1, 3)), edge)
+    N = pos.shape[0]
+    q = _c64(q, (N,))
+    mu = _c64(mu, (N, 3))
+    theta = _c64(theta, (N, 6))
+    L = order
+    nu = L ** 3
+    E = depth
+    nleaf_ax = 1 << E
+    w_leaf = edge / nleaf_ax
+    h = 0.5 * w_leaf
+
+    # step 1: tree
+    ijk = leaf_index(pos, edge, E)
+    leaf = (ijk[:, 0] * nleaf_ax + ijk[:, 1]) * nleaf_ax + ijk[:, 2]
+    ctr = -0.5 * edge + (ijk + 0.5) * w_leaf
+    yhat = (pos - ctr) / h
+
+    # step 2: modified charges (Alg. 2), derivatives up to 2 (3 for forces)
+    nd = 3 if grad else 2
+    S = lagrange_derivs(yhat, L, nd, h)          # [N, 3, nd+1, L]
+    Sx, Sy, Sz = S[:, 0], S[:, 1], S[:, 2]
+
+    def tens(a, b, c):
+        return np.einsum("ni,nj,nk->nijk", Sx[:, a], Sy[:, b], Sz[:, c])
+
+    contrib = q[:, None, None, None] * tens(0, 0, 0)
+    if mu is not None:
+        contrib += mu[:, 0, None, None, None] * tens(1, 0, 0)
+        contrib += mu[:, 1, None, None, None] * tens(0, 1, 0)
+        contrib += mu[:, 2, None, None, None] * tens(0, 0, 1)
+    if theta is not None:
+        xx, xy, xz, yy, yz, zz = [theta[:, c, None, None, None] for c in range(6)]
+        contrib += xx * tens(2, 0, 0) + 2 * xy * tens(1, 1, 0) + 2 * xz * tens(1, 0, 1)
+        contrib += yy * tens(0, 2, 0) + 2 * yz * tens(0, 1, 1) + zz * tens(0, 0, 2)
+    Q = np.zeros((nleaf_ax ** 3, L, L, L))
+    np.add.at(Q, leaf, contrib)
+
+    # upward pass (M2M) to the root
+    V = m2m_1d(L)
+    M = [None] * (E + 1)
+    M[E] = Q.reshape(nleaf_ax, nleaf_ax, nleaf_ax, nu)
+    for e in range(E - 1, -1, -1):
+        n = 1 << e
+        child = M[e + 1].reshape(n, 2, n, 2, n, 2, L, L, L)
+        par = np.zeros((n, n, n, L, L, L))
+        for bx, by, bz in itertools.product((0, 1), repeat=3):
+            par += np.einsum("ai,bj,ck,xyzijk->xyzabc", V[bx], V[by], V[bz],
+                             child[:, bx, :, by, :, bz])
+        M[e] = par.reshape(n, n, n, nu)
+
+    # far field by M2L on every level 1..E (cells of the adjacent images included)
+    offs = interaction_offsets()
+    Lloc = [None] * (E + 1)
+    e_far_levels = []
+    for e in range(1, E + 1):
+        n = 1 << e
+        w = edge / n
+        acc = np.zeros((n, n, n, nu))
+        for d in offs:
+            K = m2l_matrix(d, w, L, xi)
+            Ms = np.roll(M[e], shift=(-d[0], -d[1], -d[2]), axis=(0, 1, 2))
+            acc += _valid_mask(n, d)[..., None] * (Ms @ K.T)
+        Lloc[e] = acc
+        e_far_levels.append(0.5 * float(np.sum(M[e] * acc)))
+
+    # far periodic images through the root
+    Cper = periodic_root_matrix(edge, L, xi, p)
+    Lroot = M[0].reshape(nu) @ Cper.T
+    e_per = 0.5 * float(M[0].reshape(nu) @ Lroot)
+
+    # near field: direct pair sums over adjacent leaves
+    eatom = np.zeros(N)
+    Fn = np.zeros((N, 3)) if grad else None
+    Gn = np.zeros((N, 3)) if grad else None
+    rc = _oracle_lib().oracle_near_field(N, _p(pos), _p(q), _p(mu), _p(theta), float(edge), float(xi),
+                                         int(E), int(nthreads), _p(eatom), _p(Fn), _p(Gn))
+    if rc != 0:
+        raise ValueError("oracle_near_field failed")
+    e_near = float(np.sum(eatom))
+
+    # self energy and background
+    s = q * q
+    if mu is not None:
+        s = s + (2 * xi ** 2 / 3) * np.sum(mu * mu, axis=1)
+    if theta is not None:
+        tt = theta[:, 0] ** 2 + theta[:, 3] ** 2 + theta[:, 5] ** 2 + 2 * (
+            theta[:, 1] ** 2 + theta[:, 2] ** 2 + theta[:, 4] ** 2)
+        s = s + (8 * xi ** 4 / 5) * tt
+    e_self = float(-(xi / math.sqrt(math.pi)) * np.sum(s))
+    Qtot = float(np.sum(q))
+    e_bg = -math.pi * Qtot ** 2 / (2 * edge ** 3 * xi ** 2)
+
+    out = dict(energy=e_near + sum(e_far_levels) + e_per + e_self + e_bg, e_near=e_near,
+               e_far_levels=e_far_levels, e_per=e_per, e_self=e_self, e_bg=e_bg)
+
+    if grad:
+        # downward pass: L2L is the transpose of M2M
+        Lam = Lroot.reshape(1, 1, 1, nu)
+        for e in range(1, E + 1):
+            n = 1 << e
+            down = np.zeros((n, n, n, L, L, L))
+            par = Lam.reshape(n // 2, n // 2, n // 2, L, L, L)
+            dv = down.reshape(n // 2, 2, n // 2, 2, n // 2, 2, L, L, L)
+            for bx, by, bz in itertools.product((0, 1), repeat=3):
+                dv[:, bx, :, by, :, bz] += np.einsum("ai,bj,ck,xyzabc->xyzijk", V[bx], V[by], V[bz], par)
+            Lam = down.reshape(n, n, n, nu) + Lloc[e]
+        Lam_leaf = Lam.reshape(-1, L, L, L)[leaf]          # [N, L, L, L]
+        # L2P: derivatives of phi(y) = sum_k Lam_k S_k(y) up to order 3
+        phi = {}
+        for a in range(4):
+            for b in range(4 - a):
+                for c in range(4 - a - b):
+                    phi[(a, b, c)] = np.einsum("nijk,ni,nj,nk->n", Lam_leaf, Sx[:, a], Sy[:, b], Sz[:, c])
+
+        def dphi(*axes):
+            cnt = [0, 0, 0]
+            for ax in axes:
+                cnt[ax] += 1
+            return phi[tuple(cnt)]
+
+        Ff = np.zeros((N, 3))
+        Gf = np.zeros((N, 3))
+        Th = None
+        if theta is not None:
+            t = theta
+            Th = np.stack([np.stack([t[:, 0], t[:, 1], t[:, 2]], 1),
+                           np.stack([t[:, 1], t[:, 3], t[:, 4]], 1),
+                           np.stack([t[:, 2], t[:, 4], t[:, 5]], 1)], 1)
+        for x in range(3):
+            g = q * dphi(x)
+            if mu is not None:
+                for a in range(3):
+                    g = g + mu[:, a] * dphi(a, x)
+            if Th is not None:
+                for a in range(3):
+                    for b in range(3):
+                        g = g + Th[:, a, b] * dphi(a, b, x)
+            Ff[:, x] = -g
+            Gf[:, x] = dphi(x)
+        # equals sum(e_far_levels) + e_per: the leaf form of the same quadratic form
+        e_far_leaf = 0.5 * float(np.sum(Q.reshape(-1, nu) * Lam.reshape(-1, nu)))
+        Gs = np.zeros((N, 3)) if mu is None else -(4 * xi ** 3 / (3 * math.sqrt(math.pi))) * mu
+        out.update(forces=Fn + Ff, dEdmu=(Gn + Gf + Gs) if mu is not None else np.zeros((N, 3)),
+                   forces_near=Fn, forces_far=Ff, e_far_leaf=e_far_leaf)
+    if keep:
+        out.update(Q=Q, M=M, Lloc=Lloc, leaf=leaf, Cper=Cper)
+    return out

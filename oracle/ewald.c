@@ -592,3 +592,102 @@ int oracle_dtensor(const double r[3], double alpha, int n, double *out)
     memcpy(out, T[n], sizeof(double) * ipow3(n));
     return 0;
 }
+
+/*
+ * Near field of the interpolated Ewald method (the direct term N_real of the
+ * ANKH reformulation): for every atom i, the pair operator on erfc(xi r)/r
+ * summed over all atoms j of the 27 leaves adjacent to i's leaf in a perfect
+ * octree of depth `depth` (periodic, each neighbour leaf with its image
+ * shift), excluding j = i at zero shift.  Leaves: wrap x into [-L/2, L/2),
+ * leaf index clamp(floor((x + L/2) / w), 0, 2^depth - 1), w = L / 2^depth.
+ * eatom[i] = 1/2 sum_j pair energy; forces = -grad; dEdmu = field from the
+ * pairs (no self term).  Any output may be NULL.
+ */
+int oracle_near_field(int64_t n, const double *pos, const double *q, const double *mu, const double *theta,
+                      double edge, double xi, int depth, int nthreads,
+                      double *eatom, double *forces, double *dEdmu)
+{
+    if (n <= 0 || !pos || !q || edge <= 0 || xi <= 0 || depth < 0 || depth > 10) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    ctx_t c;
+    /* a cell list whose cells are the leaves: nc = 2^depth, R = 1, no cutoff */
+    ctx_init(&c, n, pos, q, mu, theta, edge, xi, edge, 0);
+    free(c.cell_start); free(c.cell_atoms);
+    const int nc = 1 << depth;
+    const double w = edge / nc;
+    const int ncell = nc * nc * nc;
+    int *cnt = (int *)calloc(ncell + 1, sizeof(int));
+    int *cid = (int *)malloc(sizeof(int) * n);
+    for (int64_t i = 0; i < n; i++) {
+        int ix[3];
+        for (int d = 0; d < 3; d++) {
+            int v = (int)floor((c.pos[3 * i + d] + 0.5 * edge) / w);
+            if (v < 0) v = 0;
+            if (v >= nc) v = nc - 1;
+            ix[d] = v;
+        }
+        cid[i] = (ix[0] * nc + ix[1]) * nc + ix[2];
+        cnt[cid[i] + 1]++;
+    }
+    for (int i = 0; i < ncell; i++) cnt[i + 1] += cnt[i];
+    int *atoms = (int *)malloc(sizeof(int) * n);
+    int *fill = (int *)malloc(sizeof(int) * ncell);
+    memcpy(fill, cnt, sizeof(int) * ncell);
+    for (int64_t i = 0; i < n; i++) atoms[fill[cid[i]]++] = (int)i;
+    free(fill);
+    const int want_grad = (forces || dEdmu) ? 1 : 0;
+    int nmax = 2 * c.order + (want_grad ? 1 : 0);
+    if (nmax < 1) nmax = 1;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < n; i++) {
+        double B[MAXRANK + 2];
+        static __thread double T[MAXRANK + 1][NTUPLE5];
+        const double *xi_ = c.pos + 3 * i;
+        const double *mi = c.mu ? c.mu + 3 * i : NULL;
+        const double *Ti = c.Th ? c.Th + 9 * i : NULL;
+        int li = cid[i];
+        int ci[3] = {li / (nc * nc), (li / nc) % nc, li % nc};
+        double e = 0, f[3] = {0, 0, 0}, g[3] = {0, 0, 0};
+        for (int dx = -1; dx <= 1; dx++)
+        for (int dy = -1; dy <= 1; dy++)
+        for (int dz = -1; dz <= 1; dz++) {
+            int u[3] = {ci[0] + dx, ci[1] + dy, ci[2] + dz}, wv[3];
+            double sh[3];
+            for (int d = 0; d < 3; d++) {
+                int m = (int)floor((double)u[d] / nc);
+                wv[d] = u[d] - m * nc;
+                sh[d] = m * edge;
+            }
+            int cell = (wv[0] * nc + wv[1]) * nc + wv[2];
+            for (int p = cnt[cell]; p < cnt[cell + 1]; p++) {
+                int j = atoms[p];
+                if (j == i && sh[0] == 0 && sh[1] == 0 && sh[2] == 0) continue;
+                double r[3];
+                for (int d = 0; d < 3; d++) r[d] = xi_[d] - (c.pos[3 * j + d] + sh[d]);
+                double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                radial(r2, xi, nmax, B);
+                dtensors(r, B, nmax, T);
+                const double *mj = c.mu ? c.mu + 3 * j : NULL;
+                const double *Tj = c.Th ? c.Th + 9 * j : NULL;
+                e += 0.5 * pair_phi(T, -1, q[i], mi, Ti, q[j], mj, Tj);
+                if (want_grad) {
+                    for (int d = 0; d < 3; d++) f[d] -= pair_phi(T, d, q[i], mi, Ti, q[j], mj, Tj);
+                    if (mi) {
+                        double h[3];
+                        pair_field(T, q[j], mj, Tj, h);
+                        for (int d = 0; d < 3; d++) g[d] += h[d];
+                    }
+                }
+            }
+        }
+        if (eatom) eatom[i] = e;
+        if (forces) for (int d = 0; d < 3; d++) forces[3 * i + d] = f[d];
+        if (dEdmu) for (int d = 0; d < 3; d++) dEdmu[3 * i + d] = g[d];
+    }
+    free(cnt); free(cid); free(atoms);
+    c.cell_start = NULL; c.cell_atoms = NULL;
+    ctx_free(&c);
+    return 0;
+}

@@ -1,0 +1,266 @@
+"""Python binding of the MI355X interpolated-Ewald library (libankh.so).
+
+Argument marshalling only: every step of an evaluation runs in the HIP
+kernels behind the C ABI declared in include/ankh.h.  The functions below
+carry the C names (`ankh_plan`, `ankh_energy`, `ankh_energy_forces`, ...);
+`Plan` wraps a plan handle and `AnkhEnergy` is the autograd function whose
+backward returns -g F for the positions and g dE/dmu for the dipoles.
+
+Device memory and streams come from PyTorch (ROCm): every array argument is
+a contiguous float64 tensor on the GPU.  There is no CPU fallback: the module
+raises if the library is not built or no GPU is present.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libankh.so")
+
+ANKH_FP64 = 0
+ANKH_MIXED = 1
+
+STATUS = {
+    0: "ok", 1: "invalid argument", 2: "non-finite input", 3: "quadrupole not traceless",
+    4: "leaf overflow", 5: "accuracy unreachable in this precision", 6: "out of device memory",
+    7: "HIP runtime error",
+}
+
+STAGES = ["sort", "gather", "p2m", "m2m", "m2l", "periodic", "l2l", "l2p", "p2p", "reduce"]
+
+
+class AnkhError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, 'unknown')} (status {status})")
+        self.status = status
+
+
+class _Overrides(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("order", ctypes.c_int32), ("images", ctypes.c_int32),
+                ("xi", ctypes.c_double)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int64), ("depth", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("images", ctypes.c_int32), ("max_order", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("xi", ctypes.c_double), ("box_radius", ctypes.c_double), ("rel_accuracy", ctypes.c_double),
+                ("plan_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_int64), ("m2l_flops", ctypes.c_double),
+                ("near_pairs", ctypes.c_int64), ("stage_ms", ctypes.c_double * 10)]
+
+
+_lib = None
+
+EXPORTS = ["ankh_plan", "ankh_energy", "ankh_energy_forces", "ankh_sync", "ankh_get_stats", "ankh_set_timing",
+           "ankh_last_terms", "ankh_leaf_multipoles", "ankh_destroy", "ankh_status_string"]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libankh.so and declare the C signatures (no GPU call is made)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libankh.so is not built ({path}); run paper_2212_08284_amd/build.py")
+    L = ctypes.CDLL(path)
+    vp, dp, i64 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64
+    L.ankh_plan.restype = ctypes.c_int
+    L.ankh_plan.argtypes = [ctypes.POINTER(vp), i64, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                            ctypes.c_int32, ctypes.POINTER(_Overrides), vp]
+    L.ankh_energy.restype = ctypes.c_int
+    L.ankh_energy.argtypes = [vp, dp, dp, dp, dp, dp]
+    L.ankh_energy_forces.restype = ctypes.c_int
+    L.ankh_energy_forces.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp]
+    L.ankh_sync.restype = ctypes.c_int
+    L.ankh_sync.argtypes = [vp]
+    L.ankh_get_stats.restype = ctypes.c_int
+    L.ankh_get_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+    L.ankh_set_timing.restype = ctypes.c_int
+    L.ankh_set_timing.argtypes = [vp, ctypes.c_int32]
+    L.ankh_last_terms.restype = ctypes.c_int
+    L.ankh_last_terms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.ankh_leaf_multipoles.restype = ctypes.c_int
+    L.ankh_leaf_multipoles.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64]
+    L.ankh_destroy.restype = None
+    L.ankh_destroy.argtypes = [vp]
+    L.ankh_status_string.restype = ctypes.c_char_p
+    L.ankh_status_string.argtypes = [ctypes.c_int]
+    _lib = L
+    return L
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise AnkhError(st, where)
+
+
+def _dev(t, n_cols, n, name, optional=False):
+    if t is None:
+        if optional:
+            return None, None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    t = t.contiguous()
+    want = (n,) if n_cols == 1 else (n, n_cols)
+    if tuple(t.shape) != want:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {want}")
+    return t, ctypes.c_void_p(t.data_ptr())
+
+
+# ---- C-named entry points ------------------------------------------------------
+
+def ankh_plan(n_atoms: int, box_radius: float, rel_accuracy: float, max_order: int = 2,
+              precision: int = ANKH_FP64, depth: int | None = None, order: int | None = None,
+              images: int | None = None, xi: float | None = None, stream=None):
+    """Create a plan; returns the opaque handle (ctypes.c_void_p)."""
+    L = load_library()
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the interpolated-Ewald library runs on the GPU only")
+    ov = _Overrides(-1 if depth is None else int(depth), 0 if order is None else int(order),
+                    0 if images is None else int(images), 0.0 if xi is None else float(xi))
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    h = ctypes.c_void_p()
+    _check(L.ankh_plan(ctypes.byref(h), int(n_atoms), float(box_radius), float(rel_accuracy), int(max_order),
+                       int(precision), ctypes.byref(ov), ctypes.c_void_p(stream.cuda_stream)), "ankh_plan")
+    return h
+
+
+def ankh_energy(plan, pos, q, mu, theta, energy):
+    _check(load_library().ankh_energy(plan, pos, q, mu, theta, energy), "ankh_energy")
+
+
+def ankh_energy_forces(plan, pos, q, mu, theta, energy, forces, dE_dmu):
+    _check(load_library().ankh_energy_forces(plan, pos, q, mu, theta, energy, forces, dE_dmu), "ankh_energy_forces")
+
+
+def ankh_sync(plan):
+    _check(load_library().ankh_sync(plan), "ankh_sync")
+
+
+def ankh_get_stats(plan) -> dict:
+    s = _Stats()
+    _check(load_library().ankh_get_stats(plan, ctypes.byref(s)), "ankh_get_stats")
+    d = {f: getattr(s, f) for f, _ in _Stats._fields_ if f != "stage_ms"}
+    d["stage_ms"] = {STAGES[i]: s.stage_ms[i] for i in range(10)}
+    return d
+
+
+def ankh_set_timing(plan, enable: bool):
+    _check(load_library().ankh_set_timing(plan, 1 if enable else 0), "ankh_set_timing")
+
+
+def ankh_last_terms(plan) -> dict:
+    buf = (ctypes.c_double * 7)()
+    _check(load_library().ankh_last_terms(plan, buf), "ankh_last_terms")
+    keys = ["near", "far_levels", "periodic", "self", "background", "total", "charge"]
+    return {k: buf[i] for i, k in enumerate(keys)}
+
+
+def ankh_leaf_multipoles(plan, count: int):
+    import numpy as np
+    out = np.zeros(count)
+    _check(load_library().ankh_leaf_multipoles(plan, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), count),
+           "ankh_leaf_multipoles")
+    return out
+
+
+def ankh_destroy(plan):
+    if plan is not None and plan.value:
+        load_library().ankh_destroy(plan)
+
+
+# ---- convenience wrapper ----------------------------------------------------------
+
+class Plan:
+    """A plan for n atoms in a cubic box of half-edge box_radius (see ankh.h)."""
+
+    def __init__(self, n_atoms, box_radius, rel_accuracy=1e-6, max_order=2, precision="fp64", depth=None,
+                 order=None, images=None, xi=None, stream=None):
+        prec = {"fp64": ANKH_FP64, "mixed": ANKH_MIXED}[precision] if isinstance(precision, str) else int(precision)
+        self.n = int(n_atoms)
+        self.max_order = int(max_order)
+        self.handle = ankh_plan(n_atoms, box_radius, rel_accuracy, max_order, prec, depth, order, images, xi,
+                                stream)
+        self.stats = ankh_get_stats(self.handle)
+
+    def _args(self, pos, q, mu, theta):
+        n = self.n
+        pos, pp = _dev(pos, 3, n, "pos")
+        q, qp = _dev(q, 1, n, "q")
+        mu, mp = _dev(mu, 3, n, "mu", optional=True)
+        theta, tp = _dev(theta, 6, n, "theta", optional=True)
+        return (pos, q, mu, theta), (pp, qp, mp, tp)
+
+    def energy(self, pos, q, mu=None, theta=None):
+        keep, (pp, qp, mp, tp) = self._args(pos, q, mu, theta)
+        e = torch.empty(1, dtype=torch.float64, device=pos.device)
+        ankh_energy(self.handle, pp, qp, mp, tp, ctypes.c_void_p(e.data_ptr()))
+        return e
+
+    def energy_forces(self, pos, q, mu=None, theta=None, fields=True):
+        keep, (pp, qp, mp, tp) = self._args(pos, q, mu, theta)
+        e = torch.empty(1, dtype=torch.float64, device=pos.device)
+        F = torch.empty((self.n, 3), dtype=torch.float64, device=pos.device)
+        G = torch.empty((self.n, 3), dtype=torch.float64, device=pos.device) if fields else None
+        ankh_energy_forces(self.handle, pp, qp, mp, tp, ctypes.c_void_p(e.data_ptr()),
+                           ctypes.c_void_p(F.data_ptr()), None if G is None else ctypes.c_void_p(G.data_ptr()))
+        return e, F, G
+
+    def sync(self):
+        ankh_sync(self.handle)
+
+    def get_stats(self):
+        return ankh_get_stats(self.handle)
+
+    def set_timing(self, on=True):
+        ankh_set_timing(self.handle, on)
+
+    def last_terms(self):
+        return ankh_last_terms(self.handle)
+
+    def leaf_multipoles(self):
+        s = self.stats
+        nleaf = 8 ** s["depth"]
+        nu = s["order"] ** 3
+        return ankh_leaf_multipoles(self.handle, nleaf * nu).reshape(nleaf, nu)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            ankh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class AnkhEnergy(torch.autograd.Function):
+    """E(pos, q, mu, theta) with the hand-written adjoint: dE/dpos = -F, dE/dmu = fields."""
+
+    @staticmethod
+    def forward(ctx, pos, q, mu, theta, plan: Plan):
+        e, F, G = plan.energy_forces(pos.detach(), q.detach(), None if mu is None else mu.detach(),
+                                     None if theta is None else theta.detach(), fields=mu is not None)
+        ctx.save_for_backward(F, G if G is not None else F.new_zeros(0))
+        ctx.has_mu = mu is not None
+        return e[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        F, G = ctx.saved_tensors
+        dpos = -g * F
+        dmu = g * G if ctx.has_mu else None
+        return dpos, None, dmu, None, None
+
+
+def energy(pos, q, mu=None, theta=None, plan: Plan | None = None):
+    """Differentiable energy (positions and dipoles)."""
+    return AnkhEnergy.apply(pos, q, mu, theta, plan)

@@ -1,0 +1,119 @@
+// Internal declarations shared by the host driver and the kernel files of the
+// interpolated-Ewald library.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "ankh.h"
+
+namespace ankh {
+
+constexpr int kMaxOrder = 10;        // largest Chebyshev order per axis
+constexpr int kMaxDepth = 7;         // 2^21 leaves at most
+constexpr int kNumOff = 343;         // slots for offsets d in [-3,3]^3 (316 used)
+constexpr int kNumIL = 189;          // interaction-list length of every cell
+constexpr int kRedBlocks = 256;      // first-stage blocks of the energy reduction
+constexpr int kNumStages = 10;
+
+// index of offset d in [-3,3]^3
+__host__ __device__ inline int off_index(int dx, int dy, int dz) {
+    return ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3);
+}
+
+// Particle data in leaf order (structure of arrays).  Positions are relative
+// to the centre of the atom's leaf (float64 in every mode, so that pair
+// separations are formed exactly); moments in float64 and, for the mixed
+// mode, float32 copies for the pair kernel.
+struct Particles {
+    double *x, *y, *z;
+    double *q;
+    double *mu;      // [3][n]
+    double *th;      // [6][n] (xx, xy, xz, yy, yz, zz)
+    float *qf, *muf, *thf;
+};
+
+struct Level {
+    int e;            // level index (0 = root)
+    int nside;        // 2^e
+    int64_t ncell;    // 8^e
+    size_t cell0;     // first cell of this level in the concatenated M / L arrays
+    double width;     // cell width
+};
+
+}  // namespace ankh
+
+struct ankh_plan_s {
+    // parameters
+    int64_t n = 0;
+    double rB = 0, edge = 0, eps = 0, xi = 0;
+    int depth = 0, order = 0, nu = 0, nup = 0, images = 0, max_order = 0, precision = 0;
+    hipStream_t stream = nullptr;
+    int nside = 1;
+    int64_t nleaf = 1;
+    ankh::Level lv[ankh::kMaxDepth + 1];
+    size_t ncell_total = 0;
+
+    // host tables (float64)
+    double nodes[ankh::kMaxOrder];
+    double Hm[ankh::kMaxOrder * ankh::kMaxOrder];      // S(x) = H T(x), H[k][m]
+    double V[2][ankh::kMaxOrder * ankh::kMaxOrder];    // M2M: V[b][a][i]
+
+    // device buffers
+    double *d_tab = nullptr;      // nodes[L], H[L*L], V[2][L*L]
+    int32_t *d_leaf = nullptr;    // leaf id per input atom
+    int32_t *d_count = nullptr;   // atoms per leaf
+    int32_t *d_offs = nullptr;    // CSR offsets [nleaf + 1]
+    int32_t *d_fill = nullptr;    // scatter cursors [nleaf]
+    int32_t *d_perm = nullptr;    // leaf-order slot -> input atom
+    int32_t *d_tmp = nullptr;     // [n] segment-sort scratch
+    ankh::Particles P{};
+    double *d_M = nullptr;        // multipole expansions, all levels [cells][nup]
+    double *d_L = nullptr;        // local expansions, all levels [cells][nup]
+    double *d_K = nullptr;        // fp64 M2L matrices: level e>=1 at (e-1) * 343 * nup * nup, [d][l][k]
+    float *d_Kf = nullptr;        // fp32 copy for the mixed mode
+    double *d_Cper = nullptr;     // far-image root operator [nup][nup]
+    double *d_eatom = nullptr;    // near-field energy per leaf-order atom
+    double *d_eleaf = nullptr;    // far energy per leaf
+    double *d_F = nullptr;        // forces in leaf order [3][n]
+    double *d_G = nullptr;        // fields in leaf order [3][n]
+    double *d_terms = nullptr;    // energy terms [8]
+    double *d_part = nullptr;     // reduction partials
+    int32_t *d_err = nullptr;     // latched device errors [4]
+    size_t bytes = 0;
+
+    // statistics / timing
+    double plan_ms = 0;
+    bool timing = false;
+    hipEvent_t ev[ankh::kNumStages + 1] = {};
+    bool ev_valid = false;
+    int last_kind = 0;            // 0 none, 1 energy, 2 energy+forces
+    int last_order = 0;
+};
+
+namespace ankh {
+
+// ---- launchers (defined in the kernel files) -------------------------------
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
+hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
+hipError_t launch_sort(ankh_plan_s *pl, const double *pos, const double *q, const double *mu,
+                       const double *th);
+hipError_t launch_gather(ankh_plan_s *pl, const double *pos, const double *q, const double *mu,
+                         const double *th);
+hipError_t launch_p2m(ankh_plan_s *pl, int ord);
+hipError_t launch_m2m(ankh_plan_s *pl, int e_parent);
+hipError_t launch_l2l(ankh_plan_s *pl, int e_child);
+hipError_t launch_cper(ankh_plan_s *pl);
+hipError_t launch_leafdot(ankh_plan_s *pl);
+hipError_t launch_l2p(ankh_plan_s *pl, int ord, bool fields);
+hipError_t launch_reduce(ankh_plan_s *pl, double *energy_out, int ord);
+hipError_t launch_unpermute(ankh_plan_s *pl, double *forces, double *dEdmu, bool have_mu);
+hipError_t launch_m2l(ankh_plan_s *pl, int e);
+hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields);
+hipError_t launch_build_m2l(ankh_plan_s *pl, int e, double *K);
+hipError_t launch_build_cper(ankh_plan_s *pl);
+hipError_t launch_convert_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+
+}  // namespace ankh

@@ -1,0 +1,755 @@
+// Tree construction, anterpolation (P2M), M2M / L2L, the far-image root
+// operator, L2P, reductions and the plan-time operator builders.
+//
+// Cell and leaf numbering: cell (i, j, k) of level e is (i * 2^e + j) * 2^e + k;
+// interpolation node (a, b, c) of a cell is (a * L + b) * L + c; expansions are
+// stored cell-major with a row stride nup >= L^3 (a multiple of 64, zero padded).
+#include <cmath>
+
+#include "ankh_internal.h"
+
+namespace ankh {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ inline int leaf_coord(double x, double rB, double edge, double w, int nside, double *xw) {
+    // wrap into [-rB, rB) then bin; clamp guards the upper face
+    double t = x - edge * floor((x + rB) / edge);
+    if (t >= rB) t -= edge;
+    *xw = t;
+    int v = (int)floor((t + rB) / w);
+    return v < 0 ? 0 : (v >= nside ? nside - 1 : v);
+}
+
+__global__ void k_zero_i32(int32_t *p, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void k_zero_f64(double *p, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_to_f32(const double *s, float *d, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (float)s[i];
+}
+
+// ---- tree: bin atoms into leaves, count, validate inputs --------------------
+__global__ void k_bin(int64_t n, const double *pos, const double *q, const double *mu, const double *th,
+                      double rB, double edge, double w, int nside, int32_t *leaf, int32_t *count,
+                      int32_t *err) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool fin = isfinite(q[i]);
+    int ix[3];
+    for (int d = 0; d < 3; d++) {
+        double v = pos[3 * i + d], xw;
+        fin = fin && isfinite(v);
+        ix[d] = isfinite(v) ? leaf_coord(v, rB, edge, w, nside, &xw) : 0;
+    }
+    if (mu)
+        for (int d = 0; d < 3; d++) fin = fin && isfinite(mu[3 * i + d]);
+    if (th) {
+        double tr = 0, mx = 0;
+        for (int d = 0; d < 6; d++) fin = fin && isfinite(th[6 * i + d]);
+        const double xx = th[6 * i], yy = th[6 * i + 3], zz = th[6 * i + 5];
+        tr = xx + yy + zz;
+        mx = fmax(fabs(xx), fmax(fabs(yy), fabs(zz)));
+        if (fabs(tr) > 1e-6 * (1.0 + mx)) err[1] = 1;
+    }
+    if (!fin) err[0] = 1;
+    int id = (ix[0] * nside + ix[1]) * nside + ix[2];
+    leaf[i] = id;
+    atomicAdd(&count[id], 1);
+}
+
+// exclusive scan of the leaf counts (one block; m up to 8^7)
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *count, int32_t *offs, int64_t m) {
+    __shared__ long long part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (m + 1023) / 1024;
+    const int64_t b = t * per, e = (b + per < m) ? b + per : m;
+    long long s = 0;
+    for (int64_t i = b; i < e; i++) s += count[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        long long v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    long long base = part[t] - s;
+    for (int64_t i = b; i < e; i++) {
+        offs[i] = (int32_t)base;
+        base += count[i];
+    }
+    if (t == 1023) offs[m] = (int32_t)part[1023];
+}
+
+__global__ void k_scatter(int64_t n, const int32_t *leaf, const int32_t *offs, int32_t *fill, int32_t *perm) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int l = leaf[i];
+    int slot = offs[l] + atomicAdd(&fill[l], 1);
+    perm[slot] = (int32_t)i;
+}
+
+// order the atoms of each leaf by input index (rank sort), so that every
+// later sum runs in an order independent of the scatter's atomics
+__global__ __launch_bounds__(256) void k_segsort(const int32_t *offs, const int32_t *perm, int32_t *out) {
+    __shared__ int32_t seg[2048];
+    const int64_t leaf = blockIdx.x;
+    const int s0 = offs[leaf], cnt = offs[leaf + 1] - s0;
+    const bool cached = cnt <= 2048;
+    if (cached)
+        for (int e = threadIdx.x; e < cnt; e += blockDim.x) seg[e] = perm[s0 + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const int v = cached ? seg[e] : perm[s0 + e];
+        int rank = 0;
+        for (int j = 0; j < cnt; j++) rank += ((cached ? seg[j] : perm[s0 + j]) < v);
+        out[s0 + rank] = v;
+    }
+}
+
+// leaf-order particle arrays: local coordinates (relative to the leaf centre)
+__global__ void k_gather(int64_t n, const int32_t *perm, const int32_t *leaf, const double *pos,
+                         const double *q, const double *mu, const double *th, double rB, double edge,
+                         double w, int nside, Particles P, int planned_order, int mixed) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int i = perm[s];
+    const int id = leaf[i];
+    const int ix[3] = {id / (nside * nside), (id / nside) % nside, id % nside};
+    double loc[3];
+    for (int d = 0; d < 3; d++) {
+        double v = pos[3 * (int64_t)i + d], xw = 0;
+        if (isfinite(v)) leaf_coord(v, rB, edge, w, nside, &xw);
+        else xw = v;
+        loc[d] = xw - (-rB + (ix[d] + 0.5) * w);
+    }
+    P.x[s] = loc[0];
+    P.y[s] = loc[1];
+    P.z[s] = loc[2];
+    const double qi = q[i];
+    P.q[s] = qi;
+    if (mixed) P.qf[s] = (float)qi;
+    if (planned_order >= 1) {
+        for (int d = 0; d < 3; d++) {
+            double v = mu ? mu[3 * (int64_t)i + d] : 0.0;
+            P.mu[d * n + s] = v;
+            if (mixed) P.muf[d * n + s] = (float)v;
+        }
+    }
+    if (planned_order >= 2) {
+        for (int d = 0; d < 6; d++) {
+            double v = th ? th[6 * (int64_t)i + d] : 0.0;
+            P.th[d * n + s] = v;
+            if (mixed) P.thf[d * n + s] = (float)v;
+        }
+    }
+}
+
+// ---- Chebyshev basis ---------------------------------------------------------
+// T_m and its derivatives up to order ND-1 by the differentiated three-term
+// recurrence (identical to D^n T with the differentiation matrix D), then
+// S^(n)_k = (1/h)^n sum_m H[k][m] T^(n)_m.
+template <int ND>
+__device__ inline void cheb_basis(double xh, double hinv, int L, const double *sH, double *out /* [ND][L] */,
+                                  int stride_n) {
+    double T[ND][kMaxOrder];
+#pragma unroll
+    for (int n = 0; n < ND; n++) {
+        T[n][0] = (n == 0) ? 1.0 : 0.0;
+        T[n][1] = (n == 0) ? xh : (n == 1 ? 1.0 : 0.0);
+    }
+    for (int m = 1; m + 1 < L; m++) {
+        T[0][m + 1] = 2 * xh * T[0][m] - T[0][m - 1];
+#pragma unroll
+        for (int n = 1; n < ND; n++) T[n][m + 1] = 2 * n * T[n - 1][m] + 2 * xh * T[n][m] - T[n][m - 1];
+    }
+    double sc = 1.0;
+#pragma unroll
+    for (int n = 0; n < ND; n++) {
+        for (int k = 0; k < L; k++) {
+            double s = 0;
+            for (int m = 0; m < L; m++) s += sH[k * L + m] * T[n][m];
+            out[n * stride_n + k] = s * sc;
+        }
+        sc *= hinv;
+    }
+}
+
+// ---- P2M: modified charges of every leaf (Alg. 2) --------------------------
+template <int ORD>
+__global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, const double *tab, int L,
+                                             int nu, int nup, double hinv, double *Q, int64_t n) {
+    constexpr int ND = ORD + 1;
+    constexpr int CH = 64;
+    extern __shared__ double sm[];
+    double *sH = sm;                       // L*L
+    double *sS = sH + L * L;               // [CH][3][ND][L]
+    double *sMom = sS + CH * 3 * ND * L;   // [CH][10]
+    const int tid = threadIdx.x;
+    const int64_t leaf = blockIdx.x;
+    for (int t = tid; t < L * L; t += 256) sH[t] = tab[L + t];
+    const int s0 = offs[leaf], cnt = offs[leaf + 1] - s0;
+    double acc[4] = {0, 0, 0, 0};
+    for (int c0 = 0; c0 < cnt; c0 += CH) {
+        const int m = min(CH, cnt - c0);
+        __syncthreads();
+        if (tid < 3 * m) {
+            const int a = tid / 3, ax = tid % 3;
+            const int64_t slot = s0 + c0 + a;
+            const double xl = ax == 0 ? P.x[slot] : (ax == 1 ? P.y[slot] : P.z[slot]);
+            cheb_basis<ND>(xl * hinv, hinv, L, sH, sS + (a * 3 + ax) * ND * L, L);
+        }
+        if (tid < m) {
+            const int64_t slot = s0 + c0 + tid;
+            double *mo = sMom + tid * 10;
+            mo[0] = P.q[slot];
+            if (ORD >= 1) {
+                mo[1] = P.mu[slot];
+                mo[2] = P.mu[n + slot];
+                mo[3] = P.mu[2 * n + slot];
+            }
+            if (ORD >= 2) {
+                mo[4] = P.th[slot];                 // xx
+                mo[5] = 2 * P.th[n + slot];         // 2 xy
+                mo[6] = 2 * P.th[2 * n + slot];     // 2 xz
+                mo[7] = P.th[3 * n + slot];         // yy
+                mo[8] = 2 * P.th[4 * n + slot];     // 2 yz
+                mo[9] = P.th[5 * n + slot];         // zz
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int node = tid + 256 * r;
+            if (node >= nu) break;
+            const int i = node / (L * L), j = (node / L) % L, k = node % L;
+            double s = 0;
+            for (int a = 0; a < m; a++) {
+                const double *Sx = sS + (a * 3 + 0) * ND * L;
+                const double *Sy = sS + (a * 3 + 1) * ND * L;
+                const double *Sz = sS + (a * 3 + 2) * ND * L;
+                const double *mo = sMom + a * 10;
+                const double x0 = Sx[i], y0 = Sy[j], z0 = Sz[k];
+                double v = mo[0] * x0 * y0 * z0;
+                if (ORD >= 1) {
+                    const double x1 = Sx[L + i], y1 = Sy[L + j], z1 = Sz[L + k];
+                    v += mo[1] * x1 * y0 * z0 + mo[2] * x0 * y1 * z0 + mo[3] * x0 * y0 * z1;
+                    if (ORD >= 2) {
+                        const double x2 = Sx[2 * L + i], y2 = Sy[2 * L + j], z2 = Sz[2 * L + k];
+                        v += mo[4] * x2 * y0 * z0 + mo[5] * x1 * y1 * z0 + mo[6] * x1 * y0 * z1 +
+                             mo[7] * x0 * y2 * z0 + mo[8] * x0 * y1 * z1 + mo[9] * x0 * y0 * z2;
+                    }
+                }
+                s += v;
+            }
+            acc[r] += s;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int node = tid + 256 * r;
+        if (node < nup) Q[leaf * nup + node] = node < nu ? acc[r] : 0.0;
+    }
+    for (int node = tid + 1024; node < nup; node += 256) Q[leaf * nup + node] = 0.0;
+}
+
+// ---- M2M: parent expansion from the 8 children (three 1D passes) ---------
+__global__ __launch_bounds__(256) void k_m2m(const double *Mc, double *Mp, const double *tab, int L, int nu,
+                                             int nup, int ns_par) {
+    extern __shared__ double sm[];
+    double *sV = sm;             // [2][L*L]
+    double *b0 = sV + 2 * L * L; // nu
+    double *b1 = b0 + nu;        // nu
+    const int tid = threadIdx.x;
+    for (int t = tid; t < 2 * L * L; t += 256) sV[t] = tab[L + L * L + t];
+    const int64_t p = blockIdx.x;
+    const int px = (int)(p / ((int64_t)ns_par * ns_par)), py = (int)((p / ns_par) % ns_par), pz = (int)(p % ns_par);
+    const int nsc = 2 * ns_par;
+    double acc[4] = {0, 0, 0, 0};
+    const int LL = L * L;
+    for (int bits = 0; bits < 8; bits++) {
+        const int bx = bits >> 2, by = (bits >> 1) & 1, bz = bits & 1;
+        const int64_t c = ((int64_t)(2 * px + bx) * nsc + (2 * py + by)) * nsc + (2 * pz + bz);
+        __syncthreads();
+        for (int t = tid; t < nu; t += 256) b0[t] = Mc[c * nup + t];
+        __syncthreads();
+        const double *Vz = sV + bz * LL, *Vy = sV + by * LL, *Vx = sV + bx * LL;
+        for (int t = tid; t < nu; t += 256) {   // (i, j, cz)
+            const int ij = t / L, cz = t % L;
+            double s = 0;
+            for (int k = 0; k < L; k++) s += Vz[cz * L + k] * b0[ij * L + k];
+            b1[t] = s;
+        }
+        __syncthreads();
+        for (int t = tid; t < nu; t += 256) {   // (i, cy, cz)
+            const int i = t / LL, cy = (t / L) % L, cz = t % L;
+            double s = 0;
+            for (int j = 0; j < L; j++) s += Vy[cy * L + j] * b1[(i * L + j) * L + cz];
+            b0[t] = s;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int t = tid + 256 * r;
+            if (t >= nu) break;
+            const int cx = t / LL, yz = t % LL;
+            double s = 0;
+            for (int i = 0; i < L; i++) s += Vx[cx * L + i] * b0[i * LL + yz];
+            acc[r] += s;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int t = tid + 256 * r;
+        if (t < nup) Mp[p * nup + t] = t < nu ? acc[r] : 0.0;
+    }
+    for (int t = tid + 1024; t < nup; t += 256) Mp[p * nup + t] = 0.0;
+}
+
+// ---- L2L: child local expansion += transpose of M2M applied to the parent's ----
+__global__ __launch_bounds__(256) void k_l2l(const double *Lp, double *Lc, const double *tab, int L, int nu,
+                                             int nup, int ns_child) {
+    extern __shared__ double sm[];
+    double *sV = sm;
+    double *b0 = sV + 2 * L * L;
+    double *b1 = b0 + nu;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < 2 * L * L; t += 256) sV[t] = tab[L + L * L + t];
+    const int64_t c = blockIdx.x;
+    const int cx = (int)(c / ((int64_t)ns_child * ns_child)), cy = (int)((c / ns_child) % ns_child),
+              cz = (int)(c % ns_child);
+    const int nsp = ns_child / 2;
+    const int64_t p = ((int64_t)(cx >> 1) * nsp + (cy >> 1)) * nsp + (cz >> 1);
+    const int bx = cx & 1, by = cy & 1, bz = cz & 1;
+    const int LL = L * L;
+    const double *Vz = sV + bz * LL, *Vy = sV + by * LL, *Vx = sV + bx * LL;
+    for (int t = tid; t < nu; t += 256) b0[t] = Lp[p * nup + t];
+    __syncthreads();
+    for (int t = tid; t < nu; t += 256) {   // (a, b, k) = sum_c V[c][k] Lp[a, b, c]
+        const int ab = t / L, k = t % L;
+        double s = 0;
+        for (int cc = 0; cc < L; cc++) s += Vz[cc * L + k] * b0[ab * L + cc];
+        b1[t] = s;
+    }
+    __syncthreads();
+    for (int t = tid; t < nu; t += 256) {   // (a, j, k) = sum_b V[b][j] (a, b, k)
+        const int a = t / LL, j = (t / L) % L, k = t % L;
+        double s = 0;
+        for (int bb = 0; bb < L; bb++) s += Vy[bb * L + j] * b1[(a * L + bb) * L + k];
+        b0[t] = s;
+    }
+    __syncthreads();
+    for (int t = tid; t < nu; t += 256) {   // (i, j, k) = sum_a V[a][i] (a, j, k)
+        const int i = t / LL, jk = t % LL;
+        double s = 0;
+        for (int a = 0; a < L; a++) s += Vx[a * L + i] * b0[a * LL + jk];
+        Lc[c * nup + t] += s;
+    }
+}
+
+// ---- far periodic images: L_root = C_per M_root, E_per = 1/2 M.C M -----------
+__global__ __launch_bounds__(1024) void k_cper(const double *C, const double *M, double *Lr, int nu, int nup,
+                                               double *terms) {
+    __shared__ double sM[1024];
+    __shared__ double red[1024];
+    const int t = threadIdx.x;
+    for (int k = t; k < nu; k += 1024) sM[k] = M[k];
+    __syncthreads();
+    double part = 0;
+    for (int k = t; k < nup; k += 1024) {
+        double s = 0;
+        if (k < nu)
+            for (int l = 0; l < nu; l++) s += C[(int64_t)l * nup + k] * sM[l];
+        Lr[k] = s;
+        if (k < nu) part += sM[k] * s;
+    }
+    red[t] = part;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if (t < off) red[t] += red[t + off];
+        __syncthreads();
+    }
+    if (t == 0) terms[2] = 0.5 * red[0];
+}
+
+// ---- far energy per leaf: 1/2 Q_t . Lambda_t ---------------------------------
+__global__ __launch_bounds__(256) void k_leafdot(const double *Q, const double *Lam, int nu, int nup, double *eleaf) {
+    __shared__ double red[256];
+    const int64_t leaf = blockIdx.x;
+    double s = 0;
+    for (int k = threadIdx.x; k < nu; k += 256) s += Q[leaf * nup + k] * Lam[leaf * nup + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) eleaf[leaf] = 0.5 * red[0];
+}
+
+// ---- L2P: far-field forces and fields at the atoms (adjoint of P2M) --------
+// phi(y) = sum_k Lambda_k S_k(y); F = -(q grad phi + mu_a grad d_a phi + Th_ab grad d_a d_b phi),
+// dE/dmu = grad phi.  One wave per leaf, one atom per lane.
+template <int ORD, bool FIELD>
+__global__ __launch_bounds__(64) void k_l2p(Particles P, const int32_t *offs, const double *tab, int L, int nu,
+                                            int nup, double hinv, const double *Lam, double *F, double *G,
+                                            int64_t n) {
+    constexpr int ND = ORD + 2;   // derivative orders 0..ORD+1
+    extern __shared__ double sm[];
+    double *sH = sm;                    // L*L
+    double *sL = sH + L * L;            // nu
+    double *sS = sL + nu;               // [blockDim][3][ND][L]
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int64_t leaf = blockIdx.x;
+    for (int t = tid; t < L * L; t += nt) sH[t] = tab[L + t];
+    for (int t = tid; t < nu; t += nt) sL[t] = Lam[leaf * nup + t];
+    __syncthreads();
+    const int s0 = offs[leaf], cnt = offs[leaf + 1] - s0;
+    double *Sx = sS + tid * 3 * ND * L, *Sy = Sx + ND * L, *Sz = Sy + ND * L;
+    for (int a = tid; a < cnt; a += nt) {
+        const int64_t slot = s0 + a;
+        cheb_basis<ND>(P.x[slot] * hinv, hinv, L, sH, Sx, L);
+        cheb_basis<ND>(P.y[slot] * hinv, hinv, L, sH, Sy, L);
+        cheb_basis<ND>(P.z[slot] * hinv, hinv, L, sH, Sz, L);
+        double phi[ND][ND][ND];
+#pragma unroll
+        for (int x = 0; x < ND; x++)
+#pragma unroll
+            for (int y = 0; y < ND; y++)
+#pragma unroll
+                for (int z = 0; z < ND; z++) phi[x][y][z] = 0;
+        for (int i = 0; i < L; i++) {
+            double h[ND][ND];
+#pragma unroll
+            for (int y = 0; y < ND; y++)
+#pragma unroll
+                for (int z = 0; z < ND; z++) h[y][z] = 0;
+            for (int j = 0; j < L; j++) {
+                double g[ND];
+#pragma unroll
+                for (int z = 0; z < ND; z++) g[z] = 0;
+                const double *row = sL + (i * L + j) * L;
+                for (int k = 0; k < L; k++) {
+                    const double lv = row[k];
+#pragma unroll
+                    for (int z = 0; z < ND; z++) g[z] += lv * Sz[z * L + k];
+                }
+#pragma unroll
+                for (int y = 0; y < ND; y++)
+#pragma unroll
+                    for (int z = 0; z + y < ND; z++) h[y][z] += Sy[y * L + j] * g[z];
+            }
+#pragma unroll
+            for (int x = 0; x < ND; x++)
+#pragma unroll
+                for (int y = 0; x + y < ND; y++)
+#pragma unroll
+                    for (int z = 0; x + y + z < ND; z++) phi[x][y][z] += Sx[x * L + i] * h[y][z];
+        }
+        // gradient components
+        const double q = P.q[slot];
+        double f[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const int ex = c == 0, ey = c == 1, ez = c == 2;
+            double v = q * phi[ex][ey][ez];
+            if (ORD >= 1) {
+                const double m0 = P.mu[slot], m1 = P.mu[n + slot], m2 = P.mu[2 * n + slot];
+                v += m0 * phi[1 + ex][ey][ez] + m1 * phi[ex][1 + ey][ez] + m2 * phi[ex][ey][1 + ez];
+            }
+            if (ORD >= 2) {
+                const double xx = P.th[slot], xy = P.th[n + slot], xz = P.th[2 * n + slot];
+                const double yy = P.th[3 * n + slot], yz = P.th[4 * n + slot], zz = P.th[5 * n + slot];
+                v += xx * phi[2 + ex][ey][ez] + yy * phi[ex][2 + ey][ez] + zz * phi[ex][ey][2 + ez] +
+                     2 * xy * phi[1 + ex][1 + ey][ez] + 2 * xz * phi[1 + ex][ey][1 + ez] +
+                     2 * yz * phi[ex][1 + ey][1 + ez];
+            }
+            f[c] = -v;
+        }
+        F[slot] = f[0];
+        F[n + slot] = f[1];
+        F[2 * n + slot] = f[2];
+        if (FIELD) {
+            G[slot] = phi[1][0][0];
+            G[n + slot] = phi[0][1][0];
+            G[2 * n + slot] = phi[0][0][1];
+        }
+    }
+}
+
+// ---- energy reduction (two deterministic stages) -----------------------------
+__global__ __launch_bounds__(256) void k_reduce1(int64_t n, int64_t nleaf, const double *eatom, const double *eleaf,
+                                                 Particles P, int ord, double xi, double *part) {
+    __shared__ double red[4][256];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int64_t a0 = n * b / kRedBlocks, a1 = n * (b + 1) / kRedBlocks;
+    const int64_t l0 = nleaf * b / kRedBlocks, l1 = nleaf * (b + 1) / kRedBlocks;
+    const double c0 = -xi / sqrt(kPi), c1 = 2 * xi * xi / 3, c2 = 8 * xi * xi * xi * xi / 5;
+    double near = 0, self = 0, qs = 0, far = 0;
+    for (int64_t s = a0 + t; s < a1; s += 256) {
+        near += eatom[s];
+        const double q = P.q[s];
+        qs += q;
+        double v = q * q;
+        if (ord >= 1) {
+            const double m0 = P.mu[s], m1 = P.mu[n + s], m2 = P.mu[2 * n + s];
+            v += c1 * (m0 * m0 + m1 * m1 + m2 * m2);
+        }
+        if (ord >= 2) {
+            const double xx = P.th[s], xy = P.th[n + s], xz = P.th[2 * n + s];
+            const double yy = P.th[3 * n + s], yz = P.th[4 * n + s], zz = P.th[5 * n + s];
+            v += c2 * (xx * xx + yy * yy + zz * zz + 2 * (xy * xy + xz * xz + yz * yz));
+        }
+        self += c0 * v;
+    }
+    for (int64_t l = l0 + t; l < l1; l += 256) far += eleaf[l];
+    red[0][t] = near;
+    red[1][t] = self;
+    red[2][t] = qs;
+    red[3][t] = far;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off)
+            for (int c = 0; c < 4; c++) red[c][t] += red[c][t + off];
+        __syncthreads();
+    }
+    if (t < 4) part[b * 4 + t] = red[t][0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce2(const double *part, double *terms, double *energy, double xi,
+                                                 double vol) {
+    __shared__ double red[4][kRedBlocks];
+    const int t = threadIdx.x;
+    for (int c = 0; c < 4; c++) red[c][t] = part[t * 4 + c];
+    __syncthreads();
+    for (int off = kRedBlocks / 2; off > 0; off >>= 1) {
+        if (t < off)
+            for (int c = 0; c < 4; c++) red[c][t] += red[c][t + off];
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double near = red[0][0], self = red[1][0], Q = red[2][0], far = red[3][0];
+        const double per = terms[2];
+        const double bg = -kPi * Q * Q / (2 * vol * xi * xi);
+        const double tot = near + far + self + bg;
+        terms[0] = near;
+        terms[1] = far - per;
+        terms[3] = self;
+        terms[4] = bg;
+        terms[5] = tot;
+        terms[6] = Q;
+        if (energy) *energy = tot;
+    }
+}
+
+__global__ void k_unpermute(int64_t n, const int32_t *perm, const double *F, const double *G, const Particles P,
+                            double fself, double *forces, double *dEdmu, int have_mu) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t i = perm[s];
+    for (int d = 0; d < 3; d++) forces[3 * i + d] = F[d * n + s];
+    if (dEdmu) {
+        for (int d = 0; d < 3; d++)
+            dEdmu[3 * i + d] = have_mu ? G[d * n + s] + fself * P.mu[d * n + s] : 0.0;
+    }
+}
+
+// ---- plan-time builders ------------------------------------------------------
+// K_d[k][l] = H(w (1/2 (r_k - r_l) - d)) stored as [d][l][k]; zero for the
+// 27 adjacent offsets and for padded rows / columns.
+__global__ void k_build_m2l(double *K, const double *tab, int L, int nu, int nup, double w, double xi) {
+    const int64_t tot = (int64_t)kNumOff * nup * nup;
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= tot) return;
+    const int k = (int)(idx % nup);
+    const int l = (int)((idx / nup) % nup);
+    const int di = (int)(idx / ((int64_t)nup * nup));
+    const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
+    const int am = max(abs(dx), max(abs(dy), abs(dz)));
+    double v = 0;
+    if (am >= 2 && k < nu && l < nu) {
+        const int ki[3] = {k / (L * L), (k / L) % L, k % L};
+        const int li[3] = {l / (L * L), (l / L) % L, l % L};
+        const int dd[3] = {dx, dy, dz};
+        double r2 = 0;
+        for (int c = 0; c < 3; c++) {
+            const double u = w * (0.5 * (tab[ki[c]] - tab[li[c]]) - dd[c]);
+            r2 += u * u;
+        }
+        const double r = sqrt(r2);
+        v = erfc(xi * r) / r;
+    }
+    K[idx] = v;
+}
+
+// C_per[l][k] = sum_{I in Z_p, |I|_inf >= 2} H(x_k - x_l - edge I) on the root grid
+__global__ void k_build_cper(double *C, const double *tab, int L, int nu, int nup, double edge, double xi, int p) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nup * nup) return;
+    const int k = (int)(idx % nup), l = (int)(idx / nup);
+    double s = 0;
+    if (k < nu && l < nu) {
+        const double rB = 0.5 * edge;
+        const int ki[3] = {k / (L * L), (k / L) % L, k % L};
+        const int li[3] = {l / (L * L), (l / L) % L, l % L};
+        double b[3];
+        for (int c = 0; c < 3; c++) b[c] = rB * (tab[ki[c]] - tab[li[c]]);
+        for (int ix = -p; ix <= p; ix++)
+            for (int iy = -p; iy <= p; iy++)
+                for (int iz = -p; iz <= p; iz++) {
+                    if (max(abs(ix), max(abs(iy), abs(iz))) < 2) continue;
+                    const double u0 = b[0] - edge * ix, u1 = b[1] - edge * iy, u2 = b[2] - edge * iz;
+                    const double r = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
+                    s += erfc(xi * r) / r;
+                }
+    }
+    C[idx] = s;
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// ---- launchers ---------------------------------------------------------------
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_i32, dim3(nblk(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_f64, dim3(nblk(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_f32, dim3(nblk(n, 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th) {
+    hipStream_t s = pl->stream;
+    const double w = pl->edge / pl->nside;
+    hipError_t e;
+    if ((e = launch_zero_i32(pl->d_count, pl->nleaf, s)) != hipSuccess) return e;
+    if ((e = launch_zero_i32(pl->d_fill, pl->nleaf, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin, dim3(nblk(pl->n, 256)), dim3(256), 0, s, pl->n, pos, q, mu, th, pl->rB, pl->edge, w,
+                       pl->nside, pl->d_leaf, pl->d_count, pl->d_err);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, pl->d_count, pl->d_offs, pl->nleaf);
+    hipLaunchKernelGGL(k_scatter, dim3(nblk(pl->n, 256)), dim3(256), 0, s, pl->n, pl->d_leaf, pl->d_offs,
+                       pl->d_fill, pl->d_tmp);
+    hipLaunchKernelGGL(k_segsort, dim3((unsigned)pl->nleaf), dim3(256), 0, s, pl->d_offs, pl->d_tmp, pl->d_perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th) {
+    const double w = pl->edge / pl->nside;
+    hipLaunchKernelGGL(k_gather, dim3(nblk(pl->n, 256)), dim3(256), 0, pl->stream, pl->n, pl->d_perm, pl->d_leaf,
+                       pos, q, mu, th, pl->rB, pl->edge, w, pl->nside, pl->P, pl->max_order,
+                       pl->precision == ANKH_MIXED ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2m(ankh_plan_s *pl, int ord) {
+    const int L = pl->order;
+    const double hinv = 2.0 / (pl->edge / pl->nside);
+    double *Q = pl->d_M + pl->lv[pl->depth].cell0 * pl->nup;
+    const size_t shm = sizeof(double) * (L * L + 64 * 3 * (ord + 1) * L + 64 * 10);
+    dim3 g((unsigned)pl->nleaf), b(256);
+    if (ord == 0)
+        hipLaunchKernelGGL(k_p2m<0>, g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, L, pl->nu, pl->nup, hinv, Q, pl->n);
+    else if (ord == 1)
+        hipLaunchKernelGGL(k_p2m<1>, g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, L, pl->nu, pl->nup, hinv, Q, pl->n);
+    else
+        hipLaunchKernelGGL(k_p2m<2>, g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, L, pl->nu, pl->nup, hinv, Q, pl->n);
+    return hipGetLastError();
+}
+
+hipError_t launch_m2m(ankh_plan_s *pl, int e_par) {
+    const ankh::Level &P = pl->lv[e_par], &C = pl->lv[e_par + 1];
+    const size_t shm = sizeof(double) * (2 * pl->order * pl->order + 2 * pl->nu);
+    hipLaunchKernelGGL(k_m2m, dim3((unsigned)P.ncell), dim3(256), shm, pl->stream, pl->d_M + C.cell0 * pl->nup,
+                       pl->d_M + P.cell0 * pl->nup, pl->d_tab, pl->order, pl->nu, pl->nup, P.nside);
+    return hipGetLastError();
+}
+
+hipError_t launch_l2l(ankh_plan_s *pl, int e_child) {
+    const ankh::Level &P = pl->lv[e_child - 1], &C = pl->lv[e_child];
+    const size_t shm = sizeof(double) * (2 * pl->order * pl->order + 2 * pl->nu);
+    hipLaunchKernelGGL(k_l2l, dim3((unsigned)C.ncell), dim3(256), shm, pl->stream, pl->d_L + P.cell0 * pl->nup,
+                       pl->d_L + C.cell0 * pl->nup, pl->d_tab, pl->order, pl->nu, pl->nup, C.nside);
+    return hipGetLastError();
+}
+
+hipError_t launch_cper(ankh_plan_s *pl) {
+    hipLaunchKernelGGL(k_cper, dim3(1), dim3(1024), 0, pl->stream, pl->d_Cper, pl->d_M, pl->d_L, pl->nu, pl->nup,
+                       pl->d_terms);
+    return hipGetLastError();
+}
+
+hipError_t launch_leafdot(ankh_plan_s *pl) {
+    const size_t off = pl->lv[pl->depth].cell0 * pl->nup;
+    hipLaunchKernelGGL(k_leafdot, dim3((unsigned)pl->nleaf), dim3(256), 0, pl->stream, pl->d_M + off, pl->d_L + off,
+                       pl->nu, pl->nup, pl->d_eleaf);
+    return hipGetLastError();
+}
+
+hipError_t launch_l2p(ankh_plan_s *pl, int ord, bool fields) {
+    const int L = pl->order;
+    const double hinv = 2.0 / (pl->edge / pl->nside);
+    const double *Lam = pl->d_L + pl->lv[pl->depth].cell0 * pl->nup;
+    // one atom per lane; the per-lane basis tables live in LDS (kept within 64 KiB)
+    const int nt = (sizeof(double) * (L * L + pl->nu + 64 * 3 * (ord + 2) * L) <= 65536) ? 64 : 32;
+    const size_t shm = sizeof(double) * (L * L + pl->nu + nt * 3 * (ord + 2) * L);
+    dim3 g((unsigned)pl->nleaf), b(nt);
+#define ANKH_L2P(O, FL) \
+    hipLaunchKernelGGL((k_l2p<O, FL>), g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, L, pl->nu, pl->nup, \
+                       hinv, Lam, pl->d_F, pl->d_G, pl->n)
+    if (ord == 0) { if (fields) ANKH_L2P(0, true); else ANKH_L2P(0, false); }
+    else if (ord == 1) { if (fields) ANKH_L2P(1, true); else ANKH_L2P(1, false); }
+    else { if (fields) ANKH_L2P(2, true); else ANKH_L2P(2, false); }
+#undef ANKH_L2P
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(ankh_plan_s *pl, double *energy_out, int ord) {
+    hipLaunchKernelGGL(k_reduce1, dim3(kRedBlocks), dim3(256), 0, pl->stream, pl->n, pl->nleaf, pl->d_eatom,
+                       pl->d_eleaf, pl->P, ord, pl->xi, pl->d_part);
+    hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(kRedBlocks), 0, pl->stream, pl->d_part, pl->d_terms, energy_out,
+                       pl->xi, pl->edge * pl->edge * pl->edge);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpermute(ankh_plan_s *pl, double *forces, double *dEdmu, bool have_mu) {
+    const double fself = -4.0 * pl->xi * pl->xi * pl->xi / (3.0 * sqrt(kPi));
+    hipLaunchKernelGGL(k_unpermute, dim3(nblk(pl->n, 256)), dim3(256), 0, pl->stream, pl->n, pl->d_perm, pl->d_F,
+                       pl->d_G, pl->P, fself, forces, dEdmu, have_mu ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_m2l(ankh_plan_s *pl, int e, double *K) {
+    const int64_t tot = (int64_t)kNumOff * pl->nup * pl->nup;
+    hipLaunchKernelGGL(k_build_m2l, dim3(nblk(tot, 256)), dim3(256), 0, pl->stream, K, pl->d_tab, pl->order, pl->nu,
+                       pl->nup, pl->lv[e].width, pl->xi);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_cper(ankh_plan_s *pl) {
+    const int64_t tot = (int64_t)pl->nup * pl->nup;
+    hipLaunchKernelGGL(k_build_cper, dim3(nblk(tot, 128)), dim3(128), 0, pl->stream, pl->d_Cper, pl->d_tab, pl->order,
+                       pl->nu, pl->nup, pl->edge, pl->xi, pl->images);
+    return hipGetLastError();
+}
+
+}  // namespace ankh

@@ -1,0 +1,417 @@
+// C ABI of the interpolated-Ewald library: planner (parameter rules, operator
+// tables, device buffers) and the evaluation driver that enqueues the
+// kernels of one energy / energy+forces evaluation on the plan's stream.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ankh_internal.h"
+
+using namespace ankh;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct HipFail {
+    hipError_t e;
+};
+
+inline void ck(hipError_t e) {
+    if (e != hipSuccess) throw HipFail{e};
+}
+
+template <typename T>
+void dalloc(ankh_plan_s *pl, T **p, size_t count) {
+    if (count == 0) count = 1;
+    void *v = nullptr;
+    hipError_t e = hipMalloc(&v, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw std::bad_alloc();
+    }
+    *p = static_cast<T *>(v);
+    pl->bytes += count * sizeof(T);
+}
+
+void free_all(ankh_plan_s *pl) {
+    void *ptrs[] = {pl->d_tab, pl->d_leaf, pl->d_count, pl->d_offs, pl->d_fill, pl->d_perm, pl->d_tmp,
+                    pl->P.x, pl->P.y, pl->P.z, pl->P.q, pl->P.mu, pl->P.th, pl->P.qf, pl->P.muf, pl->P.thf,
+                    pl->d_M, pl->d_L, pl->d_K, pl->d_Kf, pl->d_Cper, pl->d_eatom, pl->d_eleaf, pl->d_F,
+                    pl->d_G, pl->d_terms, pl->d_part, pl->d_err};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (pl->ev_valid)
+        for (auto &e : pl->ev) (void)hipEventDestroy(e);
+}
+
+// Chebyshev order from the accuracy target: the interpolation error decays
+// geometrically in L (numerical-results section); the table is calibrated
+// against the classical-Ewald oracle on the synthetic water and ionic boxes.
+int order_for(double eps) {
+    if (eps >= 1e-4) return 4;
+    if (eps >= 1e-5) return 5;
+    if (eps >= 1e-6) return 6;
+    if (eps >= 1e-7) return 7;
+    if (eps >= 1e-8) return 8;
+    if (eps >= 1e-9) return 9;
+    return 10;
+}
+
+// Depth: leaves whose mean occupancy balances the per-leaf far-field work
+// (189 M2L products of n_u x n_u) against the near-field pair work.
+int depth_for(int64_t n, int nu) {
+    const double occ = std::max(16.0, 0.3 * nu);
+    double e = std::log(std::max(1.0, (double)n / occ)) / std::log(8.0);
+    int E = (int)std::floor(e + 0.5);
+    return std::min(std::max(E, 0), kMaxDepth);
+}
+
+void build_tables(ankh_plan_s *pl) {
+    const int L = pl->order;
+    for (int k = 0; k < L; k++) pl->nodes[k] = std::cos((2 * k + 1) * kPi / (2 * L));
+    // H[k][m] = (1/L)(1 if m = 0 else 2 T_m(r_k))
+    for (int k = 0; k < L; k++) {
+        double t0 = 1, t1 = pl->nodes[k];
+        for (int m = 0; m < L; m++) {
+            double tm = m == 0 ? 1.0 : (m == 1 ? pl->nodes[k] : 0.0);
+            if (m >= 2) {
+                tm = 2 * pl->nodes[k] * t1 - t0;
+                t0 = t1;
+                t1 = tm;
+            }
+            pl->Hm[k * L + m] = (m == 0 ? 1.0 : 2.0 * tm) / L;
+        }
+    }
+    // V[b][a][i] = S_a((r_i -+ 1) / 2): child node i of the low (b = 0) or high (b = 1) child
+    for (int b = 0; b < 2; b++)
+        for (int i = 0; i < L; i++) {
+            const double x = (pl->nodes[i] + (b ? 1.0 : -1.0)) / 2;
+            double T[kMaxOrder];
+            T[0] = 1;
+            if (L > 1) T[1] = x;
+            for (int m = 2; m < L; m++) T[m] = 2 * x * T[m - 1] - T[m - 2];
+            for (int a = 0; a < L; a++) {
+                double s = 0;
+                for (int m = 0; m < L; m++) s += pl->Hm[a * L + m] * T[m];
+                pl->V[b][a * L + i] = s;
+            }
+        }
+}
+
+ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th,
+                double *energy, double *forces, double *dEdmu) {
+    const bool grad = forces != nullptr;
+    const int ord = th ? 2 : (mu ? 1 : 0);
+    const bool fields = grad && dEdmu && ord >= 1;
+    hipStream_t s = pl->stream;
+    auto mark = [&](int i) {
+        if (pl->timing) ck(hipEventRecord(pl->ev[i], s));
+    };
+    try {
+        mark(0);
+        ck(launch_sort(pl, pos, q, mu, th));
+        mark(1);
+        ck(launch_gather(pl, pos, q, mu, th));
+        mark(2);
+        ck(launch_p2m(pl, ord));
+        mark(3);
+        for (int e = pl->depth - 1; e >= 0; e--) ck(launch_m2m(pl, e));
+        mark(4);
+        for (int e = 1; e <= pl->depth; e++) ck(launch_m2l(pl, e));
+        mark(5);
+        ck(launch_cper(pl));
+        mark(6);
+        for (int e = 1; e <= pl->depth; e++) ck(launch_l2l(pl, e));
+        ck(launch_leafdot(pl));
+        mark(7);
+        if (grad) ck(launch_l2p(pl, ord, fields));
+        mark(8);
+        ck(launch_p2p(pl, ord, grad, fields));
+        mark(9);
+        ck(launch_reduce(pl, energy, ord));
+        if (grad) ck(launch_unpermute(pl, forces, dEdmu, ord >= 1));
+        mark(10);
+    } catch (const HipFail &) {
+        return ANKH_ERR_HIP;
+    }
+    pl->last_kind = grad ? 2 : 1;
+    pl->last_order = ord;
+    return ANKH_OK;
+}
+
+ankh_status check_inputs(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th) {
+    if (!pl || !pos || !q) return ANKH_ERR_INVALID_ARG;
+    if (pl->max_order < 1 && mu) return ANKH_ERR_INVALID_ARG;
+    if (pl->max_order < 2 && th) return ANKH_ERR_INVALID_ARG;
+    return ANKH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ankh_status_string(ankh_status st) {
+    switch (st) {
+        case ANKH_OK: return "ok";
+        case ANKH_ERR_INVALID_ARG: return "invalid argument";
+        case ANKH_ERR_NONFINITE_INPUT: return "non-finite input";
+        case ANKH_ERR_THETA_NOT_TRACELESS: return "quadrupole not traceless";
+        case ANKH_ERR_LEAF_OVERFLOW: return "leaf overflow";
+        case ANKH_ERR_ACCURACY_UNREACHABLE: return "accuracy unreachable in this precision";
+        case ANKH_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case ANKH_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, double rel_accuracy, int32_t max_order,
+                      int32_t precision, const ankh_overrides *ov, void *hip_stream) {
+    if (!out) return ANKH_ERR_INVALID_ARG;
+    if (n_atoms < 1 || n_atoms > (int64_t)0x7fffffff) return ANKH_ERR_INVALID_ARG;
+    if (!(box_radius > 0) || !std::isfinite(box_radius)) return ANKH_ERR_INVALID_ARG;
+    if (!(rel_accuracy >= 1e-12 && rel_accuracy <= 1e-2)) return ANKH_ERR_INVALID_ARG;
+    if (max_order < 0 || max_order > 2) return ANKH_ERR_INVALID_ARG;
+    if (precision != ANKH_FP64 && precision != ANKH_MIXED) return ANKH_ERR_INVALID_ARG;
+    if (precision == ANKH_MIXED && rel_accuracy < 1e-7) return ANKH_ERR_ACCURACY_UNREACHABLE;
+    if (ov) {
+        if (ov->depth > kMaxDepth) return ANKH_ERR_INVALID_ARG;
+        if (ov->order > 0 && (ov->order < 2 || ov->order > kMaxOrder)) return ANKH_ERR_INVALID_ARG;
+        if (ov->images > 64) return ANKH_ERR_INVALID_ARG;
+        if (!std::isfinite(ov->xi)) return ANKH_ERR_INVALID_ARG;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    ankh_plan_s *pl = new (std::nothrow) ankh_plan_s();
+    if (!pl) return ANKH_ERR_OUT_OF_MEMORY;
+    pl->n = n_atoms;
+    pl->rB = box_radius;
+    pl->edge = 2 * box_radius;
+    pl->eps = rel_accuracy;
+    pl->max_order = max_order;
+    pl->precision = precision;
+    pl->stream = static_cast<hipStream_t>(hip_stream);
+
+    // splitting parameter: the largest reciprocal weight exp(-(pi/(xi edge))^2)
+    // equals eps/10, so the dropped reciprocal term stays below the target
+    const double s2 = std::log(10.0 / rel_accuracy);
+    pl->xi = (ov && ov->xi > 0) ? ov->xi : kPi / (pl->edge * std::sqrt(s2));
+    // image radius: pairs beyond the cube Z_p are >= p * edge apart, where erfc(xi p edge) <~ eps/10
+    {
+        const double sr = std::sqrt(s2);
+        int p = (int)std::ceil(sr / (pl->xi * pl->edge)) + 1;
+        pl->images = (ov && ov->images > 0) ? ov->images : std::max(p, 2);
+    }
+    pl->order = (ov && ov->order > 0) ? ov->order : order_for(rel_accuracy);
+    pl->nu = pl->order * pl->order * pl->order;
+    pl->nup = (pl->nu + 63) / 64 * 64;
+    pl->depth = (ov && ov->depth >= 0) ? ov->depth : depth_for(n_atoms, pl->nu);
+    pl->nside = 1 << pl->depth;
+    pl->nleaf = (int64_t)pl->nside * pl->nside * pl->nside;
+    size_t cells = 0;
+    for (int e = 0; e <= pl->depth; e++) {
+        Level &lv = pl->lv[e];
+        lv.e = e;
+        lv.nside = 1 << e;
+        lv.ncell = (int64_t)lv.nside * lv.nside * lv.nside;
+        lv.cell0 = cells;
+        lv.width = pl->edge / lv.nside;
+        cells += lv.ncell;
+    }
+    pl->ncell_total = cells;
+    build_tables(pl);
+
+    const int64_t n = n_atoms;
+    try {
+        const int L = pl->order;
+        dalloc(pl, &pl->d_tab, L + L * L + 2 * L * L);
+        std::vector<double> tab(L + 3 * L * L);
+        for (int k = 0; k < L; k++) tab[k] = pl->nodes[k];
+        for (int k = 0; k < L * L; k++) tab[L + k] = pl->Hm[k];
+        for (int b = 0; b < 2; b++)
+            for (int k = 0; k < L * L; k++) tab[L + L * L + b * L * L + k] = pl->V[b][k];
+        ck(hipMemcpy(pl->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+        dalloc(pl, &pl->d_leaf, n);
+        dalloc(pl, &pl->d_count, pl->nleaf);
+        dalloc(pl, &pl->d_offs, pl->nleaf + 1);
+        dalloc(pl, &pl->d_fill, pl->nleaf);
+        dalloc(pl, &pl->d_perm, n);
+        dalloc(pl, &pl->d_tmp, n);
+        dalloc(pl, &pl->P.x, n);
+        dalloc(pl, &pl->P.y, n);
+        dalloc(pl, &pl->P.z, n);
+        dalloc(pl, &pl->P.q, n);
+        if (max_order >= 1) dalloc(pl, &pl->P.mu, 3 * n);
+        if (max_order >= 2) dalloc(pl, &pl->P.th, 6 * n);
+        if (precision == ANKH_MIXED) {
+            dalloc(pl, &pl->P.qf, n);
+            if (max_order >= 1) dalloc(pl, &pl->P.muf, 3 * n);
+            if (max_order >= 2) dalloc(pl, &pl->P.thf, 6 * n);
+        }
+        dalloc(pl, &pl->d_M, cells * pl->nup);
+        dalloc(pl, &pl->d_L, cells * pl->nup);
+        const size_t kper = (size_t)kNumOff * pl->nup * pl->nup;
+        dalloc(pl, &pl->d_Cper, (size_t)pl->nup * pl->nup);
+        dalloc(pl, &pl->d_eatom, n);
+        dalloc(pl, &pl->d_eleaf, pl->nleaf);
+        dalloc(pl, &pl->d_F, 3 * n);
+        dalloc(pl, &pl->d_G, 3 * n);
+        dalloc(pl, &pl->d_terms, 8);
+        dalloc(pl, &pl->d_part, 4 * kRedBlocks);
+        dalloc(pl, &pl->d_err, 4);
+        ck(launch_zero_i32(pl->d_err, 4, pl->stream));
+        ck(launch_zero_f64(pl->d_terms, 8, pl->stream));
+        ck(launch_zero_f64(pl->d_G, 3 * n, pl->stream));
+        ck(launch_zero_f64(pl->d_eatom, n, pl->stream));
+        // operator tables: M2L matrices of levels 1..E and the far-image root operator
+        if (pl->depth >= 1) {
+            if (precision == ANKH_MIXED) {
+                dalloc(pl, &pl->d_Kf, kper * pl->depth);
+                double *tmp = nullptr;
+                ck(hipMalloc((void **)&tmp, kper * sizeof(double)));
+                for (int e = 1; e <= pl->depth; e++) {
+                    ck(launch_build_m2l(pl, e, tmp));
+                    ck(launch_convert_f32(tmp, pl->d_Kf + (size_t)(e - 1) * kper, (int64_t)kper, pl->stream));
+                }
+                ck(hipStreamSynchronize(pl->stream));
+                ck(hipFree(tmp));
+            } else {
+                dalloc(pl, &pl->d_K, kper * pl->depth);
+                for (int e = 1; e <= pl->depth; e++)
+                    ck(launch_build_m2l(pl, e, pl->d_K + (size_t)(e - 1) * kper));
+            }
+        }
+        ck(launch_build_cper(pl));
+        ck(hipStreamSynchronize(pl->stream));
+    } catch (const std::bad_alloc &) {
+        free_all(pl);
+        delete pl;
+        return ANKH_ERR_OUT_OF_MEMORY;
+    } catch (const HipFail &) {
+        free_all(pl);
+        delete pl;
+        return ANKH_ERR_HIP;
+    }
+    pl->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = pl;
+    return ANKH_OK;
+}
+
+ankh_status ankh_energy(ankh_plan_t pl, const double *pos, const double *q, const double *mu, const double *theta,
+                        double *energy) {
+    ankh_status st = check_inputs(pl, pos, q, mu, theta);
+    if (st != ANKH_OK) return st;
+    if (!energy) return ANKH_ERR_INVALID_ARG;
+    return run(pl, pos, q, mu, theta, energy, nullptr, nullptr);
+}
+
+ankh_status ankh_energy_forces(ankh_plan_t pl, const double *pos, const double *q, const double *mu,
+                               const double *theta, double *energy, double *forces, double *dE_dmu) {
+    ankh_status st = check_inputs(pl, pos, q, mu, theta);
+    if (st != ANKH_OK) return st;
+    if (!energy || !forces) return ANKH_ERR_INVALID_ARG;
+    return run(pl, pos, q, mu, theta, energy, forces, dE_dmu);
+}
+
+ankh_status ankh_sync(ankh_plan_t pl) {
+    if (!pl) return ANKH_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(pl->stream) != hipSuccess) return ANKH_ERR_HIP;
+    int32_t err[4] = {0, 0, 0, 0};
+    if (hipMemcpy(err, pl->d_err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return ANKH_ERR_HIP;
+    if (err[0] || err[1]) {
+        if (launch_zero_i32(pl->d_err, 4, pl->stream) != hipSuccess) return ANKH_ERR_HIP;
+        if (hipStreamSynchronize(pl->stream) != hipSuccess) return ANKH_ERR_HIP;
+        return err[0] ? ANKH_ERR_NONFINITE_INPUT : ANKH_ERR_THETA_NOT_TRACELESS;
+    }
+    return ANKH_OK;
+}
+
+ankh_status ankh_set_timing(ankh_plan_t pl, int32_t enable) {
+    if (!pl) return ANKH_ERR_INVALID_ARG;
+    if (enable && !pl->ev_valid) {
+        for (auto &e : pl->ev)
+            if (hipEventCreate(&e) != hipSuccess) return ANKH_ERR_HIP;
+        pl->ev_valid = true;
+    }
+    pl->timing = enable != 0;
+    return ANKH_OK;
+}
+
+ankh_status ankh_get_stats(ankh_plan_t pl, ankh_plan_stats *out) {
+    if (!pl || !out) return ANKH_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(pl->stream) != hipSuccess) return ANKH_ERR_HIP;
+    std::memset(out, 0, sizeof(*out));
+    out->n_atoms = pl->n;
+    out->depth = pl->depth;
+    out->order = pl->order;
+    out->images = pl->images;
+    out->max_order = pl->max_order;
+    out->precision = pl->precision;
+    out->xi = pl->xi;
+    out->box_radius = pl->rB;
+    out->rel_accuracy = pl->eps;
+    out->plan_ms = pl->plan_ms;
+    out->workspace_bytes = (int64_t)pl->bytes;
+    double cells = 0;
+    for (int e = 1; e <= pl->depth; e++) cells += (double)pl->lv[e].ncell;
+    out->m2l_flops = 2.0 * kNumIL * (double)pl->nu * pl->nu * cells;
+    out->near_pairs = -1;
+    if (pl->last_kind) {
+        std::vector<int32_t> offs(pl->nleaf + 1);
+        if (hipMemcpy(offs.data(), pl->d_offs, offs.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+            return ANKH_ERR_HIP;
+        const int ns = pl->nside;
+        int64_t pairs = 0;
+        for (int64_t l = 0; l < pl->nleaf; l++) {
+            const int x = (int)(l / ((int64_t)ns * ns)), y = (int)((l / ns) % ns), z = (int)(l % ns);
+            int64_t src = 0;
+            for (int d = 0; d < 27; d++) {
+                const int sx = (x + d / 9 - 1 + ns) % ns, sy = (y + (d / 3) % 3 - 1 + ns) % ns,
+                          sz = (z + d % 3 - 1 + ns) % ns;
+                const int64_t s = ((int64_t)sx * ns + sy) * ns + sz;
+                src += offs[s + 1] - offs[s];
+            }
+            pairs += (int64_t)(offs[l + 1] - offs[l]) * src;
+        }
+        out->near_pairs = pairs - pl->n;
+    }
+    for (int i = 0; i < kNumStages; i++) out->stage_ms[i] = -1;
+    if (pl->timing && pl->ev_valid && pl->last_kind) {
+        for (int i = 0; i < kNumStages; i++) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, pl->ev[i], pl->ev[i + 1]) == hipSuccess) out->stage_ms[i] = ms;
+        }
+    }
+    return ANKH_OK;
+}
+
+ankh_status ankh_last_terms(ankh_plan_t pl, double *out_host) {
+    if (!pl || !out_host) return ANKH_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(pl->stream) != hipSuccess) return ANKH_ERR_HIP;
+    if (hipMemcpy(out_host, pl->d_terms, 7 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return ANKH_ERR_HIP;
+    return ANKH_OK;
+}
+
+ankh_status ankh_leaf_multipoles(ankh_plan_t pl, double *out_host, int64_t count) {
+    if (!pl || !out_host) return ANKH_ERR_INVALID_ARG;
+    const int64_t need = pl->nleaf * pl->nu;
+    if (count < need) return ANKH_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(pl->stream) != hipSuccess) return ANKH_ERR_HIP;
+    const double *Q = pl->d_M + pl->lv[pl->depth].cell0 * pl->nup;
+    if (hipMemcpy2D(out_host, pl->nu * sizeof(double), Q, pl->nup * sizeof(double), pl->nu * sizeof(double),
+                    pl->nleaf, hipMemcpyDeviceToHost) != hipSuccess)
+        return ANKH_ERR_HIP;
+    return ANKH_OK;
+}
+
+void ankh_destroy(ankh_plan_t pl) {
+    if (!pl) return;
+    (void)hipStreamSynchronize(pl->stream);
+    free_all(pl);
+    delete pl;
+}
+
+}  // extern "C"
