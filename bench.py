@@ -1,0 +1,186 @@
+"""Benchmark of the interpolated-Ewald hot path on one MI355X.
+
+One step = one energy + forces + fields evaluation (the whole hot path:
+sort, P2M, M2M, M2L on every level, far-image root operator, L2L, L2P, P2P,
+reductions) of the synthetic water box of 96,000 rigid 3-site molecules
+(288,000 atoms, edge 142.18 A, charges + dipoles + quadrupoles), inputs
+resident in HBM.  The mixed-precision path is the headline; the FP64 path is
+timed on the same inputs and plan parameters for the speed-up and the
+accuracy of the mixed path.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "E+forces evals/s per atom on 1 MI355X, mixed vs FP64, rel RMS force err"
+
+# flops per ordered near-field pair of the pair kernel for charges + dipoles +
+# quadrupoles with forces and fields, counted from the pair formula
+# (FMA = 2, add / mul = 1, erfc / exp / rsqrt = 1 each)
+P2P_FLOP_PER_PAIR = 380.0
+
+PEAK = {  # MI355X, TFLOP/s
+    "valu_fp64": 78.6,    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+    "valu_fp32": 78.6,    # same issue rate without packed FP32 (disabled in this build)
+    "mfma_fp64": 78.6,
+    "mfma_fp32": 157.3,
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def rel_rms(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def timed_run(plan, args_dev, steps, warmup, torch):
+    for _ in range(warmup):
+        plan.energy_forces(*args_dev)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = plan.energy_forces(*args_dev)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    stats = plan.get_stats()
+    plan.set_timing(False)
+    plan.sync()
+    return dt, stats, out
+
+
+def cpu_baseline(data, eps):
+    """The classical-Ewald oracle on a bounded cut-out of the same water box."""
+    import oracle
+    import synth
+    sub_edge = (2000 / synth.WATER_DENSITY) ** (1.0 / 3.0)     # ~2000 molecules, same density
+    cut = synth.water_cutout(data, sub_edge)
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n = len(cut["q"])
+    t0 = time.perf_counter()
+    oracle.ewald(cut["pos"], cut["q"], cut["mu"], cut["theta"], edge=cut["edge"], eps=eps, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "atoms*evals/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"classical-Ewald oracle, energy+forces+fields, on a periodic cut-out of {n} atoms "
+                      f"(whole molecules, edge {cut['edge']:.2f} A) of the benchmark box, accuracy {eps:g}; "
+                      f"{dt:.2f} s wall; Ewald cost grows as N^1.5, so per-atom throughput at 288,000 atoms "
+                      f"would be lower"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="water_288000")
+    ap.add_argument("--eps", type=float, default=1e-6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed-only", action="store_true", help="skip the FP64 comparison run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU sharding is a "
+              f"design only (DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    import paper_2212_08284_amd as ak
+    import synth
+
+    data = synth.workload(args.workload)
+    n = len(data["q"])
+    dev = torch.device("cuda:0")
+
+    def T(a):
+        return None if a is None else torch.tensor(a, dtype=torch.float64, device=dev)
+
+    args_dev = (T(data["pos"]), T(data["q"]), T(data["mu"]), T(data["theta"]))
+    rB = 0.5 * data["edge"]
+    log(f"workload {args.workload}: n={n} edge={data['edge']:.3f}")
+
+    pm = ak.Plan(n, rB, args.eps, 2, "mixed")
+    log(f"mixed plan: {pm.stats}")
+    t_mixed, st_mixed, out_mixed = timed_run(pm, args_dev, args.steps, args.warmup, torch)
+    log(f"mixed: {t_mixed * 1e3:.3f} ms/step stages {st_mixed['stage_ms']}")
+
+    res = {}
+    if not args.mixed_only:
+        pf = ak.Plan(n, rB, args.eps, 2, "fp64")
+        t_fp64, st_fp64, out_fp64 = timed_run(pf, args_dev, args.steps, args.warmup, torch)
+        log(f"fp64: {t_fp64 * 1e3:.3f} ms/step stages {st_fp64['stage_ms']}")
+        Em, Fm, Gm = [x.double().cpu().numpy() for x in out_mixed]
+        Ef, Ff, Gf = [x.double().cpu().numpy() for x in out_fp64]
+        res = {
+            "fp64_ms_per_step": t_fp64 * 1e3,
+            "fp64_value": n / t_fp64,
+            "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
+            "mixed_vs_fp64": {"rel_energy_err": float(abs(Em[0] - Ef[0]) / abs(Ef[0])),
+                              "rel_rms_force_err": rel_rms(Fm, Ff), "rel_rms_field_err": rel_rms(Gm, Gf)},
+            "fp64_stage_ms": st_fp64["stage_ms"],
+        }
+        pf.close()
+
+    # roofline of the dominant kernel of the timed (mixed) path, from the live hipEvent stage timings
+    sm = st_mixed["stage_ms"]
+    if sm["p2p"] >= sm["m2l"]:
+        flops = st_mixed["near_pairs"] * P2P_FLOP_PER_PAIR
+        achieved = flops / (sm["p2p"] * 1e-3) / 1e12
+        roof = {"kernel": "p2p", "bound": "alu", "achieved": achieved, "peak": PEAK["valu_fp32"],
+                "unit": "TFLOP/s", "frac": achieved / PEAK["valu_fp32"], "traffic": None,
+                "flop_per_launch": flops, "avg_launch_ms": sm["p2p"],
+                "note": "FP32 vector peak without packed FP32 (157.3 TFLOP/s needs packed FP32, disabled)"}
+    else:
+        flops = st_mixed["m2l_flops"]
+        achieved = flops / (sm["m2l"] * 1e-3) / 1e12
+        roof = {"kernel": "m2l", "bound": "mfma", "achieved": achieved, "peak": PEAK["mfma_fp32"],
+                "unit": "TFLOP/s", "frac": achieved / PEAK["mfma_fp32"], "traffic": None,
+                "flop_per_launch": flops, "avg_launch_ms": sm["m2l"]}
+
+    line = {
+        "metric": METRIC,
+        "value": n / t_mixed,
+        "unit": "atoms*evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_mixed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: rigid 3-site water, q+mu+Theta, energy+forces+fields",
+                   "n_atoms": n, "edge_A": data["edge"], "rel_accuracy": args.eps,
+                   "depth": st_mixed["depth"], "order": st_mixed["order"], "images": st_mixed["images"],
+                   "xi": st_mixed["xi"], "parallelism": "single GPU"},
+        "evals_per_s": 1.0 / t_mixed,
+        "ns_per_day_equiv_dt2fs": 86400.0 / t_mixed * 2e-6,
+        "stage_ms": sm,
+        "roofline": roof,
+    }
+    line.update(res)
+    pm.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(data, args.eps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -84,11 +84,13 @@ typedef struct {
     int64_t workspace_bytes;   /* device memory owned by the plan */
     double m2l_flops;          /* algorithmic M2L flops per evaluation (2 * 189 * n_u^2 per cell) */
     int64_t near_pairs;        /* ordered near-field pairs of the last evaluation (-1 if unknown) */
-    /* per-stage device time of the last evaluation in ms (hipEvent), valid when
-       timing is enabled with ankh_set_timing; -1 otherwise.
-       Stages: 0 bin+sort, 1 gather, 2 p2m, 3 m2m, 4 m2l, 5 periodic root,
-               6 l2l, 7 l2p, 8 p2p, 9 reduce + unpermute */
+    /* per-stage device time in ms (hipEvents on the plan's stream), averaged
+       over the evaluations run since timing was last enabled with
+       ankh_set_timing; -1 when there were none.
+       Stages: 0 bin+sort, 1 gather, 2 p2m, 3 m2m, 4 m2l (all levels), 5 periodic root,
+               6 l2l + leaf energies, 7 l2p, 8 p2p, 9 reduce + unpermute */
     double stage_ms[10];
+    int64_t timed_evals;       /* evaluations averaged into stage_ms */
 } ankh_plan_stats;
 
 /*
@@ -141,7 +143,7 @@ ankh_status ankh_sync(ankh_plan_t plan);
 /* Copies the plan's parameters and statistics (synchronises the plan's stream). */
 ankh_status ankh_get_stats(ankh_plan_t plan, ankh_plan_stats *out);
 
-/* Enables (1) or disables (0) per-stage hipEvent timing of later evaluations. */
+/* Enables (1, restarting the averaging window) or disables (0) per-stage hipEvent timing of later evaluations. */
 ankh_status ankh_set_timing(ankh_plan_t plan, int32_t enable);
 
 /*

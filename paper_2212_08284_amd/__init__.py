@@ -48,7 +48,7 @@ class _Stats(ctypes.Structure):
                 ("images", ctypes.c_int32), ("max_order", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("xi", ctypes.c_double), ("box_radius", ctypes.c_double), ("rel_accuracy", ctypes.c_double),
                 ("plan_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_int64), ("m2l_flops", ctypes.c_double),
-                ("near_pairs", ctypes.c_int64), ("stage_ms", ctypes.c_double * 10)]
+                ("near_pairs", ctypes.c_int64), ("stage_ms", ctypes.c_double * 10), ("timed_evals", ctypes.c_int64)]
 
 
 _lib = None
@@ -173,6 +173,10 @@ def ankh_leaf_multipoles(plan, count: int):
 def ankh_destroy(plan):
     if plan is not None and plan.value:
         load_library().ankh_destroy(plan)
+
+
+def ankh_status_string(status: int) -> str:
+    return load_library().ankh_status_string(int(status)).decode()
 
 
 # ---- convenience wrapper ----------------------------------------------------------

@@ -4,8 +4,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "ankh.h"
 
@@ -87,8 +89,9 @@ struct ankh_plan_s {
     // statistics / timing
     double plan_ms = 0;
     bool timing = false;
-    hipEvent_t ev[ankh::kNumStages + 1] = {};
-    bool ev_valid = false;
+    // one set of stage-boundary events per timed evaluation since timing was enabled
+    std::vector<std::array<hipEvent_t, ankh::kNumStages + 1>> evsets;
+    int64_t n_timed = 0;
     int last_kind = 0;            // 0 none, 1 energy, 2 energy+forces
     int last_order = 0;
 };

@@ -45,8 +45,9 @@ void free_all(ankh_plan_s *pl) {
                     pl->d_G, pl->d_terms, pl->d_part, pl->d_err};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    if (pl->ev_valid)
-        for (auto &e : pl->ev) (void)hipEventDestroy(e);
+    for (auto &set : pl->evsets)
+        for (auto &e : set) (void)hipEventDestroy(e);
+    pl->evsets.clear();
 }
 
 // Chebyshev order from the accuracy target: the interpolation error decays
@@ -109,8 +110,18 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
     const int ord = th ? 2 : (mu ? 1 : 0);
     const bool fields = grad && dEdmu && ord >= 1;
     hipStream_t s = pl->stream;
+    hipEvent_t *ev = nullptr;
+    if (pl->timing) {
+        if ((size_t)pl->n_timed == pl->evsets.size()) {
+            std::array<hipEvent_t, kNumStages + 1> set{};
+            for (auto &e : set)
+                if (hipEventCreate(&e) != hipSuccess) return ANKH_ERR_HIP;
+            pl->evsets.push_back(set);
+        }
+        ev = pl->evsets[pl->n_timed].data();
+    }
     auto mark = [&](int i) {
-        if (pl->timing) ck(hipEventRecord(pl->ev[i], s));
+        if (ev) ck(hipEventRecord(ev[i], s));
     };
     try {
         mark(0);
@@ -141,6 +152,7 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
     }
     pl->last_kind = grad ? 2 : 1;
     pl->last_order = ord;
+    if (ev) pl->n_timed++;
     return ANKH_OK;
 }
 
@@ -331,11 +343,7 @@ ankh_status ankh_sync(ankh_plan_t pl) {
 
 ankh_status ankh_set_timing(ankh_plan_t pl, int32_t enable) {
     if (!pl) return ANKH_ERR_INVALID_ARG;
-    if (enable && !pl->ev_valid) {
-        for (auto &e : pl->ev)
-            if (hipEventCreate(&e) != hipSuccess) return ANKH_ERR_HIP;
-        pl->ev_valid = true;
-    }
+    if (enable) pl->n_timed = 0;   // restart the averaging window
     pl->timing = enable != 0;
     return ANKH_OK;
 }
@@ -379,10 +387,16 @@ ankh_status ankh_get_stats(ankh_plan_t pl, ankh_plan_stats *out) {
         out->near_pairs = pairs - pl->n;
     }
     for (int i = 0; i < kNumStages; i++) out->stage_ms[i] = -1;
-    if (pl->timing && pl->ev_valid && pl->last_kind) {
+    out->timed_evals = pl->n_timed;
+    if (pl->n_timed > 0) {
         for (int i = 0; i < kNumStages; i++) {
-            float ms = 0;
-            if (hipEventElapsedTime(&ms, pl->ev[i], pl->ev[i + 1]) == hipSuccess) out->stage_ms[i] = ms;
+            double sum = 0;
+            for (int64_t t = 0; t < pl->n_timed; t++) {
+                float ms = 0;
+                if (hipEventElapsedTime(&ms, pl->evsets[t][i], pl->evsets[t][i + 1]) != hipSuccess) return ANKH_ERR_HIP;
+                sum += ms;
+            }
+            out->stage_ms[i] = sum / pl->n_timed;
         }
     }
     return ANKH_OK;

@@ -1,0 +1,162 @@
+"""Pins of the NumPy transcription of the method (oracle/ankh_ref) against
+facts fixed by the mathematics, not by the transcription itself:
+
+* Lagrange property of the Chebyshev basis: S_k(r_j) = delta_kj, and the
+  differentiation matrix reproduces T_n' = n U_{n-1};
+* anterpolation reproduces polynomial moments exactly (degree < L per axis):
+  total charge, dipole moment sum(q x + mu), second moment
+  sum(q x x^T + mu x^T + x mu^T + 2 Theta);
+* M2M preserves those moments from children to parent;
+* the far-image root operator equals a direct image sum of the kernel;
+* forces and fields are the exact gradient of the approximate energy
+  (central finite differences);
+* the approximation converges geometrically in L to the classical-Ewald
+  value, and agrees across tree depths within the approximation error.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import ankh_ref as R
+
+
+@pytest.mark.parametrize("L", [2, 3, 5, 8])
+def test_lagrange_property(L):
+    r = R.cheb_nodes(L)
+    S = R.cheb_T(r, L) @ R.cheb_H(L).T          # S[j, k] = S_k(r_j)
+    np.testing.assert_allclose(S, np.eye(L), atol=1e-13)
+
+
+@pytest.mark.parametrize("L", [3, 6, 9])
+def test_differentiation_matrix(L):
+    x = np.linspace(-0.97, 0.97, 11)
+    dT = R.cheb_T(x, L) @ R.cheb_D(L).T
+    # T_n'(x) = n U_{n-1}(x), U by its own recurrence
+    U = np.zeros((len(x), L))
+    U[:, 0] = 1
+    if L > 1:
+        U[:, 1] = 2 * x
+    for m in range(2, L):
+        U[:, m] = 2 * x * U[:, m - 1] - U[:, m - 2]
+    ref = np.zeros_like(dT)
+    for n in range(1, L):
+        ref[:, n] = n * U[:, n - 1]
+    np.testing.assert_allclose(dT, ref, atol=1e-11)
+    assert np.allclose(np.triu(R.cheb_D(L)), 0)   # strictly lower triangular
+
+
+def _leaf_moments(Q, L, centre, h):
+    nodes = R.nodes3d(L) * h + centre               # physical node positions
+    m0 = Q.sum()
+    m1 = nodes.T @ Q
+    m2 = np.einsum("ka,kb,k->ab", nodes, nodes, Q)
+    return m0, m1, m2
+
+
+def test_p2m_reproduces_moments():
+    rng = np.random.default_rng(1)
+    edge, E, L = 10.0, 0, 4
+    n = 12
+    pos = rng.uniform(-5, 5, (n, 3))
+    q = rng.normal(size=n)
+    mu = rng.normal(size=(n, 3)) * 0.3
+    th = synth.random_traceless_theta(rng, n, 0.2)
+    out = R.evaluate(pos, q, mu, th, edge, E, L, 0.1, 2, grad=False, keep=True)
+    Q = out["Q"].reshape(-1)
+    m0, m1, m2 = _leaf_moments(Q, L, np.zeros(3), 0.5 * edge)
+    x = R.wrap(pos, edge)
+    Th = np.stack([np.stack([th[:, 0], th[:, 1], th[:, 2]], 1), np.stack([th[:, 1], th[:, 3], th[:, 4]], 1),
+                   np.stack([th[:, 2], th[:, 4], th[:, 5]], 1)], 1)
+    assert m0 == pytest.approx(q.sum(), abs=1e-12)
+    np.testing.assert_allclose(m1, (q[:, None] * x + mu).sum(0), atol=1e-11)
+    want = (np.einsum("n,na,nb->ab", q, x, x) + np.einsum("na,nb->ab", mu, x) + np.einsum("na,nb->ab", x, mu)
+            + 2 * Th.sum(0))
+    np.testing.assert_allclose(m2, want, atol=1e-10)
+
+
+def test_m2m_preserves_moments():
+    rng = np.random.default_rng(2)
+    edge, E, L = 12.0, 2, 4
+    n = 200
+    pos = rng.uniform(-6, 6, (n, 3))
+    q = rng.normal(size=n)
+    mu = rng.normal(size=(n, 3)) * 0.3
+    out = R.evaluate(pos, q, mu, None, edge, E, L, 0.1, 2, grad=False, keep=True)
+    M = out["M"]
+    for e in range(E):
+        ns = 1 << e
+        w = edge / ns
+        for cell in itertools.product(range(ns), repeat=3):
+            c = -0.5 * edge + (np.array(cell) + 0.5) * w
+            par = _leaf_moments(M[e][cell], L, c, 0.5 * w)
+            acc = [0.0, np.zeros(3), np.zeros((3, 3))]
+            for b in itertools.product((0, 1), repeat=3):
+                ch = tuple(2 * np.array(cell) + np.array(b))
+                cc = -0.5 * edge + (np.array(ch) + 0.5) * (w / 2)
+                m = _leaf_moments(M[e + 1][ch], L, cc, 0.25 * w)
+                for k in range(3):
+                    acc[k] = acc[k] + m[k]
+            assert par[0] == pytest.approx(acc[0], abs=1e-11)
+            np.testing.assert_allclose(par[1], acc[1], atol=1e-10)
+            np.testing.assert_allclose(par[2], acc[2], atol=1e-9)
+
+
+def test_root_operator_is_image_sum():
+    L, edge, xi, p = 3, 7.0, 0.2, 3
+    C = R.periodic_root_matrix(edge, L, xi, p)
+    g = R.nodes3d(L) * 0.5 * edge
+    k, l = 5, 17
+    s = 0.0
+    for I in itertools.product(range(-p, p + 1), repeat=3):
+        if max(map(abs, I)) < 2:
+            continue
+        r = np.linalg.norm(g[k] - g[l] - edge * np.array(I))
+        s += math.erfc(xi * r) / r
+    assert C[k, l] == pytest.approx(s, rel=1e-13)
+    np.testing.assert_allclose(C, C.T, rtol=1e-13)
+
+
+def test_reference_gradient_is_exact():
+    d = synth.water(40, seed=3)
+    edge = d["edge"]
+    E, L, xi, p = 1, 4, 0.08, 3
+    base = R.evaluate(d["pos"], d["q"], d["mu"], d["theta"], edge, E, L, xi, p, grad=True)
+    h = 1e-5
+    for i in (4, 50):
+        for c in range(3):
+            vals = []
+            for s in (1, -1):
+                pp = d["pos"].copy()
+                pp[i, c] += s * h
+                vals.append(R.evaluate(pp, d["q"], d["mu"], d["theta"], edge, E, L, xi, p, grad=False)["energy"])
+            assert -(vals[0] - vals[1]) / (2 * h) == pytest.approx(base["forces"][i, c], rel=1e-6, abs=1e-7)
+            vals = []
+            for s in (1, -1):
+                mm = d["mu"].copy()
+                mm[i, c] += s * h
+                vals.append(R.evaluate(d["pos"], d["q"], mm, d["theta"], edge, E, L, xi, p, grad=False)["energy"])
+            assert (vals[0] - vals[1]) / (2 * h) == pytest.approx(base["dEdmu"][i, c], rel=1e-6, abs=1e-7)
+
+
+def test_geometric_convergence_to_ewald():
+    d = synth.water(150, seed=8)
+    edge = d["edge"]
+    ex = oracle.ewald(d["pos"], d["q"], d["mu"], d["theta"], edge=edge, eps=1e-13)
+    s2 = math.log(10 / 1e-7)
+    xi = math.pi / (edge * math.sqrt(s2))
+    p = int(math.ceil(math.sqrt(s2) / (xi * edge))) + 1
+    errs = []
+    for L in (3, 4, 6):
+        r = R.evaluate(d["pos"], d["q"], d["mu"], d["theta"], edge, 1, L, xi, p, grad=True)
+        errs.append((abs(r["energy"] - ex["energy"]) / abs(ex["energy"]),
+                     np.sqrt(np.sum((r["forces"] - ex["forces"]) ** 2) / np.sum(ex["forces"] ** 2))))
+    assert errs[0][1] > errs[1][1] > errs[2][1]
+    assert errs[0][0] > errs[2][0]
+    assert errs[2][0] < 2e-6 and errs[2][1] < 2e-5
+    # depth consistency: depth 0 and depth 1 agree within the approximation error
+    r0 = R.evaluate(d["pos"], d["q"], d["mu"], d["theta"], edge, 0, 6, xi, p, grad=False)
+    assert abs(r0["energy"] - ex["energy"]) < 2e-6 * abs(ex["energy"])
