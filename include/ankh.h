@@ -74,11 +74,13 @@ typedef struct {
     int32_t order;   /* Chebyshev interpolation order L per axis, 2..10 */
     int32_t images;  /* image radius p: images I with |I|_inf <= p are summed */
     double xi;       /* Ewald splitting parameter (1/Angstrom) */
+    int32_t root_order; /* order of the root grid that carries the far images, 2..12 (depth >= 1) */
 } ankh_overrides;
 
 typedef struct {
     int64_t n_atoms;
     int32_t depth, order, images, max_order, precision;
+    int32_t root_order;        /* order of the root grid of the far-image operator */
     double xi, box_radius, rel_accuracy;
     double plan_ms;            /* wall time of ankh_plan (operator tables included) */
     int64_t workspace_bytes;   /* device memory owned by the plan */

@@ -122,12 +122,14 @@ def nodes3d(L: int) -> np.ndarray:
     return g.reshape(-1, 3)
 
 
-def m2m_1d(L: int):
-    """V[b][a, i] = S_a(child node i in parent coordinates), b = 0 low, 1 high child."""
-    r = cheb_nodes(L)
-    H = cheb_H(L)
-    lo = cheb_T((r - 1) / 2, L) @ H.T     # [i, a]
-    hi = cheb_T((r + 1) / 2, L) @ H.T
+def m2m_1d(Lp: int, Lc: int | None = None):
+    """V[b][a, i] = S_a(child node i in parent coordinates), b = 0 low, 1 high child;
+    parent order Lp, child order Lc (equal on the octree levels; the root may be finer)."""
+    Lc = Lp if Lc is None else Lc
+    r = cheb_nodes(Lc)
+    H = cheb_H(Lp)
+    lo = cheb_T((r - 1) / 2, Lp) @ H.T     # [i, a]
+    hi = cheb_T((r + 1) / 2, Lp) @ H.T
     return [lo.T.copy(), hi.T.copy()]
 
 
@@ -172,7 +174,9 @@ def _valid_mask(n, d):
 # ---- evaluation --------------------------------------------------------------
 
 def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, p: int,
-             grad: bool = True, nthreads: int = 0, keep: bool = False) -> dict:
+             grad: bool = True, nthreads: int = 0, keep: bool = False, root_order: int | None = None) -> dict:
+    """root_order: Chebyshev order of the root grid that carries the far
+    images (depth >= 1); defaults to `order`."""
     pos = wrap(_c64(pos, (-1, 3)), edge)
     N = pos.shape[0]
     q = _c64(q, (N,))
@@ -213,16 +217,19 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
 
     # upward pass (M2M) to the root
     V = m2m_1d(L)
+    L0 = L if (E == 0 or root_order is None) else int(root_order)
+    V0 = m2m_1d(L0, L)          # level 1 -> root
     M = [None] * (E + 1)
     M[E] = Q.reshape(nleaf_ax, nleaf_ax, nleaf_ax, nu)
     for e in range(E - 1, -1, -1):
         n = 1 << e
         child = M[e + 1].reshape(n, 2, n, 2, n, 2, L, L, L)
-        par = np.zeros((n, n, n, L, L, L))
+        Vp, Lp = (V0, L0) if e == 0 else (V, L)
+        par = np.zeros((n, n, n, Lp, Lp, Lp))
         for bx, by, bz in itertools.product((0, 1), repeat=3):
-            par += np.einsum("ai,bj,ck,xyzijk->xyzabc", V[bx], V[by], V[bz],
+            par += np.einsum("ai,bj,ck,xyzijk->xyzabc", Vp[bx], Vp[by], Vp[bz],
                              child[:, bx, :, by, :, bz])
-        M[e] = par.reshape(n, n, n, nu)
+        M[e] = par.reshape(n, n, n, Lp ** 3)
 
     # far field by M2L on every level 1..E (cells of the adjacent images included)
     offs = interaction_offsets()
@@ -240,9 +247,10 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
         e_far_levels.append(0.5 * float(np.sum(M[e] * acc)))
 
     # far periodic images through the root
-    Cper = periodic_root_matrix(edge, L, xi, p)
-    Lroot = M[0].reshape(nu) @ Cper.T
-    e_per = 0.5 * float(M[0].reshape(nu) @ Lroot)
+    nu0 = L0 ** 3
+    Cper = periodic_root_matrix(edge, L0, xi, p)
+    Lroot = M[0].reshape(nu0) @ Cper.T
+    e_per = 0.5 * float(M[0].reshape(nu0) @ Lroot)
 
     # near field: direct pair sums over adjacent leaves
     eatom = np.zeros(N)
@@ -271,14 +279,15 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
 
     if grad:
         # downward pass: L2L is the transpose of M2M
-        Lam = Lroot.reshape(1, 1, 1, nu)
+        Lam = Lroot.reshape(1, 1, 1, nu0)
         for e in range(1, E + 1):
             n = 1 << e
             down = np.zeros((n, n, n, L, L, L))
-            par = Lam.reshape(n // 2, n // 2, n // 2, L, L, L)
+            Vp, Lp = (V0, L0) if e == 1 else (V, L)
+            par = Lam.reshape(n // 2, n // 2, n // 2, Lp, Lp, Lp)
             dv = down.reshape(n // 2, 2, n // 2, 2, n // 2, 2, L, L, L)
             for bx, by, bz in itertools.product((0, 1), repeat=3):
-                dv[:, bx, :, by, :, bz] += np.einsum("ai,bj,ck,xyzabc->xyzijk", V[bx], V[by], V[bz], par)
+                dv[:, bx, :, by, :, bz] += np.einsum("ai,bj,ck,xyzabc->xyzijk", Vp[bx], Vp[by], Vp[bz], par)
             Lam = down.reshape(n, n, n, nu) + Lloc[e]
         Lam_leaf = Lam.reshape(-1, L, L, L)[leaf]          # [N, L, L, L]
         # L2P: derivatives of phi(y) = sum_k Lam_k S_k(y) up to order 3

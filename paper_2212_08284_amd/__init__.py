@@ -40,13 +40,13 @@ class AnkhError(RuntimeError):
 
 class _Overrides(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("order", ctypes.c_int32), ("images", ctypes.c_int32),
-                ("xi", ctypes.c_double)]
+                ("xi", ctypes.c_double), ("root_order", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("n_atoms", ctypes.c_int64), ("depth", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("images", ctypes.c_int32), ("max_order", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("xi", ctypes.c_double), ("box_radius", ctypes.c_double), ("rel_accuracy", ctypes.c_double),
+                ("root_order", ctypes.c_int32), ("xi", ctypes.c_double), ("box_radius", ctypes.c_double), ("rel_accuracy", ctypes.c_double),
                 ("plan_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_int64), ("m2l_flops", ctypes.c_double),
                 ("near_pairs", ctypes.c_int64), ("stage_ms", ctypes.c_double * 10), ("timed_evals", ctypes.c_int64)]
 
@@ -116,13 +116,14 @@ def _dev(t, n_cols, n, name, optional=False):
 
 def ankh_plan(n_atoms: int, box_radius: float, rel_accuracy: float, max_order: int = 2,
               precision: int = ANKH_FP64, depth: int | None = None, order: int | None = None,
-              images: int | None = None, xi: float | None = None, stream=None):
+              images: int | None = None, xi: float | None = None, root_order: int | None = None, stream=None):
     """Create a plan; returns the opaque handle (ctypes.c_void_p)."""
     L = load_library()
     if not torch.cuda.is_available():
         raise RuntimeError("no GPU: the interpolated-Ewald library runs on the GPU only")
     ov = _Overrides(-1 if depth is None else int(depth), 0 if order is None else int(order),
-                    0 if images is None else int(images), 0.0 if xi is None else float(xi))
+                    0 if images is None else int(images), 0.0 if xi is None else float(xi),
+                    0 if root_order is None else int(root_order))
     if stream is None:
         stream = torch.cuda.current_stream()
     h = ctypes.c_void_p()
@@ -185,12 +186,12 @@ class Plan:
     """A plan for n atoms in a cubic box of half-edge box_radius (see ankh.h)."""
 
     def __init__(self, n_atoms, box_radius, rel_accuracy=1e-6, max_order=2, precision="fp64", depth=None,
-                 order=None, images=None, xi=None, stream=None):
+                 order=None, images=None, xi=None, root_order=None, stream=None):
         prec = {"fp64": ANKH_FP64, "mixed": ANKH_MIXED}[precision] if isinstance(precision, str) else int(precision)
         self.n = int(n_atoms)
         self.max_order = int(max_order)
         self.handle = ankh_plan(n_atoms, box_radius, rel_accuracy, max_order, prec, depth, order, images, xi,
-                                stream)
+                                root_order, stream)
         self.stats = ankh_get_stats(self.handle)
 
     def _args(self, pos, q, mu, theta):

@@ -13,7 +13,9 @@
 
 namespace ankh {
 
-constexpr int kMaxOrder = 10;        // largest Chebyshev order per axis
+constexpr int kMaxOrder = 10;        // largest Chebyshev order per axis of the octree levels
+constexpr int kMaxRootOrder = 12;    // largest order of the root (far-image) grid
+constexpr int kMaxRootNodes = kMaxRootOrder * kMaxRootOrder * kMaxRootOrder;
 constexpr int kMaxDepth = 7;         // 2^21 leaves at most
 constexpr int kNumOff = 343;         // slots for offsets d in [-3,3]^3 (316 used)
 constexpr int kNumIL = 189;          // interaction-list length of every cell
@@ -52,6 +54,7 @@ struct ankh_plan_s {
     int64_t n = 0;
     double rB = 0, edge = 0, eps = 0, xi = 0;
     int depth = 0, order = 0, nu = 0, nup = 0, images = 0, max_order = 0, precision = 0;
+    int order0 = 0, nu0 = 0, nup0 = 0;   // root grid (far images): its own order
     hipStream_t stream = nullptr;
     int nside = 1;
     int64_t nleaf = 1;
@@ -65,6 +68,10 @@ struct ankh_plan_s {
 
     // device buffers
     double *d_tab = nullptr;      // nodes[L], H[L*L], V[2][L*L]
+    double *d_tab0 = nullptr;     // root: nodes[L0], V0[2][L0][L] (level-1 child nodes in root coordinates)
+    double *d_rootM = nullptr;    // root multipole / local expansions [nup0]: separate buffers when
+    double *d_rootL = nullptr;    // depth >= 1, else the level-0 rows of d_M / d_L
+    bool root_owned = false;
     int32_t *d_leaf = nullptr;    // leaf id per input atom
     int32_t *d_count = nullptr;   // atoms per leaf
     int32_t *d_offs = nullptr;    // CSR offsets [nleaf + 1]
@@ -76,7 +83,7 @@ struct ankh_plan_s {
     double *d_L = nullptr;        // local expansions, all levels [cells][nup]
     double *d_K = nullptr;        // fp64 M2L matrices: level e>=1 at (e-1) * 343 * nup * nup, [d][l][k]
     float *d_Kf = nullptr;        // fp32 copy for the mixed mode
-    double *d_Cper = nullptr;     // far-image root operator [nup][nup]
+    double *d_Cper = nullptr;     // far-image root operator [nup0][nup0]
     double *d_eatom = nullptr;    // near-field energy per leaf-order atom
     double *d_eleaf = nullptr;    // far energy per leaf
     double *d_F = nullptr;        // forces in leaf order [3][n]

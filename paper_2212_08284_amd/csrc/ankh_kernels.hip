@@ -4,6 +4,7 @@
 // Cell and leaf numbering: cell (i, j, k) of level e is (i * 2^e + j) * 2^e + k;
 // interpolation node (a, b, c) of a cell is (a * L + b) * L + c; expansions are
 // stored cell-major with a row stride nup >= L^3 (a multiple of 64, zero padded).
+#include <algorithm>
 #include <cmath>
 
 #include "ankh_internal.h"
@@ -262,104 +263,109 @@ __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, c
     for (int node = tid + 1024; node < nup; node += 256) Q[leaf * nup + node] = 0.0;
 }
 
-// ---- M2M: parent expansion from the 8 children (three 1D passes) ---------
-__global__ __launch_bounds__(256) void k_m2m(const double *Mc, double *Mp, const double *tab, int L, int nu,
-                                             int nup, int ns_par) {
+// ---- M2M: parent expansion (order Lp) from its 8 children (order Lc) ----------
+// M_p[a,b,c] = sum_children sum_{i,j,k} V[bx][a][i] V[by][b][j] V[bz][c][k] M_child[i,j,k],
+// V[b][a][i] = S_a(child node i in parent coordinates), applied as three 1D passes.
+__global__ __launch_bounds__(256) void k_m2m(const double *Mc, double *Mp, const double *Vg, int Lp, int Lc,
+                                             int nupc, int nupp, int ns_par) {
     extern __shared__ double sm[];
-    double *sV = sm;             // [2][L*L]
-    double *b0 = sV + 2 * L * L; // nu
-    double *b1 = b0 + nu;        // nu
+    const int nc = Lc * Lc * Lc, np = Lp * Lp * Lp;
+    const int nbuf = max(nc, max(Lc * Lc * Lp, Lc * Lp * Lp));
+    double *sV = sm;                 // [2][Lp][Lc]
+    double *b0 = sV + 2 * Lp * Lc;   // nbuf
+    double *b1 = b0 + nbuf;          // nbuf
     const int tid = threadIdx.x;
-    for (int t = tid; t < 2 * L * L; t += 256) sV[t] = tab[L + L * L + t];
+    for (int t = tid; t < 2 * Lp * Lc; t += 256) sV[t] = Vg[t];
     const int64_t p = blockIdx.x;
     const int px = (int)(p / ((int64_t)ns_par * ns_par)), py = (int)((p / ns_par) % ns_par), pz = (int)(p % ns_par);
     const int nsc = 2 * ns_par;
-    double acc[4] = {0, 0, 0, 0};
-    const int LL = L * L;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int VS = Lp * Lc;
     for (int bits = 0; bits < 8; bits++) {
         const int bx = bits >> 2, by = (bits >> 1) & 1, bz = bits & 1;
         const int64_t c = ((int64_t)(2 * px + bx) * nsc + (2 * py + by)) * nsc + (2 * pz + bz);
         __syncthreads();
-        for (int t = tid; t < nu; t += 256) b0[t] = Mc[c * nup + t];
+        for (int t = tid; t < nc; t += 256) b0[t] = Mc[c * nupc + t];
         __syncthreads();
-        const double *Vz = sV + bz * LL, *Vy = sV + by * LL, *Vx = sV + bx * LL;
-        for (int t = tid; t < nu; t += 256) {   // (i, j, cz)
-            const int ij = t / L, cz = t % L;
+        const double *Vz = sV + bz * VS, *Vy = sV + by * VS, *Vx = sV + bx * VS;
+        for (int t = tid; t < Lc * Lc * Lp; t += 256) {   // (i, j, cz)
+            const int ij = t / Lp, cz = t % Lp;
             double s = 0;
-            for (int k = 0; k < L; k++) s += Vz[cz * L + k] * b0[ij * L + k];
+            for (int k = 0; k < Lc; k++) s += Vz[cz * Lc + k] * b0[ij * Lc + k];
             b1[t] = s;
         }
         __syncthreads();
-        for (int t = tid; t < nu; t += 256) {   // (i, cy, cz)
-            const int i = t / LL, cy = (t / L) % L, cz = t % L;
+        for (int t = tid; t < Lc * Lp * Lp; t += 256) {   // (i, cy, cz)
+            const int i = t / (Lp * Lp), cy = (t / Lp) % Lp, cz = t % Lp;
             double s = 0;
-            for (int j = 0; j < L; j++) s += Vy[cy * L + j] * b1[(i * L + j) * L + cz];
+            for (int j = 0; j < Lc; j++) s += Vy[cy * Lc + j] * b1[(i * Lc + j) * Lp + cz];
             b0[t] = s;
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
+        for (int r = 0; r < 8; r++) {
             const int t = tid + 256 * r;
-            if (t >= nu) break;
-            const int cx = t / LL, yz = t % LL;
+            if (t >= np) break;
+            const int cx = t / (Lp * Lp), yz = t % (Lp * Lp);
             double s = 0;
-            for (int i = 0; i < L; i++) s += Vx[cx * L + i] * b0[i * LL + yz];
+            for (int i = 0; i < Lc; i++) s += Vx[cx * Lc + i] * b0[i * Lp * Lp + yz];
             acc[r] += s;
         }
     }
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
+    for (int r = 0; r < 8; r++) {
         const int t = tid + 256 * r;
-        if (t < nup) Mp[p * nup + t] = t < nu ? acc[r] : 0.0;
+        if (t < nupp) Mp[p * nupp + t] = t < np ? acc[r] : 0.0;
     }
-    for (int t = tid + 1024; t < nup; t += 256) Mp[p * nup + t] = 0.0;
+    for (int t = tid + 2048; t < nupp; t += 256) Mp[p * nupp + t] = 0.0;
 }
 
-// ---- L2L: child local expansion += transpose of M2M applied to the parent's ----
-__global__ __launch_bounds__(256) void k_l2l(const double *Lp, double *Lc, const double *tab, int L, int nu,
-                                             int nup, int ns_child) {
+// ---- L2L: child local expansion (order Lc) += M2M^T of the parent's (order Lp) ----
+__global__ __launch_bounds__(256) void k_l2l(const double *Lpar, double *Lch, const double *Vg, int Lp, int Lc,
+                                             int nupp, int nupc, int ns_child) {
     extern __shared__ double sm[];
+    const int nc = Lc * Lc * Lc, np = Lp * Lp * Lp;
+    const int nbuf = max(np, max(Lp * Lp * Lc, Lp * Lc * Lc));
     double *sV = sm;
-    double *b0 = sV + 2 * L * L;
-    double *b1 = b0 + nu;
+    double *b0 = sV + 2 * Lp * Lc;
+    double *b1 = b0 + nbuf;
     const int tid = threadIdx.x;
-    for (int t = tid; t < 2 * L * L; t += 256) sV[t] = tab[L + L * L + t];
+    for (int t = tid; t < 2 * Lp * Lc; t += 256) sV[t] = Vg[t];
     const int64_t c = blockIdx.x;
     const int cx = (int)(c / ((int64_t)ns_child * ns_child)), cy = (int)((c / ns_child) % ns_child),
               cz = (int)(c % ns_child);
     const int nsp = ns_child / 2;
     const int64_t p = ((int64_t)(cx >> 1) * nsp + (cy >> 1)) * nsp + (cz >> 1);
-    const int bx = cx & 1, by = cy & 1, bz = cz & 1;
-    const int LL = L * L;
-    const double *Vz = sV + bz * LL, *Vy = sV + by * LL, *Vx = sV + bx * LL;
-    for (int t = tid; t < nu; t += 256) b0[t] = Lp[p * nup + t];
+    const int VS = Lp * Lc;
+    const double *Vz = sV + (cz & 1) * VS, *Vy = sV + (cy & 1) * VS, *Vx = sV + (cx & 1) * VS;
+    for (int t = tid; t < np; t += 256) b0[t] = Lpar[p * nupp + t];
     __syncthreads();
-    for (int t = tid; t < nu; t += 256) {   // (a, b, k) = sum_c V[c][k] Lp[a, b, c]
-        const int ab = t / L, k = t % L;
+    for (int t = tid; t < Lp * Lp * Lc; t += 256) {   // (a, b, k) = sum_c V[c][k] Lp[a, b, c]
+        const int ab = t / Lc, k = t % Lc;
         double s = 0;
-        for (int cc = 0; cc < L; cc++) s += Vz[cc * L + k] * b0[ab * L + cc];
+        for (int cc = 0; cc < Lp; cc++) s += Vz[cc * Lc + k] * b0[ab * Lp + cc];
         b1[t] = s;
     }
     __syncthreads();
-    for (int t = tid; t < nu; t += 256) {   // (a, j, k) = sum_b V[b][j] (a, b, k)
-        const int a = t / LL, j = (t / L) % L, k = t % L;
+    for (int t = tid; t < Lp * Lc * Lc; t += 256) {   // (a, j, k) = sum_b V[b][j] (a, b, k)
+        const int a = t / (Lc * Lc), j = (t / Lc) % Lc, k = t % Lc;
         double s = 0;
-        for (int bb = 0; bb < L; bb++) s += Vy[bb * L + j] * b1[(a * L + bb) * L + k];
+        for (int bb = 0; bb < Lp; bb++) s += Vy[bb * Lc + j] * b1[(a * Lp + bb) * Lc + k];
         b0[t] = s;
     }
     __syncthreads();
-    for (int t = tid; t < nu; t += 256) {   // (i, j, k) = sum_a V[a][i] (a, j, k)
-        const int i = t / LL, jk = t % LL;
+    for (int t = tid; t < nc; t += 256) {   // (i, j, k) = sum_a V[a][i] (a, j, k)
+        const int i = t / (Lc * Lc), jk = t % (Lc * Lc);
         double s = 0;
-        for (int a = 0; a < L; a++) s += Vx[a * L + i] * b0[a * LL + jk];
-        Lc[c * nup + t] += s;
+        for (int a = 0; a < Lp; a++) s += Vx[a * Lc + i] * b0[a * Lc * Lc + jk];
+        Lch[c * nupc + t] += s;
     }
 }
 
 // ---- far periodic images: L_root = C_per M_root, E_per = 1/2 M.C M -----------
 __global__ __launch_bounds__(1024) void k_cper(const double *C, const double *M, double *Lr, int nu, int nup,
                                                double *terms) {
-    __shared__ double sM[1024];
+    __shared__ double sM[kMaxRootNodes];
     __shared__ double red[1024];
     const int t = threadIdx.x;
     for (int k = t; k < nu; k += 1024) sM[k] = M[k];
@@ -676,25 +682,41 @@ hipError_t launch_p2m(ankh_plan_s *pl, int ord) {
     return hipGetLastError();
 }
 
+static size_t mlshm(int Lp, int Lc) {
+    const int nbuf = std::max(std::max(Lc * Lc * Lc, Lp * Lp * Lp),
+                              std::max(std::max(Lc * Lc * Lp, Lc * Lp * Lp), Lp * Lp * Lc));
+    return sizeof(double) * (2 * Lp * Lc + 2 * nbuf);
+}
+
+// The root (level 0) may carry its own, higher order: M2M from level 1 into
+// the root and L2L out of it then use the rectangular root matrices.
 hipError_t launch_m2m(ankh_plan_s *pl, int e_par) {
     const ankh::Level &P = pl->lv[e_par], &C = pl->lv[e_par + 1];
-    const size_t shm = sizeof(double) * (2 * pl->order * pl->order + 2 * pl->nu);
-    hipLaunchKernelGGL(k_m2m, dim3((unsigned)P.ncell), dim3(256), shm, pl->stream, pl->d_M + C.cell0 * pl->nup,
-                       pl->d_M + P.cell0 * pl->nup, pl->d_tab, pl->order, pl->nu, pl->nup, P.nside);
+    const bool root = e_par == 0;
+    const int Lp = root ? pl->order0 : pl->order, Lc = pl->order;
+    const double *V = root ? pl->d_tab0 + pl->order0 : pl->d_tab + Lc + Lc * Lc;
+    double *Mp = root ? pl->d_rootM : pl->d_M + P.cell0 * pl->nup;
+    const int nupp = root ? pl->nup0 : pl->nup;
+    hipLaunchKernelGGL(k_m2m, dim3((unsigned)P.ncell), dim3(256), mlshm(Lp, Lc), pl->stream,
+                       pl->d_M + C.cell0 * pl->nup, Mp, V, Lp, Lc, pl->nup, nupp, P.nside);
     return hipGetLastError();
 }
 
 hipError_t launch_l2l(ankh_plan_s *pl, int e_child) {
     const ankh::Level &P = pl->lv[e_child - 1], &C = pl->lv[e_child];
-    const size_t shm = sizeof(double) * (2 * pl->order * pl->order + 2 * pl->nu);
-    hipLaunchKernelGGL(k_l2l, dim3((unsigned)C.ncell), dim3(256), shm, pl->stream, pl->d_L + P.cell0 * pl->nup,
-                       pl->d_L + C.cell0 * pl->nup, pl->d_tab, pl->order, pl->nu, pl->nup, C.nside);
+    const bool root = e_child == 1;
+    const int Lp = root ? pl->order0 : pl->order, Lc = pl->order;
+    const double *V = root ? pl->d_tab0 + pl->order0 : pl->d_tab + Lc + Lc * Lc;
+    const double *Lpar = root ? pl->d_rootL : pl->d_L + P.cell0 * pl->nup;
+    const int nupp = root ? pl->nup0 : pl->nup;
+    hipLaunchKernelGGL(k_l2l, dim3((unsigned)C.ncell), dim3(256), mlshm(Lp, Lc), pl->stream, Lpar,
+                       pl->d_L + C.cell0 * pl->nup, V, Lp, Lc, nupp, pl->nup, C.nside);
     return hipGetLastError();
 }
 
 hipError_t launch_cper(ankh_plan_s *pl) {
-    hipLaunchKernelGGL(k_cper, dim3(1), dim3(1024), 0, pl->stream, pl->d_Cper, pl->d_M, pl->d_L, pl->nu, pl->nup,
-                       pl->d_terms);
+    hipLaunchKernelGGL(k_cper, dim3(1), dim3(1024), 0, pl->stream, pl->d_Cper, pl->d_rootM, pl->d_rootL, pl->nu0,
+                       pl->nup0, pl->d_terms);
     return hipGetLastError();
 }
 
@@ -746,9 +768,9 @@ hipError_t launch_build_m2l(ankh_plan_s *pl, int e, double *K) {
 }
 
 hipError_t launch_build_cper(ankh_plan_s *pl) {
-    const int64_t tot = (int64_t)pl->nup * pl->nup;
-    hipLaunchKernelGGL(k_build_cper, dim3(nblk(tot, 128)), dim3(128), 0, pl->stream, pl->d_Cper, pl->d_tab, pl->order,
-                       pl->nu, pl->nup, pl->edge, pl->xi, pl->images);
+    const int64_t tot = (int64_t)pl->nup0 * pl->nup0;
+    hipLaunchKernelGGL(k_build_cper, dim3(nblk(tot, 128)), dim3(128), 0, pl->stream, pl->d_Cper, pl->d_tab0,
+                       pl->order0, pl->nu0, pl->nup0, pl->edge, pl->xi, pl->images);
     return hipGetLastError();
 }
 

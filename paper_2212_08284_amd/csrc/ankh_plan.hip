@@ -42,7 +42,8 @@ void free_all(ankh_plan_s *pl) {
     void *ptrs[] = {pl->d_tab, pl->d_leaf, pl->d_count, pl->d_offs, pl->d_fill, pl->d_perm, pl->d_tmp,
                     pl->P.x, pl->P.y, pl->P.z, pl->P.q, pl->P.mu, pl->P.th, pl->P.qf, pl->P.muf, pl->P.thf,
                     pl->d_M, pl->d_L, pl->d_K, pl->d_Kf, pl->d_Cper, pl->d_eatom, pl->d_eleaf, pl->d_F,
-                    pl->d_G, pl->d_terms, pl->d_part, pl->d_err};
+                    pl->d_G, pl->d_terms, pl->d_part, pl->d_err, pl->d_tab0,
+                    pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &set : pl->evsets)
@@ -193,6 +194,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
     if (ov) {
         if (ov->depth > kMaxDepth) return ANKH_ERR_INVALID_ARG;
         if (ov->order > 0 && (ov->order < 2 || ov->order > kMaxOrder)) return ANKH_ERR_INVALID_ARG;
+        if (ov->root_order > 0 && (ov->root_order < 2 || ov->root_order > kMaxRootOrder)) return ANKH_ERR_INVALID_ARG;
         if (ov->images > 64) return ANKH_ERR_INVALID_ARG;
         if (!std::isfinite(ov->xi)) return ANKH_ERR_INVALID_ARG;
     }
@@ -234,6 +236,15 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         cells += lv.ncell;
     }
     pl->ncell_total = cells;
+    // Root grid of the far-image operator: the image sum is interpolated over
+    // the whole box, where a few more nodes than on the octree levels keep its
+    // error below theirs (the paper also raises the order of the far-image
+    // interpolation above the leaf order).  At depth 0 the root is the leaf.
+    if (pl->depth == 0) pl->order0 = pl->order;
+    else if (ov && ov->root_order > 0) pl->order0 = ov->root_order;
+    else pl->order0 = std::min(kMaxRootOrder, std::max(9, pl->order + 2));
+    pl->nu0 = pl->order0 * pl->order0 * pl->order0;
+    pl->nup0 = (pl->nu0 + 63) / 64 * 64;
     build_tables(pl);
 
     const int64_t n = n_atoms;
@@ -246,6 +257,37 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         for (int b = 0; b < 2; b++)
             for (int k = 0; k < L * L; k++) tab[L + L * L + b * L * L + k] = pl->V[b][k];
         ck(hipMemcpy(pl->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+        {
+            // root tables: nodes of order L0 and V0[b][a][i] = S^(L0)_a((r_i -+ 1) / 2), i over the level-1 nodes
+            const int L0 = pl->order0;
+            std::vector<double> t0(L0 + 2 * L0 * L);
+            std::vector<double> r0(L0), H0(L0 * L0);
+            for (int k = 0; k < L0; k++) r0[k] = std::cos((2 * k + 1) * kPi / (2 * L0));
+            for (int k = 0; k < L0; k++) {
+                double a = 1, b = r0[k];
+                for (int m = 0; m < L0; m++) {
+                    double tm = m == 0 ? 1.0 : (m == 1 ? r0[k] : 2 * r0[k] * b - a);
+                    if (m >= 2) { a = b; b = tm; }
+                    H0[k * L0 + m] = (m == 0 ? 1.0 : 2.0 * tm) / L0;
+                }
+            }
+            for (int k = 0; k < L0; k++) t0[k] = r0[k];
+            for (int bb = 0; bb < 2; bb++)
+                for (int i = 0; i < L; i++) {
+                    const double x = (pl->nodes[i] + (bb ? 1.0 : -1.0)) / 2;
+                    double T[kMaxRootOrder];
+                    T[0] = 1;
+                    if (L0 > 1) T[1] = x;
+                    for (int m = 2; m < L0; m++) T[m] = 2 * x * T[m - 1] - T[m - 2];
+                    for (int a = 0; a < L0; a++) {
+                        double sacc = 0;
+                        for (int m = 0; m < L0; m++) sacc += H0[a * L0 + m] * T[m];
+                        t0[L0 + bb * L0 * L + a * L + i] = sacc;
+                    }
+                }
+            dalloc(pl, &pl->d_tab0, t0.size());
+            ck(hipMemcpy(pl->d_tab0, t0.data(), t0.size() * sizeof(double), hipMemcpyHostToDevice));
+        }
         dalloc(pl, &pl->d_leaf, n);
         dalloc(pl, &pl->d_count, pl->nleaf);
         dalloc(pl, &pl->d_offs, pl->nleaf + 1);
@@ -266,7 +308,15 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         dalloc(pl, &pl->d_M, cells * pl->nup);
         dalloc(pl, &pl->d_L, cells * pl->nup);
         const size_t kper = (size_t)kNumOff * pl->nup * pl->nup;
-        dalloc(pl, &pl->d_Cper, (size_t)pl->nup * pl->nup);
+        dalloc(pl, &pl->d_Cper, (size_t)pl->nup0 * pl->nup0);
+        if (pl->depth >= 1) {
+            dalloc(pl, &pl->d_rootM, pl->nup0);
+            dalloc(pl, &pl->d_rootL, pl->nup0);
+            pl->root_owned = true;
+        } else {
+            pl->d_rootM = pl->d_M;
+            pl->d_rootL = pl->d_L;
+        }
         dalloc(pl, &pl->d_eatom, n);
         dalloc(pl, &pl->d_eleaf, pl->nleaf);
         dalloc(pl, &pl->d_F, 3 * n);
@@ -355,6 +405,7 @@ ankh_status ankh_get_stats(ankh_plan_t pl, ankh_plan_stats *out) {
     out->n_atoms = pl->n;
     out->depth = pl->depth;
     out->order = pl->order;
+    out->root_order = pl->order0;
     out->images = pl->images;
     out->max_order = pl->max_order;
     out->precision = pl->precision;

@@ -62,16 +62,16 @@ def _run(ak, d, eps=1e-6, prec="fp64", **ov):
     return pl, e.item(), F.cpu().numpy(), G.cpu().numpy()
 
 
-@pytest.mark.parametrize("depth,order,kind", [(0, 4, "qmt"), (1, 4, "qmt"), (2, 5, "qmt"), (2, 3, "q"),
-                                              (3, 4, "qm")])
-def test_stage_parity_with_reference(ak, depth, order, kind):
+@pytest.mark.parametrize("depth,order,root,kind", [(0, 4, None, "qmt"), (1, 4, None, "qmt"), (2, 5, 6, "qmt"),
+                                                   (2, 3, 5, "q"), (3, 4, 4, "qm")])
+def test_stage_parity_with_reference(ak, depth, order, root, kind):
     d = _system(kind)
-    pl, e, F, G = _run(ak, d, depth=depth, order=order, images=4)
+    pl, e, F, G = _run(ak, d, depth=depth, order=order, images=4, root_order=root)
     st = pl.stats
     terms = pl.last_terms()
     Q = pl.leaf_multipoles()
     r = ankh_ref.evaluate(d["pos"], d["q"], d["mu"], d["theta"], d["edge"], st["depth"], st["order"], st["xi"],
-                          st["images"], grad=True, keep=True)
+                          st["images"], grad=True, keep=True, root_order=st["root_order"])
     scale = abs(r["e_near"]) + abs(r["e_self"]) + 1.0
     assert abs(terms["near"] - r["e_near"]) <= 1e-12 * scale
     assert abs(terms["far_levels"] - sum(r["e_far_levels"])) <= 1e-12 * scale
