@@ -83,6 +83,8 @@ struct ankh_plan_s {
     double *d_L = nullptr;        // local expansions, all levels [cells][nup]
     double *d_K = nullptr;        // fp64 M2L matrices: level e>=1 at (e-1) * 343 * nup * nup, [d][l][k]
     float *d_Kf = nullptr;        // fp32 copy for the mixed mode
+    float *d_Mf = nullptr;        // fp32 multipoles of one level (mixed mode M2L operand)
+    double *d_m2l_part = nullptr; // split-K partial local expansions of one level
     double *d_Cper = nullptr;     // far-image root operator [nup0][nup0]
     double *d_eatom = nullptr;    // near-field energy per leaf-order atom
     double *d_eleaf = nullptr;    // far energy per leaf
@@ -121,6 +123,7 @@ hipError_t launch_l2p(ankh_plan_s *pl, int ord, bool fields);
 hipError_t launch_reduce(ankh_plan_s *pl, double *energy_out, int ord);
 hipError_t launch_unpermute(ankh_plan_s *pl, double *forces, double *dEdmu, bool have_mu);
 hipError_t launch_m2l(ankh_plan_s *pl, int e);
+int m2l_splits(const ankh_plan_s *pl, int e);
 hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields);
 hipError_t launch_build_m2l(ankh_plan_s *pl, int e, double *K);
 hipError_t launch_build_cper(ankh_plan_s *pl);

@@ -9,114 +9,215 @@
 // periodically, so at coarse levels the cells of the adjacent images take
 // part as the paper's periodicity section requires.
 //
-// Per parity class the level is one implicit GEMM
-//   [n_u x 189 n_u] x [189 n_u x (cells of the class)],
-// whose right operand is gathered from the multipole array.  A block computes a
-// 64 (nodes) x 64 (cells) tile of L; the 189 x n_u contraction streams K_d and
-// the gathered M through LDS in steps of TK rows.
+// Per parity class of the target cells the level is one implicit GEMM
+//   L[n_u x cells] = [K_d1 .. K_d189] (n_u x 189 n_u) * im2col(M) (189 n_u x cells)
+// run on the matrix cores (v_mfma 16x16x4, f64 or f32).  A block owns a
+// 64 (nodes) x 64 (cells) tile of L and a slice of the 189 offsets; K_d and
+// the gathered multipoles stream through double-buffered LDS in steps of 16
+// along the contraction.  Slices of the offset list (split-K) give the launch
+// enough blocks to fill the chip at every level; their partial tiles are
+// summed in a fixed order by k_m2l_reduce, so results do not depend on
+// scheduling.
 #include "ankh_internal.h"
 
 namespace ankh {
 namespace {
 
-constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int BM = 64, BN = 64, BK = 16;
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mma;
+// Operands of both 16x16x4 forms: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16].  Result element v of lane l sits in column l % 16 and in
+// row 4 (l / 16) + v (f32) or row l / 16 + 4 v (f64).
+template <> struct Mma<float> {
+    using acc = f32x4;
+    static __device__ inline acc run(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lk, int v) { return 4 * lk + v; }
+};
+template <> struct Mma<double> {
+    using acc = f64x4;
+    static __device__ inline acc run(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lk, int v) { return lk + 4 * v; }
+};
+
+// blockIdx: x = row tile, y = cell tile, z = class * nsplit + split
 template <typename T>
-__global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const double *__restrict__ M,
-                                             double *__restrict__ Lout, int nside, int nup) {
-    __shared__ T As[TK][TM];
-    __shared__ T Bs[TK][TN + 1];
+__global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *__restrict__ M,
+                                             double *__restrict__ out, int nside, int nup, int nsplit,
+                                             int64_t out_stride) {
+    using Acc = typename Mma<T>::acc;
+    __shared__ T As[2][BK][BM + 4];
+    __shared__ T Bs[2][BK][BN + 4];
+    __shared__ int il[kNumIL];
+
     const int tid = threadIdx.x;
-    const int rt = blockIdx.x, ct = blockIdx.y, cls = blockIdx.z;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int rt = blockIdx.x, ct = blockIdx.y;
+    const int cls = blockIdx.z / nsplit, split = blockIdx.z % nsplit;
     const int px = cls >> 2, py = (cls >> 1) & 1, pz = cls & 1;
     const int h = nside >> 1;
     const int ncls = h * h * h;
-    const int ty = tid >> 4, tx = tid & 15;
+    const int row0 = rt * BM, col0 = ct * BN;
 
-    // the column this thread loads B for, and its target cell
-    const int lcol = tid >> 2, lrow = (tid & 3) * 4;
-    const int tcell_local = ct * TN + lcol;
-    const bool lvalid = tcell_local < ncls;
+    // interaction list of this parity class, in a fixed order
+    if (tid == 0) {
+        int k = 0;
+        for (int a = 0; a < 6; a++)
+            for (int b = 0; b < 6; b++)
+                for (int c = 0; c < 6; c++) {
+                    const int dx = (px ? -3 : -2) + a, dy = (py ? -3 : -2) + b, dz = (pz ? -3 : -2) + c;
+                    if (max(abs(dx), max(abs(dy), abs(dz))) >= 2) il[k++] = off_index(dx, dy, dz);
+                }
+    }
+    __syncthreads();
+    const int o_begin = kNumIL * split / nsplit, o_end = kNumIL * (split + 1) / nsplit;
+
+    // loader roles: A (K_d rows l, cols = output nodes) and B (M of the source cell of one column)
+    const int a_r = tid >> 4, a_c = (tid & 15) * 4;          // 16 x 64 tile, 4 per thread
+    const int b_col = tid >> 2, b_r = (tid & 3) * 4;         // 16 x 64 tile, 4 per thread
+    const int tcell = col0 + b_col;
+    const bool b_ok = tcell < ncls;
     int gx = 0, gy = 0, gz = 0;
-    if (lvalid) {
-        gx = 2 * (tcell_local / (h * h)) + px;
-        gy = 2 * ((tcell_local / h) % h) + py;
-        gz = 2 * (tcell_local % h) + pz;
+    if (b_ok) {
+        gx = 2 * (tcell / (h * h)) + px;
+        gy = 2 * ((tcell / h) % h) + py;
+        gz = 2 * (tcell % h) + pz;
+    }
+    const bool a_ok = row0 + a_c < nup;   // nup is a multiple of 32 and a_c of 4
+
+    const int nk = nup / BK;
+    const int niter = (o_end - o_begin) * nk;
+    T ra[4], rb[4];
+    auto load = [&](int it) {
+        const int oi = o_begin + it / nk, k0 = (it % nk) * BK;
+        const int di = il[oi];
+        const T *Kd = K + (size_t)di * nup * nup;
+#pragma unroll
+        for (int u = 0; u < 4; u++) ra[u] = a_ok ? Kd[(size_t)(k0 + a_r) * nup + row0 + a_c + u] : (T)0;
+        if (b_ok) {
+            const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
+            const int sx = (gx + dx + 4 * nside) % nside, sy = (gy + dy + 4 * nside) % nside,
+                      sz = (gz + dz + 4 * nside) % nside;
+            const T *Ms = M + ((size_t)(sx * nside + sy) * nside + sz) * nup + k0 + b_r;
+#pragma unroll
+            for (int u = 0; u < 4; u++) rb[u] = Ms[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; u++) rb[u] = (T)0;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) As[buf][a_r][a_c + u] = ra[u];
+#pragma unroll
+        for (int u = 0; u < 4; u++) Bs[buf][b_r + u][b_col] = rb[u];
+    };
+
+    Acc acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = Acc{0, 0, 0, 0};
+
+    if (niter > 0) {
+        load(0);
+        store(0);
+    }
+    __syncthreads();
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int it = 0; it < niter; it++) {
+        const int cur = it & 1;
+        if (it + 1 < niter) load(it + 1);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            T av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; i++) av[i] = As[cur][kk + lk][wr * 32 + i * 16 + lr];
+#pragma unroll
+            for (int j = 0; j < 2; j++) bv[j] = Bs[cur][kk + lk][wc * 32 + j * 16 + lr];
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++) acc[i][j] = Mma<T>::run(av[i], bv[j], acc[i][j]);
+        }
+        if (it + 1 < niter) store(cur ^ 1);
+        __syncthreads();
     }
 
-    T acc[4][4];
+    // scatter each 16 x 16 result block (rows per Mma<T>::row, column lane % 16)
+    double *o = out + (size_t)split * out_stride;
 #pragma unroll
-    for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = 0;
-
-    const int dx0 = px ? -3 : -2, dy0 = py ? -3 : -2, dz0 = pz ? -3 : -2;
-    for (int a = 0; a < 6; a++)
-        for (int b = 0; b < 6; b++)
-            for (int c = 0; c < 6; c++) {
-                const int dx = dx0 + a, dy = dy0 + b, dz = dz0 + c;
-                if (max(abs(dx), max(abs(dy), abs(dz))) < 2) continue;
-                const T *Kd = K + (size_t)off_index(dx, dy, dz) * nup * nup + (size_t)rt * TM;
-                const double *Ms = nullptr;
-                if (lvalid) {
-                    const int sx = (gx + dx + 4 * nside) % nside;
-                    const int sy = (gy + dy + 4 * nside) % nside;
-                    const int sz = (gz + dz + 4 * nside) % nside;
-                    Ms = M + ((size_t)(sx * nside + sy) * nside + sz) * nup;
-                }
-                for (int l0 = 0; l0 < nup; l0 += TK) {
-                    // A: K_d[l0 + r][rt*64 + col], 16 x 64
-#pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        const int e = tid + 256 * u;
-                        const int r = e >> 6, col = e & 63;
-                        As[r][col] = Kd[(size_t)(l0 + r) * nup + col];
-                    }
-                    // B: M_src[l0 + r] for this thread's column
-#pragma unroll
-                    for (int u = 0; u < 4; u++) Bs[lrow + u][lcol] = lvalid ? (T)Ms[l0 + lrow + u] : (T)0;
-                    __syncthreads();
-#pragma unroll
-                    for (int r = 0; r < TK; r++) {
-                        T av[4], bv[4];
-#pragma unroll
-                        for (int i = 0; i < 4; i++) av[i] = As[r][ty * 4 + i];
-#pragma unroll
-                        for (int j = 0; j < 4; j++) bv[j] = Bs[r][tx * 4 + j];
-#pragma unroll
-                        for (int i = 0; i < 4; i++)
-#pragma unroll
-                            for (int j = 0; j < 4; j++) acc[i][j] += av[i] * bv[j];
-                    }
-                    __syncthreads();
-                }
-            }
-
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        const int cl = ct * TN + tx * 4 + j;
+    for (int j = 0; j < 2; j++) {
+        const int cl = col0 + wc * 32 + j * 16 + lr;
         if (cl >= ncls) continue;
         const int cx = 2 * (cl / (h * h)) + px, cy = 2 * ((cl / h) % h) + py, cz = 2 * (cl % h) + pz;
-        double *Lc = Lout + ((size_t)(cx * nside + cy) * nside + cz) * nup + (size_t)rt * TM;
+        double *Lc = o + ((size_t)(cx * nside + cy) * nside + cz) * nup;
 #pragma unroll
-        for (int i = 0; i < 4; i++) Lc[ty * 4 + i] = (double)acc[i][j];
+        for (int i = 0; i < 2; i++) {
+            const int rb = row0 + wr * 32 + i * 16;   // 16-row block, entirely inside or outside nup
+            if (rb >= nup) continue;
+#pragma unroll
+            for (int v = 0; v < 4; v++) Lc[rb + Mma<T>::row(lk, v)] = (double)acc[i][j][v];
+        }
     }
 }
 
+// L = sum over the split-K partials, in split order
+__global__ void k_m2l_reduce(const double *__restrict__ part, double *__restrict__ L, int64_t n, int nsplit) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = part[i];
+    for (int k = 1; k < nsplit; k++) s += part[k * n + i];
+    L[i] = s;
+}
+
+__global__ void k_f64_to_f32(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (float)s[i];
+}
+
 }  // namespace
+
+// number of offset slices so that a level launches at least ~4 blocks per CU
+int m2l_splits(const ankh_plan_s *pl, int e) {
+    const int h = pl->lv[e].nside / 2;
+    const int64_t tiles = (int64_t)((pl->nup + BM - 1) / BM) * ((h * h * h + BN - 1) / BN) * 8;
+    int s = 1;
+    while (s < 27 && tiles * s < 1024) s++;
+    return s;
+}
 
 hipError_t launch_m2l(ankh_plan_s *pl, int e) {
     const ankh::Level &lv = pl->lv[e];
     const int h = lv.nside / 2;
     const int ncls = h * h * h;
-    dim3 grid(pl->nup / TM, (ncls + TN - 1) / TN, 8);
-    const double *M = pl->d_M + lv.cell0 * pl->nup;
+    const int nsplit = m2l_splits(pl, e);
+    dim3 grid((pl->nup + BM - 1) / BM, (ncls + BN - 1) / BN, 8 * nsplit);
+    const int64_t nval = lv.ncell * pl->nup;
     double *L = pl->d_L + lv.cell0 * pl->nup;
+    double *out = nsplit > 1 ? pl->d_m2l_part : L;
     const size_t koff = (size_t)(e - 1) * kNumOff * pl->nup * pl->nup;
-    if (pl->precision == ANKH_MIXED)
-        hipLaunchKernelGGL(k_m2l<float>, grid, dim3(256), 0, pl->stream, pl->d_Kf + koff, M, L, lv.nside, pl->nup);
-    else
-        hipLaunchKernelGGL(k_m2l<double>, grid, dim3(256), 0, pl->stream, pl->d_K + koff, M, L, lv.nside, pl->nup);
+    if (pl->precision == ANKH_MIXED) {
+        float *Mf = pl->d_Mf;   // this level's multipoles in float32
+        hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream,
+                           pl->d_M + lv.cell0 * pl->nup, Mf, nval);
+        hipLaunchKernelGGL(k_m2l<float>, grid, dim3(256), 0, pl->stream, pl->d_Kf + koff, Mf, out, lv.nside,
+                           pl->nup, nsplit, nval);
+    } else {
+        hipLaunchKernelGGL(k_m2l<double>, grid, dim3(256), 0, pl->stream, pl->d_K + koff,
+                           pl->d_M + lv.cell0 * pl->nup, out, lv.nside, pl->nup, nsplit, nval);
+    }
+    if (nsplit > 1)
+        hipLaunchKernelGGL(k_m2l_reduce, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream,
+                           pl->d_m2l_part, L, nval, nsplit);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // C ABI of the interpolated-Ewald library: planner (parameter rules, operator
 // tables, device buffers) and the evaluation driver that enqueues the
 // kernels of one energy / energy+forces evaluation on the plan's stream.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -42,7 +43,7 @@ void free_all(ankh_plan_s *pl) {
     void *ptrs[] = {pl->d_tab, pl->d_leaf, pl->d_count, pl->d_offs, pl->d_fill, pl->d_perm, pl->d_tmp,
                     pl->P.x, pl->P.y, pl->P.z, pl->P.q, pl->P.mu, pl->P.th, pl->P.qf, pl->P.muf, pl->P.thf,
                     pl->d_M, pl->d_L, pl->d_K, pl->d_Kf, pl->d_Cper, pl->d_eatom, pl->d_eleaf, pl->d_F,
-                    pl->d_G, pl->d_terms, pl->d_part, pl->d_err, pl->d_tab0,
+                    pl->d_G, pl->d_terms, pl->d_part, pl->d_err, pl->d_tab0, pl->d_Mf, pl->d_m2l_part,
                     pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -221,7 +222,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
     }
     pl->order = (ov && ov->order > 0) ? ov->order : order_for(rel_accuracy);
     pl->nu = pl->order * pl->order * pl->order;
-    pl->nup = (pl->nu + 63) / 64 * 64;
+    pl->nup = (pl->nu + 31) / 32 * 32;   // row stride: a multiple of the M2L tile step
     pl->depth = (ov && ov->depth >= 0) ? ov->depth : depth_for(n_atoms, pl->nu);
     pl->nside = 1 << pl->depth;
     pl->nleaf = (int64_t)pl->nside * pl->nside * pl->nside;
@@ -307,6 +308,16 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         }
         dalloc(pl, &pl->d_M, cells * pl->nup);
         dalloc(pl, &pl->d_L, cells * pl->nup);
+        {
+            // M2L scratch: split-K partials and (mixed mode) a float32 copy of one level's multipoles
+            size_t part = 0;
+            for (int e = 1; e <= pl->depth; e++) {
+                const int s = m2l_splits(pl, e);
+                if (s > 1) part = std::max(part, (size_t)s * pl->lv[e].ncell * pl->nup);
+            }
+            if (part) dalloc(pl, &pl->d_m2l_part, part);
+            if (precision == ANKH_MIXED && pl->depth >= 1) dalloc(pl, &pl->d_Mf, pl->lv[pl->depth].ncell * pl->nup);
+        }
         const size_t kper = (size_t)kNumOff * pl->nup * pl->nup;
         dalloc(pl, &pl->d_Cper, (size_t)pl->nup0 * pl->nup0);
         if (pl->depth >= 1) {
