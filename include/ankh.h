@@ -62,10 +62,13 @@ typedef enum {
 } ankh_status;
 
 typedef enum {
-    ANKH_FP64 = 0,  /* every stage in float64 */
-    ANKH_MIXED = 1  /* near-field pair terms and the far-field contraction in float32;
-                       pair separations, self/background terms, moments, and every
-                       reduction in float64 */
+    ANKH_FP64 = 0,          /* every stage in float64 */
+    ANKH_MIXED = 1,         /* near-field pair terms and the far-field contraction in float32;
+                               pair separations, self/background terms, moments, and every
+                               reduction in float64 */
+    ANKH_MIXED_BF16X3 = 2   /* as ANKH_MIXED, with the far-field contraction on the bf16
+                               matrix cores in split precision (hi*hi + hi*lo + lo*hi,
+                               float32 accumulation) */
 } ankh_precision;
 
 /* Optional overrides of the planner's choices: depth < 0 and any other field <= 0 mean "auto". */

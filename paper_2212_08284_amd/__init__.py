@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libankh.so")
 
 ANKH_FP64 = 0
 ANKH_MIXED = 1
+ANKH_MIXED_BF16X3 = 2
 
 STATUS = {
     0: "ok", 1: "invalid argument", 2: "non-finite input", 3: "quadrupole not traceless",
@@ -187,7 +188,8 @@ class Plan:
 
     def __init__(self, n_atoms, box_radius, rel_accuracy=1e-6, max_order=2, precision="fp64", depth=None,
                  order=None, images=None, xi=None, root_order=None, stream=None):
-        prec = {"fp64": ANKH_FP64, "mixed": ANKH_MIXED}[precision] if isinstance(precision, str) else int(precision)
+        prec = ({"fp64": ANKH_FP64, "mixed": ANKH_MIXED, "mixed_bf16x3": ANKH_MIXED_BF16X3}[precision]
+                if isinstance(precision, str) else int(precision))
         self.n = int(n_atoms)
         self.max_order = int(max_order)
         self.handle = ankh_plan(n_atoms, box_radius, rel_accuracy, max_order, prec, depth, order, images, xi,

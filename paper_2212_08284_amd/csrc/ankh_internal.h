@@ -84,6 +84,8 @@ struct ankh_plan_s {
     double *d_K = nullptr;        // fp64 M2L matrices: level e>=1 at (e-1) * 343 * nup * nup, [d][l][k]
     float *d_Kf = nullptr;        // fp32 copy for the mixed mode
     float *d_Mf = nullptr;        // fp32 multipoles of one level (mixed mode M2L operand)
+    __bf16 *d_Kb = nullptr;       // bf16 hi parts of all levels' K (row-major K_d[k][l]), then the lo parts
+    __bf16 *d_Mb = nullptr;       // bf16 hi / lo split of one level's multipoles
     double *d_m2l_part = nullptr; // split-K partial local expansions of one level
     double *d_Cper = nullptr;     // far-image root operator [nup0][nup0]
     double *d_eatom = nullptr;    // near-field energy per leaf-order atom
@@ -124,6 +126,8 @@ hipError_t launch_reduce(ankh_plan_s *pl, double *energy_out, int ord);
 hipError_t launch_unpermute(ankh_plan_s *pl, double *forces, double *dEdmu, bool have_mu);
 hipError_t launch_m2l(ankh_plan_s *pl, int e);
 int m2l_splits(const ankh_plan_s *pl, int e);
+hipError_t launch_split_K_bf16(ankh_plan_s *pl, const double *K, __bf16 *hi, __bf16 *lo);
+inline bool is_mixed(const ankh_plan_s *pl) { return pl->precision != ANKH_FP64; }
 hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields);
 hipError_t launch_build_m2l(ankh_plan_s *pl, int e, double *K);
 hipError_t launch_build_cper(ankh_plan_s *pl);

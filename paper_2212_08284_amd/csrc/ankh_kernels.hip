@@ -663,7 +663,7 @@ hipError_t launch_gather(ankh_plan_s *pl, const double *pos, const double *q, co
     const double w = pl->edge / pl->nside;
     hipLaunchKernelGGL(k_gather, dim3(nblk(pl->n, 256)), dim3(256), 0, pl->stream, pl->n, pl->d_perm, pl->d_leaf,
                        pos, q, mu, th, pl->rB, pl->edge, w, pl->nside, pl->P, pl->max_order,
-                       pl->precision == ANKH_MIXED ? 1 : 0);
+                       is_mixed(pl) ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -170,6 +170,171 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
     }
 }
 
+// ---- split-precision variant: BF16 x 3 on the 16x16x32 BF16 matrix cores ------
+// Each float32 operand is split as x = hi + lo (hi = bf16(x), lo = bf16(x - hi)),
+// and the product is accumulated in float32 as hi*hi + hi*lo + lo*hi (the
+// lo*lo term is below the float32 rounding of the sum).  K is stored row-major
+// per offset (K_d[k][l]); the multipoles of the level are split on the fly.
+// Lane l of v_mfma_f32_16x16x32_bf16 supplies A[l % 16][8 (l / 16) .. +8] and
+// B[8 (l / 16) .. +8][l % 16]; result element v sits at row 4 (l / 16) + v,
+// column l % 16.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int BK3 = 32, PADK = 8;
+
+__global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ Kh, const __bf16 *__restrict__ Kl,
+                                                    const __bf16 *__restrict__ Mh, const __bf16 *__restrict__ Ml,
+                                                    double *__restrict__ out, int nside, int nup, int nsplit,
+                                                    int64_t out_stride) {
+    __shared__ __attribute__((aligned(16))) __bf16 Ash[2][BM][BK3 + PADK];
+    __shared__ __attribute__((aligned(16))) __bf16 Asl[2][BM][BK3 + PADK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bsh[2][BN][BK3 + PADK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bsl[2][BN][BK3 + PADK];
+    __shared__ int il[kNumIL];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int rt = blockIdx.x, ct = blockIdx.y;
+    const int cls = blockIdx.z / nsplit, split = blockIdx.z % nsplit;
+    const int px = cls >> 2, py = (cls >> 1) & 1, pz = cls & 1;
+    const int h = nside >> 1;
+    const int ncls = h * h * h;
+    const int row0 = rt * BM, col0 = ct * BN;
+    if (tid == 0) {
+        int k = 0;
+        for (int a = 0; a < 6; a++)
+            for (int b = 0; b < 6; b++)
+                for (int c = 0; c < 6; c++) {
+                    const int dx = (px ? -3 : -2) + a, dy = (py ? -3 : -2) + b, dz = (pz ? -3 : -2) + c;
+                    if (max(abs(dx), max(abs(dy), abs(dz))) >= 2) il[k++] = off_index(dx, dy, dz);
+                }
+    }
+    __syncthreads();
+    const int o_begin = kNumIL * split / nsplit, o_end = kNumIL * (split + 1) / nsplit;
+
+    // loaders: one 16-byte chunk (8 bf16 along the contraction) of hi and of lo per thread for A and B
+    const int ld_r = tid >> 2, ld_c = (tid & 3) * 8;
+    const bool a_ok = row0 + ld_r < nup;
+    const int tcell = col0 + ld_r;
+    const bool b_ok = tcell < ncls;
+    int gx = 0, gy = 0, gz = 0;
+    if (b_ok) {
+        gx = 2 * (tcell / (h * h)) + px;
+        gy = 2 * ((tcell / h) % h) + py;
+        gz = 2 * (tcell % h) + pz;
+    }
+    const int nk = nup / BK3;
+    const int niter = (o_end - o_begin) * nk;
+    uint4 rah, ral, rbh, rbl;
+    const uint4 zero4 = {0u, 0u, 0u, 0u};
+    auto load = [&](int it) {
+        const int oi = o_begin + it / nk, k0 = (it % nk) * BK3;
+        const int di = il[oi];
+        if (a_ok) {
+            const size_t off = ((size_t)di * nup + row0 + ld_r) * nup + k0 + ld_c;
+            rah = *reinterpret_cast<const uint4 *>(Kh + off);
+            ral = *reinterpret_cast<const uint4 *>(Kl + off);
+        } else {
+            rah = zero4;
+            ral = zero4;
+        }
+        if (b_ok) {
+            const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
+            const int sx = (gx + dx + 4 * nside) % nside, sy = (gy + dy + 4 * nside) % nside,
+                      sz = (gz + dz + 4 * nside) % nside;
+            const size_t off = ((size_t)(sx * nside + sy) * nside + sz) * nup + k0 + ld_c;
+            rbh = *reinterpret_cast<const uint4 *>(Mh + off);
+            rbl = *reinterpret_cast<const uint4 *>(Ml + off);
+        } else {
+            rbh = zero4;
+            rbl = zero4;
+        }
+    };
+    auto store = [&](int buf) {
+        *reinterpret_cast<uint4 *>(&Ash[buf][ld_r][ld_c]) = rah;
+        *reinterpret_cast<uint4 *>(&Asl[buf][ld_r][ld_c]) = ral;
+        *reinterpret_cast<uint4 *>(&Bsh[buf][ld_r][ld_c]) = rbh;
+        *reinterpret_cast<uint4 *>(&Bsl[buf][ld_r][ld_c]) = rbl;
+    };
+
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0, 0, 0, 0};
+    if (niter > 0) {
+        load(0);
+        store(0);
+    }
+    __syncthreads();
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int it = 0; it < niter; it++) {
+        const int cur = it & 1;
+        if (it + 1 < niter) load(it + 1);
+        bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            ah[i] = *reinterpret_cast<const bf16x8 *>(&Ash[cur][wr * 32 + i * 16 + lr][8 * lk]);
+            al[i] = *reinterpret_cast<const bf16x8 *>(&Asl[cur][wr * 32 + i * 16 + lr][8 * lk]);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            bh[j] = *reinterpret_cast<const bf16x8 *>(&Bsh[cur][wc * 32 + j * 16 + lr][8 * lk]);
+            bl[j] = *reinterpret_cast<const bf16x8 *>(&Bsl[cur][wc * 32 + j * 16 + lr][8 * lk]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int j = 0; j < 2; j++) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+        if (it + 1 < niter) store(cur ^ 1);
+        __syncthreads();
+    }
+    double *o = out + (size_t)split * out_stride;
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        const int cl = col0 + wc * 32 + j * 16 + lr;
+        if (cl >= ncls) continue;
+        const int cx = 2 * (cl / (h * h)) + px, cy = 2 * ((cl / h) % h) + py, cz = 2 * (cl % h) + pz;
+        double *Lc = o + ((size_t)(cx * nside + cy) * nside + cz) * nup;
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            const int rb = row0 + wr * 32 + i * 16;
+            if (rb >= nup) continue;
+#pragma unroll
+            for (int v = 0; v < 4; v++) Lc[rb + 4 * lk + v] = (double)acc[i][j][v];
+        }
+    }
+}
+
+// hi / lo bf16 split of a float64 array (via float32)
+__global__ void k_split_bf16(const double *__restrict__ s, __bf16 *__restrict__ hi, __bf16 *__restrict__ lo,
+                             int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = (float)s[i];
+    const __bf16 a = (__bf16)x;
+    hi[i] = a;
+    lo[i] = (__bf16)(x - (float)a);
+}
+
+// plan time: row-major K_d[k][l] from the [d][l][k] float64 stack (K_{-d} = K_d^T)
+__global__ void k_split_K_bf16(const double *__restrict__ K, __bf16 *__restrict__ hi, __bf16 *__restrict__ lo,
+                               int nup) {
+    const int64_t n = (int64_t)kNumOff * nup * nup;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t per = (int64_t)nup * nup;
+    const int d = (int)(i / per);
+    const float x = (float)K[(int64_t)(kNumOff - 1 - d) * per + i % per];
+    const __bf16 a = (__bf16)x;
+    hi[i] = a;
+    lo[i] = (__bf16)(x - (float)a);
+}
+
 // L = sum over the split-K partials, in split order
 __global__ void k_m2l_reduce(const double *__restrict__ part, double *__restrict__ L, int64_t n, int nsplit) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -187,6 +352,12 @@ __global__ void k_f64_to_f32(const double *__restrict__ s, float *__restrict__ d
 }  // namespace
 
 // number of offset slices so that a level launches at least ~4 blocks per CU
+hipError_t launch_split_K_bf16(ankh_plan_s *pl, const double *K, __bf16 *hi, __bf16 *lo) {
+    const int64_t n = (int64_t)kNumOff * pl->nup * pl->nup;
+    hipLaunchKernelGGL(k_split_K_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pl->stream, K, hi, lo, pl->nup);
+    return hipGetLastError();
+}
+
 int m2l_splits(const ankh_plan_s *pl, int e) {
     const int h = pl->lv[e].nside / 2;
     const int64_t tiles = (int64_t)((pl->nup + BM - 1) / BM) * ((h * h * h + BN - 1) / BN) * 8;
@@ -205,7 +376,15 @@ hipError_t launch_m2l(ankh_plan_s *pl, int e) {
     double *L = pl->d_L + lv.cell0 * pl->nup;
     double *out = nsplit > 1 ? pl->d_m2l_part : L;
     const size_t koff = (size_t)(e - 1) * kNumOff * pl->nup * pl->nup;
-    if (pl->precision == ANKH_MIXED) {
+    if (pl->precision == ANKH_MIXED_BF16X3) {
+        __bf16 *Mh = pl->d_Mb, *Ml = pl->d_Mb + nval;
+        hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream,
+                           pl->d_M + lv.cell0 * pl->nup, Mh, Ml, nval);
+        const size_t kb = (size_t)(e - 1) * kNumOff * pl->nup * pl->nup;
+        const size_t kall = (size_t)pl->depth * kNumOff * pl->nup * pl->nup;
+        hipLaunchKernelGGL(k_m2l_bf16x3, grid, dim3(256), 0, pl->stream, pl->d_Kb + kb, pl->d_Kb + kall + kb, Mh, Ml,
+                           out, lv.nside, pl->nup, nsplit, nval);
+    } else if (pl->precision == ANKH_MIXED) {
         float *Mf = pl->d_Mf;   // this level's multipoles in float32
         hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream,
                            pl->d_M + lv.cell0 * pl->nup, Mf, nval);

@@ -331,7 +331,7 @@ hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields) {
     a.eatom = pl->d_eatom;
     a.F = pl->d_F;
     a.G = pl->d_G;
-    if (pl->precision == ANKH_MIXED) return launch_t<float>(pl, a, ord, grad, fields);
+    if (is_mixed(pl)) return launch_t<float>(pl, a, ord, grad, fields);
     return launch_t<double>(pl, a, ord, grad, fields);
 }
 

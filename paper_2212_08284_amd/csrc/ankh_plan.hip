@@ -44,7 +44,8 @@ void free_all(ankh_plan_s *pl) {
                     pl->P.x, pl->P.y, pl->P.z, pl->P.q, pl->P.mu, pl->P.th, pl->P.qf, pl->P.muf, pl->P.thf,
                     pl->d_M, pl->d_L, pl->d_K, pl->d_Kf, pl->d_Cper, pl->d_eatom, pl->d_eleaf, pl->d_F,
                     pl->d_G, pl->d_terms, pl->d_part, pl->d_err, pl->d_tab0, pl->d_Mf, pl->d_m2l_part,
-                    pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr};
+                    pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr,
+                    pl->d_Kb, pl->d_Mb};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &set : pl->evsets)
@@ -190,8 +191,8 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
     if (!(box_radius > 0) || !std::isfinite(box_radius)) return ANKH_ERR_INVALID_ARG;
     if (!(rel_accuracy >= 1e-12 && rel_accuracy <= 1e-2)) return ANKH_ERR_INVALID_ARG;
     if (max_order < 0 || max_order > 2) return ANKH_ERR_INVALID_ARG;
-    if (precision != ANKH_FP64 && precision != ANKH_MIXED) return ANKH_ERR_INVALID_ARG;
-    if (precision == ANKH_MIXED && rel_accuracy < 1e-7) return ANKH_ERR_ACCURACY_UNREACHABLE;
+    if (precision != ANKH_FP64 && precision != ANKH_MIXED && precision != ANKH_MIXED_BF16X3) return ANKH_ERR_INVALID_ARG;
+    if (precision != ANKH_FP64 && rel_accuracy < 1e-7) return ANKH_ERR_ACCURACY_UNREACHABLE;
     if (ov) {
         if (ov->depth > kMaxDepth) return ANKH_ERR_INVALID_ARG;
         if (ov->order > 0 && (ov->order < 2 || ov->order > kMaxOrder)) return ANKH_ERR_INVALID_ARG;
@@ -301,7 +302,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         dalloc(pl, &pl->P.q, n);
         if (max_order >= 1) dalloc(pl, &pl->P.mu, 3 * n);
         if (max_order >= 2) dalloc(pl, &pl->P.th, 6 * n);
-        if (precision == ANKH_MIXED) {
+        if (precision != ANKH_FP64) {
             dalloc(pl, &pl->P.qf, n);
             if (max_order >= 1) dalloc(pl, &pl->P.muf, 3 * n);
             if (max_order >= 2) dalloc(pl, &pl->P.thf, 6 * n);
@@ -317,6 +318,8 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
             }
             if (part) dalloc(pl, &pl->d_m2l_part, part);
             if (precision == ANKH_MIXED && pl->depth >= 1) dalloc(pl, &pl->d_Mf, pl->lv[pl->depth].ncell * pl->nup);
+            if (precision == ANKH_MIXED_BF16X3 && pl->depth >= 1)
+                dalloc(pl, &pl->d_Mb, 2 * pl->lv[pl->depth].ncell * pl->nup);
         }
         const size_t kper = (size_t)kNumOff * pl->nup * pl->nup;
         dalloc(pl, &pl->d_Cper, (size_t)pl->nup0 * pl->nup0);
@@ -341,13 +344,20 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         ck(launch_zero_f64(pl->d_eatom, n, pl->stream));
         // operator tables: M2L matrices of levels 1..E and the far-image root operator
         if (pl->depth >= 1) {
-            if (precision == ANKH_MIXED) {
-                dalloc(pl, &pl->d_Kf, kper * pl->depth);
+            if (precision != ANKH_FP64) {
+                // build each level in float64, then keep the float32 or bf16 hi/lo form
+                const bool bf = precision == ANKH_MIXED_BF16X3;
+                if (bf) dalloc(pl, &pl->d_Kb, 2 * kper * pl->depth);
+                else dalloc(pl, &pl->d_Kf, kper * pl->depth);
                 double *tmp = nullptr;
                 ck(hipMalloc((void **)&tmp, kper * sizeof(double)));
                 for (int e = 1; e <= pl->depth; e++) {
                     ck(launch_build_m2l(pl, e, tmp));
-                    ck(launch_convert_f32(tmp, pl->d_Kf + (size_t)(e - 1) * kper, (int64_t)kper, pl->stream));
+                    if (bf)
+                        ck(launch_split_K_bf16(pl, tmp, pl->d_Kb + (size_t)(e - 1) * kper,
+                                               pl->d_Kb + (size_t)pl->depth * kper + (size_t)(e - 1) * kper));
+                    else
+                        ck(launch_convert_f32(tmp, pl->d_Kf + (size_t)(e - 1) * kper, (int64_t)kper, pl->stream));
                 }
                 ck(hipStreamSynchronize(pl->stream));
                 ck(hipFree(tmp));

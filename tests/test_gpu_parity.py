@@ -132,11 +132,12 @@ def test_water_9000_fp64_vs_oracle(ak):
     pl.close()
 
 
-def test_water_9000_mixed_vs_fp64(ak):
+@pytest.mark.parametrize("mode", ["mixed", "mixed_bf16x3"])
+def test_water_9000_mixed_vs_fp64(ak, mode):
     d = synth.workload("water_9000")
     g = np.load(os.path.join(GOLDEN, "water_9000.npz"))
     p64, e64, F64, G64 = _run(ak, d, eps=1e-6)
-    pmx, emx, Fmx, Gmx = _run(ak, d, eps=1e-6, prec="mixed")
+    pmx, emx, Fmx, Gmx = _run(ak, d, eps=1e-6, prec=mode)
     assert pmx.stats["order"] == p64.stats["order"] and pmx.stats["depth"] == p64.stats["depth"]
     assert abs(emx - e64) <= 1e-5 * abs(e64)
     assert rel_rms(Fmx, F64) <= 1e-4
@@ -255,7 +256,7 @@ def test_water_288000_sampled_vs_oracle(ak):
     g = np.load(path)
     d = synth.workload("water_288000")
     sel = g["sel"]
-    for prec, ftol in (("fp64", 1e-5), ("mixed", 1e-4)):
+    for prec, ftol in (("fp64", 1e-5), ("mixed", 1e-4), ("mixed_bf16x3", 1e-4)):
         pl, e, F, G = _run(ak, d, eps=1e-6, prec=prec)
         assert rel_rms(F[sel], g["forces"]) <= ftol
         assert rel_rms(G[sel], g["dEdmu"]) <= 10 * ftol
@@ -267,7 +268,7 @@ def test_water_9000000_mixed_vs_fp64(ak):
     d = synth.workload("water_9000000")
     n = len(d["q"])
     out = {}
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed_bf16x3"):
         pl = ak.Plan(n, 0.5 * d["edge"], 1e-5, 2, prec)
         e, F, G = pl.energy_forces(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
         pl.sync()
@@ -275,6 +276,7 @@ def test_water_9000000_mixed_vs_fp64(ak):
         pl.close()
         del e, F, G
         torch.cuda.empty_cache()
-    assert abs(out["mixed"][0] - out["fp64"][0]) <= 1e-5 * abs(out["fp64"][0])
-    assert rel_rms(out["mixed"][1], out["fp64"][1]) <= 1e-4
-    assert rel_rms(out["mixed"][2], out["fp64"][2]) <= 1e-4
+    mx = out["mixed_bf16x3"]
+    assert abs(mx[0] - out["fp64"][0]) <= 1e-5 * abs(out["fp64"][0])
+    assert rel_rms(mx[1], out["fp64"][1]) <= 1e-4
+    assert rel_rms(mx[2], out["fp64"][2]) <= 1e-4
