@@ -159,15 +159,16 @@ __global__ void k_gather(int64_t n, const int32_t *perm, const int32_t *leaf, co
 // T_m and its derivatives up to order ND-1 by the differentiated three-term
 // recurrence (identical to D^n T with the differentiation matrix D), then
 // S^(n)_k = (1/h)^n sum_m H[k][m] T^(n)_m.
-template <int ND>
-__device__ inline void cheb_basis(double xh, double hinv, int L, const double *sH, double *out /* [ND][L] */,
+template <int ND, int L>
+__device__ inline void cheb_basis(double xh, double hinv, const double *sH, double *out /* [ND][L] */,
                                   int stride_n) {
-    double T[ND][kMaxOrder];
+    double T[ND][L > 2 ? L : 2];
 #pragma unroll
     for (int n = 0; n < ND; n++) {
         T[n][0] = (n == 0) ? 1.0 : 0.0;
         T[n][1] = (n == 0) ? xh : (n == 1 ? 1.0 : 0.0);
     }
+#pragma unroll
     for (int m = 1; m + 1 < L; m++) {
         T[0][m + 1] = 2 * xh * T[0][m] - T[0][m - 1];
 #pragma unroll
@@ -176,8 +177,10 @@ __device__ inline void cheb_basis(double xh, double hinv, int L, const double *s
     double sc = 1.0;
 #pragma unroll
     for (int n = 0; n < ND; n++) {
+#pragma unroll
         for (int k = 0; k < L; k++) {
             double s = 0;
+#pragma unroll
             for (int m = 0; m < L; m++) s += sH[k * L + m] * T[n][m];
             out[n * stride_n + k] = s * sc;
         }
@@ -186,9 +189,9 @@ __device__ inline void cheb_basis(double xh, double hinv, int L, const double *s
 }
 
 // ---- P2M: modified charges of every leaf (Alg. 2) --------------------------
-template <int ORD>
-__global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, const double *tab, int L,
-                                             int nu, int nup, double hinv, double *Q, int64_t n) {
+template <int L, int ORD>
+__global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, const double *tab, int nu, int nup,
+                                             double hinv, double *Q, int64_t n) {
     constexpr int ND = ORD + 1;
     constexpr int CH = 64;
     extern __shared__ double sm[];
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, c
             const int a = tid / 3, ax = tid % 3;
             const int64_t slot = s0 + c0 + a;
             const double xl = ax == 0 ? P.x[slot] : (ax == 1 ? P.y[slot] : P.z[slot]);
-            cheb_basis<ND>(xl * hinv, hinv, L, sH, sS + (a * 3 + ax) * ND * L, L);
+            cheb_basis<ND, L>(xl * hinv, hinv, sH, sS + (a * 3 + ax) * ND * L, L);
         }
         if (tid < m) {
             const int64_t slot = s0 + c0 + tid;
@@ -363,24 +366,28 @@ __global__ __launch_bounds__(256) void k_l2l(const double *Lpar, double *Lch, co
 }
 
 // ---- far periodic images: L_root = C_per M_root, E_per = 1/2 M.C M -----------
-__global__ __launch_bounds__(1024) void k_cper(const double *C, const double *M, double *Lr, int nu, int nup,
-                                               double *terms) {
-    __shared__ double sM[kMaxRootNodes];
-    __shared__ double red[1024];
+// 64 rows per block, the contraction split over the block's 4 waves and
+// summed in a fixed order; the energy dot product follows in one block.
+__global__ __launch_bounds__(256) void k_cper(const double *C, const double *M, double *Lr, int nu, int nup) {
+    __shared__ double part[4][64];
+    const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + r;
+    double s = 0;
+    if (k < nu)
+        for (int l = w; l < nu; l += 4) s += C[(int64_t)l * nup + k] * M[l];
+    part[w][r] = s;
+    __syncthreads();
+    if (w == 0 && k < nup) Lr[k] = k < nu ? ((part[0][r] + part[1][r]) + (part[2][r] + part[3][r])) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_cper_dot(const double *M, const double *Lr, int nu, double *terms) {
+    __shared__ double red[256];
     const int t = threadIdx.x;
-    for (int k = t; k < nu; k += 1024) sM[k] = M[k];
+    double s = 0;
+    for (int k = t; k < nu; k += 256) s += M[k] * Lr[k];
+    red[t] = s;
     __syncthreads();
-    double part = 0;
-    for (int k = t; k < nup; k += 1024) {
-        double s = 0;
-        if (k < nu)
-            for (int l = 0; l < nu; l++) s += C[(int64_t)l * nup + k] * sM[l];
-        Lr[k] = s;
-        if (k < nu) part += sM[k] * s;
-    }
-    red[t] = part;
-    __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
+    for (int off = 128; off > 0; off >>= 1) {
         if (t < off) red[t] += red[t + off];
         __syncthreads();
     }
@@ -405,8 +412,8 @@ __global__ __launch_bounds__(256) void k_leafdot(const double *Q, const double *
 // ---- L2P: far-field forces and fields at the atoms (adjoint of P2M) --------
 // phi(y) = sum_k Lambda_k S_k(y); F = -(q grad phi + mu_a grad d_a phi + Th_ab grad d_a d_b phi),
 // dE/dmu = grad phi.  One wave per leaf, one atom per lane.
-template <int ORD, bool FIELD>
-__global__ __launch_bounds__(64) void k_l2p(Particles P, const int32_t *offs, const double *tab, int L, int nu,
+template <int L, int ORD, bool FIELD>
+__global__ __launch_bounds__(64) void k_l2p(Particles P, const int32_t *offs, const double *tab, int nu,
                                             int nup, double hinv, const double *Lam, double *F, double *G,
                                             int64_t n) {
     constexpr int ND = ORD + 2;   // derivative orders 0..ORD+1
@@ -423,9 +430,9 @@ __global__ __launch_bounds__(64) void k_l2p(Particles P, const int32_t *offs, co
     double *Sx = sS + tid * 3 * ND * L, *Sy = Sx + ND * L, *Sz = Sy + ND * L;
     for (int a = tid; a < cnt; a += nt) {
         const int64_t slot = s0 + a;
-        cheb_basis<ND>(P.x[slot] * hinv, hinv, L, sH, Sx, L);
-        cheb_basis<ND>(P.y[slot] * hinv, hinv, L, sH, Sy, L);
-        cheb_basis<ND>(P.z[slot] * hinv, hinv, L, sH, Sz, L);
+        cheb_basis<ND, L>(P.x[slot] * hinv, hinv, sH, Sx, L);
+        cheb_basis<ND, L>(P.y[slot] * hinv, hinv, sH, Sy, L);
+        cheb_basis<ND, L>(P.z[slot] * hinv, hinv, sH, Sz, L);
         double phi[ND][ND][ND];
 #pragma unroll
         for (int x = 0; x < ND; x++)
@@ -433,17 +440,20 @@ __global__ __launch_bounds__(64) void k_l2p(Particles P, const int32_t *offs, co
             for (int y = 0; y < ND; y++)
 #pragma unroll
                 for (int z = 0; z < ND; z++) phi[x][y][z] = 0;
+#pragma unroll 2
         for (int i = 0; i < L; i++) {
             double h[ND][ND];
 #pragma unroll
             for (int y = 0; y < ND; y++)
 #pragma unroll
                 for (int z = 0; z < ND; z++) h[y][z] = 0;
+#pragma unroll 2
             for (int j = 0; j < L; j++) {
                 double g[ND];
 #pragma unroll
                 for (int z = 0; z < ND; z++) g[z] = 0;
                 const double *row = sL + (i * L + j) * L;
+#pragma unroll
                 for (int k = 0; k < L; k++) {
                     const double lv = row[k];
 #pragma unroll
@@ -667,18 +677,37 @@ hipError_t launch_gather(ankh_plan_s *pl, const double *pos, const double *q, co
     return hipGetLastError();
 }
 
+#define ANKH_FOR_ORDER(L, X) \
+    switch (L) {                 \
+        case 2: X(2); break;     \
+        case 3: X(3); break;     \
+        case 4: X(4); break;     \
+        case 5: X(5); break;     \
+        case 6: X(6); break;     \
+        case 7: X(7); break;     \
+        case 8: X(8); break;     \
+        case 9: X(9); break;     \
+        default: X(10); break;   \
+    }
+
 hipError_t launch_p2m(ankh_plan_s *pl, int ord) {
     const int L = pl->order;
     const double hinv = 2.0 / (pl->edge / pl->nside);
     double *Q = pl->d_M + pl->lv[pl->depth].cell0 * pl->nup;
     const size_t shm = sizeof(double) * (L * L + 64 * 3 * (ord + 1) * L + 64 * 10);
     dim3 g((unsigned)pl->nleaf), b(256);
-    if (ord == 0)
-        hipLaunchKernelGGL(k_p2m<0>, g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, L, pl->nu, pl->nup, hinv, Q, pl->n);
-    else if (ord == 1)
-        hipLaunchKernelGGL(k_p2m<1>, g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, L, pl->nu, pl->nup, hinv, Q, pl->n);
-    else
-        hipLaunchKernelGGL(k_p2m<2>, g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, L, pl->nu, pl->nup, hinv, Q, pl->n);
+#define ANKH_P2M(LL)                                                                                              \
+    if (ord == 0)                                                                                                 \
+        hipLaunchKernelGGL((k_p2m<LL, 0>), g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, pl->nu, pl->nup, \
+                           hinv, Q, pl->n);                                                                       \
+    else if (ord == 1)                                                                                            \
+        hipLaunchKernelGGL((k_p2m<LL, 1>), g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, pl->nu, pl->nup, \
+                           hinv, Q, pl->n);                                                                       \
+    else                                                                                                          \
+        hipLaunchKernelGGL((k_p2m<LL, 2>), g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, pl->nu, pl->nup, \
+                           hinv, Q, pl->n);
+    ANKH_FOR_ORDER(L, ANKH_P2M)
+#undef ANKH_P2M
     return hipGetLastError();
 }
 
@@ -715,8 +744,9 @@ hipError_t launch_l2l(ankh_plan_s *pl, int e_child) {
 }
 
 hipError_t launch_cper(ankh_plan_s *pl) {
-    hipLaunchKernelGGL(k_cper, dim3(1), dim3(1024), 0, pl->stream, pl->d_Cper, pl->d_rootM, pl->d_rootL, pl->nu0,
-                       pl->nup0, pl->d_terms);
+    hipLaunchKernelGGL(k_cper, dim3((pl->nup0 + 63) / 64), dim3(256), 0, pl->stream, pl->d_Cper, pl->d_rootM,
+                       pl->d_rootL, pl->nu0, pl->nup0);
+    hipLaunchKernelGGL(k_cper_dot, dim3(1), dim3(256), 0, pl->stream, pl->d_rootM, pl->d_rootL, pl->nu0, pl->d_terms);
     return hipGetLastError();
 }
 
@@ -735,12 +765,15 @@ hipError_t launch_l2p(ankh_plan_s *pl, int ord, bool fields) {
     const int nt = (sizeof(double) * (L * L + pl->nu + 64 * 3 * (ord + 2) * L) <= 65536) ? 64 : 32;
     const size_t shm = sizeof(double) * (L * L + pl->nu + nt * 3 * (ord + 2) * L);
     dim3 g((unsigned)pl->nleaf), b(nt);
-#define ANKH_L2P(O, FL) \
-    hipLaunchKernelGGL((k_l2p<O, FL>), g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, L, pl->nu, pl->nup, \
+#define ANKH_L2P3(LL, O, FL)                                                                                      \
+    hipLaunchKernelGGL((k_l2p<LL, O, FL>), g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, pl->nu, pl->nup,  \
                        hinv, Lam, pl->d_F, pl->d_G, pl->n)
-    if (ord == 0) { if (fields) ANKH_L2P(0, true); else ANKH_L2P(0, false); }
-    else if (ord == 1) { if (fields) ANKH_L2P(1, true); else ANKH_L2P(1, false); }
-    else { if (fields) ANKH_L2P(2, true); else ANKH_L2P(2, false); }
+#define ANKH_L2P(LL)                                                                         \
+    if (ord == 0) { if (fields) ANKH_L2P3(LL, 0, true); else ANKH_L2P3(LL, 0, false); }     \
+    else if (ord == 1) { if (fields) ANKH_L2P3(LL, 1, true); else ANKH_L2P3(LL, 1, false); } \
+    else { if (fields) ANKH_L2P3(LL, 2, true); else ANKH_L2P3(LL, 2, false); }
+    ANKH_FOR_ORDER(L, ANKH_L2P)
+#undef ANKH_L2P3
 #undef ANKH_L2P
     return hipGetLastError();
 }
