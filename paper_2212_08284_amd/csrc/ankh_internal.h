@@ -89,6 +89,9 @@ struct ankh_plan_s {
     double *d_m2l_part = nullptr; // split-K partial local expansions of one level
     double *d_Cper = nullptr;     // far-image root operator [nup0][nup0]
     double *d_eatom = nullptr;    // near-field energy per leaf-order atom
+    double *d_slot_e = nullptr;   // near-field partials per atom and adjacent-leaf task: energy [27][n]
+    void *d_slot_f = nullptr;     //   forces [3][27][n] and fields [3][27][n], float64 or float32
+    void *d_slot_g = nullptr;
     double *d_eleaf = nullptr;    // far energy per leaf
     double *d_F = nullptr;        // forces in leaf order [3][n]
     double *d_G = nullptr;        // fields in leaf order [3][n]

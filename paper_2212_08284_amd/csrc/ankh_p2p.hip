@@ -1,26 +1,34 @@
 // P2P near field (ANKH-FMM, Alg. 3 step 3): direct pair sums of the
-// multipole operator on H = erfc(xi r)/r between every leaf and the 27
-// leaves adjacent to it (periodic, so at depth <= 1 a leaf meets images of
-// itself), excluding an atom with itself at zero shift.
+// multipole operator on H = erfc(xi r)/r between every leaf and the 27 leaves
+// adjacent to it (periodic, so at depth <= 1 a leaf meets images of itself),
+// excluding an atom with itself at zero shift.
 //
-// Gather form: a block owns one target leaf; every target atom sums over all
-// its sources, so each ordered pair is evaluated once per endpoint and no
-// atomics are needed.  Sources are streamed through LDS in chunks drawn from
-// the concatenation of the 27 neighbour leaves, already shifted into the
-// target leaf's frame; the block's threads are split into (target, slice)
-// pairs so that small leaves still fill the block, and the slices are
-// reduced in a fixed order.
+// Mutual form (the pair symmetry of the mutual-interactions section): each
+// unordered pair of adjacent leaves is one task, (t, t + d) for the 13 offsets
+// d > 0 (lexicographically), and every pair of atoms in it is evaluated once:
+// the target atom takes the energy, its force and its field, the source atom
+// takes the opposite force and its own field.  The leaf with itself is a
+// fourteenth task evaluated in gather form (all ordered pairs, half energy).
 //
-// Pair terms (r = x_i - x_j, D_x = q + mu.d + Th:dd on x, and the mirrored
-// operator on the source):  with B_0 = H, B_{n+1} = -(1/r) dB_n/dr,
+// Inside a task block the 256 threads form 16 groups of 16 lanes.  The lanes
+// of a group hold 16 target atoms and read the same source atom (an LDS
+// broadcast); the source's share is summed over the 16 lanes with DPP row
+// operations and added to that source's LDS accumulator by the one group that
+// owns it.  The target shares of the 16 groups are summed through LDS.  Every
+// atom receives one partial per adjacent-leaf task (27 slots); k_p2p_slots
+// adds them in slot order.  No atomics: results are bitwise reproducible.
+//
+// Pair terms (r = x_i - x_j, D_x = q + mu.d + Th:dd on x, the mirrored
+// operator on the source): with B_0 = H, B_{n+1} = -(1/r) dB_n/dr,
 //   E_ij = c0 B0 + c1 B1 + c2 B2 + c3 B3 + c4 B4,
 //   c0 = qi qk
 //   c1 = qi (dk.r) - qk (di.r) + di.dk
 //   c2 = -(di.r)(dk.r) + qi r.Qk.r + qk r.Qi.r + 2 di.Qk.r - 2 dk.Qi.r + 2 Qi:Qk
 //   c3 = -(di.r) r.Qk.r + (dk.r) r.Qi.r - 4 (Qi r).(Qk r)
 //   c4 = (r.Qi.r)(r.Qk.r)
-// grad_r E_ij = sum_n grad(c_n) B_n - r sum_n c_n B_{n+1};  F_i = -sum_j grad_r E_ij;
-// dE/d(di) = B1 (dk - qk r) + B2 (2 Qk r - (dk.r) r) - B3 (r.Qk.r) r.
+// grad_r E_ij = sum_n grad(c_n) B_n - r sum_n c_n B_{n+1};  F_i = -grad_r E_ij = -F_j;
+// dE/d(di) = B1 (dk - qk r) + B2 (2 Qk r - (dk.r) r) - B3 (r.Qk.r) r,
+// dE/d(dk) = B1 (di + qi r) - B2 (2 Qi r + (di.r) r) + B3 (r.Qi.r) r.
 // The radial functions follow B_n = [(2n-1) B_{n-1} + (2 xi^2)^n exp(-xi^2 r^2)/(xi sqrt(pi))] / r^2.
 #include <cmath>
 
@@ -29,7 +37,10 @@
 namespace ankh {
 namespace {
 
-constexpr int CH = 256;   // sources per LDS chunk
+constexpr int CH = 128;     // source atoms per LDS chunk
+constexpr int NT = 14;      // tasks per leaf: itself + 13 half-shell neighbours
+constexpr int G = 16;       // lanes per group (one DPP row)
+constexpr int NG = 16;      // groups per block
 
 struct P2PArgs {
     const double *x, *y, *z;
@@ -39,7 +50,9 @@ struct P2PArgs {
     int64_t n;
     int nside, depth;
     double w, xi;
-    double *eatom, *F, *G;
+    double *slot_e;         // [27][n] energy partials (target side)
+    void *slot_f;           // [3][27][n] force partials (R)
+    void *slot_g;           // [3][27][n] field partials (R)
 };
 
 template <typename R> __device__ inline R dev_erfc(R v);
@@ -52,6 +65,45 @@ template <typename R> __device__ inline R dev_rsqrt(R v);
 template <> __device__ inline double dev_rsqrt<double>(double v) { return 1.0 / sqrt(v); }
 template <> __device__ inline float dev_rsqrt<float>(float v) { return rsqrtf(v); }
 
+// sum over the 16 lanes of a DPP row; every lane of the row receives the sum
+__device__ inline float row16_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));  // row half-mirror
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false));  // row mirror
+    return v;
+}
+__device__ inline double dpp64(double v, int ctrl) {
+    const long long b = __double_as_longlong(v);
+    int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+    switch (ctrl) {
+        case 0xB1:
+            lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+            break;
+        case 0x4E:
+            lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
+            break;
+        case 0x141:
+            lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false);
+            break;
+        default:
+            lo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false);
+            break;
+    }
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double row16_sum(double v) {
+    v += dpp64(v, 0xB1);
+    v += dpp64(v, 0x4E);
+    v += dpp64(v, 0x141);
+    v += dpp64(v, 0x140);
+    return v;
+}
+
 template <typename R>
 __device__ inline void symv(const R *Q, R vx, R vy, R vz, R &ox, R &oy, R &oz) {
     // Q = (xx, xy, xz, yy, yz, zz)
@@ -60,9 +112,11 @@ __device__ inline void symv(const R *Q, R vx, R vy, R vz, R &ox, R &oy, R &oz) {
     oz = Q[2] * vx + Q[4] * vy + Q[5] * vz;
 }
 
-template <typename R, int ORD, bool GRAD, bool FIELD>
+// One pair: adds ew * E to e, -grad to f (target force) and the target field
+// to g; with SRC also the source field to gs (the source force is -f's share).
+template <typename R, int ORD, bool GRAD, bool FIELD, bool SRC>
 __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *Qi, R ck, const R *dk,
-                                  const R *Qk, R xi, R xi2, R cex, double &e, R *f, R *g) {
+                                  const R *Qk, R xi, R xi2, R cex, R ew, R &e, R *f, R *g, R *gs) {
     constexpr int NB = 2 * ORD + 1 + (GRAD ? 1 : 0);
     const R r2 = rx * rx + ry * ry + rz * rz;
     const R rinv = dev_rsqrt<R>(r2);
@@ -106,9 +160,8 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
     R E = c0 * B[0];
     if (ORD >= 1) E += c1 * B[1] + c2 * B[2];
     if (ORD >= 2) E += c3 * B[3] + c4 * B[4];
-    e += 0.5 * (double)E;
+    e += ew * E;
     if (GRAD) {
-        // s = sum_n c_n B_{n+1}
         R s = c0 * B[1];
         if (ORD >= 1) s += c1 * B[2] + c2 * B[3];
         if (ORD >= 2) s += c3 * B[4] + c4 * B[5];
@@ -134,18 +187,22 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
                 gr[a] += B[4] * (2 * qkrr * Qir[a] + 2 * qirr * Qkr[a]);
             }
         }
-        f[0] -= gr[0];
-        f[1] -= gr[1];
-        f[2] -= gr[2];
+        f[0] = -gr[0];
+        f[1] = -gr[1];
+        f[2] = -gr[2];
     }
     if (FIELD) {
         const R rv[3] = {rx, ry, rz};
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            R v = B[1] * (dk[a] - ck * rv[a]);
-            if (ORD >= 1) v -= B[2] * dkr * rv[a];
+            R v = B[1] * (dk[a] - ck * rv[a]) - B[2] * dkr * rv[a];
             if (ORD >= 2) v += B[2] * 2 * Qkr[a] - B[3] * qkrr * rv[a];
-            g[a] += v;
+            g[a] = v;
+            if (SRC) {
+                R u = B[1] * (di[a] + ci * rv[a]) - B[2] * dir * rv[a];
+                if (ORD >= 2) u += B[3] * qirr * rv[a] - B[2] * 2 * Qir[a];
+                gs[a] = u;
+            }
         }
     }
 }
@@ -164,136 +221,200 @@ template <typename R> __device__ inline const R *pick(const double *d, const flo
 template <> __device__ inline const double *pick<double>(const double *d, const float *) { return d; }
 template <> __device__ inline const float *pick<float>(const double *, const float *f) { return f; }
 
+// task k of a leaf: 0 = itself, 1..13 = the half-shell offsets in lexicographic order
+__device__ inline void task_offset(int k, int &dx, int &dy, int &dz) {
+    if (k == 0) { dx = dy = dz = 0; return; }
+    int c = 0;
+    for (int a = -1; a <= 1; a++)
+        for (int b = -1; b <= 1; b++)
+            for (int e = -1; e <= 1; e++) {
+                const bool pos = a > 0 || (a == 0 && (b > 0 || (b == 0 && e > 0)));
+                if (!pos) continue;
+                if (++c == k) { dx = a; dy = b; dz = e; return; }
+            }
+}
+
 template <typename R, int ORD, bool GRAD, bool FIELD>
 __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
+    constexpr int NM = 1 + (ORD >= 1 ? 3 : 0) + (ORD >= 2 ? 6 : 0);   // moment components
     __shared__ double sx[CH], sy[CH], sz[CH];
-    __shared__ R sq[CH];
-    __shared__ R smu[ORD >= 1 ? 3 : 1][CH];
-    __shared__ R sth[ORD >= 2 ? 6 : 1][CH];
-    __shared__ int sid[CH];
-    __shared__ int nb_start[27], nb_pref[28];
-    __shared__ double nb_sh[27][3];
-    __shared__ double red[7][256];
+    __shared__ R smo[NM][CH];
+    __shared__ R sacc[6][CH];           // source-side force (3) and field (3)
+    __shared__ double tpart[7][NG][G];  // target-side partials of the 16 groups
 
     const int tid = threadIdx.x;
-    const int64_t nleaf = (int64_t)a.nside * a.nside * a.nside;
-    // XCD-aware order: consecutive blocks go to different XCDs, so give each
-    // XCD a contiguous Morton range of leaves (neighbours share its L2)
-    int64_t logical = blockIdx.x;
-    if ((nleaf & 7) == 0) logical = (int64_t)(blockIdx.x & 7) * (nleaf >> 3) + (blockIdx.x >> 3);
-    const int leaf = morton_leaf(logical, a.depth, a.nside);
+    const int grp = tid >> 4, ln = tid & 15;
     const int ns = a.nside;
+    const int64_t nleaf = (int64_t)ns * ns * ns;
+    // XCD-aware order: each XCD receives a contiguous Morton range of leaves with all their tasks
+    const int64_t nblk = nleaf * NT;
+    int64_t task = blockIdx.x;
+    if ((nblk & 7) == 0) task = (int64_t)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
+    const int k = (int)(task % NT);
+    const int leaf = morton_leaf(task / NT, a.depth, ns);
+    int dx, dy, dz;
+    task_offset(k, dx, dy, dz);
+    const bool self = k == 0;
     const int tx = leaf / (ns * ns), ty = (leaf / ns) % ns, tz = leaf % ns;
+    const int src = (((tx + dx + ns) % ns) * ns + (ty + dy + ns) % ns) * ns + (tz + dz + ns) % ns;
     const int t0 = a.offs[leaf], nt = a.offs[leaf + 1] - t0;
-    if (nt == 0) return;
-
-    if (tid < 27) {
-        const int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
-        const int sxl = (tx + dx + ns) % ns, syl = (ty + dy + ns) % ns, szl = (tz + dz + ns) % ns;
-        const int s = (sxl * ns + syl) * ns + szl;
-        nb_start[tid] = a.offs[s];
-        nb_pref[tid + 1] = a.offs[s + 1] - a.offs[s];
-        nb_sh[tid][0] = dx * a.w;
-        nb_sh[tid][1] = dy * a.w;
-        nb_sh[tid][2] = dz * a.w;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        nb_pref[0] = 0;
-        for (int i = 0; i < 27; i++) nb_pref[i + 1] += nb_pref[i];
-    }
-    __syncthreads();
-    const int total = nb_pref[27];
+    const int s0 = a.offs[src], nsrc = a.offs[src + 1] - s0;
+    const int slot_t = (dx + 1) * 9 + (dy + 1) * 3 + (dz + 1);       // target side of this task
+    const int slot_s = (1 - dx) * 9 + (1 - dy) * 3 + (1 - dz);       // source side (offset -d)
+    const double shx = dx * a.w, shy = dy * a.w, shz = dz * a.w;
 
     const R *q = pick<R>(a.q, a.qf), *mu = pick<R>(a.mu, a.muf), *th = pick<R>(a.th, a.thf);
     const int64_t n = a.n;
+    R *SF = static_cast<R *>(a.slot_f), *SG = static_cast<R *>(a.slot_g);
+    const int64_t sstride = 27 * n;     // component stride of the slot arrays
     const R xi = (R)a.xi, xi2 = (R)(a.xi * a.xi), cex = (R)(1.0 / (a.xi * 1.7724538509055160273));
+    const R ew = self ? (R)0.5 : (R)1.0;
 
-    for (int tc0 = 0; tc0 < nt; tc0 += 256) {
-        const int ntc = min(256, nt - tc0);
-        const int nsl = 256 / ntc;
-        const int my_t = tid % ntc, my_sl = tid / ntc;
-        const bool active = my_sl < nsl;
-        const int64_t slot = t0 + tc0 + my_t;
-        double xt = 0, yt = 0, zt = 0;
-        R ci = 0, di[3] = {0, 0, 0}, Qi[6] = {0, 0, 0, 0, 0, 0};
-        if (active) {
-            xt = a.x[slot];
-            yt = a.y[slot];
-            zt = a.z[slot];
-            ci = q[slot];
+    for (int cs = 0; cs < nsrc || (cs == 0 && nsrc == 0); cs += CH) {
+        const int chn = min(CH, nsrc - cs);
+        __syncthreads();
+        for (int f = tid; f < chn; f += 256) {
+            const int64_t sj = s0 + cs + f;
+            sx[f] = a.x[sj] + shx;
+            sy[f] = a.y[sj] + shy;
+            sz[f] = a.z[sj] + shz;
+            smo[0][f] = q[sj];
             if (ORD >= 1)
-                for (int c = 0; c < 3; c++) di[c] = mu[c * n + slot];
+                for (int c = 0; c < 3; c++) smo[1 + c][f] = mu[c * n + sj];
             if (ORD >= 2)
-                for (int c = 0; c < 6; c++) Qi[c] = th[c * n + slot];
+                for (int c = 0; c < 6; c++) smo[4 + c][f] = th[c * n + sj];
+            for (int c = 0; c < 6; c++) sacc[c][f] = 0;
         }
-        double e = 0;
-        R f[3] = {0, 0, 0}, g[3] = {0, 0, 0};
-        for (int cs = 0; cs < total; cs += CH) {
-            const int chn = min(CH, total - cs);
-            __syncthreads();
-            for (int fidx = tid; fidx < chn; fidx += 256) {
-                const int flat = cs + fidx;
-                int nb = 0;
-                while (flat >= nb_pref[nb + 1]) nb++;
-                const int64_t src = nb_start[nb] + (flat - nb_pref[nb]);
-                sx[fidx] = a.x[src] + nb_sh[nb][0];
-                sy[fidx] = a.y[src] + nb_sh[nb][1];
-                sz[fidx] = a.z[src] + nb_sh[nb][2];
-                sq[fidx] = q[src];
+        __syncthreads();
+        for (int tp = 0; tp < nt; tp += G) {
+            const int i = tp + ln;
+            const bool iv = i < nt;
+            const int64_t ti = t0 + (iv ? i : 0);
+            // an absent target sits far away with zero moments: its pair terms vanish
+            const double xt = iv ? a.x[ti] : 1.0e4, yt = iv ? a.y[ti] : 1.0e4, zt = iv ? a.z[ti] : 1.0e4;
+            R ci = iv ? q[ti] : (R)0, di[3] = {0, 0, 0}, Qi[6] = {0, 0, 0, 0, 0, 0};
+            if (ORD >= 1 && iv)
+                for (int c = 0; c < 3; c++) di[c] = mu[c * n + ti];
+            if (ORD >= 2 && iv)
+                for (int c = 0; c < 6; c++) Qi[c] = th[c * n + ti];
+            R te = 0, tf[3] = {0, 0, 0}, tg[3] = {0, 0, 0};
+            for (int j = grp; j < chn; j += NG) {
+                const bool skip = self && (j + cs == i);   // an atom with itself at zero shift
+                const R rx = (R)(xt - sx[j]), ry = (R)(yt - sy[j]), rz = (R)(zt - sz[j]);
+                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
                 if (ORD >= 1)
-                    for (int c = 0; c < 3; c++) smu[c][fidx] = mu[c * n + src];
+                    for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
                 if (ORD >= 2)
-                    for (int c = 0; c < 6; c++) sth[c][fidx] = th[c * n + src];
-                sid[fidx] = (nb == 13) ? (int)src : -1;
-            }
-            __syncthreads();
-            if (active) {
-                for (int j = my_sl; j < chn; j += nsl) {
-                    if (sid[j] == (int)slot) continue;
-                    const R rx = (R)(xt - sx[j]), ry = (R)(yt - sy[j]), rz = (R)(zt - sz[j]);
-                    R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
-                    if (ORD >= 1)
-                        for (int c = 0; c < 3; c++) dk[c] = smu[c][j];
-                    if (ORD >= 2)
-                        for (int c = 0; c < 6; c++) Qk[c] = sth[c][j];
-                    pair_terms<R, ORD, GRAD, FIELD>(rx, ry, rz, ci, di, Qi, sq[j], dk, Qk, xi, xi2, cex, e, f, g);
+                    for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
+                R pe = 0, pf[3] = {0, 0, 0}, pg[3] = {0, 0, 0}, ps[3] = {0, 0, 0};
+                if (!skip) {
+                    if (self)
+                        pair_terms<R, ORD, GRAD, FIELD, false>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, xi, xi2,
+                                                               cex, ew, pe, pf, pg, ps);
+                    else
+                        pair_terms<R, ORD, GRAD, FIELD, true>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, xi, xi2,
+                                                              cex, ew, pe, pf, pg, ps);
+                }
+                te += pe;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    tf[c] += pf[c];
+                    tg[c] += pg[c];
+                }
+                if (!self && (GRAD || FIELD)) {
+                    // the source's share, summed over the 16 targets of the group
+                    R v[6];
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        v[c] = GRAD ? row16_sum(-pf[c]) : (R)0;
+                        v[3 + c] = FIELD ? row16_sum(ps[c]) : (R)0;
+                    }
+                    if (ln == 0) {
+#pragma unroll
+                        for (int c = 0; c < 6; c++) sacc[c][j] += v[c];
+                    }
                 }
             }
-        }
-        // reduce the slices of each target in a fixed order
-        __syncthreads();
-        red[0][tid] = active ? e : 0.0;
-        red[1][tid] = active ? (double)f[0] : 0.0;
-        red[2][tid] = active ? (double)f[1] : 0.0;
-        red[3][tid] = active ? (double)f[2] : 0.0;
-        red[4][tid] = active ? (double)g[0] : 0.0;
-        red[5][tid] = active ? (double)g[1] : 0.0;
-        red[6][tid] = active ? (double)g[2] : 0.0;
-        __syncthreads();
-        if (tid < ntc) {
-            double v[7] = {0, 0, 0, 0, 0, 0, 0};
-            for (int sl = 0; sl < nsl; sl++)
-                for (int c = 0; c < 7; c++) v[c] += red[c][sl * ntc + tid];
-            const int64_t s = t0 + tc0 + tid;
-            a.eatom[s] = v[0];
-            if (GRAD) {
-                a.F[s] += v[1];
-                a.F[n + s] += v[2];
-                a.F[2 * n + s] += v[3];
+            // target partials: sum the 16 groups in a fixed order
+            tpart[0][grp][ln] = (double)te;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                tpart[1 + c][grp][ln] = (double)tf[c];
+                tpart[4 + c][grp][ln] = (double)tg[c];
             }
-            if (FIELD) {
-                a.G[s] += v[4];
-                a.G[n + s] += v[5];
-                a.G[2 * n + s] += v[6];
+            __syncthreads();
+            if (tid < 7 * G) {
+                const int c = tid / G, l = tid % G;
+                const int ii = tp + l;
+                if (ii < nt) {
+                    double s = 0;
+                    for (int g2 = 0; g2 < NG; g2++) s += tpart[c][g2][l];
+                    const int64_t at = t0 + ii;
+                    if (c == 0) {
+                        double *pe = a.slot_e + (int64_t)slot_t * n + at;
+                        *pe = (cs == 0) ? s : *pe + s;
+                    } else if ((c <= 3 && GRAD) || (c >= 4 && FIELD)) {
+                        R *p = (c <= 3 ? SF + (int64_t)(c - 1) * sstride : SG + (int64_t)(c - 4) * sstride) +
+                               (int64_t)slot_t * n + at;
+                        *p = (cs == 0) ? (R)s : (R)(*p + (R)s);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // source side of this chunk (mutual tasks only)
+        if (!self) {
+            for (int f = tid; f < chn; f += 256) {
+                const int64_t sj = s0 + cs + f;
+                if (GRAD)
+                    for (int c = 0; c < 3; c++) SF[(int64_t)c * sstride + (int64_t)slot_s * n + sj] = sacc[c][f];
+                if (FIELD)
+                    for (int c = 0; c < 3; c++) SG[(int64_t)c * sstride + (int64_t)slot_s * n + sj] = sacc[3 + c][f];
+                a.slot_e[(int64_t)slot_s * n + sj] = 0.0;
+            }
+        }
+        if (nsrc == 0) break;
+    }
+    // with no source atoms the target slot must still hold zeros
+    if (nsrc == 0) {
+        for (int i = tid; i < nt; i += 256) {
+            const int64_t at = t0 + i;
+            a.slot_e[(int64_t)slot_t * n + at] = 0.0;
+            for (int c = 0; c < 3; c++) {
+                if (GRAD) SF[(int64_t)c * sstride + (int64_t)slot_t * n + at] = 0;
+                if (FIELD) SG[(int64_t)c * sstride + (int64_t)slot_t * n + at] = 0;
             }
         }
     }
 }
 
+// per atom: near energy = sum of the energy slots; F, G += sum of their slots (fixed slot order)
+template <typename R, bool GRAD, bool FIELD>
+__global__ void k_p2p_slots(int64_t n, const double *slot_e, const R *SF, const R *SG, double *eatom, double *F,
+                            double *G) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double e = 0;
+    for (int s = 0; s < 27; s++) e += slot_e[(int64_t)s * n + i];
+    eatom[i] = e;
+    const int64_t st = 27 * n;
+    if (GRAD)
+        for (int c = 0; c < 3; c++) {
+            double v = 0;
+            for (int s = 0; s < 27; s++) v += (double)SF[c * st + (int64_t)s * n + i];
+            F[c * n + i] += v;
+        }
+    if (FIELD)
+        for (int c = 0; c < 3; c++) {
+            double v = 0;
+            for (int s = 0; s < 27; s++) v += (double)SG[c * st + (int64_t)s * n + i];
+            G[c * n + i] += v;
+        }
+}
+
 template <typename R>
 hipError_t launch_t(ankh_plan_s *pl, const P2PArgs &a, int ord, bool grad, bool fields) {
-    dim3 g((unsigned)pl->nleaf), b(256);
+    dim3 g((unsigned)(pl->nleaf * NT)), b(256);
     hipStream_t s = pl->stream;
 #define ANKH_P2P(O, GR, FL) hipLaunchKernelGGL((k_p2p<R, O, GR, FL>), g, b, 0, s, a)
     if (ord == 0) {
@@ -306,6 +427,17 @@ hipError_t launch_t(ankh_plan_s *pl, const P2PArgs &a, int ord, bool grad, bool 
         else ANKH_P2P(2, false, false);
     }
 #undef ANKH_P2P
+    dim3 g2((unsigned)((pl->n + 255) / 256));
+    const R *SF = static_cast<const R *>(a.slot_f), *SG = static_cast<const R *>(a.slot_g);
+    if (grad && fields)
+        hipLaunchKernelGGL((k_p2p_slots<R, true, true>), g2, b, 0, s, pl->n, a.slot_e, SF, SG, pl->d_eatom, pl->d_F,
+                           pl->d_G);
+    else if (grad)
+        hipLaunchKernelGGL((k_p2p_slots<R, true, false>), g2, b, 0, s, pl->n, a.slot_e, SF, SG, pl->d_eatom, pl->d_F,
+                           pl->d_G);
+    else
+        hipLaunchKernelGGL((k_p2p_slots<R, false, false>), g2, b, 0, s, pl->n, a.slot_e, SF, SG, pl->d_eatom,
+                           pl->d_F, pl->d_G);
     return hipGetLastError();
 }
 
@@ -328,9 +460,9 @@ hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields) {
     a.depth = pl->depth;
     a.w = pl->edge / pl->nside;
     a.xi = pl->xi;
-    a.eatom = pl->d_eatom;
-    a.F = pl->d_F;
-    a.G = pl->d_G;
+    a.slot_e = pl->d_slot_e;
+    a.slot_f = pl->d_slot_f;
+    a.slot_g = pl->d_slot_g;
     if (is_mixed(pl)) return launch_t<float>(pl, a, ord, grad, fields);
     return launch_t<double>(pl, a, ord, grad, fields);
 }
