@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--mixed-only", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--mode", default="mixed_bf16x3", choices=["mixed", "mixed_bf16x3"],
                     help="precision mode of the headline (mixed) path")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before the timed region, one device-to-device copy of this many MiB (a plain copy kernel "
+                         "of known size that calibrates the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU sharding is a "
@@ -115,6 +118,15 @@ def main():
         return None if a is None else torch.tensor(a, dtype=torch.float64, device=dev)
 
     args_dev = (T(data["pos"]), T(data["q"]), T(data["mu"]), T(data["theta"]))
+    if args.calib_copy_mb > 0:
+        nb = args.calib_copy_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nb} bytes read, {nb} bytes written")
+        del src, dst
     rB = 0.5 * data["edge"]
     log(f"workload {args.workload}: n={n} edge={data['edge']:.3f}")
 

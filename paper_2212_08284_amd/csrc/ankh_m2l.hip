@@ -18,6 +18,9 @@
 // enough blocks to fill the chip at every level; their partial tiles are
 // summed in a fixed order by k_m2l_reduce, so results do not depend on
 // scheduling.
+#include <algorithm>
+#include <cmath>
+
 #include "ankh_internal.h"
 
 namespace ankh {
@@ -47,7 +50,34 @@ template <> struct Mma<double> {
     static __device__ inline int row(int lk, int v) { return lk + 4 * v; }
 };
 
-// blockIdx: x = row tile, y = cell tile, z = class * nsplit + split
+// Block order: the 8 XCDs receive blocks round-robin (block id mod 8).  All
+// blocks placed on one XCD share one (row tile, offset slice) of K, small
+// enough for that XCD's L2, so each slice is fetched from memory once; the
+// cell tiles and parity classes vary fastest.
+struct M2LTile {
+    int rt, ct, cls, split;
+};
+__device__ inline M2LTile m2l_tile(int nrt, int nct, int nsplit) {
+    const int b = blockIdx.x;
+    const int ncc = nct * 8, nrs = nrt * nsplit;
+    int rs, cc;
+    if ((nrs & 7) == 0) {
+        const int xcd = b & 7, local = b >> 3;
+        rs = xcd * (nrs >> 3) + local / ncc;
+        cc = local % ncc;
+    } else {
+        rs = b / ncc;
+        cc = b % ncc;
+    }
+    M2LTile t;
+    t.rt = rs % nrt;
+    t.split = rs / nrt;
+    t.ct = cc % nct;
+    t.cls = cc / nct;
+    return t;
+}
+
+// one block per (row tile, cell tile, parity class, offset slice), ordered by m2l_tile
 template <typename T>
 __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *__restrict__ M,
                                              double *__restrict__ out, int nside, int nup, int nsplit,
@@ -60,8 +90,9 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int rt = blockIdx.x, ct = blockIdx.y;
-    const int cls = blockIdx.z / nsplit, split = blockIdx.z % nsplit;
+    const M2LTile tile = m2l_tile((nup + BM - 1) / BM, ((nside >> 1) * (nside >> 1) * (nside >> 1) + BN - 1) / BN,
+                                  nsplit);
+    const int rt = tile.rt, ct = tile.ct, cls = tile.cls, split = tile.split;
     const int px = cls >> 2, py = (cls >> 1) & 1, pz = cls & 1;
     const int h = nside >> 1;
     const int ncls = h * h * h;
@@ -194,8 +225,9 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ K
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int rt = blockIdx.x, ct = blockIdx.y;
-    const int cls = blockIdx.z / nsplit, split = blockIdx.z % nsplit;
+    const M2LTile tile = m2l_tile((nup + BM - 1) / BM, ((nside >> 1) * (nside >> 1) * (nside >> 1) + BN - 1) / BN,
+                                  nsplit);
+    const int rt = tile.rt, ct = tile.ct, cls = tile.cls, split = tile.split;
     const int px = cls >> 2, py = (cls >> 1) & 1, pz = cls & 1;
     const int h = nside >> 1;
     const int ncls = h * h * h;
@@ -358,12 +390,21 @@ hipError_t launch_split_K_bf16(ankh_plan_s *pl, const double *K, __bf16 *hi, __b
     return hipGetLastError();
 }
 
+// Number of offset slices (split-K): enough blocks to fill the chip (>= 1024),
+// K slices of at most ~3 MiB (one per XCD L2 at a time), and, where possible,
+// (row tiles x slices) a multiple of 8 for the XCD-aware block order.
 int m2l_splits(const ankh_plan_s *pl, int e) {
     const int h = pl->lv[e].nside / 2;
-    const int64_t tiles = (int64_t)((pl->nup + BM - 1) / BM) * ((h * h * h + BN - 1) / BN) * 8;
-    int s = 1;
-    while (s < 27 && tiles * s < 1024) s++;
-    return s;
+    const int nrt = (pl->nup + BM - 1) / BM;
+    const int64_t tiles = (int64_t)nrt * ((h * h * h + BN - 1) / BN) * 8;
+    const double bytes = pl->precision == ANKH_FP64 ? 8.0 : 4.0;   // f64, f32, or bf16 hi + lo
+    const double slice = (double)BM * pl->nup * kNumIL * bytes;
+    int smin = (int)std::ceil(slice / (3.0 * 1024 * 1024));
+    while ((int64_t)smin * tiles < 1024) smin++;
+    smin = std::min(std::max(smin, 1), 27);
+    for (int s = smin; s <= 27; s++)
+        if ((nrt * s) % 8 == 0) return s;
+    return smin;
 }
 
 hipError_t launch_m2l(ankh_plan_s *pl, int e) {
@@ -371,7 +412,7 @@ hipError_t launch_m2l(ankh_plan_s *pl, int e) {
     const int h = lv.nside / 2;
     const int ncls = h * h * h;
     const int nsplit = m2l_splits(pl, e);
-    dim3 grid((pl->nup + BM - 1) / BM, (ncls + BN - 1) / BN, 8 * nsplit);
+    dim3 grid((unsigned)(((pl->nup + BM - 1) / BM) * ((ncls + BN - 1) / BN) * 8 * nsplit));
     const int64_t nval = lv.ncell * pl->nup;
     double *L = pl->d_L + lv.cell0 * pl->nup;
     double *out = nsplit > 1 ? pl->d_m2l_part : L;

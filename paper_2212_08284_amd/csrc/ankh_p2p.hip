@@ -104,6 +104,36 @@ __device__ inline double row16_sum(double v) {
     return v;
 }
 
+// Short-range forms of erfc and exp, valid for xi r <= 1/2 (every near pair
+// when the leaves are small against 1/xi; the planner checks the bound):
+// erf(x) = (2/sqrt(pi)) x sum_n (-x^2)^n / (n! (2n+1)) (Maclaurin series,
+// Abramowitz & Stegun 7.1.5) and exp(-u) = sum_n (-u)^n / n!, truncated where
+// the next term is below the working precision (7 / 8 terms in float32,
+// 13 / 14 terms in float64).
+template <typename R> struct NearSeries;
+template <> struct NearSeries<float> {
+    static constexpr int NE = 7, NX = 8;
+};
+template <> struct NearSeries<double> {
+    static constexpr int NE = 13, NX = 14;
+};
+template <typename R> __device__ inline R erfc_near(R x) {
+    constexpr double c[13] = {1.0, -1.0 / 3, 1.0 / 10, -1.0 / 42, 1.0 / 216, -1.0 / 1320, 1.0 / 9360, -1.0 / 75600,
+                              1.0 / 685440, -1.0 / 6894720, 1.0 / 76204800, -1.0 / 918086400,
+                              1.0 / 11975040000.0};
+    const R u = x * x;
+    R s = (R)c[NearSeries<R>::NE - 1];
+#pragma unroll
+    for (int k = NearSeries<R>::NE - 2; k >= 0; k--) s = s * u + (R)c[k];
+    return (R)1 - (R)1.1283791670955125739 * x * s;
+}
+template <typename R> __device__ inline R exp_near(R u) {   // exp(-u)
+    R s = (R)1;
+#pragma unroll
+    for (int k = NearSeries<R>::NX - 1; k >= 1; k--) s = (R)1 - s * u / (R)k;
+    return s;
+}
+
 template <typename R>
 __device__ inline void symv(const R *Q, R vx, R vy, R vz, R &ox, R &oy, R &oz) {
     // Q = (xx, xy, xz, yy, yz, zz)
@@ -114,7 +144,7 @@ __device__ inline void symv(const R *Q, R vx, R vy, R vz, R &ox, R &oy, R &oz) {
 
 // One pair: adds ew * E to e, -grad to f (target force) and the target field
 // to g; with SRC also the source field to gs (the source force is -f's share).
-template <typename R, int ORD, bool GRAD, bool FIELD, bool SRC>
+template <typename R, int ORD, bool GRAD, bool FIELD, bool SRC, bool SER>
 __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *Qi, R ck, const R *dk,
                                   const R *Qk, R xi, R xi2, R cex, R ew, R &e, R *f, R *g, R *gs) {
     constexpr int NB = 2 * ORD + 1 + (GRAD ? 1 : 0);
@@ -123,9 +153,9 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
     const R rinv2 = rinv * rinv;
     const R r = r2 * rinv;
     R B[NB > 2 ? NB : 2];
-    B[0] = dev_erfc<R>(xi * r) * rinv;
+    B[0] = (SER ? erfc_near<R>(xi * r) : dev_erfc<R>(xi * r)) * rinv;
     {
-        const R ex = dev_exp<R>(-xi2 * r2) * cex;
+        const R ex = (SER ? exp_near<R>(xi2 * r2) : dev_exp<R>(-xi2 * r2)) * cex;
         R pw = 1;
 #pragma unroll
         for (int n = 1; n < NB; n++) {
@@ -234,7 +264,7 @@ __device__ inline void task_offset(int k, int &dx, int &dy, int &dz) {
             }
 }
 
-template <typename R, int ORD, bool GRAD, bool FIELD>
+template <typename R, int ORD, bool GRAD, bool FIELD, bool SER>
 __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
     constexpr int NM = 1 + (ORD >= 1 ? 3 : 0) + (ORD >= 2 ? 6 : 0);   // moment components
     __shared__ double sx[CH], sy[CH], sz[CH];
@@ -309,11 +339,11 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
                 R pe = 0, pf[3] = {0, 0, 0}, pg[3] = {0, 0, 0}, ps[3] = {0, 0, 0};
                 if (!skip) {
                     if (self)
-                        pair_terms<R, ORD, GRAD, FIELD, false>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, xi, xi2,
-                                                               cex, ew, pe, pf, pg, ps);
+                        pair_terms<R, ORD, GRAD, FIELD, false, SER>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, xi,
+                                                                    xi2, cex, ew, pe, pf, pg, ps);
                     else
-                        pair_terms<R, ORD, GRAD, FIELD, true>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, xi, xi2,
-                                                              cex, ew, pe, pf, pg, ps);
+                        pair_terms<R, ORD, GRAD, FIELD, true, SER>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, xi,
+                                                                   xi2, cex, ew, pe, pf, pg, ps);
                 }
                 te += pe;
 #pragma unroll
@@ -412,11 +442,11 @@ __global__ void k_p2p_slots(int64_t n, const double *slot_e, const R *SF, const 
         }
 }
 
-template <typename R>
+template <typename R, bool SER>
 hipError_t launch_t(ankh_plan_s *pl, const P2PArgs &a, int ord, bool grad, bool fields) {
     dim3 g((unsigned)(pl->nleaf * NT)), b(256);
     hipStream_t s = pl->stream;
-#define ANKH_P2P(O, GR, FL) hipLaunchKernelGGL((k_p2p<R, O, GR, FL>), g, b, 0, s, a)
+#define ANKH_P2P(O, GR, FL) hipLaunchKernelGGL((k_p2p<R, O, GR, FL, SER>), g, b, 0, s, a)
     if (ord == 0) {
         if (grad) ANKH_P2P(0, true, false); else ANKH_P2P(0, false, false);
     } else if (ord == 1) {
@@ -463,8 +493,11 @@ hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields) {
     a.slot_e = pl->d_slot_e;
     a.slot_f = pl->d_slot_f;
     a.slot_g = pl->d_slot_g;
-    if (is_mixed(pl)) return launch_t<float>(pl, a, ord, grad, fields);
-    return launch_t<double>(pl, a, ord, grad, fields);
+    // largest near-pair distance: opposite corners of diagonally adjacent leaves
+    const bool ser = pl->xi * 2.0 * std::sqrt(3.0) * a.w <= 0.5;
+    if (is_mixed(pl))
+        return ser ? launch_t<float, true>(pl, a, ord, grad, fields) : launch_t<float, false>(pl, a, ord, grad, fields);
+    return ser ? launch_t<double, true>(pl, a, ord, grad, fields) : launch_t<double, false>(pl, a, ord, grad, fields);
 }
 
 }  // namespace ankh
