@@ -129,6 +129,7 @@ hipError_t launch_reduce(ankh_plan_s *pl, double *energy_out, int ord);
 hipError_t launch_unpermute(ankh_plan_s *pl, double *forces, double *dEdmu, bool have_mu);
 hipError_t launch_m2l(ankh_plan_s *pl, int e);
 int m2l_splits(const ankh_plan_s *pl, int e);
+int m2l_row_frags(int nup);
 hipError_t launch_split_K_bf16(ankh_plan_s *pl, const double *K, __bf16 *hi, __bf16 *lo);
 inline bool is_mixed(const ankh_plan_s *pl) { return pl->precision != ANKH_FP64; }
 hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields);

@@ -11,13 +11,14 @@
 //
 // Per parity class of the target cells the level is one implicit GEMM
 //   L[n_u x cells] = [K_d1 .. K_d189] (n_u x 189 n_u) * im2col(M) (189 n_u x cells)
-// run on the matrix cores (v_mfma 16x16x4, f64 or f32).  A block owns a
-// 64 (nodes) x 64 (cells) tile of L and a slice of the 189 offsets; K_d and
-// the gathered multipoles stream through double-buffered LDS in steps of 16
-// along the contraction.  Slices of the offset list (split-K) give the launch
-// enough blocks to fill the chip at every level; their partial tiles are
-// summed in a fixed order by k_m2l_reduce, so results do not depend on
-// scheduling.
+// run on the matrix cores (v_mfma 16x16x4 f64 / f32, or 16x16x32 bf16 in the
+// split-precision mode).  A block owns a tile of up to 256 output nodes (all
+// n_u of them for the usual orders, so the gathered multipoles are read once
+// per tile) x 64 cells and a slice of the 189 offsets; K_d and the gathered
+// multipoles stream through double-buffered LDS.  Slices of the offset list
+// (split-K) give the launch enough blocks to fill the chip at every level;
+// their partial tiles are summed in a fixed order by k_m2l_reduce, so results
+// do not depend on scheduling.
 #include <algorithm>
 #include <cmath>
 
@@ -26,10 +27,12 @@
 namespace ankh {
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BN = 64;       // cells per block tile: 2 waves x 2 fragments of 16
+constexpr int NTHR = 256;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 template <typename T> struct Mma;
 // Operands of both 16x16x4 forms: lane l supplies A[l % 16][l / 16] and
@@ -51,9 +54,9 @@ template <> struct Mma<double> {
 };
 
 // Block order: the 8 XCDs receive blocks round-robin (block id mod 8).  All
-// blocks placed on one XCD share one (row tile, offset slice) of K, small
-// enough for that XCD's L2, so each slice is fetched from memory once; the
-// cell tiles and parity classes vary fastest.
+// blocks placed on one XCD share one (row tile, offset slice) of K, so each
+// slice is fetched from memory once per XCD; the cell tiles and parity
+// classes vary fastest.
 struct M2LTile {
     int rt, ct, cls, split;
 };
@@ -77,43 +80,62 @@ __device__ inline M2LTile m2l_tile(int nrt, int nct, int nsplit) {
     return t;
 }
 
-// one block per (row tile, cell tile, parity class, offset slice), ordered by m2l_tile
-template <typename T>
+// interaction list of parity class (px, py, pz) as offset indices, in a fixed order
+__device__ inline void class_list(int px, int py, int pz, int *il) {
+    int k = 0;
+    for (int a = 0; a < 6; a++)
+        for (int b = 0; b < 6; b++)
+            for (int c = 0; c < 6; c++) {
+                const int dx = (px ? -3 : -2) + a, dy = (py ? -3 : -2) + b, dz = (pz ? -3 : -2) + c;
+                if (max(abs(dx), max(abs(dy), abs(dz))) >= 2) il[k++] = off_index(dx, dy, dz);
+            }
+}
+
+// leaf-grid coordinates of the source cell of target cell (gx, gy, gz) at offset index di (periodic)
+__device__ inline size_t source_cell(int gx, int gy, int gz, int di, int nside) {
+    const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
+    const int sx = (gx + dx + 4 * nside) % nside, sy = (gy + dy + 4 * nside) % nside,
+              sz = (gz + dz + 4 * nside) % nside;
+    return ((size_t)sx * nside + sy) * nside + sz;
+}
+
+// ---- f64 / f32 on the 16x16x4 matrix cores ---------------------------------
+// Block tile: 32 RF output nodes x 64 cells; the 4 waves form a 2 x 2 grid of
+// 16 RF x 32 sub-tiles.  K is the [d][l][k] stack (contraction index l, output
+// node k), so the A tile of one step is BK contiguous runs of rows.  BK = 8
+// (f64) or 16 (f32): 64 bytes of contraction per row and step.  Row strides
+// of the LDS tiles are BM + 16 and BN + 16 elements, which puts the four
+// 16-lane groups of a fragment read on disjoint banks.
+template <typename T, int RF>
 __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *__restrict__ M,
                                              double *__restrict__ out, int nside, int nup, int nsplit,
                                              int64_t out_stride) {
     using Acc = typename Mma<T>::acc;
-    __shared__ T As[2][BK][BM + 4];
-    __shared__ T Bs[2][BK][BN + 4];
+    constexpr int BM = 32 * RF;
+    constexpr int BK = 64 / (int)sizeof(T);
+    constexpr int SA = BM + 16, SB = BN + 16;
+    __shared__ T As[2][BK][SA];
+    __shared__ T Bs[2][BK][SB];
     __shared__ int il[kNumIL];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const M2LTile tile = m2l_tile((nup + BM - 1) / BM, ((nside >> 1) * (nside >> 1) * (nside >> 1) + BN - 1) / BN,
-                                  nsplit);
-    const int rt = tile.rt, ct = tile.ct, cls = tile.cls, split = tile.split;
-    const int px = cls >> 2, py = (cls >> 1) & 1, pz = cls & 1;
     const int h = nside >> 1;
     const int ncls = h * h * h;
-    const int row0 = rt * BM, col0 = ct * BN;
-
-    // interaction list of this parity class, in a fixed order
-    if (tid == 0) {
-        int k = 0;
-        for (int a = 0; a < 6; a++)
-            for (int b = 0; b < 6; b++)
-                for (int c = 0; c < 6; c++) {
-                    const int dx = (px ? -3 : -2) + a, dy = (py ? -3 : -2) + b, dz = (pz ? -3 : -2) + c;
-                    if (max(abs(dx), max(abs(dy), abs(dz))) >= 2) il[k++] = off_index(dx, dy, dz);
-                }
-    }
+    const M2LTile tile = m2l_tile((nup + BM - 1) / BM, (ncls + BN - 1) / BN, nsplit);
+    const int px = tile.cls >> 2, py = (tile.cls >> 1) & 1, pz = tile.cls & 1;
+    const int row0 = tile.rt * BM, col0 = tile.ct * BN;
+    if (tid == 0) class_list(px, py, pz, il);
     __syncthreads();
-    const int o_begin = kNumIL * split / nsplit, o_end = kNumIL * (split + 1) / nsplit;
+    const int o_begin = kNumIL * tile.split / nsplit, o_end = kNumIL * (tile.split + 1) / nsplit;
 
-    // loader roles: A (K_d rows l, cols = output nodes) and B (M of the source cell of one column)
-    const int a_r = tid >> 4, a_c = (tid & 15) * 4;          // 16 x 64 tile, 4 per thread
-    const int b_col = tid >> 2, b_r = (tid & 3) * 4;         // 16 x 64 tile, 4 per thread
+    // A loader: pairs of adjacent rows; LA pairs per thread
+    constexpr int NPA = BK * BM / 2, LA = (NPA + NTHR - 1) / NTHR;
+    // B loader: 16 bytes (PB contraction values) of one cell's multipoles per thread
+    constexpr int PB = 16 / (int)sizeof(T);
+    static_assert(BK * BN == PB * NTHR, "B tile must be one 16-byte load per thread");
+    const int b_col = tid / (BK / PB), b_k = (tid % (BK / PB)) * PB;
     const int tcell = col0 + b_col;
     const bool b_ok = tcell < ncls;
     int gx = 0, gy = 0, gz = 0;
@@ -122,39 +144,54 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
         gy = 2 * ((tcell / h) % h) + py;
         gz = 2 * (tcell % h) + pz;
     }
-    const bool a_ok = row0 + a_c < nup;   // nup is a multiple of 32 and a_c of 4
 
     const int nk = nup / BK;
     const int niter = (o_end - o_begin) * nk;
-    T ra[4], rb[4];
+    T ra[LA][2], rb[PB];
     auto load = [&](int it) {
-        const int oi = o_begin + it / nk, k0 = (it % nk) * BK;
-        const int di = il[oi];
-        const T *Kd = K + (size_t)di * nup * nup;
+        const int di = il[o_begin + it / nk], k0 = (it % nk) * BK;
+        const T *Kd = K + (size_t)di * nup * nup + (size_t)k0 * nup + row0;
 #pragma unroll
-        for (int u = 0; u < 4; u++) ra[u] = a_ok ? Kd[(size_t)(k0 + a_r) * nup + row0 + a_c + u] : (T)0;
+        for (int u = 0; u < LA; u++) {
+            const int p = tid + NTHR * u;
+            const int k = p / (BM / 2), r = (p % (BM / 2)) * 2;
+            if (p < NPA && row0 + r < nup) {
+                const T *src = Kd + (size_t)k * nup + r;
+                ra[u][0] = src[0];
+                ra[u][1] = src[1];
+            } else {
+                ra[u][0] = (T)0;
+                ra[u][1] = (T)0;
+            }
+        }
         if (b_ok) {
-            const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
-            const int sx = (gx + dx + 4 * nside) % nside, sy = (gy + dy + 4 * nside) % nside,
-                      sz = (gz + dz + 4 * nside) % nside;
-            const T *Ms = M + ((size_t)(sx * nside + sy) * nside + sz) * nup + k0 + b_r;
+            const T *src = M + source_cell(gx, gy, gz, di, nside) * nup + k0 + b_k;
+            const uint4 v = *reinterpret_cast<const uint4 *>(src);
+            const T *pv = reinterpret_cast<const T *>(&v);
 #pragma unroll
-            for (int u = 0; u < 4; u++) rb[u] = Ms[u];
+            for (int u = 0; u < PB; u++) rb[u] = pv[u];
         } else {
 #pragma unroll
-            for (int u = 0; u < 4; u++) rb[u] = (T)0;
+            for (int u = 0; u < PB; u++) rb[u] = (T)0;
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int u = 0; u < 4; u++) As[buf][a_r][a_c + u] = ra[u];
+        for (int u = 0; u < LA; u++) {
+            const int p = tid + NTHR * u;
+            if (p < NPA) {
+                const int k = p / (BM / 2), r = (p % (BM / 2)) * 2;
+                As[buf][k][r] = ra[u][0];
+                As[buf][k][r + 1] = ra[u][1];
+            }
+        }
 #pragma unroll
-        for (int u = 0; u < 4; u++) Bs[buf][b_r + u][b_col] = rb[u];
+        for (int u = 0; u < PB; u++) Bs[buf][b_k + u][b_col] = rb[u];
     };
 
-    Acc acc[2][2];
+    Acc acc[RF][2];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < RF; i++)
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = Acc{0, 0, 0, 0};
 
@@ -169,13 +206,13 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
         if (it + 1 < niter) load(it + 1);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
-            T av[2], bv[2];
+            T av[RF], bv[2];
 #pragma unroll
-            for (int i = 0; i < 2; i++) av[i] = As[cur][kk + lk][wr * 32 + i * 16 + lr];
+            for (int i = 0; i < RF; i++) av[i] = As[cur][kk + lk][wr * 16 * RF + i * 16 + lr];
 #pragma unroll
             for (int j = 0; j < 2; j++) bv[j] = Bs[cur][kk + lk][wc * 32 + j * 16 + lr];
 #pragma unroll
-            for (int i = 0; i < 2; i++)
+            for (int i = 0; i < RF; i++)
 #pragma unroll
                 for (int j = 0; j < 2; j++) acc[i][j] = Mma<T>::run(av[i], bv[j], acc[i][j]);
         }
@@ -184,7 +221,7 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
     }
 
     // scatter each 16 x 16 result block (rows per Mma<T>::row, column lane % 16)
-    double *o = out + (size_t)split * out_stride;
+    double *o = out + (size_t)tile.split * out_stride;
 #pragma unroll
     for (int j = 0; j < 2; j++) {
         const int cl = col0 + wc * 32 + j * 16 + lr;
@@ -192,8 +229,8 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
         const int cx = 2 * (cl / (h * h)) + px, cy = 2 * ((cl / h) % h) + py, cz = 2 * (cl % h) + pz;
         double *Lc = o + ((size_t)(cx * nside + cy) * nside + cz) * nup;
 #pragma unroll
-        for (int i = 0; i < 2; i++) {
-            const int rb = row0 + wr * 32 + i * 16;   // 16-row block, entirely inside or outside nup
+        for (int i = 0; i < RF; i++) {
+            const int rb = row0 + wr * 16 * RF + i * 16;   // 16-row block, entirely inside or outside nup
             if (rb >= nup) continue;
 #pragma unroll
             for (int v = 0; v < 4; v++) Lc[rb + Mma<T>::row(lk, v)] = (double)acc[i][j][v];
@@ -204,50 +241,45 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
 // ---- split-precision variant: BF16 x 3 on the 16x16x32 BF16 matrix cores ------
 // Each float32 operand is split as x = hi + lo (hi = bf16(x), lo = bf16(x - hi)),
 // and the product is accumulated in float32 as hi*hi + hi*lo + lo*hi (the
-// lo*lo term is below the float32 rounding of the sum).  K is stored row-major
-// per offset (K_d[k][l]); the multipoles of the level are split on the fly.
+// lo*lo term is below the float32 rounding of the sum).  K_d is stored tiled,
+// [d][l / 32][k][l % 32], so the A tile of one 32-wide contraction step is one
+// contiguous run; the multipoles of the level are split once per launch.
 // Lane l of v_mfma_f32_16x16x32_bf16 supplies A[l % 16][8 (l / 16) .. +8] and
 // B[8 (l / 16) .. +8][l % 16]; result element v sits at row 4 (l / 16) + v,
-// column l % 16.
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-constexpr int BK3 = 32, PADK = 8;
+// column l % 16.  LDS rows are 32 bf16 (four 16-byte chunks); chunk c of row r
+// is stored at chunk position c ^ ((r >> 2) & 3), which spreads the 16 rows of
+// a fragment read over all banks without padding.
+__device__ inline int swz(int r, int c) { return r * 32 + 8 * (c ^ ((r >> 2) & 3)); }
 
+template <int RF>
 __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ Kh, const __bf16 *__restrict__ Kl,
                                                     const __bf16 *__restrict__ Mh, const __bf16 *__restrict__ Ml,
                                                     double *__restrict__ out, int nside, int nup, int nsplit,
                                                     int64_t out_stride) {
-    __shared__ __attribute__((aligned(16))) __bf16 Ash[2][BM][BK3 + PADK];
-    __shared__ __attribute__((aligned(16))) __bf16 Asl[2][BM][BK3 + PADK];
-    __shared__ __attribute__((aligned(16))) __bf16 Bsh[2][BN][BK3 + PADK];
-    __shared__ __attribute__((aligned(16))) __bf16 Bsl[2][BN][BK3 + PADK];
+    constexpr int BM = 32 * RF, BK = 32;
+    __shared__ __attribute__((aligned(16))) __bf16 Ash[2][BM * BK];
+    __shared__ __attribute__((aligned(16))) __bf16 Asl[2][BM * BK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bsh[2][BN * BK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bsl[2][BN * BK];
     __shared__ int il[kNumIL];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const M2LTile tile = m2l_tile((nup + BM - 1) / BM, ((nside >> 1) * (nside >> 1) * (nside >> 1) + BN - 1) / BN,
-                                  nsplit);
-    const int rt = tile.rt, ct = tile.ct, cls = tile.cls, split = tile.split;
-    const int px = cls >> 2, py = (cls >> 1) & 1, pz = cls & 1;
     const int h = nside >> 1;
     const int ncls = h * h * h;
-    const int row0 = rt * BM, col0 = ct * BN;
-    if (tid == 0) {
-        int k = 0;
-        for (int a = 0; a < 6; a++)
-            for (int b = 0; b < 6; b++)
-                for (int c = 0; c < 6; c++) {
-                    const int dx = (px ? -3 : -2) + a, dy = (py ? -3 : -2) + b, dz = (pz ? -3 : -2) + c;
-                    if (max(abs(dx), max(abs(dy), abs(dz))) >= 2) il[k++] = off_index(dx, dy, dz);
-                }
-    }
+    const M2LTile tile = m2l_tile((nup + BM - 1) / BM, (ncls + BN - 1) / BN, nsplit);
+    const int px = tile.cls >> 2, py = (tile.cls >> 1) & 1, pz = tile.cls & 1;
+    const int row0 = tile.rt * BM, col0 = tile.ct * BN;
+    if (tid == 0) class_list(px, py, pz, il);
     __syncthreads();
-    const int o_begin = kNumIL * split / nsplit, o_end = kNumIL * (split + 1) / nsplit;
+    const int o_begin = kNumIL * tile.split / nsplit, o_end = kNumIL * (tile.split + 1) / nsplit;
 
-    // loaders: one 16-byte chunk (8 bf16 along the contraction) of hi and of lo per thread for A and B
-    const int ld_r = tid >> 2, ld_c = (tid & 3) * 8;
-    const bool a_ok = row0 + ld_r < nup;
-    const int tcell = col0 + ld_r;
+    // A loader: 16-byte chunks (8 bf16 of the contraction) of hi and of lo, LA per thread
+    constexpr int NCA = BM * 4, LA = (NCA + NTHR - 1) / NTHR;
+    // B loader: one chunk of hi and of lo per thread
+    const int b_col = tid >> 2, b_c = tid & 3;
+    const int tcell = col0 + b_col;
     const bool b_ok = tcell < ncls;
     int gx = 0, gy = 0, gz = 0;
     if (b_ok) {
@@ -255,43 +287,52 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ K
         gy = 2 * ((tcell / h) % h) + py;
         gz = 2 * (tcell % h) + pz;
     }
-    const int nk = nup / BK3;
+    const int nk = nup / BK;
     const int niter = (o_end - o_begin) * nk;
-    uint4 rah, ral, rbh, rbl;
-    const uint4 zero4 = {0u, 0u, 0u, 0u};
+    bf16x8 rah[LA], ral[LA], rbh, rbl;
+    const bf16x8 zero4 = {};
     auto load = [&](int it) {
-        const int oi = o_begin + it / nk, k0 = (it % nk) * BK3;
-        const int di = il[oi];
-        if (a_ok) {
-            const size_t off = ((size_t)di * nup + row0 + ld_r) * nup + k0 + ld_c;
-            rah = *reinterpret_cast<const uint4 *>(Kh + off);
-            ral = *reinterpret_cast<const uint4 *>(Kl + off);
-        } else {
-            rah = zero4;
-            ral = zero4;
+        const int di = il[o_begin + it / nk], kb = it % nk;
+        const size_t base = ((size_t)di * nk + kb) * nup * BK;
+#pragma unroll
+        for (int u = 0; u < LA; u++) {
+            const int p = tid + NTHR * u;
+            const int r = p >> 2, c = p & 3;
+            if (p < NCA && row0 + r < nup) {
+                const size_t off = base + (size_t)(row0 + r) * BK + 8 * c;
+                rah[u] = *reinterpret_cast<const bf16x8 *>(Kh + off);
+                ral[u] = *reinterpret_cast<const bf16x8 *>(Kl + off);
+            } else {
+                rah[u] = zero4;
+                ral[u] = zero4;
+            }
         }
         if (b_ok) {
-            const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
-            const int sx = (gx + dx + 4 * nside) % nside, sy = (gy + dy + 4 * nside) % nside,
-                      sz = (gz + dz + 4 * nside) % nside;
-            const size_t off = ((size_t)(sx * nside + sy) * nside + sz) * nup + k0 + ld_c;
-            rbh = *reinterpret_cast<const uint4 *>(Mh + off);
-            rbl = *reinterpret_cast<const uint4 *>(Ml + off);
+            const size_t off = source_cell(gx, gy, gz, di, nside) * nup + kb * BK + 8 * b_c;
+            rbh = *reinterpret_cast<const bf16x8 *>(Mh + off);
+            rbl = *reinterpret_cast<const bf16x8 *>(Ml + off);
         } else {
             rbh = zero4;
             rbl = zero4;
         }
     };
     auto store = [&](int buf) {
-        *reinterpret_cast<uint4 *>(&Ash[buf][ld_r][ld_c]) = rah;
-        *reinterpret_cast<uint4 *>(&Asl[buf][ld_r][ld_c]) = ral;
-        *reinterpret_cast<uint4 *>(&Bsh[buf][ld_r][ld_c]) = rbh;
-        *reinterpret_cast<uint4 *>(&Bsl[buf][ld_r][ld_c]) = rbl;
+#pragma unroll
+        for (int u = 0; u < LA; u++) {
+            const int p = tid + NTHR * u;
+            if (p < NCA) {
+                const int r = p >> 2, c = p & 3;
+                *reinterpret_cast<bf16x8 *>(&Ash[buf][swz(r, c)]) = rah[u];
+                *reinterpret_cast<bf16x8 *>(&Asl[buf][swz(r, c)]) = ral[u];
+            }
+        }
+        *reinterpret_cast<bf16x8 *>(&Bsh[buf][swz(b_col, b_c)]) = rbh;
+        *reinterpret_cast<bf16x8 *>(&Bsl[buf][swz(b_col, b_c)]) = rbl;
     };
 
-    f32x4 acc[2][2];
+    f32x4 acc[RF][2];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < RF; i++)
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0, 0, 0, 0};
     if (niter > 0) {
@@ -303,19 +344,21 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ K
     for (int it = 0; it < niter; it++) {
         const int cur = it & 1;
         if (it + 1 < niter) load(it + 1);
-        bf16x8 ah[2], al[2], bh[2], bl[2];
+        bf16x8 ah[RF], al[RF], bh[2], bl[2];
 #pragma unroll
-        for (int i = 0; i < 2; i++) {
-            ah[i] = *reinterpret_cast<const bf16x8 *>(&Ash[cur][wr * 32 + i * 16 + lr][8 * lk]);
-            al[i] = *reinterpret_cast<const bf16x8 *>(&Asl[cur][wr * 32 + i * 16 + lr][8 * lk]);
+        for (int i = 0; i < RF; i++) {
+            const int r = wr * 16 * RF + i * 16 + lr;
+            ah[i] = *reinterpret_cast<const bf16x8 *>(&Ash[cur][swz(r, lk)]);
+            al[i] = *reinterpret_cast<const bf16x8 *>(&Asl[cur][swz(r, lk)]);
         }
 #pragma unroll
         for (int j = 0; j < 2; j++) {
-            bh[j] = *reinterpret_cast<const bf16x8 *>(&Bsh[cur][wc * 32 + j * 16 + lr][8 * lk]);
-            bl[j] = *reinterpret_cast<const bf16x8 *>(&Bsl[cur][wc * 32 + j * 16 + lr][8 * lk]);
+            const int cl = wc * 32 + j * 16 + lr;
+            bh[j] = *reinterpret_cast<const bf16x8 *>(&Bsh[cur][swz(cl, lk)]);
+            bl[j] = *reinterpret_cast<const bf16x8 *>(&Bsl[cur][swz(cl, lk)]);
         }
 #pragma unroll
-        for (int i = 0; i < 2; i++)
+        for (int i = 0; i < RF; i++)
 #pragma unroll
             for (int j = 0; j < 2; j++) {
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
@@ -325,7 +368,7 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ K
         if (it + 1 < niter) store(cur ^ 1);
         __syncthreads();
     }
-    double *o = out + (size_t)split * out_stride;
+    double *o = out + (size_t)tile.split * out_stride;
 #pragma unroll
     for (int j = 0; j < 2; j++) {
         const int cl = col0 + wc * 32 + j * 16 + lr;
@@ -333,8 +376,8 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ K
         const int cx = 2 * (cl / (h * h)) + px, cy = 2 * ((cl / h) % h) + py, cz = 2 * (cl % h) + pz;
         double *Lc = o + ((size_t)(cx * nside + cy) * nside + cz) * nup;
 #pragma unroll
-        for (int i = 0; i < 2; i++) {
-            const int rb = row0 + wr * 32 + i * 16;
+        for (int i = 0; i < RF; i++) {
+            const int rb = row0 + wr * 16 * RF + i * 16;
             if (rb >= nup) continue;
 #pragma unroll
             for (int v = 0; v < 4; v++) Lc[rb + 4 * lk + v] = (double)acc[i][j][v];
@@ -353,7 +396,8 @@ __global__ void k_split_bf16(const double *__restrict__ s, __bf16 *__restrict__ 
     lo[i] = (__bf16)(x - (float)a);
 }
 
-// plan time: row-major K_d[k][l] from the [d][l][k] float64 stack (K_{-d} = K_d^T)
+// plan time: K_d for the BF16 x 3 kernel from the [d][l][k] float64 stack
+// (K_{-d} = K_d^T), tiled as [d][l / 32][k][l % 32]
 __global__ void k_split_K_bf16(const double *__restrict__ K, __bf16 *__restrict__ hi, __bf16 *__restrict__ lo,
                                int nup) {
     const int64_t n = (int64_t)kNumOff * nup * nup;
@@ -361,7 +405,9 @@ __global__ void k_split_K_bf16(const double *__restrict__ K, __bf16 *__restrict_
     if (i >= n) return;
     const int64_t per = (int64_t)nup * nup;
     const int d = (int)(i / per);
-    const float x = (float)K[(int64_t)(kNumOff - 1 - d) * per + i % per];
+    const int64_t rem = i % per;
+    const int lb = (int)(rem / (32 * (int64_t)nup)), k = (int)((rem / 32) % nup), l = lb * 32 + (int)(rem % 32);
+    const float x = (float)K[(int64_t)(kNumOff - 1 - d) * per + (int64_t)k * nup + l];
     const __bf16 a = (__bf16)x;
     hi[i] = a;
     lo[i] = (__bf16)(x - (float)a);
@@ -383,57 +429,83 @@ __global__ void k_f64_to_f32(const double *__restrict__ s, float *__restrict__ d
 
 }  // namespace
 
-// number of offset slices so that a level launches at least ~4 blocks per CU
 hipError_t launch_split_K_bf16(ankh_plan_s *pl, const double *K, __bf16 *hi, __bf16 *lo) {
     const int64_t n = (int64_t)kNumOff * pl->nup * pl->nup;
     hipLaunchKernelGGL(k_split_K_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pl->stream, K, hi, lo, pl->nup);
     return hipGetLastError();
 }
 
-// Number of offset slices (split-K): enough blocks to fill the chip (>= 1024),
-// K slices of at most ~3 MiB (one per XCD L2 at a time), and, where possible,
-// (row tiles x slices) a multiple of 8 for the XCD-aware block order.
+// Rows of the output block tile, 32 RF with RF in {2, 4, 7, 8}: the height
+// that pads n_u least (the taller one on ties).
+int m2l_row_frags(int nup) {
+    int best = 2;
+    int64_t best_pad = INT64_MAX;
+    for (int rf : {8, 7, 4, 2}) {
+        const int bm = 32 * rf;
+        const int64_t pad = (int64_t)((nup + bm - 1) / bm) * bm;
+        if (pad < best_pad) {
+            best_pad = pad;
+            best = rf;
+        }
+    }
+    return best;
+}
+
+// Number of offset slices (split-K): a multiple of 8 (the XCD-aware block
+// order then gives every XCD whole slices), enough for >= 512 blocks, at most 32.
 int m2l_splits(const ankh_plan_s *pl, int e) {
     const int h = pl->lv[e].nside / 2;
-    const int nrt = (pl->nup + BM - 1) / BM;
-    const int64_t tiles = (int64_t)nrt * ((h * h * h + BN - 1) / BN) * 8;
-    const double bytes = pl->precision == ANKH_FP64 ? 8.0 : 4.0;   // f64, f32, or bf16 hi + lo
-    const double slice = (double)BM * pl->nup * kNumIL * bytes;
-    int smin = (int)std::ceil(slice / (3.0 * 1024 * 1024));
-    while ((int64_t)smin * tiles < 1024) smin++;
-    smin = std::min(std::max(smin, 1), 27);
-    for (int s = smin; s <= 27; s++)
-        if ((nrt * s) % 8 == 0) return s;
-    return smin;
+    const int bm = 32 * m2l_row_frags(pl->nup);
+    const int64_t tiles = (int64_t)((pl->nup + bm - 1) / bm) * ((h * h * h + BN - 1) / BN) * 8;
+    int s = 8;
+    while (s < 32 && tiles * s < 512) s += 8;
+    return s;
 }
+
+namespace {
+template <int RF>
+void launch_rf(ankh_plan_s *pl, int e, dim3 grid, double *out, int nsplit, int64_t nval) {
+    const ankh::Level &lv = pl->lv[e];
+    const size_t kper = (size_t)kNumOff * pl->nup * pl->nup;
+    const size_t koff = (size_t)(e - 1) * kper;
+    if (pl->precision == ANKH_MIXED_BF16X3) {
+        const __bf16 *Mh = pl->d_Mb, *Ml = pl->d_Mb + nval;
+        const size_t kall = (size_t)pl->depth * kper;
+        hipLaunchKernelGGL(k_m2l_bf16x3<RF>, grid, dim3(NTHR), 0, pl->stream, pl->d_Kb + koff,
+                           pl->d_Kb + kall + koff, Mh, Ml, out, lv.nside, pl->nup, nsplit, nval);
+    } else if (pl->precision == ANKH_MIXED) {
+        hipLaunchKernelGGL((k_m2l<float, RF>), grid, dim3(NTHR), 0, pl->stream, pl->d_Kf + koff, pl->d_Mf, out,
+                           lv.nside, pl->nup, nsplit, nval);
+    } else {
+        hipLaunchKernelGGL((k_m2l<double, RF>), grid, dim3(NTHR), 0, pl->stream, pl->d_K + koff,
+                           pl->d_M + lv.cell0 * pl->nup, out, lv.nside, pl->nup, nsplit, nval);
+    }
+}
+}  // namespace
 
 hipError_t launch_m2l(ankh_plan_s *pl, int e) {
     const ankh::Level &lv = pl->lv[e];
     const int h = lv.nside / 2;
     const int ncls = h * h * h;
     const int nsplit = m2l_splits(pl, e);
-    dim3 grid((unsigned)(((pl->nup + BM - 1) / BM) * ((ncls + BN - 1) / BN) * 8 * nsplit));
+    const int rf = m2l_row_frags(pl->nup);
+    const int bm = 32 * rf;
+    dim3 grid((unsigned)(((pl->nup + bm - 1) / bm) * ((ncls + BN - 1) / BN) * 8 * nsplit));
     const int64_t nval = lv.ncell * pl->nup;
     double *L = pl->d_L + lv.cell0 * pl->nup;
     double *out = nsplit > 1 ? pl->d_m2l_part : L;
-    const size_t koff = (size_t)(e - 1) * kNumOff * pl->nup * pl->nup;
-    if (pl->precision == ANKH_MIXED_BF16X3) {
-        __bf16 *Mh = pl->d_Mb, *Ml = pl->d_Mb + nval;
+    // this level's multipoles in the working precision of the contraction
+    if (pl->precision == ANKH_MIXED_BF16X3)
         hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream,
-                           pl->d_M + lv.cell0 * pl->nup, Mh, Ml, nval);
-        const size_t kb = (size_t)(e - 1) * kNumOff * pl->nup * pl->nup;
-        const size_t kall = (size_t)pl->depth * kNumOff * pl->nup * pl->nup;
-        hipLaunchKernelGGL(k_m2l_bf16x3, grid, dim3(256), 0, pl->stream, pl->d_Kb + kb, pl->d_Kb + kall + kb, Mh, Ml,
-                           out, lv.nside, pl->nup, nsplit, nval);
-    } else if (pl->precision == ANKH_MIXED) {
-        float *Mf = pl->d_Mf;   // this level's multipoles in float32
+                           pl->d_M + lv.cell0 * pl->nup, pl->d_Mb, pl->d_Mb + nval, nval);
+    else if (pl->precision == ANKH_MIXED)
         hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream,
-                           pl->d_M + lv.cell0 * pl->nup, Mf, nval);
-        hipLaunchKernelGGL(k_m2l<float>, grid, dim3(256), 0, pl->stream, pl->d_Kf + koff, Mf, out, lv.nside,
-                           pl->nup, nsplit, nval);
-    } else {
-        hipLaunchKernelGGL(k_m2l<double>, grid, dim3(256), 0, pl->stream, pl->d_K + koff,
-                           pl->d_M + lv.cell0 * pl->nup, out, lv.nside, pl->nup, nsplit, nval);
+                           pl->d_M + lv.cell0 * pl->nup, pl->d_Mf, nval);
+    switch (rf) {
+        case 2: launch_rf<2>(pl, e, grid, out, nsplit, nval); break;
+        case 4: launch_rf<4>(pl, e, grid, out, nsplit, nval); break;
+        case 7: launch_rf<7>(pl, e, grid, out, nsplit, nval); break;
+        default: launch_rf<8>(pl, e, grid, out, nsplit, nval); break;
     }
     if (nsplit > 1)
         hipLaunchKernelGGL(k_m2l_reduce, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream,

@@ -66,11 +66,13 @@ template <> __device__ inline double dev_rsqrt<double>(double v) { return 1.0 / 
 template <> __device__ inline float dev_rsqrt<float>(float v) { return rsqrtf(v); }
 
 // sum over the 16 lanes of a DPP row; every lane of the row receives the sum
+// (every lane reads a lane of its own row, so bound_ctrl never applies; it lets
+// the compiler fold each move into the add as a DPP operand)
 __device__ inline float row16_sum(float v) {
-    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
-    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
-    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));  // row half-mirror
-    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false));  // row mirror
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));   // quad [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));   // quad [2,3,0,1]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));  // row half-mirror
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));  // row mirror
     return v;
 }
 __device__ inline double dpp64(double v, int ctrl) {
@@ -127,10 +129,10 @@ template <typename R> __device__ inline R erfc_near(R x) {
     for (int k = NearSeries<R>::NE - 2; k >= 0; k--) s = s * u + (R)c[k];
     return (R)1 - (R)1.1283791670955125739 * x * s;
 }
-template <typename R> __device__ inline R exp_near(R u) {   // exp(-u)
+template <typename R> __device__ inline R exp_near(R u) {   // exp(-u), Horner form with 1/k as constants
     R s = (R)1;
 #pragma unroll
-    for (int k = NearSeries<R>::NX - 1; k >= 1; k--) s = (R)1 - s * u / (R)k;
+    for (int k = NearSeries<R>::NX - 1; k >= 1; k--) s = (R)1 - s * (u * (R)(1.0 / k));
     return s;
 }
 

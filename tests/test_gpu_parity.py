@@ -89,6 +89,35 @@ def test_stage_parity_with_reference(ak, depth, order, root, kind):
     pl.close()
 
 
+def test_stage_parity_high_order(ak):
+    """Order 8 (512 nodes per cell): the tallest far-field tile shape."""
+    d = _system("q")
+    pl, e, F, G = _run(ak, d, depth=2, order=8, images=2, root_order=8)
+    st = pl.stats
+    terms = pl.last_terms()
+    r = ankh_ref.evaluate(d["pos"], d["q"], d["mu"], d["theta"], d["edge"], st["depth"], st["order"], st["xi"],
+                          st["images"], grad=True, keep=False, root_order=st["root_order"])
+    scale = abs(r["e_near"]) + abs(r["e_self"]) + 1.0
+    assert abs(terms["far_levels"] - sum(r["e_far_levels"])) <= 1e-12 * scale
+    assert abs(e - r["energy"]) <= 1e-12 * scale
+    assert rel_rms(F, r["forces"]) <= 1e-11
+    pl.close()
+
+
+@pytest.mark.parametrize("mode", ["mixed", "mixed_bf16x3"])
+@pytest.mark.parametrize("depth,order", [(2, 3), (2, 4), (3, 5), (2, 8)])
+def test_mixed_modes_vs_fp64_tile_shapes(ak, mode, depth, order):
+    """Every far-field tile height (orders 3-8) in both mixed modes against the FP64 path."""
+    d = _system("qmt")
+    p64, e64, F64, G64 = _run(ak, d, depth=depth, order=order, images=2, root_order=max(order, 4))
+    pmx, emx, Fmx, Gmx = _run(ak, d, prec=mode, depth=depth, order=order, images=2, root_order=max(order, 4))
+    assert abs(emx - e64) <= 1e-5 * abs(e64)
+    assert rel_rms(Fmx, F64) <= 1e-4
+    assert rel_rms(Gmx, G64) <= 1e-4
+    p64.close()
+    pmx.close()
+
+
 def test_energy_only_path_matches(ak):
     d = _system("qmt")
     pl, e, F, G = _run(ak, d)
