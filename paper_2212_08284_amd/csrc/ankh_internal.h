@@ -21,6 +21,8 @@ constexpr int kNumOff = 343;         // slots for offsets d in [-3,3]^3 (316 use
 constexpr int kNumIL = 189;          // interaction-list length of every cell
 constexpr int kRedBlocks = 256;      // first-stage blocks of the energy reduction
 constexpr int kNumStages = 10;
+constexpr int kCperSlices = 16;
+constexpr int kNumSlots = 16;       // near-field partials per atom (see the pair kernel)     // column slices of the far-image root matvec
 
 // index of offset d in [-3,3]^3
 __host__ __device__ inline int off_index(int dx, int dy, int dz) {
@@ -88,9 +90,10 @@ struct ankh_plan_s {
     __bf16 *d_Mb = nullptr;       // bf16 hi / lo split of one level's multipoles
     double *d_m2l_part = nullptr; // split-K partial local expansions of one level
     double *d_Cper = nullptr;     // far-image root operator [nup0][nup0]
+    double *d_cper_part = nullptr;// its column-slice partial products [kCperSlices][nup0]
     double *d_eatom = nullptr;    // near-field energy per leaf-order atom
-    double *d_slot_e = nullptr;   // near-field partials per atom and adjacent-leaf task: energy [27][n]
-    void *d_slot_f = nullptr;     //   forces [3][27][n] and fields [3][27][n], float64 or float32
+    double *d_slot_e = nullptr;   // near-field partials per atom: energy [kNumSlots][n]
+    void *d_slot_f = nullptr;     //   forces [3][kNumSlots][n] and fields [3][kNumSlots][n], float64 or float32
     void *d_slot_g = nullptr;
     double *d_eleaf = nullptr;    // far energy per leaf
     double *d_F = nullptr;        // forces in leaf order [3][n]

@@ -368,16 +368,28 @@ __global__ __launch_bounds__(256) void k_l2l(const double *Lpar, double *Lch, co
 // ---- far periodic images: L_root = C_per M_root, E_per = 1/2 M.C M -----------
 // 64 rows per block, the contraction split over the block's 4 waves and
 // summed in a fixed order; the energy dot product follows in one block.
-__global__ __launch_bounds__(256) void k_cper(const double *C, const double *M, double *Lr, int nu, int nup) {
-    __shared__ double part[4][64];
+// one block per (64 rows k, slice of the columns l): part[slice][k] = sum over the slice of C[l][k] M[l]
+__global__ __launch_bounds__(256) void k_cper(const double *C, const double *M, double *part, int nu, int nup) {
+    __shared__ double red[4][64];
     const int r = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int k = blockIdx.x * 64 + r;
+    const int k = blockIdx.x * 64 + r, slice = blockIdx.y;
+    const int l0 = nu * slice / kCperSlices, l1 = nu * (slice + 1) / kCperSlices;
     double s = 0;
     if (k < nu)
-        for (int l = w; l < nu; l += 4) s += C[(int64_t)l * nup + k] * M[l];
-    part[w][r] = s;
+        for (int l = l0 + w; l < l1; l += 4) s += C[(int64_t)l * nup + k] * M[l];
+    red[w][r] = s;
     __syncthreads();
-    if (w == 0 && k < nup) Lr[k] = k < nu ? ((part[0][r] + part[1][r]) + (part[2][r] + part[3][r])) : 0.0;
+    if (w == 0 && k < nup) part[(int64_t)slice * nup + k] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+}
+
+// L_root[k] = sum of the slices in slice order (zero in the padding rows)
+__global__ void k_cper_sum(const double *part, double *Lr, int nu, int nup) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nup) return;
+    double s = 0;
+    if (k < nu)
+        for (int sl = 0; sl < kCperSlices; sl++) s += part[(int64_t)sl * nup + k];
+    Lr[k] = s;
 }
 
 __global__ __launch_bounds__(256) void k_cper_dot(const double *M, const double *Lr, int nu, double *terms) {
@@ -744,7 +756,9 @@ hipError_t launch_l2l(ankh_plan_s *pl, int e_child) {
 }
 
 hipError_t launch_cper(ankh_plan_s *pl) {
-    hipLaunchKernelGGL(k_cper, dim3((pl->nup0 + 63) / 64), dim3(256), 0, pl->stream, pl->d_Cper, pl->d_rootM,
+    hipLaunchKernelGGL(k_cper, dim3((pl->nup0 + 63) / 64, kCperSlices), dim3(256), 0, pl->stream, pl->d_Cper,
+                       pl->d_rootM, pl->d_cper_part, pl->nu0, pl->nup0);
+    hipLaunchKernelGGL(k_cper_sum, dim3((pl->nup0 + 255) / 256), dim3(256), 0, pl->stream, pl->d_cper_part,
                        pl->d_rootL, pl->nu0, pl->nup0);
     hipLaunchKernelGGL(k_cper_dot, dim3(1), dim3(256), 0, pl->stream, pl->d_rootM, pl->d_rootL, pl->nu0, pl->d_terms);
     return hipGetLastError();

@@ -10,13 +10,17 @@
 // takes the opposite force and its own field.  The leaf with itself is a
 // fourteenth task evaluated in gather form (all ordered pairs, half energy).
 //
-// Inside a task block the 256 threads form 16 groups of 16 lanes.  The lanes
-// of a group hold 16 target atoms and read the same source atom (an LDS
-// broadcast); the source's share is summed over the 16 lanes with DPP row
-// operations and added to that source's LDS accumulator by the one group that
-// owns it.  The target shares of the 16 groups are summed through LDS.  Every
-// atom receives one partial per adjacent-leaf task (27 slots); k_p2p_slots
-// adds them in slot order.  No atomics: results are bitwise reproducible.
+// Blocks are formed per source leaf s: the mutual tasks (s - d, s) of one
+// block share the source atoms, staged once in LDS, and the target atoms of
+// all their target leaves form one list.  The 256 threads form 16 groups of
+// 16 lanes.  The lanes of a group hold 16 consecutive targets of the list and
+// read the same source atom (an LDS broadcast); the source's share is summed
+// over the 16 lanes with DPP row operations and added to that source's LDS
+// accumulator by the one group that owns it.  The target shares of the 16
+// groups are summed through LDS.  Every atom receives one partial per task
+// it is a target of (slot 0: its own leaf, slots 1..13: the half-shell
+// tasks) and one per block it is a source of (slots 14, 15); k_p2p_slots adds
+// the 16 slots in order.  No atomics: results are bitwise reproducible.
 //
 // Pair terms (r = x_i - x_j, D_x = q + mu.d + Th:dd on x, the mirrored
 // operator on the source): with B_0 = H, B_{n+1} = -(1/r) dB_n/dr,
@@ -38,7 +42,9 @@ namespace ankh {
 namespace {
 
 constexpr int CH = 128;     // source atoms per LDS chunk
-constexpr int NT = 14;      // tasks per leaf: itself + 13 half-shell neighbours
+constexpr int NHALF = 13;   // half-shell neighbour offsets (mutual tasks per leaf)
+constexpr int NKIND = 2;    // blocks per source leaf
+constexpr int KMAX = 7;     // mutual tasks of a kind-0 block (kind 1: the other 6 and the leaf itself)
 constexpr int G = 16;       // lanes per group (one DPP row)
 constexpr int NG = 16;      // groups per block
 
@@ -266,6 +272,11 @@ __device__ inline void task_offset(int k, int &dx, int &dy, int &dz) {
             }
 }
 
+// Blocks: two per source leaf s.  Kind 0 evaluates the mutual tasks (s - d, s)
+// for the first 7 half-shell offsets d, kind 1 those for the other 6 and then
+// the leaf with itself (gather form).  The target atoms of all target leaves
+// of a block form one list that streams through the 16-lane groups, so only
+// the last pass of a block is partly empty.
 template <typename R, int ORD, bool GRAD, bool FIELD, bool SER>
 __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
     constexpr int NM = 1 + (ORD >= 1 ? 3 : 0) + (ORD >= 2 ? 6 : 0);   // moment components
@@ -273,43 +284,94 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
     __shared__ R smo[NM][CH];
     __shared__ R sacc[6][CH];           // source-side force (3) and field (3)
     __shared__ double tpart[7][NG][G];  // target-side partials of the 16 groups
+    __shared__ int tfirst[KMAX], tcount[KMAX], tpre[KMAX + 1];   // target leaves: first atom, atoms, prefix
+    __shared__ double tshift[KMAX][3];                            // their position shift, -d w
 
     const int tid = threadIdx.x;
     const int grp = tid >> 4, ln = tid & 15;
     const int ns = a.nside;
     const int64_t nleaf = (int64_t)ns * ns * ns;
-    // XCD-aware order: each XCD receives a contiguous Morton range of leaves with all their tasks
-    const int64_t nblk = nleaf * NT;
-    int64_t task = blockIdx.x;
-    if ((nblk & 7) == 0) task = (int64_t)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
-    const int k = (int)(task % NT);
-    const int leaf = morton_leaf(task / NT, a.depth, ns);
-    int dx, dy, dz;
-    task_offset(k, dx, dy, dz);
-    const bool self = k == 0;
-    const int tx = leaf / (ns * ns), ty = (leaf / ns) % ns, tz = leaf % ns;
-    const int src = (((tx + dx + ns) % ns) * ns + (ty + dy + ns) % ns) * ns + (tz + dz + ns) % ns;
-    const int t0 = a.offs[leaf], nt = a.offs[leaf + 1] - t0;
-    const int s0 = a.offs[src], nsrc = a.offs[src + 1] - s0;
-    const int slot_t = (dx + 1) * 9 + (dy + 1) * 3 + (dz + 1);       // target side of this task
-    const int slot_s = (1 - dx) * 9 + (1 - dy) * 3 + (1 - dz);       // source side (offset -d)
-    const double shx = dx * a.w, shy = dy * a.w, shz = dz * a.w;
+    // XCD-aware order: each XCD receives a contiguous Morton range of source leaves
+    const int64_t nblk = nleaf * NKIND;
+    int64_t b = blockIdx.x;
+    if ((nblk & 7) == 0) b = (int64_t)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
+    const int kind = (int)(b % NKIND);
+    const int leaf = morton_leaf(b / NKIND, a.depth, ns);
+    const int lx = leaf / (ns * ns), ly = (leaf / ns) % ns, lz = leaf % ns;
+    const int k_first = kind == 0 ? 1 : KMAX + 1;
+    const int ntl = kind == 0 ? KMAX : NHALF - KMAX;
+    if (tid < ntl) {
+        int dx, dy, dz;
+        task_offset(k_first + tid, dx, dy, dz);
+        const int t = (((lx - dx + ns) % ns) * ns + (ly - dy + ns) % ns) * ns + (lz - dz + ns) % ns;
+        tfirst[tid] = a.offs[t];
+        tcount[tid] = a.offs[t + 1] - a.offs[t];
+        tshift[tid][0] = -dx * a.w;
+        tshift[tid][1] = -dy * a.w;
+        tshift[tid][2] = -dz * a.w;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        tpre[0] = 0;
+        for (int k = 0; k < ntl; k++) tpre[k + 1] = tpre[k] + tcount[k];
+    }
+    __syncthreads();
+    const int ntg = tpre[ntl];
+    const int s0 = a.offs[leaf], nsrc = a.offs[leaf + 1] - s0;
+    const int slot_src = NHALF + 1 + kind;
 
     const R *q = pick<R>(a.q, a.qf), *mu = pick<R>(a.mu, a.muf), *th = pick<R>(a.th, a.thf);
     const int64_t n = a.n;
     R *SF = static_cast<R *>(a.slot_f), *SG = static_cast<R *>(a.slot_g);
-    const int64_t sstride = 27 * n;     // component stride of the slot arrays
+    const int64_t sstride = (int64_t)kNumSlots * n;     // component stride of the slot arrays
     const R xi = (R)a.xi, xi2 = (R)(a.xi * a.xi), cex = (R)(1.0 / (a.xi * 1.7724538509055160273));
-    const R ew = self ? (R)0.5 : (R)1.0;
 
-    for (int cs = 0; cs < nsrc || (cs == 0 && nsrc == 0); cs += CH) {
+    // target leaf (segment of the block's list) of list position f < ntg
+    auto segment = [&](int f) {
+        int s = 0;
+        while (s + 1 < ntl && f >= tpre[s + 1]) s++;
+        return s;
+    };
+    // sums the 16 groups' partials of pass tp (fixed order) and stores them in the atoms' slots
+    auto flush = [&](int tp, int nt_pass, bool mutual, bool first) {
+        __syncthreads();
+        if (tid < 7 * G) {
+            const int c = tid / G, l = tid % G;
+            const int f = tp + l;
+            if (f < nt_pass) {
+                double s = 0;
+                for (int g2 = 0; g2 < NG; g2++) s += tpart[c][g2][l];
+                int64_t at;
+                int slot;
+                if (mutual) {
+                    const int sg = segment(f);
+                    at = tfirst[sg] + (f - tpre[sg]);
+                    slot = k_first + sg;
+                } else {
+                    at = s0 + f;
+                    slot = 0;
+                }
+                if (c == 0) {
+                    double *pe = a.slot_e + (int64_t)slot * n + at;
+                    *pe = first ? s : *pe + s;
+                } else if ((c <= 3 && GRAD) || (c >= 4 && FIELD)) {
+                    R *p = (c <= 3 ? SF + (int64_t)(c - 1) * sstride : SG + (int64_t)(c - 4) * sstride) +
+                           (int64_t)slot * n + at;
+                    *p = first ? (R)s : (R)(*p + (R)s);
+                }
+            }
+        }
+        __syncthreads();
+    };
+
+    for (int cs = 0; cs < nsrc; cs += CH) {
         const int chn = min(CH, nsrc - cs);
         __syncthreads();
         for (int f = tid; f < chn; f += 256) {
             const int64_t sj = s0 + cs + f;
-            sx[f] = a.x[sj] + shx;
-            sy[f] = a.y[sj] + shy;
-            sz[f] = a.z[sj] + shz;
+            sx[f] = a.x[sj];
+            sy[f] = a.y[sj];
+            sz[f] = a.z[sj];
             smo[0][f] = q[sj];
             if (ORD >= 1)
                 for (int c = 0; c < 3; c++) smo[1 + c][f] = mu[c * n + sj];
@@ -318,12 +380,15 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
             for (int c = 0; c < 6; c++) sacc[c][f] = 0;
         }
         __syncthreads();
-        for (int tp = 0; tp < nt; tp += G) {
-            const int i = tp + ln;
-            const bool iv = i < nt;
-            const int64_t ti = t0 + (iv ? i : 0);
+        // mutual tasks: every target atom of the block against this chunk
+        for (int tp = 0; tp < ntg; tp += G) {
+            const int f = tp + ln;
+            const bool iv = f < ntg;
+            const int sg = iv ? segment(f) : 0;
+            const int64_t ti = iv ? tfirst[sg] + (f - tpre[sg]) : 0;
             // an absent target sits far away with zero moments: its pair terms vanish
-            const double xt = iv ? a.x[ti] : 1.0e4, yt = iv ? a.y[ti] : 1.0e4, zt = iv ? a.z[ti] : 1.0e4;
+            const double xt = iv ? a.x[ti] + tshift[sg][0] : 1.0e4, yt = iv ? a.y[ti] + tshift[sg][1] : 1.0e4,
+                         zt = iv ? a.z[ti] + tshift[sg][2] : 1.0e4;
             R ci = iv ? q[ti] : (R)0, di[3] = {0, 0, 0}, Qi[6] = {0, 0, 0, 0, 0, 0};
             if (ORD >= 1 && iv)
                 for (int c = 0; c < 3; c++) di[c] = mu[c * n + ti];
@@ -331,7 +396,6 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
                 for (int c = 0; c < 6; c++) Qi[c] = th[c * n + ti];
             R te = 0, tf[3] = {0, 0, 0}, tg[3] = {0, 0, 0};
             for (int j = grp; j < chn; j += NG) {
-                const bool skip = self && (j + cs == i);   // an atom with itself at zero shift
                 const R rx = (R)(xt - sx[j]), ry = (R)(yt - sy[j]), rz = (R)(zt - sz[j]);
                 R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
                 if (ORD >= 1)
@@ -339,21 +403,15 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
                 if (ORD >= 2)
                     for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
                 R pe = 0, pf[3] = {0, 0, 0}, pg[3] = {0, 0, 0}, ps[3] = {0, 0, 0};
-                if (!skip) {
-                    if (self)
-                        pair_terms<R, ORD, GRAD, FIELD, false, SER>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, xi,
-                                                                    xi2, cex, ew, pe, pf, pg, ps);
-                    else
-                        pair_terms<R, ORD, GRAD, FIELD, true, SER>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, xi,
-                                                                   xi2, cex, ew, pe, pf, pg, ps);
-                }
+                pair_terms<R, ORD, GRAD, FIELD, true, SER>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, xi, xi2, cex,
+                                                           (R)1, pe, pf, pg, ps);
                 te += pe;
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
                     tf[c] += pf[c];
                     tg[c] += pg[c];
                 }
-                if (!self && (GRAD || FIELD)) {
+                if (GRAD || FIELD) {
                     // the source's share, summed over the 16 targets of the group
                     R v[6];
 #pragma unroll
@@ -367,54 +425,74 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
                     }
                 }
             }
-            // target partials: sum the 16 groups in a fixed order
             tpart[0][grp][ln] = (double)te;
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 tpart[1 + c][grp][ln] = (double)tf[c];
                 tpart[4 + c][grp][ln] = (double)tg[c];
             }
-            __syncthreads();
-            if (tid < 7 * G) {
-                const int c = tid / G, l = tid % G;
-                const int ii = tp + l;
-                if (ii < nt) {
-                    double s = 0;
-                    for (int g2 = 0; g2 < NG; g2++) s += tpart[c][g2][l];
-                    const int64_t at = t0 + ii;
-                    if (c == 0) {
-                        double *pe = a.slot_e + (int64_t)slot_t * n + at;
-                        *pe = (cs == 0) ? s : *pe + s;
-                    } else if ((c <= 3 && GRAD) || (c >= 4 && FIELD)) {
-                        R *p = (c <= 3 ? SF + (int64_t)(c - 1) * sstride : SG + (int64_t)(c - 4) * sstride) +
-                               (int64_t)slot_t * n + at;
-                        *p = (cs == 0) ? (R)s : (R)(*p + (R)s);
+            flush(tp, ntg, true, cs == 0);
+        }
+        // source side of this chunk
+        for (int f = tid; f < chn; f += 256) {
+            const int64_t sj = s0 + cs + f;
+            if (GRAD)
+                for (int c = 0; c < 3; c++) SF[(int64_t)c * sstride + (int64_t)slot_src * n + sj] = sacc[c][f];
+            if (FIELD)
+                for (int c = 0; c < 3; c++) SG[(int64_t)c * sstride + (int64_t)slot_src * n + sj] = sacc[3 + c][f];
+            a.slot_e[(int64_t)slot_src * n + sj] = 0.0;
+        }
+        // the leaf with itself: its atoms against this chunk, all ordered pairs, half energy
+        if (kind == 1) {
+            for (int tp = 0; tp < nsrc; tp += G) {
+                const int i = tp + ln;
+                const bool iv = i < nsrc;
+                const int64_t ti = s0 + (iv ? i : 0);
+                const double xt = iv ? a.x[ti] : 1.0e4, yt = iv ? a.y[ti] : 1.0e4, zt = iv ? a.z[ti] : 1.0e4;
+                R ci = iv ? q[ti] : (R)0, di[3] = {0, 0, 0}, Qi[6] = {0, 0, 0, 0, 0, 0};
+                if (ORD >= 1 && iv)
+                    for (int c = 0; c < 3; c++) di[c] = mu[c * n + ti];
+                if (ORD >= 2 && iv)
+                    for (int c = 0; c < 6; c++) Qi[c] = th[c * n + ti];
+                R te = 0, tf[3] = {0, 0, 0}, tg[3] = {0, 0, 0};
+                for (int j = grp; j < chn; j += NG) {
+                    if (j + cs == i) continue;   // an atom with itself at zero shift
+                    const R rx = (R)(xt - sx[j]), ry = (R)(yt - sy[j]), rz = (R)(zt - sz[j]);
+                    R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
+                    if (ORD >= 1)
+                        for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
+                    if (ORD >= 2)
+                        for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
+                    R pe = 0, pf[3] = {0, 0, 0}, pg[3] = {0, 0, 0}, ps[3];
+                    pair_terms<R, ORD, GRAD, FIELD, false, SER>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, xi, xi2,
+                                                                cex, (R)0.5, pe, pf, pg, ps);
+                    te += pe;
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        tf[c] += pf[c];
+                        tg[c] += pg[c];
                     }
                 }
-            }
-            __syncthreads();
-        }
-        // source side of this chunk (mutual tasks only)
-        if (!self) {
-            for (int f = tid; f < chn; f += 256) {
-                const int64_t sj = s0 + cs + f;
-                if (GRAD)
-                    for (int c = 0; c < 3; c++) SF[(int64_t)c * sstride + (int64_t)slot_s * n + sj] = sacc[c][f];
-                if (FIELD)
-                    for (int c = 0; c < 3; c++) SG[(int64_t)c * sstride + (int64_t)slot_s * n + sj] = sacc[3 + c][f];
-                a.slot_e[(int64_t)slot_s * n + sj] = 0.0;
+                tpart[0][grp][ln] = (double)te;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    tpart[1 + c][grp][ln] = (double)tf[c];
+                    tpart[4 + c][grp][ln] = (double)tg[c];
+                }
+                flush(tp, nsrc, false, cs == 0);
             }
         }
-        if (nsrc == 0) break;
     }
-    // with no source atoms the target slot must still hold zeros
+    // an empty source leaf: the target slots of the block's tasks still hold zeros
     if (nsrc == 0) {
-        for (int i = tid; i < nt; i += 256) {
-            const int64_t at = t0 + i;
-            a.slot_e[(int64_t)slot_t * n + at] = 0.0;
+        for (int f = tid; f < ntg; f += 256) {
+            const int sg = segment(f);
+            const int64_t at = tfirst[sg] + (f - tpre[sg]);
+            const int slot = k_first + sg;
+            a.slot_e[(int64_t)slot * n + at] = 0.0;
             for (int c = 0; c < 3; c++) {
-                if (GRAD) SF[(int64_t)c * sstride + (int64_t)slot_t * n + at] = 0;
-                if (FIELD) SG[(int64_t)c * sstride + (int64_t)slot_t * n + at] = 0;
+                if (GRAD) SF[(int64_t)c * sstride + (int64_t)slot * n + at] = 0;
+                if (FIELD) SG[(int64_t)c * sstride + (int64_t)slot * n + at] = 0;
             }
         }
     }
@@ -427,26 +505,26 @@ __global__ void k_p2p_slots(int64_t n, const double *slot_e, const R *SF, const 
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     double e = 0;
-    for (int s = 0; s < 27; s++) e += slot_e[(int64_t)s * n + i];
+    for (int s = 0; s < kNumSlots; s++) e += slot_e[(int64_t)s * n + i];
     eatom[i] = e;
-    const int64_t st = 27 * n;
+    const int64_t st = (int64_t)kNumSlots * n;
     if (GRAD)
         for (int c = 0; c < 3; c++) {
             double v = 0;
-            for (int s = 0; s < 27; s++) v += (double)SF[c * st + (int64_t)s * n + i];
+            for (int s = 0; s < kNumSlots; s++) v += (double)SF[c * st + (int64_t)s * n + i];
             F[c * n + i] += v;
         }
     if (FIELD)
         for (int c = 0; c < 3; c++) {
             double v = 0;
-            for (int s = 0; s < 27; s++) v += (double)SG[c * st + (int64_t)s * n + i];
+            for (int s = 0; s < kNumSlots; s++) v += (double)SG[c * st + (int64_t)s * n + i];
             G[c * n + i] += v;
         }
 }
 
 template <typename R, bool SER>
 hipError_t launch_t(ankh_plan_s *pl, const P2PArgs &a, int ord, bool grad, bool fields) {
-    dim3 g((unsigned)(pl->nleaf * NT)), b(256);
+    dim3 g((unsigned)(pl->nleaf * NKIND)), b(256);
     hipStream_t s = pl->stream;
 #define ANKH_P2P(O, GR, FL) hipLaunchKernelGGL((k_p2p<R, O, GR, FL, SER>), g, b, 0, s, a)
     if (ord == 0) {

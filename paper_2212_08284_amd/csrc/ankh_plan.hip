@@ -45,7 +45,7 @@ void free_all(ankh_plan_s *pl) {
                     pl->d_M, pl->d_L, pl->d_K, pl->d_Kf, pl->d_Cper, pl->d_eatom, pl->d_eleaf, pl->d_F,
                     pl->d_G, pl->d_terms, pl->d_part, pl->d_err, pl->d_tab0, pl->d_Mf, pl->d_m2l_part,
                     pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr,
-                    pl->d_Kb, pl->d_Mb, pl->d_slot_e, pl->d_slot_f, pl->d_slot_g};
+                    pl->d_Kb, pl->d_Mb, pl->d_slot_e, pl->d_slot_f, pl->d_slot_g, pl->d_cper_part};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &set : pl->evsets)
@@ -323,6 +323,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         }
         const size_t kper = (size_t)kNumOff * pl->nup * pl->nup;
         dalloc(pl, &pl->d_Cper, (size_t)pl->nup0 * pl->nup0);
+        dalloc(pl, &pl->d_cper_part, (size_t)kCperSlices * pl->nup0);
         if (pl->depth >= 1) {
             dalloc(pl, &pl->d_rootM, pl->nup0);
             dalloc(pl, &pl->d_rootL, pl->nup0);
@@ -332,17 +333,17 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
             pl->d_rootL = pl->d_L;
         }
         dalloc(pl, &pl->d_eatom, n);
-        dalloc(pl, &pl->d_slot_e, 27 * n);
+        dalloc(pl, &pl->d_slot_e, (size_t)kNumSlots * n);
         if (precision == ANKH_FP64) {
             double *f = nullptr, *g = nullptr;
-            dalloc(pl, &f, 81 * n);
-            dalloc(pl, &g, 81 * n);
+            dalloc(pl, &f, (size_t)3 * kNumSlots * n);
+            dalloc(pl, &g, (size_t)3 * kNumSlots * n);
             pl->d_slot_f = f;
             pl->d_slot_g = g;
         } else {
             float *f = nullptr, *g = nullptr;
-            dalloc(pl, &f, 81 * n);
-            dalloc(pl, &g, 81 * n);
+            dalloc(pl, &f, (size_t)3 * kNumSlots * n);
+            dalloc(pl, &g, (size_t)3 * kNumSlots * n);
             pl->d_slot_f = f;
             pl->d_slot_g = g;
         }
