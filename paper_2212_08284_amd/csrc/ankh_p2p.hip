@@ -380,7 +380,18 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
             for (int c = 0; c < 6; c++) sacc[c][f] = 0;
         }
         __syncthreads();
-        // mutual tasks: every target atom of the block against this chunk
+        // mutual tasks: every target atom of the block against this chunk.  In
+        // float32 each lane keeps its share of the group's sources (at most
+        // CH / NG of them) in registers over all passes; the 16 lanes' shares
+        // are summed once per chunk.  In float64 (register-bound) the share is
+        // summed over the lanes for every pair.
+        constexpr bool RACC = sizeof(R) == 4;
+        constexpr int MS = RACC ? CH / NG : 1;
+        R psrc[MS][6];
+#pragma unroll
+        for (int m = 0; m < MS; m++)
+#pragma unroll
+            for (int c = 0; c < 6; c++) psrc[m][c] = 0;
         for (int tp = 0; tp < ntg; tp += G) {
             const int f = tp + ln;
             const bool iv = f < ntg;
@@ -395,14 +406,15 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
             if (ORD >= 2 && iv)
                 for (int c = 0; c < 6; c++) Qi[c] = th[c * n + ti];
             R te = 0, tf[3] = {0, 0, 0}, tg[3] = {0, 0, 0};
-            for (int j = grp; j < chn; j += NG) {
+            // one pair with source j: the target's share into te / tf / tg, the source's into pf / ps
+            auto pair = [&](int j, R *pf, R *ps) {
                 const R rx = (R)(xt - sx[j]), ry = (R)(yt - sy[j]), rz = (R)(zt - sz[j]);
                 R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
                 if (ORD >= 1)
                     for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
                 if (ORD >= 2)
                     for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
-                R pe = 0, pf[3] = {0, 0, 0}, pg[3] = {0, 0, 0}, ps[3] = {0, 0, 0};
+                R pe = 0, pg[3] = {0, 0, 0};
                 pair_terms<R, ORD, GRAD, FIELD, true, SER>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, xi, xi2, cex,
                                                            (R)1, pe, pf, pg, ps);
                 te += pe;
@@ -411,17 +423,37 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
                     tf[c] += pf[c];
                     tg[c] += pg[c];
                 }
-                if (GRAD || FIELD) {
-                    // the source's share, summed over the 16 targets of the group
-                    R v[6];
+            };
+            if constexpr (RACC) {
 #pragma unroll
-                    for (int c = 0; c < 3; c++) {
-                        v[c] = GRAD ? row16_sum(-pf[c]) : (R)0;
-                        v[3 + c] = FIELD ? row16_sum(ps[c]) : (R)0;
+                for (int m = 0; m < MS; m++) {
+                    const int j = grp + NG * m;
+                    if (j < chn) {
+                        R pf[3] = {0, 0, 0}, ps[3] = {0, 0, 0};
+                        pair(j, pf, ps);
+#pragma unroll
+                        for (int c = 0; c < 3; c++) {
+                            psrc[m][c] -= pf[c];
+                            psrc[m][3 + c] += ps[c];
+                        }
                     }
-                    if (ln == 0) {
+                }
+            } else {
+                for (int j = grp; j < chn; j += NG) {
+                    R pf[3] = {0, 0, 0}, ps[3] = {0, 0, 0};
+                    pair(j, pf, ps);
+                    if (GRAD || FIELD) {
+                        // the source's share, summed over the 16 targets of the group
+                        R v[6];
 #pragma unroll
-                        for (int c = 0; c < 6; c++) sacc[c][j] += v[c];
+                        for (int c = 0; c < 3; c++) {
+                            v[c] = GRAD ? row16_sum(-pf[c]) : (R)0;
+                            v[3 + c] = FIELD ? row16_sum(ps[c]) : (R)0;
+                        }
+                        if (ln == 0) {
+#pragma unroll
+                            for (int c = 0; c < 6; c++) sacc[c][j] += v[c];
+                        }
                     }
                 }
             }
@@ -432,6 +464,25 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
                 tpart[4 + c][grp][ln] = (double)tg[c];
             }
             flush(tp, ntg, true, cs == 0);
+        }
+        if constexpr (RACC) {
+            if (GRAD || FIELD) {
+#pragma unroll
+                for (int m = 0; m < MS; m++) {
+                    const int j = grp + NG * m;
+                    R v[6];
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        v[c] = GRAD ? row16_sum(psrc[m][c]) : (R)0;
+                        v[3 + c] = FIELD ? row16_sum(psrc[m][3 + c]) : (R)0;
+                    }
+                    if (ln == 0 && j < chn) {
+#pragma unroll
+                        for (int c = 0; c < 6; c++) sacc[c][j] = v[c];
+                    }
+                }
+            }
+            __syncthreads();
         }
         // source side of this chunk
         for (int f = tid; f < chn; f += 256) {
