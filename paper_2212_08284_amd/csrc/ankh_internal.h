@@ -25,7 +25,7 @@ constexpr int kCperSlices = 16;
 constexpr int kNumSlots = 16;       // near-field partials per atom (see the pair kernel)     // column slices of the far-image root matvec
 
 // index of offset d in [-3,3]^3
-__host__ __device__ inline int off_index(int dx, int dy, int dz) {
+__host__ __device__ constexpr int off_index(int dx, int dy, int dz) {
     return ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3);
 }
 

@@ -80,16 +80,27 @@ __device__ inline M2LTile m2l_tile(int nrt, int nct, int nsplit) {
     return t;
 }
 
-// interaction list of parity class (px, py, pz) as offset indices, in a fixed order
-__device__ inline void class_list(int px, int py, int pz, int *il) {
-    int k = 0;
-    for (int a = 0; a < 6; a++)
-        for (int b = 0; b < 6; b++)
-            for (int c = 0; c < 6; c++) {
-                const int dx = (px ? -3 : -2) + a, dy = (py ? -3 : -2) + b, dz = (pz ? -3 : -2) + c;
-                if (max(abs(dx), max(abs(dy), abs(dz))) >= 2) il[k++] = off_index(dx, dy, dz);
-            }
+// interaction lists of the 8 parity classes (px, py, pz) = (c >> 2, (c >> 1) & 1, c & 1)
+// as offset indices, each in a fixed (lexicographic) order
+struct ILTable {
+    int v[8][kNumIL];
+};
+constexpr ILTable make_il_table() {
+    ILTable t{};
+    for (int cls = 0; cls < 8; cls++) {
+        const int px = cls >> 2, py = (cls >> 1) & 1, pz = cls & 1;
+        int k = 0;
+        for (int a = 0; a < 6; a++)
+            for (int b = 0; b < 6; b++)
+                for (int c = 0; c < 6; c++) {
+                    const int dx = (px ? -3 : -2) + a, dy = (py ? -3 : -2) + b, dz = (pz ? -3 : -2) + c;
+                    const bool far = dx <= -2 || dx >= 2 || dy <= -2 || dy >= 2 || dz <= -2 || dz >= 2;
+                    if (far) t.v[cls][k++] = off_index(dx, dy, dz);
+                }
+    }
+    return t;
 }
+__constant__ ILTable c_il = make_il_table();
 
 // leaf-grid coordinates of the source cell of target cell (gx, gy, gz) at offset index di (periodic)
 __device__ inline size_t source_cell(int gx, int gy, int gz, int di, int nside) {
@@ -116,7 +127,6 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
     constexpr int SA = BM + 16, SB = BN + 16;
     __shared__ T As[2][BK][SA];
     __shared__ T Bs[2][BK][SB];
-    __shared__ int il[kNumIL];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -126,8 +136,7 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
     const M2LTile tile = m2l_tile((nup + BM - 1) / BM, (ncls + BN - 1) / BN, nsplit);
     const int px = tile.cls >> 2, py = (tile.cls >> 1) & 1, pz = tile.cls & 1;
     const int row0 = tile.rt * BM, col0 = tile.ct * BN;
-    if (tid == 0) class_list(px, py, pz, il);
-    __syncthreads();
+    const int *il = c_il.v[tile.cls];
     const int o_begin = kNumIL * tile.split / nsplit, o_end = kNumIL * (tile.split + 1) / nsplit;
 
     // A loader: pairs of adjacent rows; LA pairs per thread
@@ -247,9 +256,11 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
 // Lane l of v_mfma_f32_16x16x32_bf16 supplies A[l % 16][8 (l / 16) .. +8] and
 // B[8 (l / 16) .. +8][l % 16]; result element v sits at row 4 (l / 16) + v,
 // column l % 16.  LDS rows are 32 bf16 (four 16-byte chunks); chunk c of row r
-// is stored at chunk position c ^ ((r >> 2) & 3), which spreads the 16 rows of
-// a fragment read over all banks without padding.
-__device__ inline int swz(int r, int c) { return r * 32 + 8 * (c ^ ((r >> 2) & 3)); }
+// is stored at chunk position c ^ (((r >> 1) ^ (r >> 3)) & 3).  That spreads
+// any 8 consecutive rows (one 128-byte LDS access phase) and any 16
+// consecutive rows (one 256-byte phase) of a fragment read over distinct
+// banks without padding.
+__device__ inline int swz(int r, int c) { return r * 32 + 8 * (c ^ (((r >> 1) ^ (r >> 3)) & 3)); }
 
 template <int RF>
 __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ Kh, const __bf16 *__restrict__ Kl,
@@ -261,7 +272,6 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ K
     __shared__ __attribute__((aligned(16))) __bf16 Asl[2][BM * BK];
     __shared__ __attribute__((aligned(16))) __bf16 Bsh[2][BN * BK];
     __shared__ __attribute__((aligned(16))) __bf16 Bsl[2][BN * BK];
-    __shared__ int il[kNumIL];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -271,8 +281,7 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ K
     const M2LTile tile = m2l_tile((nup + BM - 1) / BM, (ncls + BN - 1) / BN, nsplit);
     const int px = tile.cls >> 2, py = (tile.cls >> 1) & 1, pz = tile.cls & 1;
     const int row0 = tile.rt * BM, col0 = tile.ct * BN;
-    if (tid == 0) class_list(px, py, pz, il);
-    __syncthreads();
+    const int *il = c_il.v[tile.cls];
     const int o_begin = kNumIL * tile.split / nsplit, o_end = kNumIL * (tile.split + 1) / nsplit;
 
     // A loader: 16-byte chunks (8 bf16 of the contraction) of hi and of lo, LA per thread
@@ -413,13 +422,20 @@ __global__ void k_split_K_bf16(const double *__restrict__ K, __bf16 *__restrict_
     lo[i] = (__bf16)(x - (float)a);
 }
 
-// L = sum over the split-K partials, in split order
-__global__ void k_m2l_reduce(const double *__restrict__ part, double *__restrict__ L, int64_t n, int nsplit) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = part[i];
-    for (int k = 1; k < nsplit; k++) s += part[k * n + i];
-    L[i] = s;
+// L = sum over the split-K partials in a fixed order: four interleaved runs of
+// the slices (slice k in run k mod 4), each added in slice order, then the
+// four run sums
+__global__ __launch_bounds__(256) void k_m2l_reduce(const double *__restrict__ part, double *__restrict__ L,
+                                                    int64_t n, int nsplit) {
+    __shared__ double red[4][64];
+    const int w = threadIdx.x >> 6, r = threadIdx.x & 63;
+    const int64_t i = blockIdx.x * (int64_t)64 + r;
+    double s = 0;
+    if (i < n)
+        for (int k = w; k < nsplit; k += 4) s += part[k * n + i];
+    red[w][r] = s;
+    __syncthreads();
+    if (w == 0 && i < n) L[i] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
 }
 
 __global__ void k_f64_to_f32(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
@@ -451,14 +467,19 @@ int m2l_row_frags(int nup) {
     return best;
 }
 
-// Number of offset slices (split-K): a multiple of 8 (the XCD-aware block
-// order then gives every XCD whole slices), enough for >= 512 blocks, at most 32.
+// Number of offset slices (split-K).  A level with >= 2048 block tiles runs
+// unsplit.  Otherwise a multiple of 8 (the XCD-aware block order then gives
+// every XCD whole slices), raised until the level launches >= 1024 blocks,
+// while the partial tiles stay within 32768 cells x n_u and every slice keeps
+// at least one offset.
 int m2l_splits(const ankh_plan_s *pl, int e) {
     const int h = pl->lv[e].nside / 2;
     const int bm = 32 * m2l_row_frags(pl->nup);
     const int64_t tiles = (int64_t)((pl->nup + bm - 1) / bm) * ((h * h * h + BN - 1) / BN) * 8;
+    const int64_t ncell = pl->lv[e].ncell;
+    if (tiles >= 2048) return 1;
     int s = 8;
-    while (s < 32 && tiles * s < 512) s += 8;
+    while (tiles * s < 1024 && (s + 8) * ncell <= 32768 && s + 8 <= kNumIL) s += 8;
     return s;
 }
 
@@ -508,7 +529,7 @@ hipError_t launch_m2l(ankh_plan_s *pl, int e) {
         default: launch_rf<8>(pl, e, grid, out, nsplit, nval); break;
     }
     if (nsplit > 1)
-        hipLaunchKernelGGL(k_m2l_reduce, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream,
+        hipLaunchKernelGGL(k_m2l_reduce, dim3((unsigned)((nval + 63) / 64)), dim3(256), 0, pl->stream,
                            pl->d_m2l_part, L, nval, nsplit);
     return hipGetLastError();
 }
