@@ -189,20 +189,34 @@ __device__ inline void cheb_basis(double xh, double hinv, const double *sH, doub
 }
 
 // ---- P2M: modified charges of every leaf (Alg. 2) --------------------------
+// Q[i][j][k] = sum_atoms sum_(a,b,c) m_abc S^(a)_i(x) S^(b)_j(y) S^(c)_k(z), the
+// ten (a,b,c) of q, mu and Theta (off-diagonal Theta doubled).  Grouped by the
+// x order a, the sum is sum_a S^(a)_i(x) w_a(j, k) with
+//   w_0 = q y0 z0 + mu_y y1 z0 + mu_z y0 z1 + Th_yy y2 z0 + 2 Th_yz y1 z1 + Th_zz y0 z2,
+//   w_1 = mu_x y0 z0 + 2 Th_xy y1 z0 + 2 Th_xz y0 z1,   w_2 = Th_xx y0 z0,
+// so a thread owns one (j, k) line of L nodes and a slice of the leaf's atoms;
+// the slices' lines are summed in slice order at the end.
 template <int L, int ORD>
 __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, const double *tab, int nu, int nup,
                                              double hinv, double *Q, int64_t n) {
     constexpr int ND = ORD + 1;
-    constexpr int CH = 64;
-    extern __shared__ double sm[];
-    double *sH = sm;                       // L*L
-    double *sS = sH + L * L;               // [CH][3][ND][L]
-    double *sMom = sS + CH * 3 * ND * L;   // [CH][10]
+    constexpr int CH = 32;                 // atoms per LDS chunk
+    constexpr int NJK = L * L;
+    constexpr int NSL = 256 / NJK;         // atom slices
+    constexpr int NMO = ORD == 0 ? 1 : (ORD == 1 ? 4 : 10);
+    __shared__ double sH[L * L];
+    __shared__ double sS[CH][3][ND][L];
+    __shared__ double sMom[CH][NMO];
+    __shared__ double red[NSL][L * L * L];
     const int tid = threadIdx.x;
     const int64_t leaf = blockIdx.x;
     for (int t = tid; t < L * L; t += 256) sH[t] = tab[L + t];
     const int s0 = offs[leaf], cnt = offs[leaf + 1] - s0;
-    double acc[4] = {0, 0, 0, 0};
+    const int jk = tid % NJK, sl = tid / NJK;
+    const int j = jk / L, k = jk % L;
+    double acc[L];
+#pragma unroll
+    for (int i = 0; i < L; i++) acc[i] = 0;
     for (int c0 = 0; c0 < cnt; c0 += CH) {
         const int m = min(CH, cnt - c0);
         __syncthreads();
@@ -210,11 +224,11 @@ __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, c
             const int a = tid / 3, ax = tid % 3;
             const int64_t slot = s0 + c0 + a;
             const double xl = ax == 0 ? P.x[slot] : (ax == 1 ? P.y[slot] : P.z[slot]);
-            cheb_basis<ND, L>(xl * hinv, hinv, sH, sS + (a * 3 + ax) * ND * L, L);
-        }
-        if (tid < m) {
-            const int64_t slot = s0 + c0 + tid;
-            double *mo = sMom + tid * 10;
+            cheb_basis<ND, L>(xl * hinv, hinv, sH, &sS[a][ax][0][0], L);
+        } else if (tid >= 128 && tid < 128 + m) {
+            const int a = tid - 128;
+            const int64_t slot = s0 + c0 + a;
+            double *mo = sMom[a];
             mo[0] = P.q[slot];
             if (ORD >= 1) {
                 mo[1] = P.mu[slot];
@@ -231,39 +245,44 @@ __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, c
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int node = tid + 256 * r;
-            if (node >= nu) break;
-            const int i = node / (L * L), j = (node / L) % L, k = node % L;
-            double s = 0;
-            for (int a = 0; a < m; a++) {
-                const double *Sx = sS + (a * 3 + 0) * ND * L;
-                const double *Sy = sS + (a * 3 + 1) * ND * L;
-                const double *Sz = sS + (a * 3 + 2) * ND * L;
-                const double *mo = sMom + a * 10;
-                const double x0 = Sx[i], y0 = Sy[j], z0 = Sz[k];
-                double v = mo[0] * x0 * y0 * z0;
-                if (ORD >= 1) {
-                    const double x1 = Sx[L + i], y1 = Sy[L + j], z1 = Sz[L + k];
-                    v += mo[1] * x1 * y0 * z0 + mo[2] * x0 * y1 * z0 + mo[3] * x0 * y0 * z1;
-                    if (ORD >= 2) {
-                        const double x2 = Sx[2 * L + i], y2 = Sy[2 * L + j], z2 = Sz[2 * L + k];
-                        v += mo[4] * x2 * y0 * z0 + mo[5] * x1 * y1 * z0 + mo[6] * x1 * y0 * z1 +
-                             mo[7] * x0 * y2 * z0 + mo[8] * x0 * y1 * z1 + mo[9] * x0 * y0 * z2;
+        if (sl < NSL) {
+            for (int a = sl; a < m; a += NSL) {
+                const double *mo = sMom[a];
+                const double y0 = sS[a][1][0][j], z0 = sS[a][2][0][k];
+                double w[ND];
+                w[0] = mo[0] * y0 * z0;
+                if constexpr (ORD >= 1) {
+                    const double y1 = sS[a][1][1][j], z1 = sS[a][2][1][k];
+                    w[0] += mo[2] * y1 * z0 + mo[3] * y0 * z1;
+                    w[1] = mo[1] * y0 * z0;
+                    if constexpr (ORD >= 2) {
+                        const double y2 = sS[a][1][ND - 1][j], z2 = sS[a][2][ND - 1][k];
+                        w[0] += mo[7] * y2 * z0 + mo[8] * y1 * z1 + mo[9] * y0 * z2;
+                        w[1] += mo[5] * y1 * z0 + mo[6] * y0 * z1;
+                        w[ND - 1] = mo[4] * y0 * z0;
                     }
                 }
-                s += v;
+#pragma unroll
+                for (int i = 0; i < L; i++) {
+                    double v = acc[i];
+#pragma unroll
+                    for (int d = 0; d < ND; d++) v += sS[a][0][d][i] * w[d];
+                    acc[i] = v;
+                }
             }
-            acc[r] += s;
         }
     }
+    if (sl < NSL) {
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-        const int node = tid + 256 * r;
-        if (node < nup) Q[leaf * nup + node] = node < nu ? acc[r] : 0.0;
+        for (int i = 0; i < L; i++) red[sl][i * NJK + jk] = acc[i];
     }
-    for (int node = tid + 1024; node < nup; node += 256) Q[leaf * nup + node] = 0.0;
+    __syncthreads();
+    for (int node = tid; node < nup; node += 256) {
+        double v = 0;
+        if (node < nu)
+            for (int t = 0; t < NSL; t++) v += red[t][node];
+        Q[leaf * nup + node] = v;
+    }
 }
 
 // ---- M2M: parent expansion (order Lp) from its 8 children (order Lc) ----------
@@ -423,28 +442,25 @@ __global__ __launch_bounds__(256) void k_leafdot(const double *Q, const double *
 
 // ---- L2P: far-field forces and fields at the atoms (adjoint of P2M) --------
 // phi(y) = sum_k Lambda_k S_k(y); F = -(q grad phi + mu_a grad d_a phi + Th_ab grad d_a d_b phi),
-// dE/dmu = grad phi.  One wave per leaf, one atom per lane.
+// dE/dmu = grad phi.  One thread per atom (leaf order): its 1D bases in
+// registers, the leaf's expansion contracted along z, then y, then x.
 template <int L, int ORD, bool FIELD>
-__global__ __launch_bounds__(64) void k_l2p(Particles P, const int32_t *offs, const double *tab, int nu,
-                                            int nup, double hinv, const double *Lam, double *F, double *G,
-                                            int64_t n) {
+__global__ __launch_bounds__(256, L <= 6 ? 2 : 1) void k_l2p(Particles P, const int32_t *leaf_in, const int32_t *perm,
+                                             const double *tab, int nup, double hinv, const double *Lam, double *F,
+                                             double *G, int64_t n) {
     constexpr int ND = ORD + 2;   // derivative orders 0..ORD+1
-    extern __shared__ double sm[];
-    double *sH = sm;                    // L*L
-    double *sL = sH + L * L;            // nu
-    double *sS = sL + nu;               // [blockDim][3][ND][L]
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int64_t leaf = blockIdx.x;
-    for (int t = tid; t < L * L; t += nt) sH[t] = tab[L + t];
-    for (int t = tid; t < nu; t += nt) sL[t] = Lam[leaf * nup + t];
+    __shared__ double sH[L * L];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < L * L; t += 256) sH[t] = tab[L + t];
     __syncthreads();
-    const int s0 = offs[leaf], cnt = offs[leaf + 1] - s0;
-    double *Sx = sS + tid * 3 * ND * L, *Sy = Sx + ND * L, *Sz = Sy + ND * L;
-    for (int a = tid; a < cnt; a += nt) {
-        const int64_t slot = s0 + a;
-        cheb_basis<ND, L>(P.x[slot] * hinv, hinv, sH, Sx, L);
-        cheb_basis<ND, L>(P.y[slot] * hinv, hinv, sH, Sy, L);
-        cheb_basis<ND, L>(P.z[slot] * hinv, hinv, sH, Sz, L);
+    const int64_t slot = blockIdx.x * (int64_t)256 + tid;
+    if (slot >= n) return;
+    const double *lam = Lam + (int64_t)leaf_in[perm[slot]] * nup;
+    double Sx[ND * L], Sy[ND * L], Sz[ND * L];
+    cheb_basis<ND, L>(P.x[slot] * hinv, hinv, sH, Sx, L);
+    cheb_basis<ND, L>(P.y[slot] * hinv, hinv, sH, Sy, L);
+    cheb_basis<ND, L>(P.z[slot] * hinv, hinv, sH, Sz, L);
+    {
         double phi[ND][ND][ND];
 #pragma unroll
         for (int x = 0; x < ND; x++)
@@ -452,19 +468,19 @@ __global__ __launch_bounds__(64) void k_l2p(Particles P, const int32_t *offs, co
             for (int y = 0; y < ND; y++)
 #pragma unroll
                 for (int z = 0; z < ND; z++) phi[x][y][z] = 0;
-#pragma unroll 2
+#pragma unroll
         for (int i = 0; i < L; i++) {
             double h[ND][ND];
 #pragma unroll
             for (int y = 0; y < ND; y++)
 #pragma unroll
                 for (int z = 0; z < ND; z++) h[y][z] = 0;
-#pragma unroll 2
+#pragma unroll
             for (int j = 0; j < L; j++) {
                 double g[ND];
 #pragma unroll
                 for (int z = 0; z < ND; z++) g[z] = 0;
-                const double *row = sL + (i * L + j) * L;
+                const double *row = lam + (i * L + j) * L;
 #pragma unroll
                 for (int k = 0; k < L; k++) {
                     const double lv = row[k];
@@ -706,7 +722,7 @@ hipError_t launch_p2m(ankh_plan_s *pl, int ord) {
     const int L = pl->order;
     const double hinv = 2.0 / (pl->edge / pl->nside);
     double *Q = pl->d_M + pl->lv[pl->depth].cell0 * pl->nup;
-    const size_t shm = sizeof(double) * (L * L + 64 * 3 * (ord + 1) * L + 64 * 10);
+    const size_t shm = 0;
     dim3 g((unsigned)pl->nleaf), b(256);
 #define ANKH_P2M(LL)                                                                                              \
     if (ord == 0)                                                                                                 \
@@ -775,12 +791,9 @@ hipError_t launch_l2p(ankh_plan_s *pl, int ord, bool fields) {
     const int L = pl->order;
     const double hinv = 2.0 / (pl->edge / pl->nside);
     const double *Lam = pl->d_L + pl->lv[pl->depth].cell0 * pl->nup;
-    // one atom per lane; the per-lane basis tables live in LDS (kept within 64 KiB)
-    const int nt = (sizeof(double) * (L * L + pl->nu + 64 * 3 * (ord + 2) * L) <= 65536) ? 64 : 32;
-    const size_t shm = sizeof(double) * (L * L + pl->nu + nt * 3 * (ord + 2) * L);
-    dim3 g((unsigned)pl->nleaf), b(nt);
-#define ANKH_L2P3(LL, O, FL)                                                                                      \
-    hipLaunchKernelGGL((k_l2p<LL, O, FL>), g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, pl->nu, pl->nup,  \
+    dim3 g((unsigned)((pl->n + 255) / 256)), b(256);
+#define ANKH_L2P3(LL, O, FL)                                                                                       \
+    hipLaunchKernelGGL((k_l2p<LL, O, FL>), g, b, 0, pl->stream, pl->P, pl->d_leaf, pl->d_perm, pl->d_tab, pl->nup, \
                        hinv, Lam, pl->d_F, pl->d_G, pl->n)
 #define ANKH_L2P(LL)                                                                         \
     if (ord == 0) { if (fields) ANKH_L2P3(LL, 0, true); else ANKH_L2P3(LL, 0, false); }     \
