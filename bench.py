@@ -26,18 +26,48 @@ sys.path.insert(0, ROOT)
 
 METRIC = "E+forces evals/s per atom on 1 MI355X, mixed vs FP64, rel RMS force err"
 
-# flops per ordered near-field pair of the pair kernel for charges + dipoles +
-# quadrupoles with forces and fields, counted from the pair formula
-# (FMA = 2, add / mul = 1, erfc / exp / rsqrt = 1 each)
-P2P_FLOP_PER_PAIR = 380.0
+# Algorithmic flops of the near field per UNORDERED pair of atoms (the mutual
+# form evaluates each pair once): the pair formula for charges + dipoles +
+# quadrupoles with the energy, the force, the field at both atoms and the
+# accumulation into both atoms, counted term by term (FMA = 2, add / mul = 1,
+# erfc / exp / rsqrt = 1 each).  Breakdown in the design doc.
+P2P_FLOP_PER_UNORDERED_PAIR = 437.0
+
+# HBM traffic of one P2P launch measured with rocprofv3 counters (FETCH_SIZE and
+# WRITE_SIZE, calibrated against a copy of known size) for the kernel source
+# with the recorded SHA-256; reported only while the source is unchanged.
+P2P_COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "p2p_water_288000_counters.txt")
+P2P_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2212_08284_amd", "csrc",
+                          "ankh_p2p.hip")
 
 PEAK = {  # MI355X, TFLOP/s
-    "valu_fp64": 78.6,    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
-    "valu_fp32": 78.6,    # same issue rate without packed FP32 (disabled in this build)
+    "valu_fp64": 78.6,    # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+    "valu_fp32": 78.6,    # the same issue rate: packed FP32 (157.3) is not used by this build
+    "valu_fp32_packed": 157.3,
     "mfma_fp64": 78.6,
     "mfma_fp32": 157.3,
     "mfma_bf16": 2500.0,
 }
+
+
+def p2p_traffic():
+    """Calibrated HBM bytes per P2P launch from the committed counter summary, or None."""
+    import hashlib
+    try:
+        rec = {}
+        with open(P2P_COUNTERS) as fh:
+            for ln in fh:
+                if "=" in ln and not ln.lstrip().startswith("#"):
+                    k, v = ln.split("=", 1)
+                    rec[k.strip()] = v.strip()
+        with open(P2P_SOURCE, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+        if rec.get("kernel_source_sha256") != sha:
+            return None
+        return float(rec["fetch_bytes_per_launch"]) + float(rec["write_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -154,20 +184,22 @@ def main():
 
     # roofline of the dominant kernel of the timed (mixed) path, from the live hipEvent stage timings
     sm = st_mixed["stage_ms"]
-    if sm["p2p"] >= sm["m2l"]:
-        flops = st_mixed["near_pairs"] * P2P_FLOP_PER_PAIR
-        achieved = flops / (sm["p2p"] * 1e-3) / 1e12
-        roof = {"kernel": "p2p", "bound": "alu", "achieved": achieved, "peak": PEAK["valu_fp32"],
-                "unit": "TFLOP/s", "frac": achieved / PEAK["valu_fp32"], "traffic": None,
-                "flop_per_launch": flops, "avg_launch_ms": sm["p2p"],
-                "note": "FP32 vector peak without packed FP32 (157.3 TFLOP/s needs packed FP32, disabled)"}
-    else:
-        flops = st_mixed["m2l_flops"]
-        achieved = flops / (sm["m2l"] * 1e-3) / 1e12
-        pk = PEAK["mfma_bf16"] if args.mode == "mixed_bf16x3" else PEAK["mfma_fp32"]
-        roof = {"kernel": "m2l", "bound": "mfma", "achieved": achieved, "peak": pk,
-                "unit": "TFLOP/s", "frac": achieved / pk, "traffic": None,
-                "flop_per_launch": flops, "avg_launch_ms": sm["m2l"]}
+    unordered = st_mixed["near_pairs"] / 2.0
+    p2p_flops = unordered * P2P_FLOP_PER_UNORDERED_PAIR
+    p2p_tf = p2p_flops / (sm["p2p"] * 1e-3) / 1e12
+    m2l_flops = st_mixed["m2l_flops"]
+    m2l_tf = m2l_flops / (sm["m2l"] * 1e-3) / 1e12
+    m2l_peak = PEAK["mfma_bf16"] if args.mode == "mixed_bf16x3" else PEAK["mfma_fp32"]
+    p2p_roof = {"kernel": "p2p", "bound": "alu", "achieved": p2p_tf, "peak": PEAK["valu_fp32"],
+                "unit": "TFLOP/s", "frac": p2p_tf / PEAK["valu_fp32"], "traffic": p2p_traffic(),
+                "flop_per_launch": p2p_flops, "unordered_pairs": unordered,
+                "flop_per_unordered_pair": P2P_FLOP_PER_UNORDERED_PAIR, "avg_launch_ms": sm["p2p"],
+                "frac_of_packed_fp32_peak": p2p_tf / PEAK["valu_fp32_packed"],
+                "note": "peak = 256 CU x 4 SIMD x 16 lanes x FMA x 2.4 GHz (unpacked FP32, as issued)"}
+    m2l_roof = {"kernel": "m2l", "bound": "mfma", "achieved": m2l_tf, "peak": m2l_peak, "unit": "TFLOP/s",
+                "frac": m2l_tf / m2l_peak, "traffic": None, "flop_per_launch": m2l_flops, "avg_launch_ms": sm["m2l"],
+                "note": "algorithmic flops 2 * 189 * n_u^2 per cell over all levels; the BF16x3 split issues 3x"}
+    roof, other = (p2p_roof, m2l_roof) if sm["p2p"] >= sm["m2l"] else (m2l_roof, p2p_roof)
 
     line = {
         "metric": METRIC,
@@ -191,6 +223,7 @@ def main():
         "ns_per_day_equiv_dt2fs": 86400.0 / t_mixed * 2e-6,
         "stage_ms": sm,
         "roofline": roof,
+        "roofline_" + other["kernel"]: other,
     }
     line.update(res)
     pm.close()

@@ -93,8 +93,9 @@ typedef struct {
        over the evaluations run since timing was last enabled with
        ankh_set_timing; -1 when there were none.
        Stages: 0 bin+sort, 1 gather, 2 p2m, 3 m2m, 4 m2l (all levels), 5 periodic root,
-               6 l2l + leaf energies, 7 l2p, 8 p2p, 9 reduce + unpermute */
-    double stage_ms[10];
+               6 l2l + leaf energies, 7 l2p, 8 p2p pair kernel, 9 p2p partial sums,
+               10 reduce + unpermute */
+    double stage_ms[11];
     int64_t timed_evals;       /* evaluations averaged into stage_ms */
 } ankh_plan_stats;
 

@@ -30,7 +30,7 @@ STATUS = {
     7: "HIP runtime error",
 }
 
-STAGES = ["sort", "gather", "p2m", "m2m", "m2l", "periodic", "l2l", "l2p", "p2p", "reduce"]
+STAGES = ["sort", "gather", "p2m", "m2m", "m2l", "periodic", "l2l", "l2p", "p2p", "p2p_sum", "reduce"]
 
 
 class AnkhError(RuntimeError):
@@ -49,7 +49,7 @@ class _Stats(ctypes.Structure):
                 ("images", ctypes.c_int32), ("max_order", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("root_order", ctypes.c_int32), ("xi", ctypes.c_double), ("box_radius", ctypes.c_double), ("rel_accuracy", ctypes.c_double),
                 ("plan_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_int64), ("m2l_flops", ctypes.c_double),
-                ("near_pairs", ctypes.c_int64), ("stage_ms", ctypes.c_double * 10), ("timed_evals", ctypes.c_int64)]
+                ("near_pairs", ctypes.c_int64), ("stage_ms", ctypes.c_double * len(STAGES)), ("timed_evals", ctypes.c_int64)]
 
 
 _lib = None
@@ -149,7 +149,7 @@ def ankh_get_stats(plan) -> dict:
     s = _Stats()
     _check(load_library().ankh_get_stats(plan, ctypes.byref(s)), "ankh_get_stats")
     d = {f: getattr(s, f) for f, _ in _Stats._fields_ if f != "stage_ms"}
-    d["stage_ms"] = {STAGES[i]: s.stage_ms[i] for i in range(10)}
+    d["stage_ms"] = {STAGES[i]: s.stage_ms[i] for i in range(len(STAGES))}
     return d
 
 

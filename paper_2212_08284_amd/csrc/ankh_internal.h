@@ -20,7 +20,7 @@ constexpr int kMaxDepth = 7;         // 2^21 leaves at most
 constexpr int kNumOff = 343;         // slots for offsets d in [-3,3]^3 (316 used)
 constexpr int kNumIL = 189;          // interaction-list length of every cell
 constexpr int kRedBlocks = 256;      // first-stage blocks of the energy reduction
-constexpr int kNumStages = 10;
+constexpr int kNumStages = 11;
 constexpr int kCperSlices = 16;
 constexpr int kNumSlots = 16;       // near-field partials per atom (see the pair kernel)     // column slices of the far-image root matvec
 
@@ -136,6 +136,7 @@ int m2l_row_frags(int nup);
 hipError_t launch_split_K_bf16(ankh_plan_s *pl, const double *K, __bf16 *hi, __bf16 *lo);
 inline bool is_mixed(const ankh_plan_s *pl) { return pl->precision != ANKH_FP64; }
 hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields);
+hipError_t launch_p2p_sum(ankh_plan_s *pl, bool grad, bool fields);
 hipError_t launch_build_m2l(ankh_plan_s *pl, int e, double *K);
 hipError_t launch_build_cper(ankh_plan_s *pl);
 hipError_t launch_convert_f32(const double *src, float *dst, int64_t n, hipStream_t s);

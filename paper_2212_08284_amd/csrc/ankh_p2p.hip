@@ -588,16 +588,22 @@ hipError_t launch_t(ankh_plan_s *pl, const P2PArgs &a, int ord, bool grad, bool 
         else ANKH_P2P(2, false, false);
     }
 #undef ANKH_P2P
-    dim3 g2((unsigned)((pl->n + 255) / 256));
-    const R *SF = static_cast<const R *>(a.slot_f), *SG = static_cast<const R *>(a.slot_g);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_sum_t(ankh_plan_s *pl, bool grad, bool fields) {
+    dim3 g2((unsigned)((pl->n + 255) / 256)), b(256);
+    hipStream_t s = pl->stream;
+    const R *SF = static_cast<const R *>(pl->d_slot_f), *SG = static_cast<const R *>(pl->d_slot_g);
     if (grad && fields)
-        hipLaunchKernelGGL((k_p2p_slots<R, true, true>), g2, b, 0, s, pl->n, a.slot_e, SF, SG, pl->d_eatom, pl->d_F,
-                           pl->d_G);
+        hipLaunchKernelGGL((k_p2p_slots<R, true, true>), g2, b, 0, s, pl->n, pl->d_slot_e, SF, SG, pl->d_eatom,
+                           pl->d_F, pl->d_G);
     else if (grad)
-        hipLaunchKernelGGL((k_p2p_slots<R, true, false>), g2, b, 0, s, pl->n, a.slot_e, SF, SG, pl->d_eatom, pl->d_F,
-                           pl->d_G);
+        hipLaunchKernelGGL((k_p2p_slots<R, true, false>), g2, b, 0, s, pl->n, pl->d_slot_e, SF, SG, pl->d_eatom,
+                           pl->d_F, pl->d_G);
     else
-        hipLaunchKernelGGL((k_p2p_slots<R, false, false>), g2, b, 0, s, pl->n, a.slot_e, SF, SG, pl->d_eatom,
+        hipLaunchKernelGGL((k_p2p_slots<R, false, false>), g2, b, 0, s, pl->n, pl->d_slot_e, SF, SG, pl->d_eatom,
                            pl->d_F, pl->d_G);
     return hipGetLastError();
 }
@@ -629,6 +635,11 @@ hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields) {
     if (is_mixed(pl))
         return ser ? launch_t<float, true>(pl, a, ord, grad, fields) : launch_t<float, false>(pl, a, ord, grad, fields);
     return ser ? launch_t<double, true>(pl, a, ord, grad, fields) : launch_t<double, false>(pl, a, ord, grad, fields);
+}
+
+// per atom: the near-field energy and the sums of the force / field partial slots
+hipError_t launch_p2p_sum(ankh_plan_s *pl, bool grad, bool fields) {
+    return is_mixed(pl) ? launch_sum_t<float>(pl, grad, fields) : launch_sum_t<double>(pl, grad, fields);
 }
 
 }  // namespace ankh

@@ -147,9 +147,11 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
         mark(8);
         ck(launch_p2p(pl, ord, grad, fields));
         mark(9);
+        ck(launch_p2p_sum(pl, grad, fields));
+        mark(10);
         ck(launch_reduce(pl, energy, ord));
         if (grad) ck(launch_unpermute(pl, forces, dEdmu, ord >= 1));
-        mark(10);
+        mark(11);
     } catch (const HipFail &) {
         return ANKH_ERR_HIP;
     }
