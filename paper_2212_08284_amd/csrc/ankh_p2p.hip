@@ -150,8 +150,24 @@ __device__ inline void symv(const R *Q, R vx, R vy, R vz, R &ox, R &oy, R &oz) {
     oz = Q[2] * vx + Q[4] * vy + Q[5] * vz;
 }
 
+// exp(-u) for the Gaussian factor of the radial functions: the short series,
+// or in float32 the hardware base-2 exponential (relative error ~1e-7 here)
+template <typename R, bool SER> __device__ inline R gauss(R u);
+template <> __device__ inline float gauss<float, true>(float u) { return __expf(-u); }
+template <> __device__ inline float gauss<float, false>(float u) { return expf(-u); }
+template <> __device__ inline double gauss<double, true>(double u) { return exp_near<double>(u); }
+template <> __device__ inline double gauss<double, false>(double u) { return exp(-u); }
+
 // One pair: adds ew * E to e, -grad to f (target force) and the target field
 // to g; with SRC also the source field to gs (the source force is -f's share).
+// The gradient is grouped by vector (the same algebra as grad(c_n) B_n - r
+// sum c_n B_{n+1}):
+//   grad_r E = a1 di + a2 dk + a3 Qk r + a4 Qi r + 2 B2 (Qk di - Qi dk)
+//              - 4 B3 (Qi Qk r + Qk Qi r) - r sum_n c_n B_{n+1},
+//   a1 = -(qk B1 + (dk.r) B2 + (r.Qk.r) B3),   a2 = qi B1 - (di.r) B2 + (r.Qi.r) B3,
+//   a3 = 2 (qi B2 - (di.r) B3 + (r.Qi.r) B4),  a4 = 2 (qk B2 + (dk.r) B3 + (r.Qk.r) B4),
+// and the fields reuse a1, a2:  dE/d(di) = B1 dk + 2 B2 Qk r + a1 r,
+// dE/d(dk) = B1 di - 2 B2 Qi r + a2 r.
 template <typename R, int ORD, bool GRAD, bool FIELD, bool SRC, bool SER>
 __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *Qi, R ck, const R *dk,
                                   const R *Qk, R xi, R xi2, R cex, R ew, R &e, R *f, R *g, R *gs) {
@@ -163,7 +179,7 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
     R B[NB > 2 ? NB : 2];
     B[0] = (SER ? erfc_near<R>(xi * r) : dev_erfc<R>(xi * r)) * rinv;
     {
-        const R ex = (SER ? exp_near<R>(xi2 * r2) : dev_exp<R>(-xi2 * r2)) * cex;
+        const R ex = gauss<R, SER>(xi2 * r2) * cex;
         R pw = 1;
 #pragma unroll
         for (int n = 1; n < NB; n++) {
@@ -171,17 +187,18 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
             B[n] = ((2 * n - 1) * B[n - 1] + pw * ex) * rinv2;
         }
     }
+    const R rv[3] = {rx, ry, rz};
     R c0 = ci * ck, c1 = 0, c2 = 0, c3 = 0, c4 = 0;
-    R dir = 0, dkr = 0, dik = 0;
+    R dir = 0, dkr = 0;
     R Qir[3] = {0, 0, 0}, Qkr[3] = {0, 0, 0}, qirr = 0, qkrr = 0;
-    if (ORD >= 1) {
+    if constexpr (ORD >= 1) {
         dir = di[0] * rx + di[1] * ry + di[2] * rz;
         dkr = dk[0] * rx + dk[1] * ry + dk[2] * rz;
-        dik = di[0] * dk[0] + di[1] * dk[1] + di[2] * dk[2];
+        const R dik = di[0] * dk[0] + di[1] * dk[1] + di[2] * dk[2];
         c1 = ci * dkr - ck * dir + dik;
         c2 = -dir * dkr;
     }
-    if (ORD >= 2) {
+    if constexpr (ORD >= 2) {
         symv(Qi, rx, ry, rz, Qir[0], Qir[1], Qir[2]);
         symv(Qk, rx, ry, rz, Qkr[0], Qkr[1], Qkr[2]);
         qirr = Qir[0] * rx + Qir[1] * ry + Qir[2] * rz;
@@ -191,54 +208,62 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
         const R QirQkr = Qir[0] * Qkr[0] + Qir[1] * Qkr[1] + Qir[2] * Qkr[2];
         const R QiQk = Qi[0] * Qk[0] + Qi[3] * Qk[3] + Qi[5] * Qk[5] +
                        2 * (Qi[1] * Qk[1] + Qi[2] * Qk[2] + Qi[4] * Qk[4]);
-        c2 += ci * qkrr + ck * qirr + 2 * diQkr - 2 * dkQir + 2 * QiQk;
+        c2 += ci * qkrr + ck * qirr + 2 * (diQkr - dkQir + QiQk);
         c3 = -dir * qkrr + dkr * qirr - 4 * QirQkr;
         c4 = qirr * qkrr;
     }
     R E = c0 * B[0];
-    if (ORD >= 1) E += c1 * B[1] + c2 * B[2];
-    if (ORD >= 2) E += c3 * B[3] + c4 * B[4];
+    if constexpr (ORD >= 1) E += c1 * B[1] + c2 * B[2];
+    if constexpr (ORD >= 2) E += c3 * B[3] + c4 * B[4];
     e += ew * E;
-    if (GRAD) {
-        R s = c0 * B[1];
-        if (ORD >= 1) s += c1 * B[2] + c2 * B[3];
-        if (ORD >= 2) s += c3 * B[4] + c4 * B[5];
-        R gr[3] = {-rx * s, -ry * s, -rz * s};
-        if (ORD >= 1) {
-#pragma unroll
-            for (int a = 0; a < 3; a++) {
-                gr[a] += B[1] * (ci * dk[a] - ck * di[a]);
-                gr[a] += B[2] * (-dkr * di[a] - dir * dk[a]);
-            }
+    if constexpr (!GRAD && !FIELD) return;
+    // coefficients shared by the force and the fields
+    R a1 = 0, a2 = 0;
+    if constexpr (ORD >= 1) {
+        a1 = -(ck * B[1] + dkr * B[2]);
+        a2 = ci * B[1] - dir * B[2];
+        if constexpr (ORD >= 2) {
+            a1 -= qkrr * B[3];
+            a2 += qirr * B[3];
         }
-        if (ORD >= 2) {
+    }
+    if constexpr (GRAD) {
+        R sn = c0 * B[1];
+        if constexpr (ORD >= 1) sn += c1 * B[2] + c2 * B[3];
+        if constexpr (ORD >= 2) sn += c3 * B[4] + c4 * B[5];
+        R gr[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) gr[a] = -sn * rv[a];
+        if constexpr (ORD >= 1) {
+#pragma unroll
+            for (int a = 0; a < 3; a++) gr[a] += a1 * di[a] + a2 * dk[a];
+        }
+        if constexpr (ORD >= 2) {
+            const R a3 = 2 * (ci * B[2] - dir * B[3] + qirr * B[4]);
+            const R a4 = 2 * (ck * B[2] + dkr * B[3] + qkrr * B[4]);
             R Qkdi[3], Qidk[3], QiQkr[3], QkQir[3];
             symv(Qk, di[0], di[1], di[2], Qkdi[0], Qkdi[1], Qkdi[2]);
             symv(Qi, dk[0], dk[1], dk[2], Qidk[0], Qidk[1], Qidk[2]);
             symv(Qi, Qkr[0], Qkr[1], Qkr[2], QiQkr[0], QiQkr[1], QiQkr[2]);
             symv(Qk, Qir[0], Qir[1], Qir[2], QkQir[0], QkQir[1], QkQir[2]);
+            const R b2 = 2 * B[2], b3 = -4 * B[3];
 #pragma unroll
-            for (int a = 0; a < 3; a++) {
-                gr[a] += B[2] * (2 * ci * Qkr[a] + 2 * ck * Qir[a] + 2 * Qkdi[a] - 2 * Qidk[a]);
-                gr[a] += B[3] * (-qkrr * di[a] - 2 * dir * Qkr[a] + qirr * dk[a] + 2 * dkr * Qir[a] -
-                                 4 * (QiQkr[a] + QkQir[a]));
-                gr[a] += B[4] * (2 * qkrr * Qir[a] + 2 * qirr * Qkr[a]);
-            }
+            for (int a = 0; a < 3; a++)
+                gr[a] += a3 * Qkr[a] + a4 * Qir[a] + b2 * (Qkdi[a] - Qidk[a]) + b3 * (QiQkr[a] + QkQir[a]);
         }
-        f[0] = -gr[0];
-        f[1] = -gr[1];
-        f[2] = -gr[2];
+#pragma unroll
+        for (int a = 0; a < 3; a++) f[a] = -gr[a];
     }
-    if (FIELD) {
-        const R rv[3] = {rx, ry, rz};
+    if constexpr (FIELD) {
+        const R b2 = 2 * B[2];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            R v = B[1] * (dk[a] - ck * rv[a]) - B[2] * dkr * rv[a];
-            if (ORD >= 2) v += B[2] * 2 * Qkr[a] - B[3] * qkrr * rv[a];
+            R v = B[1] * dk[a] + a1 * rv[a];
+            if constexpr (ORD >= 2) v += b2 * Qkr[a];
             g[a] = v;
-            if (SRC) {
-                R u = B[1] * (di[a] + ci * rv[a]) - B[2] * dir * rv[a];
-                if (ORD >= 2) u += B[3] * qirr * rv[a] - B[2] * 2 * Qir[a];
+            if constexpr (SRC) {
+                R u = B[1] * di[a] + a2 * rv[a];
+                if constexpr (ORD >= 2) u -= b2 * Qir[a];
                 gs[a] = u;
             }
         }
