@@ -67,9 +67,18 @@ template <> __device__ inline float dev_erfc<float>(float v) { return erfcf(v); 
 template <typename R> __device__ inline R dev_exp(R v);
 template <> __device__ inline double dev_exp<double>(double v) { return exp(v); }
 template <> __device__ inline float dev_exp<float>(float v) { return expf(v); }
+// 1/sqrt(v) for v = r^2 of a near pair (never denormal, never zero): the
+// hardware reciprocal square root (float32, ~1 ulp), refined in float64 by two
+// Newton steps y <- y (3/2 - v y^2 / 2), each squaring the relative error.
 template <typename R> __device__ inline R dev_rsqrt(R v);
-template <> __device__ inline double dev_rsqrt<double>(double v) { return 1.0 / sqrt(v); }
-template <> __device__ inline float dev_rsqrt<float>(float v) { return rsqrtf(v); }
+template <> __device__ inline double dev_rsqrt<double>(double v) {
+    double y = __builtin_amdgcn_rsq(v);
+    const double hv = 0.5 * v;
+    y = y * (1.5 - hv * y * y);
+    y = y * (1.5 - hv * y * y);
+    return y;
+}
+template <> __device__ inline float dev_rsqrt<float>(float v) { return __builtin_amdgcn_rsqf(v); }
 
 // sum over the 16 lanes of a DPP row; every lane of the row receives the sum
 // (every lane reads a lane of its own row, so bound_ctrl never applies; it lets
