@@ -27,11 +27,11 @@ sys.path.insert(0, ROOT)
 METRIC = "E+forces evals/s per atom on 1 MI355X, mixed vs FP64, rel RMS force err"
 
 # Algorithmic flops of the near field per UNORDERED pair of atoms (the mutual
-# form evaluates each pair once): the pair formula for charges + dipoles +
-# quadrupoles with the energy, the force, the field at both atoms and the
-# accumulation into both atoms, counted term by term (FMA = 2, add / mul = 1,
-# erfc / exp / rsqrt = 1 each).  Breakdown in the design doc.
-P2P_FLOP_PER_UNORDERED_PAIR = 437.0
+# form evaluates each pair once): the pair kernel's formula for charges +
+# dipoles + quadrupoles with the energy, the force, the field at both atoms and
+# the accumulation into both atoms, counted term by term from its source
+# (FMA = 2, add / mul = 1, erfc / exp / rsqrt = 1 each).  Breakdown in the design doc.
+P2P_FLOP_PER_UNORDERED_PAIR = 333.0
 
 # HBM traffic of one P2P launch measured with rocprofv3 counters (FETCH_SIZE and
 # WRITE_SIZE, calibrated against a copy of known size) for the kernel source

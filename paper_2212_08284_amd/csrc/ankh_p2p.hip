@@ -317,7 +317,7 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
     __shared__ double sx[CH], sy[CH], sz[CH];
     __shared__ R smo[NM][CH];
     __shared__ R sacc[6][CH];           // source-side force (3) and field (3)
-    __shared__ double tpart[7][NG][G];  // target-side partials of the 16 groups
+    __shared__ double tpart[2][7][NG][G];   // target-side partials of the 16 groups (two passes)
     __shared__ int tfirst[KMAX], tcount[KMAX], tpre[KMAX + 1];   // target leaves: first atom, atoms, prefix
     __shared__ double tshift[KMAX][3];                            // their position shift, -d w
 
@@ -366,15 +366,18 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
         while (s + 1 < ntl && f >= tpre[s + 1]) s++;
         return s;
     };
-    // sums the 16 groups' partials of pass tp (fixed order) and stores them in the atoms' slots
-    auto flush = [&](int tp, int nt_pass, bool mutual, bool first) {
+    // sums the 16 groups' partials of pass tp (fixed order) and stores them in
+    // the atoms' slots.  The partials alternate between two LDS buffers, so one
+    // barrier per pass suffices: a buffer is rewritten two passes later, after
+    // every thread has passed the next pass's barrier.
+    auto flush = [&](int buf, int tp, int nt_pass, bool mutual, bool first) {
         __syncthreads();
         if (tid < 7 * G) {
             const int c = tid / G, l = tid % G;
             const int f = tp + l;
             if (f < nt_pass) {
                 double s = 0;
-                for (int g2 = 0; g2 < NG; g2++) s += tpart[c][g2][l];
+                for (int g2 = 0; g2 < NG; g2++) s += tpart[buf][c][g2][l];
                 int64_t at;
                 int slot;
                 if (mutual) {
@@ -395,8 +398,38 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
                 }
             }
         }
-        __syncthreads();
     };
+    // one lane's target atom of a pass: position (shifted into the source leaf's frame) and moments
+    struct Target {
+        double x, y, z;
+        R c, d[3], Q[6];
+    };
+    auto load_target = [&](int f, int nt_pass, bool mutual, Target &t) {
+        const bool iv = f < nt_pass;
+        int64_t ti = s0;
+        double shx = 0, shy = 0, shz = 0;
+        if (iv) {
+            if (mutual) {
+                const int sg = segment(f);
+                ti = tfirst[sg] + (f - tpre[sg]);
+                shx = tshift[sg][0];
+                shy = tshift[sg][1];
+                shz = tshift[sg][2];
+            } else {
+                ti = s0 + f;
+            }
+        }
+        // an absent target sits far away with zero moments: its pair terms vanish
+        t.x = iv ? a.x[ti] + shx : 1.0e4;
+        t.y = iv ? a.y[ti] + shy : 1.0e4;
+        t.z = iv ? a.z[ti] + shz : 1.0e4;
+        t.c = iv ? q[ti] : (R)0;
+#pragma unroll
+        for (int c = 0; c < 3; c++) t.d[c] = (ORD >= 1 && iv) ? mu[c * n + ti] : (R)0;
+#pragma unroll
+        for (int c = 0; c < 6; c++) t.Q[c] = (ORD >= 2 && iv) ? th[c * n + ti] : (R)0;
+    };
+    int pbuf = 0;
 
     for (int cs = 0; cs < nsrc; cs += CH) {
         const int chn = min(CH, nsrc - cs);
@@ -427,18 +460,11 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
 #pragma unroll
             for (int c = 0; c < 6; c++) psrc[m][c] = 0;
         for (int tp = 0; tp < ntg; tp += G) {
-            const int f = tp + ln;
-            const bool iv = f < ntg;
-            const int sg = iv ? segment(f) : 0;
-            const int64_t ti = iv ? tfirst[sg] + (f - tpre[sg]) : 0;
-            // an absent target sits far away with zero moments: its pair terms vanish
-            const double xt = iv ? a.x[ti] + tshift[sg][0] : 1.0e4, yt = iv ? a.y[ti] + tshift[sg][1] : 1.0e4,
-                         zt = iv ? a.z[ti] + tshift[sg][2] : 1.0e4;
-            R ci = iv ? q[ti] : (R)0, di[3] = {0, 0, 0}, Qi[6] = {0, 0, 0, 0, 0, 0};
-            if (ORD >= 1 && iv)
-                for (int c = 0; c < 3; c++) di[c] = mu[c * n + ti];
-            if (ORD >= 2 && iv)
-                for (int c = 0; c < 6; c++) Qi[c] = th[c * n + ti];
+            Target tcur;
+            load_target(tp + ln, ntg, true, tcur);
+            const double xt = tcur.x, yt = tcur.y, zt = tcur.z;
+            const R ci = tcur.c;
+            const R *di = tcur.d, *Qi = tcur.Q;
             R te = 0, tf[3] = {0, 0, 0}, tg[3] = {0, 0, 0};
             // one pair with source j: the target's share into te / tf / tg, the source's into pf / ps
             auto pair = [&](int j, R *pf, R *ps) {
@@ -491,13 +517,14 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
                     }
                 }
             }
-            tpart[0][grp][ln] = (double)te;
+            tpart[pbuf][0][grp][ln] = (double)te;
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                tpart[1 + c][grp][ln] = (double)tf[c];
-                tpart[4 + c][grp][ln] = (double)tg[c];
+                tpart[pbuf][1 + c][grp][ln] = (double)tf[c];
+                tpart[pbuf][4 + c][grp][ln] = (double)tg[c];
             }
-            flush(tp, ntg, true, cs == 0);
+            flush(pbuf, tp, ntg, true, cs == 0);
+            pbuf ^= 1;
         }
         if constexpr (RACC) {
             if (GRAD || FIELD) {
@@ -530,15 +557,12 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
         // the leaf with itself: its atoms against this chunk, all ordered pairs, half energy
         if (kind == 1) {
             for (int tp = 0; tp < nsrc; tp += G) {
+                Target tcur;
+                load_target(tp + ln, nsrc, false, tcur);
                 const int i = tp + ln;
-                const bool iv = i < nsrc;
-                const int64_t ti = s0 + (iv ? i : 0);
-                const double xt = iv ? a.x[ti] : 1.0e4, yt = iv ? a.y[ti] : 1.0e4, zt = iv ? a.z[ti] : 1.0e4;
-                R ci = iv ? q[ti] : (R)0, di[3] = {0, 0, 0}, Qi[6] = {0, 0, 0, 0, 0, 0};
-                if (ORD >= 1 && iv)
-                    for (int c = 0; c < 3; c++) di[c] = mu[c * n + ti];
-                if (ORD >= 2 && iv)
-                    for (int c = 0; c < 6; c++) Qi[c] = th[c * n + ti];
+                const double xt = tcur.x, yt = tcur.y, zt = tcur.z;
+                const R ci = tcur.c;
+                const R *di = tcur.d, *Qi = tcur.Q;
                 R te = 0, tf[3] = {0, 0, 0}, tg[3] = {0, 0, 0};
                 for (int j = grp; j < chn; j += NG) {
                     if (j + cs == i) continue;   // an atom with itself at zero shift
@@ -558,13 +582,14 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
                         tg[c] += pg[c];
                     }
                 }
-                tpart[0][grp][ln] = (double)te;
+                tpart[pbuf][0][grp][ln] = (double)te;
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    tpart[1 + c][grp][ln] = (double)tf[c];
-                    tpart[4 + c][grp][ln] = (double)tg[c];
+                    tpart[pbuf][1 + c][grp][ln] = (double)tf[c];
+                    tpart[pbuf][4 + c][grp][ln] = (double)tg[c];
                 }
-                flush(tp, nsrc, false, cs == 0);
+                flush(pbuf, tp, nsrc, false, cs == 0);
+                pbuf ^= 1;
             }
         }
     }
