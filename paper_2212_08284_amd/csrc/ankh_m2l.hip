@@ -102,6 +102,24 @@ constexpr ILTable make_il_table() {
 }
 __constant__ ILTable c_il = make_il_table();
 
+// all 316 offsets d in [-3,3]^3 with |d|_inf >= 2 (the union of the class lists), lexicographic
+constexpr int kNumFar = 316;
+struct FarTable {
+    int v[kNumFar];
+};
+constexpr FarTable make_far_table() {
+    FarTable t{};
+    int k = 0;
+    for (int dx = -3; dx <= 3; dx++)
+        for (int dy = -3; dy <= 3; dy++)
+            for (int dz = -3; dz <= 3; dz++)
+                if (dx <= -2 || dx >= 2 || dy <= -2 || dy >= 2 || dz <= -2 || dz >= 2) t.v[k++] = off_index(dx, dy, dz);
+    return t;
+}
+__constant__ FarTable c_far = make_far_table();
+// offset d is in the interaction list of a cell with coordinate parity p along one axis
+__device__ inline bool in_list_1d(int d, int p) { return p ? d <= 2 : d >= -2; }
+
 // leaf-grid coordinates of the source cell of target cell (gx, gy, gz) at offset index di (periodic)
 __device__ inline size_t source_cell(int gx, int gy, int gz, int di, int nside) {
     const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
@@ -394,6 +412,136 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ K
     }
 }
 
+// ---- coarse levels (at most 64 cells): all cells in one column tile ---------
+// The 8 parity classes of a level with <= 8 cells per class would fill only 1 or
+// 8 of a tile's 64 columns.  Here the columns are the level's cells in natural
+// order and the contraction runs over the union of the class lists (316
+// offsets); a cell's column reads zero multipoles for the offsets outside its
+// own list, so each cell still sums exactly its 189 terms.  One offset slice
+// per block.
+template <int RF>
+__global__ __launch_bounds__(256) void k_m2l_bf16x3_all(const __bf16 *__restrict__ Kh, const __bf16 *__restrict__ Kl,
+                                                        const __bf16 *__restrict__ Mh, const __bf16 *__restrict__ Ml,
+                                                        double *__restrict__ out, int nside, int nup, int nsplit,
+                                                        int64_t out_stride) {
+    constexpr int BM = 32 * RF, BK = 32;
+    __shared__ __attribute__((aligned(16))) __bf16 Ash[2][BM * BK];
+    __shared__ __attribute__((aligned(16))) __bf16 Asl[2][BM * BK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bsh[2][BN * BK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bsl[2][BN * BK];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int ncell = nside * nside * nside;
+    const int nrt = (nup + BM - 1) / BM;
+    const int rt = blockIdx.x % nrt, split = blockIdx.x / nrt;
+    const int row0 = rt * BM;
+    const int o_begin = kNumFar * split / nsplit, o_end = kNumFar * (split + 1) / nsplit;
+
+    constexpr int NCA = BM * 4, LA = (NCA + NTHR - 1) / NTHR;
+    const int b_col = tid >> 2, b_c = tid & 3;
+    const bool b_ok = b_col < ncell;
+    const int gx = b_ok ? b_col / (nside * nside) : 0, gy = b_ok ? (b_col / nside) % nside : 0,
+              gz = b_ok ? b_col % nside : 0;
+    const int nk = nup / BK;
+    const int niter = (o_end - o_begin) * nk;
+    bf16x8 rah[LA], ral[LA], rbh, rbl;
+    const bf16x8 zero4 = {};
+    auto load = [&](int it) {
+        const int di = c_far.v[o_begin + it / nk], kb = it % nk;
+        const size_t base = ((size_t)di * nk + kb) * nup * BK;
+#pragma unroll
+        for (int u = 0; u < LA; u++) {
+            const int p = tid + NTHR * u;
+            const int r = p >> 2, c = p & 3;
+            if (p < NCA && row0 + r < nup) {
+                const size_t off = base + (size_t)(row0 + r) * BK + 8 * c;
+                rah[u] = *reinterpret_cast<const bf16x8 *>(Kh + off);
+                ral[u] = *reinterpret_cast<const bf16x8 *>(Kl + off);
+            } else {
+                rah[u] = zero4;
+                ral[u] = zero4;
+            }
+        }
+        const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
+        if (b_ok && in_list_1d(dx, gx & 1) && in_list_1d(dy, gy & 1) && in_list_1d(dz, gz & 1)) {
+            const size_t off = source_cell(gx, gy, gz, di, nside) * nup + kb * BK + 8 * b_c;
+            rbh = *reinterpret_cast<const bf16x8 *>(Mh + off);
+            rbl = *reinterpret_cast<const bf16x8 *>(Ml + off);
+        } else {
+            rbh = zero4;
+            rbl = zero4;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < LA; u++) {
+            const int p = tid + NTHR * u;
+            if (p < NCA) {
+                const int r = p >> 2, c = p & 3;
+                *reinterpret_cast<bf16x8 *>(&Ash[buf][swz(r, c)]) = rah[u];
+                *reinterpret_cast<bf16x8 *>(&Asl[buf][swz(r, c)]) = ral[u];
+            }
+        }
+        *reinterpret_cast<bf16x8 *>(&Bsh[buf][swz(b_col, b_c)]) = rbh;
+        *reinterpret_cast<bf16x8 *>(&Bsl[buf][swz(b_col, b_c)]) = rbl;
+    };
+
+    f32x4 acc[RF][2];
+#pragma unroll
+    for (int i = 0; i < RF; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0, 0, 0, 0};
+    if (niter > 0) {
+        load(0);
+        store(0);
+    }
+    __syncthreads();
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int it = 0; it < niter; it++) {
+        const int cur = it & 1;
+        if (it + 1 < niter) load(it + 1);
+        bf16x8 ah[RF], al[RF], bh[2], bl[2];
+#pragma unroll
+        for (int i = 0; i < RF; i++) {
+            const int r = wr * 16 * RF + i * 16 + lr;
+            ah[i] = *reinterpret_cast<const bf16x8 *>(&Ash[cur][swz(r, lk)]);
+            al[i] = *reinterpret_cast<const bf16x8 *>(&Asl[cur][swz(r, lk)]);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const int cl = wc * 32 + j * 16 + lr;
+            bh[j] = *reinterpret_cast<const bf16x8 *>(&Bsh[cur][swz(cl, lk)]);
+            bl[j] = *reinterpret_cast<const bf16x8 *>(&Bsl[cur][swz(cl, lk)]);
+        }
+#pragma unroll
+        for (int i = 0; i < RF; i++)
+#pragma unroll
+            for (int j = 0; j < 2; j++) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+        if (it + 1 < niter) store(cur ^ 1);
+        __syncthreads();
+    }
+    double *o = out + (size_t)split * out_stride;
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        const int cl = wc * 32 + j * 16 + lr;
+        if (cl >= ncell) continue;
+        double *Lc = o + (size_t)cl * nup;
+#pragma unroll
+        for (int i = 0; i < RF; i++) {
+            const int rb = row0 + wr * 16 * RF + i * 16;
+            if (rb >= nup) continue;
+#pragma unroll
+            for (int v = 0; v < 4; v++) Lc[rb + 4 * lk + v] = (double)acc[i][j][v];
+        }
+    }
+}
+
 // hi / lo bf16 split of a float64 array (via float32)
 __global__ void k_split_bf16(const double *__restrict__ s, __bf16 *__restrict__ hi, __bf16 *__restrict__ lo,
                              int64_t n) {
@@ -422,20 +570,26 @@ __global__ void k_split_K_bf16(const double *__restrict__ K, __bf16 *__restrict_
     lo[i] = (__bf16)(x - (float)a);
 }
 
-// L = sum over the split-K partials in a fixed order: four interleaved runs of
-// the slices (slice k in run k mod 4), each added in slice order, then the
-// four run sums
+// L = sum over the split-K partials in a fixed order: NR interleaved runs of
+// the slices (slice k in run k mod NR), each added in slice order, then the
+// NR run sums in run order.  256 threads = NR runs x (256 / NR) elements.
+template <int NR>
 __global__ __launch_bounds__(256) void k_m2l_reduce(const double *__restrict__ part, double *__restrict__ L,
                                                     int64_t n, int nsplit) {
-    __shared__ double red[4][64];
-    const int w = threadIdx.x >> 6, r = threadIdx.x & 63;
-    const int64_t i = blockIdx.x * (int64_t)64 + r;
+    constexpr int NE = 256 / NR;
+    __shared__ double red[NR][NE];
+    const int w = threadIdx.x / NE, r = threadIdx.x % NE;
+    const int64_t i = blockIdx.x * (int64_t)NE + r;
     double s = 0;
     if (i < n)
-        for (int k = w; k < nsplit; k += 4) s += part[k * n + i];
+        for (int k = w; k < nsplit; k += NR) s += part[k * n + i];
     red[w][r] = s;
     __syncthreads();
-    if (w == 0 && i < n) L[i] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+    if (w == 0 && i < n) {
+        double t = red[0][r];
+        for (int k = 1; k < NR; k++) t += red[k][r];
+        L[i] = t;
+    }
 }
 
 __global__ void k_f64_to_f32(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
@@ -467,6 +621,12 @@ int m2l_row_frags(int nup) {
     return best;
 }
 
+// Coarse levels of the split-precision mode (at most 64 cells) run all cells in
+// one column tile over the 316 offsets, one offset per slice.
+bool m2l_all_cells(const ankh_plan_s *pl, int e) {
+    return pl->precision == ANKH_MIXED_BF16X3 && pl->lv[e].ncell <= BN;
+}
+
 // Number of offset slices (split-K).  A level with >= 2048 block tiles runs
 // unsplit.  Otherwise a multiple of 8 (the XCD-aware block order then gives
 // every XCD whole slices), raised until the level launches >= 1024 blocks,
@@ -477,6 +637,7 @@ int m2l_splits(const ankh_plan_s *pl, int e) {
     const int bm = 32 * m2l_row_frags(pl->nup);
     const int64_t tiles = (int64_t)((pl->nup + bm - 1) / bm) * ((h * h * h + BN - 1) / BN) * 8;
     const int64_t ncell = pl->lv[e].ncell;
+    if (m2l_all_cells(pl, e)) return kNumFar;
     if (tiles >= 2048) return 1;
     int s = 8;
     while (tiles * s < 1024 && (s + 8) * ncell <= 32768 && s + 8 <= kNumIL) s += 8;
@@ -492,8 +653,13 @@ void launch_rf(ankh_plan_s *pl, int e, dim3 grid, double *out, int nsplit, int64
     if (pl->precision == ANKH_MIXED_BF16X3) {
         const __bf16 *Mh = pl->d_Mb, *Ml = pl->d_Mb + nval;
         const size_t kall = (size_t)pl->depth * kper;
-        hipLaunchKernelGGL(k_m2l_bf16x3<RF>, grid, dim3(NTHR), 0, pl->stream, pl->d_Kb + koff,
-                           pl->d_Kb + kall + koff, Mh, Ml, out, lv.nside, pl->nup, nsplit, nval);
+        if (m2l_all_cells(pl, e))
+            hipLaunchKernelGGL(k_m2l_bf16x3_all<RF>, dim3((unsigned)(((pl->nup + 32 * RF - 1) / (32 * RF)) * nsplit)),
+                               dim3(NTHR), 0, pl->stream, pl->d_Kb + koff, pl->d_Kb + kall + koff, Mh, Ml, out,
+                               lv.nside, pl->nup, nsplit, nval);
+        else
+            hipLaunchKernelGGL(k_m2l_bf16x3<RF>, grid, dim3(NTHR), 0, pl->stream, pl->d_Kb + koff,
+                               pl->d_Kb + kall + koff, Mh, Ml, out, lv.nside, pl->nup, nsplit, nval);
     } else if (pl->precision == ANKH_MIXED) {
         hipLaunchKernelGGL((k_m2l<float, RF>), grid, dim3(NTHR), 0, pl->stream, pl->d_Kf + koff, pl->d_Mf, out,
                            lv.nside, pl->nup, nsplit, nval);
@@ -528,8 +694,11 @@ hipError_t launch_m2l(ankh_plan_s *pl, int e) {
         case 7: launch_rf<7>(pl, e, grid, out, nsplit, nval); break;
         default: launch_rf<8>(pl, e, grid, out, nsplit, nval); break;
     }
-    if (nsplit > 1)
-        hipLaunchKernelGGL(k_m2l_reduce, dim3((unsigned)((nval + 63) / 64)), dim3(256), 0, pl->stream,
+    if (nsplit > 64)
+        hipLaunchKernelGGL(k_m2l_reduce<16>, dim3((unsigned)((nval + 15) / 16)), dim3(256), 0, pl->stream,
+                           pl->d_m2l_part, L, nval, nsplit);
+    else if (nsplit > 1)
+        hipLaunchKernelGGL(k_m2l_reduce<4>, dim3((unsigned)((nval + 63) / 64)), dim3(256), 0, pl->stream,
                            pl->d_m2l_part, L, nval, nsplit);
     return hipGetLastError();
 }
