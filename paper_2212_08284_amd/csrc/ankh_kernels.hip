@@ -343,6 +343,64 @@ __global__ __launch_bounds__(256) void k_m2m(const double *Mc, double *Mp, const
 }
 
 // ---- L2L: child local expansion (order Lc) += M2M^T of the parent's (order Lp) ----
+// The same with the 8 children side by side: each 1D pass runs over all
+// children at once (3 barriers per parent instead of 4 per child), and the x
+// pass sums the children in order.  Used when the buffers fit in 64 KiB.
+__global__ __launch_bounds__(256) void k_m2m8(const double *Mc, double *Mp, const double *Vg, int Lp, int Lc,
+                                              int nupc, int nupp, int ns_par) {
+    extern __shared__ double sm[];
+    const int nc = Lc * Lc * Lc, np = Lp * Lp * Lp;
+    const int n1 = Lc * Lc * Lp, n2 = Lc * Lp * Lp;
+    const int nbuf = max(nc, n2);
+    double *sV = sm;                 // [2][Lp][Lc]
+    double *b0 = sV + 2 * Lp * Lc;   // [8][nbuf]
+    double *b1 = b0 + 8 * nbuf;      // [8][n1]
+    const int tid = threadIdx.x;
+    for (int t = tid; t < 2 * Lp * Lc; t += 256) sV[t] = Vg[t];
+    const int64_t p = blockIdx.x;
+    const int px = (int)(p / ((int64_t)ns_par * ns_par)), py = (int)((p / ns_par) % ns_par), pz = (int)(p % ns_par);
+    const int nsc = 2 * ns_par;
+    const int VS = Lp * Lc;
+    for (int t = tid; t < 8 * nc; t += 256) {
+        const int bits = t / nc, e = t % nc;
+        const int bx = bits >> 2, by = (bits >> 1) & 1, bz = bits & 1;
+        const int64_t c = ((int64_t)(2 * px + bx) * nsc + (2 * py + by)) * nsc + (2 * pz + bz);
+        b0[bits * nbuf + e] = Mc[c * nupc + e];
+    }
+    __syncthreads();
+    for (int t = tid; t < 8 * n1; t += 256) {   // child, (i, j, cz)
+        const int bits = t / n1, u = t % n1;
+        const int ij = u / Lp, cz = u % Lp;
+        const double *Vz = sV + (bits & 1) * VS;
+        double s = 0;
+        for (int k = 0; k < Lc; k++) s += Vz[cz * Lc + k] * b0[bits * nbuf + ij * Lc + k];
+        b1[bits * n1 + u] = s;
+    }
+    __syncthreads();
+    for (int t = tid; t < 8 * n2; t += 256) {   // child, (i, cy, cz)
+        const int bits = t / n2, u = t % n2;
+        const int i = u / (Lp * Lp), cy = (u / Lp) % Lp, cz = u % Lp;
+        const double *Vy = sV + ((bits >> 1) & 1) * VS;
+        double s = 0;
+        for (int j = 0; j < Lc; j++) s += Vy[cy * Lc + j] * b1[bits * n1 + (i * Lc + j) * Lp + cz];
+        b0[bits * nbuf + u] = s;
+    }
+    __syncthreads();
+    for (int t = tid; t < nupp; t += 256) {
+        double acc = 0;
+        if (t < np) {
+            const int cx = t / (Lp * Lp), yz = t % (Lp * Lp);
+            for (int bits = 0; bits < 8; bits++) {
+                const double *Vx = sV + (bits >> 2) * VS;
+                double s = 0;
+                for (int i = 0; i < Lc; i++) s += Vx[cx * Lc + i] * b0[bits * nbuf + i * Lp * Lp + yz];
+                acc += s;
+            }
+        }
+        Mp[p * nupp + t] = acc;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_l2l(const double *Lpar, double *Lch, const double *Vg, int Lp, int Lc,
                                              int nupp, int nupc, int ns_child) {
     extern __shared__ double sm[];
@@ -754,8 +812,13 @@ hipError_t launch_m2m(ankh_plan_s *pl, int e_par) {
     const double *V = root ? pl->d_tab0 + pl->order0 : pl->d_tab + Lc + Lc * Lc;
     double *Mp = root ? pl->d_rootM : pl->d_M + P.cell0 * pl->nup;
     const int nupp = root ? pl->nup0 : pl->nup;
-    hipLaunchKernelGGL(k_m2m, dim3((unsigned)P.ncell), dim3(256), mlshm(Lp, Lc), pl->stream,
-                       pl->d_M + C.cell0 * pl->nup, Mp, V, Lp, Lc, pl->nup, nupp, P.nside);
+    const size_t shm8 = sizeof(double) * (2 * Lp * Lc + 8 * std::max(Lc * Lc * Lc, Lc * Lp * Lp) + 8 * Lc * Lc * Lp);
+    if (shm8 <= 65536)
+        hipLaunchKernelGGL(k_m2m8, dim3((unsigned)P.ncell), dim3(256), shm8, pl->stream,
+                           pl->d_M + C.cell0 * pl->nup, Mp, V, Lp, Lc, pl->nup, nupp, P.nside);
+    else
+        hipLaunchKernelGGL(k_m2m, dim3((unsigned)P.ncell), dim3(256), mlshm(Lp, Lc), pl->stream,
+                           pl->d_M + C.cell0 * pl->nup, Mp, V, Lp, Lc, pl->nup, nupp, P.nside);
     return hipGetLastError();
 }
 
