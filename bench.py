@@ -198,7 +198,9 @@ def main():
                 "note": "peak = 256 CU x 4 SIMD x 16 lanes x FMA x 2.4 GHz (unpacked FP32, as issued)"}
     m2l_roof = {"kernel": "m2l", "bound": "mfma", "achieved": m2l_tf, "peak": m2l_peak, "unit": "TFLOP/s",
                 "frac": m2l_tf / m2l_peak, "traffic": None, "flop_per_launch": m2l_flops, "avg_launch_ms": sm["m2l"],
-                "note": "algorithmic flops 2 * 189 * n_u^2 per cell over all levels; the BF16x3 split issues 3x"}
+                "note": "algorithmic flops per cell of level e: 2 * 189 * r_e^2 (r_e the kept rank of the compressed "
+                        "operators, n_u if uncompressed) + 4 * n_u * r_e for the basis change; the BF16x3 split issues 3x "
+                        "the contraction flops", "ranks": st_mixed.get("m2l_rank")}
     roof, other = (p2p_roof, m2l_roof) if sm["p2p"] >= sm["m2l"] else (m2l_roof, p2p_roof)
 
     line = {

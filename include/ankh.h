@@ -78,6 +78,9 @@ typedef struct {
     int32_t images;  /* image radius p: images I with |I|_inf <= p are summed */
     double xi;       /* Ewald splitting parameter (1/Angstrom) */
     int32_t root_order; /* order of the root grid that carries the far images, 2..12 (depth >= 1) */
+    double m2l_tol;     /* compressed M2L (the singular-value compression of the far-field operators):
+                           singular values above m2l_tol x the largest are kept; 0 = auto (0.1 x
+                           rel_accuracy, orders <= 7), NEGATIVE = no compression */
 } ankh_overrides;
 
 typedef struct {
@@ -87,7 +90,9 @@ typedef struct {
     double xi, box_radius, rel_accuracy;
     double plan_ms;            /* wall time of ankh_plan (operator tables included) */
     int64_t workspace_bytes;   /* device memory owned by the plan */
-    double m2l_flops;          /* algorithmic M2L flops per evaluation (2 * 189 * n_u^2 per cell) */
+    double m2l_flops;          /* algorithmic M2L flops per evaluation: 2 * 189 * r_e^2 per cell of level e
+                                  (r_e = the kept rank, n_u when uncompressed), plus 4 n_u r_e per cell
+                                  for the projection and expansion of compressed levels */
     int64_t near_pairs;        /* ordered near-field pairs of the last evaluation (-1 if unknown) */
     /* per-stage device time in ms (hipEvents on the plan's stream), averaged
        over the evaluations run since timing was last enabled with
@@ -97,6 +102,8 @@ typedef struct {
                10 reduce + unpermute */
     double stage_ms[11];
     int64_t timed_evals;       /* evaluations averaged into stage_ms */
+    int32_t m2l_rank[8];       /* kept rank of the M2L operators per level e = 1..depth (n_u when the
+                                  level is not compressed; 0 for e = 0 and e > depth) */
 } ankh_plan_stats;
 
 /*

@@ -173,10 +173,26 @@ def _valid_mask(n, d):
 
 # ---- evaluation --------------------------------------------------------------
 
+def m2l_projector(w: float, L: int, xi: float, rank: int) -> np.ndarray:
+    """Low-rank compression of the M2L operators of one level (the SVD
+    compression of the far-field operator in the compressed-M2L passage): P =
+    U U^T, U = the `rank` leading left singular vectors of the stack [K_d] over
+    all 316 offsets d with |d|_inf >= 2.  The compressed operator of offset d
+    is P K_d P (the stack is closed under transposition, K_-d = K_d^T, so the
+    right singular vectors span the same space)."""
+    offs = [d for d in itertools.product(range(-3, 4), repeat=3) if max(abs(c) for c in d) >= 2]
+    A = np.hstack([m2l_matrix(d, w, L, xi) for d in offs])
+    U = np.linalg.svd(A, full_matrices=False)[0][:, :rank]
+    return U @ U.T
+
+
 def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, p: int,
-             grad: bool = True, nthreads: int = 0, keep: bool = False, root_order: int | None = None) -> dict:
+             grad: bool = True, nthreads: int = 0, keep: bool = False, root_order: int | None = None,
+             m2l_ranks=None) -> dict:
     """root_order: Chebyshev order of the root grid that carries the far
-    images (depth >= 1); defaults to `order`."""
+    images (depth >= 1); defaults to `order`.  m2l_ranks: optional rank per
+    level (index e = 1..depth; a rank >= L^3 or 0 leaves the level
+    uncompressed) of the compressed M2L operators."""
     pos = wrap(_c64(pos, (-1, 3)), edge)
     N = pos.shape[0]
     q = _c64(q, (N,))
@@ -239,8 +255,12 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
         n = 1 << e
         w = edge / n
         acc = np.zeros((n, n, n, nu))
+        r = 0 if m2l_ranks is None else int(m2l_ranks[e])
+        P = m2l_projector(w, L, xi, r) if 0 < r < nu else None
         for d in offs:
             K = m2l_matrix(d, w, L, xi)
+            if P is not None:
+                K = P @ K @ P
             Ms = np.roll(M[e], shift=(-d[0], -d[1], -d[2]), axis=(0, 1, 2))
             acc += _valid_mask(n, d)[..., None] * (Ms @ K.T)
         Lloc[e] = acc

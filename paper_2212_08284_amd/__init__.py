@@ -41,7 +41,7 @@ class AnkhError(RuntimeError):
 
 class _Overrides(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("order", ctypes.c_int32), ("images", ctypes.c_int32),
-                ("xi", ctypes.c_double), ("root_order", ctypes.c_int32)]
+                ("xi", ctypes.c_double), ("root_order", ctypes.c_int32), ("m2l_tol", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -49,7 +49,8 @@ class _Stats(ctypes.Structure):
                 ("images", ctypes.c_int32), ("max_order", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("root_order", ctypes.c_int32), ("xi", ctypes.c_double), ("box_radius", ctypes.c_double), ("rel_accuracy", ctypes.c_double),
                 ("plan_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_int64), ("m2l_flops", ctypes.c_double),
-                ("near_pairs", ctypes.c_int64), ("stage_ms", ctypes.c_double * len(STAGES)), ("timed_evals", ctypes.c_int64)]
+                ("near_pairs", ctypes.c_int64), ("stage_ms", ctypes.c_double * len(STAGES)), ("timed_evals", ctypes.c_int64),
+                ("m2l_rank", ctypes.c_int32 * 8)]
 
 
 _lib = None
@@ -117,14 +118,16 @@ def _dev(t, n_cols, n, name, optional=False):
 
 def ankh_plan(n_atoms: int, box_radius: float, rel_accuracy: float, max_order: int = 2,
               precision: int = ANKH_FP64, depth: int | None = None, order: int | None = None,
-              images: int | None = None, xi: float | None = None, root_order: int | None = None, stream=None):
-    """Create a plan; returns the opaque handle (ctypes.c_void_p)."""
+              images: int | None = None, xi: float | None = None, root_order: int | None = None,
+              m2l_tol: float | None = None, stream=None):
+    """Create a plan; returns the opaque handle (ctypes.c_void_p).  m2l_tol: singular-value cutoff of the
+    compressed M2L (None = automatic, negative = no compression)."""
     L = load_library()
     if not torch.cuda.is_available():
         raise RuntimeError("no GPU: the interpolated-Ewald library runs on the GPU only")
     ov = _Overrides(-1 if depth is None else int(depth), 0 if order is None else int(order),
                     0 if images is None else int(images), 0.0 if xi is None else float(xi),
-                    0 if root_order is None else int(root_order))
+                    0 if root_order is None else int(root_order), 0.0 if m2l_tol is None else float(m2l_tol))
     if stream is None:
         stream = torch.cuda.current_stream()
     h = ctypes.c_void_p()
@@ -148,7 +151,8 @@ def ankh_sync(plan):
 def ankh_get_stats(plan) -> dict:
     s = _Stats()
     _check(load_library().ankh_get_stats(plan, ctypes.byref(s)), "ankh_get_stats")
-    d = {f: getattr(s, f) for f, _ in _Stats._fields_ if f != "stage_ms"}
+    d = {f: getattr(s, f) for f, _ in _Stats._fields_ if f not in ("stage_ms", "m2l_rank")}
+    d["m2l_rank"] = [s.m2l_rank[i] for i in range(8)]
     d["stage_ms"] = {STAGES[i]: s.stage_ms[i] for i in range(len(STAGES))}
     return d
 
@@ -187,13 +191,13 @@ class Plan:
     """A plan for n atoms in a cubic box of half-edge box_radius (see ankh.h)."""
 
     def __init__(self, n_atoms, box_radius, rel_accuracy=1e-6, max_order=2, precision="fp64", depth=None,
-                 order=None, images=None, xi=None, root_order=None, stream=None):
+                 order=None, images=None, xi=None, root_order=None, m2l_tol=None, stream=None):
         prec = ({"fp64": ANKH_FP64, "mixed": ANKH_MIXED, "mixed_bf16x3": ANKH_MIXED_BF16X3}[precision]
                 if isinstance(precision, str) else int(precision))
         self.n = int(n_atoms)
         self.max_order = int(max_order)
         self.handle = ankh_plan(n_atoms, box_radius, rel_accuracy, max_order, prec, depth, order, images, xi,
-                                root_order, stream)
+                                root_order, m2l_tol, stream)
         self.stats = ankh_get_stats(self.handle)
 
     def _args(self, pos, q, mu, theta):

@@ -89,6 +89,13 @@ struct ankh_plan_s {
     __bf16 *d_Kb = nullptr;       // bf16 hi parts of all levels' K (row-major K_d[k][l]), then the lo parts
     __bf16 *d_Mb = nullptr;       // bf16 hi / lo split of one level's multipoles
     double *d_m2l_part = nullptr; // split-K partial local expansions of one level
+    // compressed M2L, per level e >= 1: kept rank, padded rank (n_up when the level is
+    // uncompressed), basis U [n_up][rpad] at d_U + u_off[e], compressed multipoles and
+    // locals [cells][rpad] at d_Mc / d_Lc + c_off[e]
+    int m2l_rank[ankh::kMaxDepth + 1] = {};
+    int rpad[ankh::kMaxDepth + 1] = {};
+    size_t u_off[ankh::kMaxDepth + 1] = {}, c_off[ankh::kMaxDepth + 1] = {};
+    double *d_U = nullptr, *d_Mc = nullptr, *d_Lc = nullptr;
     double *d_Cper = nullptr;     // far-image root operator [nup0][nup0]
     double *d_cper_part = nullptr;// its column-slice partial products [kCperSlices][nup0]
     double *d_eatom = nullptr;    // near-field energy per leaf-order atom
@@ -133,7 +140,11 @@ hipError_t launch_unpermute(ankh_plan_s *pl, double *forces, double *dEdmu, bool
 hipError_t launch_m2l(ankh_plan_s *pl, int e);
 int m2l_splits(const ankh_plan_s *pl, int e);
 int m2l_row_frags(int nup);
-hipError_t launch_split_K_bf16(ankh_plan_s *pl, const double *K, __bf16 *hi, __bf16 *lo);
+hipError_t launch_split_K_bf16(ankh_plan_s *pl, const double *K, __bf16 *hi, __bf16 *lo, int nr);
+hipError_t compress_level(ankh_plan_s *pl, int e, const double *K, double *Kc, double *work, double tol);
+hipError_t launch_m2l_basis(ankh_plan_s *pl, bool expand);
+hipError_t launch_m2l_project(ankh_plan_s *pl);   // all compressed levels: Mc = M U
+hipError_t launch_m2l_expand(ankh_plan_s *pl);    // all compressed levels: L = Lc U^T
 inline bool is_mixed(const ankh_plan_s *pl) { return pl->precision != ANKH_FP64; }
 hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields);
 hipError_t launch_p2p_sum(ankh_plan_s *pl, bool grad, bool fields);

@@ -599,20 +599,21 @@ __global__ void k_f64_to_f32(const double *__restrict__ s, float *__restrict__ d
 
 }  // namespace
 
-hipError_t launch_split_K_bf16(ankh_plan_s *pl, const double *K, __bf16 *hi, __bf16 *lo) {
-    const int64_t n = (int64_t)kNumOff * pl->nup * pl->nup;
-    hipLaunchKernelGGL(k_split_K_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pl->stream, K, hi, lo, pl->nup);
+hipError_t launch_split_K_bf16(ankh_plan_s *pl, const double *K, __bf16 *hi, __bf16 *lo, int nr) {
+    const int64_t n = (int64_t)kNumOff * nr * nr;
+    hipLaunchKernelGGL(k_split_K_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pl->stream, K, hi, lo, nr);
     return hipGetLastError();
 }
 
-// Rows of the output block tile, 32 RF with RF in {2, 4, 7, 8}: the height
-// that pads n_u least (the taller one on ties).
-int m2l_row_frags(int nup) {
+// Rows of the output block tile, 32 RF with RF in 2..8: the height that pads
+// the operand size n (n_up, or the padded rank of a compressed level) least,
+// the taller one on ties.
+int m2l_row_frags(int n) {
     int best = 2;
     int64_t best_pad = INT64_MAX;
-    for (int rf : {8, 7, 4, 2}) {
+    for (int rf : {8, 7, 6, 5, 4, 3, 2}) {
         const int bm = 32 * rf;
-        const int64_t pad = (int64_t)((nup + bm - 1) / bm) * bm;
+        const int64_t pad = (int64_t)((n + bm - 1) / bm) * bm;
         if (pad < best_pad) {
             best_pad = pad;
             best = rf;
@@ -630,23 +631,27 @@ bool m2l_all_cells(const ankh_plan_s *pl, int e) {
 // Number of offset slices (split-K).  A level with >= 2048 block tiles runs
 // unsplit.  Otherwise a multiple of 8 (the XCD-aware block order then gives
 // every XCD whole slices), raised until the level launches >= 1024 blocks,
-// while the partial tiles stay within 32768 cells x n_u and every slice keeps
-// at least one offset.
+// while the partial tiles stay within 32768 cells x 224 values and every slice
+// keeps at least one offset.
 int m2l_splits(const ankh_plan_s *pl, int e) {
     const int h = pl->lv[e].nside / 2;
-    const int bm = 32 * m2l_row_frags(pl->nup);
-    const int64_t tiles = (int64_t)((pl->nup + bm - 1) / bm) * ((h * h * h + BN - 1) / BN) * 8;
+    const int n = pl->rpad[e];
+    const int bm = 32 * m2l_row_frags(n);
+    const int64_t tiles = (int64_t)((n + bm - 1) / bm) * ((h * h * h + BN - 1) / BN) * 8;
     const int64_t ncell = pl->lv[e].ncell;
     if (m2l_all_cells(pl, e)) return kNumFar;
     if (tiles >= 2048) return 1;
     int s = 8;
-    while (tiles * s < 1024 && (s + 8) * ncell <= 32768 && s + 8 <= kNumIL) s += 8;
+    while (tiles * s < 1024 && (s + 8) * ncell * n <= (int64_t)32768 * 224 && s + 8 <= kNumIL) s += 8;
     return s;
 }
 
 namespace {
+// one level's contraction: operand size n (rows and contraction per offset), source
+// multipoles M [cells][n] (float64), K stack of the level at its slot
 template <int RF>
-void launch_rf(ankh_plan_s *pl, int e, dim3 grid, double *out, int nsplit, int64_t nval) {
+void launch_rf(ankh_plan_s *pl, int e, dim3 grid, int n, const double *Msrc, double *out, int nsplit,
+               int64_t nval) {
     const ankh::Level &lv = pl->lv[e];
     const size_t kper = (size_t)kNumOff * pl->nup * pl->nup;
     const size_t koff = (size_t)(e - 1) * kper;
@@ -654,18 +659,18 @@ void launch_rf(ankh_plan_s *pl, int e, dim3 grid, double *out, int nsplit, int64
         const __bf16 *Mh = pl->d_Mb, *Ml = pl->d_Mb + nval;
         const size_t kall = (size_t)pl->depth * kper;
         if (m2l_all_cells(pl, e))
-            hipLaunchKernelGGL(k_m2l_bf16x3_all<RF>, dim3((unsigned)(((pl->nup + 32 * RF - 1) / (32 * RF)) * nsplit)),
+            hipLaunchKernelGGL(k_m2l_bf16x3_all<RF>, dim3((unsigned)(((n + 32 * RF - 1) / (32 * RF)) * nsplit)),
                                dim3(NTHR), 0, pl->stream, pl->d_Kb + koff, pl->d_Kb + kall + koff, Mh, Ml, out,
-                               lv.nside, pl->nup, nsplit, nval);
+                               lv.nside, n, nsplit, nval);
         else
             hipLaunchKernelGGL(k_m2l_bf16x3<RF>, grid, dim3(NTHR), 0, pl->stream, pl->d_Kb + koff,
-                               pl->d_Kb + kall + koff, Mh, Ml, out, lv.nside, pl->nup, nsplit, nval);
+                               pl->d_Kb + kall + koff, Mh, Ml, out, lv.nside, n, nsplit, nval);
     } else if (pl->precision == ANKH_MIXED) {
         hipLaunchKernelGGL((k_m2l<float, RF>), grid, dim3(NTHR), 0, pl->stream, pl->d_Kf + koff, pl->d_Mf, out,
-                           lv.nside, pl->nup, nsplit, nval);
+                           lv.nside, n, nsplit, nval);
     } else {
-        hipLaunchKernelGGL((k_m2l<double, RF>), grid, dim3(NTHR), 0, pl->stream, pl->d_K + koff,
-                           pl->d_M + lv.cell0 * pl->nup, out, lv.nside, pl->nup, nsplit, nval);
+        hipLaunchKernelGGL((k_m2l<double, RF>), grid, dim3(NTHR), 0, pl->stream, pl->d_K + koff, Msrc, out,
+                           lv.nside, n, nsplit, nval);
     }
 }
 }  // namespace
@@ -674,32 +679,43 @@ hipError_t launch_m2l(ankh_plan_s *pl, int e) {
     const ankh::Level &lv = pl->lv[e];
     const int h = lv.nside / 2;
     const int ncls = h * h * h;
+    const int n = pl->rpad[e];
+    const bool comp = n < pl->nup;
     const int nsplit = m2l_splits(pl, e);
-    const int rf = m2l_row_frags(pl->nup);
+    const int rf = m2l_row_frags(n);
     const int bm = 32 * rf;
-    dim3 grid((unsigned)(((pl->nup + bm - 1) / bm) * ((ncls + BN - 1) / BN) * 8 * nsplit));
-    const int64_t nval = lv.ncell * pl->nup;
+    dim3 grid((unsigned)(((n + bm - 1) / bm) * ((ncls + BN - 1) / BN) * 8 * nsplit));
+    const int64_t nval = lv.ncell * n;
     double *L = pl->d_L + lv.cell0 * pl->nup;
-    double *out = nsplit > 1 ? pl->d_m2l_part : L;
+    const double *M = pl->d_M + lv.cell0 * pl->nup;
+    // compressed levels contract in the rank-n basis: M' = M U (projected for all
+    // levels before the first contraction), L = L' U^T (after the last)
+    double *Msrc = comp ? pl->d_Mc + pl->c_off[e] : const_cast<double *>(M);
+    double *Ldst = comp ? pl->d_Lc + pl->c_off[e] : L;
+    hipError_t err;
+    double *out = nsplit > 1 ? pl->d_m2l_part : Ldst;
     // this level's multipoles in the working precision of the contraction
     if (pl->precision == ANKH_MIXED_BF16X3)
-        hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream,
-                           pl->d_M + lv.cell0 * pl->nup, pl->d_Mb, pl->d_Mb + nval, nval);
+        hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream, Msrc,
+                           pl->d_Mb, pl->d_Mb + nval, nval);
     else if (pl->precision == ANKH_MIXED)
-        hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream,
-                           pl->d_M + lv.cell0 * pl->nup, pl->d_Mf, nval);
+        hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream, Msrc,
+                           pl->d_Mf, nval);
     switch (rf) {
-        case 2: launch_rf<2>(pl, e, grid, out, nsplit, nval); break;
-        case 4: launch_rf<4>(pl, e, grid, out, nsplit, nval); break;
-        case 7: launch_rf<7>(pl, e, grid, out, nsplit, nval); break;
-        default: launch_rf<8>(pl, e, grid, out, nsplit, nval); break;
+        case 2: launch_rf<2>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
+        case 3: launch_rf<3>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
+        case 4: launch_rf<4>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
+        case 5: launch_rf<5>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
+        case 6: launch_rf<6>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
+        case 7: launch_rf<7>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
+        default: launch_rf<8>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
     }
     if (nsplit > 64)
         hipLaunchKernelGGL(k_m2l_reduce<16>, dim3((unsigned)((nval + 15) / 16)), dim3(256), 0, pl->stream,
-                           pl->d_m2l_part, L, nval, nsplit);
+                           pl->d_m2l_part, Ldst, nval, nsplit);
     else if (nsplit > 1)
         hipLaunchKernelGGL(k_m2l_reduce<4>, dim3((unsigned)((nval + 63) / 64)), dim3(256), 0, pl->stream,
-                           pl->d_m2l_part, L, nval, nsplit);
+                           pl->d_m2l_part, Ldst, nval, nsplit);
     return hipGetLastError();
 }
 

@@ -45,7 +45,8 @@ void free_all(ankh_plan_s *pl) {
                     pl->d_M, pl->d_L, pl->d_K, pl->d_Kf, pl->d_Cper, pl->d_eatom, pl->d_eleaf, pl->d_F,
                     pl->d_G, pl->d_terms, pl->d_part, pl->d_err, pl->d_tab0, pl->d_Mf, pl->d_m2l_part,
                     pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr,
-                    pl->d_Kb, pl->d_Mb, pl->d_slot_e, pl->d_slot_f, pl->d_slot_g, pl->d_cper_part};
+                    pl->d_Kb, pl->d_Mb, pl->d_slot_e, pl->d_slot_f, pl->d_slot_g, pl->d_cper_part,
+                    pl->d_U, pl->d_Mc, pl->d_Lc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &set : pl->evsets)
@@ -136,7 +137,9 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
         mark(3);
         for (int e = pl->depth - 1; e >= 0; e--) ck(launch_m2m(pl, e));
         mark(4);
+        ck(launch_m2l_project(pl));
         for (int e = 1; e <= pl->depth; e++) ck(launch_m2l(pl, e));
+        ck(launch_m2l_expand(pl));
         mark(5);
         ck(launch_cper(pl));
         mark(6);
@@ -201,6 +204,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         if (ov->root_order > 0 && (ov->root_order < 2 || ov->root_order > kMaxRootOrder)) return ANKH_ERR_INVALID_ARG;
         if (ov->images > 64) return ANKH_ERR_INVALID_ARG;
         if (!std::isfinite(ov->xi)) return ANKH_ERR_INVALID_ARG;
+        if (!std::isfinite(ov->m2l_tol) || ov->m2l_tol >= 1) return ANKH_ERR_INVALID_ARG;
     }
     auto t0 = std::chrono::steady_clock::now();
     ankh_plan_s *pl = new (std::nothrow) ankh_plan_s();
@@ -311,18 +315,6 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         }
         dalloc(pl, &pl->d_M, cells * pl->nup);
         dalloc(pl, &pl->d_L, cells * pl->nup);
-        {
-            // M2L scratch: split-K partials and (mixed mode) a float32 copy of one level's multipoles
-            size_t part = 0;
-            for (int e = 1; e <= pl->depth; e++) {
-                const int s = m2l_splits(pl, e);
-                if (s > 1) part = std::max(part, (size_t)s * pl->lv[e].ncell * pl->nup);
-            }
-            if (part) dalloc(pl, &pl->d_m2l_part, part);
-            if (precision == ANKH_MIXED && pl->depth >= 1) dalloc(pl, &pl->d_Mf, pl->lv[pl->depth].ncell * pl->nup);
-            if (precision == ANKH_MIXED_BF16X3 && pl->depth >= 1)
-                dalloc(pl, &pl->d_Mb, 2 * pl->lv[pl->depth].ncell * pl->nup);
-        }
         const size_t kper = (size_t)kNumOff * pl->nup * pl->nup;
         dalloc(pl, &pl->d_Cper, (size_t)pl->nup0 * pl->nup0);
         dalloc(pl, &pl->d_cper_part, (size_t)kCperSlices * pl->nup0);
@@ -359,30 +351,74 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         ck(launch_zero_f64(pl->d_terms, 8, pl->stream));
         ck(launch_zero_f64(pl->d_G, 3 * n, pl->stream));
         ck(launch_zero_f64(pl->d_eatom, n, pl->stream));
-        // operator tables: M2L matrices of levels 1..E and the far-image root operator
+        // operator tables: M2L matrices of levels 1..E (each built in float64, compressed
+        // when that pays, then kept in the working precision) and the far-image root operator
+        for (int e = 0; e <= pl->depth; e++) {
+            pl->rpad[e] = pl->nup;
+            pl->m2l_rank[e] = e >= 1 ? pl->nu : 0;
+        }
         if (pl->depth >= 1) {
-            if (precision != ANKH_FP64) {
-                // build each level in float64, then keep the float32 or bf16 hi/lo form
-                const bool bf = precision == ANKH_MIXED_BF16X3;
-                if (bf) dalloc(pl, &pl->d_Kb, 2 * kper * pl->depth);
-                else dalloc(pl, &pl->d_Kf, kper * pl->depth);
-                double *tmp = nullptr;
-                ck(hipMalloc((void **)&tmp, kper * sizeof(double)));
-                for (int e = 1; e <= pl->depth; e++) {
-                    ck(launch_build_m2l(pl, e, tmp));
-                    if (bf)
-                        ck(launch_split_K_bf16(pl, tmp, pl->d_Kb + (size_t)(e - 1) * kper,
-                                               pl->d_Kb + (size_t)pl->depth * kper + (size_t)(e - 1) * kper));
-                    else
-                        ck(launch_convert_f32(tmp, pl->d_Kf + (size_t)(e - 1) * kper, (int64_t)kper, pl->stream));
+            const double tol = (ov && ov->m2l_tol != 0) ? ov->m2l_tol : 0.1 * rel_accuracy;
+            const bool compress = tol > 0 && pl->nu <= 400;
+            const bool bf = precision == ANKH_MIXED_BF16X3;
+            if (precision == ANKH_FP64) dalloc(pl, &pl->d_K, kper * pl->depth);
+            else if (bf) dalloc(pl, &pl->d_Kb, 2 * kper * pl->depth);
+            else dalloc(pl, &pl->d_Kf, kper * pl->depth);
+            if (compress) {
+                dalloc(pl, &pl->d_U, (size_t)pl->depth * pl->nup * pl->nup);
+                for (int e = 1; e <= pl->depth; e++) pl->u_off[e] = (size_t)(e - 1) * pl->nup * pl->nup;
+            }
+            // scratch: the full float64 stack of a level, and room for the compression's
+            // intermediate products or the compressed float64 stack
+            double *tmp = nullptr, *work = nullptr, *kc = nullptr;
+            ck(hipMalloc((void **)&tmp, kper * sizeof(double)));
+            if (compress) ck(hipMalloc((void **)&work, kper * sizeof(double)));
+            if (compress && precision != ANKH_FP64) ck(hipMalloc((void **)&kc, kper * sizeof(double)));
+            for (int e = 1; e <= pl->depth; e++) {
+                const size_t slot = (size_t)(e - 1) * kper;
+                ck(launch_build_m2l(pl, e, tmp));
+                const double *full = tmp;
+                if (compress) {
+                    double *dst = precision == ANKH_FP64 ? pl->d_K + slot : kc;
+                    ck(compress_level(pl, e, tmp, dst, work, tol));
+                    if (pl->rpad[e] < pl->nup) full = dst;
+                }
+                const int nr = pl->rpad[e];
+                const size_t cnt = (size_t)kNumOff * nr * nr;
+                if (precision == ANKH_FP64) {
+                    if (full == tmp) ck(hipMemcpyAsync(pl->d_K + slot, tmp, cnt * sizeof(double),
+                                                       hipMemcpyDeviceToDevice, pl->stream));
+                } else if (bf) {
+                    ck(launch_split_K_bf16(pl, full, pl->d_Kb + slot, pl->d_Kb + (size_t)pl->depth * kper + slot, nr));
+                } else {
+                    ck(launch_convert_f32(full, pl->d_Kf + slot, (int64_t)cnt, pl->stream));
                 }
                 ck(hipStreamSynchronize(pl->stream));
-                ck(hipFree(tmp));
-            } else {
-                dalloc(pl, &pl->d_K, kper * pl->depth);
-                for (int e = 1; e <= pl->depth; e++)
-                    ck(launch_build_m2l(pl, e, pl->d_K + (size_t)(e - 1) * kper));
             }
+            ck(hipFree(tmp));
+            if (work) ck(hipFree(work));
+            if (kc) ck(hipFree(kc));
+            // compressed multipoles / locals of the compressed levels
+            size_t coff = 0;
+            for (int e = 1; e <= pl->depth; e++) {
+                pl->c_off[e] = coff;
+                if (pl->rpad[e] < pl->nup) coff += (size_t)pl->lv[e].ncell * pl->rpad[e];
+            }
+            if (coff) {
+                dalloc(pl, &pl->d_Mc, coff);
+                dalloc(pl, &pl->d_Lc, coff);
+            }
+            // M2L scratch: split-K partials and one level's multipoles in the working precision
+            size_t part = 0, mlev = 0;
+            for (int e = 1; e <= pl->depth; e++) {
+                const size_t nv = (size_t)pl->lv[e].ncell * pl->rpad[e];
+                const int sp = m2l_splits(pl, e);
+                if (sp > 1) part = std::max(part, (size_t)sp * nv);
+                mlev = std::max(mlev, nv);
+            }
+            if (part) dalloc(pl, &pl->d_m2l_part, part);
+            if (precision == ANKH_MIXED) dalloc(pl, &pl->d_Mf, mlev);
+            if (bf) dalloc(pl, &pl->d_Mb, 2 * mlev);
         }
         ck(launch_build_cper(pl));
         ck(hipStreamSynchronize(pl->stream));
@@ -452,9 +488,13 @@ ankh_status ankh_get_stats(ankh_plan_t pl, ankh_plan_stats *out) {
     out->rel_accuracy = pl->eps;
     out->plan_ms = pl->plan_ms;
     out->workspace_bytes = (int64_t)pl->bytes;
-    double cells = 0;
-    for (int e = 1; e <= pl->depth; e++) cells += (double)pl->lv[e].ncell;
-    out->m2l_flops = 2.0 * kNumIL * (double)pl->nu * pl->nu * cells;
+    out->m2l_flops = 0;
+    for (int e = 1; e <= pl->depth; e++) {
+        const double r = pl->m2l_rank[e], ncell = (double)pl->lv[e].ncell;
+        out->m2l_flops += 2.0 * kNumIL * r * r * ncell;
+        if (r < pl->nu) out->m2l_flops += 4.0 * pl->nu * r * ncell;
+    }
+    for (int e = 0; e < 8; e++) out->m2l_rank[e] = (e >= 1 && e <= pl->depth) ? pl->m2l_rank[e] : 0;
     out->near_pairs = -1;
     if (pl->last_kind) {
         std::vector<int32_t> offs(pl->nleaf + 1);

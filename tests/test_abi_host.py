@@ -69,7 +69,8 @@ def test_plan_rejects_invalid_arguments(lib, kw):
 def test_plan_rejects_bad_overrides(lib):
     import paper_2212_08284_amd as ak
     for ov in (ak._Overrides(9, 0, 0, 0.0), ak._Overrides(-1, 1, 0, 0.0), ak._Overrides(-1, 11, 0, 0.0),
-               ak._Overrides(-1, 0, 99, 0.0), ak._Overrides(-1, 0, 0, float("inf"))):
+               ak._Overrides(-1, 0, 99, 0.0), ak._Overrides(-1, 0, 0, float("inf")),
+               ak._Overrides(-1, 0, 0, 0.0, 0, 2.0), ak._Overrides(-1, 0, 0, 0.0, 0, float("nan"))):
         st, h = _plan(lib, ov=ov)
         assert st == 1 and not h.value
 

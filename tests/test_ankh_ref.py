@@ -160,3 +160,24 @@ def test_geometric_convergence_to_ewald():
     # depth consistency: depth 0 and depth 1 agree within the approximation error
     r0 = R.evaluate(d["pos"], d["q"], d["mu"], d["theta"], edge, 0, 6, xi, p, grad=False)
     assert abs(r0["energy"] - ex["energy"]) < 2e-6 * abs(ex["energy"])
+
+
+def test_m2l_projector_pins():
+    """Compressed M2L: P is the orthogonal projector on the leading singular subspace of the stacked
+    operators; full rank reproduces every operator, and the truncation error of the stack equals the
+    first dropped singular value (Eckart-Young, spectral norm)."""
+    L, w, xi = 4, 6.0, 0.05
+    nu = L ** 3
+    offs = [d for d in itertools.product(range(-3, 4), repeat=3) if max(abs(c) for c in d) >= 2]
+    A = np.hstack([R.m2l_matrix(d, w, L, xi) for d in offs])
+    s = np.linalg.svd(A, compute_uv=False)
+    P = R.m2l_projector(w, L, xi, nu)
+    assert np.max(np.abs(P - np.eye(nu))) < 1e-10
+    r = 20
+    P = R.m2l_projector(w, L, xi, r)
+    assert np.max(np.abs(P @ P - P)) < 1e-12 and np.max(np.abs(P - P.T)) < 1e-14
+    err = np.linalg.norm(A - P @ A, 2)
+    assert abs(err - s[r]) <= 1e-8 * s[0]
+    # K_-d = K_d^T: the projected stack of transposes loses the same
+    At = np.hstack([R.m2l_matrix(d, w, L, xi).T for d in offs])
+    assert abs(np.linalg.norm(At - P @ At, 2) - s[r]) <= 1e-8 * s[0]

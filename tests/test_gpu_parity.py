@@ -66,7 +66,7 @@ def _run(ak, d, eps=1e-6, prec="fp64", **ov):
                                                    (2, 3, 5, "q"), (3, 4, 4, "qm")])
 def test_stage_parity_with_reference(ak, depth, order, root, kind):
     d = _system(kind)
-    pl, e, F, G = _run(ak, d, depth=depth, order=order, images=4, root_order=root)
+    pl, e, F, G = _run(ak, d, depth=depth, order=order, images=4, root_order=root, m2l_tol=-1.0)
     st = pl.stats
     terms = pl.last_terms()
     Q = pl.leaf_multipoles()
@@ -92,7 +92,7 @@ def test_stage_parity_with_reference(ak, depth, order, root, kind):
 def test_stage_parity_high_order(ak):
     """Order 8 (512 nodes per cell): the tallest far-field tile shape."""
     d = _system("q")
-    pl, e, F, G = _run(ak, d, depth=2, order=8, images=2, root_order=8)
+    pl, e, F, G = _run(ak, d, depth=2, order=8, images=2, root_order=8, m2l_tol=-1.0)
     st = pl.stats
     terms = pl.last_terms()
     r = ankh_ref.evaluate(d["pos"], d["q"], d["mu"], d["theta"], d["edge"], st["depth"], st["order"], st["xi"],
@@ -101,6 +101,37 @@ def test_stage_parity_high_order(ak):
     assert abs(terms["far_levels"] - sum(r["e_far_levels"])) <= 1e-12 * scale
     assert abs(e - r["energy"]) <= 1e-12 * scale
     assert rel_rms(F, r["forces"]) <= 1e-11
+    pl.close()
+
+
+@pytest.mark.parametrize("depth,order,kind", [(2, 6, "qmt"), (3, 6, "qm")])
+def test_stage_parity_compressed_m2l(ak, depth, order, kind):
+    """Compressed M2L (singular-value cutoff tau = 1e-7) against the NumPy transcription with the same
+    ranks.  The library takes its basis from the eigenvectors of sum_d A_d A_d^T (float64 Jacobi), the
+    transcription from numpy's SVD of the stack.  Both are valid rank-r compressions, but directions whose
+    singular values lie near the cutoff (within the Gram matrix's resolution, or in a cluster that the
+    cutoff splits) are chosen differently; they carry ~tau of the operator.  So the two agree to O(tau) of
+    the far field, not to rounding: far energies within 2 tau |E_far|, forces and fields within 10 tau.
+    A wrong basis, projection or transposition would miss these by orders of magnitude."""
+    tau = 1e-7
+    d = _system(kind)
+    pl, e, F, G = _run(ak, d, depth=depth, order=order, images=4, root_order=max(order, 4), m2l_tol=tau)
+    st = pl.stats
+    ranks = st["m2l_rank"]
+    assert all(0 < ranks[l] < order ** 3 for l in range(1, depth + 1))
+    terms = pl.last_terms()
+    r = ankh_ref.evaluate(d["pos"], d["q"], d["mu"], d["theta"], d["edge"], st["depth"], st["order"], st["xi"],
+                          st["images"], grad=True, root_order=st["root_order"], m2l_ranks=ranks)
+    far = abs(sum(r["e_far_levels"])) + 1.0
+    assert abs(terms["far_levels"] - sum(r["e_far_levels"])) <= 2 * tau * far
+    assert abs(e - r["energy"]) <= 2 * tau * far
+    assert rel_rms(F, r["forces"]) <= 10 * tau
+    if d["mu"] is not None:
+        assert rel_rms(G, r["dEdmu"]) <= 10 * tau
+    # the near field, self and periodic terms are untouched by the compression
+    scale = abs(r["e_near"]) + abs(r["e_self"]) + 1.0
+    assert abs(terms["near"] - r["e_near"]) <= 1e-12 * scale
+    assert abs(terms["periodic"] - r["e_per"]) <= 1e-12 * scale
     pl.close()
 
 
