@@ -95,6 +95,23 @@ def timed_run(plan, args_dev, steps, warmup, torch):
     return dt, stats, out
 
 
+def induce_run(plan, args_dev, alpha, tol, torch, dev, reps=3):
+    """Induced dipoles of the water polarisabilities: wall time of whole solves (the permanent
+    field, the conjugate-gradient products, the final energy and forces), inputs resident."""
+    a = torch.tensor(alpha, dtype=torch.float64, device=dev)
+    plan.induce(*args_dev, a, tol=tol, forces=True)            # warm-up (allocates the solver vectors)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mi, e, F, it, r = plan.induce(*args_dev, a, tol=tol, forces=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    return {"tol": tol, "iterations": it, "rel_residual": r, "ms": ms, "ms_per_product": ms / (it + 2),
+            "polarisabilities_A3": {"O": float(alpha[0]), "H": float(alpha[1])},
+            "note": "one solve = the permanent field + one dipole-field evaluation per iteration + the final "
+                    "energy and forces (it + 2 evaluations)", "_mu": mi.cpu().numpy()}
+
+
 def cpu_baseline(data, eps):
     """The classical-Ewald oracle on a bounded cut-out of the same water box."""
     import oracle
@@ -124,6 +141,8 @@ def main():
     ap.add_argument("--mixed-only", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--mode", default="mixed_bf16x3", choices=["mixed", "mixed_bf16x3"],
                     help="precision mode of the headline (mixed) path")
+    ap.add_argument("--no-induce", action="store_true", help="skip the induced-dipole solve")
+    ap.add_argument("--induce-tol", type=float, default=1e-6)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the timed region, one device-to-device copy of this many MiB (a plain copy kernel "
                          "of known size that calibrates the HBM byte counters of a profiler run)")
@@ -165,10 +184,21 @@ def main():
     t_mixed, st_mixed, out_mixed = timed_run(pm, args_dev, args.steps, args.warmup, torch)
     log(f"mixed: {t_mixed * 1e3:.3f} ms/step stages {st_mixed['stage_ms']}")
 
+    induce = None
+    if not args.no_induce and args.workload.startswith("water"):
+        induce = induce_run(pm, args_dev, synth.water_polarisabilities(n // 3), args.induce_tol, torch, dev)
+        log(f"induce: { {k: v for k, v in induce.items() if k != '_mu'} }")
+
     res = {}
     if not args.mixed_only:
         pf = ak.Plan(n, rB, args.eps, 2, "fp64")
         t_fp64, st_fp64, out_fp64 = timed_run(pf, args_dev, args.steps, args.warmup, torch)
+        if induce is not None:
+            ind64 = induce_run(pf, args_dev, synth.water_polarisabilities(n // 3), args.induce_tol, torch, dev,
+                               reps=1)
+            induce["fp64"] = {k: ind64[k] for k in ("ms", "iterations", "ms_per_product")}
+            induce["mixed_vs_fp64_rel_rms_mu_ind"] = rel_rms(induce.pop("_mu"), ind64.pop("_mu"))
+            induce.pop("_mu", None)
         log(f"fp64: {t_fp64 * 1e3:.3f} ms/step stages {st_fp64['stage_ms']}")
         Em, Fm, Gm = [x.double().cpu().numpy() for x in out_mixed]
         Ef, Ff, Gf = [x.double().cpu().numpy() for x in out_fp64]
@@ -228,6 +258,9 @@ def main():
         "roofline_" + other["kernel"]: other,
     }
     line.update(res)
+    if induce is not None:
+        induce.pop("_mu", None)
+        line["induce"] = induce
     pm.close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(data, args.eps)

@@ -58,7 +58,10 @@ typedef enum {
     ANKH_ERR_LEAF_OVERFLOW = 4,        /* reserved: no kernel has a per-leaf capacity limit */
     ANKH_ERR_ACCURACY_UNREACHABLE = 5, /* plan: accuracy below what the precision mode can reach */
     ANKH_ERR_OUT_OF_MEMORY = 6,        /* plan: device allocation failed */
-    ANKH_ERR_HIP = 7                   /* a HIP runtime call failed */
+    ANKH_ERR_HIP = 7,                  /* a HIP runtime call failed */
+    ANKH_ERR_NOT_CONVERGED = 8         /* ankh_induce: the tolerance was not reached within max_iter, or the
+                                          iteration met a non-positive curvature (the polarisabilities are too
+                                          large for the geometry: polarisation catastrophe) */
 } ankh_status;
 
 typedef enum {
@@ -149,6 +152,48 @@ ankh_status ankh_energy(ankh_plan_t plan, const double *pos, const double *q, co
  */
 ankh_status ankh_energy_forces(ankh_plan_t plan, const double *pos, const double *q, const double *mu,
                                const double *theta, double *energy, double *forces, double *dE_dmu);
+
+/*
+ * ankh_induce: induced dipoles of isotropic point polarisabilities, the
+ * polarizable use of the method that the paper's introduction names (the
+ * moments of eq. 1 extended by induced dipoles).  The induced dipoles are the
+ * minimiser of
+ *
+ *     U(mu_ind) = E(q, mu + mu_ind, Theta) + sum_i |mu_ind_i|^2 / (2 alpha_i),
+ *
+ * E the energy of this plan's approximation.  E is quadratic in the moments,
+ * so the minimiser solves (alpha^-1 + H) mu_ind = -dE/dmu(q, mu, Theta), where
+ * H p = dE/dmu of the dipoles p alone: one field evaluation per product.  In
+ * the scaled unknown y = alpha^(-1/2) mu_ind the matrix I + alpha^(1/2) H
+ * alpha^(1/2) is symmetric, positive definite below the polarisation
+ * catastrophe, and alpha = 0 atoms drop out; it is solved by conjugate
+ * gradients from y = 0, driven from the host (two scalars read back per
+ * iteration), every vector operation and dot product on the device in
+ * float64 with a fixed-order reduction.  The field evaluations run in the
+ * plan's precision mode.
+ *   pos, q, mu, theta  as for ankh_energy_forces (device); mu may be NULL
+ *                  (no permanent dipoles); the plan needs max_order >= 1.
+ *   alpha  [n]     polarisabilities in Angstrom^3 (device, finite, >= 0; 0 =
+ *                  not polarisable).  A negative value is latched
+ *                  (ANKH_ERR_INVALID_ARG from ankh_sync), a non-finite one as
+ *                  ANKH_ERR_NONFINITE_INPUT; such atoms are treated as alpha = 0.
+ *   tol            stop when |r| <= tol |b| in the scaled system (> 0).
+ *   max_iter       at most this many products (>= 0).
+ *   mu_ind [n][3]  device output: the induced dipoles (the last iterate when
+ *                  not converged).
+ *   energy [1]     device output or NULL: U at mu_ind (one more evaluation).
+ *   forces [n][3]  device output or NULL: -dU/dx at mu_ind (held fixed; exact
+ *                  at the minimiser, where dU/dmu_ind = 0).
+ *   iterations     host output or NULL: products done.
+ *   rel_residual   host output or NULL: |r| / |b| at the end (0 when b = 0).
+ * Synchronises the plan's stream.  Returns ANKH_ERR_NOT_CONVERGED (outputs
+ * written) when tol is not reached; host-checkable errors as elsewhere.  The
+ * plan allocates its solver vectors (7 x 3n + 2n doubles) on the first call.
+ * Stage timings (ankh_set_timing) include the evaluations made here.
+ */
+ankh_status ankh_induce(ankh_plan_t plan, const double *pos, const double *q, const double *mu,
+                        const double *theta, const double *alpha, double tol, int32_t max_iter, double *mu_ind,
+                        double *energy, double *forces, int32_t *iterations, double *rel_residual);
 
 /* Waits for the plan's stream; returns the first latched device-side input error, then clears it. */
 ankh_status ankh_sync(ankh_plan_t plan);

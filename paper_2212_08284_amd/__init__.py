@@ -2,7 +2,8 @@
 
 Argument marshalling only: every step of an evaluation runs in the HIP
 kernels behind the C ABI declared in include/ankh.h.  The functions below
-carry the C names (`ankh_plan`, `ankh_energy`, `ankh_energy_forces`, ...);
+carry the C names (`ankh_plan`, `ankh_energy`, `ankh_energy_forces`,
+`ankh_induce`, ...);
 `Plan` wraps a plan handle and `AnkhEnergy` is the autograd function whose
 backward returns -g F for the positions and g dE/dmu for the dipoles.
 
@@ -27,7 +28,7 @@ ANKH_MIXED_BF16X3 = 2
 STATUS = {
     0: "ok", 1: "invalid argument", 2: "non-finite input", 3: "quadrupole not traceless",
     4: "leaf overflow", 5: "accuracy unreachable in this precision", 6: "out of device memory",
-    7: "HIP runtime error",
+    7: "HIP runtime error", 8: "induced dipoles not converged",
 }
 
 STAGES = ["sort", "gather", "p2m", "m2m", "m2l", "periodic", "l2l", "l2p", "p2p", "p2p_sum", "reduce"]
@@ -56,7 +57,7 @@ class _Stats(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["ankh_plan", "ankh_energy", "ankh_energy_forces", "ankh_sync", "ankh_get_stats", "ankh_set_timing",
-           "ankh_last_terms", "ankh_leaf_multipoles", "ankh_destroy", "ankh_status_string"]
+           "ankh_last_terms", "ankh_leaf_multipoles", "ankh_destroy", "ankh_status_string", "ankh_induce"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -75,6 +76,9 @@ def load_library(path: str = LIB_PATH):
     L.ankh_energy.argtypes = [vp, dp, dp, dp, dp, dp]
     L.ankh_energy_forces.restype = ctypes.c_int
     L.ankh_energy_forces.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp]
+    L.ankh_induce.restype = ctypes.c_int
+    L.ankh_induce.argtypes = [vp, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int32, dp, dp, dp,
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
     L.ankh_sync.restype = ctypes.c_int
     L.ankh_sync.argtypes = [vp]
     L.ankh_get_stats.restype = ctypes.c_int
@@ -142,6 +146,17 @@ def ankh_energy(plan, pos, q, mu, theta, energy):
 
 def ankh_energy_forces(plan, pos, q, mu, theta, energy, forces, dE_dmu):
     _check(load_library().ankh_energy_forces(plan, pos, q, mu, theta, energy, forces, dE_dmu), "ankh_energy_forces")
+
+
+def ankh_induce(plan, pos, q, mu, theta, alpha, tol, max_iter, mu_ind, energy, forces):
+    """Returns (status, iterations, rel_residual); raises on every status but ANKH_ERR_NOT_CONVERGED (8)."""
+    it = ctypes.c_int32(0)
+    res = ctypes.c_double(0.0)
+    st = load_library().ankh_induce(plan, pos, q, mu, theta, alpha, float(tol), int(max_iter), mu_ind, energy,
+                                    forces, ctypes.byref(it), ctypes.byref(res))
+    if st not in (0, 8):
+        raise AnkhError(st, "ankh_induce")
+    return st, it.value, res.value
 
 
 def ankh_sync(plan):
@@ -222,6 +237,25 @@ class Plan:
         ankh_energy_forces(self.handle, pp, qp, mp, tp, ctypes.c_void_p(e.data_ptr()),
                            ctypes.c_void_p(F.data_ptr()), None if G is None else ctypes.c_void_p(G.data_ptr()))
         return e, F, G
+
+    def induce(self, pos, q, mu, theta, alpha, tol=1e-8, max_iter=100, energy=True, forces=False,
+               check=True):
+        """Induced dipoles of the polarisabilities alpha [n] (see ankh_induce in ankh.h).  Returns
+        (mu_ind, U or None, forces or None, iterations, rel_residual).  With check, raises AnkhError
+        if the tolerance was not reached and reports latched input errors (one ankh_sync)."""
+        keep, (pp, qp, mp, tp) = self._args(pos, q, mu, theta)
+        alpha, ap = _dev(alpha, 1, self.n, "alpha")
+        mi = torch.empty((self.n, 3), dtype=torch.float64, device=pos.device)
+        e = torch.empty(1, dtype=torch.float64, device=pos.device) if energy else None
+        F = torch.empty((self.n, 3), dtype=torch.float64, device=pos.device) if forces else None
+        st, it, res = ankh_induce(self.handle, pp, qp, mp, tp, ap, tol, max_iter, ctypes.c_void_p(mi.data_ptr()),
+                                  None if e is None else ctypes.c_void_p(e.data_ptr()),
+                                  None if F is None else ctypes.c_void_p(F.data_ptr()))
+        if check:
+            ankh_sync(self.handle)
+            if st != 0:
+                raise AnkhError(st, f"ankh_induce ({it} iterations, residual {res:.3g})")
+        return mi, e, F, it, res
 
     def sync(self):
         ankh_sync(self.handle)

@@ -107,7 +107,8 @@ struct ankh_plan_s {
     double *d_G = nullptr;        // fields in leaf order [3][n]
     double *d_terms = nullptr;    // energy terms [8]
     double *d_part = nullptr;     // reduction partials
-    int32_t *d_err = nullptr;     // latched device errors [4]
+    int32_t *d_err = nullptr;     // latched device errors [4]: non-finite, theta trace, invalid value
+    double *d_ind = nullptr;      // induced-dipole solver vectors (allocated by the first ankh_induce)
     size_t bytes = 0;
 
     // statistics / timing
@@ -148,6 +149,9 @@ hipError_t launch_m2l_expand(ankh_plan_s *pl);    // all compressed levels: L = 
 inline bool is_mixed(const ankh_plan_s *pl) { return pl->precision != ANKH_FP64; }
 hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields);
 hipError_t launch_p2p_sum(ankh_plan_s *pl, bool grad, bool fields);
+// one evaluation of the path (the body of ankh_energy / ankh_energy_forces; inputs already checked)
+ankh_status evaluate(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th,
+                     double *energy, double *forces, double *dEdmu);
 hipError_t launch_build_m2l(ankh_plan_s *pl, int e, double *K);
 hipError_t launch_build_cper(ankh_plan_s *pl);
 hipError_t launch_convert_f32(const double *src, float *dst, int64_t n, hipStream_t s);

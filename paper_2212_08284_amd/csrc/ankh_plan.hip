@@ -46,7 +46,7 @@ void free_all(ankh_plan_s *pl) {
                     pl->d_G, pl->d_terms, pl->d_part, pl->d_err, pl->d_tab0, pl->d_Mf, pl->d_m2l_part,
                     pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr,
                     pl->d_Kb, pl->d_Mb, pl->d_slot_e, pl->d_slot_f, pl->d_slot_g, pl->d_cper_part,
-                    pl->d_U, pl->d_Mc, pl->d_Lc};
+                    pl->d_U, pl->d_Mc, pl->d_Lc, pl->d_ind};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &set : pl->evsets)
@@ -173,6 +173,11 @@ ankh_status check_inputs(ankh_plan_s *pl, const double *pos, const double *q, co
 
 }  // namespace
 
+ankh_status ankh::evaluate(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th,
+                           double *energy, double *forces, double *dEdmu) {
+    return run(pl, pos, q, mu, th, energy, forces, dEdmu);
+}
+
 extern "C" {
 
 const char *ankh_status_string(ankh_status st) {
@@ -185,6 +190,7 @@ const char *ankh_status_string(ankh_status st) {
         case ANKH_ERR_ACCURACY_UNREACHABLE: return "accuracy unreachable in this precision";
         case ANKH_ERR_OUT_OF_MEMORY: return "out of device memory";
         case ANKH_ERR_HIP: return "HIP runtime error";
+        case ANKH_ERR_NOT_CONVERGED: return "induced dipoles not converged";
     }
     return "unknown status";
 }
@@ -457,10 +463,10 @@ ankh_status ankh_sync(ankh_plan_t pl) {
     if (hipStreamSynchronize(pl->stream) != hipSuccess) return ANKH_ERR_HIP;
     int32_t err[4] = {0, 0, 0, 0};
     if (hipMemcpy(err, pl->d_err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return ANKH_ERR_HIP;
-    if (err[0] || err[1]) {
+    if (err[0] || err[1] || err[2]) {
         if (launch_zero_i32(pl->d_err, 4, pl->stream) != hipSuccess) return ANKH_ERR_HIP;
         if (hipStreamSynchronize(pl->stream) != hipSuccess) return ANKH_ERR_HIP;
-        return err[0] ? ANKH_ERR_NONFINITE_INPUT : ANKH_ERR_THETA_NOT_TRACELESS;
+        return err[0] ? ANKH_ERR_NONFINITE_INPUT : err[1] ? ANKH_ERR_THETA_NOT_TRACELESS : ANKH_ERR_INVALID_ARG;
     }
     return ANKH_OK;
 }

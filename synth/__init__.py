@@ -108,6 +108,16 @@ def water(n_mol: int, seed: int = 2, mu_sigma: float = 0.1, theta_sigma: float =
                 name=f"water_nmol{n_mol}")
 
 
+def water_polarisabilities(n_mol: int, alpha_o: float = 0.3, alpha_h: float = 0.03) -> np.ndarray:
+    """Isotropic point polarisabilities (A^3) in the atom order of `water` (O, H, H per molecule).
+
+    The kernel has no short-range damping, so the values are kept small enough that the undamped
+    dipole-dipole coupling 2 sqrt(alpha_i alpha_j) / r^3 stays below 0.25 for the O-H bond (0.957 A)
+    and for the closest intermolecular H-H pairs of the seeded boxes (0.63 A): the induced-dipole
+    matrix stays positive definite."""
+    return np.tile(np.array([alpha_o, alpha_h, alpha_h]), n_mol)
+
+
 def ionic(n: int, density: float = 0.1, seed: int = 4, mu_sigma: float = 0.05) -> dict:
     """Ionic melt: n charges +-1 (neutral), uniform at `density` atoms/A^3, N(0, mu_sigma) dipoles."""
     rng = np.random.default_rng(seed)

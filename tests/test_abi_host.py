@@ -45,10 +45,11 @@ def test_binding_carries_the_c_names():
 
 
 def test_status_strings(lib):
-    for code in range(8):
+    for code in range(9):
         s = lib.ankh_status_string(code)
         assert isinstance(s, bytes) and len(s) > 0
     assert lib.ankh_status_string(0) == b"ok"
+    assert lib.ankh_status_string(8) == b"induced dipoles not converged"
 
 
 def _plan(lib, n=100, rb=10.0, eps=1e-6, order=2, prec=0, ov=None):
@@ -89,4 +90,5 @@ def test_null_plan_and_null_outputs(lib):
     assert lib.ankh_set_timing(None, 1) == 1
     assert lib.ankh_last_terms(None, None) == 1
     assert lib.ankh_plan(None, 10, 1.0, 1e-6, 0, 0, None, None) == 1
+    assert lib.ankh_induce(None, vp(8), vp(8), None, None, vp(8), 1e-8, 10, vp(8), None, None, None, None) == 1
     lib.ankh_destroy(None)   # no-op
