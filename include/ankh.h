@@ -201,7 +201,10 @@ ankh_status ankh_sync(ankh_plan_t plan);
 /* Copies the plan's parameters and statistics (synchronises the plan's stream). */
 ankh_status ankh_get_stats(ankh_plan_t plan, ankh_plan_stats *out);
 
-/* Enables (1, restarting the averaging window) or disables (0) per-stage hipEvent timing of later evaluations. */
+/* Per-stage hipEvent timing of later evaluations: 0 disables it; 1 records an event at every stage
+ * boundary; 2 only around stage 4 (far-field contraction) and stage 8 (pair kernel), the other stages
+ * reading -1.  Each recorded event idles the device for a few microseconds, so mode 2 perturbs the
+ * evaluation less.  1 and 2 restart the averaging window; other values are ANKH_ERR_INVALID_ARG. */
 ankh_status ankh_set_timing(ankh_plan_t plan, int32_t enable);
 
 /*

@@ -172,8 +172,9 @@ def ankh_get_stats(plan) -> dict:
     return d
 
 
-def ankh_set_timing(plan, enable: bool):
-    _check(load_library().ankh_set_timing(plan, 1 if enable else 0), "ankh_set_timing")
+def ankh_set_timing(plan, enable):
+    """enable: False / 0 off, True / 1 every stage boundary, 2 around the M2L and pair-kernel stages only."""
+    _check(load_library().ankh_set_timing(plan, int(enable)), "ankh_set_timing")
 
 
 def ankh_last_terms(plan) -> dict:

@@ -134,7 +134,7 @@ __global__ void k_add_half(double *energy, const double *yy) {
 
 struct Work {
     double *vec[kNumVec];
-    double *s, *qzero, *ftmp, *etmp, *part, *dot;
+    double *s, *qzero, *etmp, *part, *dot;
 };
 
 Work layout(ankh_plan_s *pl) {
@@ -145,14 +145,13 @@ Work layout(ankh_plan_s *pl) {
     b += kNumVec * m;
     w.s = b;
     w.qzero = b + pl->n;
-    w.ftmp = b + 2 * pl->n;     // forces of the products (not needed, the path computes them with the fields)
-    w.etmp = w.ftmp + m;
+    w.etmp = b + 2 * pl->n;
     w.part = w.etmp + 8;
     w.dot = w.part + kDotBlocks;
     return w;
 }
 
-size_t work_doubles(int64_t n) { return (size_t)(kNumVec + 1) * 3 * n + 2 * n + 8 + kDotBlocks + 8; }
+size_t work_doubles(int64_t n) { return (size_t)kNumVec * 3 * n + 2 * n + 8 + kDotBlocks + 8; }
 
 }  // namespace
 }  // namespace ankh
@@ -198,7 +197,7 @@ extern "C" ankh_status ankh_induce(ankh_plan_t pl, const double *pos, const doub
         if (launch_zero_f64(v, m, st) != hipSuccess) return ANKH_ERR_HIP;
         mu0 = v;
     }
-    if ((res = evaluate(pl, pos, q, mu0, theta, w.etmp, w.ftmp, g0)) != ANKH_OK) return res;
+    if ((res = evaluate(pl, pos, q, mu0, theta, w.etmp, nullptr, g0)) != ANKH_OK) return res;
     hipLaunchKernelGGL(k_cg_init, gd, b256, 0, st, m, w.s, g0, y, r, p, v, w.part);
     double bb = 0.0;
     if (hipGetLastError() != hipSuccess || !dot(bb)) return ANKH_ERR_HIP;
@@ -207,8 +206,8 @@ extern "C" ankh_status ankh_induce(ankh_plan_t pl, const double *pos, const doub
     bool ok = bb == 0.0;
     if (!std::isfinite(bb)) max_iter = 0;   // a latched input error: report it through ankh_sync
     while (!ok && it < max_iter) {
-        // w = H v: the fields of the dipoles v alone
-        if ((res = evaluate(pl, pos, w.qzero, v, nullptr, w.etmp, w.ftmp, Hv)) != ANKH_OK) return res;
+        // w = H v: the fields of the dipoles v alone (a fields-only evaluation: no force arithmetic)
+        if ((res = evaluate(pl, pos, w.qzero, v, nullptr, w.etmp, nullptr, Hv)) != ANKH_OK) return res;
         hipLaunchKernelGGL(k_cg_apply, gd, b256, 0, st, m, w.s, p, Hv, Ap, w.part);
         double pAp = 0.0;
         if (hipGetLastError() != hipSuccess || !dot(pAp)) return ANKH_ERR_HIP;
@@ -233,7 +232,7 @@ extern "C" ankh_status ankh_induce(ankh_plan_t pl, const double *pos, const doub
     if (energy || forces) {
         hipLaunchKernelGGL(k_dot_sum, dim3(1), b256, 0, st, w.part, w.dot);
         double *e = energy ? energy : w.etmp;
-        if ((res = evaluate(pl, pos, q, v, theta, e, forces ? forces : w.ftmp, nullptr)) != ANKH_OK) return res;
+        if ((res = evaluate(pl, pos, q, v, theta, e, forces, nullptr)) != ANKH_OK) return res;
         hipLaunchKernelGGL(k_add_half, dim3(1), dim3(64), 0, st, e, w.dot);
         if (hipGetLastError() != hipSuccess) return ANKH_ERR_HIP;
     }

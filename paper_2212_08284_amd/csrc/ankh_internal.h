@@ -113,10 +113,11 @@ struct ankh_plan_s {
 
     // statistics / timing
     double plan_ms = 0;
-    bool timing = false;
+    int timing = 0;               // 0 off, 1 every stage boundary, 2 the boundaries of stages 4 and 8 only
     // one set of stage-boundary events per timed evaluation since timing was enabled
     std::vector<std::array<hipEvent_t, ankh::kNumStages + 1>> evsets;
     int64_t n_timed = 0;
+    int timed_mode = 1;           // the timing mode of the evaluations in the averaging window
     int last_kind = 0;            // 0 none, 1 energy, 2 energy+forces
     int last_order = 0;
 };
@@ -149,7 +150,8 @@ hipError_t launch_m2l_expand(ankh_plan_s *pl);    // all compressed levels: L = 
 inline bool is_mixed(const ankh_plan_s *pl) { return pl->precision != ANKH_FP64; }
 hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields);
 hipError_t launch_p2p_sum(ankh_plan_s *pl, bool grad, bool fields);
-// one evaluation of the path (the body of ankh_energy / ankh_energy_forces; inputs already checked)
+// one evaluation of the path (the body of ankh_energy / ankh_energy_forces; inputs already checked);
+// forces == nullptr with dEdmu != nullptr is a fields-only evaluation
 ankh_status evaluate(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th,
                      double *energy, double *forces, double *dEdmu);
 hipError_t launch_build_m2l(ankh_plan_s *pl, int e, double *K);

@@ -658,7 +658,8 @@ __global__ void k_unpermute(int64_t n, const int32_t *perm, const double *F, con
     int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int64_t i = perm[s];
-    for (int d = 0; d < 3; d++) forces[3 * i + d] = F[d * n + s];
+    if (forces)
+        for (int d = 0; d < 3; d++) forces[3 * i + d] = F[d * n + s];
     if (dEdmu) {
         for (int d = 0; d < 3; d++)
             dEdmu[3 * i + d] = have_mu ? G[d * n + s] + fself * P.mu[d * n + s] : 0.0;

@@ -641,9 +641,11 @@ hipError_t launch_t(ankh_plan_s *pl, const P2PArgs &a, int ord, bool grad, bool 
         if (grad) ANKH_P2P(0, true, false); else ANKH_P2P(0, false, false);
     } else if (ord == 1) {
         if (grad) { if (fields) ANKH_P2P(1, true, true); else ANKH_P2P(1, true, false); }
+        else if (fields) ANKH_P2P(1, false, true);
         else ANKH_P2P(1, false, false);
     } else {
         if (grad) { if (fields) ANKH_P2P(2, true, true); else ANKH_P2P(2, true, false); }
+        else if (fields) ANKH_P2P(2, false, true);
         else ANKH_P2P(2, false, false);
     }
 #undef ANKH_P2P
@@ -660,6 +662,9 @@ hipError_t launch_sum_t(ankh_plan_s *pl, bool grad, bool fields) {
                            pl->d_F, pl->d_G);
     else if (grad)
         hipLaunchKernelGGL((k_p2p_slots<R, true, false>), g2, b, 0, s, pl->n, pl->d_slot_e, SF, SG, pl->d_eatom,
+                           pl->d_F, pl->d_G);
+    else if (fields)
+        hipLaunchKernelGGL((k_p2p_slots<R, false, true>), g2, b, 0, s, pl->n, pl->d_slot_e, SF, SG, pl->d_eatom,
                            pl->d_F, pl->d_G);
     else
         hipLaunchKernelGGL((k_p2p_slots<R, false, false>), g2, b, 0, s, pl->n, pl->d_slot_e, SF, SG, pl->d_eatom,

@@ -108,11 +108,18 @@ void build_tables(ankh_plan_s *pl) {
         }
 }
 
+// in timing mode 2 only the far-field contraction (stage 4) and the pair kernel (stage 8) are bracketed
+// by events: every event record idles the device for a few microseconds
+bool stage_recorded(int mode, int stage) { return mode == 1 || (mode == 2 && (stage == 4 || stage == 8)); }
+
 ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th,
                 double *energy, double *forces, double *dEdmu) {
+    // forces and / or fields (dE/dmu); a null forces pointer with fields asked for is the fields-only
+    // evaluation of the induced-dipole iteration (the pair kernel then skips the force arithmetic)
     const bool grad = forces != nullptr;
     const int ord = th ? 2 : (mu ? 1 : 0);
-    const bool fields = grad && dEdmu && ord >= 1;
+    const bool fields = dEdmu && ord >= 1;
+    const bool adj = grad || fields;
     hipStream_t s = pl->stream;
     hipEvent_t *ev = nullptr;
     if (pl->timing) {
@@ -125,7 +132,8 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
         ev = pl->evsets[pl->n_timed].data();
     }
     auto mark = [&](int i) {
-        if (ev) ck(hipEventRecord(ev[i], s));
+        if (ev && (pl->timing == 1 || stage_recorded(pl->timing, i) || stage_recorded(pl->timing, i - 1)))
+            ck(hipEventRecord(ev[i], s));
     };
     try {
         mark(0);
@@ -146,14 +154,14 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
         for (int e = 1; e <= pl->depth; e++) ck(launch_l2l(pl, e));
         ck(launch_leafdot(pl));
         mark(7);
-        if (grad) ck(launch_l2p(pl, ord, fields));
+        if (adj) ck(launch_l2p(pl, ord, fields));
         mark(8);
         ck(launch_p2p(pl, ord, grad, fields));
         mark(9);
         ck(launch_p2p_sum(pl, grad, fields));
         mark(10);
         ck(launch_reduce(pl, energy, ord));
-        if (grad) ck(launch_unpermute(pl, forces, dEdmu, ord >= 1));
+        if (adj) ck(launch_unpermute(pl, forces, dEdmu, ord >= 1));
         mark(11);
     } catch (const HipFail &) {
         return ANKH_ERR_HIP;
@@ -473,8 +481,10 @@ ankh_status ankh_sync(ankh_plan_t pl) {
 
 ankh_status ankh_set_timing(ankh_plan_t pl, int32_t enable) {
     if (!pl) return ANKH_ERR_INVALID_ARG;
+    if (enable < 0 || enable > 2) return ANKH_ERR_INVALID_ARG;
     if (enable) pl->n_timed = 0;   // restart the averaging window
-    pl->timing = enable != 0;
+    pl->timing = enable;
+    if (enable) pl->timed_mode = enable;
     return ANKH_OK;
 }
 
@@ -525,6 +535,7 @@ ankh_status ankh_get_stats(ankh_plan_t pl, ankh_plan_stats *out) {
     out->timed_evals = pl->n_timed;
     if (pl->n_timed > 0) {
         for (int i = 0; i < kNumStages; i++) {
+            if (!stage_recorded(pl->timed_mode, i)) continue;
             double sum = 0;
             for (int64_t t = 0; t < pl->n_timed; t++) {
                 float ms = 0;

@@ -158,6 +158,27 @@ def test_energy_only_path_matches(ak):
     pl.close()
 
 
+def test_stage_timing_modes(ak):
+    d = _system("qmt")
+    pl = ak.Plan(len(d["q"]), 0.5 * d["edge"], 1e-6, 2, "fp64")
+    args = (T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
+    for mode in (1, 2):
+        pl.set_timing(mode)
+        pl.energy_forces(*args)
+        pl.energy_forces(*args)
+        st = pl.get_stats()
+        assert st["timed_evals"] == 2
+        for name, ms in st["stage_ms"].items():
+            if mode == 1 or name in ("m2l", "p2p"):
+                assert ms >= 0.0, (mode, name)
+            else:
+                assert ms == -1.0, (mode, name)
+    pl.set_timing(0)
+    with pytest.raises(ak.AnkhError):
+        pl.set_timing(3)
+    pl.close()
+
+
 def test_bitwise_reproducible(ak):
     d = _system("qmt", seed=3)
     pl, e, F, G = _run(ak, d)
