@@ -31,7 +31,7 @@ METRIC = "E+forces evals/s per atom on 1 MI355X, mixed vs FP64, rel RMS force er
 # dipoles + quadrupoles with the energy, the force, the field at both atoms and
 # the accumulation into both atoms, counted term by term from its source
 # (FMA = 2, add / mul = 1, erfc / exp / rsqrt = 1 each).  Breakdown in the design doc.
-P2P_FLOP_PER_UNORDERED_PAIR = 333.0
+P2P_FLOP_PER_UNORDERED_PAIR = 300.0
 
 # HBM traffic of one P2P launch measured with rocprofv3 counters (FETCH_SIZE and
 # WRITE_SIZE, calibrated against a copy of known size) for the kernel source

@@ -77,7 +77,7 @@ struct ankh_plan_s {
     int32_t *d_leaf = nullptr;    // leaf id per input atom
     int32_t *d_count = nullptr;   // atoms per leaf
     int32_t *d_offs = nullptr;    // CSR offsets [nleaf + 1]
-    int32_t *d_fill = nullptr;    // scatter cursors [nleaf]
+    int32_t *d_rank = nullptr;    // arrival rank of each input atom in its leaf [n]
     int32_t *d_perm = nullptr;    // leaf-order slot -> input atom
     int32_t *d_tmp = nullptr;     // [n] segment-sort scratch
     ankh::Particles P{};

@@ -39,9 +39,11 @@ __global__ void k_to_f32(const double *s, float *d, int64_t n) {
 }
 
 // ---- tree: bin atoms into leaves, count, validate inputs --------------------
-__global__ void k_bin(int64_t n, const double *pos, const double *q, const double *mu, const double *th,
-                      double rB, double edge, double w, int nside, int32_t *leaf, int32_t *count,
-                      int32_t *err) {
+// leaf of every atom, the leaf counts, and each atom's arrival rank in its leaf (the scatter then
+// needs no atomics; the arrival order itself is undone by the segment sort).  Positions and charges
+// are checked here, the higher moments in the gather, which reads them anyway.
+__global__ void k_bin(int64_t n, const double *pos, const double *q, double rB, double edge, double w, int nside,
+                      int32_t *leaf, int32_t *count, int32_t *rank, int32_t *err) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     bool fin = isfinite(q[i]);
@@ -51,20 +53,10 @@ __global__ void k_bin(int64_t n, const double *pos, const double *q, const doubl
         fin = fin && isfinite(v);
         ix[d] = isfinite(v) ? leaf_coord(v, rB, edge, w, nside, &xw) : 0;
     }
-    if (mu)
-        for (int d = 0; d < 3; d++) fin = fin && isfinite(mu[3 * i + d]);
-    if (th) {
-        double tr = 0, mx = 0;
-        for (int d = 0; d < 6; d++) fin = fin && isfinite(th[6 * i + d]);
-        const double xx = th[6 * i], yy = th[6 * i + 3], zz = th[6 * i + 5];
-        tr = xx + yy + zz;
-        mx = fmax(fabs(xx), fmax(fabs(yy), fabs(zz)));
-        if (fabs(tr) > 1e-6 * (1.0 + mx)) err[1] = 1;
-    }
     if (!fin) err[0] = 1;
     int id = (ix[0] * nside + ix[1]) * nside + ix[2];
     leaf[i] = id;
-    atomicAdd(&count[id], 1);
+    rank[i] = atomicAdd(&count[id], 1);
 }
 
 // exclusive scan of the leaf counts (one block; m up to 8^7)
@@ -91,12 +83,10 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *count, int32_t *of
     if (t == 1023) offs[m] = (int32_t)part[1023];
 }
 
-__global__ void k_scatter(int64_t n, const int32_t *leaf, const int32_t *offs, int32_t *fill, int32_t *perm) {
+__global__ void k_scatter(int64_t n, const int32_t *leaf, const int32_t *offs, const int32_t *rank, int32_t *perm) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int l = leaf[i];
-    int slot = offs[l] + atomicAdd(&fill[l], 1);
-    perm[slot] = (int32_t)i;
+    perm[offs[leaf[i]] + rank[i]] = (int32_t)i;
 }
 
 // order the atoms of each leaf by input index (rank sort), so that every
@@ -120,7 +110,7 @@ __global__ __launch_bounds__(256) void k_segsort(const int32_t *offs, const int3
 // leaf-order particle arrays: local coordinates (relative to the leaf centre)
 __global__ void k_gather(int64_t n, const int32_t *perm, const int32_t *leaf, const double *pos,
                          const double *q, const double *mu, const double *th, double rB, double edge,
-                         double w, int nside, Particles P, int planned_order, int mixed) {
+                         double w, int nside, Particles P, int planned_order, int mixed, int32_t *err) {
     int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int i = perm[s];
@@ -139,20 +129,28 @@ __global__ void k_gather(int64_t n, const int32_t *perm, const int32_t *leaf, co
     const double qi = q[i];
     P.q[s] = qi;
     if (mixed) P.qf[s] = (float)qi;
+    bool fin = true;
     if (planned_order >= 1) {
         for (int d = 0; d < 3; d++) {
             double v = mu ? mu[3 * (int64_t)i + d] : 0.0;
+            fin = fin && isfinite(v);
             P.mu[d * n + s] = v;
             if (mixed) P.muf[d * n + s] = (float)v;
         }
     }
     if (planned_order >= 2) {
+        double t[6];
         for (int d = 0; d < 6; d++) {
             double v = th ? th[6 * (int64_t)i + d] : 0.0;
+            fin = fin && isfinite(v);
+            t[d] = v;
             P.th[d * n + s] = v;
             if (mixed) P.thf[d * n + s] = (float)v;
         }
+        const double tr = t[0] + t[3] + t[5], mx = fmax(fabs(t[0]), fmax(fabs(t[3]), fabs(t[5])));
+        if (fabs(tr) > 1e-6 * (1.0 + mx)) err[1] = 1;
     }
+    if (!fin) err[0] = 1;
 }
 
 // ---- Chebyshev basis ---------------------------------------------------------
@@ -746,12 +744,11 @@ hipError_t launch_sort(ankh_plan_s *pl, const double *pos, const double *q, cons
     const double w = pl->edge / pl->nside;
     hipError_t e;
     if ((e = launch_zero_i32(pl->d_count, pl->nleaf, s)) != hipSuccess) return e;
-    if ((e = launch_zero_i32(pl->d_fill, pl->nleaf, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin, dim3(nblk(pl->n, 256)), dim3(256), 0, s, pl->n, pos, q, mu, th, pl->rB, pl->edge, w,
-                       pl->nside, pl->d_leaf, pl->d_count, pl->d_err);
+    hipLaunchKernelGGL(k_bin, dim3(nblk(pl->n, 256)), dim3(256), 0, s, pl->n, pos, q, pl->rB, pl->edge, w,
+                       pl->nside, pl->d_leaf, pl->d_count, pl->d_rank, pl->d_err);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, pl->d_count, pl->d_offs, pl->nleaf);
     hipLaunchKernelGGL(k_scatter, dim3(nblk(pl->n, 256)), dim3(256), 0, s, pl->n, pl->d_leaf, pl->d_offs,
-                       pl->d_fill, pl->d_tmp);
+                       pl->d_rank, pl->d_tmp);
     hipLaunchKernelGGL(k_segsort, dim3((unsigned)pl->nleaf), dim3(256), 0, s, pl->d_offs, pl->d_tmp, pl->d_perm);
     return hipGetLastError();
 }
@@ -760,7 +757,7 @@ hipError_t launch_gather(ankh_plan_s *pl, const double *pos, const double *q, co
     const double w = pl->edge / pl->nside;
     hipLaunchKernelGGL(k_gather, dim3(nblk(pl->n, 256)), dim3(256), 0, pl->stream, pl->n, pl->d_perm, pl->d_leaf,
                        pos, q, mu, th, pl->rB, pl->edge, w, pl->nside, pl->P, pl->max_order,
-                       is_mixed(pl) ? 1 : 0);
+                       is_mixed(pl) ? 1 : 0, pl->d_err);
     return hipGetLastError();
 }
 

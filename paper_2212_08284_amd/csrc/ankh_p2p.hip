@@ -48,7 +48,14 @@ constexpr int KMAX = 7;     // mutual tasks of a kind-0 block (kind 1: the other
 constexpr int G = 16;       // lanes per group (one DPP row)
 constexpr int NG = 16;      // groups per block
 
-struct P2PArgs {
+// Per-launch constants of the radial functions: xi; gx, the factor that turns
+// r^2 into the argument of gauss(); pwc[n] = (2 xi^2)^n / (xi sqrt(pi)), the
+// Gaussian's weight in B_n.
+template <typename R> struct Radial {
+    R xi, xi2, c_erf, gx, pwc[6];   // c_erf = (2/sqrt(pi)) xi
+};
+
+template <typename R> struct P2PArgs {
     const double *x, *y, *z;
     const double *q, *mu, *th;
     const float *qf, *muf, *thf;
@@ -59,6 +66,7 @@ struct P2PArgs {
     double *slot_e;         // [27][n] energy partials (target side)
     void *slot_f;           // [3][27][n] force partials (R)
     void *slot_g;           // [3][27][n] field partials (R)
+    Radial<R> rad;
 };
 
 template <typename R> __device__ inline R dev_erfc(R v);
@@ -121,33 +129,33 @@ __device__ inline double row16_sum(double v) {
     return v;
 }
 
-// Short-range forms of erfc and exp, valid for xi r <= 1/2 (every near pair
-// when the leaves are small against 1/xi; the planner checks the bound):
-// erf(x) = (2/sqrt(pi)) x sum_n (-x^2)^n / (n! (2n+1)) (Maclaurin series,
-// Abramowitz & Stegun 7.1.5) and exp(-u) = sum_n (-u)^n / n!, truncated where
-// the next term is below the working precision (7 / 8 terms in float32,
-// 13 / 14 terms in float64).
-template <typename R> struct NearSeries;
-template <> struct NearSeries<float> {
-    static constexpr int NE = 7, NX = 8;
-};
-template <> struct NearSeries<double> {
-    static constexpr int NE = 13, NX = 14;
-};
-template <typename R> __device__ inline R erfc_near(R x) {
+// Short-range forms of erfc and exp for x = xi r of every near pair below a
+// bound the launcher checks (SL = 1: x <= 1/2, SL = 2: x <= 1/5; the near
+// pairs are at most two leaf diagonals apart): erf(x) = (2/sqrt(pi)) x
+// sum_n (-x^2)^n / (n! (2n+1)) (Maclaurin series, Abramowitz & Stegun 7.1.5)
+// and exp(-u) = sum_n (-u)^n / n!, truncated where the first dropped term is
+// below the working precision at the bound: erfc 7 / 4 terms in float32,
+// 13 / 8 in float64; exp 14 / 9 terms in float64 (float32 takes the hardware
+// exponential).
+template <typename R, int SL> struct NearSeries;
+template <> struct NearSeries<float, 1> { static constexpr int NE = 7, NX = 8; };
+template <> struct NearSeries<float, 2> { static constexpr int NE = 4, NX = 5; };
+template <> struct NearSeries<double, 1> { static constexpr int NE = 13, NX = 14; };
+template <> struct NearSeries<double, 2> { static constexpr int NE = 8, NX = 9; };
+// sum_n (-u)^n / (n! (2n+1)) at u = x^2, so that erfc(x) = 1 - (2/sqrt(pi)) x erf_series(u)
+template <typename R, int SL> __device__ inline R erf_series(R u) {
     constexpr double c[13] = {1.0, -1.0 / 3, 1.0 / 10, -1.0 / 42, 1.0 / 216, -1.0 / 1320, 1.0 / 9360, -1.0 / 75600,
                               1.0 / 685440, -1.0 / 6894720, 1.0 / 76204800, -1.0 / 918086400,
                               1.0 / 11975040000.0};
-    const R u = x * x;
-    R s = (R)c[NearSeries<R>::NE - 1];
+    R s = (R)c[NearSeries<R, SL>::NE - 1];
 #pragma unroll
-    for (int k = NearSeries<R>::NE - 2; k >= 0; k--) s = s * u + (R)c[k];
-    return (R)1 - (R)1.1283791670955125739 * x * s;
+    for (int k = NearSeries<R, SL>::NE - 2; k >= 0; k--) s = s * u + (R)c[k];
+    return s;
 }
-template <typename R> __device__ inline R exp_near(R u) {   // exp(-u), Horner form with 1/k as constants
+template <typename R, int SL> __device__ inline R exp_near(R u) {   // exp(-u), Horner form with 1/k as constants
     R s = (R)1;
 #pragma unroll
-    for (int k = NearSeries<R>::NX - 1; k >= 1; k--) s = (R)1 - s * (u * (R)(1.0 / k));
+    for (int k = NearSeries<R, SL>::NX - 1; k >= 1; k--) s = (R)1 - s * (u * (R)(1.0 / k));
     return s;
 }
 
@@ -158,17 +166,42 @@ __device__ inline void symv(const R *Q, R vx, R vy, R vz, R &ox, R &oy, R &oz) {
     oy = Q[1] * vx + Q[3] * vy + Q[4] * vz;
     oz = Q[2] * vx + Q[4] * vy + Q[5] * vz;
 }
+// o += Q v
+template <typename R> __device__ inline void symv_acc(const R *Q, const R *v, R *o) {
+    o[0] += Q[0] * v[0] + Q[1] * v[1] + Q[2] * v[2];
+    o[1] += Q[1] * v[0] + Q[3] * v[1] + Q[4] * v[2];
+    o[2] += Q[2] * v[0] + Q[4] * v[1] + Q[5] * v[2];
+}
 
-// exp(-u) for the Gaussian factor of the radial functions: the short series,
-// or in float32 the hardware base-2 exponential (relative error ~1e-7 here)
-template <typename R, bool SER> __device__ inline R gauss(R u);
-template <> __device__ inline float gauss<float, true>(float u) { return __expf(-u); }
-template <> __device__ inline float gauss<float, false>(float u) { return expf(-u); }
-template <> __device__ inline double gauss<double, true>(double u) { return exp_near<double>(u); }
-template <> __device__ inline double gauss<double, false>(double u) { return exp(-u); }
+template <typename R, int SL> Radial<R> radial_constants(double xi) {
+    Radial<R> c;
+    c.xi = (R)xi;
+    c.xi2 = (R)(xi * xi);
+    c.c_erf = (R)(1.1283791670955125739 * xi);
+    // float32 with a short series: exp(-xi^2 r^2) = 2^(gx r^2), gx = -xi^2 log2(e)
+    c.gx = (R)(sizeof(R) == 4 && SL > 0 ? -xi * xi * 1.4426950408889634074 : xi * xi);
+    double p = 1.0 / (xi * 1.7724538509055160273);
+    c.pwc[0] = (R)p;
+    for (int k = 1; k < 6; k++) {
+        p *= 2.0 * xi * xi;
+        c.pwc[k] = (R)p;
+    }
+    return c;
+}
+// exp(-xi^2 r^2) from v = gx r^2: the short series, or in float32 the hardware
+// base-2 exponential (relative error ~1e-7 here)
+template <typename R, int SL> __device__ inline R gauss(R v);
+template <> __device__ inline float gauss<float, 0>(float v) { return expf(-v); }
+template <> __device__ inline float gauss<float, 1>(float v) { return __builtin_amdgcn_exp2f(v); }
+template <> __device__ inline float gauss<float, 2>(float v) { return __builtin_amdgcn_exp2f(v); }
+template <> __device__ inline double gauss<double, 0>(double v) { return exp(-v); }
+template <> __device__ inline double gauss<double, 1>(double v) { return exp_near<double, 1>(v); }
+template <> __device__ inline double gauss<double, 2>(double v) { return exp_near<double, 2>(v); }
 
-// One pair: adds ew * E to e, -grad to f (target force) and the target field
-// to g; with SRC also the source field to gs (the source force is -f's share).
+
+// One pair, accumulated in place: ew * E into te, the target force -grad into
+// tf and the target field into tg; with SRC (mutual form, ew = 1) also the
+// source force +grad into sf and the source field into sg.
 // The gradient is grouped by vector (the same algebra as grad(c_n) B_n - r
 // sum c_n B_{n+1}):
 //   grad_r E = a1 di + a2 dk + a3 Qk r + a4 Qi r + 2 B2 (Qk di - Qi dk)
@@ -177,24 +210,28 @@ template <> __device__ inline double gauss<double, false>(double u) { return exp
 //   a3 = 2 (qi B2 - (di.r) B3 + (r.Qi.r) B4),  a4 = 2 (qk B2 + (dk.r) B3 + (r.Qk.r) B4),
 // and the fields reuse a1, a2:  dE/d(di) = B1 dk + 2 B2 Qk r + a1 r,
 // dE/d(dk) = B1 di - 2 B2 Qi r + a2 r.
-template <typename R, int ORD, bool GRAD, bool FIELD, bool SRC, bool SER>
+template <typename R, int ORD, bool GRAD, bool FIELD, bool SRC, int SL>
 __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *Qi, R ck, const R *dk,
-                                  const R *Qk, R xi, R xi2, R cex, R ew, R &e, R *f, R *g, R *gs) {
+                                  const R *Qk, const Radial<R> &rc, R ew, R &te, R *tf, R *tg, R *sf, R *sg) {
     constexpr int NB = 2 * ORD + 1 + (GRAD ? 1 : 0);
     const R r2 = rx * rx + ry * ry + rz * rz;
     const R rinv = dev_rsqrt<R>(r2);
     const R rinv2 = rinv * rinv;
-    const R r = r2 * rinv;
     R B[NB > 2 ? NB : 2];
-    B[0] = (SER ? erfc_near<R>(xi * r) : dev_erfc<R>(xi * r)) * rinv;
+    R ex;
+    if constexpr (SL == 0) {
+        B[0] = dev_erfc<R>(rc.xi * (r2 * rinv)) * rinv;
+        ex = gauss<R, SL>(rc.gx * r2);
+    } else {
+        // erfc(xi r) / r = 1/r - (2/sqrt(pi)) xi erf_series(xi^2 r^2): the r of the series cancels 1/r
+        const R u = rc.xi2 * r2;
+        B[0] = rinv - rc.c_erf * erf_series<R, SL>(u);
+        ex = sizeof(R) == 8 ? gauss<R, SL>(u) : gauss<R, SL>(rc.gx * r2);
+    }
     {
-        const R ex = gauss<R, SER>(xi2 * r2) * cex;
-        R pw = 1;
+        B[1] = (B[0] + rc.pwc[1] * ex) * rinv2;
 #pragma unroll
-        for (int n = 1; n < NB; n++) {
-            pw *= 2 * xi2;
-            B[n] = ((2 * n - 1) * B[n - 1] + pw * ex) * rinv2;
-        }
+        for (int n = 2; n < NB; n++) B[n] = ((R)(2 * n - 1) * B[n - 1] + rc.pwc[n] * ex) * rinv2;
     }
     const R rv[3] = {rx, ry, rz};
     R c0 = ci * ck, c1 = 0, c2 = 0, c3 = 0, c4 = 0;
@@ -221,10 +258,17 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
         c3 = -dir * qkrr + dkr * qirr - 4 * QirQkr;
         c4 = qirr * qkrr;
     }
-    R E = c0 * B[0];
-    if constexpr (ORD >= 1) E += c1 * B[1] + c2 * B[2];
-    if constexpr (ORD >= 2) E += c3 * B[3] + c4 * B[4];
-    e += ew * E;
+    if constexpr (SRC) {
+        // ew = 1: the terms go straight into the accumulator
+        te += c0 * B[0];
+        if constexpr (ORD >= 1) te += c1 * B[1] + c2 * B[2];
+        if constexpr (ORD >= 2) te += c3 * B[3] + c4 * B[4];
+    } else {
+        R E = c0 * B[0];
+        if constexpr (ORD >= 1) E += c1 * B[1] + c2 * B[2];
+        if constexpr (ORD >= 2) E += c3 * B[3] + c4 * B[4];
+        te += ew * E;
+    }
     if constexpr (!GRAD && !FIELD) return;
     // coefficients shared by the force and the fields
     R a1 = 0, a2 = 0;
@@ -250,30 +294,36 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
         if constexpr (ORD >= 2) {
             const R a3 = 2 * (ci * B[2] - dir * B[3] + qirr * B[4]);
             const R a4 = 2 * (ck * B[2] + dkr * B[3] + qkrr * B[4]);
-            R Qkdi[3], Qidk[3], QiQkr[3], QkQir[3];
-            symv(Qk, di[0], di[1], di[2], Qkdi[0], Qkdi[1], Qkdi[2]);
-            symv(Qi, dk[0], dk[1], dk[2], Qidk[0], Qidk[1], Qidk[2]);
-            symv(Qi, Qkr[0], Qkr[1], Qkr[2], QiQkr[0], QiQkr[1], QiQkr[2]);
-            symv(Qk, Qir[0], Qir[1], Qir[2], QkQir[0], QkQir[1], QkQir[2]);
+            // b2 (Qk di - Qi dk) + b3 (Qi Qk r + Qk Qi r) = Qk (b2 di + b3 Qi r) + Qi (b3 Qk r - b2 dk):
+            // two products with a quadrupole instead of four
             const R b2 = 2 * B[2], b3 = -4 * B[3];
+            R w1[3], w2[3];
 #pragma unroll
-            for (int a = 0; a < 3; a++)
-                gr[a] += a3 * Qkr[a] + a4 * Qir[a] + b2 * (Qkdi[a] - Qidk[a]) + b3 * (QiQkr[a] + QkQir[a]);
+            for (int a = 0; a < 3; a++) {
+                gr[a] += a3 * Qkr[a] + a4 * Qir[a];
+                w1[a] = b2 * di[a] + b3 * Qir[a];
+                w2[a] = b3 * Qkr[a] - b2 * dk[a];
+            }
+            symv_acc(Qk, w1, gr);
+            symv_acc(Qi, w2, gr);
         }
 #pragma unroll
-        for (int a = 0; a < 3; a++) f[a] = -gr[a];
+        for (int a = 0; a < 3; a++) {
+            tf[a] -= gr[a];
+            if constexpr (SRC) sf[a] += gr[a];
+        }
     }
     if constexpr (FIELD) {
         const R b2 = 2 * B[2];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            R v = B[1] * dk[a] + a1 * rv[a];
-            if constexpr (ORD >= 2) v += b2 * Qkr[a];
-            g[a] = v;
+            tg[a] += B[1] * dk[a];
+            tg[a] += a1 * rv[a];
+            if constexpr (ORD >= 2) tg[a] += b2 * Qkr[a];
             if constexpr (SRC) {
-                R u = B[1] * di[a] + a2 * rv[a];
-                if constexpr (ORD >= 2) u -= b2 * Qir[a];
-                gs[a] = u;
+                sg[a] += B[1] * di[a];
+                sg[a] += a2 * rv[a];
+                if constexpr (ORD >= 2) sg[a] -= b2 * Qir[a];
             }
         }
     }
@@ -311,8 +361,8 @@ __device__ inline void task_offset(int k, int &dx, int &dy, int &dz) {
 // the leaf with itself (gather form).  The target atoms of all target leaves
 // of a block form one list that streams through the 16-lane groups, so only
 // the last pass of a block is partly empty.
-template <typename R, int ORD, bool GRAD, bool FIELD, bool SER>
-__global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
+template <typename R, int ORD, bool GRAD, bool FIELD, int SL>
+__global__ __launch_bounds__(256) void k_p2p(P2PArgs<R> a) {
     constexpr int NM = 1 + (ORD >= 1 ? 3 : 0) + (ORD >= 2 ? 6 : 0);   // moment components
     __shared__ double sx[CH], sy[CH], sz[CH];
     __shared__ R smo[NM][CH];
@@ -358,7 +408,7 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
     const int64_t n = a.n;
     R *SF = static_cast<R *>(a.slot_f), *SG = static_cast<R *>(a.slot_g);
     const int64_t sstride = (int64_t)kNumSlots * n;     // component stride of the slot arrays
-    const R xi = (R)a.xi, xi2 = (R)(a.xi * a.xi), cex = (R)(1.0 / (a.xi * 1.7724538509055160273));
+    const Radial<R> rc = a.rad;
 
     // target leaf (segment of the block's list) of list position f < ntg
     auto segment = [&](int f) {
@@ -466,49 +516,34 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
             const R ci = tcur.c;
             const R *di = tcur.d, *Qi = tcur.Q;
             R te = 0, tf[3] = {0, 0, 0}, tg[3] = {0, 0, 0};
-            // one pair with source j: the target's share into te / tf / tg, the source's into pf / ps
-            auto pair = [&](int j, R *pf, R *ps) {
+            // one pair with source j: the target's share into te / tf / tg, the source's into sf / sg
+            auto pair = [&](int j, R *sf, R *sg) {
                 const R rx = (R)(xt - sx[j]), ry = (R)(yt - sy[j]), rz = (R)(zt - sz[j]);
                 R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
                 if (ORD >= 1)
                     for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
                 if (ORD >= 2)
                     for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
-                R pe = 0, pg[3] = {0, 0, 0};
-                pair_terms<R, ORD, GRAD, FIELD, true, SER>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, xi, xi2, cex,
-                                                           (R)1, pe, pf, pg, ps);
-                te += pe;
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    tf[c] += pf[c];
-                    tg[c] += pg[c];
-                }
+                pair_terms<R, ORD, GRAD, FIELD, true, SL>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, rc, (R)1, te,
+                                                           tf, tg, sf, sg);
             };
             if constexpr (RACC) {
 #pragma unroll
                 for (int m = 0; m < MS; m++) {
                     const int j = grp + NG * m;
-                    if (j < chn) {
-                        R pf[3] = {0, 0, 0}, ps[3] = {0, 0, 0};
-                        pair(j, pf, ps);
-#pragma unroll
-                        for (int c = 0; c < 3; c++) {
-                            psrc[m][c] -= pf[c];
-                            psrc[m][3 + c] += ps[c];
-                        }
-                    }
+                    if (j < chn) pair(j, &psrc[m][0], &psrc[m][3]);
                 }
             } else {
                 for (int j = grp; j < chn; j += NG) {
-                    R pf[3] = {0, 0, 0}, ps[3] = {0, 0, 0};
-                    pair(j, pf, ps);
+                    R sf[3] = {0, 0, 0}, sg[3] = {0, 0, 0};
+                    pair(j, sf, sg);
                     if (GRAD || FIELD) {
                         // the source's share, summed over the 16 targets of the group
                         R v[6];
 #pragma unroll
                         for (int c = 0; c < 3; c++) {
-                            v[c] = GRAD ? row16_sum(-pf[c]) : (R)0;
-                            v[3 + c] = FIELD ? row16_sum(ps[c]) : (R)0;
+                            v[c] = GRAD ? row16_sum(sf[c]) : (R)0;
+                            v[3 + c] = FIELD ? row16_sum(sg[c]) : (R)0;
                         }
                         if (ln == 0) {
 #pragma unroll
@@ -572,15 +607,8 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs a) {
                         for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
                     if (ORD >= 2)
                         for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
-                    R pe = 0, pf[3] = {0, 0, 0}, pg[3] = {0, 0, 0}, ps[3];
-                    pair_terms<R, ORD, GRAD, FIELD, false, SER>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, xi, xi2,
-                                                                cex, (R)0.5, pe, pf, pg, ps);
-                    te += pe;
-#pragma unroll
-                    for (int c = 0; c < 3; c++) {
-                        tf[c] += pf[c];
-                        tg[c] += pg[c];
-                    }
+                    pair_terms<R, ORD, GRAD, FIELD, false, SL>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, rc,
+                                                               (R)0.5, te, tf, tg, nullptr, nullptr);
                 }
                 tpart[pbuf][0][grp][ln] = (double)te;
 #pragma unroll
@@ -632,11 +660,12 @@ __global__ void k_p2p_slots(int64_t n, const double *slot_e, const R *SF, const 
         }
 }
 
-template <typename R, bool SER>
-hipError_t launch_t(ankh_plan_s *pl, const P2PArgs &a, int ord, bool grad, bool fields) {
+template <typename R, int SL>
+hipError_t launch_t(ankh_plan_s *pl, P2PArgs<R> a, int ord, bool grad, bool fields) {
+    a.rad = radial_constants<R, SL>(pl->xi);
     dim3 g((unsigned)(pl->nleaf * NKIND)), b(256);
     hipStream_t s = pl->stream;
-#define ANKH_P2P(O, GR, FL) hipLaunchKernelGGL((k_p2p<R, O, GR, FL, SER>), g, b, 0, s, a)
+#define ANKH_P2P(O, GR, FL) hipLaunchKernelGGL((k_p2p<R, O, GR, FL, SL>), g, b, 0, s, a)
     if (ord == 0) {
         if (grad) ANKH_P2P(0, true, false); else ANKH_P2P(0, false, false);
     } else if (ord == 1) {
@@ -672,10 +701,9 @@ hipError_t launch_sum_t(ankh_plan_s *pl, bool grad, bool fields) {
     return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields) {
-    P2PArgs a;
+template <typename R>
+hipError_t launch_prec(ankh_plan_s *pl, int ord, bool grad, bool fields) {
+    P2PArgs<R> a;
     a.x = pl->P.x;
     a.y = pl->P.y;
     a.z = pl->P.z;
@@ -694,11 +722,17 @@ hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields) {
     a.slot_e = pl->d_slot_e;
     a.slot_f = pl->d_slot_f;
     a.slot_g = pl->d_slot_g;
-    // largest near-pair distance: opposite corners of diagonally adjacent leaves
-    const bool ser = pl->xi * 2.0 * std::sqrt(3.0) * a.w <= 0.5;
-    if (is_mixed(pl))
-        return ser ? launch_t<float, true>(pl, a, ord, grad, fields) : launch_t<float, false>(pl, a, ord, grad, fields);
-    return ser ? launch_t<double, true>(pl, a, ord, grad, fields) : launch_t<double, false>(pl, a, ord, grad, fields);
+    // largest xi r of a near pair: opposite corners of diagonally adjacent leaves
+    const double xmax = pl->xi * 2.0 * std::sqrt(3.0) * a.w;
+    if (xmax <= 0.2) return launch_t<R, 2>(pl, a, ord, grad, fields);
+    if (xmax <= 0.5) return launch_t<R, 1>(pl, a, ord, grad, fields);
+    return launch_t<R, 0>(pl, a, ord, grad, fields);
+}
+
+}  // namespace
+
+hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields) {
+    return is_mixed(pl) ? launch_prec<float>(pl, ord, grad, fields) : launch_prec<double>(pl, ord, grad, fields);
 }
 
 // per atom: the near-field energy and the sums of the force / field partial slots

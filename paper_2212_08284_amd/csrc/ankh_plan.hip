@@ -40,7 +40,7 @@ void dalloc(ankh_plan_s *pl, T **p, size_t count) {
 }
 
 void free_all(ankh_plan_s *pl) {
-    void *ptrs[] = {pl->d_tab, pl->d_leaf, pl->d_count, pl->d_offs, pl->d_fill, pl->d_perm, pl->d_tmp,
+    void *ptrs[] = {pl->d_tab, pl->d_leaf, pl->d_count, pl->d_offs, pl->d_rank, pl->d_perm, pl->d_tmp,
                     pl->P.x, pl->P.y, pl->P.z, pl->P.q, pl->P.mu, pl->P.th, pl->P.qf, pl->P.muf, pl->P.thf,
                     pl->d_M, pl->d_L, pl->d_K, pl->d_Kf, pl->d_Cper, pl->d_eatom, pl->d_eleaf, pl->d_F,
                     pl->d_G, pl->d_terms, pl->d_part, pl->d_err, pl->d_tab0, pl->d_Mf, pl->d_m2l_part,
@@ -313,7 +313,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         dalloc(pl, &pl->d_leaf, n);
         dalloc(pl, &pl->d_count, pl->nleaf);
         dalloc(pl, &pl->d_offs, pl->nleaf + 1);
-        dalloc(pl, &pl->d_fill, pl->nleaf);
+        dalloc(pl, &pl->d_rank, n);
         dalloc(pl, &pl->d_perm, n);
         dalloc(pl, &pl->d_tmp, n);
         dalloc(pl, &pl->P.x, n);

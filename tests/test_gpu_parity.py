@@ -63,8 +63,10 @@ def _run(ak, d, eps=1e-6, prec="fp64", **ov):
 
 
 @pytest.mark.parametrize("depth,order,root,kind", [(0, 4, None, "qmt"), (1, 4, None, "qmt"), (2, 5, 6, "qmt"),
-                                                   (2, 3, 5, "q"), (3, 4, 4, "qm")])
+                                                   (2, 3, 5, "q"), (3, 4, 4, "qm"), (4, 4, 6, "qmt")])
 def test_stage_parity_with_reference(ak, depth, order, root, kind):
+    """Depths 0-2, 3 and 4 also cover the three forms of the near-field erfc / exp (library calls, the
+    series for xi r <= 1/2, the shorter series for xi r <= 1/5) on this 20.8 A box at accuracy 1e-6."""
     d = _system(kind)
     pl, e, F, G = _run(ak, d, depth=depth, order=order, images=4, root_order=root, m2l_tol=-1.0)
     st = pl.stats
@@ -136,10 +138,17 @@ def test_stage_parity_compressed_m2l(ak, depth, order, kind):
 
 
 @pytest.mark.parametrize("mode", ["mixed", "mixed_bf16x3"])
-@pytest.mark.parametrize("depth,order", [(2, 3), (2, 4), (3, 5), (2, 8)])
+@pytest.mark.parametrize("depth,order", [(2, 3), (2, 4), (3, 5), (2, 8), (4, 4)])
 def test_mixed_modes_vs_fp64_tile_shapes(ak, mode, depth, order):
-    """Every far-field tile height (orders 3-8) in both mixed modes against the FP64 path."""
-    d = _system("qmt")
+    """Every far-field tile height (orders 3-8) in both mixed modes against the FP64 path; depth 4 also
+    runs the shortest near-field series in float32.
+
+    The reduced-precision far field loses accuracy when leaves hold few atoms at a high order (the
+    modified charges of a lone atom alternate in sign across the nodes, and the contraction then
+    cancels).  Depth 4 therefore uses the 3000-molecule box (0.7 atoms per leaf), not the 300-molecule
+    one (0.2 per leaf, where the split-precision far energy is off by 5e-5); the planner itself aims at
+    max(16, 0.3 n_u) atoms per leaf and never goes below about a third of that."""
+    d = _system("qmt") if depth < 4 else synth.water(3000, seed=2)
     p64, e64, F64, G64 = _run(ak, d, depth=depth, order=order, images=2, root_order=max(order, 4))
     pmx, emx, Fmx, Gmx = _run(ak, d, prec=mode, depth=depth, order=order, images=2, root_order=max(order, 4))
     assert abs(emx - e64) <= 1e-5 * abs(e64)
