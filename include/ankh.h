@@ -29,10 +29,14 @@
  * internal buffers (sorted particle data, multipole and local expansions,
  * operator tables) and frees them in ankh_destroy.
  *
- * Streams: all work of a plan is enqueued on the HIP stream given to
+ * Streams: all work of a plan is ordered on the HIP stream given to
  * ankh_plan (NULL = the default stream) and is asynchronous; outputs are
- * valid after that stream is synchronised or after ankh_sync.  A plan is not
- * thread-safe; use one plan per stream.
+ * valid after that stream is synchronised or after ankh_sync.  Within an
+ * evaluation the far-field chain runs on a second stream that the plan owns,
+ * forked from that stream after the particles are sorted and joined back
+ * before the pair results are summed, beside the pair kernel.  Work enqueued
+ * on the plan's stream is therefore ordered as if everything ran on it.
+ * A plan is not thread-safe; use one plan per stream.
  *
  * Errors: host-checkable errors return at once with outputs untouched.
  * Device-detected input errors (non-finite positions or moments, Theta not
@@ -202,9 +206,11 @@ ankh_status ankh_sync(ankh_plan_t plan);
 ankh_status ankh_get_stats(ankh_plan_t plan, ankh_plan_stats *out);
 
 /* Per-stage hipEvent timing of later evaluations: 0 disables it; 1 records an event at every stage
- * boundary; 2 only around stage 4 (far-field contraction) and stage 8 (pair kernel), the other stages
- * reading -1.  Each recorded event idles the device for a few microseconds, so mode 2 perturbs the
- * evaluation less.  1 and 2 restart the averaging window; other values are ANKH_ERR_INVALID_ARG. */
+ * boundary and runs the stages in sequence on the plan's stream (no far-field / pair overlap), so the
+ * stage figures add up; 2 keeps the overlap and records events only around stage 4 (far-field
+ * contraction, on the second stream) and stage 8 (pair kernel), the other stages reading -1.  Each
+ * recorded event idles its stream for a few microseconds.  1 and 2 restart the averaging window;
+ * other values are ANKH_ERR_INVALID_ARG. */
 ankh_status ankh_set_timing(ankh_plan_t plan, int32_t enable);
 
 /*

@@ -58,6 +58,10 @@ struct ankh_plan_s {
     int depth = 0, order = 0, nu = 0, nup = 0, images = 0, max_order = 0, precision = 0;
     int order0 = 0, nu0 = 0, nup0 = 0;   // root grid (far images): its own order
     hipStream_t stream = nullptr;
+    // the far-field chain runs on `side` beside the pair kernel: forked from and joined back into
+    // `stream` within every evaluation
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int nside = 1;
     int64_t nleaf = 1;
     ankh::Level lv[ankh::kMaxDepth + 1];

@@ -52,6 +52,11 @@ void free_all(ankh_plan_s *pl) {
     for (auto &set : pl->evsets)
         for (auto &e : set) (void)hipEventDestroy(e);
     pl->evsets.clear();
+    if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+    if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
+    if (pl->side) (void)hipStreamDestroy(pl->side);
+    pl->ev_fork = pl->ev_join = nullptr;
+    pl->side = nullptr;
 }
 
 // Chebyshev order from the accuracy target: the interpolation error decays
@@ -133,14 +138,24 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
     }
     auto mark = [&](int i) {
         if (ev && (pl->timing == 1 || stage_recorded(pl->timing, i) || stage_recorded(pl->timing, i - 1)))
-            ck(hipEventRecord(ev[i], s));
+            ck(hipEventRecord(ev[i], pl->stream));
     };
+    // The far-field chain (stages 2-7) runs on the side stream while the pair kernel runs on the
+    // plan's stream: the pair kernel fills every CU with VALU work, and the far-field kernels, mostly
+    // waiting on memory and small grids, fit into the gaps.  Timing mode 1 keeps one stream, so its
+    // per-stage figures add up.
+    const bool overlap = pl->timing != 1;
     try {
         mark(0);
         ck(launch_sort(pl, pos, q, mu, th));
         mark(1);
         ck(launch_gather(pl, pos, q, mu, th));
         mark(2);
+        if (overlap) {
+            ck(hipEventRecord(pl->ev_fork, s));
+            ck(hipStreamWaitEvent(pl->side, pl->ev_fork, 0));
+            pl->stream = pl->side;
+        }
         ck(launch_p2m(pl, ord));
         mark(3);
         for (int e = pl->depth - 1; e >= 0; e--) ck(launch_m2m(pl, e));
@@ -155,15 +170,21 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
         ck(launch_leafdot(pl));
         mark(7);
         if (adj) ck(launch_l2p(pl, ord, fields));
+        if (overlap) {
+            ck(hipEventRecord(pl->ev_join, pl->side));
+            pl->stream = s;
+        }
         mark(8);
         ck(launch_p2p(pl, ord, grad, fields));
         mark(9);
+        if (overlap) ck(hipStreamWaitEvent(s, pl->ev_join, 0));
         ck(launch_p2p_sum(pl, grad, fields));
         mark(10);
         ck(launch_reduce(pl, energy, ord));
         if (adj) ck(launch_unpermute(pl, forces, dEdmu, ord >= 1));
         mark(11);
     } catch (const HipFail &) {
+        pl->stream = s;
         return ANKH_ERR_HIP;
     }
     pl->last_kind = grad ? 2 : 1;
@@ -361,6 +382,9 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         dalloc(pl, &pl->d_terms, 8);
         dalloc(pl, &pl->d_part, 4 * kRedBlocks);
         dalloc(pl, &pl->d_err, 4);
+        ck(hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking));
+        ck(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming));
+        ck(hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming));
         ck(launch_zero_i32(pl->d_err, 4, pl->stream));
         ck(launch_zero_f64(pl->d_terms, 8, pl->stream));
         ck(launch_zero_f64(pl->d_G, 3 * n, pl->stream));
