@@ -139,11 +139,14 @@ void jacobi_eig(std::vector<double> &A, int n, std::vector<double> &w, std::vect
 // Batched basis change of the compressed levels, C = A B per level with
 // A [rows][K] (row stride lda), C [rows][N] (row stride ldc) and B either
 // [K][N] (TN, row stride ldb) or [N][K] (NT).  Float64.  Block tile 32 rows x 32
-// columns, 128 threads with 4 x 2 outputs each, contraction in chunks of 32
-// staged through LDS with the next chunk held in registers while the current
-// one is used.  Tiles of a level are numbered row-major (columns fastest) and
-// dealt to the 8 XCDs in contiguous runs, so the column tiles of one row tile
-// share an L2.  Strides and bases are even (16-byte pairs of doubles).
+// columns; the 4 waves of a block split the contraction (wave w takes chunks
+// w, w + 4, ... of 16), each accumulating the whole tile (4 x 4 outputs per
+// lane) from its own LDS slice with the next chunk held in registers; the 4
+// partial tiles are summed through LDS in wave order at the end.  The short
+// per-wave chain keeps the launch from waiting on one long dependent sequence.
+// Tiles of a level are numbered row-major (columns fastest) and dealt to the
+// 8 XCDs in contiguous runs, so the column tiles of one row tile share an L2.
+// Strides and bases are even (16-byte pairs of doubles).
 struct BasisLevel {
     const double *A;
     const double *B;
@@ -155,11 +158,12 @@ struct BasisJob {
     BasisLevel lv[kMaxBasisLevels];
     int nlv, ntiles, per_xcd;
 };
-constexpr int BT = 32, BKC = 32;
+constexpr int BT = 32, BKC = 16, BW = 4;   // tile, chunk, waves per block
 
 template <bool NT>
-__global__ __launch_bounds__(128) void k_basis(BasisJob job) {
-    __shared__ double As[BKC][BT + 1], Bs[BKC][BT + 1];
+__global__ __launch_bounds__(256) void k_basis(BasisJob job) {
+    // per wave: A chunk [16][33] and B chunk [16][33]; reused for the final sum [4][32][33]
+    __shared__ double lds[BW * 2 * BKC * (BT + 1)];
     const int b = blockIdx.x;
     const int v = (b % 8) * job.per_xcd + b / 8;
     if (v >= job.ntiles) return;
@@ -168,65 +172,84 @@ __global__ __launch_bounds__(128) void k_basis(BasisJob job) {
     const BasisLevel L = job.lv[li];
     const int tl = v - L.tile0;
     const int m0 = (tl / L.ntn) * BT, n0 = (tl % L.ntn) * BT;
-    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-    // loader roles: 4 pairs of doubles per operand per thread
-    // A: row = idx / 16, pair = idx % 16 (contiguous along K)
-    // B TN: k = idx / 16, pair along N;  B NT: n = idx / 16, pair along K
-    // K and N are multiples of the chunk and tile widths (host-checked); rows of
-    // A beyond the level are clamped to its last row and their results dropped.
+    const int wv = threadIdx.x / 64, ln = threadIdx.x % 64, tx = ln % 8, ty = ln / 8;
+    double(*As)[BT + 1] = reinterpret_cast<double(*)[BT + 1]>(lds + wv * 2 * BKC * (BT + 1));
+    double(*Bs)[BT + 1] = reinterpret_cast<double(*)[BT + 1]>(lds + (wv * 2 + 1) * BKC * (BT + 1));
+    // K and N are multiples of the chunk and tile widths (host-checked); rows of A beyond the level
+    // are clamped to its last row and their results dropped.  A wave past the last chunk loads zeros.
+    const int nchunk = L.K / BKC, steps = (nchunk + BW - 1) / BW;
     double2 ra[4], rb[4];
-    auto load = [&](int k0) {
+    auto load = [&](int c) {
+        const bool ok = c < nchunk;
+        const int k0 = c * BKC;
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-            const int idx = tid + 128 * q, r = idx / 16, p = 2 * (idx % 16);
+            const int idx = ln + 64 * q;
+            const int r = idx / 8, p = 2 * (idx % 8);          // A and B (NT): 32 rows x 8 pairs
             const int m = min(m0 + r, L.rows - 1);
-            ra[q] = *reinterpret_cast<const double2 *>(L.A + (int64_t)m * L.lda + k0 + p);
-            rb[q] = NT ? *reinterpret_cast<const double2 *>(L.B + (int64_t)(n0 + r) * L.ldb + k0 + p)
-                       : *reinterpret_cast<const double2 *>(L.B + (int64_t)(k0 + r) * L.ldb + n0 + p);
+            ra[q] = ok ? *reinterpret_cast<const double2 *>(L.A + (int64_t)m * L.lda + k0 + p) : double2{0.0, 0.0};
+            if (NT) {
+                rb[q] = ok ? *reinterpret_cast<const double2 *>(L.B + (int64_t)(n0 + r) * L.ldb + k0 + p)
+                           : double2{0.0, 0.0};
+            } else {
+                const int rk = idx / 16, pn = 2 * (idx % 16);   // B (TN): 16 rows of K x 16 pairs along N
+                rb[q] = ok ? *reinterpret_cast<const double2 *>(L.B + (int64_t)(k0 + rk) * L.ldb + n0 + pn)
+                           : double2{0.0, 0.0};
+            }
         }
     };
     auto store = [&]() {
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-            const int idx = tid + 128 * q, r = idx / 16, p = 2 * (idx % 16);
+            const int idx = ln + 64 * q;
+            const int r = idx / 8, p = 2 * (idx % 8);
             As[p][r] = ra[q].x;
             As[p + 1][r] = ra[q].y;
             if (NT) {
                 Bs[p][r] = rb[q].x;
                 Bs[p + 1][r] = rb[q].y;
             } else {
-                Bs[r][p] = rb[q].x;
-                Bs[r][p + 1] = rb[q].y;
+                const int rk = idx / 16, pn = 2 * (idx % 16);
+                Bs[rk][pn] = rb[q].x;
+                Bs[rk][pn + 1] = rb[q].y;
             }
         }
     };
-    double acc[4][2] = {};
-    load(0);
-    for (int k0 = 0; k0 < L.K; k0 += BKC) {
+    double acc[4][4] = {};
+    load(wv);
+    for (int t = 0; t < steps; t++) {
+        __syncthreads();   // the previous chunk's reads are done
         store();
         __syncthreads();
-        if (k0 + BKC < L.K) load(k0 + BKC);
-#pragma unroll 8
+        if (t + 1 < steps) load(wv + BW * (t + 1));
+#pragma unroll
         for (int kk = 0; kk < BKC; kk++) {
-            double a[4], bb[2];
+            double a[4], bb[4];
 #pragma unroll
             for (int i = 0; i < 4; i++) a[i] = As[kk][ty + 8 * i];
 #pragma unroll
-            for (int j = 0; j < 2; j++) bb[j] = Bs[kk][tx + 16 * j];
+            for (int j = 0; j < 4; j++) bb[j] = Bs[kk][tx + 8 * j];
 #pragma unroll
             for (int i = 0; i < 4; i++)
 #pragma unroll
-                for (int j = 0; j < 2; j++) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
+                for (int j = 0; j < 4; j++) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
         }
-        __syncthreads();
     }
+    // the 4 waves' partial tiles, summed in wave order
+    __syncthreads();
+    double(*red)[BT][BT + 1] = reinterpret_cast<double(*)[BT][BT + 1]>(lds);
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) {
-            const int m = m0 + ty + 8 * i, n = n0 + tx + 16 * j;
-            if (m < L.rows) L.C[(int64_t)m * L.ldc + n] = acc[i][j];
-        }
+        for (int j = 0; j < 4; j++) red[wv][ty + 8 * i][tx + 8 * j] = acc[i][j];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int o = threadIdx.x + 256 * q, r = o / BT, c = o % BT;
+        const int m = m0 + r;
+        const double sum = (red[0][r][c] + red[1][r][c]) + (red[2][r][c] + red[3][r][c]);
+        if (m < L.rows) L.C[(int64_t)m * L.ldc + n0 + c] = sum;
+    }
 }
 
 }  // namespace
@@ -263,9 +286,9 @@ hipError_t launch_m2l_basis(ankh_plan_s *pl, bool expand) {
     job.per_xcd = (nt + 7) / 8;
     const dim3 grid((unsigned)(8 * job.per_xcd));
     if (expand)
-        hipLaunchKernelGGL(k_basis<true>, grid, dim3(128), 0, pl->stream, job);
+        hipLaunchKernelGGL(k_basis<true>, grid, dim3(256), 0, pl->stream, job);
     else
-        hipLaunchKernelGGL(k_basis<false>, grid, dim3(128), 0, pl->stream, job);
+        hipLaunchKernelGGL(k_basis<false>, grid, dim3(256), 0, pl->stream, job);
     return hipGetLastError();
 }
 
