@@ -51,6 +51,9 @@ def lib():
         L.oracle_near_field.restype = ctypes.c_int
         L.oracle_near_field.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.oracle_ewald_moments.restype = ctypes.c_int
+        L.oracle_ewald_moments.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_dtensor.restype = ctypes.c_int
         L.oracle_dtensor.argtypes = [dp, ctypes.c_double, ctypes.c_int, dp]
         _lib = L
@@ -111,6 +114,27 @@ def ewald(pos, q, mu=None, theta=None, edge=None, eps: float = 1e-10, alpha: flo
         out["forces"] = F
         out["dEdmu"] = G
     return out
+
+
+def ewald_moments(pos, q, mu=None, theta=None, edge=None, eps: float = 1e-10, alpha: float | None = None,
+                  nthreads: int = 0):
+    """dE/dq [n] and dE/dTheta [n][6] of the classical Ewald energy.  E is defined for traceless Theta,
+    so dE/dTheta is the traceless part of the full-tensor derivative per stored component
+    (xx, xy, xz, yy, yz, zz) = (G_xx, 2 G_xy, 2 G_xz, G_yy, 2 G_yz, G_zz): its dot product with any
+    traceless change of the stored components is the change of E."""
+    pos = _c64(pos, (-1, 3))
+    n = pos.shape[0]
+    q = _c64(q, (n,))
+    mu = _c64(mu, (n, 3))
+    theta = _c64(theta, (n, 6))
+    a, r, k = ewald_params(n, edge, eps, alpha)
+    dq = np.zeros(n)
+    dth = np.zeros((n, 6))
+    rcode = lib().oracle_ewald_moments(n, _p(pos), _p(q), _p(mu), _p(theta), float(edge), float(a), float(r),
+                                       int(k), int(nthreads), _p(dq), _p(dth))
+    if rcode != 0:
+        raise ValueError(f"oracle_ewald_moments failed ({rcode})")
+    return dict(dEdq=dq, dEdtheta=dth, alpha=a, rc=r, kmax=k)
 
 
 def ewald_sites(pos, q, mu, theta, edge, sel, eps: float = 1e-10, alpha: float | None = None,

@@ -30,7 +30,8 @@
  *                prod(delta over the pairs) prod(r over the unpaired indices),
  * enumerated explicitly for every index tuple (no hand-expanded formulas).
  *
- * Forces are -dE/dx_i; fields are dE/dmu_i.  Sums are gathered per atom in
+ * Forces are -dE/dx_i; fields are dE/dmu_i; oracle_ewald_moments gives
+ * dE/dq_i and the traceless part of dE/dTheta_i.  Sums are gathered per atom in
  * a fixed order and reduced serially, so results are run-to-run identical
  * for a given thread count.
  */
@@ -538,6 +539,135 @@ int oracle_ewald(int64_t n, const double *pos, const double *q, const double *mu
     energy_out[3] = eb;
     energy_out[4] = er + erec + es + eb;
     free(ereal); free(eself);
+    rec_free(&rc);
+    ctx_free(&c);
+    return 0;
+}
+
+/* ---- derivatives in the charges and quadrupoles ------------------------ */
+/* dE/dq_i and dE/dTheta_i (full symmetric 3x3, before projection) of the
+ * real-space sum: d/dq_i of the pair functional is q_j T - mu_j.T1 + Th_j:T2,
+ * d/dTh_i,ab is q_j T2_ab - (T3 mu_j)_ab + (T4:Th_j)_ab. */
+static void real_moments(const ctx_t *c, int64_t i, double *phi, double G[9])
+{
+    const double L = c->L, wc = L / c->nc;
+    const int nc = c->nc, R = c->R;
+    const double *xi = c->pos + 3 * i;
+    const int nmax = 2 + c->order;   /* T2 with q_j, T3 with mu_j, T4 with Theta_j */
+    double B[MAXRANK + 2];
+    static __thread double T[MAXRANK + 1][NTUPLE5];
+    double p = 0, g[9] = {0};
+    int ci[3];
+    for (int d = 0; d < 3; d++) {
+        int v = (int)floor((xi[d] + 0.5 * L) / wc);
+        if (v < 0) v = 0;
+        if (v >= nc) v = nc - 1;
+        ci[d] = v;
+    }
+    const double rc2 = c->rc * c->rc;
+    for (int dx = -R; dx <= R; dx++)
+    for (int dy = -R; dy <= R; dy++)
+    for (int dz = -R; dz <= R; dz++) {
+        int u[3] = {ci[0] + dx, ci[1] + dy, ci[2] + dz};
+        int w[3];
+        double sh[3];
+        for (int d = 0; d < 3; d++) {
+            int m = (int)floor((double)u[d] / nc);
+            w[d] = u[d] - m * nc;
+            sh[d] = m * L;
+        }
+        int cell = (w[0] * nc + w[1]) * nc + w[2];
+        for (int q = c->cell_start[cell]; q < c->cell_start[cell + 1]; q++) {
+            int j = c->cell_atoms[q];
+            double r[3];
+            for (int d = 0; d < 3; d++) r[d] = xi[d] - (c->pos[3 * j + d] + sh[d]);
+            double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            if (r2 >= rc2) continue;
+            if (j == i && sh[0] == 0 && sh[1] == 0 && sh[2] == 0) continue;
+            radial(r2, c->a, nmax, B);
+            dtensors(r, B, nmax, T);
+            const double qj = c->q[j];
+            const double *mj = c->mu ? c->mu + 3 * j : NULL;
+            const double *Tj = c->Th ? c->Th + 9 * j : NULL;
+            p += qj * T[0][0];
+            if (mj) for (int a = 0; a < 3; a++) p -= mj[a] * T[1][a];
+            if (Tj) for (int a = 0; a < 9; a++) p += Tj[a] * T[2][a];
+            for (int ab = 0; ab < 9; ab++) {
+                double v = qj * T[2][ab];
+                if (mj) for (int cc = 0; cc < 3; cc++) v -= T[3][ab * 3 + cc] * mj[cc];
+                if (Tj) for (int cd = 0; cd < 9; cd++) v += T[4][ab * 9 + cd] * Tj[cd];
+                g[ab] += v;
+            }
+        }
+    }
+    *phi = p;
+    for (int ab = 0; ab < 9; ab++) G[ab] = g[ab];
+}
+
+/* reciprocal part: with w = exp(i k.r_i) conj(S(k)) over the half-space list,
+ * dE/dq_i = (8 pi / V) sum g Re w and dE/dTh_i,ab = -(8 pi / V) sum g k_a k_b Re w */
+static void rec_moments(const ctx_t *c, const rec_t *rc, int64_t i, double *phi, double G[9])
+{
+    const int K = c->kmax, W = 2 * K + 1;
+    const double L = c->L, V = L * L * L;
+    double p = 0, g[9] = {0};
+    for (int t = 0; t < rc->nk; t++) {
+        const int *m = rc->m + 3 * t;
+        double k[3] = {2 * M_PI * m[0] / L, 2 * M_PI * m[1] / L, 2 * M_PI * m[2] / L};
+        double pr = 1, pi = 0;
+        for (int d = 0; d < 3; d++) {
+            double er = rc->ex_re[((size_t)i * 3 + d) * W + m[d] + K];
+            double ei = rc->ex_im[((size_t)i * 3 + d) * W + m[d] + K];
+            double nr = pr * er - pi * ei, ni = pr * ei + pi * er;
+            pr = nr; pi = ni;
+        }
+        double wr = pr * rc->Sre[t] + pi * rc->Sim[t];
+        p += rc->g[t] * wr;
+        for (int a = 0; a < 3; a++) for (int b = 0; b < 3; b++) g[a * 3 + b] -= rc->g[t] * k[a] * k[b] * wr;
+    }
+    *phi = (8 * M_PI / V) * p;
+    for (int ab = 0; ab < 9; ab++) G[ab] = (8 * M_PI / V) * g[ab];
+}
+
+/*
+ * dE/dq [n] and dE/dTheta [n][6] (either may be NULL).  E is defined for
+ * traceless Theta only, so the quadrupole derivative is the traceless part G
+ * of the full-tensor derivative, reported per stored component: (xx, xy, xz,
+ * yy, yz, zz) = (G_xx, 2 G_xy, 2 G_xz, G_yy, 2 G_yz, G_zz); then
+ * sum dE/dTheta . dTheta = dE for every traceless change dTheta.
+ */
+int oracle_ewald_moments(int64_t n, const double *pos, const double *q, const double *mu, const double *theta,
+                         double edge, double alpha, double rcut, int kmax, int nthreads,
+                         double *dEdq, double *dEdth)
+{
+    if (n <= 0 || !pos || !q || edge <= 0 || alpha <= 0 || rcut <= 0 || kmax < 0) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    ctx_t c;
+    ctx_init(&c, n, pos, q, mu, theta, edge, alpha, rcut, kmax);
+    rec_t rc;
+    rec_build(&c, &rc);
+    const double Q = psum(q, n), V = edge * edge * edge, a = alpha, sp = sqrt(M_PI);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < n; i++) {
+        double p1, p2, G1[9], G2[9], G[9];
+        real_moments(&c, i, &p1, G1);
+        rec_moments(&c, &rc, i, &p2, G2);
+        /* self: -(a/sqrt(pi)) (q^2 + 8a^4/5 Th:Th); background: -pi Q^2 / (2 V a^2) */
+        const double ps = -(a / sp) * 2 * q[i] - M_PI * Q / (V * a * a);
+        for (int ab = 0; ab < 9; ab++) {
+            G[ab] = G1[ab] + G2[ab];
+            if (c.Th) G[ab] += -(a / sp) * (8 * a * a * a * a / 5) * 2 * c.Th[9 * i + ab];
+        }
+        if (dEdq) dEdq[i] = p1 + p2 + ps;
+        if (dEdth) {
+            const double tr = (G[0] + G[4] + G[8]) / 3;
+            double *o = dEdth + 6 * i;
+            o[0] = G[0] - tr; o[1] = G[1] + G[3]; o[2] = G[2] + G[6];
+            o[3] = G[4] - tr; o[4] = G[5] + G[7]; o[5] = G[8] - tr;
+        }
+    }
     rec_free(&rc);
     ctx_free(&c);
     return 0;

@@ -14,6 +14,9 @@ them:
   mu . grad and Theta : grad grad (no 1/2 or 1/3 factor);
 * brute-force cube sums on tiny cells: the summation convention of eq. (1);
 * finite differences: forces -dE/dx and fields dE/dmu;
+* potentials dE/dq: the rock-salt site potential -M/r0 and finite differences;
+* quadrupole derivatives dE/dTheta: a point charge's field gradient and
+  finite differences along traceless directions;
 * derivative tensors: rank n+1 equals the gradient of rank n.
 """
 import math
@@ -213,6 +216,49 @@ def test_forces_fields_finite_difference(oracle_lib):
             e1 = oracle_lib.ewald(pos, q, m1, th, edge=edge, eps=EPS, alpha=0.45, grad=False)["energy"]
             e2 = oracle_lib.ewald(pos, q, m2, th, edge=edge, eps=EPS, alpha=0.45, grad=False)["energy"]
             assert (e1 - e2) / (2 * h) == pytest.approx(o["dEdmu"][i, d], rel=1e-7, abs=1e-9)
+
+
+def test_potential_rock_salt_site(oracle_lib):
+    # every site of a rock-salt crystal sits at potential -q_i M / r0 (r0 = 1: nearest neighbours)
+    d = synth.nacl_conventional(2, 2.0)
+    m = oracle_lib.ewald_moments(d["pos"], d["q"], edge=d["edge"], eps=EPS)
+    np.testing.assert_allclose(m["dEdq"], -d["q"] * 1.747564594633, rtol=1e-11)
+
+
+def test_field_gradient_of_a_point_charge(oracle_lib):
+    # a charge q at the origin and a bare quadrupole at r z in a box much larger than r: dE/dTheta is
+    # q d_a d_b (1/r) = q (3 r_a r_b - r^2 delta_ab) / r^5, per stored component (xy, xz, yz doubled);
+    # the images and the background add an isotropic part (removed with the trace) and
+    # anisotropic parts of relative size (r / L)^3
+    L, r, qc = 200.0, 2.5, 0.7
+    pos = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, r]])
+    th = np.zeros((2, 6))
+    th[1] = [0.1, 0.05, -0.02, 0.2, 0.03, -0.3]
+    m = oracle_lib.ewald_moments(pos, np.array([qc, 0.0]), None, th, edge=L, eps=EPS)
+    c = qc / r ** 3
+    np.testing.assert_allclose(m["dEdtheta"][1], [-c, 0, 0, -c, 0, 2 * c], rtol=1e-5, atol=1e-6 * c)
+
+
+def test_moment_derivatives_finite_difference(oracle_lib):
+    pos, q, mu, th, edge = _rand_system(19, n=16)
+    m = oracle_lib.ewald_moments(pos, q, mu, th, edge=edge, eps=EPS, alpha=0.45)
+    E = lambda q_, th_: oracle_lib.ewald(pos, q_, mu, th_, edge=edge, eps=EPS, alpha=0.45, grad=False)["energy"]
+    h = 1e-5
+    for i in (0, 9):
+        q1, q2 = q.copy(), q.copy()
+        q1[i] += h
+        q2[i] -= h
+        assert (E(q1, th) - E(q2, th)) / (2 * h) == pytest.approx(m["dEdq"][i], rel=1e-7, abs=1e-9)
+        # traceless directions of the stored components
+        for dl in ([0, 1, 0, 0, 0, 0], [0, 0, 1, 0, 0, 0], [0, 0, 0, 0, 1, 0], [1, 0, 0, -1, 0, 0],
+                   [1, 0, 0, 0, 0, -1]):
+            dl = np.array(dl, dtype=np.float64)
+            t1, t2 = th.copy(), th.copy()
+            t1[i] += h * dl
+            t2[i] -= h * dl
+            assert (E(q, t1) - E(q, t2)) / (2 * h) == pytest.approx(m["dEdtheta"][i] @ dl, rel=1e-7, abs=1e-9)
+    # the reported derivative is traceless
+    np.testing.assert_allclose(m["dEdtheta"][:, 0] + m["dEdtheta"][:, 3] + m["dEdtheta"][:, 5], 0, atol=1e-12)
 
 
 def test_sites_match_full(oracle_lib):
