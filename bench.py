@@ -119,6 +119,22 @@ def induce_run(plan, args_dev, alpha, tol, torch, dev, reps=3):
                     "energy and forces (it + 2 evaluations)", "_mu": mi.cpu().numpy()}
 
 
+def derivs_run(plan, args_dev, torch, reps=5):
+    """Wall time of one evaluation with every derivative (forces, fields, dE/dq, dE/dTheta) against
+    energy + forces + fields alone; returns the outputs of the last call too."""
+    plan.energy_derivs(*args_dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = plan.energy_derivs(*args_dev)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    return {"ms_all_derivs": ms, "reps": reps,
+            "note": "energy, forces, dE/dmu, dE/dq and dE/dTheta in one call (ankh_energy_derivs); the "
+                    "charge and quadrupole derivatives add a gather-form pass over the near pairs and one over "
+                    "the atoms"}, out
+
+
 def cpu_baseline(data, eps):
     """The classical-Ewald oracle on a bounded cut-out of the same water box."""
     import oracle
@@ -149,6 +165,7 @@ def main():
     ap.add_argument("--mode", default="mixed_bf16x3", choices=["mixed", "mixed_bf16x3"],
                     help="precision mode of the headline (mixed) path")
     ap.add_argument("--no-induce", action="store_true", help="skip the induced-dipole solve")
+    ap.add_argument("--no-derivs", action="store_true", help="skip the charge / quadrupole derivative timing")
     ap.add_argument("--induce-tol", type=float, default=1e-6)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the timed region, one device-to-device copy of this many MiB (a plain copy kernel "
@@ -191,6 +208,12 @@ def main():
     t_mixed, st_mixed, bd_mixed, out_mixed = timed_run(pm, args_dev, args.steps, args.warmup, torch)
     log(f"mixed: {t_mixed * 1e3:.3f} ms/step timed stages {st_mixed['stage_ms']} breakdown {bd_mixed}")
 
+    derivs = None
+    if not args.no_derivs:
+        derivs, dmix = derivs_run(pm, args_dev, torch)
+        derivs["ms_energy_forces_fields"] = t_mixed * 1e3
+        log(f"derivs: {derivs}")
+
     induce = None
     if not args.no_induce and args.workload.startswith("water"):
         induce = induce_run(pm, args_dev, synth.water_polarisabilities(n // 3), args.induce_tol, torch, dev)
@@ -200,6 +223,12 @@ def main():
     if not args.mixed_only:
         pf = ak.Plan(n, rB, args.eps, 2, "fp64")
         t_fp64, st_fp64, bd_fp64, out_fp64 = timed_run(pf, args_dev, args.steps, args.warmup, torch)
+        if derivs is not None:
+            d64, dfp = derivs_run(pf, args_dev, torch)
+            derivs["fp64"] = {"ms_all_derivs": d64["ms_all_derivs"], "ms_energy_forces_fields": t_fp64 * 1e3}
+            derivs["mixed_vs_fp64"] = {
+                "rel_rms_dEdq": rel_rms(dmix["dEdq"].cpu().numpy(), dfp["dEdq"].cpu().numpy()),
+                "rel_rms_dEdtheta": rel_rms(dmix["dEdtheta"].cpu().numpy(), dfp["dEdtheta"].cpu().numpy())}
         if induce is not None:
             ind64 = induce_run(pf, args_dev, synth.water_polarisabilities(n // 3), args.induce_tol, torch, dev,
                                reps=1)
@@ -274,6 +303,8 @@ def main():
         "roofline_" + other["kernel"]: other,
     }
     line.update(res)
+    if derivs is not None:
+        line["derivs"] = derivs
     if induce is not None:
         induce.pop("_mu", None)
         line["induce"] = induce

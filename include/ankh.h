@@ -158,6 +158,33 @@ ankh_status ankh_energy_forces(ankh_plan_t plan, const double *pos, const double
                                const double *theta, double *energy, double *forces, double *dE_dmu);
 
 /*
+ * ankh_energy_derivs: the energy with any of its derivatives in the atoms'
+ * positions and moments (the q, mu, Theta of eq. 1), the adjoint of the same
+ * approximation.  The paper evaluates the energy and names forces as a
+ * direct perspective of the method; these are the derivatives in every
+ * input of the energy.
+ *   energy    [1]     device output, not NULL.
+ *   forces    [n][3]  device output or NULL: -dE/dx.
+ *   dE_dmu    [n][3]  device output or NULL: dE/dmu (zeros without dipoles).
+ *   dE_dq     [n]     device output or NULL: dE/dq_i, the potential of all
+ *                     other moments (and the atom's periodic images) at atom
+ *                     i, with the self and neutralising-background terms.
+ *   dE_dtheta [n][6]  device output or NULL: dE/dTheta_i.  E is defined for
+ *                     traceless Theta only, so this is the traceless part G of
+ *                     the full-tensor derivative, per stored component
+ *                     (xx, xy, xz, yy, yz, zz) = (G_xx, 2 G_xy, 2 G_xz, G_yy,
+ *                     2 G_yz, G_zz): for every traceless change dTheta of the
+ *                     stored components, sum dE_dtheta . dTheta = dE.  Needs a
+ *                     plan with max_order 2; defined also when theta is NULL.
+ * The charge and quadrupole derivatives cost one more pass over the near
+ * pairs (gather form, in the plan's precision) and one over the atoms for the
+ * far field.  The plan allocates 7 n doubles for them on the first call.
+ */
+ankh_status ankh_energy_derivs(ankh_plan_t plan, const double *pos, const double *q, const double *mu,
+                               const double *theta, double *energy, double *forces, double *dE_dmu,
+                               double *dE_dq, double *dE_dtheta);
+
+/*
  * ankh_induce: induced dipoles of isotropic point polarisabilities, the
  * polarizable use of the method that the paper's introduction names (the
  * moments of eq. 1 extended by induced dipoles).  The induced dipoles are the

@@ -3,7 +3,7 @@
 Argument marshalling only: every step of an evaluation runs in the HIP
 kernels behind the C ABI declared in include/ankh.h.  The functions below
 carry the C names (`ankh_plan`, `ankh_energy`, `ankh_energy_forces`,
-`ankh_induce`, ...);
+`ankh_energy_derivs`, `ankh_induce`, ...);
 `Plan` wraps a plan handle and `AnkhEnergy` is the autograd function whose
 backward returns -g F for the positions and g dE/dmu for the dipoles.
 
@@ -57,7 +57,8 @@ class _Stats(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["ankh_plan", "ankh_energy", "ankh_energy_forces", "ankh_sync", "ankh_get_stats", "ankh_set_timing",
-           "ankh_last_terms", "ankh_leaf_multipoles", "ankh_destroy", "ankh_status_string", "ankh_induce"]
+           "ankh_last_terms", "ankh_leaf_multipoles", "ankh_destroy", "ankh_status_string", "ankh_induce",
+           "ankh_energy_derivs"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -76,6 +77,8 @@ def load_library(path: str = LIB_PATH):
     L.ankh_energy.argtypes = [vp, dp, dp, dp, dp, dp]
     L.ankh_energy_forces.restype = ctypes.c_int
     L.ankh_energy_forces.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp]
+    L.ankh_energy_derivs.restype = ctypes.c_int
+    L.ankh_energy_derivs.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
     L.ankh_induce.restype = ctypes.c_int
     L.ankh_induce.argtypes = [vp, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int32, dp, dp, dp,
                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
@@ -146,6 +149,11 @@ def ankh_energy(plan, pos, q, mu, theta, energy):
 
 def ankh_energy_forces(plan, pos, q, mu, theta, energy, forces, dE_dmu):
     _check(load_library().ankh_energy_forces(plan, pos, q, mu, theta, energy, forces, dE_dmu), "ankh_energy_forces")
+
+
+def ankh_energy_derivs(plan, pos, q, mu, theta, energy, forces, dE_dmu, dE_dq, dE_dtheta):
+    _check(load_library().ankh_energy_derivs(plan, pos, q, mu, theta, energy, forces, dE_dmu, dE_dq, dE_dtheta),
+           "ankh_energy_derivs")
 
 
 def ankh_induce(plan, pos, q, mu, theta, alpha, tol, max_iter, mu_ind, energy, forces):
@@ -238,6 +246,26 @@ class Plan:
         ankh_energy_forces(self.handle, pp, qp, mp, tp, ctypes.c_void_p(e.data_ptr()),
                            ctypes.c_void_p(F.data_ptr()), None if G is None else ctypes.c_void_p(G.data_ptr()))
         return e, F, G
+
+    def energy_derivs(self, pos, q, mu=None, theta=None, forces=True, fields=True, potentials=True,
+                      theta_grad=True):
+        """Energy and the requested derivatives (see ankh_energy_derivs in ankh.h): a dict with "energy"
+        and, as asked, "forces" -dE/dx, "dEdmu", "dEdq" [n] and "dEdtheta" [n][6]."""
+        keep, (pp, qp, mp, tp) = self._args(pos, q, mu, theta)
+        dev = pos.device
+        out = {"energy": torch.empty(1, dtype=torch.float64, device=dev)}
+        if forces:
+            out["forces"] = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        if fields:
+            out["dEdmu"] = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        if potentials:
+            out["dEdq"] = torch.empty(self.n, dtype=torch.float64, device=dev)
+        if theta_grad:
+            out["dEdtheta"] = torch.empty((self.n, 6), dtype=torch.float64, device=dev)
+        ptr = lambda k: ctypes.c_void_p(out[k].data_ptr()) if k in out else None
+        ankh_energy_derivs(self.handle, pp, qp, mp, tp, ptr("energy"), ptr("forces"), ptr("dEdmu"), ptr("dEdq"),
+                           ptr("dEdtheta"))
+        return out
 
     def induce(self, pos, q, mu, theta, alpha, tol=1e-8, max_iter=100, energy=True, forces=False,
                check=True):

@@ -113,6 +113,7 @@ struct ankh_plan_s {
     double *d_part = nullptr;     // reduction partials
     int32_t *d_err = nullptr;     // latched device errors [4]: non-finite, theta trace, invalid value
     double *d_ind = nullptr;      // induced-dipole solver vectors (allocated by the first ankh_induce)
+    double *d_mom = nullptr;      // near-field dE/dq, dE/dTheta [7][n] (allocated by the first ankh_energy_derivs)
     size_t bytes = 0;
 
     // statistics / timing
@@ -154,6 +155,10 @@ hipError_t launch_m2l_expand(ankh_plan_s *pl);    // all compressed levels: L = 
 inline bool is_mixed(const ankh_plan_s *pl) { return pl->precision != ANKH_FP64; }
 hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields);
 hipError_t launch_p2p_sum(ankh_plan_s *pl, bool grad, bool fields);
+// derivatives in the charges and quadrupoles: near part into near [7][n] (leaf order), then the far
+// part, self and background terms and the output in caller order
+hipError_t launch_p2p_moments(ankh_plan_s *pl, int ord, double *near);
+hipError_t launch_l2p_moments(ankh_plan_s *pl, int ord, const double *near, double *dEdq, double *dEdth);
 // one evaluation of the path (the body of ankh_energy / ankh_energy_forces; inputs already checked);
 // forces == nullptr with dEdmu != nullptr is a fields-only evaluation
 ankh_status evaluate(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th,

@@ -718,6 +718,91 @@ __global__ void k_build_cper(double *C, const double *tab, int L, int nu, int nu
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Far-field derivatives in the charges and quadrupoles, then the output: per
+// leaf-order atom, the leaf's local expansion against the basis values
+// (dE/dq) and its second derivatives (dE/dTh, full symmetric), added to the
+// near-field part (near [7][n]), the self terms -(2 xi / sqrt(pi)) q and
+// -(xi / sqrt(pi)) (8 xi^4 / 5) 2 Th, and the background -pi Q / (V xi^2).
+// dE/dTh is reported as its traceless part per stored component (xx, xy, xz,
+// yy, yz, zz) = (G_xx - t, 2 G_xy, 2 G_xz, G_yy - t, 2 G_yz, G_zz - t),
+// t = tr G / 3: E is defined for traceless Theta only.  Written in caller order.
+template <int L>
+__global__ __launch_bounds__(256) void k_l2p_moments(Particles P, const int32_t *leaf_in, const int32_t *perm,
+                                                     const double *tab, int nup, double hinv, const double *Lam,
+                                                     const double *near, const double *terms, double xi, double vol,
+                                                     int ord, double *dEdq, double *dEdth, int64_t n) {
+    constexpr int ND = 3;
+    __shared__ double sH[L * L];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < L * L; t += 256) sH[t] = tab[L + t];
+    __syncthreads();
+    const int64_t s = blockIdx.x * (int64_t)256 + tid;
+    if (s >= n) return;
+    const double *lam = Lam + (int64_t)leaf_in[perm[s]] * nup;
+    double Sx[ND * L], Sy[ND * L], Sz[ND * L];
+    cheb_basis<ND, L>(P.x[s] * hinv, hinv, sH, Sx, L);
+    cheb_basis<ND, L>(P.y[s] * hinv, hinv, sH, Sy, L);
+    cheb_basis<ND, L>(P.z[s] * hinv, hinv, sH, Sz, L);
+    double phi[ND][ND][ND];
+#pragma unroll
+    for (int x = 0; x < ND; x++)
+#pragma unroll
+        for (int y = 0; y < ND; y++)
+#pragma unroll
+            for (int z = 0; z < ND; z++) phi[x][y][z] = 0;
+#pragma unroll
+    for (int i = 0; i < L; i++) {
+        double h[ND][ND];
+#pragma unroll
+        for (int y = 0; y < ND; y++)
+#pragma unroll
+            for (int z = 0; z < ND; z++) h[y][z] = 0;
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            double g[ND] = {0, 0, 0};
+            const double *row = lam + (i * L + j) * L;
+#pragma unroll
+            for (int k = 0; k < L; k++) {
+                const double lv = row[k];
+#pragma unroll
+                for (int z = 0; z < ND; z++) g[z] += lv * Sz[z * L + k];
+            }
+#pragma unroll
+            for (int y = 0; y < ND; y++)
+#pragma unroll
+                for (int z = 0; z + y < ND; z++) h[y][z] += Sy[y * L + j] * g[z];
+        }
+#pragma unroll
+        for (int x = 0; x < ND; x++)
+#pragma unroll
+            for (int y = 0; x + y < ND; y++)
+#pragma unroll
+                for (int z = 0; x + y + z < ND; z++) phi[x][y][z] += Sx[x * L + i] * h[y][z];
+    }
+    const double sp = sqrt(kPi);
+    const int64_t i = perm[s];
+    if (dEdq) {
+        const double Q = terms[6];
+        dEdq[i] = near[s] + phi[0][0][0] - (2 * xi / sp) * P.q[s] - kPi * Q / (vol * xi * xi);
+    }
+    if (dEdth) {
+        double G[6] = {near[n + s] + phi[2][0][0], near[2 * n + s] + phi[1][1][0], near[3 * n + s] + phi[1][0][1],
+                       near[4 * n + s] + phi[0][2][0], near[5 * n + s] + phi[0][1][1], near[6 * n + s] + phi[0][0][2]};
+        if (ord >= 2) {
+            const double cs = -(xi / sp) * (8 * xi * xi * xi * xi / 5) * 2;
+            for (int c = 0; c < 6; c++) G[c] += cs * P.th[c * n + s];
+        }
+        const double t = (G[0] + G[3] + G[5]) / 3;
+        double *o = dEdth + 6 * i;
+        o[0] = G[0] - t;
+        o[1] = 2 * G[1];
+        o[2] = 2 * G[2];
+        o[3] = G[3] - t;
+        o[4] = 2 * G[4];
+        o[5] = G[5] - t;
+    }
+}
+
 }  // namespace
 
 // ---- launchers ---------------------------------------------------------------
@@ -863,6 +948,20 @@ hipError_t launch_l2p(ankh_plan_s *pl, int ord, bool fields) {
     ANKH_FOR_ORDER(L, ANKH_L2P)
 #undef ANKH_L2P3
 #undef ANKH_L2P
+    return hipGetLastError();
+}
+
+hipError_t launch_l2p_moments(ankh_plan_s *pl, int ord, const double *near, double *dEdq, double *dEdth) {
+    const int L = pl->order;
+    const double hinv = 2.0 / (pl->edge / pl->nside);
+    const double *Lam = pl->d_L + pl->lv[pl->depth].cell0 * pl->nup;
+    const double vol = pl->edge * pl->edge * pl->edge;
+    dim3 g((unsigned)((pl->n + 255) / 256)), b(256);
+#define ANKH_L2PM(LL)                                                                                              \
+    hipLaunchKernelGGL((k_l2p_moments<LL>), g, b, 0, pl->stream, pl->P, pl->d_leaf, pl->d_perm, pl->d_tab, pl->nup, \
+                       hinv, Lam, near, pl->d_terms, pl->xi, vol, ord, dEdq, dEdth, pl->n)
+    ANKH_FOR_ORDER(L, ANKH_L2PM)
+#undef ANKH_L2PM
     return hipGetLastError();
 }
 

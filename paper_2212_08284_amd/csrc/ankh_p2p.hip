@@ -660,6 +660,174 @@ __global__ void k_p2p_slots(int64_t n, const double *slot_e, const R *SF, const 
         }
 }
 
+// Near-field derivatives in the target's charge and quadrupole, gather form:
+// every atom against the atoms of the 27 leaves around its own (periodic,
+// itself at zero shift excluded).  For one pair (r = x_i - x_k):
+//   dE/dq_i     += q_k B0 + (d_k.r) B1 + (r.Q_k.r) B2,
+//   dE/dTh_i,ab += s r_a r_b - (v_a r_b + r_a v_b) + 2 B2 Q_k,ab,
+//   s = q_k B2 + (d_k.r) B3 + (r.Q_k.r) B4,  v = B2 d_k + 2 B3 Q_k r,
+// the derivative of the pair terms in c_n with respect to q_i and to the full
+// symmetric Th_i (up to its trace, which is dropped at the end).  Block: one
+// target leaf; the 16 lanes of a group hold 16 targets, the 16 groups split the
+// sources, and the groups' sums are added in group order: no atomics.
+// Output: [7][n] in leaf order (dE/dq, then xx, xy, xz, yy, yz, zz).
+template <typename R> struct MomArgs {
+    const double *x, *y, *z;
+    const R *q, *mu, *th;
+    const int32_t *offs;
+    int64_t n;
+    int nside;
+    double w;
+    Radial<R> rad;
+    double *out;
+};
+
+template <typename R, int ORD, int SL>
+__global__ __launch_bounds__(256) void k_p2p_moments(MomArgs<R> a) {
+    constexpr int NB = 3 + ORD;            // B0 .. B_{2+ORD}
+    __shared__ double sx[CH], sy[CH], sz[CH];
+    __shared__ R smo[10][CH];
+    __shared__ double part[7][NG][G];
+    const int tid = threadIdx.x, grp = tid / G, ln = tid % G;
+    const int ns = a.nside;
+    const int leaf = blockIdx.x;
+    const int lx = leaf / (ns * ns), ly = (leaf / ns) % ns, lz = leaf % ns;
+    const int t0 = a.offs[leaf], nt = a.offs[leaf + 1] - t0;
+    const int64_t n = a.n;
+    const Radial<R> rc = a.rad;
+    for (int tp = 0; tp < nt; tp += G) {
+        const bool iv = tp + ln < nt;
+        const int ti = t0 + (iv ? tp + ln : 0);
+        const double xt = a.x[ti], yt = a.y[ti], zt = a.z[ti];
+        // float64 totals; each chunk's few terms are summed in the working precision first
+        double phi_t = 0, G_t[6] = {0, 0, 0, 0, 0, 0};
+        for (int nb = 0; nb < 27; nb++) {
+            const int dx = nb / 9 - 1, dy = (nb / 3) % 3 - 1, dz = nb % 3 - 1;
+            const int sl = (((lx + dx + ns) % ns) * ns + (ly + dy + ns) % ns) * ns + (lz + dz + ns) % ns;
+            const int s0 = a.offs[sl], nsrc = a.offs[sl + 1] - s0;
+            for (int cs = 0; cs < nsrc; cs += CH) {
+                const int chn = min(CH, nsrc - cs);
+                __syncthreads();
+                for (int f = tid; f < chn; f += 256) {
+                    const int64_t sj = s0 + cs + f;
+                    // the source in the target leaf's frame
+                    sx[f] = a.x[sj] + dx * a.w;
+                    sy[f] = a.y[sj] + dy * a.w;
+                    sz[f] = a.z[sj] + dz * a.w;
+                    smo[0][f] = a.q[sj];
+                    if (ORD >= 1)
+                        for (int c = 0; c < 3; c++) smo[1 + c][f] = a.mu[c * n + sj];
+                    if (ORD >= 2)
+                        for (int c = 0; c < 6; c++) smo[4 + c][f] = a.th[c * n + sj];
+                }
+                __syncthreads();
+                if (!iv) continue;
+                R phi = 0, Gm[6] = {0, 0, 0, 0, 0, 0};
+                for (int j = grp; j < chn; j += NG) {
+                    if (nb == 13 && s0 + cs + j == ti) continue;   // the atom itself at zero shift
+                    const R rx = (R)(xt - sx[j]), ry = (R)(yt - sy[j]), rz = (R)(zt - sz[j]);
+                    const R r2 = rx * rx + ry * ry + rz * rz;
+                    const R rinv = dev_rsqrt<R>(r2);
+                    const R rinv2 = rinv * rinv;
+                    R B[NB];
+                    R ex;
+                    if constexpr (SL == 0) {
+                        B[0] = dev_erfc<R>(rc.xi * (r2 * rinv)) * rinv;
+                        ex = gauss<R, SL>(rc.gx * r2);
+                    } else {
+                        const R u = rc.xi2 * r2;
+                        B[0] = rinv - rc.c_erf * erf_series<R, SL>(u);
+                        ex = sizeof(R) == 8 ? gauss<R, SL>(u) : gauss<R, SL>(rc.gx * r2);
+                    }
+                    B[1] = (B[0] + rc.pwc[1] * ex) * rinv2;
+#pragma unroll
+                    for (int k = 2; k < NB; k++) B[k] = ((R)(2 * k - 1) * B[k - 1] + rc.pwc[k] * ex) * rinv2;
+                    const R rv[3] = {rx, ry, rz};
+                    const R ck = smo[0][j];
+                    R dkr = 0, qkrr = 0, Qkr[3] = {0, 0, 0}, dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
+                    if (ORD >= 1) {
+                        for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
+                        dkr = dk[0] * rx + dk[1] * ry + dk[2] * rz;
+                    }
+                    if (ORD >= 2) {
+                        for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
+                        symv(Qk, rx, ry, rz, Qkr[0], Qkr[1], Qkr[2]);
+                        qkrr = Qkr[0] * rx + Qkr[1] * ry + Qkr[2] * rz;
+                    }
+                    phi += ck * B[0];
+                    if (ORD >= 1) phi += dkr * B[1];
+                    if (ORD >= 2) phi += qkrr * B[2];
+                    R sv = ck * B[2];
+                    if (ORD >= 1) sv += dkr * B[3];
+                    if (ORD >= 2) sv += qkrr * B[4];
+                    R v[3];
+#pragma unroll
+                    for (int c = 0; c < 3; c++) v[c] = B[2] * dk[c] + 2 * B[3] * Qkr[c];
+                    // (xx, xy, xz, yy, yz, zz)
+                    constexpr int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+                    for (int c = 0; c < 6; c++) {
+                        const int p = ia[c], q2 = ib[c];
+                        Gm[c] += sv * rv[p] * rv[q2] - (v[p] * rv[q2] + rv[p] * v[q2]);
+                        if (ORD >= 2) Gm[c] += 2 * B[2] * Qk[c];
+                    }
+                }
+                phi_t += (double)phi;
+#pragma unroll
+                for (int c = 0; c < 6; c++) G_t[c] += (double)Gm[c];
+            }
+        }
+        __syncthreads();
+        part[0][grp][ln] = phi_t;
+#pragma unroll
+        for (int c = 0; c < 6; c++) part[1 + c][grp][ln] = G_t[c];
+        __syncthreads();
+        if (tid < 7 * G) {
+            const int c = tid / G, l = tid % G;
+            if (tp + l < nt) {
+                double sum = 0;
+                for (int g2 = 0; g2 < NG; g2++) sum += part[c][g2][l];
+                a.out[(int64_t)c * n + t0 + tp + l] = sum;
+            }
+        }
+    }
+}
+
+template <typename R, int SL>
+hipError_t launch_moments_t(ankh_plan_s *pl, int ord, double *out) {
+    MomArgs<R> a;
+    a.x = pl->P.x;
+    a.y = pl->P.y;
+    a.z = pl->P.z;
+    // the working-precision copies of the moments (float32 in the mixed modes)
+    auto sel = [](const double *d, const float *f) {
+        if constexpr (sizeof(R) == 8) return reinterpret_cast<const R *>(d);
+        else return reinterpret_cast<const R *>(f);
+    };
+    a.q = sel(pl->P.q, pl->P.qf);
+    a.mu = sel(pl->P.mu, pl->P.muf);
+    a.th = sel(pl->P.th, pl->P.thf);
+    a.offs = pl->d_offs;
+    a.n = pl->n;
+    a.nside = pl->nside;
+    a.w = pl->edge / pl->nside;
+    a.rad = radial_constants<R, SL>(pl->xi);
+    a.out = out;
+    const dim3 g((unsigned)pl->nleaf), b(256);
+    if (ord == 0) hipLaunchKernelGGL((k_p2p_moments<R, 0, SL>), g, b, 0, pl->stream, a);
+    else if (ord == 1) hipLaunchKernelGGL((k_p2p_moments<R, 1, SL>), g, b, 0, pl->stream, a);
+    else hipLaunchKernelGGL((k_p2p_moments<R, 2, SL>), g, b, 0, pl->stream, a);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_moments_prec(ankh_plan_s *pl, int ord, double *out) {
+    const double xmax = pl->xi * 2.0 * std::sqrt(3.0) * (pl->edge / pl->nside);
+    if (xmax <= 0.2) return launch_moments_t<R, 2>(pl, ord, out);
+    if (xmax <= 0.5) return launch_moments_t<R, 1>(pl, ord, out);
+    return launch_moments_t<R, 0>(pl, ord, out);
+}
+
 template <typename R, int SL>
 hipError_t launch_t(ankh_plan_s *pl, P2PArgs<R> a, int ord, bool grad, bool fields) {
     a.rad = radial_constants<R, SL>(pl->xi);
@@ -733,6 +901,11 @@ hipError_t launch_prec(ankh_plan_s *pl, int ord, bool grad, bool fields) {
 
 hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields) {
     return is_mixed(pl) ? launch_prec<float>(pl, ord, grad, fields) : launch_prec<double>(pl, ord, grad, fields);
+}
+
+// near-field dE/dq and dE/dTheta per leaf-order atom into out [7][n]
+hipError_t launch_p2p_moments(ankh_plan_s *pl, int ord, double *out) {
+    return is_mixed(pl) ? launch_moments_prec<float>(pl, ord, out) : launch_moments_prec<double>(pl, ord, out);
 }
 
 // per atom: the near-field energy and the sums of the force / field partial slots

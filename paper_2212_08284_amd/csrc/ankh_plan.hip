@@ -46,7 +46,7 @@ void free_all(ankh_plan_s *pl) {
                     pl->d_G, pl->d_terms, pl->d_part, pl->d_err, pl->d_tab0, pl->d_Mf, pl->d_m2l_part,
                     pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr,
                     pl->d_Kb, pl->d_Mb, pl->d_slot_e, pl->d_slot_f, pl->d_slot_g, pl->d_cper_part,
-                    pl->d_U, pl->d_Mc, pl->d_Lc, pl->d_ind};
+                    pl->d_U, pl->d_Mc, pl->d_Lc, pl->d_ind, pl->d_mom};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &set : pl->evsets)
@@ -488,6 +488,30 @@ ankh_status ankh_energy_forces(ankh_plan_t pl, const double *pos, const double *
     if (st != ANKH_OK) return st;
     if (!energy || !forces) return ANKH_ERR_INVALID_ARG;
     return run(pl, pos, q, mu, theta, energy, forces, dE_dmu);
+}
+
+ankh_status ankh_energy_derivs(ankh_plan_t pl, const double *pos, const double *q, const double *mu,
+                               const double *theta, double *energy, double *forces, double *dE_dmu, double *dE_dq,
+                               double *dE_dtheta) {
+    ankh_status st = check_inputs(pl, pos, q, mu, theta);
+    if (st != ANKH_OK) return st;
+    if (!energy || (dE_dtheta && pl->max_order < 2)) return ANKH_ERR_INVALID_ARG;
+    if ((st = run(pl, pos, q, mu, theta, energy, forces, dE_dmu)) != ANKH_OK) return st;
+    if (!dE_dq && !dE_dtheta) return ANKH_OK;
+    if (!pl->d_mom) {
+        void *v = nullptr;
+        const size_t bytes = (size_t)7 * pl->n * sizeof(double);
+        if (hipMalloc(&v, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return ANKH_ERR_OUT_OF_MEMORY;
+        }
+        pl->d_mom = static_cast<double *>(v);
+        pl->bytes += bytes;
+    }
+    const int ord = theta ? 2 : (mu ? 1 : 0);
+    if (launch_p2p_moments(pl, ord, pl->d_mom) != hipSuccess) return ANKH_ERR_HIP;
+    if (launch_l2p_moments(pl, ord, pl->d_mom, dE_dq, dE_dtheta) != hipSuccess) return ANKH_ERR_HIP;
+    return ANKH_OK;
 }
 
 ankh_status ankh_sync(ankh_plan_t pl) {
