@@ -19,7 +19,7 @@ constexpr int kMaxRootNodes = kMaxRootOrder * kMaxRootOrder * kMaxRootOrder;
 constexpr int kMaxDepth = 7;         // 2^21 leaves at most
 constexpr int kNumOff = 343;         // slots for offsets d in [-3,3]^3 (316 used)
 constexpr int kNumIL = 189;          // interaction-list length of every cell
-constexpr int kRedBlocks = 256;      // first-stage blocks of the energy reduction
+constexpr int kRedBlocks = 1024;     // first-stage blocks of the energy reduction (the epilogue)
 constexpr int kNumStages = 11;
 constexpr int kCperSlices = 16;
 constexpr int kNumSlots = 16;       // near-field partials per atom (see the pair kernel)     // column slices of the far-image root matvec
@@ -102,7 +102,6 @@ struct ankh_plan_s {
     double *d_U = nullptr, *d_Mc = nullptr, *d_Lc = nullptr;
     double *d_Cper = nullptr;     // far-image root operator [nup0][nup0]
     double *d_cper_part = nullptr;// its column-slice partial products [kCperSlices][nup0]
-    double *d_eatom = nullptr;    // near-field energy per leaf-order atom
     double *d_slot_e = nullptr;   // near-field partials per atom: energy [kNumSlots][n]
     void *d_slot_f = nullptr;     //   forces [3][kNumSlots][n] and fields [3][kNumSlots][n], float64 or float32
     void *d_slot_g = nullptr;
@@ -142,8 +141,7 @@ hipError_t launch_l2l(ankh_plan_s *pl, int e_child);
 hipError_t launch_cper(ankh_plan_s *pl);
 hipError_t launch_leafdot(ankh_plan_s *pl);
 hipError_t launch_l2p(ankh_plan_s *pl, int ord, bool fields);
-hipError_t launch_reduce(ankh_plan_s *pl, double *energy_out, int ord);
-hipError_t launch_unpermute(ankh_plan_s *pl, double *forces, double *dEdmu, bool have_mu);
+hipError_t launch_reduce(ankh_plan_s *pl, double *energy_out);   // the epilogue's partials, in block order
 hipError_t launch_m2l(ankh_plan_s *pl, int e);
 int m2l_splits(const ankh_plan_s *pl, int e);
 int m2l_row_frags(int nup);
@@ -154,7 +152,7 @@ hipError_t launch_m2l_project(ankh_plan_s *pl);   // all compressed levels: Mc =
 hipError_t launch_m2l_expand(ankh_plan_s *pl);    // all compressed levels: L = Lc U^T
 inline bool is_mixed(const ankh_plan_s *pl) { return pl->precision != ANKH_FP64; }
 hipError_t launch_p2p(ankh_plan_s *pl, int ord, bool grad, bool fields);
-hipError_t launch_p2p_sum(ankh_plan_s *pl, bool grad, bool fields);
+hipError_t launch_epilogue(ankh_plan_s *pl, int ord, bool grad, bool fields, double *forces, double *dEdmu);
 // derivatives in the charges and quadrupoles: near part into near [7][n] (leaf order), then the far
 // part, self and background terms and the output in caller order
 hipError_t launch_p2p_moments(ankh_plan_s *pl, int ord, double *near);

@@ -587,45 +587,7 @@ __global__ __launch_bounds__(256, L <= 6 ? 2 : 1) void k_l2p(Particles P, const 
 }
 
 // ---- energy reduction (two deterministic stages) -----------------------------
-__global__ __launch_bounds__(256) void k_reduce1(int64_t n, int64_t nleaf, const double *eatom, const double *eleaf,
-                                                 Particles P, int ord, double xi, double *part) {
-    __shared__ double red[4][256];
-    const int b = blockIdx.x, t = threadIdx.x;
-    const int64_t a0 = n * b / kRedBlocks, a1 = n * (b + 1) / kRedBlocks;
-    const int64_t l0 = nleaf * b / kRedBlocks, l1 = nleaf * (b + 1) / kRedBlocks;
-    const double c0 = -xi / sqrt(kPi), c1 = 2 * xi * xi / 3, c2 = 8 * xi * xi * xi * xi / 5;
-    double near = 0, self = 0, qs = 0, far = 0;
-    for (int64_t s = a0 + t; s < a1; s += 256) {
-        near += eatom[s];
-        const double q = P.q[s];
-        qs += q;
-        double v = q * q;
-        if (ord >= 1) {
-            const double m0 = P.mu[s], m1 = P.mu[n + s], m2 = P.mu[2 * n + s];
-            v += c1 * (m0 * m0 + m1 * m1 + m2 * m2);
-        }
-        if (ord >= 2) {
-            const double xx = P.th[s], xy = P.th[n + s], xz = P.th[2 * n + s];
-            const double yy = P.th[3 * n + s], yz = P.th[4 * n + s], zz = P.th[5 * n + s];
-            v += c2 * (xx * xx + yy * yy + zz * zz + 2 * (xy * xy + xz * xz + yz * yz));
-        }
-        self += c0 * v;
-    }
-    for (int64_t l = l0 + t; l < l1; l += 256) far += eleaf[l];
-    red[0][t] = near;
-    red[1][t] = self;
-    red[2][t] = qs;
-    red[3][t] = far;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (t < off)
-            for (int c = 0; c < 4; c++) red[c][t] += red[c][t + off];
-        __syncthreads();
-    }
-    if (t < 4) part[b * 4 + t] = red[t][0];
-}
-
-__global__ __launch_bounds__(256) void k_reduce2(const double *part, double *terms, double *energy, double xi,
+__global__ __launch_bounds__(kRedBlocks) void k_reduce2(const double *part, double *terms, double *energy, double xi,
                                                  double vol) {
     __shared__ double red[4][kRedBlocks];
     const int t = threadIdx.x;
@@ -651,18 +613,6 @@ __global__ __launch_bounds__(256) void k_reduce2(const double *part, double *ter
     }
 }
 
-__global__ void k_unpermute(int64_t n, const int32_t *perm, const double *F, const double *G, const Particles P,
-                            double fself, double *forces, double *dEdmu, int have_mu) {
-    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int64_t i = perm[s];
-    if (forces)
-        for (int d = 0; d < 3; d++) forces[3 * i + d] = F[d * n + s];
-    if (dEdmu) {
-        for (int d = 0; d < 3; d++)
-            dEdmu[3 * i + d] = have_mu ? G[d * n + s] + fself * P.mu[d * n + s] : 0.0;
-    }
-}
 
 // ---- plan-time builders ------------------------------------------------------
 // K_d[k][l] = H(w (1/2 (r_k - r_l) - d)) stored as [d][l][k]; zero for the
@@ -965,18 +915,9 @@ hipError_t launch_l2p_moments(ankh_plan_s *pl, int ord, const double *near, doub
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(ankh_plan_s *pl, double *energy_out, int ord) {
-    hipLaunchKernelGGL(k_reduce1, dim3(kRedBlocks), dim3(256), 0, pl->stream, pl->n, pl->nleaf, pl->d_eatom,
-                       pl->d_eleaf, pl->P, ord, pl->xi, pl->d_part);
+hipError_t launch_reduce(ankh_plan_s *pl, double *energy_out) {
     hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(kRedBlocks), 0, pl->stream, pl->d_part, pl->d_terms, energy_out,
                        pl->xi, pl->edge * pl->edge * pl->edge);
-    return hipGetLastError();
-}
-
-hipError_t launch_unpermute(ankh_plan_s *pl, double *forces, double *dEdmu, bool have_mu) {
-    const double fself = -4.0 * pl->xi * pl->xi * pl->xi / (3.0 * sqrt(kPi));
-    hipLaunchKernelGGL(k_unpermute, dim3(nblk(pl->n, 256)), dim3(256), 0, pl->stream, pl->n, pl->d_perm, pl->d_F,
-                       pl->d_G, pl->P, fself, forces, dEdmu, have_mu ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -636,28 +636,82 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs<R> a) {
     }
 }
 
-// per atom: near energy = sum of the energy slots; F, G += sum of their slots (fixed slot order)
+// The evaluation's epilogue, per atom in kRedBlocks blocks of contiguous leaf-order ranges:
+//  - the near energy, the sum of its energy slots (slot order);
+//  - forces and fields, the far-field part (from L2P) plus the slots, written in caller order
+//    (fields with the self-field term of the dipole);
+//  - the block's partial sums of the energy terms: near, self, total charge and the far energies of
+//    its share of the leaves (finished by k_reduce2 in block order).
+template <typename R> struct EpiArgs {
+    int64_t n, nleaf;
+    const double *slot_e;
+    const R *SF, *SG;
+    const double *F, *G, *eleaf;
+    Particles P;
+    const int32_t *perm;
+    int ord;
+    double xi, fself;
+    double *forces, *dEdmu, *part;
+};
+
 template <typename R, bool GRAD, bool FIELD>
-__global__ void k_p2p_slots(int64_t n, const double *slot_e, const R *SF, const R *SG, double *eatom, double *F,
-                            double *G) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double e = 0;
-    for (int s = 0; s < kNumSlots; s++) e += slot_e[(int64_t)s * n + i];
-    eatom[i] = e;
-    const int64_t st = (int64_t)kNumSlots * n;
-    if (GRAD)
-        for (int c = 0; c < 3; c++) {
-            double v = 0;
-            for (int s = 0; s < kNumSlots; s++) v += (double)SF[c * st + (int64_t)s * n + i];
-            F[c * n + i] += v;
+__global__ __launch_bounds__(256) void k_epilogue(EpiArgs<R> a) {
+    __shared__ double red[4][256];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int64_t n = a.n, st = (int64_t)kNumSlots * n;
+    const int64_t a0 = n * b / kRedBlocks, a1 = n * (b + 1) / kRedBlocks;
+    const int64_t l0 = a.nleaf * b / kRedBlocks, l1 = a.nleaf * (b + 1) / kRedBlocks;
+    const double xi = a.xi;
+    const double c0 = -xi / sqrt(3.14159265358979323846), c1 = 2 * xi * xi / 3, c2 = 8 * xi * xi * xi * xi / 5;
+    double near = 0, self = 0, qs = 0, far = 0;
+    for (int64_t s = a0 + t; s < a1; s += 256) {
+        double e = 0;
+        for (int k = 0; k < kNumSlots; k++) e += a.slot_e[(int64_t)k * n + s];
+        near += e;
+        const double q = a.P.q[s];
+        qs += q;
+        double v = q * q;
+        if (a.ord >= 1) {
+            const double m0 = a.P.mu[s], m1 = a.P.mu[n + s], m2 = a.P.mu[2 * n + s];
+            v += c1 * (m0 * m0 + m1 * m1 + m2 * m2);
         }
-    if (FIELD)
-        for (int c = 0; c < 3; c++) {
-            double v = 0;
-            for (int s = 0; s < kNumSlots; s++) v += (double)SG[c * st + (int64_t)s * n + i];
-            G[c * n + i] += v;
+        if (a.ord >= 2) {
+            const double xx = a.P.th[s], xy = a.P.th[n + s], xz = a.P.th[2 * n + s];
+            const double yy = a.P.th[3 * n + s], yz = a.P.th[4 * n + s], zz = a.P.th[5 * n + s];
+            v += c2 * (xx * xx + yy * yy + zz * zz + 2 * (xy * xy + xz * xz + yz * yz));
         }
+        self += c0 * v;
+        const int64_t i = a.perm[s];
+        if (GRAD && a.forces)
+            for (int c = 0; c < 3; c++) {
+                double w = 0;
+                for (int k = 0; k < kNumSlots; k++) w += (double)a.SF[c * st + (int64_t)k * n + s];
+                a.forces[3 * i + c] = a.F[c * n + s] + w;
+            }
+        if (a.dEdmu) {
+            for (int c = 0; c < 3; c++) {
+                double g = 0;
+                if (FIELD) {
+                    double w = 0;
+                    for (int k = 0; k < kNumSlots; k++) w += (double)a.SG[c * st + (int64_t)k * n + s];
+                    g = (a.G[c * n + s] + w) + a.fself * a.P.mu[c * n + s];
+                }
+                a.dEdmu[3 * i + c] = g;
+            }
+        }
+    }
+    for (int64_t l = l0 + t; l < l1; l += 256) far += a.eleaf[l];
+    red[0][t] = near;
+    red[1][t] = self;
+    red[2][t] = qs;
+    red[3][t] = far;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off)
+            for (int c = 0; c < 4; c++) red[c][t] += red[c][t + off];
+        __syncthreads();
+    }
+    if (t < 4) a.part[b * 4 + t] = red[t][0];
 }
 
 // Near-field derivatives in the target's charge and quadrupole, gather form:
@@ -850,22 +904,30 @@ hipError_t launch_t(ankh_plan_s *pl, P2PArgs<R> a, int ord, bool grad, bool fiel
 }
 
 template <typename R>
-hipError_t launch_sum_t(ankh_plan_s *pl, bool grad, bool fields) {
-    dim3 g2((unsigned)((pl->n + 255) / 256)), b(256);
+hipError_t launch_epi_t(ankh_plan_s *pl, int ord, bool grad, bool fields, double *forces, double *dEdmu) {
+    EpiArgs<R> a;
+    a.n = pl->n;
+    a.nleaf = pl->nleaf;
+    a.slot_e = pl->d_slot_e;
+    a.SF = static_cast<const R *>(pl->d_slot_f);
+    a.SG = static_cast<const R *>(pl->d_slot_g);
+    a.F = pl->d_F;
+    a.G = pl->d_G;
+    a.eleaf = pl->d_eleaf;
+    a.P = pl->P;
+    a.perm = pl->d_perm;
+    a.ord = ord;
+    a.xi = pl->xi;
+    a.fself = -4.0 * pl->xi * pl->xi * pl->xi / (3.0 * std::sqrt(3.14159265358979323846));
+    a.forces = grad ? forces : nullptr;
+    a.dEdmu = dEdmu;
+    a.part = pl->d_part;
+    const dim3 g(kRedBlocks), b(256);
     hipStream_t s = pl->stream;
-    const R *SF = static_cast<const R *>(pl->d_slot_f), *SG = static_cast<const R *>(pl->d_slot_g);
-    if (grad && fields)
-        hipLaunchKernelGGL((k_p2p_slots<R, true, true>), g2, b, 0, s, pl->n, pl->d_slot_e, SF, SG, pl->d_eatom,
-                           pl->d_F, pl->d_G);
-    else if (grad)
-        hipLaunchKernelGGL((k_p2p_slots<R, true, false>), g2, b, 0, s, pl->n, pl->d_slot_e, SF, SG, pl->d_eatom,
-                           pl->d_F, pl->d_G);
-    else if (fields)
-        hipLaunchKernelGGL((k_p2p_slots<R, false, true>), g2, b, 0, s, pl->n, pl->d_slot_e, SF, SG, pl->d_eatom,
-                           pl->d_F, pl->d_G);
-    else
-        hipLaunchKernelGGL((k_p2p_slots<R, false, false>), g2, b, 0, s, pl->n, pl->d_slot_e, SF, SG, pl->d_eatom,
-                           pl->d_F, pl->d_G);
+    if (grad && fields) hipLaunchKernelGGL((k_epilogue<R, true, true>), g, b, 0, s, a);
+    else if (grad) hipLaunchKernelGGL((k_epilogue<R, true, false>), g, b, 0, s, a);
+    else if (fields) hipLaunchKernelGGL((k_epilogue<R, false, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_epilogue<R, false, false>), g, b, 0, s, a);
     return hipGetLastError();
 }
 
@@ -908,9 +970,10 @@ hipError_t launch_p2p_moments(ankh_plan_s *pl, int ord, double *out) {
     return is_mixed(pl) ? launch_moments_prec<float>(pl, ord, out) : launch_moments_prec<double>(pl, ord, out);
 }
 
-// per atom: the near-field energy and the sums of the force / field partial slots
-hipError_t launch_p2p_sum(ankh_plan_s *pl, bool grad, bool fields) {
-    return is_mixed(pl) ? launch_sum_t<float>(pl, grad, fields) : launch_sum_t<double>(pl, grad, fields);
+// the slot sums, forces and fields in caller order, the energy partials
+hipError_t launch_epilogue(ankh_plan_s *pl, int ord, bool grad, bool fields, double *forces, double *dEdmu) {
+    return is_mixed(pl) ? launch_epi_t<float>(pl, ord, grad, fields, forces, dEdmu)
+                        : launch_epi_t<double>(pl, ord, grad, fields, forces, dEdmu);
 }
 
 }  // namespace ankh

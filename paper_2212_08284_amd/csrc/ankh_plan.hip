@@ -42,7 +42,7 @@ void dalloc(ankh_plan_s *pl, T **p, size_t count) {
 void free_all(ankh_plan_s *pl) {
     void *ptrs[] = {pl->d_tab, pl->d_leaf, pl->d_count, pl->d_offs, pl->d_rank, pl->d_perm, pl->d_tmp,
                     pl->P.x, pl->P.y, pl->P.z, pl->P.q, pl->P.mu, pl->P.th, pl->P.qf, pl->P.muf, pl->P.thf,
-                    pl->d_M, pl->d_L, pl->d_K, pl->d_Kf, pl->d_Cper, pl->d_eatom, pl->d_eleaf, pl->d_F,
+                    pl->d_M, pl->d_L, pl->d_K, pl->d_Kf, pl->d_Cper, pl->d_eleaf, pl->d_F,
                     pl->d_G, pl->d_terms, pl->d_part, pl->d_err, pl->d_tab0, pl->d_Mf, pl->d_m2l_part,
                     pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr,
                     pl->d_Kb, pl->d_Mb, pl->d_slot_e, pl->d_slot_f, pl->d_slot_g, pl->d_cper_part,
@@ -178,10 +178,9 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
         ck(launch_p2p(pl, ord, grad, fields));
         mark(9);
         if (overlap) ck(hipStreamWaitEvent(s, pl->ev_join, 0));
-        ck(launch_p2p_sum(pl, grad, fields));
+        ck(launch_epilogue(pl, ord, grad, fields, forces, dEdmu));
         mark(10);
-        ck(launch_reduce(pl, energy, ord));
-        if (adj) ck(launch_unpermute(pl, forces, dEdmu, ord >= 1));
+        ck(launch_reduce(pl, energy));
         mark(11);
     } catch (const HipFail &) {
         pl->stream = s;
@@ -361,7 +360,6 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
             pl->d_rootM = pl->d_M;
             pl->d_rootL = pl->d_L;
         }
-        dalloc(pl, &pl->d_eatom, n);
         dalloc(pl, &pl->d_slot_e, (size_t)kNumSlots * n);
         if (precision == ANKH_FP64) {
             double *f = nullptr, *g = nullptr;
@@ -388,7 +386,6 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         ck(launch_zero_i32(pl->d_err, 4, pl->stream));
         ck(launch_zero_f64(pl->d_terms, 8, pl->stream));
         ck(launch_zero_f64(pl->d_G, 3 * n, pl->stream));
-        ck(launch_zero_f64(pl->d_eatom, n, pl->stream));
         // operator tables: M2L matrices of levels 1..E (each built in float64, compressed
         // when that pays, then kept in the working precision) and the far-image root operator
         for (int e = 0; e <= pl->depth; e++) {
