@@ -25,6 +25,21 @@ Readings of the paper taken here (each also listed in the design notes):
 * E_rec is dropped (small xi); the background -pi Q^2/(2 V xi^2) is added for
   non-neutral cells.
 
+ANKH-FFT (far="fft"): the leaf modified charges are reinterpolated onto an
+equispaced grid per leaf (Le nodes per axis spanning the leaf), and the far
+energy 1/2 v^T A v over all non-adjacent leaf pairs is evaluated in the
+Fourier domain, 1/2 (1/N) sum D |F6 chi v|^2 with D = F6 applied to the
+generating entries of A.  Readings taken here:
+* the grid spans the leaf (the node spacing of the diagonal-construction
+  algorithm; the printed grid radius is half of that);
+* the leaf grid is periodic, so the cell dimensions of the 6D transform are
+  circular of length 2^E with no padding; the node dimensions are padded to
+  2 Le - 1 (node differences -(Le-1)..Le-1);
+* the image sum of each entry runs over the source-cell displacements
+  within n (p + 1/2) cells per axis, which keeps each entry a function of
+  the cell difference modulo n; adjacent displacements (the near field) are
+  excluded, and the far images need no separate root operator.
+
 The near-field pair sums use the pinned pair routine of `ewald.c`
 (`oracle_near_field`).  Parameters (depth E, order L, xi, image radius p) are
 inputs: this module chooses nothing.
@@ -171,6 +186,105 @@ def _valid_mask(n, d):
     return masks[0][:, None, None] & masks[1][None, :, None] & masks[2][None, None, :]
 
 
+# ---- ANKH-FFT far field (the ANKH-FFT section) -------------------------------
+
+def equi_nodes(Le: int) -> np.ndarray:
+    """Equispaced nodes of a leaf in scaled coordinates: -1 + 2a/(Le - 1), a = 0..Le-1.  The grid
+    spans the whole leaf (the node spacing of the diagonal-construction algorithm, 2v/(L-1) with v
+    the leaf half-width), so adjacent leaves share their face nodes."""
+    return -1.0 + 2.0 * np.arange(Le) / (Le - 1)
+
+
+def equi_lagrange(x, Le: int) -> np.ndarray:
+    """U_a(x), the Lagrange polynomials of the equispaced nodes; shape x.shape + (Le,)."""
+    t = equi_nodes(Le)
+    x = np.asarray(x, dtype=np.float64)
+    out = np.ones(x.shape + (Le,))
+    for a in range(Le):
+        for b in range(Le):
+            if b != a:
+                out[..., a] *= (x - t[b]) / (t[a] - t[b])
+    return out
+
+
+def equi_reinterp(L: int, Le: int) -> np.ndarray:
+    """E[a, k] = U_a(r_k): maps the modified charges of the Chebyshev nodes r_k of a leaf to those
+    of its equispaced nodes (H(r_k, .) ~ sum_a U_a(r_k) H(x_a, .))."""
+    return equi_lagrange(cheb_nodes(L), Le).T.copy()
+
+
+def fft_node_period(Le: int) -> int:
+    """Length of the node dimensions of the transform: node differences span -(Le-1)..Le-1."""
+    return 2 * Le - 1
+
+
+def fft_kernel_table(n: int, w: float, Le: int, xi: float, p: int) -> np.ndarray:
+    """The generating entries of the far-field matrix A in circulant order, K[gx, ax, gy, ay, gz, az]:
+    cell residue g (mod n = 2^E) and node difference a (mod Pa = 2Le - 1) per axis.  The entry sums
+    H over the images of the source cell whose cell displacement D = g - n I has |D_axis| <= n (p + 1/2)
+    on every axis and is not adjacent (max |D| >= 2, the leaf pairs the direct near field does not
+    take); the displacement of the two nodes is D w + a h, h = w / (Le - 1)."""
+    Pa = fft_node_period(Le)
+    h = w / (Le - 1)
+    da = np.arange(-(Le - 1), Le)
+    lim = n * (p + 0.5)
+    disp = {g: [g - n * I for I in range(-p - 2, p + 3) if abs(g - n * I) <= lim] for g in range(n)}
+    K = np.zeros((n, Pa, n, Pa, n, Pa))
+    idx = da % Pa
+    for gx, gy, gz in itertools.product(range(n), repeat=3):
+        acc = np.zeros((len(da),) * 3)
+        for Dx in disp[gx]:
+            for Dy in disp[gy]:
+                for Dz in disp[gz]:
+                    if max(abs(Dx), abs(Dy), abs(Dz)) < 2:
+                        continue
+                    zx, zy, zz = Dx * w + da * h, Dy * w + da * h, Dz * w + da * h
+                    r = np.sqrt(zx[:, None, None] ** 2 + zy[None, :, None] ** 2 + zz[None, None, :] ** 2)
+                    acc += kernel_H(r, xi)
+        K[gx, :, gy, :, gz, :][np.ix_(idx, idx, idx)] = acc
+    return K
+
+
+def fft_far(Q, n: int, L: int, Le: int, K) -> tuple:
+    """ANKH-FFT far field from the leaf modified charges Q [n^3, L^3] (leaves in lexicographic order):
+    M = E Q on the equispaced grids, v = the zero-padded 6D array chi v, w = F6 v, D = F6 K (real),
+    energy 1/2 (1/N) sum D |w|^2 and the leaf local expansions Lambda = E^T chi^T F6^-1 (D w)."""
+    Pa = fft_node_period(Le)
+    E = equi_reinterp(L, Le)
+    M = np.einsum("ai,bj,ck,xyzijk->xyzabc", E, E, E, Q.reshape(n, n, n, L, L, L))
+    X = np.zeros((n, Pa, n, Pa, n, Pa))
+    X[:, :Le, :, :Le, :, :Le] = M.transpose(0, 3, 1, 4, 2, 5)
+    D = np.fft.fftn(K)
+    W = np.fft.fftn(X)
+    energy = 0.5 * float(np.sum(D.real * np.abs(W) ** 2)) / X.size
+    phi = np.fft.ifftn(D * W).real[:, :Le, :, :Le, :, :Le].transpose(0, 2, 4, 1, 3, 5)
+    Lam = np.einsum("ai,bj,ck,xyzabc->xyzijk", E, E, E, phi)
+    return energy, Lam.reshape(n ** 3, L ** 3), D
+
+
+def fft_far_dense(Q, n: int, w: float, L: int, Le: int, xi: float, p: int) -> float:
+    """The same far energy by its definition (tiny cases): 1/2 sum over leaf pairs (t, s) and the
+    images of s within the displacement cube, not adjacent to t, of M_t^T G M_s, G[a, b] = H between
+    the equispaced nodes."""
+    E = equi_reinterp(L, Le)
+    M = np.einsum("ai,bj,ck,xyzijk->xyzabc", E, E, E, Q.reshape(n, n, n, L, L, L)).reshape(n ** 3, Le ** 3)
+    g = np.stack(np.meshgrid(*(equi_nodes(Le),) * 3, indexing="ij"), axis=-1).reshape(-1, 3) * (0.5 * w)
+    cells = list(itertools.product(range(n), repeat=3))
+    lim = n * (p + 0.5)
+    e = 0.0
+    for it, ct in enumerate(cells):
+        for js, cs in enumerate(cells):
+            ranges = [[ct[a] - cs[a] - n * I for I in range(-p - 2, p + 3) if abs(ct[a] - cs[a] - n * I) <= lim]
+                      for a in range(3)]
+            for D in itertools.product(*ranges):
+                if max(abs(c) for c in D) < 2:
+                    continue
+                diff = g[:, None, :] - g[None, :, :] + w * np.asarray(D, dtype=np.float64)
+                G = kernel_H(np.sqrt(np.sum(diff * diff, axis=-1)), xi)
+                e += 0.5 * float(M[it] @ G @ M[js])
+    return e
+
+
 # ---- evaluation --------------------------------------------------------------
 
 def m2l_projector(w: float, L: int, xi: float, rank: int) -> np.ndarray:
@@ -188,11 +302,13 @@ def m2l_projector(w: float, L: int, xi: float, rank: int) -> np.ndarray:
 
 def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, p: int,
              grad: bool = True, nthreads: int = 0, keep: bool = False, root_order: int | None = None,
-             m2l_ranks=None) -> dict:
+             m2l_ranks=None, far: str = "fmm", eq_order: int | None = None) -> dict:
     """root_order: Chebyshev order of the root grid that carries the far
     images (depth >= 1); defaults to `order`.  m2l_ranks: optional rank per
     level (index e = 1..depth; a rank >= L^3 or 0 leaves the level
-    uncompressed) of the compressed M2L operators."""
+    uncompressed) of the compressed M2L operators.  far = "fft": the far
+    field of ANKH-FFT instead (leaf level only, equispaced order eq_order;
+    the far images are inside its matrix, so e_per = 0)."""
     pos = wrap(_c64(pos, (-1, 3)), edge)
     N = pos.shape[0]
     q = _c64(q, (N,))
@@ -231,46 +347,51 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
     Q = np.zeros((nleaf_ax ** 3, L, L, L))
     np.add.at(Q, leaf, contrib)
 
-    # upward pass (M2M) to the root
-    V = m2m_1d(L)
-    L0 = L if (E == 0 or root_order is None) else int(root_order)
-    V0 = m2m_1d(L0, L)          # level 1 -> root
-    M = [None] * (E + 1)
-    M[E] = Q.reshape(nleaf_ax, nleaf_ax, nleaf_ax, nu)
-    for e in range(E - 1, -1, -1):
-        n = 1 << e
-        child = M[e + 1].reshape(n, 2, n, 2, n, 2, L, L, L)
-        Vp, Lp = (V0, L0) if e == 0 else (V, L)
-        par = np.zeros((n, n, n, Lp, Lp, Lp))
-        for bx, by, bz in itertools.product((0, 1), repeat=3):
-            par += np.einsum("ai,bj,ck,xyzijk->xyzabc", Vp[bx], Vp[by], Vp[bz],
-                             child[:, bx, :, by, :, bz])
-        M[e] = par.reshape(n, n, n, Lp ** 3)
+    if far == "fft":
+        e_fft, Lam_fft, _ = fft_far(Q.reshape(-1, nu), nleaf_ax, L, int(eq_order),
+                                    fft_kernel_table(nleaf_ax, w_leaf, int(eq_order), xi, p))
+        e_far_levels, e_per, M, Lloc, Cper = [e_fft], 0.0, None, None, None
+    else:
+        # upward pass (M2M) to the root
+        V = m2m_1d(L)
+        L0 = L if (E == 0 or root_order is None) else int(root_order)
+        V0 = m2m_1d(L0, L)          # level 1 -> root
+        M = [None] * (E + 1)
+        M[E] = Q.reshape(nleaf_ax, nleaf_ax, nleaf_ax, nu)
+        for e in range(E - 1, -1, -1):
+            n = 1 << e
+            child = M[e + 1].reshape(n, 2, n, 2, n, 2, L, L, L)
+            Vp, Lp = (V0, L0) if e == 0 else (V, L)
+            par = np.zeros((n, n, n, Lp, Lp, Lp))
+            for bx, by, bz in itertools.product((0, 1), repeat=3):
+                par += np.einsum("ai,bj,ck,xyzijk->xyzabc", Vp[bx], Vp[by], Vp[bz],
+                                 child[:, bx, :, by, :, bz])
+            M[e] = par.reshape(n, n, n, Lp ** 3)
 
-    # far field by M2L on every level 1..E (cells of the adjacent images included)
-    offs = interaction_offsets()
-    Lloc = [None] * (E + 1)
-    e_far_levels = []
-    for e in range(1, E + 1):
-        n = 1 << e
-        w = edge / n
-        acc = np.zeros((n, n, n, nu))
-        r = 0 if m2l_ranks is None else int(m2l_ranks[e])
-        P = m2l_projector(w, L, xi, r) if 0 < r < nu else None
-        for d in offs:
-            K = m2l_matrix(d, w, L, xi)
-            if P is not None:
-                K = P @ K @ P
-            Ms = np.roll(M[e], shift=(-d[0], -d[1], -d[2]), axis=(0, 1, 2))
-            acc += _valid_mask(n, d)[..., None] * (Ms @ K.T)
-        Lloc[e] = acc
-        e_far_levels.append(0.5 * float(np.sum(M[e] * acc)))
+        # far field by M2L on every level 1..E (cells of the adjacent images included)
+        offs = interaction_offsets()
+        Lloc = [None] * (E + 1)
+        e_far_levels = []
+        for e in range(1, E + 1):
+            n = 1 << e
+            w = edge / n
+            acc = np.zeros((n, n, n, nu))
+            r = 0 if m2l_ranks is None else int(m2l_ranks[e])
+            P = m2l_projector(w, L, xi, r) if 0 < r < nu else None
+            for d in offs:
+                K = m2l_matrix(d, w, L, xi)
+                if P is not None:
+                    K = P @ K @ P
+                Ms = np.roll(M[e], shift=(-d[0], -d[1], -d[2]), axis=(0, 1, 2))
+                acc += _valid_mask(n, d)[..., None] * (Ms @ K.T)
+            Lloc[e] = acc
+            e_far_levels.append(0.5 * float(np.sum(M[e] * acc)))
 
-    # far periodic images through the root
-    nu0 = L0 ** 3
-    Cper = periodic_root_matrix(edge, L0, xi, p)
-    Lroot = M[0].reshape(nu0) @ Cper.T
-    e_per = 0.5 * float(M[0].reshape(nu0) @ Lroot)
+        # far periodic images through the root
+        nu0 = L0 ** 3
+        Cper = periodic_root_matrix(edge, L0, xi, p)
+        Lroot = M[0].reshape(nu0) @ Cper.T
+        e_per = 0.5 * float(M[0].reshape(nu0) @ Lroot)
 
     # near field: direct pair sums over adjacent leaves
     eatom = np.zeros(N)
@@ -298,17 +419,20 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
                e_far_levels=e_far_levels, e_per=e_per, e_self=e_self, e_bg=e_bg)
 
     if grad:
-        # downward pass: L2L is the transpose of M2M
-        Lam = Lroot.reshape(1, 1, 1, nu0)
-        for e in range(1, E + 1):
-            n = 1 << e
-            down = np.zeros((n, n, n, L, L, L))
-            Vp, Lp = (V0, L0) if e == 1 else (V, L)
-            par = Lam.reshape(n // 2, n // 2, n // 2, Lp, Lp, Lp)
-            dv = down.reshape(n // 2, 2, n // 2, 2, n // 2, 2, L, L, L)
-            for bx, by, bz in itertools.product((0, 1), repeat=3):
-                dv[:, bx, :, by, :, bz] += np.einsum("ai,bj,ck,xyzabc->xyzijk", Vp[bx], Vp[by], Vp[bz], par)
-            Lam = down.reshape(n, n, n, nu) + Lloc[e]
+        # leaf local expansions: from the transform (ANKH-FFT), or by the downward pass (L2L = M2M^T)
+        if far == "fft":
+            Lam = Lam_fft
+        else:
+            Lam = Lroot.reshape(1, 1, 1, nu0)
+            for e in range(1, E + 1):
+                n = 1 << e
+                down = np.zeros((n, n, n, L, L, L))
+                Vp, Lp = (V0, L0) if e == 1 else (V, L)
+                par = Lam.reshape(n // 2, n // 2, n // 2, Lp, Lp, Lp)
+                dv = down.reshape(n // 2, 2, n // 2, 2, n // 2, 2, L, L, L)
+                for bx, by, bz in itertools.product((0, 1), repeat=3):
+                    dv[:, bx, :, by, :, bz] += np.einsum("ai,bj,ck,xyzabc->xyzijk", Vp[bx], Vp[by], Vp[bz], par)
+                Lam = down.reshape(n, n, n, nu) + Lloc[e]
         Lam_leaf = Lam.reshape(-1, L, L, L)[leaf]          # [N, L, L, L]
         # L2P: derivatives of phi(y) = sum_k Lam_k S_k(y) up to order 3
         phi = {}
@@ -348,5 +472,5 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
         out.update(forces=Fn + Ff, dEdmu=(Gn + Gf + Gs) if mu is not None else np.zeros((N, 3)),
                    forces_near=Fn, forces_far=Ff, e_far_leaf=e_far_leaf)
     if keep:
-        out.update(Q=Q, M=M, Lloc=Lloc, leaf=leaf, Cper=Cper)
+        out.update(Q=Q, M=M, Lloc=Lloc, leaf=leaf, Cper=Cper, Lam=Lam if grad else None)
     return out

@@ -11,7 +11,12 @@ facts fixed by the mathematics, not by the transcription itself:
 * forces and fields are the exact gradient of the approximate energy
   (central finite differences);
 * the approximation converges geometrically in L to the classical-Ewald
-  value, and agrees across tree depths within the approximation error.
+  value, and agrees across tree depths within the approximation error;
+* ANKH-FFT: the reinterpolation onto the equispaced grids preserves the
+  polynomial moments it can represent, the transform-based far energy equals
+  the plain double sum over leaf pairs and images that defines it, its
+  spectrum is real, its leaf local expansions are the gradient of that
+  quadratic form, and the method converges to the classical-Ewald value.
 """
 import itertools
 import math
@@ -120,11 +125,13 @@ def test_root_operator_is_image_sum():
     np.testing.assert_allclose(C, C.T, rtol=1e-13)
 
 
-def test_reference_gradient_is_exact():
+@pytest.mark.parametrize("far", ["fmm", "fft"])
+def test_reference_gradient_is_exact(far):
     d = synth.water(40, seed=3)
     edge = d["edge"]
     E, L, xi, p = 1, 4, 0.08, 3
-    base = R.evaluate(d["pos"], d["q"], d["mu"], d["theta"], edge, E, L, xi, p, grad=True)
+    kw = dict(far=far, eq_order=4)
+    base = R.evaluate(d["pos"], d["q"], d["mu"], d["theta"], edge, E, L, xi, p, grad=True, **kw)
     h = 1e-5
     for i in (4, 50):
         for c in range(3):
@@ -132,13 +139,13 @@ def test_reference_gradient_is_exact():
             for s in (1, -1):
                 pp = d["pos"].copy()
                 pp[i, c] += s * h
-                vals.append(R.evaluate(pp, d["q"], d["mu"], d["theta"], edge, E, L, xi, p, grad=False)["energy"])
+                vals.append(R.evaluate(pp, d["q"], d["mu"], d["theta"], edge, E, L, xi, p, grad=False, **kw)["energy"])
             assert -(vals[0] - vals[1]) / (2 * h) == pytest.approx(base["forces"][i, c], rel=1e-6, abs=1e-7)
             vals = []
             for s in (1, -1):
                 mm = d["mu"].copy()
                 mm[i, c] += s * h
-                vals.append(R.evaluate(d["pos"], d["q"], mm, d["theta"], edge, E, L, xi, p, grad=False)["energy"])
+                vals.append(R.evaluate(d["pos"], d["q"], mm, d["theta"], edge, E, L, xi, p, grad=False, **kw)["energy"])
             assert (vals[0] - vals[1]) / (2 * h) == pytest.approx(base["dEdmu"][i, c], rel=1e-6, abs=1e-7)
 
 
@@ -181,3 +188,63 @@ def test_m2l_projector_pins():
     # K_-d = K_d^T: the projected stack of transposes loses the same
     At = np.hstack([R.m2l_matrix(d, w, L, xi).T for d in offs])
     assert abs(np.linalg.norm(At - P @ At, 2) - s[r]) <= 1e-8 * s[0]
+
+
+@pytest.mark.parametrize("L,Le", [(6, 4), (5, 5), (4, 6)])
+def test_fft_reinterpolation_preserves_moments(L, Le):
+    """The equispaced Lagrange basis reproduces polynomials of degree < Le, so the reinterpolated
+    charges keep every moment of that degree: sum_a M_a x_a^m = sum_k Q_k r_k^m."""
+    E = R.equi_reinterp(L, Le)
+    Q = np.random.default_rng(L * 10 + Le).normal(size=L)
+    M = E @ Q
+    t, r = R.equi_nodes(Le), R.cheb_nodes(L)
+    for m in range(min(Le, L)):
+        assert np.sum(M * t ** m) == pytest.approx(np.sum(Q * r ** m), abs=1e-12)
+    # Le >= L: the map is exact on the whole Chebyshev space (its own interpolant back is the identity)
+    if Le >= L:
+        back = R.cheb_T(t, L) @ R.cheb_H(L).T      # S_k(x_a)
+        np.testing.assert_allclose(back.T @ E, np.eye(L), atol=1e-12)
+
+
+def test_fft_far_equals_its_definition():
+    """Tiny cell (depth 1, 8 leaves): the energy through the 6D transform equals the plain sum over
+    leaf pairs, the images of the source leaf in the displacement cube and the equispaced nodes; the
+    spectrum of the embedded matrix is real; the leaf local expansions are the gradient of the
+    energy in the leaf charges (exact for a quadratic form: E(Q+d) - E(Q-d) = 2 d . Lambda)."""
+    rng = np.random.default_rng(11)
+    edge, E, L, Le, xi, p = 6.0, 1, 3, 3, 0.3, 2
+    n, w = 2, 3.0
+    pos = rng.uniform(-3, 3, (10, 3))
+    q = rng.normal(size=10)
+    mu = 0.3 * rng.normal(size=(10, 3))
+    th = synth.random_traceless_theta(rng, 10, 0.2)
+    Q = R.evaluate(pos, q, mu, th, edge, E, L, xi, p, grad=False, keep=True)["Q"].reshape(n ** 3, L ** 3)
+    K = R.fft_kernel_table(n, w, Le, xi, p)
+    e, Lam, D = R.fft_far(Q, n, L, Le, K)
+    dense = R.fft_far_dense(Q, n, w, L, Le, xi, p)
+    assert e == pytest.approx(dense, rel=1e-12)
+    assert np.max(np.abs(D.imag)) <= 1e-12 * np.max(np.abs(D.real))
+    assert 0.5 * np.sum(Q * Lam) == pytest.approx(e, rel=1e-12)
+    d = rng.normal(size=Q.shape)
+    ep, em = R.fft_far(Q + d, n, L, Le, K)[0], R.fft_far(Q - d, n, L, Le, K)[0]
+    assert (ep - em) / 2 == pytest.approx(np.sum(d * Lam), rel=1e-10)
+
+
+def test_fft_far_field_converges_to_ewald():
+    """ANKH-FFT converges in the equispaced order to the classical-Ewald value and, at the order of
+    the Chebyshev grids, matches the accuracy of the multilevel far field."""
+    d = synth.water(150, seed=8)
+    edge = d["edge"]
+    ex = oracle.ewald(d["pos"], d["q"], d["mu"], d["theta"], edge=edge, eps=1e-13)
+    s2 = math.log(10 / 1e-7)
+    xi = math.pi / (edge * math.sqrt(s2))
+    p = int(math.ceil(math.sqrt(s2) / (xi * edge))) + 1
+    errs = []
+    for Le in (3, 4, 6):
+        r = R.evaluate(d["pos"], d["q"], d["mu"], d["theta"], edge, 1, 6, xi, p, grad=True, far="fft", eq_order=Le)
+        errs.append((abs(r["energy"] - ex["energy"]) / abs(ex["energy"]),
+                     np.sqrt(np.sum((r["forces"] - ex["forces"]) ** 2) / np.sum(ex["forces"] ** 2))))
+        assert r["e_per"] == 0.0
+    assert errs[0][1] > errs[1][1] > errs[2][1]
+    assert errs[0][0] > errs[2][0]
+    assert errs[2][0] < 2e-6 and errs[2][1] < 2e-5
