@@ -88,7 +88,26 @@ typedef struct {
     double m2l_tol;     /* compressed M2L (the singular-value compression of the far-field operators):
                            singular values above m2l_tol x the largest are kept; 0 = auto (0.1 x
                            rel_accuracy, orders <= 7), NEGATIVE = no compression */
+    int32_t far_field;  /* far-field method, an ankh_far_field value; 0 = auto (ANKH_FAR_FMM) */
+    int32_t eq_order;   /* ANKH-FFT: equispaced nodes per axis of each leaf grid, 2..10; 0 = the
+                           Chebyshev order */
 } ankh_overrides;
+
+/* Far-field methods.
+ *   ANKH_FAR_FMM  ANKH-FMM (the ANKH-FMM section): multipoles up the octree, M2L over the
+ *                 interaction lists of every level, the far images through one root operator,
+ *                 locals down the tree.
+ *   ANKH_FAR_FFT  ANKH-FFT (the ANKH-FFT section): the leaf modified charges reinterpolated onto an
+ *                 equispaced grid per leaf, and every non-adjacent leaf pair, far images included,
+ *                 through one 6D convolution evaluated by FFT (matrix factorisation, diagonalisation
+ *                 and real-spectrum passages).  Needs depth <= 4 (auto depth is capped there) and
+ *                 2 eq_order - 1 node frequencies per axis within the per-block LDS budget (eq_order
+ *                 <= 8 at order <= 8).  The near field, P2M, L2P, self and background terms are
+ *                 those of ANKH-FMM; stage 3 of the timing is the forward node transform, stage 4 the
+ *                 cell transforms and the product with the spectrum, stage 5 is empty and stage 6
+ *                 the inverse node transform with the leaf energies.  The spectrum of the 6D
+ *                 convolution is built at plan time (an image sum per entry on the device). */
+typedef enum { ANKH_FAR_AUTO = 0, ANKH_FAR_FMM = 1, ANKH_FAR_FFT = 2 } ankh_far_field;
 
 typedef struct {
     int64_t n_atoms;
@@ -111,6 +130,8 @@ typedef struct {
     int64_t timed_evals;       /* evaluations averaged into stage_ms */
     int32_t m2l_rank[8];       /* kept rank of the M2L operators per level e = 1..depth (n_u when the
                                   level is not compressed; 0 for e = 0 and e > depth) */
+    int32_t far_field;         /* ANKH_FAR_FMM or ANKH_FAR_FFT */
+    int32_t eq_order;          /* ANKH-FFT: equispaced nodes per axis (0 for ANKH-FMM) */
 } ankh_plan_stats;
 
 /*

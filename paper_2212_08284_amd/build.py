@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libankh.so")
-SOURCES = ["ankh_plan.hip", "ankh_kernels.hip", "ankh_m2l.hip", "ankh_p2p.hip", "ankh_compress.hip", "ankh_induce.hip"]
+SOURCES = ["ankh_plan.hip", "ankh_kernels.hip", "ankh_m2l.hip", "ankh_p2p.hip", "ankh_compress.hip", "ankh_induce.hip", "ankh_fft.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,0 +1,464 @@
+// ANKH-FFT far field (the ANKH-FFT section of the paper): one leaf-level
+// operator instead of the multilevel M2L.
+//
+// The leaf modified charges Q_c (Chebyshev nodes, L per axis) are
+// reinterpolated onto an equispaced grid of Le nodes per axis spanning the
+// leaf, M_c = E Q_c with E[a][i] = U_a(r_i) (the equispaced Lagrange
+// polynomials at the Chebyshev nodes).  The far energy 1/2 v^T A v couples
+// every pair of non-adjacent leaves through the kernel between their grid
+// nodes.  Per axis the entries of A depend only on the cell difference (modulo
+// n = 2^E: the leaf grid is periodic and the image sum of each entry is taken
+// over a displacement cube) and on the node difference in -(Le-1)..Le-1, so A
+// is a 6D convolution: circular of length n in the cell dimensions and, after
+// zero padding to Pa = 2 Le - 1, circular in the node dimensions.  Its
+// diagonalisation by the 6D DFT gives (Theorem / Corollary of the
+// diagonalisation passage, real spectrum by the corollary on mutual
+// interactions)
+//     phi = F^-1 (D . F chi v) / N,   D = F K (real),   Lambda_c = E^T phi_c,
+// and the energy is the leaf form 1/2 sum_c Q_c . Lambda_c, whose gradient the
+// existing L2P stage evaluates.
+//
+// Layout of the spectrum (float64 complex): X[f][c], f = (f1 Pa + f2) Ph + f3
+// over the node frequencies with f3 < Ph = Pa/2 + 1 (the input is real, so the
+// other half follows by conjugate symmetry), c the lexicographic leaf index.
+// Three kernels per evaluation:
+//   k_fft_nodes_fwd  per leaf: E and the node DFT fused into one complex
+//                    matrix B = W E per axis (Pa x L), three separable stages
+//                    in LDS, the half spectrum written to X[f][c];
+//   k_fft_cells      per node frequency: the 3D FFT over the n^3 cells in LDS,
+//                    the product with D / N, the inverse 3D FFT, in place;
+//   k_fft_nodes_inv  per leaf: the adjoint of the first (conj(B)^T per axis,
+//                    the half spectrum counted twice), Lambda_c into the leaf
+//                    row of the local expansions.
+// Plan time: k_fft_table sums the kernel over the images for every entry of
+// the generating cube K[g][a] (cell residue g, node difference a), applies the
+// node DFT, and k_fft_cells (forward only) leaves D = Re F K.
+#include <cmath>
+#include <vector>
+
+#include "ankh_internal.h"
+
+namespace ankh {
+namespace {
+
+constexpr double kPiF = 3.14159265358979323846;
+
+// e^{-2 pi i k / 16}, k = 0..7: the roots of unity of every cell FFT (n <= 16)
+struct Tw16 {
+    double2 w[8];
+};
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cmulc(double2 a, double2 b) {   // conj(a) * b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// blocks are dealt to the 8 XCDs in turn: give each XCD a contiguous range of
+// leaves, so that the partial rows the node kernels write into X[f][.] for
+// neighbouring leaves meet in the same L2
+__device__ inline int64_t xcd_leaf(int64_t b, int64_t ncell) {
+    if (ncell % 8 != 0) return b;
+    return (b % 8) * (ncell / 8) + b / 8;
+}
+
+// radix-2 FFT of N <= 16 points in registers (decimation in time, bit-reversed
+// input order); INV uses the conjugate roots and no scaling
+template <int N, bool INV>
+__device__ inline void fft_line(double2 (&v)[N], const Tw16 &tw) {
+    if constexpr (N > 1) {
+#pragma unroll
+        for (int i = 0; i < N; i++) {
+            int j = 0;
+#pragma unroll
+            for (int b = 1, r = N >> 1; b < N; b <<= 1, r >>= 1)
+                if (i & b) j |= r;
+            if (i < j) {
+                const double2 t = v[i];
+                v[i] = v[j];
+                v[j] = t;
+            }
+        }
+#pragma unroll
+        for (int len = 2; len <= N; len <<= 1) {
+#pragma unroll
+            for (int i = 0; i < N; i += len) {
+#pragma unroll
+                for (int k = 0; k < len / 2; k++) {
+                    double2 w = tw.w[k * (16 / len)];
+                    if (INV) w.y = -w.y;
+                    const double2 u = v[i + k], t = cmul(w, v[i + k + len / 2]);
+                    v[i + k] = make_double2(u.x + t.x, u.y + t.y);
+                    v[i + k + len / 2] = make_double2(u.x - t.x, u.y - t.y);
+                }
+            }
+        }
+    }
+}
+
+// the three separable stages of a forward node transform of one real cube
+// in[lin^3] (x slowest) with the matrix Bm[pa][lin]: X[(f1 pa + f2) ph + f3] =
+// sum_ijk Bm[f1][i] Bm[f2][j] Bm[f3][k] in[i][j][k], written to out[f * ncell]
+__device__ void node_forward(const double *in, int lin, const double2 *Bm, int pa, int ph, double2 *T1, double2 *T2,
+                             double2 *out, int64_t ncell, int nt) {
+    const int t = threadIdx.x;
+    const int ll = lin * lin;
+    for (int o = t; o < pa * ll; o += nt) {          // x: T1[f1][j][k]
+        const int f1 = o / ll, jk = o - f1 * ll;
+        double re = 0, im = 0;
+        for (int i = 0; i < lin; i++) {
+            const double2 b = Bm[f1 * lin + i];
+            const double v = in[i * ll + jk];
+            re += b.x * v;
+            im += b.y * v;
+        }
+        T1[o] = make_double2(re, im);
+    }
+    __syncthreads();
+    for (int o = t; o < pa * pa * lin; o += nt) {    // y: T2[f1][f2][k]
+        const int f1 = o / (pa * lin), r = o - f1 * pa * lin, f2 = r / lin, k = r - f2 * lin;
+        double re = 0, im = 0;
+        for (int j = 0; j < lin; j++) {
+            const double2 b = Bm[f2 * lin + j], v = T1[(f1 * lin + j) * lin + k];
+            re += b.x * v.x - b.y * v.y;
+            im += b.x * v.y + b.y * v.x;
+        }
+        T2[o] = make_double2(re, im);
+    }
+    __syncthreads();
+    for (int o = t; o < pa * pa * ph; o += nt) {     // z, half spectrum
+        const int f12 = o / ph, f3 = o - f12 * ph;
+        double re = 0, im = 0;
+        for (int k = 0; k < lin; k++) {
+            const double2 b = Bm[f3 * lin + k], v = T2[f12 * lin + k];
+            re += b.x * v.x - b.y * v.y;
+            im += b.x * v.y + b.y * v.x;
+        }
+        out[(int64_t)o * ncell] = make_double2(re, im);
+    }
+}
+
+// ---- per evaluation ------------------------------------------------------------
+
+// one wave per leaf: Q (leaf row of the multipoles) -> X[.][c]
+__global__ __launch_bounds__(64) void k_fft_nodes_fwd(const double *Q, int nup, int L, const double2 *B, int pa,
+                                                      int ph, double2 *X, int64_t ncell) {
+    extern __shared__ double2 sm[];
+    double2 *sB = sm, *T1 = sB + pa * L, *T2 = T1 + pa * L * L;
+    double *sQ = reinterpret_cast<double *>(T2 + pa * pa * L);
+    const int64_t c = xcd_leaf(blockIdx.x, ncell);
+    for (int i = threadIdx.x; i < pa * L; i += 64) sB[i] = B[i];
+    for (int i = threadIdx.x; i < L * L * L; i += 64) sQ[i] = Q[c * nup + i];
+    __syncthreads();
+    node_forward(sQ, L, sB, pa, ph, T1, T2, X + c, ncell, 64);
+}
+
+// one wave per leaf: X[.][c] -> Lambda_c = Re sum_f conj(B[f1][i] B[f2][j] B[f3][k]) w(f3) X[f][c],
+// w = 1 for f3 = 0 (and f3 = pa/2 when pa is even), 2 for the other kept f3
+__global__ __launch_bounds__(64) void k_fft_nodes_inv(const double2 *X, const double2 *B, int pa, int ph, int L,
+                                                      double *Lam, int nup, int64_t ncell) {
+    extern __shared__ double2 sm[];
+    double2 *sB = sm, *U = sB + pa * L, *sX = U + pa * pa * L;   // V aliases sX once sX is consumed
+    const int64_t c = xcd_leaf(blockIdx.x, ncell);
+    const int t = threadIdx.x;
+    const int nf = pa * pa * ph;
+    for (int i = t; i < pa * L; i += 64) sB[i] = B[i];
+    for (int f = t; f < nf; f += 64) sX[f] = X[(int64_t)f * ncell + c];
+    __syncthreads();
+    for (int o = t; o < pa * pa * L; o += 64) {      // z: U[f1][f2][k]
+        const int f12 = o / L, k = o - f12 * L;
+        double re = 0, im = 0;
+        for (int f3 = 0; f3 < ph; f3++) {
+            const double w = (f3 == 0 || 2 * f3 == pa) ? 1.0 : 2.0;
+            const double2 v = cmulc(sB[f3 * L + k], sX[f12 * ph + f3]);
+            re += w * v.x;
+            im += w * v.y;
+        }
+        U[o] = make_double2(re, im);
+    }
+    __syncthreads();
+    double2 *V = sX;
+    for (int o = t; o < pa * L * L; o += 64) {       // y: V[f1][j][k]
+        const int f1 = o / (L * L), jk = o - f1 * L * L, j = jk / L, k = jk - j * L;
+        double re = 0, im = 0;
+        for (int f2 = 0; f2 < pa; f2++) {
+            const double2 v = cmulc(sB[f2 * L + j], U[(f1 * pa + f2) * L + k]);
+            re += v.x;
+            im += v.y;
+        }
+        V[o] = make_double2(re, im);
+    }
+    __syncthreads();
+    for (int o = t; o < L * L * L; o += 64) {        // x, real part
+        const int i = o / (L * L), jk = o - i * L * L;
+        double re = 0;
+        for (int f1 = 0; f1 < pa; f1++) re += cmulc(sB[f1 * L + i], V[f1 * L * L + jk]).x;
+        Lam[c * nup + o] = re;
+    }
+}
+
+// one block per kept node frequency f: 3D FFT over the NS^3 cells of X[f][.]
+// in LDS (element (x, y, z) at ((x NS + y) NS + (z ^ y')), y' = the low bits of
+// x NS + y, which spreads every pass over the banks).  MODE 0: forward, times
+// D[f][.] * scale, inverse, back to X.  MODE 1 (plan): forward, the real part
+// to D.
+template <int NS>
+__device__ inline int cell_at(int x, int y, int z) {
+    const int xy = x * NS + y;
+    return xy * NS + (z ^ (xy & (NS - 1)));
+}
+
+template <int NS, int MODE>
+__global__ __launch_bounds__(256) void k_fft_cells(double2 *X, double *D, int64_t ncell, double scale, Tw16 tw) {
+    extern __shared__ double2 sm[];
+    const int64_t f = blockIdx.x;
+    double2 *xf = X + f * ncell;
+    const int t = threadIdx.x;
+    constexpr int NL = NS * NS;
+    for (int i = t; i < NS * NS * NS; i += 256) {
+        const int x = i / NL, y = (i / NS) % NS, z = i % NS;
+        sm[cell_at<NS>(x, y, z)] = xf[i];
+    }
+    __syncthreads();
+    double2 v[NS];
+    if (t < NL) {                                   // z lines
+        const int x = t / NS, y = t % NS;
+#pragma unroll
+        for (int z = 0; z < NS; z++) v[z] = sm[cell_at<NS>(x, y, z)];
+        fft_line<NS, false>(v, tw);
+#pragma unroll
+        for (int z = 0; z < NS; z++) sm[cell_at<NS>(x, y, z)] = v[z];
+    }
+    __syncthreads();
+    if (t < NL) {                                   // y lines
+        const int x = t / NS, z = t % NS;
+#pragma unroll
+        for (int y = 0; y < NS; y++) v[y] = sm[cell_at<NS>(x, y, z)];
+        fft_line<NS, false>(v, tw);
+#pragma unroll
+        for (int y = 0; y < NS; y++) sm[cell_at<NS>(x, y, z)] = v[y];
+    }
+    __syncthreads();
+    if (t < NL) {                                   // x lines, the product with D, and back along x
+        const int y = t / NS, z = t % NS;
+#pragma unroll
+        for (int x = 0; x < NS; x++) v[x] = sm[cell_at<NS>(x, y, z)];
+        fft_line<NS, false>(v, tw);
+        if (MODE == 1) {
+#pragma unroll
+            for (int x = 0; x < NS; x++) D[f * ncell + (x * NS + y) * NS + z] = v[x].x;
+        } else {
+#pragma unroll
+            for (int x = 0; x < NS; x++) {
+                const double d = D[f * ncell + (x * NS + y) * NS + z] * scale;
+                v[x] = make_double2(v[x].x * d, v[x].y * d);
+            }
+            fft_line<NS, true>(v, tw);
+#pragma unroll
+            for (int x = 0; x < NS; x++) sm[cell_at<NS>(x, y, z)] = v[x];
+        }
+    }
+    if (MODE == 1) return;
+    __syncthreads();
+    if (t < NL) {                                   // y lines, inverse
+        const int x = t / NS, z = t % NS;
+#pragma unroll
+        for (int y = 0; y < NS; y++) v[y] = sm[cell_at<NS>(x, y, z)];
+        fft_line<NS, true>(v, tw);
+#pragma unroll
+        for (int y = 0; y < NS; y++) sm[cell_at<NS>(x, y, z)] = v[y];
+    }
+    __syncthreads();
+    if (t < NL) {                                   // z lines, inverse
+        const int x = t / NS, y = t % NS;
+#pragma unroll
+        for (int z = 0; z < NS; z++) v[z] = sm[cell_at<NS>(x, y, z)];
+        fft_line<NS, true>(v, tw);
+#pragma unroll
+        for (int z = 0; z < NS; z++) sm[cell_at<NS>(x, y, z)] = v[z];
+    }
+    __syncthreads();
+    for (int i = t; i < NS * NS * NS; i += 256) {
+        const int x = i / NL, y = (i / NS) % NS, z = i % NS;
+        xf[i] = sm[cell_at<NS>(x, y, z)];
+    }
+}
+
+// ---- plan time: the generating cube of A and its node DFT --------------------
+
+// one block per cell residue g = (gx, gy, gz): K[g][a] for every node difference a (a < Le: a,
+// a > Pa - Le: a - Pa) summed over the cell displacements D = g - n I with |D_axis| <= n (p + 1/2)
+// and max |D| >= 2, then the node DFT (plain roots W[f][a]) into X[.][g]
+__global__ __launch_bounds__(256) void k_fft_table(const double2 *W, int pa, int ph, int le, int nside, int p,
+                                                   double w, double h, double xi, double2 *X, int64_t ncell) {
+    extern __shared__ double2 sm[];
+    double2 *sW = sm;
+    double *cube = reinterpret_cast<double *>(sW + pa * pa);
+    const int64_t g = blockIdx.x;
+    const int gx = (int)(g / ((int64_t)nside * nside)), gy = (int)((g / nside) % nside), gz = (int)(g % nside);
+    const int t = threadIdx.x;
+    for (int i = t; i < pa * pa; i += 256) sW[i] = W[i];
+    const double lim = nside * (p + 0.5);
+    const int n3 = pa * pa * pa;
+    for (int e = t; e < n3; e += 256) {
+        const int a1 = e / (pa * pa), a2 = (e / pa) % pa, a3 = e % pa;
+        const int d1 = a1 < le ? a1 : a1 - pa, d2 = a2 < le ? a2 : a2 - pa, d3 = a3 < le ? a3 : a3 - pa;
+        double s = 0;
+        for (int I = -p - 2; I <= p + 2; I++) {
+            const int Dx = gx - nside * I;
+            if (fabs((double)Dx) > lim) continue;
+            const double zx = Dx * w + d1 * h;
+            for (int J = -p - 2; J <= p + 2; J++) {
+                const int Dy = gy - nside * J;
+                if (fabs((double)Dy) > lim) continue;
+                const double zy = Dy * w + d2 * h;
+                for (int K = -p - 2; K <= p + 2; K++) {
+                    const int Dz = gz - nside * K;
+                    if (fabs((double)Dz) > lim) continue;
+                    if (abs(Dx) < 2 && abs(Dy) < 2 && abs(Dz) < 2) continue;
+                    const double zz = Dz * w + d3 * h;
+                    const double r = sqrt(zx * zx + zy * zy + zz * zz);
+                    s += erfc(xi * r) / r;
+                }
+            }
+        }
+        cube[e] = s;
+    }
+    __syncthreads();
+    // direct node DFT (plan time only): out[f1][f2][f3] = sum_a W[f1][a1] W[f2][a2] W[f3][a3] K[a]
+    for (int o = t; o < pa * pa * ph; o += 256) {
+        const int f1 = o / (pa * ph), f2 = (o / ph) % pa, f3 = o % ph;
+        double re = 0, im = 0;
+        for (int a1 = 0; a1 < pa; a1++) {
+            const double2 w1 = sW[f1 * pa + a1];
+            for (int a2 = 0; a2 < pa; a2++) {
+                const double2 w12 = cmul(w1, sW[f2 * pa + a2]);
+                const double *row = cube + (a1 * pa + a2) * pa;
+                double sr = 0, si = 0;
+                for (int a3 = 0; a3 < pa; a3++) {
+                    const double2 w3 = sW[f3 * pa + a3];
+                    sr += w3.x * row[a3];
+                    si += w3.y * row[a3];
+                }
+                re += w12.x * sr - w12.y * si;
+                im += w12.x * si + w12.y * sr;
+            }
+        }
+        X[(int64_t)o * ncell + g] = make_double2(re, im);
+    }
+}
+
+Tw16 roots16() {
+    Tw16 tw;
+    for (int k = 0; k < 8; k++) {
+        const long double a = -2.0L * (long double)kPiF * k / 16.0L;
+        tw.w[k] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    return tw;
+}
+
+size_t nodes_fwd_lds(int L, int pa) {
+    return sizeof(double2) * ((size_t)pa * L + (size_t)pa * L * L + (size_t)pa * pa * L) + sizeof(double) * L * L * L;
+}
+size_t nodes_inv_lds(int L, int pa, int ph) {
+    const size_t nx = std::max((size_t)pa * pa * ph, (size_t)pa * L * L);
+    return sizeof(double2) * ((size_t)pa * L + (size_t)pa * pa * L + nx);
+}
+size_t table_lds(int pa) { return sizeof(double2) * pa * pa + sizeof(double) * pa * pa * pa; }
+
+template <int MODE>
+hipError_t cells(ankh_plan_s *pl, double2 *X, double *D, double scale) {
+    const size_t shm = sizeof(double2) * pl->nleaf;
+    const dim3 g((unsigned)pl->fft_nf), b(256);
+    const Tw16 tw = roots16();
+    switch (pl->nside) {
+        case 1: hipLaunchKernelGGL((k_fft_cells<1, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, tw); break;
+        case 2: hipLaunchKernelGGL((k_fft_cells<2, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, tw); break;
+        case 4: hipLaunchKernelGGL((k_fft_cells<4, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, tw); break;
+        case 8: hipLaunchKernelGGL((k_fft_cells<8, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, tw); break;
+        default: hipLaunchKernelGGL((k_fft_cells<16, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, tw); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool fft_supported(int depth, int L, int le) {
+    if (depth < 0 || depth > kMaxFftDepth || le < 2 || le > kMaxOrder || L < 2 || L > kMaxOrder) return false;
+    const int pa = 2 * le - 1, ph = pa / 2 + 1;
+    const size_t lim = 65536;
+    return nodes_fwd_lds(L, pa) <= lim && nodes_inv_lds(L, pa, ph) <= lim && table_lds(pa) <= lim &&
+           sizeof(double2) * ((size_t)1 << (3 * depth)) <= lim;
+}
+
+void fft_host_tables(int L, int le, const double *cheb, std::vector<double2> &B, std::vector<double2> &W) {
+    const int pa = 2 * le - 1;
+    // E[a][i] = U_a(r_i): equispaced Lagrange polynomials (nodes -1 + 2a/(le-1)) at the Chebyshev nodes
+    std::vector<long double> E((size_t)le * L);
+    for (int a = 0; a < le; a++)
+        for (int i = 0; i < L; i++) {
+            long double u = 1;
+            const long double ta = -1.0L + 2.0L * a / (le - 1);
+            for (int b = 0; b < le; b++) {
+                if (b == a) continue;
+                const long double tb = -1.0L + 2.0L * b / (le - 1);
+                u *= ((long double)cheb[i] - tb) / (ta - tb);
+            }
+            E[(size_t)a * L + i] = u;
+        }
+    W.assign((size_t)pa * pa, make_double2(0, 0));
+    std::vector<long double> wr((size_t)pa * pa), wi((size_t)pa * pa);
+    for (int f = 0; f < pa; f++)
+        for (int a = 0; a < pa; a++) {
+            const int m = (f * a) % pa;
+            const long double ang = -2.0L * (long double)kPiF * m / pa;
+            wr[(size_t)f * pa + a] = cosl(ang);
+            wi[(size_t)f * pa + a] = sinl(ang);
+            W[(size_t)f * pa + a] = make_double2((double)cosl(ang), (double)sinl(ang));
+        }
+    // B = W[:, :le] E: the reinterpolation and the zero-padded node DFT in one matrix
+    B.assign((size_t)pa * L, make_double2(0, 0));
+    for (int f = 0; f < pa; f++)
+        for (int i = 0; i < L; i++) {
+            long double re = 0, im = 0;
+            for (int a = 0; a < le; a++) {
+                re += wr[(size_t)f * pa + a] * E[(size_t)a * L + i];
+                im += wi[(size_t)f * pa + a] * E[(size_t)a * L + i];
+            }
+            B[(size_t)f * L + i] = make_double2((double)re, (double)im);
+        }
+}
+
+hipError_t launch_fft_build_D(ankh_plan_s *pl) {
+    const int pa = pl->fft_pa, ph = pl->fft_ph, le = pl->eq_order;
+    const double w = pl->edge / pl->nside;
+    hipLaunchKernelGGL(k_fft_table, dim3((unsigned)pl->nleaf), dim3(256), table_lds(pa), pl->stream, pl->d_fftW, pa,
+                       ph, le, pl->nside, pl->images, w, w / (le - 1), pl->xi, pl->d_fftX, pl->nleaf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return cells<1>(pl, pl->d_fftX, pl->d_fftD, 1.0);
+}
+
+hipError_t launch_fft_forward(ankh_plan_s *pl) {
+    const int L = pl->order, pa = pl->fft_pa;
+    const double *Q = pl->d_M + pl->lv[pl->depth].cell0 * pl->nup;
+    hipLaunchKernelGGL(k_fft_nodes_fwd, dim3((unsigned)pl->nleaf), dim3(64), nodes_fwd_lds(L, pa), pl->stream, Q,
+                       pl->nup, L, pl->d_fftB, pa, pl->fft_ph, pl->d_fftX, pl->nleaf);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_cells(ankh_plan_s *pl) {
+    const double n6 = (double)pl->nleaf * pl->fft_pa * pl->fft_pa * pl->fft_pa;
+    return cells<0>(pl, pl->d_fftX, pl->d_fftD, 1.0 / n6);
+}
+
+hipError_t launch_fft_inverse(ankh_plan_s *pl) {
+    const int L = pl->order, pa = pl->fft_pa, ph = pl->fft_ph;
+    double *Lam = pl->d_L + pl->lv[pl->depth].cell0 * pl->nup;
+    hipLaunchKernelGGL(k_fft_nodes_inv, dim3((unsigned)pl->nleaf), dim3(64), nodes_inv_lds(L, pa, ph), pl->stream,
+                       pl->d_fftX, pl->d_fftB, pa, ph, L, Lam, pl->nup, pl->nleaf);
+    return hipGetLastError();
+}
+
+}  // namespace ankh

@@ -17,6 +17,7 @@ constexpr int kMaxOrder = 10;        // largest Chebyshev order per axis of the 
 constexpr int kMaxRootOrder = 12;    // largest order of the root (far-image) grid
 constexpr int kMaxRootNodes = kMaxRootOrder * kMaxRootOrder * kMaxRootOrder;
 constexpr int kMaxDepth = 7;         // 2^21 leaves at most
+constexpr int kMaxFftDepth = 4;      // ANKH-FFT: the n^3 cells of one node frequency fit one block's LDS
 constexpr int kNumOff = 343;         // slots for offsets d in [-3,3]^3 (316 used)
 constexpr int kNumIL = 189;          // interaction-list length of every cell
 constexpr int kRedBlocks = 1024;     // first-stage blocks of the energy reduction (the epilogue)
@@ -113,6 +114,14 @@ struct ankh_plan_s {
     int32_t *d_err = nullptr;     // latched device errors [4]: non-finite, theta trace, invalid value
     double *d_ind = nullptr;      // induced-dipole solver vectors (allocated by the first ankh_induce)
     double *d_mom = nullptr;      // near-field dE/dq, dE/dTheta [7][n] (allocated by the first ankh_energy_derivs)
+    // ANKH-FFT far field: equispaced order, node period pa = 2 eq_order - 1, kept node frequencies
+    // fft_nf = pa * pa * (pa / 2 + 1); B = node DFT x reinterpolation [pa][order], W = plain node
+    // DFT [pa][pa], spectrum work X [fft_nf][nleaf] (complex), real spectrum D [fft_nf][nleaf]
+    int far_field = ANKH_FAR_FMM;
+    int eq_order = 0, fft_pa = 0, fft_ph = 0;
+    int64_t fft_nf = 0;
+    double2 *d_fftB = nullptr, *d_fftW = nullptr, *d_fftX = nullptr;
+    double *d_fftD = nullptr;
     size_t bytes = 0;
 
     // statistics / timing
@@ -164,5 +173,12 @@ ankh_status evaluate(ankh_plan_s *pl, const double *pos, const double *q, const 
 hipError_t launch_build_m2l(ankh_plan_s *pl, int e, double *K);
 hipError_t launch_build_cper(ankh_plan_s *pl);
 hipError_t launch_convert_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+// ANKH-FFT (ankh_fft.hip)
+bool fft_supported(int depth, int L, int eq_order);
+void fft_host_tables(int L, int eq_order, const double *cheb_nodes, std::vector<double2> &B, std::vector<double2> &W);
+hipError_t launch_fft_build_D(ankh_plan_s *pl);    // plan time: the real spectrum D
+hipError_t launch_fft_forward(ankh_plan_s *pl);    // leaf multipoles -> half spectrum X
+hipError_t launch_fft_cells(ankh_plan_s *pl);      // cell transforms, product with D, inverse
+hipError_t launch_fft_inverse(ankh_plan_s *pl);    // X -> leaf local expansions
 
 }  // namespace ankh

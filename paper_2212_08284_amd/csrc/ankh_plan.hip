@@ -46,7 +46,8 @@ void free_all(ankh_plan_s *pl) {
                     pl->d_G, pl->d_terms, pl->d_part, pl->d_err, pl->d_tab0, pl->d_Mf, pl->d_m2l_part,
                     pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr,
                     pl->d_Kb, pl->d_Mb, pl->d_slot_e, pl->d_slot_f, pl->d_slot_g, pl->d_cper_part,
-                    pl->d_U, pl->d_Mc, pl->d_Lc, pl->d_ind, pl->d_mom};
+                    pl->d_U, pl->d_Mc, pl->d_Lc, pl->d_ind, pl->d_mom, pl->d_fftB, pl->d_fftW, pl->d_fftX,
+                    pl->d_fftD};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &set : pl->evsets)
@@ -158,15 +159,26 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
         }
         ck(launch_p2m(pl, ord));
         mark(3);
-        for (int e = pl->depth - 1; e >= 0; e--) ck(launch_m2m(pl, e));
-        mark(4);
-        ck(launch_m2l_project(pl));
-        for (int e = 1; e <= pl->depth; e++) ck(launch_m2l(pl, e));
-        ck(launch_m2l_expand(pl));
-        mark(5);
-        ck(launch_cper(pl));
-        mark(6);
-        for (int e = 1; e <= pl->depth; e++) ck(launch_l2l(pl, e));
+        if (pl->far_field == ANKH_FAR_FFT) {
+            // ANKH-FFT: node transforms, cell transforms with the spectrum, inverse node
+            // transforms into the leaf local expansions (far images included in the spectrum)
+            ck(launch_fft_forward(pl));
+            mark(4);
+            ck(launch_fft_cells(pl));
+            mark(5);
+            mark(6);
+            ck(launch_fft_inverse(pl));
+        } else {
+            for (int e = pl->depth - 1; e >= 0; e--) ck(launch_m2m(pl, e));
+            mark(4);
+            ck(launch_m2l_project(pl));
+            for (int e = 1; e <= pl->depth; e++) ck(launch_m2l(pl, e));
+            ck(launch_m2l_expand(pl));
+            mark(5);
+            ck(launch_cper(pl));
+            mark(6);
+            for (int e = 1; e <= pl->depth; e++) ck(launch_l2l(pl, e));
+        }
         ck(launch_leafdot(pl));
         mark(7);
         if (adj) ck(launch_l2p(pl, ord, fields));
@@ -239,6 +251,8 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         if (ov->images > 64) return ANKH_ERR_INVALID_ARG;
         if (!std::isfinite(ov->xi)) return ANKH_ERR_INVALID_ARG;
         if (!std::isfinite(ov->m2l_tol) || ov->m2l_tol >= 1) return ANKH_ERR_INVALID_ARG;
+        if (ov->far_field < 0 || ov->far_field > ANKH_FAR_FFT) return ANKH_ERR_INVALID_ARG;
+        if (ov->eq_order != 0 && (ov->eq_order < 2 || ov->eq_order > kMaxOrder)) return ANKH_ERR_INVALID_ARG;
     }
     auto t0 = std::chrono::steady_clock::now();
     ankh_plan_s *pl = new (std::nothrow) ankh_plan_s();
@@ -264,7 +278,22 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
     pl->order = (ov && ov->order > 0) ? ov->order : order_for(rel_accuracy);
     pl->nu = pl->order * pl->order * pl->order;
     pl->nup = (pl->nu + 31) / 32 * 32;   // row stride: a multiple of the M2L tile step
+    pl->far_field = (ov && ov->far_field == ANKH_FAR_FFT) ? ANKH_FAR_FFT : ANKH_FAR_FMM;
+    const bool fft = pl->far_field == ANKH_FAR_FFT;
     pl->depth = (ov && ov->depth >= 0) ? ov->depth : depth_for(n_atoms, pl->nu);
+    if (fft) {
+        // ANKH-FFT: equispaced order (the Chebyshev order unless set); the automatic depth stops at
+        // the deepest tree whose cell transforms fit one block
+        pl->eq_order = (ov && ov->eq_order > 0) ? ov->eq_order : pl->order;
+        if (!(ov && ov->depth >= 0)) pl->depth = std::min(pl->depth, kMaxFftDepth);
+        if (!fft_supported(pl->depth, pl->order, pl->eq_order)) {
+            delete pl;
+            return ANKH_ERR_INVALID_ARG;
+        }
+        pl->fft_pa = 2 * pl->eq_order - 1;
+        pl->fft_ph = pl->fft_pa / 2 + 1;
+        pl->fft_nf = (int64_t)pl->fft_pa * pl->fft_pa * pl->fft_ph;
+    }
     pl->nside = 1 << pl->depth;
     pl->nleaf = (int64_t)pl->nside * pl->nside * pl->nside;
     size_t cells = 0;
@@ -390,9 +419,9 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         // when that pays, then kept in the working precision) and the far-image root operator
         for (int e = 0; e <= pl->depth; e++) {
             pl->rpad[e] = pl->nup;
-            pl->m2l_rank[e] = e >= 1 ? pl->nu : 0;
+            pl->m2l_rank[e] = (e >= 1 && !fft) ? pl->nu : 0;
         }
-        if (pl->depth >= 1) {
+        if (pl->depth >= 1 && !fft) {
             const double tol = (ov && ov->m2l_tol != 0) ? ov->m2l_tol : 0.1 * rel_accuracy;
             const bool compress = tol > 0 && pl->nu <= 400;
             const bool bf = precision == ANKH_MIXED_BF16X3;
@@ -455,7 +484,21 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
             if (precision == ANKH_MIXED) dalloc(pl, &pl->d_Mf, mlev);
             if (bf) dalloc(pl, &pl->d_Mb, 2 * mlev);
         }
-        ck(launch_build_cper(pl));
+        if (fft) {
+            // the 6D spectrum: node transforms of the reinterpolation (B) and of the generating
+            // cube (W), the work spectrum X and the real spectrum D
+            std::vector<double2> B, W;
+            fft_host_tables(pl->order, pl->eq_order, pl->nodes, B, W);
+            dalloc(pl, &pl->d_fftB, B.size());
+            dalloc(pl, &pl->d_fftW, W.size());
+            dalloc(pl, &pl->d_fftX, (size_t)pl->fft_nf * pl->nleaf);
+            dalloc(pl, &pl->d_fftD, (size_t)pl->fft_nf * pl->nleaf);
+            ck(hipMemcpy(pl->d_fftB, B.data(), B.size() * sizeof(double2), hipMemcpyHostToDevice));
+            ck(hipMemcpy(pl->d_fftW, W.data(), W.size() * sizeof(double2), hipMemcpyHostToDevice));
+            ck(launch_fft_build_D(pl));
+        } else {
+            ck(launch_build_cper(pl));
+        }
         ck(hipStreamSynchronize(pl->stream));
     } catch (const std::bad_alloc &) {
         free_all(pl);
@@ -556,6 +599,8 @@ ankh_status ankh_get_stats(ankh_plan_t pl, ankh_plan_stats *out) {
         if (r < pl->nu) out->m2l_flops += 4.0 * pl->nu * r * ncell;
     }
     for (int e = 0; e < 8; e++) out->m2l_rank[e] = (e >= 1 && e <= pl->depth) ? pl->m2l_rank[e] : 0;
+    out->far_field = pl->far_field;
+    out->eq_order = pl->far_field == ANKH_FAR_FFT ? pl->eq_order : 0;
     out->near_pairs = -1;
     if (pl->last_kind) {
         std::vector<int32_t> offs(pl->nleaf + 1);
