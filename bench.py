@@ -1,14 +1,17 @@
 """Benchmark of the interpolated-Ewald hot path on one MI355X.
 
 One step = one energy + forces + fields evaluation (the whole hot path:
-sort, P2M, M2M, M2L on every level, far-image root operator, L2L, L2P, P2P,
-reductions) of the synthetic water box of 96,000 rigid 3-site molecules
+sort, P2M, the far field, L2P, P2P, reductions) of the synthetic water box
+of 96,000 rigid 3-site molecules
 (288,000 atoms, edge 142.18 A, charges + dipoles + quadrupoles), inputs
 resident in HBM.  The mixed-precision path is the headline; the FP64 path is
 timed on the same inputs and plan parameters for the speed-up and the
-accuracy of the mixed path.
+accuracy of the mixed path.  The far field is ANKH-FFT by default (forward
+node transform, cell FFTs with the spectrum, inverse node transform); with
+--far fmm it is the multilevel chain (M2M, M2L on every level, far-image root
+operator, L2L).  The other method is timed on the same input for comparison.
 
-Prints one JSON line (see the design doc for the fields).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -30,7 +33,7 @@ METRIC = "E+forces evals/s per atom on 1 MI355X, mixed vs FP64, rel RMS force er
 # form evaluates each pair once): the pair kernel's formula for charges +
 # dipoles + quadrupoles with the energy, the force, the field at both atoms and
 # the accumulation into both atoms, counted term by term from its source
-# (FMA = 2, add / mul = 1, erfc / exp / rsqrt = 1 each).  Breakdown in the design doc.
+# (FMA = 2, add / mul = 1, erfc / exp / rsqrt = 1 each).
 P2P_FLOP_PER_UNORDERED_PAIR = 300.0
 
 # HBM traffic of one P2P launch measured with rocprofv3 counters (FETCH_SIZE and
@@ -41,7 +44,8 @@ P2P_COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profile
 P2P_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2212_08284_amd", "csrc",
                           "ankh_p2p.hip")
 
-PEAK = {  # MI355X, TFLOP/s
+PEAK = {  # MI355X, TFLOP/s (hbm: GB/s)
+    "hbm": 8000.0,
     "valu_fp64": 78.6,    # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
     "valu_fp32": 78.6,    # the same issue rate: packed FP32 (157.3) is not used by this build
     "valu_fp32_packed": 157.3,
@@ -167,13 +171,18 @@ def main():
     ap.add_argument("--no-induce", action="store_true", help="skip the induced-dipole solve")
     ap.add_argument("--no-derivs", action="store_true", help="skip the charge / quadrupole derivative timing")
     ap.add_argument("--induce-tol", type=float, default=1e-6)
+    ap.add_argument("--far", default="fft", choices=["fmm", "fft"],
+                    help="far-field method of the timed path: ANKH-FFT (the variant the paper times) or "
+                         "ANKH-FMM (multilevel M2L)")
+    ap.add_argument("--no-far-compare", action="store_true",
+                    help="skip timing the other far-field method on the same input")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the timed region, one device-to-device copy of this many MiB (a plain copy kernel "
                          "of known size that calibrates the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU sharding is a "
-              f"design only (DESIGN.md)", file=sys.stderr)
+              f"design only", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -203,10 +212,24 @@ def main():
     rB = 0.5 * data["edge"]
     log(f"workload {args.workload}: n={n} edge={data['edge']:.3f}")
 
-    pm = ak.Plan(n, rB, args.eps, 2, args.mode)
+    pm = ak.Plan(n, rB, args.eps, 2, args.mode, far=args.far)
     log(f"mixed plan: {pm.stats}")
     t_mixed, st_mixed, bd_mixed, out_mixed = timed_run(pm, args_dev, args.steps, args.warmup, torch)
     log(f"mixed: {t_mixed * 1e3:.3f} ms/step timed stages {st_mixed['stage_ms']} breakdown {bd_mixed}")
+
+    far_other = None
+    if not args.no_far_compare:
+        alt = "fft" if args.far == "fmm" else "fmm"
+        pa = ak.Plan(n, rB, args.eps, 2, args.mode, far=alt)
+        t_a, st_a, bd_a, out_a = timed_run(pa, args_dev, args.steps, args.warmup, torch)
+        Em, Fm, Gm = [x.double().cpu().numpy() for x in out_mixed]
+        Ea, Fa, Ga = [x.double().cpu().numpy() for x in out_a]
+        far_other = {"far": alt, "ms_per_step": t_a * 1e3, "value": n / t_a, "plan_ms": st_a["plan_ms"],
+                     "depth": st_a["depth"], "eq_order": st_a["eq_order"], "stage_ms": bd_a,
+                     "rel_energy_diff": float(abs(Ea[0] - Em[0]) / abs(Em[0])),
+                     "rel_rms_force_diff": rel_rms(Fa, Fm), "rel_rms_field_diff": rel_rms(Ga, Gm)}
+        pa.close()
+        log(f"{alt}: {far_other}")
 
     derivs = None
     if not args.no_derivs:
@@ -221,7 +244,7 @@ def main():
 
     res = {}
     if not args.mixed_only:
-        pf = ak.Plan(n, rB, args.eps, 2, "fp64")
+        pf = ak.Plan(n, rB, args.eps, 2, "fp64", far=args.far)
         t_fp64, st_fp64, bd_fp64, out_fp64 = timed_run(pf, args_dev, args.steps, args.warmup, torch)
         if derivs is not None:
             d64, dfp = derivs_run(pf, args_dev, torch)
@@ -273,6 +296,19 @@ def main():
                 "note": "algorithmic flops per cell of level e: 2 * 189 * r_e^2 (r_e the kept rank of the compressed "
                         "operators, n_u if uncompressed) + 4 * n_u * r_e for the basis change; the BF16x3 split issues 3x "
                         "the contraction flops", "ranks": st_mixed.get("m2l_rank")}
+    if args.far == "fft":
+        # stage 4 of ANKH-FFT is the cell-transform kernel: per launch it reads and writes the half
+        # spectrum (complex float64) and reads the real spectrum, 40 B per kept node frequency and leaf
+        pa = 2 * st_mixed["eq_order"] - 1
+        nf = pa * pa * (pa // 2 + 1)
+        nleaf = 8 ** st_mixed["depth"]
+        fft_bytes = 40.0 * nf * nleaf
+        fft_gbs = fft_bytes / (sm["m2l"] * 1e-3) / 1e9
+        m2l_roof = {"kernel": "fft_cells", "bound": "hbm", "achieved": fft_gbs, "peak": PEAK["hbm"], "unit": "GB/s",
+                    "frac": fft_gbs / PEAK["hbm"], "traffic": None, "bytes_per_launch": fft_bytes,
+                    "avg_launch_ms": sm["m2l"],
+                    "note": f"ANKH-FFT cell transforms: {nf} kept node frequencies x {nleaf} leaves, each read and "
+                            "written once as complex float64 and multiplied by the real spectrum (float64)"}
     roof, other = (p2p_roof, m2l_roof) if sm["p2p"] >= sm["m2l"] else (m2l_roof, p2p_roof)
 
     line = {
@@ -292,17 +328,23 @@ def main():
         "config": {"workload": f"{args.workload}: rigid 3-site water, q+mu+Theta, energy+forces+fields",
                    "n_atoms": n, "edge_A": data["edge"], "rel_accuracy": args.eps,
                    "depth": st_mixed["depth"], "order": st_mixed["order"], "images": st_mixed["images"],
-                   "xi": st_mixed["xi"], "parallelism": "single GPU"},
+                   "xi": st_mixed["xi"], "far_field": args.far, "eq_order": st_mixed["eq_order"],
+                   "parallelism": "single GPU"},
+        "plan_ms": st_mixed["plan_ms"],
         "evals_per_s": 1.0 / t_mixed,
         "ns_per_day_equiv_dt2fs": 86400.0 / t_mixed * 2e-6,
         "stage_ms": bd_mixed,
         "stage_ms_note": "a separate pass of the same number of steps with an event at every stage boundary and the "
                          "stages in sequence on one stream; the timed steps overlap the far-field chain with the pair "
-                         "kernel and carry events around the M2L and pair-kernel stages only",
+                         "kernel and carry events around stage 4 (the M2L, or the cell transforms of ANKH-FFT) and the "
+                         "pair kernel only.  ANKH-FFT stages: m2m = forward node transform, m2l = cell transforms "
+                         "with the spectrum, l2l = inverse node transform + leaf energies, periodic = none",
         "roofline": roof,
         "roofline_" + other["kernel"]: other,
     }
     line.update(res)
+    if far_other is not None:
+        line["far_other"] = far_other
     if derivs is not None:
         line["derivs"] = derivs
     if induce is not None:
