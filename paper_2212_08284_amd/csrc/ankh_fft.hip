@@ -285,6 +285,124 @@ __global__ __launch_bounds__(256) void k_fft_cells(double2 *X, double *D, int64_
     }
 }
 
+// ---- per evaluation, equispaced order = Chebyshev order (pa = 2L - 1, ph = L) --
+// Four consecutive leaves per block (the leaves of one XCD are consecutive, so
+// each row X[f][.] receives 64-byte runs), each line of an axis held in
+// registers by one thread, B read with uniform addresses (scalar loads).
+constexpr int kCB = 4;
+
+template <int L>
+__global__ __launch_bounds__(256) void k_fft_nodes_fwd_t(const double *Q, int nup, const double2 *B, double2 *X,
+                                                         int64_t ncell) {
+    constexpr int PA = 2 * L - 1, PH = L, NQ = L * L * L, NT2 = PA * PA * L;
+    __shared__ double sQ[kCB][NQ];
+    __shared__ double2 T2[kCB][NT2];
+    const int64_t c0 = xcd_leaf(blockIdx.x, ncell / kCB) * kCB;
+    const int t = threadIdx.x;
+    for (int i = t; i < kCB * NQ; i += 256) sQ[i / NQ][i % NQ] = Q[(c0 + i / NQ) * nup + i % NQ];
+    __syncthreads();
+    // x and y: thread (cell, f1, k): t1[j] = sum_i B[f1][i] Q[i][j][k], T2[f1][f2][k] = sum_j B[f2][j] t1[j]
+    for (int o = t; o < kCB * PA * L; o += 256) {
+        const int cell = o / (PA * L), r = o - cell * PA * L, f1 = r / L, k = r - f1 * L;
+        double2 t1[L];
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            double re = 0, im = 0;
+#pragma unroll
+            for (int i = 0; i < L; i++) {
+                const double2 b = B[f1 * L + i];
+                const double q = sQ[cell][(i * L + j) * L + k];
+                re += b.x * q;
+                im += b.y * q;
+            }
+            t1[j] = make_double2(re, im);
+        }
+#pragma unroll
+        for (int f2 = 0; f2 < PA; f2++) {
+            double re = 0, im = 0;
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                const double2 b = B[f2 * L + j];
+                re += b.x * t1[j].x - b.y * t1[j].y;
+                im += b.x * t1[j].y + b.y * t1[j].x;
+            }
+            T2[cell][(f1 * PA + f2) * L + k] = make_double2(re, im);
+        }
+    }
+    __syncthreads();
+    // z, half spectrum: thread (line f1 f2, cell), the kCB cells of a line adjacent
+    for (int o = t; o < kCB * PA * PA; o += 256) {
+        const int cell = o % kCB, f12 = o / kCB;
+        double2 v[L];
+#pragma unroll
+        for (int k = 0; k < L; k++) v[k] = T2[cell][f12 * L + k];
+#pragma unroll
+        for (int f3 = 0; f3 < PH; f3++) {
+            double re = 0, im = 0;
+#pragma unroll
+            for (int k = 0; k < L; k++) {
+                const double2 b = B[f3 * L + k];
+                re += b.x * v[k].x - b.y * v[k].y;
+                im += b.x * v[k].y + b.y * v[k].x;
+            }
+            X[(int64_t)(f12 * PH + f3) * ncell + c0 + cell] = make_double2(re, im);
+        }
+    }
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void k_fft_nodes_inv_t(const double2 *X, const double2 *B, double *Lam, int nup,
+                                                         int64_t ncell) {
+    constexpr int PA = 2 * L - 1, PH = L, NU = PA * PA * L;
+    __shared__ double2 U[kCB][NU];
+    const int64_t c0 = xcd_leaf(blockIdx.x, ncell / kCB) * kCB;
+    const int t = threadIdx.x;
+    // z: thread (line f1 f2, cell): U[f1][f2][k] = sum_f3 w(f3) conj(B[f3][k]) X[f1 f2 f3]
+    for (int o = t; o < kCB * PA * PA; o += 256) {
+        const int cell = o % kCB, f12 = o / kCB;
+        double2 x[PH];
+#pragma unroll
+        for (int f3 = 0; f3 < PH; f3++) x[f3] = X[(int64_t)(f12 * PH + f3) * ncell + c0 + cell];
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            double re = 0, im = 0;
+#pragma unroll
+            for (int f3 = 0; f3 < PH; f3++) {
+                const double w = f3 == 0 ? 1.0 : 2.0;           // pa odd: no unpaired frequency besides 0
+                const double2 v = cmulc(B[f3 * L + k], x[f3]);
+                re += w * v.x;
+                im += w * v.y;
+            }
+            U[cell][f12 * L + k] = make_double2(re, im);
+        }
+    }
+    __syncthreads();
+    // y and x: thread (cell, j, k): v[f1] = sum_f2 conj(B[f2][j]) U[f1][f2][k],
+    // Lambda[i][j][k] = Re sum_f1 conj(B[f1][i]) v[f1]
+    for (int o = t; o < kCB * L * L; o += 256) {
+        const int cell = o / (L * L), jk = o - cell * L * L, j = jk / L, k = jk - j * L;
+        double2 v[PA];
+#pragma unroll
+        for (int f1 = 0; f1 < PA; f1++) {
+            double re = 0, im = 0;
+#pragma unroll
+            for (int f2 = 0; f2 < PA; f2++) {
+                const double2 u = cmulc(B[f2 * L + j], U[cell][(f1 * PA + f2) * L + k]);
+                re += u.x;
+                im += u.y;
+            }
+            v[f1] = make_double2(re, im);
+        }
+#pragma unroll
+        for (int i = 0; i < L; i++) {
+            double re = 0;
+#pragma unroll
+            for (int f1 = 0; f1 < PA; f1++) re += cmulc(B[f1 * L + i], v[f1]).x;
+            Lam[(c0 + cell) * nup + (i * L + j) * L + k] = re;
+        }
+    }
+}
+
 // ---- plan time: the generating cube of A and its node DFT --------------------
 
 // one block per cell residue g = (gx, gy, gz): K[g][a] for every node difference a (a < Le: a,
@@ -440,9 +558,31 @@ hipError_t launch_fft_build_D(ankh_plan_s *pl) {
     return cells<1>(pl, pl->d_fftX, pl->d_fftD, 1.0);
 }
 
+// the register-blocked kernels for equispaced order = Chebyshev order <= 6 (four leaves per block
+// within 64 KB of LDS; at least 8 leaves), else the generic ones
+static bool fast_nodes(const ankh_plan_s *pl) {
+    return pl->eq_order == pl->order && pl->order >= 3 && pl->order <= 6 && pl->nleaf % (8 * kCB) == 0;
+}
+
+#define ANKH_FFT_ORDERS(L, X) \
+    switch (L) {              \
+        case 3: X(3); break;  \
+        case 4: X(4); break;  \
+        case 5: X(5); break;  \
+        default: X(6); break; \
+    }
+
 hipError_t launch_fft_forward(ankh_plan_s *pl) {
     const int L = pl->order, pa = pl->fft_pa;
     const double *Q = pl->d_M + pl->lv[pl->depth].cell0 * pl->nup;
+    if (fast_nodes(pl)) {
+        const dim3 g((unsigned)(pl->nleaf / kCB)), b(256);
+#define ANKH_FWD(LL) \
+        hipLaunchKernelGGL(k_fft_nodes_fwd_t<LL>, g, b, 0, pl->stream, Q, pl->nup, pl->d_fftB, pl->d_fftX, pl->nleaf)
+        ANKH_FFT_ORDERS(L, ANKH_FWD)
+#undef ANKH_FWD
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_fft_nodes_fwd, dim3((unsigned)pl->nleaf), dim3(64), nodes_fwd_lds(L, pa), pl->stream, Q,
                        pl->nup, L, pl->d_fftB, pa, pl->fft_ph, pl->d_fftX, pl->nleaf);
     return hipGetLastError();
@@ -456,6 +596,14 @@ hipError_t launch_fft_cells(ankh_plan_s *pl) {
 hipError_t launch_fft_inverse(ankh_plan_s *pl) {
     const int L = pl->order, pa = pl->fft_pa, ph = pl->fft_ph;
     double *Lam = pl->d_L + pl->lv[pl->depth].cell0 * pl->nup;
+    if (fast_nodes(pl)) {
+        const dim3 g((unsigned)(pl->nleaf / kCB)), b(256);
+#define ANKH_INV(LL) \
+        hipLaunchKernelGGL(k_fft_nodes_inv_t<LL>, g, b, 0, pl->stream, pl->d_fftX, pl->d_fftB, Lam, pl->nup, pl->nleaf)
+        ANKH_FFT_ORDERS(L, ANKH_INV)
+#undef ANKH_INV
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_fft_nodes_inv, dim3((unsigned)pl->nleaf), dim3(64), nodes_inv_lds(L, pa, ph), pl->stream,
                        pl->d_fftX, pl->d_fftB, pa, ph, L, Lam, pl->nup, pl->nleaf);
     return hipGetLastError();
