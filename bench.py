@@ -43,6 +43,10 @@ P2P_COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profile
                             "p2p_water_288000_counters.txt")
 P2P_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2212_08284_amd", "csrc",
                           "ankh_p2p.hip")
+FFT_COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "fft_cells_water_288000_counters.txt")
+FFT_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2212_08284_amd", "csrc",
+                          "ankh_fft.hip")
 
 PEAK = {  # MI355X, TFLOP/s (hbm: GB/s)
     "hbm": 8000.0,
@@ -55,17 +59,18 @@ PEAK = {  # MI355X, TFLOP/s (hbm: GB/s)
 }
 
 
-def p2p_traffic():
-    """Calibrated HBM bytes per P2P launch from the committed counter summary, or None."""
+def p2p_traffic(counters=P2P_COUNTERS, source=P2P_SOURCE):
+    """Calibrated HBM bytes per launch of a kernel from its committed counter summary, or None when
+    the summary is missing or the kernel source has changed since."""
     import hashlib
     try:
         rec = {}
-        with open(P2P_COUNTERS) as fh:
+        with open(counters) as fh:
             for ln in fh:
                 if "=" in ln and not ln.lstrip().startswith("#"):
                     k, v = ln.split("=", 1)
                     rec[k.strip()] = v.strip()
-        with open(P2P_SOURCE, "rb") as fh:
+        with open(source, "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
         if rec.get("kernel_source_sha256") != sha:
             return None
@@ -305,7 +310,11 @@ def main():
         fft_bytes = 40.0 * nf * nleaf
         fft_gbs = fft_bytes / (sm["m2l"] * 1e-3) / 1e9
         m2l_roof = {"kernel": "fft_cells", "bound": "hbm", "achieved": fft_gbs, "peak": PEAK["hbm"], "unit": "GB/s",
-                    "frac": fft_gbs / PEAK["hbm"], "traffic": None, "bytes_per_launch": fft_bytes,
+                    "frac": fft_gbs / PEAK["hbm"], "traffic": p2p_traffic(FFT_COUNTERS, FFT_SOURCE),
+                    "bytes_per_launch": fft_bytes,
+                    "alone_avg_launch_ms": bd_mixed["m2l"],
+                    "alone_achieved": fft_bytes / (bd_mixed["m2l"] * 1e-3) / 1e9,
+                    "alone_frac": fft_bytes / (bd_mixed["m2l"] * 1e-3) / 1e9 / PEAK["hbm"],
                     "avg_launch_ms": sm["m2l"],
                     "note": f"ANKH-FFT cell transforms: {nf} kept node frequencies x {nleaf} leaves, each read and "
                             "written once as complex float64 and multiplied by the real spectrum (float64)"}
