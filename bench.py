@@ -179,6 +179,8 @@ def main():
     ap.add_argument("--far", default="fft", choices=["fmm", "fft"],
                     help="far-field method of the timed path: ANKH-FFT (the variant the paper times) or "
                          "ANKH-FMM (multilevel M2L)")
+    ap.add_argument("--overlap", default="auto", choices=["auto", "on", "off"],
+                    help="far-field chain beside the pair kernel on a second stream (auto: the plan's choice)")
     ap.add_argument("--no-far-compare", action="store_true",
                     help="skip timing the other far-field method on the same input")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -217,7 +219,8 @@ def main():
     rB = 0.5 * data["edge"]
     log(f"workload {args.workload}: n={n} edge={data['edge']:.3f}")
 
-    pm = ak.Plan(n, rB, args.eps, 2, args.mode, far=args.far)
+    ovl = {"auto": None, "on": True, "off": False}[args.overlap]
+    pm = ak.Plan(n, rB, args.eps, 2, args.mode, far=args.far, overlap=ovl)
     log(f"mixed plan: {pm.stats}")
     t_mixed, st_mixed, bd_mixed, out_mixed = timed_run(pm, args_dev, args.steps, args.warmup, torch)
     log(f"mixed: {t_mixed * 1e3:.3f} ms/step timed stages {st_mixed['stage_ms']} breakdown {bd_mixed}")
@@ -225,7 +228,7 @@ def main():
     far_other = None
     if not args.no_far_compare:
         alt = "fft" if args.far == "fmm" else "fmm"
-        pa = ak.Plan(n, rB, args.eps, 2, args.mode, far=alt)
+        pa = ak.Plan(n, rB, args.eps, 2, args.mode, far=alt, overlap=ovl)
         t_a, st_a, bd_a, out_a = timed_run(pa, args_dev, args.steps, args.warmup, torch)
         Em, Fm, Gm = [x.double().cpu().numpy() for x in out_mixed]
         Ea, Fa, Ga = [x.double().cpu().numpy() for x in out_a]
@@ -249,7 +252,7 @@ def main():
 
     res = {}
     if not args.mixed_only:
-        pf = ak.Plan(n, rB, args.eps, 2, "fp64", far=args.far)
+        pf = ak.Plan(n, rB, args.eps, 2, "fp64", far=args.far, overlap=ovl)
         t_fp64, st_fp64, bd_fp64, out_fp64 = timed_run(pf, args_dev, args.steps, args.warmup, torch)
         if derivs is not None:
             d64, dfp = derivs_run(pf, args_dev, torch)
@@ -338,6 +341,7 @@ def main():
                    "n_atoms": n, "edge_A": data["edge"], "rel_accuracy": args.eps,
                    "depth": st_mixed["depth"], "order": st_mixed["order"], "images": st_mixed["images"],
                    "xi": st_mixed["xi"], "far_field": args.far, "eq_order": st_mixed["eq_order"],
+                   "overlap": bool(st_mixed["overlap"]),
                    "parallelism": "single GPU"},
         "plan_ms": st_mixed["plan_ms"],
         "evals_per_s": 1.0 / t_mixed,

@@ -32,10 +32,11 @@
  * Streams: all work of a plan is ordered on the HIP stream given to
  * ankh_plan (NULL = the default stream) and is asynchronous; outputs are
  * valid after that stream is synchronised or after ankh_sync.  Within an
- * evaluation the far-field chain runs on a second stream that the plan owns,
- * forked from that stream after the particles are sorted and joined back
- * before the pair results are summed, beside the pair kernel.  Work enqueued
- * on the plan's stream is therefore ordered as if everything ran on it.
+ * evaluation the far-field chain may run on a second stream that the plan
+ * owns (ankh_overrides.overlap), forked from that stream after the particles
+ * are sorted and joined back before the pair results are summed, beside the
+ * pair kernel.  Work enqueued on the plan's stream is therefore ordered as if
+ * everything ran on it.
  * A plan is not thread-safe; use one plan per stream.
  *
  * Errors: host-checkable errors return at once with outputs untouched.
@@ -91,6 +92,10 @@ typedef struct {
     int32_t far_field;  /* far-field method, an ankh_far_field value; 0 = auto (ANKH_FAR_FMM) */
     int32_t eq_order;   /* ANKH-FFT: equispaced nodes per axis of each leaf grid, 2..10; 0 = the
                            Chebyshev order */
+    int32_t overlap;    /* far-field chain beside the pair kernel on the plan's second stream: 1 = yes,
+                           2 = no (every stage in sequence on the plan's stream), 0 = auto (yes for
+                           ANKH-FMM, no for ANKH-FFT, whose short far field costs the pair kernel more
+                           when they share the CUs than it saves) */
 } ankh_overrides;
 
 /* Far-field methods.
@@ -132,6 +137,7 @@ typedef struct {
                                   level is not compressed; 0 for e = 0 and e > depth) */
     int32_t far_field;         /* ANKH_FAR_FMM or ANKH_FAR_FFT */
     int32_t eq_order;          /* ANKH-FFT: equispaced nodes per axis (0 for ANKH-FMM) */
+    int32_t overlap;           /* 1 if the far-field chain runs beside the pair kernel, else 0 */
 } ankh_plan_stats;
 
 /*
@@ -255,8 +261,8 @@ ankh_status ankh_get_stats(ankh_plan_t plan, ankh_plan_stats *out);
 
 /* Per-stage hipEvent timing of later evaluations: 0 disables it; 1 records an event at every stage
  * boundary and runs the stages in sequence on the plan's stream (no far-field / pair overlap), so the
- * stage figures add up; 2 keeps the overlap and records events only around stage 4 (far-field
- * contraction, on the second stream) and stage 8 (pair kernel), the other stages reading -1.  Each
+ * stage figures add up; 2 keeps the plan's overlap setting and records events only around stage 4
+ * (far-field contraction) and stage 8 (pair kernel), the other stages reading -1.  Each
  * recorded event idles its stream for a few microseconds.  1 and 2 restart the averaging window;
  * other values are ANKH_ERR_INVALID_ARG. */
 ankh_status ankh_set_timing(ankh_plan_t plan, int32_t enable);

@@ -118,6 +118,7 @@ struct ankh_plan_s {
     // fft_nf = pa * pa * (pa / 2 + 1); B = node DFT x reinterpolation [pa][order], W = plain node
     // DFT [pa][pa], spectrum work X [fft_nf][nleaf] (complex), real spectrum D [fft_nf][nleaf]
     int far_field = ANKH_FAR_FMM;
+    bool overlap = true;          // far-field chain on `side` beside the pair kernel
     int eq_order = 0, fft_pa = 0, fft_ph = 0;
     int64_t fft_nf = 0;
     double2 *d_fftB = nullptr, *d_fftW = nullptr, *d_fftX = nullptr;

@@ -145,7 +145,7 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
     // plan's stream: the pair kernel fills every CU with VALU work, and the far-field kernels, mostly
     // waiting on memory and small grids, fit into the gaps.  Timing mode 1 keeps one stream, so its
     // per-stage figures add up.
-    const bool overlap = pl->timing != 1;
+    const bool overlap = pl->overlap && pl->timing != 1;
     try {
         mark(0);
         ck(launch_sort(pl, pos, q, mu, th));
@@ -253,6 +253,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         if (!std::isfinite(ov->m2l_tol) || ov->m2l_tol >= 1) return ANKH_ERR_INVALID_ARG;
         if (ov->far_field < 0 || ov->far_field > ANKH_FAR_FFT) return ANKH_ERR_INVALID_ARG;
         if (ov->eq_order != 0 && (ov->eq_order < 2 || ov->eq_order > kMaxOrder)) return ANKH_ERR_INVALID_ARG;
+        if (ov->overlap < 0 || ov->overlap > 2) return ANKH_ERR_INVALID_ARG;
     }
     auto t0 = std::chrono::steady_clock::now();
     ankh_plan_s *pl = new (std::nothrow) ankh_plan_s();
@@ -280,6 +281,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
     pl->nup = (pl->nu + 31) / 32 * 32;   // row stride: a multiple of the M2L tile step
     pl->far_field = (ov && ov->far_field == ANKH_FAR_FFT) ? ANKH_FAR_FFT : ANKH_FAR_FMM;
     const bool fft = pl->far_field == ANKH_FAR_FFT;
+    pl->overlap = (ov && ov->overlap) ? ov->overlap == 1 : !fft;
     pl->depth = (ov && ov->depth >= 0) ? ov->depth : depth_for(n_atoms, pl->nu);
     if (fft) {
         // ANKH-FFT: equispaced order (the Chebyshev order unless set); the automatic depth stops at
@@ -600,6 +602,7 @@ ankh_status ankh_get_stats(ankh_plan_t pl, ankh_plan_stats *out) {
     }
     for (int e = 0; e < 8; e++) out->m2l_rank[e] = (e >= 1 && e <= pl->depth) ? pl->m2l_rank[e] : 0;
     out->far_field = pl->far_field;
+    out->overlap = pl->overlap ? 1 : 0;
     out->eq_order = pl->far_field == ANKH_FAR_FFT ? pl->eq_order : 0;
     out->near_pairs = -1;
     if (pl->last_kind) {
