@@ -179,6 +179,7 @@ def main():
     ap.add_argument("--far", default="fft", choices=["fmm", "fft"],
                     help="far-field method of the timed path: ANKH-FFT (the variant the paper times) or "
                          "ANKH-FMM (multilevel M2L)")
+    ap.add_argument("--depth", type=int, default=None, help="octree depth (default: the planner's choice)")
     ap.add_argument("--overlap", default="auto", choices=["auto", "on", "off"],
                     help="far-field chain beside the pair kernel on a second stream (auto: the plan's choice)")
     ap.add_argument("--no-far-compare", action="store_true",
@@ -220,7 +221,7 @@ def main():
     log(f"workload {args.workload}: n={n} edge={data['edge']:.3f}")
 
     ovl = {"auto": None, "on": True, "off": False}[args.overlap]
-    pm = ak.Plan(n, rB, args.eps, 2, args.mode, far=args.far, overlap=ovl)
+    pm = ak.Plan(n, rB, args.eps, 2, args.mode, far=args.far, overlap=ovl, depth=args.depth)
     log(f"mixed plan: {pm.stats}")
     t_mixed, st_mixed, bd_mixed, out_mixed = timed_run(pm, args_dev, args.steps, args.warmup, torch)
     log(f"mixed: {t_mixed * 1e3:.3f} ms/step timed stages {st_mixed['stage_ms']} breakdown {bd_mixed}")
@@ -228,7 +229,7 @@ def main():
     far_other = None
     if not args.no_far_compare:
         alt = "fft" if args.far == "fmm" else "fmm"
-        pa = ak.Plan(n, rB, args.eps, 2, args.mode, far=alt, overlap=ovl)
+        pa = ak.Plan(n, rB, args.eps, 2, args.mode, far=alt, overlap=ovl, depth=args.depth)
         t_a, st_a, bd_a, out_a = timed_run(pa, args_dev, args.steps, args.warmup, torch)
         Em, Fm, Gm = [x.double().cpu().numpy() for x in out_mixed]
         Ea, Fa, Ga = [x.double().cpu().numpy() for x in out_a]
@@ -252,7 +253,7 @@ def main():
 
     res = {}
     if not args.mixed_only:
-        pf = ak.Plan(n, rB, args.eps, 2, "fp64", far=args.far, overlap=ovl)
+        pf = ak.Plan(n, rB, args.eps, 2, "fp64", far=args.far, overlap=ovl, depth=args.depth)
         t_fp64, st_fp64, bd_fp64, out_fp64 = timed_run(pf, args_dev, args.steps, args.warmup, torch)
         if derivs is not None:
             d64, dfp = derivs_run(pf, args_dev, torch)

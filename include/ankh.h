@@ -92,6 +92,9 @@ typedef struct {
     int32_t far_field;  /* far-field method, an ankh_far_field value; 0 = auto (ANKH_FAR_FMM) */
     int32_t eq_order;   /* ANKH-FFT: equispaced nodes per axis of each leaf grid, 2..10; 0 = the
                            Chebyshev order */
+    int32_t fft_split;  /* ANKH-FFT: 1 = the cell transforms in three passes through HBM even when one
+                           block holds the cells of a node frequency (the path of depths 5 and 6, for
+                           testing it at small depths); 0 = only when needed */
     int32_t overlap;    /* far-field chain beside the pair kernel on the plan's second stream: 1 = yes,
                            2 = no (every stage in sequence on the plan's stream), 0 = auto (yes for
                            ANKH-FMM, no for ANKH-FFT, whose short far field costs the pair kernel more
@@ -105,10 +108,12 @@ typedef struct {
  *   ANKH_FAR_FFT  ANKH-FFT (the ANKH-FFT section): the leaf modified charges reinterpolated onto an
  *                 equispaced grid per leaf, and every non-adjacent leaf pair, far images included,
  *                 through one 6D convolution evaluated by FFT (matrix factorisation, diagonalisation
- *                 and real-spectrum passages).  Needs depth <= 4 (auto depth is capped there) and
- *                 2 eq_order - 1 node frequencies per axis within the per-block LDS budget (eq_order
- *                 <= 8 at order <= 8).  The near field, P2M, L2P, self and background terms are
- *                 those of ANKH-FMM; stage 3 of the timing is the forward node transform, stage 4 the
+ *                 and real-spectrum passages).  Needs depth <= 6 (auto depth is capped there; up
+ *                 to depth 4 the cell transforms of a node frequency run in one block, beyond in
+ *                 three passes through HBM) and 2 eq_order - 1 node frequencies per axis within
+ *                 the per-block LDS budget (eq_order <= 8 at order <= 8).  The near field, P2M,
+ *                 L2P, self and background terms are those of ANKH-FMM; stage 3 of the timing
+ *                 is the forward node transform, stage 4 the
  *                 cell transforms and the product with the spectrum, stage 5 is empty and stage 6
  *                 the inverse node transform with the leaf energies.  The spectrum of the 6D
  *                 convolution is built at plan time (an image sum per entry on the device). */
@@ -138,6 +143,7 @@ typedef struct {
     int32_t far_field;         /* ANKH_FAR_FMM or ANKH_FAR_FFT */
     int32_t eq_order;          /* ANKH-FFT: equispaced nodes per axis (0 for ANKH-FMM) */
     int32_t overlap;           /* 1 if the far-field chain runs beside the pair kernel, else 0 */
+    int32_t fft_split;         /* ANKH-FFT: 1 if the cell transforms run in three passes */
 } ankh_plan_stats;
 
 /*

@@ -26,7 +26,10 @@
 //                    matrix B = W E per axis (Pa x L), three separable stages
 //                    in LDS, the half spectrum written to X[f][c];
 //   k_fft_cells      per node frequency: the 3D FFT over the n^3 cells in LDS,
-//                    the product with D / N, the inverse 3D FFT, in place;
+//                    the product with D / N, the inverse 3D FFT, in place
+//                    (n <= 16; for 32 and 64 cells per axis three passes
+//                    through HBM: k_fft_yz planes, k_fft_x lines with the
+//                    product, k_fft_yz inverse);
 //   k_fft_nodes_inv  per leaf: the adjoint of the first (conj(B)^T per axis,
 //                    the half spectrum counted twice), Lambda_c into the leaf
 //                    row of the local expansions.
@@ -467,6 +470,202 @@ __global__ __launch_bounds__(256) void k_fft_table(const double2 *W, int pa, int
     }
 }
 
+// ---- cell transforms in three passes (32^3 or 64^3 cells, or on request) -----
+// A tile of NS x NS complex values in LDS, element (u, v) at u NS + v, is
+// transformed along v (ALONG_V) or along u by radix-2 butterflies, one per
+// thread and stage.  tile_dit: bit-reversed input, natural output; tile_dif:
+// natural input, bit-reversed output.  tw[k] = e^{-2 pi i k / NS}, k < NS/2
+// (global, cached); INV conjugates it.
+template <int NS>
+__device__ inline int brev(int v) {
+    constexpr int bits = NS == 2 ? 1 : NS == 4 ? 2 : NS == 8 ? 3 : NS == 16 ? 4 : NS == 32 ? 5 : 6;
+    return (int)(__brev((unsigned)v) >> (32 - bits));
+}
+
+template <int NS, bool ALONG_V, bool DIT, bool INV>
+__device__ void tile_fft(double2 *tile, const double2 *tw) {
+    constexpr int NB = NS * (NS / 2);
+    for (int half = DIT ? 1 : NS / 2; DIT ? half < NS : half >= 1; half = DIT ? 2 * half : half / 2) {
+        for (int b = threadIdx.x; b < NB; b += blockDim.x) {
+            // consecutive threads take consecutive elements of the line direction that is contiguous
+            const int line = ALONG_V ? b / (NS / 2) : b % NS;
+            const int k = ALONG_V ? b % (NS / 2) : b / NS;
+            const int pos = k % half, i0 = (k / half) * 2 * half + pos, i1 = i0 + half;
+            double2 w = tw[pos * (NS / (2 * half))];
+            if (INV) w.y = -w.y;
+            const int e0 = ALONG_V ? line * NS + i0 : i0 * NS + line;
+            const int e1 = ALONG_V ? line * NS + i1 : i1 * NS + line;
+            const double2 u = tile[e0], v = tile[e1];
+            if (DIT) {
+                const double2 t = cmul(w, v);
+                tile[e0] = make_double2(u.x + t.x, u.y + t.y);
+                tile[e1] = make_double2(u.x - t.x, u.y - t.y);
+            } else {
+                tile[e0] = make_double2(u.x + v.x, u.y + v.y);
+                tile[e1] = cmul(w, make_double2(u.x - v.x, u.y - v.y));
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// pass 1 / 3: block (f, x), the (y, z) plane of X[f] (contiguous): forward (DIT, natural output) or
+// inverse (DIF, written back in natural order)
+template <int NS, bool INV>
+__global__ __launch_bounds__(256) void k_fft_yz(double2 *X, const double2 *tw, int64_t ncell) {
+    __shared__ double2 tile[NS * NS];
+    double2 *p = X + (int64_t)blockIdx.x * ncell + (int64_t)blockIdx.y * NS * NS;
+    const int t = threadIdx.x;
+    for (int i = t; i < NS * NS; i += 256) {
+        const int y = i / NS, z = i % NS;
+        tile[INV ? i : brev<NS>(y) * NS + brev<NS>(z)] = p[i];
+    }
+    __syncthreads();
+    if (!INV) {
+        tile_fft<NS, true, true, false>(tile, tw);
+        tile_fft<NS, false, true, false>(tile, tw);
+    } else {
+        tile_fft<NS, true, false, true>(tile, tw);
+        tile_fft<NS, false, false, true>(tile, tw);
+    }
+    for (int i = t; i < NS * NS; i += 256) {
+        const int y = i / NS, z = i % NS;
+        p[i] = tile[INV ? brev<NS>(y) * NS + brev<NS>(z) : i];
+    }
+}
+
+// pass 2: block (f, y), the (x, z) tile of X[f]: forward along x, then MODE 0: times D * scale and the
+// inverse along x, back to X; MODE 1 (plan): the real part to D
+template <int NS, int MODE>
+__global__ __launch_bounds__(256) void k_fft_x(double2 *X, double *D, const double2 *tw, int64_t ncell,
+                                               double scale) {
+    __shared__ double2 tile[NS * NS];
+    const int64_t f = blockIdx.x;
+    const int y = blockIdx.y, t = threadIdx.x;
+    for (int i = t; i < NS * NS; i += 256) {
+        const int x = i / NS, z = i % NS;
+        tile[brev<NS>(x) * NS + z] = X[f * ncell + ((int64_t)x * NS + y) * NS + z];
+    }
+    __syncthreads();
+    tile_fft<NS, false, true, false>(tile, tw);
+    if (MODE == 1) {
+        for (int i = t; i < NS * NS; i += 256) {
+            const int x = i / NS, z = i % NS;
+            D[f * ncell + ((int64_t)x * NS + y) * NS + z] = tile[i].x;
+        }
+        return;
+    }
+    for (int i = t; i < NS * NS; i += 256) {
+        const int x = i / NS, z = i % NS;
+        const double d = D[f * ncell + ((int64_t)x * NS + y) * NS + z] * scale;
+        tile[i] = make_double2(tile[i].x * d, tile[i].y * d);
+    }
+    __syncthreads();
+    tile_fft<NS, false, false, true>(tile, tw);
+    for (int i = t; i < NS * NS; i += 256) {
+        const int x = i / NS, z = i % NS;
+        X[f * ncell + ((int64_t)x * NS + y) * NS + z] = tile[brev<NS>(x) * NS + z];
+    }
+}
+
+// ---- plan time, with the mirror symmetry of the kernel --------------------------
+// The generating cube is even along each axis separately: K(-g_x, g_y, g_z; -a_x, a_y, a_z) = K(g; a)
+// (the displacement cube and the adjacency test are symmetric), so the node spectrum of the residue
+// with axis x mirrored is that of g with f_x negated.  One block per residue with every component in
+// [0, n/2]: the cube, its full node spectrum in LDS (three separable stages), then the half spectrum
+// of each distinct mirror residue.
+__global__ __launch_bounds__(256) void k_fft_table_sym(const double2 *W, int pa, int ph, int le, int nside, int p,
+                                                       double w, double h, double xi, double2 *X, int64_t ncell) {
+    extern __shared__ double2 sm[];
+    double2 *sW = sm, *S1 = sW + pa * pa, *S2 = S1 + pa * pa * pa;
+    double *cube = reinterpret_cast<double *>(S2 + pa * pa * pa);
+    const int nh = nside / 2 + 1;
+    const int b = blockIdx.x;
+    const int gx = b / (nh * nh), gy = (b / nh) % nh, gz = b % nh;
+    const int t = threadIdx.x;
+    for (int i = t; i < pa * pa; i += 256) sW[i] = W[i];
+    const double lim = nside * (p + 0.5);
+    const int n3 = pa * pa * pa;
+    for (int e = t; e < n3; e += 256) {
+        const int a1 = e / (pa * pa), a2 = (e / pa) % pa, a3 = e % pa;
+        const int d1 = a1 < le ? a1 : a1 - pa, d2 = a2 < le ? a2 : a2 - pa, d3 = a3 < le ? a3 : a3 - pa;
+        double s = 0;
+        for (int I = -p - 2; I <= p + 2; I++) {
+            const int Dx = gx - nside * I;
+            if (fabs((double)Dx) > lim) continue;
+            const double zx = Dx * w + d1 * h;
+            for (int J = -p - 2; J <= p + 2; J++) {
+                const int Dy = gy - nside * J;
+                if (fabs((double)Dy) > lim) continue;
+                const double zy = Dy * w + d2 * h;
+                for (int K = -p - 2; K <= p + 2; K++) {
+                    const int Dz = gz - nside * K;
+                    if (fabs((double)Dz) > lim) continue;
+                    if (abs(Dx) < 2 && abs(Dy) < 2 && abs(Dz) < 2) continue;
+                    const double zz = Dz * w + d3 * h;
+                    const double r = sqrt(zx * zx + zy * zy + zz * zz);
+                    s += erfc(xi * r) / r;
+                }
+            }
+        }
+        cube[e] = s;
+    }
+    __syncthreads();
+    for (int o = t; o < n3; o += 256) {             // x: S1[f1][a2][a3]
+        const int f1 = o / (pa * pa), r = o % (pa * pa);
+        double re = 0, im = 0;
+        for (int a1 = 0; a1 < pa; a1++) {
+            const double2 c = sW[f1 * pa + a1];
+            const double v = cube[a1 * pa * pa + r];
+            re += c.x * v;
+            im += c.y * v;
+        }
+        S1[o] = make_double2(re, im);
+    }
+    __syncthreads();
+    for (int o = t; o < n3; o += 256) {             // y: S2[f1][f2][a3]
+        const int f1 = o / (pa * pa), f2 = (o / pa) % pa, a3 = o % pa;
+        double re = 0, im = 0;
+        for (int a2 = 0; a2 < pa; a2++) {
+            const double2 c = sW[f2 * pa + a2], v = S1[(f1 * pa + a2) * pa + a3];
+            re += c.x * v.x - c.y * v.y;
+            im += c.x * v.y + c.y * v.x;
+        }
+        S2[o] = make_double2(re, im);
+    }
+    __syncthreads();
+    for (int o = t; o < n3; o += 256) {             // z (full): S1[f1][f2][f3]
+        const int f12 = o / pa, f3 = o % pa;
+        double re = 0, im = 0;
+        for (int a3 = 0; a3 < pa; a3++) {
+            const double2 c = sW[f3 * pa + a3], v = S2[f12 * pa + a3];
+            re += c.x * v.x - c.y * v.y;
+            im += c.x * v.y + c.y * v.x;
+        }
+        S1[o] = make_double2(re, im);
+    }
+    __syncthreads();
+    const int g[3] = {gx, gy, gz};
+    for (int m = 0; m < 8; m++) {
+        bool dup = false;
+        int gm[3];
+        for (int a = 0; a < 3; a++) {
+            const bool flip = (m >> a) & 1;
+            // a mirror of a self-mirrored component (0 or n/2) repeats another mirror
+            if (flip && (g[a] == 0 || 2 * g[a] == nside)) dup = true;
+            gm[a] = flip ? nside - g[a] : g[a];
+        }
+        if (dup) continue;
+        const int64_t gl = ((int64_t)gm[0] * nside + gm[1]) * nside + gm[2];
+        for (int o = t; o < pa * pa * ph; o += 256) {
+            const int f1 = o / (pa * ph), f2 = (o / ph) % pa, f3 = o % ph;
+            const int F1 = (m & 1) ? (pa - f1) % pa : f1, F2 = (m & 2) ? (pa - f2) % pa : f2;
+            const int F3 = (m & 4) ? (pa - f3) % pa : f3;
+            X[(int64_t)o * ncell + gl] = S1[(F1 * pa + F2) * pa + F3];
+        }
+    }
+}
+
 Tw16 roots16() {
     Tw16 tw;
     for (int k = 0; k < 8; k++) {
@@ -484,9 +683,31 @@ size_t nodes_inv_lds(int L, int pa, int ph) {
     return sizeof(double2) * ((size_t)pa * L + (size_t)pa * pa * L + nx);
 }
 size_t table_lds(int pa) { return sizeof(double2) * pa * pa + sizeof(double) * pa * pa * pa; }
+size_t table_sym_lds(int pa) {
+    return sizeof(double2) * ((size_t)pa * pa + 2 * (size_t)pa * pa * pa) + sizeof(double) * pa * pa * pa;
+}
+
+template <int NS, int MODE>
+void split_passes(ankh_plan_s *pl, double2 *X, double *D, double scale) {
+    const dim3 g((unsigned)pl->fft_nf, NS), b(256);
+    hipLaunchKernelGGL((k_fft_yz<NS, false>), g, b, 0, pl->stream, X, pl->d_fftTw, pl->nleaf);
+    hipLaunchKernelGGL((k_fft_x<NS, MODE>), g, b, 0, pl->stream, X, D, pl->d_fftTw, pl->nleaf, scale);
+    if (MODE == 0) hipLaunchKernelGGL((k_fft_yz<NS, true>), g, b, 0, pl->stream, X, pl->d_fftTw, pl->nleaf);
+}
 
 template <int MODE>
 hipError_t cells(ankh_plan_s *pl, double2 *X, double *D, double scale) {
+    if (pl->fft_split) {
+        switch (pl->nside) {
+            case 2: split_passes<2, MODE>(pl, X, D, scale); break;
+            case 4: split_passes<4, MODE>(pl, X, D, scale); break;
+            case 8: split_passes<8, MODE>(pl, X, D, scale); break;
+            case 16: split_passes<16, MODE>(pl, X, D, scale); break;
+            case 32: split_passes<32, MODE>(pl, X, D, scale); break;
+            default: split_passes<64, MODE>(pl, X, D, scale); break;
+        }
+        return hipGetLastError();
+    }
     const size_t shm = sizeof(double2) * pl->nleaf;
     const dim3 g((unsigned)pl->fft_nf), b(256);
     const Tw16 tw = roots16();
@@ -506,8 +727,16 @@ bool fft_supported(int depth, int L, int le) {
     if (depth < 0 || depth > kMaxFftDepth || le < 2 || le > kMaxOrder || L < 2 || L > kMaxOrder) return false;
     const int pa = 2 * le - 1, ph = pa / 2 + 1;
     const size_t lim = 65536;
-    return nodes_fwd_lds(L, pa) <= lim && nodes_inv_lds(L, pa, ph) <= lim && table_lds(pa) <= lim &&
-           sizeof(double2) * ((size_t)1 << (3 * depth)) <= lim;
+    // cells of one node frequency: one block up to 16^3, else three passes over 32^2 / 64^2 tiles
+    return nodes_fwd_lds(L, pa) <= lim && nodes_inv_lds(L, pa, ph) <= lim && table_lds(pa) <= lim;
+}
+
+void fft_host_roots(int nside, std::vector<double2> &tw) {
+    tw.assign(std::max(1, nside / 2), make_double2(1, 0));
+    for (int k = 0; k < nside / 2; k++) {
+        const long double a = -2.0L * (long double)kPiF * k / nside;
+        tw[k] = make_double2((double)cosl(a), (double)sinl(a));
+    }
 }
 
 void fft_host_tables(int L, int le, const double *cheb, std::vector<double2> &B, std::vector<double2> &W) {
@@ -551,8 +780,15 @@ void fft_host_tables(int L, int le, const double *cheb, std::vector<double2> &B,
 hipError_t launch_fft_build_D(ankh_plan_s *pl) {
     const int pa = pl->fft_pa, ph = pl->fft_ph, le = pl->eq_order;
     const double w = pl->edge / pl->nside;
-    hipLaunchKernelGGL(k_fft_table, dim3((unsigned)pl->nleaf), dim3(256), table_lds(pa), pl->stream, pl->d_fftW, pa,
-                       ph, le, pl->nside, pl->images, w, w / (le - 1), pl->xi, pl->d_fftX, pl->nleaf);
+    if (pl->nside >= 2 && table_sym_lds(pa) <= 65536) {
+        const int nh = pl->nside / 2 + 1;
+        hipLaunchKernelGGL(k_fft_table_sym, dim3((unsigned)(nh * nh * nh)), dim3(256), table_sym_lds(pa), pl->stream,
+                           pl->d_fftW, pa, ph, le, pl->nside, pl->images, w, w / (le - 1), pl->xi, pl->d_fftX,
+                           pl->nleaf);
+    } else {
+        hipLaunchKernelGGL(k_fft_table, dim3((unsigned)pl->nleaf), dim3(256), table_lds(pa), pl->stream, pl->d_fftW,
+                           pa, ph, le, pl->nside, pl->images, w, w / (le - 1), pl->xi, pl->d_fftX, pl->nleaf);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return cells<1>(pl, pl->d_fftX, pl->d_fftD, 1.0);

@@ -47,7 +47,7 @@ void free_all(ankh_plan_s *pl) {
                     pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr,
                     pl->d_Kb, pl->d_Mb, pl->d_slot_e, pl->d_slot_f, pl->d_slot_g, pl->d_cper_part,
                     pl->d_U, pl->d_Mc, pl->d_Lc, pl->d_ind, pl->d_mom, pl->d_fftB, pl->d_fftW, pl->d_fftX,
-                    pl->d_fftD};
+                    pl->d_fftD, pl->d_fftTw};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &set : pl->evsets)
@@ -254,6 +254,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         if (ov->far_field < 0 || ov->far_field > ANKH_FAR_FFT) return ANKH_ERR_INVALID_ARG;
         if (ov->eq_order != 0 && (ov->eq_order < 2 || ov->eq_order > kMaxOrder)) return ANKH_ERR_INVALID_ARG;
         if (ov->overlap < 0 || ov->overlap > 2) return ANKH_ERR_INVALID_ARG;
+        if (ov->fft_split < 0 || ov->fft_split > 1) return ANKH_ERR_INVALID_ARG;
     }
     auto t0 = std::chrono::steady_clock::now();
     ankh_plan_s *pl = new (std::nothrow) ankh_plan_s();
@@ -297,6 +298,8 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         pl->fft_nf = (int64_t)pl->fft_pa * pl->fft_pa * pl->fft_ph;
     }
     pl->nside = 1 << pl->depth;
+    // three-pass cell transforms beyond 16 cells per axis, or on request (not at depth 0)
+    pl->fft_split = fft && pl->nside >= 2 && (pl->nside > 16 || (ov && ov->fft_split == 1));
     pl->nleaf = (int64_t)pl->nside * pl->nside * pl->nside;
     size_t cells = 0;
     for (int e = 0; e <= pl->depth; e++) {
@@ -491,6 +494,10 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
             // cube (W), the work spectrum X and the real spectrum D
             std::vector<double2> B, W;
             fft_host_tables(pl->order, pl->eq_order, pl->nodes, B, W);
+            std::vector<double2> tw;
+            fft_host_roots(pl->nside, tw);
+            dalloc(pl, &pl->d_fftTw, tw.size());
+            ck(hipMemcpy(pl->d_fftTw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
             dalloc(pl, &pl->d_fftB, B.size());
             dalloc(pl, &pl->d_fftW, W.size());
             dalloc(pl, &pl->d_fftX, (size_t)pl->fft_nf * pl->nleaf);
@@ -603,6 +610,7 @@ ankh_status ankh_get_stats(ankh_plan_t pl, ankh_plan_stats *out) {
     for (int e = 0; e < 8; e++) out->m2l_rank[e] = (e >= 1 && e <= pl->depth) ? pl->m2l_rank[e] : 0;
     out->far_field = pl->far_field;
     out->overlap = pl->overlap ? 1 : 0;
+    out->fft_split = pl->fft_split ? 1 : 0;
     out->eq_order = pl->far_field == ANKH_FAR_FFT ? pl->eq_order : 0;
     out->near_pairs = -1;
     if (pl->last_kind) {

@@ -14,7 +14,10 @@
   mixed modes against FP64, and FP64 against the ANKH-FMM path (both
   approximate the same energy within the accuracy target) and against the
   oracle on the stored sampled atoms.
-* Planning errors: depth beyond 4, equispaced order out of range.
+* Depths 5 and 6 (the cell transforms in three passes through HBM; the same
+  passes are forced at small depths for the stage parity): against ANKH-FMM
+  at the same depth on the 288,000- and 9,000,000-atom boxes.
+* Planning errors: depth beyond 6, equispaced order out of range.
 """
 import os
 
@@ -67,13 +70,17 @@ def _run(ak, d, eps=1e-6, prec="fp64", **ov):
     return pl, e.item(), F.cpu().numpy(), G.cpu().numpy()
 
 
-@pytest.mark.parametrize("depth,order,eq,kind", [(0, 4, 4, "qmt"), (1, 4, 3, "qmt"), (2, 5, 5, "qmt"),
-                                                 (2, 4, 6, "q"), (3, 4, 4, "qm")])
-def test_fft_stage_parity_with_reference(ak, depth, order, eq, kind):
+@pytest.mark.parametrize("depth,order,eq,kind,split", [(0, 4, 4, "qmt", False), (1, 4, 3, "qmt", False),
+                                                       (2, 5, 5, "qmt", False), (2, 4, 6, "q", False),
+                                                       (3, 4, 4, "qm", False), (1, 4, 4, "qmt", True),
+                                                       (2, 5, 5, "qmt", True), (3, 4, 4, "qm", True)])
+def test_fft_stage_parity_with_reference(ak, depth, order, eq, kind, split):
+    """split: the cell transforms in the three passes that depths 5 and 6 use, forced at small depth."""
     d = _system(kind)
-    pl, e, F, G = _run(ak, d, depth=depth, order=order, images=3, eq_order=eq)
+    pl, e, F, G = _run(ak, d, depth=depth, order=order, images=3, eq_order=eq, fft_split=split)
     st = pl.stats
     assert st["far_field"] == ak.ANKH_FAR_FFT and st["eq_order"] == eq and st["depth"] == depth
+    assert st["fft_split"] == int(split)
     terms = pl.last_terms()
     r = ankh_ref.evaluate(d["pos"], d["q"], d["mu"], d["theta"], d["edge"], st["depth"], st["order"], st["xi"],
                           st["images"], grad=True, far="fft", eq_order=eq)
@@ -183,14 +190,57 @@ def test_fft_derivs_run_on_the_fft_far_field(ak):
         assert rel_rms(out["fft"][k], out["fmm"][k]) <= 1e-5, k
 
 
+def test_fft_depth_5_vs_fmm(ak):
+    """Depth 5 (32^3 leaves: the cell transforms in three passes through HBM) on the benchmark box:
+    ANKH-FFT against ANKH-FMM at the same depth, FP64; the mixed mode against FP64."""
+    d = synth.workload("water_288000")
+    n = len(d["q"])
+    pl, e, F, G = _run(ak, d, eps=1e-6, depth=5)
+    assert pl.stats["fft_split"] == 1
+    pl.close()
+    pm, em, Fm, Gm = _run(ak, d, eps=1e-6, prec="mixed_bf16x3", depth=5)
+    pm.close()
+    pf = ak.Plan(n, 0.5 * d["edge"], 1e-6, 2, "fp64", far="fmm", depth=5)
+    ef, Ff, Gf = pf.energy_forces(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
+    pf.sync()
+    ef, Ff, Gf = ef.item(), Ff.cpu().numpy(), Gf.cpu().numpy()
+    pf.close()
+    assert abs(e - ef) <= 1e-6 * abs(ef)
+    assert rel_rms(F, Ff) <= 1e-5
+    assert rel_rms(G, Gf) <= 2e-5
+    assert abs(em - e) <= 1e-5 * abs(e)
+    assert rel_rms(Fm, F) <= 1e-4 and rel_rms(Gm, G) <= 1e-4
+
+
+def test_fft_depth_6_vs_fmm(ak):
+    """The 3,000,000-molecule box at its automatic depth 6 (64^3 leaves), ANKH-FFT against ANKH-FMM
+    (FP64, accuracy 1e-5)."""
+    d = synth.workload("water_9000000")
+    n = len(d["q"])
+    out = {}
+    for far in ("fft", "fmm"):
+        pl = ak.Plan(n, 0.5 * d["edge"], 1e-5, 2, "fp64", far=far)
+        assert pl.stats["depth"] == 6
+        e, F, G = pl.energy_forces(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
+        pl.sync()
+        out[far] = (e.item(), F.cpu().numpy(), G.cpu().numpy())
+        pl.close()
+        del e, F, G
+        torch.cuda.empty_cache()
+    (e1, F1, G1), (e2, F2, G2) = out["fft"], out["fmm"]
+    assert abs(e1 - e2) <= 1e-5 * abs(e2)
+    assert rel_rms(F1, F2) <= 1e-4 and rel_rms(G1, G2) <= 1e-4
+
+
 def test_fft_planning_errors(ak):
     d = synth.water(100, seed=4)
     n = len(d["q"])
-    for kw in (dict(depth=5), dict(eq_order=11), dict(eq_order=1)):
+    for kw in (dict(depth=7), dict(eq_order=11), dict(eq_order=1)):
         with pytest.raises(ak.AnkhError) as ei:
             ak.Plan(n, 0.5 * d["edge"], 1e-6, 2, "fp64", far="fft", **kw)
         assert ei.value.status == 1, kw
-    # the automatic depth stops at 4 for ANKH-FFT
+    # the automatic depth of ANKH-FFT is that of ANKH-FMM up to 6; beyond 16 leaves per axis the cell
+    # transforms run in three passes
     pl = ak.Plan(2_000_000, 100.0, 1e-6, 2, "mixed", far="fft")
-    assert pl.stats["depth"] == 4 and pl.stats["far_field"] == ak.ANKH_FAR_FFT
+    assert pl.stats["depth"] == 5 and pl.stats["far_field"] == ak.ANKH_FAR_FFT and pl.stats["fft_split"] == 1
     pl.close()
