@@ -42,21 +42,43 @@ __global__ void k_to_f32(const double *s, float *d, int64_t n) {
 // leaf of every atom, the leaf counts, and each atom's arrival rank in its leaf (the scatter then
 // needs no atomics; the arrival order itself is undone by the segment sort).  Positions and charges
 // are checked here, the higher moments in the gather, which reads them anyway.
-__global__ void k_bin(int64_t n, const double *pos, const double *q, double rB, double edge, double w, int nside,
-                      int32_t *leaf, int32_t *count, int32_t *rank, int32_t *err) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    bool fin = isfinite(q[i]);
-    int ix[3];
-    for (int d = 0; d < 3; d++) {
-        double v = pos[3 * i + d], xw;
-        fin = fin && isfinite(v);
-        ix[d] = isfinite(v) ? leaf_coord(v, rB, edge, w, nside, &xw) : 0;
+// The lanes of a wave that fall into the same leaf take their ranks from one atomic add (inputs in
+// spatial order put a wave's atoms into a few leaves; the segment sort fixes the in-leaf order
+// afterwards, so which lane gets which rank does not matter).  After 8 distinct leaves the rest add
+// one by one, which bounds the loop for inputs in random order.
+__global__ __launch_bounds__(256) void k_bin(int64_t n, const double *pos, const double *q, double rB, double edge,
+                                             double w, int nside, int32_t *leaf, int32_t *count, int32_t *rank,
+                                             int32_t *err) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    int id = -1;
+    if (valid) {
+        bool fin = isfinite(q[i]);
+        int ix[3];
+        for (int d = 0; d < 3; d++) {
+            double v = pos[3 * i + d], xw;
+            fin = fin && isfinite(v);
+            ix[d] = isfinite(v) ? leaf_coord(v, rB, edge, w, nside, &xw) : 0;
+        }
+        if (!fin) err[0] = 1;
+        id = (ix[0] * nside + ix[1]) * nside + ix[2];
+        leaf[i] = id;
     }
-    if (!fin) err[0] = 1;
-    int id = (ix[0] * nside + ix[1]) * nside + ix[2];
-    leaf[i] = id;
-    rank[i] = atomicAdd(&count[id], 1);
+    const int lane = (int)__lane_id();
+    unsigned long long pending = __ballot(valid);
+    int r = 0;
+    for (int round = 0; round < 8 && pending; round++) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int lid = __shfl(id, leader);
+        const unsigned long long same = __ballot(id == lid) & pending;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&count[lid], (int)__popcll(same));
+        base = __shfl(base, leader);
+        if ((same >> lane) & 1ull) r = base + (int)__popcll(same & ((1ull << lane) - 1ull));
+        pending &= ~same;
+    }
+    if ((pending >> lane) & 1ull) r = atomicAdd(&count[id], 1);
+    if (valid) rank[i] = r;
 }
 
 // exclusive scan of the leaf counts (one block; m up to 8^7)
