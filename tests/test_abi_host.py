@@ -71,9 +71,41 @@ def test_plan_rejects_bad_overrides(lib):
     import paper_2212_08284_amd as ak
     for ov in (ak._Overrides(9, 0, 0, 0.0), ak._Overrides(-1, 1, 0, 0.0), ak._Overrides(-1, 11, 0, 0.0),
                ak._Overrides(-1, 0, 99, 0.0), ak._Overrides(-1, 0, 0, float("inf")),
-               ak._Overrides(-1, 0, 0, 0.0, 0, 2.0), ak._Overrides(-1, 0, 0, 0.0, 0, float("nan"))):
+               ak._Overrides(-1, 0, 0, 0.0, 0, 2.0), ak._Overrides(-1, 0, 0, 0.0, 0, float("nan")),
+               ak._Overrides(-1, 0, 0, 0.0, 0, 0.0, 3), ak._Overrides(-1, 0, 0, 0.0, 0, 0.0, 2, 1),
+               ak._Overrides(-1, 0, 0, 0.0, 0, 0.0, 2, 11), ak._Overrides(-1, 0, 0, 0.0, 0, 0.0, 2, 0, 2),
+               ak._Overrides(-1, 0, 0, 0.0, 0, 0.0, 0, 0, 0, 3),
+               # ANKH-FFT beyond depth 6
+               ak._Overrides(7, 0, 0, 0.0, 0, 0.0, 2)):
         st, h = _plan(lib, ov=ov)
         assert st == 1 and not h.value
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of ankh_overrides and ankh_plan_stats have the C layout: the size and every
+    field offset, from a C program compiled against the header."""
+    import shutil
+    import subprocess
+    import paper_2212_08284_amd as ak
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "ankh.h"', 'int main(void) {']
+    for cname, py in (("ankh_overrides", ak._Overrides), ("ankh_plan_stats", ak._Stats)):
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(ln.split() for ln in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                   text=True).stdout.splitlines())
+    for cname, py in (("ankh_overrides", ak._Overrides), ("ankh_plan_stats", ak._Stats)):
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
 
 
 def test_mixed_precision_accuracy_floor(lib):

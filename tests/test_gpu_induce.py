@@ -52,9 +52,10 @@ def _solve(ak, d, alpha, eps=1e-8, prec="fp64", tol=1e-10, forces=True, **ov):
     return pl, mi.cpu().numpy(), e.item(), None if F is None else F.cpu().numpy(), it, res
 
 
-def test_induce_vs_oracle(ak):
+@pytest.mark.parametrize("far", ["fmm", "fft"])
+def test_induce_vs_oracle(ak, far):
     d, alpha = _water(300, 7)
-    pl, mi, U, F, it, res = _solve(ak, d, alpha)
+    pl, mi, U, F, it, res = _solve(ak, d, alpha, far=far)
     assert res <= 1e-10 and 0 < it < 60
     ref, it_ref, res_ref = P.induce_cg(d["pos"], d["q"], d["mu"], d["theta"], alpha, d["edge"], eps=1e-11,
                                        tol=1e-11)
