@@ -290,7 +290,8 @@ def test_autograd_function(ak):
     pl.close()
 
 
-def test_nonneutral_and_tiny_systems_vs_oracle(ak):
+@pytest.mark.parametrize("far", ["fmm", "fft"])
+def test_nonneutral_and_tiny_systems_vs_oracle(ak, far):
     # one charge per cell: background term; two charges; a charge + dipole pair
     cases = [
         (np.zeros((1, 3)), np.ones(1), None, 10.0),
@@ -299,7 +300,7 @@ def test_nonneutral_and_tiny_systems_vs_oracle(ak):
          np.array([[0.1, 0.2, -0.3], [0.0, 0.4, 0.1]]), 8.0),
     ]
     for pos, q, mu, edge in cases:
-        pl = ak.Plan(len(q), 0.5 * edge, 1e-8, 1 if mu is not None else 0, "fp64")
+        pl = ak.Plan(len(q), 0.5 * edge, 1e-8, 1 if mu is not None else 0, "fp64", far=far)
         e, F, _ = pl.energy_forces(T(pos), T(q), T(mu), None, fields=False)
         pl.sync()
         ref = oracle.ewald(pos, q, mu, None, edge=edge, eps=1e-13)
