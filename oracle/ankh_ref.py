@@ -122,8 +122,9 @@ def wrap(pos, edge):
     return out
 
 
-def leaf_index(pos_wrapped, edge, depth):
-    n = 1 << depth
+def leaf_index(pos_wrapped, edge, depth, nside=None):
+    """Leaf (i, j, k) of each wrapped position; nside leaves per axis (default 2^depth)."""
+    n = (1 << depth) if nside is None else int(nside)
     w = edge / n
     ijk = np.floor((pos_wrapped + 0.5 * edge) / w).astype(np.int64)
     return np.clip(ijk, 0, n - 1)
@@ -302,13 +303,16 @@ def m2l_projector(w: float, L: int, xi: float, rank: int) -> np.ndarray:
 
 def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, p: int,
              grad: bool = True, nthreads: int = 0, keep: bool = False, root_order: int | None = None,
-             m2l_ranks=None, far: str = "fmm", eq_order: int | None = None) -> dict:
+             m2l_ranks=None, far: str = "fmm", eq_order: int | None = None, leaves: int | None = None) -> dict:
     """root_order: Chebyshev order of the root grid that carries the far
     images (depth >= 1); defaults to `order`.  m2l_ranks: optional rank per
     level (index e = 1..depth; a rank >= L^3 or 0 leaves the level
     uncompressed) of the compressed M2L operators.  far = "fft": the far
     field of ANKH-FFT instead (leaf level only, equispaced order eq_order;
-    the far images are inside its matrix, so e_per = 0)."""
+    the far images are inside its matrix, so e_per = 0); its single-level
+    leaf grid may have any number `leaves` of leaves per axis (default 2^depth)."""
+    if leaves is not None and far != "fft":
+        raise ValueError("a leaf grid that is not an octree level needs far='fft'")
     pos = wrap(_c64(pos, (-1, 3)), edge)
     N = pos.shape[0]
     q = _c64(q, (N,))
@@ -317,12 +321,12 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
     L = order
     nu = L ** 3
     E = depth
-    nleaf_ax = 1 << E
+    nleaf_ax = (1 << E) if leaves is None else int(leaves)
     w_leaf = edge / nleaf_ax
     h = 0.5 * w_leaf
 
     # step 1: tree
-    ijk = leaf_index(pos, edge, E)
+    ijk = leaf_index(pos, edge, E, nleaf_ax)
     leaf = (ijk[:, 0] * nleaf_ax + ijk[:, 1]) * nleaf_ax + ijk[:, 2]
     ctr = -0.5 * edge + (ijk + 0.5) * w_leaf
     yhat = (pos - ctr) / h
@@ -398,7 +402,7 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
     Fn = np.zeros((N, 3)) if grad else None
     Gn = np.zeros((N, 3)) if grad else None
     rc = _oracle_lib().oracle_near_field(N, _p(pos), _p(q), _p(mu), _p(theta), float(edge), float(xi),
-                                         int(E), int(nthreads), _p(eatom), _p(Fn), _p(Gn))
+                                         int(nleaf_ax), int(nthreads), _p(eatom), _p(Fn), _p(Gn))
     if rc != 0:
         raise ValueError("oracle_near_field failed")
     e_near = float(np.sum(eatom))

@@ -734,18 +734,19 @@ int oracle_dtensor(const double r[3], double alpha, int n, double *out)
  * pairs (no self term).  Any output may be NULL.
  */
 int oracle_near_field(int64_t n, const double *pos, const double *q, const double *mu, const double *theta,
-                      double edge, double xi, int depth, int nthreads,
+                      double edge, double xi, int nside, int nthreads,
                       double *eatom, double *forces, double *dEdmu)
 {
-    if (n <= 0 || !pos || !q || edge <= 0 || xi <= 0 || depth < 0 || depth > 10) return -1;
+    /* nside: leaves per axis (2^depth for an octree; any count for the single-level ANKH-FFT grid) */
+    if (n <= 0 || !pos || !q || edge <= 0 || xi <= 0 || nside < 1 || nside > 1024) return -1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
     ctx_t c;
-    /* a cell list whose cells are the leaves: nc = 2^depth, R = 1, no cutoff */
+    /* a cell list whose cells are the leaves: nc = nside, R = 1, no cutoff */
     ctx_init(&c, n, pos, q, mu, theta, edge, xi, edge, 0);
     free(c.cell_start); free(c.cell_atoms);
-    const int nc = 1 << depth;
+    const int nc = nside;
     const double w = edge / nc;
     const int ncell = nc * nc * nc;
     int *cnt = (int *)calloc(ncell + 1, sizeof(int));

@@ -206,19 +206,22 @@ def test_fft_reinterpolation_preserves_moments(L, Le):
         np.testing.assert_allclose(back.T @ E, np.eye(L), atol=1e-12)
 
 
-def test_fft_far_equals_its_definition():
-    """Tiny cell (depth 1, 8 leaves): the energy through the 6D transform equals the plain sum over
-    leaf pairs, the images of the source leaf in the displacement cube and the equispaced nodes; the
-    spectrum of the embedded matrix is real; the leaf local expansions are the gradient of the
-    energy in the leaf charges (exact for a quadratic form: E(Q+d) - E(Q-d) = 2 d . Lambda)."""
+@pytest.mark.parametrize("n", [2, 3])
+def test_fft_far_equals_its_definition(n):
+    """Tiny cell (2 or 3 leaves per axis; ANKH-FFT's single-level grid need not be an octree level):
+    the energy through the 6D transform equals the plain sum over leaf pairs, the images of the source
+    leaf in the displacement cube and the equispaced nodes; the spectrum of the embedded matrix is
+    real; the leaf local expansions are the gradient of the energy in the leaf charges (exact for a
+    quadratic form: E(Q+d) - E(Q-d) = 2 d . Lambda)."""
     rng = np.random.default_rng(11)
     edge, E, L, Le, xi, p = 6.0, 1, 3, 3, 0.3, 2
-    n, w = 2, 3.0
+    w = edge / n
     pos = rng.uniform(-3, 3, (10, 3))
     q = rng.normal(size=10)
     mu = 0.3 * rng.normal(size=(10, 3))
     th = synth.random_traceless_theta(rng, 10, 0.2)
-    Q = R.evaluate(pos, q, mu, th, edge, E, L, xi, p, grad=False, keep=True)["Q"].reshape(n ** 3, L ** 3)
+    Q = R.evaluate(pos, q, mu, th, edge, E, L, xi, p, grad=False, keep=True, far="fft", eq_order=Le,
+                   leaves=n)["Q"].reshape(n ** 3, L ** 3)
     K = R.fft_kernel_table(n, w, Le, xi, p)
     e, Lam, D = R.fft_far(Q, n, L, Le, K)
     dense = R.fft_far_dense(Q, n, w, L, Le, xi, p)
@@ -248,3 +251,8 @@ def test_fft_far_field_converges_to_ewald():
     assert errs[0][1] > errs[1][1] > errs[2][1]
     assert errs[0][0] > errs[2][0]
     assert errs[2][0] < 2e-6 and errs[2][1] < 2e-5
+    # a leaf grid that is not an octree level (3 per axis) reaches the same accuracy
+    r3 = R.evaluate(d["pos"], d["q"], d["mu"], d["theta"], edge, 1, 6, xi, p, grad=True, far="fft", eq_order=6,
+                    leaves=3)
+    assert abs(r3["energy"] - ex["energy"]) < 2e-6 * abs(ex["energy"])
+    assert np.sqrt(np.sum((r3["forces"] - ex["forces"]) ** 2) / np.sum(ex["forces"] ** 2)) < 2e-5
