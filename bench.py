@@ -180,6 +180,8 @@ def main():
                     help="far-field method of the timed path: ANKH-FFT (the variant the paper times) or "
                          "ANKH-FMM (multilevel M2L)")
     ap.add_argument("--depth", type=int, default=None, help="octree depth (default: the planner's choice)")
+    ap.add_argument("--leaves", type=int, default=None,
+                    help="ANKH-FFT leaves per axis (any count up to 40, or a power of two; default 2^depth)")
     ap.add_argument("--overlap", default="auto", choices=["auto", "on", "off"],
                     help="far-field chain beside the pair kernel on a second stream (auto: the plan's choice)")
     ap.add_argument("--no-far-compare", action="store_true",
@@ -221,7 +223,8 @@ def main():
     log(f"workload {args.workload}: n={n} edge={data['edge']:.3f}")
 
     ovl = {"auto": None, "on": True, "off": False}[args.overlap]
-    pm = ak.Plan(n, rB, args.eps, 2, args.mode, far=args.far, overlap=ovl, depth=args.depth)
+    lv = args.leaves if args.far == "fft" else None
+    pm = ak.Plan(n, rB, args.eps, 2, args.mode, far=args.far, overlap=ovl, depth=args.depth, leaves=lv)
     log(f"mixed plan: {pm.stats}")
     t_mixed, st_mixed, bd_mixed, out_mixed = timed_run(pm, args_dev, args.steps, args.warmup, torch)
     log(f"mixed: {t_mixed * 1e3:.3f} ms/step timed stages {st_mixed['stage_ms']} breakdown {bd_mixed}")
@@ -253,7 +256,7 @@ def main():
 
     res = {}
     if not args.mixed_only:
-        pf = ak.Plan(n, rB, args.eps, 2, "fp64", far=args.far, overlap=ovl, depth=args.depth)
+        pf = ak.Plan(n, rB, args.eps, 2, "fp64", far=args.far, overlap=ovl, depth=args.depth, leaves=lv)
         t_fp64, st_fp64, bd_fp64, out_fp64 = timed_run(pf, args_dev, args.steps, args.warmup, torch)
         if derivs is not None:
             d64, dfp = derivs_run(pf, args_dev, torch)
@@ -310,7 +313,7 @@ def main():
         # spectrum (complex float64) and reads the real spectrum, 40 B per kept node frequency and leaf
         pa = 2 * st_mixed["eq_order"] - 1
         nf = pa * pa * (pa // 2 + 1)
-        nleaf = 8 ** st_mixed["depth"]
+        nleaf = st_mixed["leaves_per_axis"] ** 3
         fft_bytes = 40.0 * nf * nleaf
         fft_gbs = fft_bytes / (sm["m2l"] * 1e-3) / 1e9
         m2l_roof = {"kernel": "fft_cells", "bound": "hbm", "achieved": fft_gbs, "peak": PEAK["hbm"], "unit": "GB/s",
@@ -342,6 +345,7 @@ def main():
                    "n_atoms": n, "edge_A": data["edge"], "rel_accuracy": args.eps,
                    "depth": st_mixed["depth"], "order": st_mixed["order"], "images": st_mixed["images"],
                    "xi": st_mixed["xi"], "far_field": args.far, "eq_order": st_mixed["eq_order"],
+                   "leaves_per_axis": st_mixed["leaves_per_axis"],
                    "overlap": bool(st_mixed["overlap"]),
                    "parallelism": "single GPU"},
         "plan_ms": st_mixed["plan_ms"],

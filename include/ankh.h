@@ -92,6 +92,8 @@ typedef struct {
     int32_t far_field;  /* far-field method, an ankh_far_field value; 0 = auto (ANKH_FAR_FMM) */
     int32_t eq_order;   /* ANKH-FFT: equispaced nodes per axis of each leaf grid, 2..10; 0 = the
                            Chebyshev order */
+    int32_t leaves;     /* ANKH-FFT: leaves per axis of its single-level grid, 1..40 or a power of two up
+                           to 64 (any count: the grid need not be an octree level); 0 = 2^depth */
     int32_t fft_split;  /* ANKH-FFT: 1 = the cell transforms in three passes through HBM even when one
                            block holds the cells of a node frequency (the path of depths 5 and 6, for
                            testing it at small depths); 0 = only when needed */
@@ -144,6 +146,8 @@ typedef struct {
     int32_t eq_order;          /* ANKH-FFT: equispaced nodes per axis (0 for ANKH-FMM) */
     int32_t overlap;           /* 1 if the far-field chain runs beside the pair kernel, else 0 */
     int32_t fft_split;         /* ANKH-FFT: 1 if the cell transforms run in three passes */
+    int32_t leaves_per_axis;   /* leaves per axis of the finest grid (2^depth; for an ANKH-FFT grid
+                                  that is not a power of two, depth reads -1) */
 } ankh_plan_stats;
 
 /*

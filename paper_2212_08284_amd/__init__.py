@@ -46,8 +46,8 @@ class AnkhError(RuntimeError):
 class _Overrides(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("order", ctypes.c_int32), ("images", ctypes.c_int32),
                 ("xi", ctypes.c_double), ("root_order", ctypes.c_int32), ("m2l_tol", ctypes.c_double),
-                ("far_field", ctypes.c_int32), ("eq_order", ctypes.c_int32), ("fft_split", ctypes.c_int32),
-                ("overlap", ctypes.c_int32)]
+                ("far_field", ctypes.c_int32), ("eq_order", ctypes.c_int32), ("leaves", ctypes.c_int32),
+                ("fft_split", ctypes.c_int32), ("overlap", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -57,7 +57,7 @@ class _Stats(ctypes.Structure):
                 ("plan_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_int64), ("m2l_flops", ctypes.c_double),
                 ("near_pairs", ctypes.c_int64), ("stage_ms", ctypes.c_double * len(STAGES)), ("timed_evals", ctypes.c_int64),
                 ("m2l_rank", ctypes.c_int32 * 8), ("far_field", ctypes.c_int32), ("eq_order", ctypes.c_int32),
-                ("overlap", ctypes.c_int32), ("fft_split", ctypes.c_int32)]
+                ("overlap", ctypes.c_int32), ("fft_split", ctypes.c_int32), ("leaves_per_axis", ctypes.c_int32)]
 
 
 _lib = None
@@ -133,19 +133,20 @@ def ankh_plan(n_atoms: int, box_radius: float, rel_accuracy: float, max_order: i
               precision: int = ANKH_FP64, depth: int | None = None, order: int | None = None,
               images: int | None = None, xi: float | None = None, root_order: int | None = None,
               m2l_tol: float | None = None, stream=None, far_field: int = 0, eq_order: int | None = None,
-              overlap: bool | None = None, fft_split: bool = False):
+              overlap: bool | None = None, fft_split: bool = False, leaves: int | None = None):
     """Create a plan; returns the opaque handle (ctypes.c_void_p).  m2l_tol: singular-value cutoff of the
     compressed M2L (None = automatic, negative = no compression).  far_field: ANKH_FAR_FMM / ANKH_FAR_FFT
     (0 = automatic); eq_order: equispaced nodes per axis of ANKH-FFT (None = the Chebyshev order); overlap:
     far-field chain beside the pair kernel (None = automatic); fft_split: ANKH-FFT cell transforms in three
-    passes even when one block could hold them (testing)."""
+    passes even when one block could hold them (testing); leaves: ANKH-FFT leaves per axis (None = 2^depth)."""
     L = load_library()
     if not torch.cuda.is_available():
         raise RuntimeError("no GPU: the interpolated-Ewald library runs on the GPU only")
     ov = _Overrides(-1 if depth is None else int(depth), 0 if order is None else int(order),
                     0 if images is None else int(images), 0.0 if xi is None else float(xi),
                     0 if root_order is None else int(root_order), 0.0 if m2l_tol is None else float(m2l_tol),
-                    int(far_field), 0 if eq_order is None else int(eq_order), 1 if fft_split else 0,
+                    int(far_field), 0 if eq_order is None else int(eq_order), 0 if leaves is None else int(leaves),
+                    1 if fft_split else 0,
                     0 if overlap is None else (1 if overlap else 2))
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -228,7 +229,7 @@ class Plan:
 
     def __init__(self, n_atoms, box_radius, rel_accuracy=1e-6, max_order=2, precision="fp64", depth=None,
                  order=None, images=None, xi=None, root_order=None, m2l_tol=None, stream=None, far="auto",
-                 eq_order=None, overlap=None, fft_split=False):
+                 eq_order=None, overlap=None, fft_split=False, leaves=None):
         prec = ({"fp64": ANKH_FP64, "mixed": ANKH_MIXED, "mixed_bf16x3": ANKH_MIXED_BF16X3}[precision]
                 if isinstance(precision, str) else int(precision))
         far_field = ({"auto": ANKH_FAR_AUTO, "fmm": ANKH_FAR_FMM, "fft": ANKH_FAR_FFT}[far]
@@ -236,7 +237,7 @@ class Plan:
         self.n = int(n_atoms)
         self.max_order = int(max_order)
         self.handle = ankh_plan(n_atoms, box_radius, rel_accuracy, max_order, prec, depth, order, images, xi,
-                                root_order, m2l_tol, stream, far_field, eq_order, overlap, fft_split)
+                                root_order, m2l_tol, stream, far_field, eq_order, overlap, fft_split, leaves)
         self.stats = ankh_get_stats(self.handle)
 
     def _args(self, pos, q, mu, theta):

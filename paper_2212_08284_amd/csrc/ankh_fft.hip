@@ -29,7 +29,9 @@
 //                    the product with D / N, the inverse 3D FFT, in place
 //                    (n <= 16; for 32 and 64 cells per axis three passes
 //                    through HBM: k_fft_yz planes, k_fft_x lines with the
-//                    product, k_fft_yz inverse);
+//                    product, k_fft_yz inverse; for a grid that is not a
+//                    power of two the same three passes with direct DFTs,
+//                    k_dft_yz / k_dft_x);
 //   k_fft_nodes_inv  per leaf: the adjoint of the first (conj(B)^T per axis,
 //                    the half spectrum counted twice), Lambda_c into the leaf
 //                    row of the local expansions.
@@ -568,6 +570,220 @@ __global__ __launch_bounds__(256) void k_fft_x(double2 *X, double *D, const doub
     }
 }
 
+// ---- cell transforms on grids that are not powers of two ------------------------
+// Direct DFT along one direction of an n x n tile (element (u, v) at u n + v), from A into B:
+// B[..k..] = sum_j A[..j..] w^{jk}, w = e^{-/+ 2 pi i / n} (tw[m] = e^{-2 pi i m / n}, m < n, in LDS).
+__device__ void tile_dft(const double2 *A, double2 *B, const double2 *tw, int n, bool along_v, bool inv) {
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int u = e / n, v = e - u * n;
+        const int k = along_v ? v : u;
+        double re = 0, im = 0;
+        int m = 0;
+        for (int j = 0; j < n; j++) {
+            const double2 x = along_v ? A[u * n + j] : A[j * n + v];
+            const double2 w = tw[m];
+            const double wy = inv ? -w.y : w.y;
+            re += x.x * w.x - x.y * wy;
+            im += x.x * wy + x.y * w.x;
+            m += k;
+            if (m >= n) m -= n;
+        }
+        B[e] = make_double2(re, im);
+    }
+    __syncthreads();
+}
+
+// pass 1 / 3: block (f, x), the (y, z) plane, forward or inverse
+__global__ __launch_bounds__(256) void k_dft_yz(double2 *X, const double2 *twg, int n, int64_t ncell, int inv) {
+    extern __shared__ double2 sm[];
+    double2 *A = sm, *B = A + n * n, *tw = B + n * n;
+    double2 *p = X + (int64_t)blockIdx.x * ncell + (int64_t)blockIdx.y * n * n;
+    for (int i = threadIdx.x; i < n; i += 256) tw[i] = twg[i];
+    for (int i = threadIdx.x; i < n * n; i += 256) A[i] = p[i];
+    __syncthreads();
+    tile_dft(A, B, tw, n, true, inv != 0);
+    tile_dft(B, A, tw, n, false, inv != 0);
+    for (int i = threadIdx.x; i < n * n; i += 256) p[i] = A[i];
+}
+
+// pass 2: block (f, y), the (x, z) tile: forward along x, then MODE 0: times D * scale and the inverse,
+// MODE 1 (plan): the real part to D
+__global__ __launch_bounds__(256) void k_dft_x(double2 *X, double *D, const double2 *twg, int n, int64_t ncell,
+                                               double scale, int mode) {
+    extern __shared__ double2 sm[];
+    double2 *A = sm, *B = A + n * n, *tw = B + n * n;
+    const int64_t f = blockIdx.x;
+    const int y = blockIdx.y;
+    for (int i = threadIdx.x; i < n; i += 256) tw[i] = twg[i];
+    for (int i = threadIdx.x; i < n * n; i += 256) {
+        const int x = i / n, z = i - x * n;
+        A[i] = X[f * ncell + ((int64_t)x * n + y) * n + z];
+    }
+    __syncthreads();
+    tile_dft(A, B, tw, n, false, false);
+    for (int i = threadIdx.x; i < n * n; i += 256) {
+        const int x = i / n, z = i - x * n;
+        const int64_t g = f * ncell + ((int64_t)x * n + y) * n + z;
+        if (mode == 1) D[g] = B[i].x;
+        else B[i] = make_double2(B[i].x * D[g] * scale, B[i].y * D[g] * scale);
+    }
+    if (mode == 1) return;
+    __syncthreads();
+    tile_dft(B, A, tw, n, false, true);
+    for (int i = threadIdx.x; i < n * n; i += 256) {
+        const int x = i / n, z = i - x * n;
+        X[f * ncell + ((int64_t)x * n + y) * n + z] = A[i];
+    }
+}
+
+// Transforms of N = 4 N2 points along one direction of LDS tiles (Cooley-Tukey, n = n1 + 4 n2,
+// k = k2 + N2 k1), in place in two phases separated by a barrier:
+//   forward: phase 1, per (line, n1): y[n1 + 4 k2] = W^{n1 k2} sum_n2 x[n1 + 4 n2] W^{4 n2 k2};
+//            phase 2, per (line, k2): the 4-point transforms of y[4 k2 .. 4 k2 + 3] (roots +-1, +-i),
+//            X[k2 + N2 k1] left at position 4 k2 + k1 (digit-reversed);
+//   inverse: the same phases in reverse order with conjugate roots, from that order back to natural.
+// Pointwise products in between see every axis in the same permuted order, D included (it is built
+// by the same forward transform), so the permutation never needs undoing.  W = e^{-2 pi i / N},
+// tw[m] = W^m in LDS.  Element j of line `line` of tile `tile`: t[tile N^2 + (ALONG_V ? line N + j :
+// j N + line)].
+template <int N2, bool ALONG_V, bool INV>
+__device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
+    constexpr int N = 4 * N2;
+    for (int task = threadIdx.x; task < ntile * N * 4; task += blockDim.x) {
+        // consecutive threads: consecutive elements of the contiguous direction
+        int tile, line, n1;
+        if (ALONG_V) { tile = task / (N * 4); const int r = task - tile * N * 4; line = r / 4; n1 = r % 4; }
+        else { tile = task / (N * 4); const int r = task - tile * N * 4; n1 = r / N; line = r % N; }
+        double2 *b = t + tile * N * N;
+        auto at = [&](int j) -> double2 & { return b[ALONG_V ? line * N + j : j * N + line]; };
+        if (!INV) {
+            double2 x[N2];
+#pragma unroll
+            for (int n2 = 0; n2 < N2; n2++) x[n2] = at(n1 + 4 * n2);
+#pragma unroll
+            for (int k2 = 0; k2 < N2; k2++) {
+                double re = 0, im = 0;
+#pragma unroll
+                for (int n2 = 0; n2 < N2; n2++) {
+                    const double2 w = tw[(4 * n2 * k2) % N];
+                    re += x[n2].x * w.x - x[n2].y * w.y;
+                    im += x[n2].x * w.y + x[n2].y * w.x;
+                }
+                const double2 w = tw[(n1 * k2) % N];
+                at(n1 + 4 * k2) = make_double2(re * w.x - im * w.y, re * w.y + im * w.x);
+            }
+        } else {
+            // inverse of phase 1: z[n1 + 4 k2] times conj W^{n1 k2}, then the conjugate N2-point transform
+            double2 z[N2];
+#pragma unroll
+            for (int k2 = 0; k2 < N2; k2++) {
+                const double2 v = at(n1 + 4 * k2), w = tw[(n1 * k2) % N];
+                z[k2] = make_double2(v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y);
+            }
+#pragma unroll
+            for (int n2 = 0; n2 < N2; n2++) {
+                double re = 0, im = 0;
+#pragma unroll
+                for (int k2 = 0; k2 < N2; k2++) {
+                    const double2 w = tw[(4 * n2 * k2) % N];
+                    re += z[k2].x * w.x + z[k2].y * w.y;
+                    im += z[k2].y * w.x - z[k2].x * w.y;
+                }
+                at(n1 + 4 * n2) = make_double2(re, im);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int N2, bool ALONG_V, bool INV>
+__device__ inline void tiles_phase2(double2 *t, int ntile) {
+    constexpr int N = 4 * N2;
+    for (int task = threadIdx.x; task < ntile * N * N2; task += blockDim.x) {
+        int tile, line, k2;
+        if (ALONG_V) { tile = task / (N * N2); const int r = task - tile * N * N2; line = r / N2; k2 = r % N2; }
+        else { tile = task / (N * N2); const int r = task - tile * N * N2; k2 = r / N; line = r % N; }
+        double2 *b = t + tile * N * N;
+        auto at = [&](int j) -> double2 & { return b[ALONG_V ? line * N + j : j * N + line]; };
+        const double2 a = at(4 * k2), bb = at(4 * k2 + 1), c = at(4 * k2 + 2), d = at(4 * k2 + 3);
+        const double2 s0 = make_double2(a.x + c.x, a.y + c.y), s1 = make_double2(a.x - c.x, a.y - c.y);
+        const double2 s2 = make_double2(bb.x + d.x, bb.y + d.y), s3 = make_double2(bb.x - d.x, bb.y - d.y);
+        // (-i)^{n1 k1} forward, i^{n1 k1} inverse
+        const double2 js3 = INV ? make_double2(-s3.y, s3.x) : make_double2(s3.y, -s3.x);
+        at(4 * k2) = make_double2(s0.x + s2.x, s0.y + s2.y);
+        at(4 * k2 + 1) = make_double2(s1.x + js3.x, s1.y + js3.y);
+        at(4 * k2 + 2) = make_double2(s0.x - s2.x, s0.y - s2.y);
+        at(4 * k2 + 3) = make_double2(s1.x - js3.x, s1.y - js3.y);
+    }
+    __syncthreads();
+}
+
+// one axis of every tile: forward (natural -> digit-reversed) or inverse (digit-reversed -> natural)
+template <int N2, bool ALONG_V, bool INV>
+__device__ inline void tiles_axis(double2 *t, int ntile, const double2 *tw) {
+    if (!INV) {
+        tiles_phase1<N2, ALONG_V, false>(t, ntile, tw);
+        tiles_phase2<N2, ALONG_V, false>(t, ntile);
+    } else {
+        tiles_phase2<N2, ALONG_V, true>(t, ntile);
+        tiles_phase1<N2, ALONG_V, true>(t, ntile, tw);
+    }
+}
+
+// passes 1 / 3: block (f, x0 .. x0 + PB), the (y, z) planes
+template <int N1, int N2, int PB>
+__global__ __launch_bounds__(256) void k_rdft_yz(double2 *X, const double2 *twg, int64_t ncell, int inv) {
+    static_assert(N1 == 4, "4 x N2 points");
+    constexpr int N = N1 * N2;
+    __shared__ double2 t[PB * N * N];
+    __shared__ double2 tw[N];
+    const int x0 = blockIdx.y * PB, np = min(PB, N - x0);
+    double2 *p = X + (int64_t)blockIdx.x * ncell + (int64_t)x0 * N * N;
+    for (int i = threadIdx.x; i < N; i += 256) tw[i] = twg[i];
+    for (int i = threadIdx.x; i < np * N * N; i += 256) t[i] = p[i];
+    __syncthreads();
+    if (inv) {
+        tiles_axis<N2, false, true>(t, np, tw);    // y, then z: the reverse of the forward order
+        tiles_axis<N2, true, true>(t, np, tw);
+    } else {
+        tiles_axis<N2, true, false>(t, np, tw);    // z
+        tiles_axis<N2, false, false>(t, np, tw);   // y
+    }
+    for (int i = threadIdx.x; i < np * N * N; i += 256) p[i] = t[i];
+}
+
+// pass 2: block (f, y0 .. y0 + PB), the (x, z) tiles: forward along x, then times D * scale and the
+// inverse (MODE 0), or the real part to D (MODE 1)
+template <int N1, int N2, int PB, int MODE>
+__global__ __launch_bounds__(256) void k_rdft_x(double2 *X, double *D, const double2 *twg, int64_t ncell,
+                                                double scale) {
+    constexpr int N = N1 * N2;
+    __shared__ double2 t[PB * N * N];
+    __shared__ double2 tw[N];
+    const int64_t f = blockIdx.x;
+    const int y0 = blockIdx.y * PB, np = min(PB, N - y0);
+    for (int i = threadIdx.x; i < N; i += 256) tw[i] = twg[i];
+    for (int i = threadIdx.x; i < np * N * N; i += 256) {
+        const int tile = i / (N * N), r = i - tile * N * N, x = r / N, z = r - x * N;
+        t[i] = X[f * ncell + ((int64_t)x * N + y0 + tile) * N + z];
+    }
+    __syncthreads();
+    tiles_axis<N2, false, false>(t, np, tw);
+    for (int i = threadIdx.x; i < np * N * N; i += 256) {
+        const int tile = i / (N * N), r = i - tile * N * N, x = r / N, z = r - x * N;
+        const int64_t g = f * ncell + ((int64_t)x * N + y0 + tile) * N + z;
+        if (MODE == 1) D[g] = t[i].x;
+        else t[i] = make_double2(t[i].x * D[g] * scale, t[i].y * D[g] * scale);
+    }
+    if (MODE == 1) return;
+    __syncthreads();
+    tiles_axis<N2, false, true>(t, np, tw);
+    for (int i = threadIdx.x; i < np * N * N; i += 256) {
+        const int tile = i / (N * N), r = i - tile * N * N, x = r / N, z = r - x * N;
+        X[f * ncell + ((int64_t)x * N + y0 + tile) * N + z] = t[i];
+    }
+}
+
 // ---- plan time, with the mirror symmetry of the kernel --------------------------
 // The generating cube is even along each axis separately: K(-g_x, g_y, g_z; -a_x, a_y, a_z) = K(g; a)
 // (the displacement cube and the adjacency test are symmetric), so the node spectrum of the residue
@@ -697,6 +913,34 @@ void split_passes(ankh_plan_s *pl, double2 *X, double *D, double scale) {
 
 template <int MODE>
 hipError_t cells(ankh_plan_s *pl, double2 *X, double *D, double scale) {
+    if (pl->fft_dft && (pl->nside == 12 || pl->nside == 20 || pl->nside == 24)) {
+        // 12 = 4 x 3, 20 = 4 x 5, 24 = 4 x 6 points per axis: two-phase transforms, PB tiles per block
+        // (PB N^2 complex values + N roots within 64 KB)
+        const int n = pl->nside;
+        const dim3 b(256);
+#define ANKH_RDFT(A, B, PB)                                                                                        \
+        {                                                                                                          \
+            const dim3 g((unsigned)pl->fft_nf, (unsigned)((n + PB - 1) / PB));                                    \
+            hipLaunchKernelGGL((k_rdft_yz<A, B, PB>), g, b, 0, pl->stream, X, pl->d_fftTw, pl->nleaf, 0);          \
+            hipLaunchKernelGGL((k_rdft_x<A, B, PB, MODE>), g, b, 0, pl->stream, X, D, pl->d_fftTw, pl->nleaf, scale); \
+            if (MODE == 0)                                                                                          \
+                hipLaunchKernelGGL((k_rdft_yz<A, B, PB>), g, b, 0, pl->stream, X, pl->d_fftTw, pl->nleaf, 1);      \
+        }
+        if (n == 12) ANKH_RDFT(4, 3, 16)
+        else if (n == 20) ANKH_RDFT(4, 5, 9)
+        else ANKH_RDFT(4, 6, 6)
+#undef ANKH_RDFT
+        return hipGetLastError();
+    }
+    if (pl->fft_dft) {
+        const int n = pl->nside;
+        const dim3 g((unsigned)pl->fft_nf, n), b(256);
+        const size_t shm = sizeof(double2) * (2 * (size_t)n * n + n);
+        hipLaunchKernelGGL(k_dft_yz, g, b, shm, pl->stream, X, pl->d_fftTw, n, pl->nleaf, 0);
+        hipLaunchKernelGGL(k_dft_x, g, b, shm, pl->stream, X, D, pl->d_fftTw, n, pl->nleaf, scale, MODE);
+        if (MODE == 0) hipLaunchKernelGGL(k_dft_yz, g, b, shm, pl->stream, X, pl->d_fftTw, n, pl->nleaf, 1);
+        return hipGetLastError();
+    }
     if (pl->fft_split) {
         switch (pl->nside) {
             case 2: split_passes<2, MODE>(pl, X, D, scale); break;
@@ -731,9 +975,10 @@ bool fft_supported(int depth, int L, int le) {
     return nodes_fwd_lds(L, pa) <= lim && nodes_inv_lds(L, pa, ph) <= lim && table_lds(pa) <= lim;
 }
 
-void fft_host_roots(int nside, std::vector<double2> &tw) {
-    tw.assign(std::max(1, nside / 2), make_double2(1, 0));
-    for (int k = 0; k < nside / 2; k++) {
+void fft_host_roots(int nside, bool full, std::vector<double2> &tw) {
+    const int cnt = full ? nside : nside / 2;
+    tw.assign(std::max(1, cnt), make_double2(1, 0));
+    for (int k = 0; k < cnt; k++) {
         const long double a = -2.0L * (long double)kPiF * k / nside;
         tw[k] = make_double2((double)cosl(a), (double)sinl(a));
     }

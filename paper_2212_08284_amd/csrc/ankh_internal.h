@@ -18,6 +18,7 @@ constexpr int kMaxRootOrder = 12;    // largest order of the root (far-image) gr
 constexpr int kMaxRootNodes = kMaxRootOrder * kMaxRootOrder * kMaxRootOrder;
 constexpr int kMaxDepth = 7;         // 2^21 leaves at most
 constexpr int kMaxFftDepth = 6;      // ANKH-FFT: 64^2 cells of a plane of one node frequency in one block's LDS
+constexpr int kMaxFftDft = 40;       // ANKH-FFT grids that are not powers of two: two 40^2 planes in LDS
 constexpr int kNumOff = 343;         // slots for offsets d in [-3,3]^3 (316 used)
 constexpr int kNumIL = 189;          // interaction-list length of every cell
 constexpr int kRedBlocks = 1024;     // first-stage blocks of the energy reduction (the epilogue)
@@ -121,9 +122,10 @@ struct ankh_plan_s {
     bool overlap = true;          // far-field chain on `side` beside the pair kernel
     int eq_order = 0, fft_pa = 0, fft_ph = 0;
     bool fft_split = false;       // cell transforms in three passes through HBM (n > 16, or on request)
+    bool fft_dft = false;         // leaf grid not a power of two: direct DFTs along each axis (three passes)
     int64_t fft_nf = 0;
     double2 *d_fftB = nullptr, *d_fftW = nullptr, *d_fftX = nullptr;
-    double2 *d_fftTw = nullptr;   // e^{-2 pi i k / n}, k < n/2, for the three-pass cell transforms
+    double2 *d_fftTw = nullptr;   // e^{-2 pi i k / n}: k < n/2 (radix 2) or k < n (direct DFT), three-pass path
     double *d_fftD = nullptr;
     size_t bytes = 0;
 
@@ -179,7 +181,7 @@ hipError_t launch_convert_f32(const double *src, float *dst, int64_t n, hipStrea
 // ANKH-FFT (ankh_fft.hip)
 bool fft_supported(int depth, int L, int eq_order);
 void fft_host_tables(int L, int eq_order, const double *cheb_nodes, std::vector<double2> &B, std::vector<double2> &W);
-void fft_host_roots(int nside, std::vector<double2> &tw);
+void fft_host_roots(int nside, bool full, std::vector<double2> &tw);
 hipError_t launch_fft_build_D(ankh_plan_s *pl);    // plan time: the real spectrum D
 hipError_t launch_fft_forward(ankh_plan_s *pl);    // leaf multipoles -> half spectrum X
 hipError_t launch_fft_cells(ankh_plan_s *pl);      // cell transforms, product with D, inverse

@@ -380,7 +380,8 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs<R> a) {
     int64_t b = blockIdx.x;
     if ((nblk & 7) == 0) b = (int64_t)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
     const int kind = (int)(b % NKIND);
-    const int leaf = morton_leaf(b / NKIND, a.depth, ns);
+    // Morton order on an octree level; on any other grid (ANKH-FFT) the lexicographic order
+    const int leaf = a.depth >= 0 ? morton_leaf(b / NKIND, a.depth, ns) : (int)(b / NKIND);
     const int lx = leaf / (ns * ns), ly = (leaf / ns) % ns, lz = leaf % ns;
     const int k_first = kind == 0 ? 1 : KMAX + 1;
     const int ntl = kind == 0 ? KMAX : NHALF - KMAX;
@@ -946,7 +947,7 @@ hipError_t launch_prec(ankh_plan_s *pl, int ord, bool grad, bool fields) {
     a.offs = pl->d_offs;
     a.n = pl->n;
     a.nside = pl->nside;
-    a.depth = pl->depth;
+    a.depth = pl->fft_dft ? -1 : pl->depth;
     a.w = pl->edge / pl->nside;
     a.xi = pl->xi;
     a.slot_e = pl->d_slot_e;

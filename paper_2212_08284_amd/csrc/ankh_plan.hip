@@ -82,6 +82,26 @@ int depth_for(int64_t n, int nu) {
     return std::min(std::max(E, 0), kMaxDepth);
 }
 
+// ANKH-FFT leaves per axis: no octree levels above the leaves, so any grid with fast cell transforms
+// (powers of two up to 64; 12, 20, 24) is a candidate.  The far field costs little against the pair
+// kernel, so the grid targets fewer atoms per leaf than the octree rule: 0.17 n_u (36 at order 6),
+// the best of 16^3, 20^3 and 24^3 on the 288,000-atom water box.
+int leaves_for(int64_t n, int nu) {
+    static const int cand[] = {1, 2, 4, 8, 12, 16, 20, 24, 32, 64};
+    const double occ = std::max(12.0, 0.17 * nu);
+    const double target = std::cbrt(std::max(1.0, (double)n / occ));
+    int best = 1;
+    double bd = 1e300;
+    for (int c : cand) {
+        const double d = std::fabs(std::log(c / target));
+        if (d < bd) {
+            bd = d;
+            best = c;
+        }
+    }
+    return best;
+}
+
 void build_tables(ankh_plan_s *pl) {
     const int L = pl->order;
     for (int k = 0; k < L; k++) pl->nodes[k] = std::cos((2 * k + 1) * kPi / (2 * L));
@@ -255,6 +275,8 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         if (ov->eq_order != 0 && (ov->eq_order < 2 || ov->eq_order > kMaxOrder)) return ANKH_ERR_INVALID_ARG;
         if (ov->overlap < 0 || ov->overlap > 2) return ANKH_ERR_INVALID_ARG;
         if (ov->fft_split < 0 || ov->fft_split > 1) return ANKH_ERR_INVALID_ARG;
+        if (ov->leaves < 0 || ov->leaves > 64) return ANKH_ERR_INVALID_ARG;
+        if (ov->leaves > 0 && ov->far_field != ANKH_FAR_FFT) return ANKH_ERR_INVALID_ARG;
     }
     auto t0 = std::chrono::steady_clock::now();
     ankh_plan_s *pl = new (std::nothrow) ankh_plan_s();
@@ -284,11 +306,29 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
     const bool fft = pl->far_field == ANKH_FAR_FFT;
     pl->overlap = (ov && ov->overlap) ? ov->overlap == 1 : !fft;
     pl->depth = (ov && ov->depth >= 0) ? ov->depth : depth_for(n_atoms, pl->nu);
+    // ANKH-FFT's grid of leaves per axis: a power of two is the octree depth; any other count (up to
+    // kMaxFftDft) is a single level, kept as level 0
+    int grid = 0;
+    const bool auto_grid = fft && !(ov && (ov->leaves > 0 || ov->depth >= 0));
+    if (fft && ((ov && ov->leaves > 0) || auto_grid)) {
+        const int g = auto_grid ? leaves_for(n_atoms, pl->nu) : ov->leaves;
+        if ((g & (g - 1)) == 0) {
+            int e = 0;
+            while ((1 << e) < g) e++;
+            pl->depth = e;
+        } else if (g <= kMaxFftDft) {
+            grid = g;
+            pl->depth = 0;
+        } else {
+            delete pl;
+            return ANKH_ERR_INVALID_ARG;
+        }
+    }
     if (fft) {
         // ANKH-FFT: equispaced order (the Chebyshev order unless set); the automatic depth stops at
         // the deepest tree whose cell transforms fit one block
         pl->eq_order = (ov && ov->eq_order > 0) ? ov->eq_order : pl->order;
-        if (!(ov && ov->depth >= 0)) pl->depth = std::min(pl->depth, kMaxFftDepth);
+        if (!(ov && (ov->depth >= 0 || ov->leaves > 0)) && !auto_grid) pl->depth = std::min(pl->depth, kMaxFftDepth);
         if (!fft_supported(pl->depth, pl->order, pl->eq_order)) {
             delete pl;
             return ANKH_ERR_INVALID_ARG;
@@ -297,15 +337,17 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         pl->fft_ph = pl->fft_pa / 2 + 1;
         pl->fft_nf = (int64_t)pl->fft_pa * pl->fft_pa * pl->fft_ph;
     }
-    pl->nside = 1 << pl->depth;
-    // three-pass cell transforms beyond 16 cells per axis, or on request (not at depth 0)
-    pl->fft_split = fft && pl->nside >= 2 && (pl->nside > 16 || (ov && ov->fft_split == 1));
+    pl->nside = grid ? grid : 1 << pl->depth;
+    // three-pass cell transforms beyond 16 cells per axis, or on request (not at depth 0); direct
+    // DFTs along each axis on a grid that is not a power of two
+    pl->fft_dft = grid != 0;
+    pl->fft_split = fft && !grid && pl->nside >= 2 && (pl->nside > 16 || (ov && ov->fft_split == 1));
     pl->nleaf = (int64_t)pl->nside * pl->nside * pl->nside;
     size_t cells = 0;
     for (int e = 0; e <= pl->depth; e++) {
         Level &lv = pl->lv[e];
         lv.e = e;
-        lv.nside = 1 << e;
+        lv.nside = (e == pl->depth) ? pl->nside : 1 << e;
         lv.ncell = (int64_t)lv.nside * lv.nside * lv.nside;
         lv.cell0 = cells;
         lv.width = pl->edge / lv.nside;
@@ -495,7 +537,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
             std::vector<double2> B, W;
             fft_host_tables(pl->order, pl->eq_order, pl->nodes, B, W);
             std::vector<double2> tw;
-            fft_host_roots(pl->nside, tw);
+            fft_host_roots(pl->nside, pl->fft_dft, tw);
             dalloc(pl, &pl->d_fftTw, tw.size());
             ck(hipMemcpy(pl->d_fftTw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
             dalloc(pl, &pl->d_fftB, B.size());
@@ -590,7 +632,8 @@ ankh_status ankh_get_stats(ankh_plan_t pl, ankh_plan_stats *out) {
     if (hipStreamSynchronize(pl->stream) != hipSuccess) return ANKH_ERR_HIP;
     std::memset(out, 0, sizeof(*out));
     out->n_atoms = pl->n;
-    out->depth = pl->depth;
+    out->depth = pl->fft_dft ? -1 : pl->depth;
+    out->leaves_per_axis = pl->nside;
     out->order = pl->order;
     out->root_order = pl->order0;
     out->images = pl->images;

@@ -72,11 +72,13 @@ def test_plan_rejects_bad_overrides(lib):
     for ov in (ak._Overrides(9, 0, 0, 0.0), ak._Overrides(-1, 1, 0, 0.0), ak._Overrides(-1, 11, 0, 0.0),
                ak._Overrides(-1, 0, 99, 0.0), ak._Overrides(-1, 0, 0, float("inf")),
                ak._Overrides(-1, 0, 0, 0.0, 0, 2.0), ak._Overrides(-1, 0, 0, 0.0, 0, float("nan")),
-               ak._Overrides(-1, 0, 0, 0.0, 0, 0.0, 3), ak._Overrides(-1, 0, 0, 0.0, 0, 0.0, 2, 1),
-               ak._Overrides(-1, 0, 0, 0.0, 0, 0.0, 2, 11), ak._Overrides(-1, 0, 0, 0.0, 0, 0.0, 2, 0, 2),
-               ak._Overrides(-1, 0, 0, 0.0, 0, 0.0, 0, 0, 0, 3),
-               # ANKH-FFT beyond depth 6
-               ak._Overrides(7, 0, 0, 0.0, 0, 0.0, 2)):
+               ak._Overrides(depth=-1, far_field=3), ak._Overrides(depth=-1, far_field=2, eq_order=1),
+               ak._Overrides(depth=-1, far_field=2, eq_order=11), ak._Overrides(depth=-1, far_field=2, fft_split=2),
+               ak._Overrides(depth=-1, overlap=3),
+               # ANKH-FFT beyond depth 6; leaf grids: not for ANKH-FMM, at most 40 unless a power of two
+               ak._Overrides(depth=7, far_field=2), ak._Overrides(depth=-1, leaves=20),
+               ak._Overrides(depth=-1, far_field=2, leaves=41), ak._Overrides(depth=-1, far_field=2, leaves=65),
+               ak._Overrides(depth=-1, far_field=2, leaves=-1)):
         st, h = _plan(lib, ov=ov)
         assert st == 1 and not h.value
 
