@@ -98,9 +98,7 @@ typedef struct {
                            block holds the cells of a node frequency (the path of depths 5 and 6, for
                            testing it at small depths); 0 = only when needed */
     int32_t overlap;    /* far-field chain beside the pair kernel on the plan's second stream: 1 = yes,
-                           2 = no (every stage in sequence on the plan's stream), 0 = auto (yes for
-                           ANKH-FMM, no for ANKH-FFT, whose short far field costs the pair kernel more
-                           when they share the CUs than it saves) */
+                           2 = no (every stage in sequence on the plan's stream), 0 = auto (yes) */
 } ankh_overrides;
 
 /* Far-field methods.

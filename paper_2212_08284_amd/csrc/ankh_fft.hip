@@ -926,9 +926,9 @@ hipError_t cells(ankh_plan_s *pl, double2 *X, double *D, double scale) {
             if (MODE == 0)                                                                                          \
                 hipLaunchKernelGGL((k_rdft_yz<A, B, PB>), g, b, 0, pl->stream, X, pl->d_fftTw, pl->nleaf, 1);      \
         }
-        if (n == 12) ANKH_RDFT(4, 3, 16)
-        else if (n == 20) ANKH_RDFT(4, 5, 9)
-        else ANKH_RDFT(4, 6, 6)
+        if (n == 12) ANKH_RDFT(4, 3, 4)
+        else if (n == 20) ANKH_RDFT(4, 5, 2)
+        else ANKH_RDFT(4, 6, 2)
 #undef ANKH_RDFT
         return hipGetLastError();
     }

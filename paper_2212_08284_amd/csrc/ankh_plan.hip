@@ -304,7 +304,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
     pl->nup = (pl->nu + 31) / 32 * 32;   // row stride: a multiple of the M2L tile step
     pl->far_field = (ov && ov->far_field == ANKH_FAR_FFT) ? ANKH_FAR_FFT : ANKH_FAR_FMM;
     const bool fft = pl->far_field == ANKH_FAR_FFT;
-    pl->overlap = (ov && ov->overlap) ? ov->overlap == 1 : !fft;
+    pl->overlap = (ov && ov->overlap) ? ov->overlap == 1 : true;
     pl->depth = (ov && ov->depth >= 0) ? ov->depth : depth_for(n_atoms, pl->nu);
     // ANKH-FFT's grid of leaves per axis: a power of two is the octree depth; any other count (up to
     // kMaxFftDft) is a single level, kept as level 0
