@@ -323,8 +323,11 @@ def main():
                     "alone_achieved": fft_bytes / (bd_mixed["m2l"] * 1e-3) / 1e9,
                     "alone_frac": fft_bytes / (bd_mixed["m2l"] * 1e-3) / 1e9 / PEAK["hbm"],
                     "avg_launch_ms": sm["m2l"],
-                    "note": f"ANKH-FFT cell transforms: {nf} kept node frequencies x {nleaf} leaves, each read and "
-                            "written once as complex float64 and multiplied by the real spectrum (float64)"}
+                    "note": f"ANKH-FFT cell transforms (stage 4): {nf} kept node frequencies x {nleaf} leaves, each "
+                            "read and written once as complex float64 and multiplied by the real spectrum (float64): "
+                            "the algorithmic bytes.  Beyond 16^3 leaves, and on grids that are not powers of two, "
+                            "the transforms run in three passes through HBM (2.6x these bytes); traffic is the "
+                            "counters' sum over the stage's launches"}
     roof, other = (p2p_roof, m2l_roof) if sm["p2p"] >= sm["m2l"] else (m2l_roof, p2p_roof)
 
     line = {
