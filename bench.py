@@ -59,9 +59,9 @@ PEAK = {  # MI355X, TFLOP/s (hbm: GB/s)
 }
 
 
-def p2p_traffic(counters=P2P_COUNTERS, source=P2P_SOURCE):
+def p2p_traffic(counters=P2P_COUNTERS, source=P2P_SOURCE, leaves=None):
     """Calibrated HBM bytes per launch of a kernel from its committed counter summary, or None when
-    the summary is missing or the kernel source has changed since."""
+    the summary is missing, the kernel source has changed since, or it was taken on another leaf grid."""
     import hashlib
     try:
         rec = {}
@@ -73,6 +73,8 @@ def p2p_traffic(counters=P2P_COUNTERS, source=P2P_SOURCE):
         with open(source, "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
         if rec.get("kernel_source_sha256") != sha:
+            return None
+        if leaves is not None and rec.get("leaves_per_axis") != str(leaves):
             return None
         return float(rec["fetch_bytes_per_launch"]) + float(rec["write_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -293,7 +295,8 @@ def main():
     m2l_peak = PEAK["mfma_bf16"] if args.mode == "mixed_bf16x3" else PEAK["mfma_fp32"]
     p2p_alone_tf = p2p_flops / (bd_mixed["p2p"] * 1e-3) / 1e12
     p2p_roof = {"kernel": "p2p", "bound": "alu", "achieved": p2p_tf, "peak": PEAK["valu_fp32"],
-                "unit": "TFLOP/s", "frac": p2p_tf / PEAK["valu_fp32"], "traffic": p2p_traffic(),
+                "unit": "TFLOP/s", "frac": p2p_tf / PEAK["valu_fp32"],
+                "traffic": p2p_traffic(leaves=st_mixed["leaves_per_axis"]),
                 "flop_per_launch": p2p_flops, "unordered_pairs": unordered,
                 "flop_per_unordered_pair": P2P_FLOP_PER_UNORDERED_PAIR, "avg_launch_ms": sm["p2p"],
                 "frac_of_packed_fp32_peak": p2p_tf / PEAK["valu_fp32_packed"],
@@ -317,7 +320,8 @@ def main():
         fft_bytes = 40.0 * nf * nleaf
         fft_gbs = fft_bytes / (sm["m2l"] * 1e-3) / 1e9
         m2l_roof = {"kernel": "fft_cells", "bound": "hbm", "achieved": fft_gbs, "peak": PEAK["hbm"], "unit": "GB/s",
-                    "frac": fft_gbs / PEAK["hbm"], "traffic": p2p_traffic(FFT_COUNTERS, FFT_SOURCE),
+                    "frac": fft_gbs / PEAK["hbm"],
+                    "traffic": p2p_traffic(FFT_COUNTERS, FFT_SOURCE, st_mixed["leaves_per_axis"]),
                     "bytes_per_launch": fft_bytes,
                     "alone_avg_launch_ms": bd_mixed["m2l"],
                     "alone_achieved": fft_bytes / (bd_mixed["m2l"] * 1e-3) / 1e9,
