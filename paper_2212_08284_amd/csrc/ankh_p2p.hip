@@ -47,6 +47,7 @@ constexpr int NKIND = 2;    // blocks per source leaf
 constexpr int KMAX = 7;     // mutual tasks of a kind-0 block (kind 1: the other 6 and the leaf itself)
 constexpr int G = 16;       // lanes per group (one DPP row)
 constexpr int NG = 16;      // groups per block
+constexpr int kTList = 2048; // list positions whose target segment is tabulated per block
 
 // Per-launch constants of the radial functions: xi; gx, the factor that turns
 // r^2 into the argument of gauss(); pwc[n] = (2 xi^2)^n / (xi sqrt(pi)), the
@@ -370,6 +371,7 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs<R> a) {
     __shared__ double tpart[2][7][NG][G];   // target-side partials of the 16 groups (two passes)
     __shared__ int tfirst[KMAX], tcount[KMAX], tpre[KMAX + 1];   // target leaves: first atom, atoms, prefix
     __shared__ double tshift[KMAX][3];                            // their position shift, -d w
+    __shared__ unsigned char tseg[kTList];                        // segment of each list position
 
     const int tid = threadIdx.x;
     const int grp = tid >> 4, ln = tid & 15;
@@ -412,11 +414,16 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs<R> a) {
     const Radial<R> rc = a.rad;
 
     // target leaf (segment of the block's list) of list position f < ntg
-    auto segment = [&](int f) {
+    auto segment_scan = [&](int f) {
         int s = 0;
         while (s + 1 < ntl && f >= tpre[s + 1]) s++;
         return s;
     };
+    // the segment of each of the first kTList list positions, looked up once per block instead of in
+    // every pass (target loads and partial-sum stores)
+    for (int f = tid; f < min(ntg, kTList); f += 256) tseg[f] = (unsigned char)segment_scan(f);
+    __syncthreads();
+    auto segment = [&](int f) { return f < kTList ? (int)tseg[f] : segment_scan(f); };
     // sums the 16 groups' partials of pass tp (fixed order) and stores them in
     // the atoms' slots.  The partials alternate between two LDS buffers, so one
     // barrier per pass suffices: a buffer is rewritten two passes later, after

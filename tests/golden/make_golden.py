@@ -40,6 +40,19 @@ def make(name):
         r = oracle.ewald_sites(d["pos"], d["q"], d["mu"], d["theta"], d["edge"], sel, eps=1e-9,
                                alpha=0.1)
         np.savez_compressed(out, sel=sel, forces=r["forces"], dEdmu=r["dEdmu"], eps=1e-9)
+    elif name == "ionic_1000000_sites":
+        # forces and fields on 32 seeded ions of the 1,000,000-ion melt (charges + dipoles), one by one
+        d = synth.workload("ionic_1000000")
+        sel = np.sort(np.random.default_rng(44).choice(len(d["q"]), 32, replace=False))
+        r = oracle.ewald_sites(d["pos"], d["q"], d["mu"], d["theta"], d["edge"], sel, eps=1e-9,
+                               alpha=0.05)
+        np.savez_compressed(out, sel=sel, forces=r["forces"], dEdmu=r["dEdmu"], eps=1e-9)
+    elif name == "water_cutout_20k":
+        # the whole classical-Ewald solution on the corner cut-out (58.442 A) of the 3,000,000-molecule box
+        d = synth.water_cutout(synth.workload("water_9000000"), 58.442)
+        r = oracle.ewald(d["pos"], d["q"], d["mu"], d["theta"], edge=d["edge"], eps=1e-10, grad=True)
+        np.savez_compressed(out, energy=r["energy"], forces=r["forces"], dEdmu=r["dEdmu"], n=len(d["q"]),
+                            eps=1e-10)
     elif name == "water_288000_energy":
         d = synth.workload("water_288000")
         r = oracle.ewald(d["pos"], d["q"], d["mu"], d["theta"], edge=d["edge"], eps=1e-9, grad=False)
