@@ -477,15 +477,17 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs<R> a) {
                 ti = s0 + f;
             }
         }
-        // an absent target sits far away with zero moments: its pair terms vanish
-        t.x = iv ? a.x[ti] + shx : 1.0e4;
-        t.y = iv ? a.y[ti] + shy : 1.0e4;
-        t.z = iv ? a.z[ti] + shz : 1.0e4;
-        t.c = iv ? q[ti] : (R)0;
+        // an absent target sits far away with zero moments: its pair terms vanish.  Every array is
+        // read at a 32-bit unsigned offset from a uniform base (one address add per load).
+        const unsigned u = (unsigned)ti;
+        t.x = iv ? a.x[u] + shx : 1.0e4;
+        t.y = iv ? a.y[u] + shy : 1.0e4;
+        t.z = iv ? a.z[u] + shz : 1.0e4;
+        t.c = iv ? q[u] : (R)0;
 #pragma unroll
-        for (int c = 0; c < 3; c++) t.d[c] = (ORD >= 1 && iv) ? mu[c * n + ti] : (R)0;
+        for (int c = 0; c < 3; c++) t.d[c] = (ORD >= 1 && iv) ? (mu + (int64_t)c * n)[u] : (R)0;
 #pragma unroll
-        for (int c = 0; c < 6; c++) t.Q[c] = (ORD >= 2 && iv) ? th[c * n + ti] : (R)0;
+        for (int c = 0; c < 6; c++) t.Q[c] = (ORD >= 2 && iv) ? (th + (int64_t)c * n)[u] : (R)0;
     };
     int pbuf = 0;
 
