@@ -646,16 +646,19 @@ __global__ __launch_bounds__(256) void k_dft_x(double2 *X, double *D, const doub
 // by the same forward transform), so the permutation never needs undoing.  W = e^{-2 pi i / N},
 // tw[m] = W^m in LDS.  Element j of line `line` of tile `tile`: t[tile N^2 + (ALONG_V ? line N + j :
 // j N + line)].
-template <int N2, bool ALONG_V, bool INV>
+template <int N2, bool ALONG_V, bool INV, int ROW = 4 * N2>
 __device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
     constexpr int N = 4 * N2;
-    for (int task = threadIdx.x; task < ntile * N * 4; task += blockDim.x) {
+    constexpr int NL = ALONG_V ? N : ROW;     // lines per tile
+    for (int task = threadIdx.x; task < ntile * NL * 4; task += blockDim.x) {
         // consecutive threads: consecutive elements of the contiguous direction
         int tile, line, n1;
-        if (ALONG_V) { tile = task / (N * 4); const int r = task - tile * N * 4; line = r / 4; n1 = r % 4; }
-        else { tile = task / (N * 4); const int r = task - tile * N * 4; n1 = r / N; line = r % N; }
-        double2 *b = t + tile * N * N;
-        auto at = [&](int j) -> double2 & { return b[ALONG_V ? line * N + j : j * N + line]; };
+        tile = task / (NL * 4);
+        const int r = task - tile * NL * 4;
+        if (ALONG_V) { line = r / 4; n1 = r % 4; }
+        else { n1 = r / NL; line = r % NL; }
+        double2 *b = t + tile * N * ROW;
+        auto at = [&](int j) -> double2 & { return b[ALONG_V ? line * ROW + j : j * ROW + line]; };
         if (!INV) {
             double2 x[N2];
 #pragma unroll
@@ -696,15 +699,18 @@ __device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
     __syncthreads();
 }
 
-template <int N2, bool ALONG_V, bool INV>
+template <int N2, bool ALONG_V, bool INV, int ROW = 4 * N2>
 __device__ inline void tiles_phase2(double2 *t, int ntile) {
     constexpr int N = 4 * N2;
-    for (int task = threadIdx.x; task < ntile * N * N2; task += blockDim.x) {
+    constexpr int NL = ALONG_V ? N : ROW;
+    for (int task = threadIdx.x; task < ntile * NL * N2; task += blockDim.x) {
         int tile, line, k2;
-        if (ALONG_V) { tile = task / (N * N2); const int r = task - tile * N * N2; line = r / N2; k2 = r % N2; }
-        else { tile = task / (N * N2); const int r = task - tile * N * N2; k2 = r / N; line = r % N; }
-        double2 *b = t + tile * N * N;
-        auto at = [&](int j) -> double2 & { return b[ALONG_V ? line * N + j : j * N + line]; };
+        tile = task / (NL * N2);
+        const int r = task - tile * NL * N2;
+        if (ALONG_V) { line = r / N2; k2 = r % N2; }
+        else { k2 = r / NL; line = r % NL; }
+        double2 *b = t + tile * N * ROW;
+        auto at = [&](int j) -> double2 & { return b[ALONG_V ? line * ROW + j : j * ROW + line]; };
         const double2 a = at(4 * k2), bb = at(4 * k2 + 1), c = at(4 * k2 + 2), d = at(4 * k2 + 3);
         const double2 s0 = make_double2(a.x + c.x, a.y + c.y), s1 = make_double2(a.x - c.x, a.y - c.y);
         const double2 s2 = make_double2(bb.x + d.x, bb.y + d.y), s3 = make_double2(bb.x - d.x, bb.y - d.y);
@@ -719,15 +725,66 @@ __device__ inline void tiles_phase2(double2 *t, int ntile) {
 }
 
 // one axis of every tile: forward (natural -> digit-reversed) or inverse (digit-reversed -> natural)
-template <int N2, bool ALONG_V, bool INV>
+template <int N2, bool ALONG_V, bool INV, int ROW = 4 * N2>
 __device__ inline void tiles_axis(double2 *t, int ntile, const double2 *tw) {
     if (!INV) {
-        tiles_phase1<N2, ALONG_V, false>(t, ntile, tw);
-        tiles_phase2<N2, ALONG_V, false>(t, ntile);
+        tiles_phase1<N2, ALONG_V, false, ROW>(t, ntile, tw);
+        tiles_phase2<N2, ALONG_V, false, ROW>(t, ntile);
     } else {
-        tiles_phase2<N2, ALONG_V, true>(t, ntile);
-        tiles_phase1<N2, ALONG_V, true>(t, ntile, tw);
+        tiles_phase2<N2, ALONG_V, true, ROW>(t, ntile);
+        tiles_phase1<N2, ALONG_V, true, ROW>(t, ntile, tw);
     }
+}
+
+// all N^3 cells of one node frequency in LDS (dynamic: N^3 + N complex values; 128 KB at N = 20, used
+// where the device allows that much per block): the three axes forward, the product with D (MODE 0,
+// then the inverse of the three axes) or its real part to D (MODE 1).  40 B of HBM per value.
+constexpr int kAllThreads = 1024;
+
+template <int N2, int MODE>
+__global__ __launch_bounds__(kAllThreads) void k_rdft_all(double2 *X, double *D, const double2 *twg, int64_t ncell,
+                                                          double scale) {
+    constexpr int N = 4 * N2, NN = N * N, N3 = N * N * N, T = kAllThreads;
+    extern __shared__ double2 sm[];
+    double2 *t = sm, *tw = sm + N3;
+    const int64_t f = blockIdx.x;
+    double2 *xf = X + f * ncell;
+    const double *df = D + f * ncell;
+    for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
+    // eight loads in flight per thread (indices past the slab clamped to its last value, never stored)
+    for (int i0 = (int)threadIdx.x; i0 < N3; i0 += 8 * T) {
+        auto ld = [&](int k) { return xf[min(i0 + k * T, N3 - 1)]; };
+        const double2 a0 = ld(0), a1 = ld(1), a2 = ld(2), a3 = ld(3), a4 = ld(4), a5 = ld(5), a6 = ld(6), a7 = ld(7);
+        auto st = [&](int k, const double2 &a) {
+            if (i0 + k * T < N3) t[i0 + k * T] = a;
+        };
+        st(0, a0), st(1, a1), st(2, a2), st(3, a3), st(4, a4), st(5, a5), st(6, a6), st(7, a7);
+    }
+    __syncthreads();
+    tiles_axis<N2, true, false>(t, N, tw);          // z, in the N x-planes
+    tiles_axis<N2, false, false>(t, N, tw);         // y
+    tiles_axis<N2, false, false, NN>(t, 1, tw);     // x: one N x N^2 tile
+    if (MODE == 1) {
+        for (int i = threadIdx.x; i < N3; i += T) D[f * ncell + i] = t[i].x;
+        return;
+    }
+    for (int i0 = (int)threadIdx.x; i0 < N3; i0 += 8 * T) {
+        auto ld = [&](int k) { return df[min(i0 + k * T, N3 - 1)]; };
+        const double d0 = ld(0), d1 = ld(1), d2 = ld(2), d3 = ld(3), d4 = ld(4), d5 = ld(5), d6 = ld(6), d7 = ld(7);
+        auto mul = [&](int k, double d) {
+            const int i = i0 + k * T;
+            if (i < N3) {
+                const double s = d * scale;
+                t[i] = make_double2(t[i].x * s, t[i].y * s);
+            }
+        };
+        mul(0, d0), mul(1, d1), mul(2, d2), mul(3, d3), mul(4, d4), mul(5, d5), mul(6, d6), mul(7, d7);
+    }
+    __syncthreads();
+    tiles_axis<N2, false, true, NN>(t, 1, tw);
+    tiles_axis<N2, false, true>(t, N, tw);
+    tiles_axis<N2, true, true>(t, N, tw);
+    for (int i = threadIdx.x; i < N3; i += T) xf[i] = t[i];
 }
 
 // passes 1 / 3: block (f, x0 .. x0 + PB), the (y, z) planes
@@ -913,6 +970,17 @@ void split_passes(ankh_plan_s *pl, double2 *X, double *D, double scale) {
 
 template <int MODE>
 hipError_t cells(ankh_plan_s *pl, double2 *X, double *D, double scale) {
+    if (pl->fft_single) {
+        // one block per node frequency with all cells in LDS
+        const size_t shm = sizeof(double2) * ((size_t)pl->nleaf + pl->nside);
+        if (pl->nside == 12)
+            hipLaunchKernelGGL((k_rdft_all<3, MODE>), dim3((unsigned)pl->fft_nf), dim3(kAllThreads), shm, pl->stream, X, D,
+                               pl->d_fftTw, pl->nleaf, scale);
+        else
+            hipLaunchKernelGGL((k_rdft_all<5, MODE>), dim3((unsigned)pl->fft_nf), dim3(kAllThreads), shm, pl->stream, X, D,
+                               pl->d_fftTw, pl->nleaf, scale);
+        return hipGetLastError();
+    }
     if (pl->fft_dft && (pl->nside == 12 || pl->nside == 20 || pl->nside == 24)) {
         // 12 = 4 x 3, 20 = 4 x 5, 24 = 4 x 6 points per axis: two-phase transforms, PB tiles per block
         // (PB N^2 complex values + N roots within 64 KB)
@@ -966,6 +1034,32 @@ hipError_t cells(ankh_plan_s *pl, double2 *X, double *D, double scale) {
 }
 
 }  // namespace
+
+// the one-block cell transform for 12^3 and 20^3 grids, where the device grants its LDS (queried,
+// and the kernels' dynamic limit raised when above the default)
+bool fft_single_ok(int nside) {
+    if (nside != 12 && nside != 20) return false;
+    const size_t need = sizeof(double2) * ((size_t)nside * nside * nside + nside);
+    int device = 0, lim = 0;
+    if (hipGetDevice(&device) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (need > (size_t)lim) return false;
+    if (need > 65536) {
+        const int bytes = (int)need;
+        if (nside == 12) return true;
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rdft_all<5, 0>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rdft_all<5, 1>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+    }
+    return true;
+}
 
 bool fft_supported(int depth, int L, int le) {
     if (depth < 0 || depth > kMaxFftDepth || le < 2 || le > kMaxOrder || L < 2 || L > kMaxOrder) return false;

@@ -123,6 +123,7 @@ struct ankh_plan_s {
     int eq_order = 0, fft_pa = 0, fft_ph = 0;
     bool fft_split = false;       // cell transforms in three passes through HBM (n > 16, or on request)
     bool fft_dft = false;         // leaf grid not a power of two: direct DFTs along each axis (three passes)
+    bool fft_single = false;      // 12^3 / 20^3 grid: all cells of a node frequency in one block's LDS
     int64_t fft_nf = 0;
     double2 *d_fftB = nullptr, *d_fftW = nullptr, *d_fftX = nullptr;
     double2 *d_fftTw = nullptr;   // e^{-2 pi i k / n}: k < n/2 (radix 2) or k < n (direct DFT), three-pass path
@@ -180,6 +181,7 @@ hipError_t launch_build_cper(ankh_plan_s *pl);
 hipError_t launch_convert_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 // ANKH-FFT (ankh_fft.hip)
 bool fft_supported(int depth, int L, int eq_order);
+bool fft_single_ok(int nside);
 void fft_host_tables(int L, int eq_order, const double *cheb_nodes, std::vector<double2> &B, std::vector<double2> &W);
 void fft_host_roots(int nside, bool full, std::vector<double2> &tw);
 hipError_t launch_fft_build_D(ankh_plan_s *pl);    // plan time: the real spectrum D

@@ -342,6 +342,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
     // DFTs along each axis on a grid that is not a power of two
     pl->fft_dft = grid != 0;
     pl->fft_split = fft && !grid && pl->nside >= 2 && (pl->nside > 16 || (ov && ov->fft_split == 1));
+    pl->fft_single = fft && grid && !(ov && ov->fft_split == 1) && fft_single_ok(grid);
     pl->nleaf = (int64_t)pl->nside * pl->nside * pl->nside;
     size_t cells = 0;
     for (int e = 0; e <= pl->depth; e++) {
@@ -653,7 +654,7 @@ ankh_status ankh_get_stats(ankh_plan_t pl, ankh_plan_stats *out) {
     for (int e = 0; e < 8; e++) out->m2l_rank[e] = (e >= 1 && e <= pl->depth) ? pl->m2l_rank[e] : 0;
     out->far_field = pl->far_field;
     out->overlap = pl->overlap ? 1 : 0;
-    out->fft_split = pl->fft_split ? 1 : 0;
+    out->fft_split = (pl->fft_split || (pl->fft_dft && !pl->fft_single)) ? 1 : 0;
     out->eq_order = pl->far_field == ANKH_FAR_FFT ? pl->eq_order : 0;
     out->near_pairs = -1;
     if (pl->last_kind) {

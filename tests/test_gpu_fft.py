@@ -97,16 +97,20 @@ def test_fft_stage_parity_with_reference(ak, depth, order, eq, kind, split):
     pl.close()
 
 
-@pytest.mark.parametrize("leaves,order,eq,kind", [(3, 4, 4, "qmt"), (5, 4, 4, "qm"), (6, 3, 5, "q"),
-                                                  (12, 4, 4, "qm")])
-def test_fft_stage_parity_any_leaf_grid(ak, leaves, order, eq, kind):
+@pytest.mark.parametrize("leaves,order,eq,kind,split", [(3, 4, 4, "qmt", False), (5, 4, 4, "qm", False),
+                                                        (6, 3, 5, "q", False), (12, 4, 4, "qm", False),
+                                                        (12, 4, 4, "qmt", True)])
+def test_fft_stage_parity_any_leaf_grid(ak, leaves, order, eq, kind, split):
     """A leaf grid that is not an octree level (3, 5, 6 per axis: direct DFTs along the cell axes; 12:
-    the 4 x 3 two-phase transforms that 20 and 24 also use; lexicographic pair-kernel order) against
-    the NumPy transcription on the same grid."""
+    the 4 x 3 two-phase transforms that 20 and 24 also use, all cells of a node frequency in one
+    block, or in three passes through memory on request; lexicographic pair-kernel order) against the
+    NumPy transcription on the same grid."""
     d = _system(kind)
-    pl, e, F, G = _run(ak, d, leaves=leaves, order=order, images=3, eq_order=eq)
+    pl, e, F, G = _run(ak, d, leaves=leaves, order=order, images=3, eq_order=eq, fft_split=split)
     st = pl.stats
     assert st["leaves_per_axis"] == leaves and st["depth"] == -1
+    if leaves == 12:
+        assert st["fft_split"] == int(split)
     terms = pl.last_terms()
     r = ankh_ref.evaluate(d["pos"], d["q"], d["mu"], d["theta"], d["edge"], 0, st["order"], st["xi"],
                           st["images"], grad=True, far="fft", eq_order=eq, leaves=leaves)
@@ -151,6 +155,26 @@ def test_fft_water_288000_other_grids(ak, leaves):
         assert rel_rms(F[sel], g["forces"]) <= 1e-5
         assert rel_rms(G[sel], g["dEdmu"]) <= 1e-4
         assert rel_rms(Fm[sel], g["forces"]) <= 1e-4
+
+
+def test_fft_20_cells_one_block_vs_three_passes(ak):
+    """The 20^3 grid of the benchmark box with the cells of each node frequency in one block (where the
+    device grants the 128 KB of LDS this takes) and in three passes: the same transform, so the two
+    agree to rounding (the accuracy of this grid against the oracle: the full-size test)."""
+    d = synth.workload("water_9000")
+    res = {}
+    for split in (False, True):
+        pl, e, F, G = _run(ak, d, eps=1e-7, leaves=20, fft_split=split)
+        st = pl.stats
+        assert st["leaves_per_axis"] == 20
+        if split:
+            assert st["fft_split"] == 1
+        res[split] = (e, F, G, st["fft_split"])
+        pl.close()
+    (e0, F0, G0, s0), (e1, F1, G1, _) = res[False], res[True]
+    print(f"20^3 cell transforms: default path fft_split={s0}")
+    assert abs(e0 - e1) <= 1e-12 * abs(e1)
+    assert rel_rms(F0, F1) <= 1e-11 and rel_rms(G0, G1) <= 1e-11
 
 
 def test_fft_water_9000_fp64_vs_oracle(ak):
