@@ -327,11 +327,14 @@ def main():
                     "alone_achieved": fft_bytes / (bd_mixed["m2l"] * 1e-3) / 1e9,
                     "alone_frac": fft_bytes / (bd_mixed["m2l"] * 1e-3) / 1e9 / PEAK["hbm"],
                     "avg_launch_ms": sm["m2l"],
+                    "passes": 3 if st_mixed["fft_split"] else 1,
                     "note": f"ANKH-FFT cell transforms (stage 4): {nf} kept node frequencies x {nleaf} leaves, each "
                             "read and written once as complex float64 and multiplied by the real spectrum (float64): "
-                            "the algorithmic bytes.  Beyond 16^3 leaves, and on grids that are not powers of two, "
-                            "the transforms run in three passes through HBM (2.6x these bytes); traffic is the "
-                            "counters' sum over the stage's launches"}
+                            "the algorithmic bytes.  " + (
+                                "On this grid the transforms run in three passes through HBM (each value read and "
+                                "written once per pass)" if st_mixed["fft_split"] else
+                                "On this grid all cells of a node frequency sit in one block's LDS (one pass)") +
+                            "; traffic is the counters' sum over the stage's launches"}
     roof, other = (p2p_roof, m2l_roof) if sm["p2p"] >= sm["m2l"] else (m2l_roof, p2p_roof)
 
     line = {

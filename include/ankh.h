@@ -95,8 +95,10 @@ typedef struct {
     int32_t leaves;     /* ANKH-FFT: leaves per axis of its single-level grid, 1..40 or a power of two up
                            to 64 (any count: the grid need not be an octree level); 0 = 2^depth */
     int32_t fft_split;  /* ANKH-FFT: 1 = the cell transforms in three passes through HBM even when one
-                           block holds the cells of a node frequency (the path of depths 5 and 6, for
-                           testing it at small depths); 0 = only when needed */
+                           block holds the cells of a node frequency (the path of depths 5 and 6 and of
+                           24 leaves per axis, for testing it on smaller grids); 0 = only when needed
+                           (12 and 20 leaves per axis: one block if the device grants 128 KB of LDS per
+                           block, else three passes) */
     int32_t overlap;    /* far-field chain beside the pair kernel on the plan's second stream: 1 = yes,
                            2 = no (every stage in sequence on the plan's stream), 0 = auto (yes) */
 } ankh_overrides;
@@ -109,7 +111,8 @@ typedef struct {
  *                 equispaced grid per leaf, and every non-adjacent leaf pair, far images included,
  *                 through one 6D convolution evaluated by FFT (matrix factorisation, diagonalisation
  *                 and real-spectrum passages).  Needs depth <= 6 (auto depth is capped there; up
- *                 to depth 4 the cell transforms of a node frequency run in one block, beyond in
+ *                 to depth 4, and on grids of 12 and 20 leaves per axis where the device grants
+ *                 the LDS, the cell transforms of a node frequency run in one block, otherwise in
  *                 three passes through HBM) and 2 eq_order - 1 node frequencies per axis within
  *                 the per-block LDS budget (eq_order <= 8 at order <= 8).  The near field, P2M,
  *                 L2P, self and background terms are those of ANKH-FMM; stage 3 of the timing
