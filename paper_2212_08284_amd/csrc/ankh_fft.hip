@@ -291,56 +291,59 @@ __global__ __launch_bounds__(256) void k_fft_cells(double2 *X, double *D, int64_
 }
 
 // ---- per evaluation, equispaced order = Chebyshev order (pa = 2L - 1, ph = L) --
-// Four consecutive leaves per block (the leaves of one XCD are consecutive, so
-// each row X[f][.] receives 64-byte runs), each line of an axis held in
-// registers by one thread, B read with uniform addresses (scalar loads).
+// Consecutive leaves per block (the blocks of one XCD take consecutive leaves),
+// each spectrum row X[f][.] written or read in runs of one value per leaf: the
+// forward transform takes eight leaves (128-byte runs; 512 threads, the x stage
+// through LDS, y and z fused in registers), the inverse four (64-byte runs; eight
+// per block made it slower at its larger LDS footprint).  B is read from LDS where
+// its row varies across lanes, with uniform addresses otherwise.
 constexpr int kCB = 4;
+constexpr int kCF = 8, kFT = 512;
 
 template <int L>
-__global__ __launch_bounds__(256) void k_fft_nodes_fwd_t(const double *Q, int nup, const double2 *B, double2 *X,
+__global__ __launch_bounds__(kFT) void k_fft_nodes_fwd_t(const double *Q, int nup, const double2 *B, double2 *X,
                                                          int64_t ncell) {
-    constexpr int PA = 2 * L - 1, PH = L, NQ = L * L * L, NT2 = PA * PA * L;
-    __shared__ double sQ[kCB][NQ];
-    __shared__ double2 T2[kCB][NT2];
-    const int64_t c0 = xcd_leaf(blockIdx.x, ncell / kCB) * kCB;
+    constexpr int PA = 2 * L - 1, PH = L, NQ = L * L * L, NT1 = PA * L * L;
+    __shared__ double sQ[kCF][NQ];
+    __shared__ double2 T1[kCF][NT1];
+    __shared__ double2 sB[PA * L];
+    const int64_t c0 = xcd_leaf(blockIdx.x, ncell / kCF) * kCF;
     const int t = threadIdx.x;
-    for (int i = t; i < kCB * NQ; i += 256) sQ[i / NQ][i % NQ] = Q[(c0 + i / NQ) * nup + i % NQ];
+    for (int i = t; i < kCF * NQ; i += kFT) sQ[i / NQ][i % NQ] = Q[(c0 + i / NQ) * nup + i % NQ];
+    for (int i = t; i < PA * L; i += kFT) sB[i] = B[i];
     __syncthreads();
-    // x and y: thread (cell, f1, k): t1[j] = sum_i B[f1][i] Q[i][j][k], T2[f1][f2][k] = sum_j B[f2][j] t1[j]
-    for (int o = t; o < kCB * PA * L; o += 256) {
-        const int cell = o / (PA * L), r = o - cell * PA * L, f1 = r / L, k = r - f1 * L;
-        double2 t1[L];
+    // x: thread (cell, f1, j, k): T1[f1][j][k] = sum_i B[f1][i] Q[i][j][k]
+    for (int o = t; o < kCF * NT1; o += kFT) {
+        const int cell = o / NT1, r = o - cell * NT1, f1 = r / (L * L), jk = r - f1 * L * L;
+        double re = 0, im = 0;
 #pragma unroll
-        for (int j = 0; j < L; j++) {
-            double re = 0, im = 0;
-#pragma unroll
-            for (int i = 0; i < L; i++) {
-                const double2 b = B[f1 * L + i];
-                const double q = sQ[cell][(i * L + j) * L + k];
-                re += b.x * q;
-                im += b.y * q;
-            }
-            t1[j] = make_double2(re, im);
+        for (int i = 0; i < L; i++) {
+            const double2 b = sB[f1 * L + i];
+            const double q = sQ[cell][i * L * L + jk];
+            re += b.x * q;
+            im += b.y * q;
         }
-#pragma unroll
-        for (int f2 = 0; f2 < PA; f2++) {
-            double re = 0, im = 0;
-#pragma unroll
-            for (int j = 0; j < L; j++) {
-                const double2 b = B[f2 * L + j];
-                re += b.x * t1[j].x - b.y * t1[j].y;
-                im += b.x * t1[j].y + b.y * t1[j].x;
-            }
-            T2[cell][(f1 * PA + f2) * L + k] = make_double2(re, im);
-        }
+        T1[cell][r] = make_double2(re, im);
     }
     __syncthreads();
-    // z, half spectrum: thread (line f1 f2, cell), the kCB cells of a line adjacent
-    for (int o = t; o < kCB * PA * PA; o += 256) {
-        const int cell = o % kCB, f12 = o / kCB;
+    // y and z, half spectrum: thread (line f1 f2, cell), the kCF cells of a line adjacent lanes:
+    // v[k] = sum_j B[f2][j] T1[f1][j][k], then X[f1 f2 f3] = sum_k B[f3][k] v[k]
+    for (int o = t; o < kCF * PA * PA; o += kFT) {
+        const int cell = o % kCF, f12 = o / kCF, f1 = f12 / PA, f2 = f12 - f1 * PA;
+        const double2 *t1 = &T1[cell][f1 * L * L];
         double2 v[L];
 #pragma unroll
-        for (int k = 0; k < L; k++) v[k] = T2[cell][f12 * L + k];
+        for (int k = 0; k < L; k++) v[k] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            const double2 b = sB[f2 * L + j];
+#pragma unroll
+            for (int k = 0; k < L; k++) {
+                const double2 u = t1[j * L + k];
+                v[k].x += b.x * u.x - b.y * u.y;
+                v[k].y += b.x * u.y + b.y * u.x;
+            }
+        }
 #pragma unroll
         for (int f3 = 0; f3 < PH; f3++) {
             double re = 0, im = 0;
@@ -1136,7 +1139,8 @@ hipError_t launch_fft_build_D(ankh_plan_s *pl) {
 // the register-blocked kernels for equispaced order = Chebyshev order <= 6 (four leaves per block
 // within 64 KB of LDS; at least 8 leaves), else the generic ones
 static bool fast_nodes(const ankh_plan_s *pl) {
-    return pl->eq_order == pl->order && pl->order >= 3 && pl->order <= 6 && pl->nleaf % (8 * kCB) == 0;
+    return pl->eq_order == pl->order && pl->order >= 3 && pl->order <= 6 && pl->nleaf % (8 * kCB) == 0 &&
+           pl->nleaf % kCF == 0;
 }
 
 #define ANKH_FFT_ORDERS(L, X) \
@@ -1151,7 +1155,7 @@ hipError_t launch_fft_forward(ankh_plan_s *pl) {
     const int L = pl->order, pa = pl->fft_pa;
     const double *Q = pl->d_M + pl->lv[pl->depth].cell0 * pl->nup;
     if (fast_nodes(pl)) {
-        const dim3 g((unsigned)(pl->nleaf / kCB)), b(256);
+        const dim3 g((unsigned)(pl->nleaf / kCF)), b(kFT);
 #define ANKH_FWD(LL) \
         hipLaunchKernelGGL(k_fft_nodes_fwd_t<LL>, g, b, 0, pl->stream, Q, pl->nup, pl->d_fftB, pl->d_fftX, pl->nleaf)
         ANKH_FFT_ORDERS(L, ANKH_FWD)
