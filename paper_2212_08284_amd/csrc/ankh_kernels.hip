@@ -220,14 +220,16 @@ template <int L, int ORD>
 __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, const double *tab, int nu, int nup,
                                              double hinv, double *Q, int64_t n) {
     constexpr int ND = ORD + 1;
-    constexpr int CH = 32;                 // atoms per LDS chunk
+    constexpr int CH = 64;                 // atoms per LDS chunk (a leaf of the planned grids: one chunk)
     constexpr int NJK = L * L;
     constexpr int NSL = 256 / NJK;         // atom slices
     constexpr int NMO = ORD == 0 ? 1 : (ORD == 1 ? 4 : 10);
+    constexpr int NS = CH * 3 * ND * L, NR = NSL * L * L * L;
     __shared__ double sH[L * L];
-    __shared__ double sS[CH][3][ND][L];
+    __shared__ double sBuf[NS > NR ? NS : NR];   // the chunk's 1D bases, then the slices' partial lines
     __shared__ double sMom[CH][NMO];
-    __shared__ double red[NSL][L * L * L];
+    auto sS = reinterpret_cast<double (*)[3][ND][L]>(sBuf);
+    auto red = reinterpret_cast<double (*)[L * L * L]>(sBuf);
     const int tid = threadIdx.x;
     const int64_t leaf = blockIdx.x;
     for (int t = tid; t < L * L; t += 256) sH[t] = tab[L + t];
@@ -245,8 +247,8 @@ __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, c
             const int64_t slot = s0 + c0 + a;
             const double xl = ax == 0 ? P.x[slot] : (ax == 1 ? P.y[slot] : P.z[slot]);
             cheb_basis<ND, L>(xl * hinv, hinv, sH, &sS[a][ax][0][0], L);
-        } else if (tid >= 128 && tid < 128 + m) {
-            const int a = tid - 128;
+        } else if (tid >= 3 * CH && tid < 3 * CH + m) {
+            const int a = tid - 3 * CH;
             const int64_t slot = s0 + c0 + a;
             double *mo = sMom[a];
             mo[0] = P.q[slot];
@@ -292,6 +294,7 @@ __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, c
             }
         }
     }
+    __syncthreads();                        // the bases are read; their storage takes the partial lines
     if (sl < NSL) {
 #pragma unroll
         for (int i = 0; i < L; i++) red[sl][i * NJK + jk] = acc[i];
