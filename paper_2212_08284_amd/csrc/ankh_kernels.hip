@@ -81,28 +81,53 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const double *pos, const
     if (valid) rank[i] = r;
 }
 
-// exclusive scan of the leaf counts (one block; m up to 8^7)
+// exclusive scan of the leaf counts in one block (offs[m] = total; totals fit int32, as offs does): each thread sums
+// a contiguous run of counts (eight loads in flight), the runs are scanned within each wave by shuffles
+// and across the 16 waves by the first wave
 __global__ __launch_bounds__(1024) void k_scan(const int32_t *count, int32_t *offs, int64_t m) {
-    __shared__ long long part[1024];
-    const int t = threadIdx.x;
+    __shared__ int wsum[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t per = (m + 1023) / 1024;
-    const int64_t b = t * per, e = (b + per < m) ? b + per : m;
-    long long s = 0;
-    for (int64_t i = b; i < e; i++) s += count[i];
-    part[t] = s;
+    const int64_t b = t * per < m ? t * per : m, e = b + per < m ? b + per : m;
+    int s = 0;
+    for (int64_t i0 = b; i0 < e; i0 += 8) {
+        int c[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) c[u] = count[i0 + u < e ? i0 + u : e - 1];
+#pragma unroll
+        for (int u = 0; u < 8; u++) s += i0 + u < e ? c[u] : 0;
+    }
+    int v = s;                              // inclusive scan over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(v, off, 64);
+        if (lane >= off) v += y;
+    }
+    if (lane == 63) wsum[w] = v;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        long long v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    if (w == 0) {
+        int x = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane < 16) wsum[lane] = x;     // inclusive totals of the waves
     }
-    long long base = part[t] - s;
-    for (int64_t i = b; i < e; i++) {
-        offs[i] = (int32_t)base;
-        base += count[i];
+    __syncthreads();
+    int base = v - s + (w > 0 ? wsum[w - 1] : 0);
+    for (int64_t i0 = b; i0 < e; i0 += 8) {
+        int c[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) c[u] = count[i0 + u < e ? i0 + u : e - 1];
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            if (i0 + u < e) {
+                offs[i0 + u] = base;
+                base += c[u];
+            }
     }
-    if (t == 1023) offs[m] = (int32_t)part[1023];
+    if (t == 1023) offs[m] = wsum[15];
 }
 
 __global__ void k_scatter(int64_t n, const int32_t *leaf, const int32_t *offs, const int32_t *rank, int32_t *perm) {
