@@ -649,10 +649,31 @@ __global__ __launch_bounds__(256) void k_dft_x(double2 *X, double *D, const doub
 // by the same forward transform), so the permutation never needs undoing.  W = e^{-2 pi i / N},
 // tw[m] = W^m in LDS.  Element j of line `line` of tile `tile`: t[tile N^2 + (ALONG_V ? line N + j :
 // j N + line)].
+// the N2-th roots of unity e^{-2 pi i m / N2} (= W^{4m}, W = e^{-2 pi i / (4 N2)}) as compile-time
+// constants: cos and sin of multiples of 60 and 72 degrees from their closed forms, rounded to double
+template <int N2> struct Roots;
+template <> struct Roots<3> {
+    static constexpr double re[3] = {1.0, -0.5, -0.5};
+    static constexpr double im[3] = {0.0, -0.8660254037844386, 0.8660254037844386};
+};
+template <> struct Roots<5> {
+    static constexpr double re[5] = {1.0, 0.30901699437494745, -0.8090169943749475, -0.8090169943749475,
+                                     0.30901699437494745};
+    static constexpr double im[5] = {0.0, -0.9510565162951535, -0.5877852522924731, 0.5877852522924731,
+                                     0.9510565162951535};
+};
+template <> struct Roots<6> {
+    static constexpr double re[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+    static constexpr double im[6] = {0.0, -0.8660254037844386, -0.8660254037844386, 0.0, 0.8660254037844386,
+                                     0.8660254037844386};
+};
+
 template <int N2, bool ALONG_V, bool INV, int ROW = 4 * N2>
 __device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
     constexpr int N = 4 * N2;
     constexpr int NL = ALONG_V ? N : ROW;     // lines per tile
+    // the N2-point transforms take their roots as constants, and each task reads its twiddles before
+    // its stores (the tile and the table share the LDS, so a table read after a store is issued again)
     for (int task = threadIdx.x; task < ntile * NL * 4; task += blockDim.x) {
         // consecutive threads: consecutive elements of the contiguous direction
         int tile, line, n1;
@@ -662,6 +683,9 @@ __device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
         else { n1 = r / NL; line = r % NL; }
         double2 *b = t + tile * N * ROW;
         auto at = [&](int j) -> double2 & { return b[ALONG_V ? line * ROW + j : j * ROW + line]; };
+        double2 wt[N2];                      // W^{n1 k2}, n1 k2 < N
+#pragma unroll
+        for (int k2 = 0; k2 < N2; k2++) wt[k2] = tw[n1 * k2];
         if (!INV) {
             double2 x[N2];
 #pragma unroll
@@ -671,11 +695,11 @@ __device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
                 double re = 0, im = 0;
 #pragma unroll
                 for (int n2 = 0; n2 < N2; n2++) {
-                    const double2 w = tw[(4 * n2 * k2) % N];
-                    re += x[n2].x * w.x - x[n2].y * w.y;
-                    im += x[n2].x * w.y + x[n2].y * w.x;
+                    const double wx = Roots<N2>::re[(n2 * k2) % N2], wy = Roots<N2>::im[(n2 * k2) % N2];
+                    re += x[n2].x * wx - x[n2].y * wy;
+                    im += x[n2].x * wy + x[n2].y * wx;
                 }
-                const double2 w = tw[(n1 * k2) % N];
+                const double2 w = wt[k2];
                 at(n1 + 4 * k2) = make_double2(re * w.x - im * w.y, re * w.y + im * w.x);
             }
         } else {
@@ -683,7 +707,7 @@ __device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
             double2 z[N2];
 #pragma unroll
             for (int k2 = 0; k2 < N2; k2++) {
-                const double2 v = at(n1 + 4 * k2), w = tw[(n1 * k2) % N];
+                const double2 v = at(n1 + 4 * k2), w = wt[k2];
                 z[k2] = make_double2(v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y);
             }
 #pragma unroll
@@ -691,9 +715,9 @@ __device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
                 double re = 0, im = 0;
 #pragma unroll
                 for (int k2 = 0; k2 < N2; k2++) {
-                    const double2 w = tw[(4 * n2 * k2) % N];
-                    re += z[k2].x * w.x + z[k2].y * w.y;
-                    im += z[k2].y * w.x - z[k2].x * w.y;
+                    const double wx = Roots<N2>::re[(n2 * k2) % N2], wy = Roots<N2>::im[(n2 * k2) % N2];
+                    re += z[k2].x * wx + z[k2].y * wy;
+                    im += z[k2].y * wx - z[k2].x * wy;
                 }
                 at(n1 + 4 * n2) = make_double2(re, im);
             }
