@@ -695,12 +695,18 @@ __device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
                 double re = 0, im = 0;
 #pragma unroll
                 for (int n2 = 0; n2 < N2; n2++) {
+                    if ((n2 * k2) % N2 == 0) {         // root 1
+                        re += x[n2].x;
+                        im += x[n2].y;
+                        continue;
+                    }
                     const double wx = Roots<N2>::re[(n2 * k2) % N2], wy = Roots<N2>::im[(n2 * k2) % N2];
                     re += x[n2].x * wx - x[n2].y * wy;
                     im += x[n2].x * wy + x[n2].y * wx;
                 }
                 const double2 w = wt[k2];
-                at(n1 + 4 * k2) = make_double2(re * w.x - im * w.y, re * w.y + im * w.x);
+                at(n1 + 4 * k2) = k2 == 0 ? make_double2(re, im)
+                                          : make_double2(re * w.x - im * w.y, re * w.y + im * w.x);
             }
         } else {
             // inverse of phase 1: z[n1 + 4 k2] times conj W^{n1 k2}, then the conjugate N2-point transform
@@ -708,13 +714,18 @@ __device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
 #pragma unroll
             for (int k2 = 0; k2 < N2; k2++) {
                 const double2 v = at(n1 + 4 * k2), w = wt[k2];
-                z[k2] = make_double2(v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y);
+                z[k2] = k2 == 0 ? v : make_double2(v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y);
             }
 #pragma unroll
             for (int n2 = 0; n2 < N2; n2++) {
                 double re = 0, im = 0;
 #pragma unroll
                 for (int k2 = 0; k2 < N2; k2++) {
+                    if ((n2 * k2) % N2 == 0) {         // root 1
+                        re += z[k2].x;
+                        im += z[k2].y;
+                        continue;
+                    }
                     const double wx = Roots<N2>::re[(n2 * k2) % N2], wy = Roots<N2>::im[(n2 * k2) % N2];
                     re += z[k2].x * wx + z[k2].y * wy;
                     im += z[k2].y * wx - z[k2].x * wy;
