@@ -365,23 +365,34 @@ __global__ __launch_bounds__(256) void k_fft_nodes_inv_t(const double2 *X, const
     __shared__ double2 U[kCB][NU];
     const int64_t c0 = xcd_leaf(blockIdx.x, ncell / kCB) * kCB;
     const int t = threadIdx.x;
-    // z: thread (line f1 f2, cell): U[f1][f2][k] = sum_f3 w(f3) conj(B[f3][k]) X[f1 f2 f3]
-    for (int o = t; o < kCB * PA * PA; o += 256) {
-        const int cell = o % kCB, f12 = o / kCB;
-        double2 x[PH];
+    // z: thread (line f1 f2, cell): U[f1][f2][k] = sum_f3 w(f3) conj(B[f3][k]) X[f1 f2 f3]; two lines
+    // per thread and round, the loads of both issued first (a second line past the end reads the
+    // last line again and is not stored)
+    constexpr int NZ = kCB * PA * PA;
+    for (int o0 = t; o0 < NZ; o0 += 512) {
+        double2 x[2][PH];
 #pragma unroll
-        for (int f3 = 0; f3 < PH; f3++) x[f3] = X[(int64_t)(f12 * PH + f3) * ncell + c0 + cell];
+        for (int h = 0; h < 2; h++) {
+            const int o = min(o0 + 256 * h, NZ - 1), cell = o % kCB, f12 = o / kCB;
 #pragma unroll
-        for (int k = 0; k < L; k++) {
-            double re = 0, im = 0;
+            for (int f3 = 0; f3 < PH; f3++) x[h][f3] = X[(int64_t)(f12 * PH + f3) * ncell + c0 + cell];
+        }
 #pragma unroll
-            for (int f3 = 0; f3 < PH; f3++) {
-                const double w = f3 == 0 ? 1.0 : 2.0;           // pa odd: no unpaired frequency besides 0
-                const double2 v = cmulc(B[f3 * L + k], x[f3]);
-                re += w * v.x;
-                im += w * v.y;
+        for (int h = 0; h < 2; h++) {
+            const int o = o0 + 256 * h, cell = o % kCB, f12 = o / kCB;
+            if (o >= NZ) break;
+#pragma unroll
+            for (int k = 0; k < L; k++) {
+                double re = 0, im = 0;
+#pragma unroll
+                for (int f3 = 0; f3 < PH; f3++) {
+                    const double w = f3 == 0 ? 1.0 : 2.0;       // pa odd: no unpaired frequency besides 0
+                    const double2 v = cmulc(B[f3 * L + k], x[h][f3]);
+                    re += w * v.x;
+                    im += w * v.y;
+                }
+                U[cell][f12 * L + k] = make_double2(re, im);
             }
-            U[cell][f12 * L + k] = make_double2(re, im);
         }
     }
     __syncthreads();
