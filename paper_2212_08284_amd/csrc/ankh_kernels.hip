@@ -44,8 +44,9 @@ __global__ void k_to_f32(const double *s, float *d, int64_t n) {
 // are checked here, the higher moments in the gather, which reads them anyway.
 // The lanes of a wave that fall into the same leaf take their ranks from one atomic add (inputs in
 // spatial order put a wave's atoms into a few leaves; the segment sort fixes the in-leaf order
-// afterwards, so which lane gets which rank does not matter).  After 8 distinct leaves the rest add
-// one by one, which bounds the loop for inputs in random order.
+// afterwards, so which lane gets which rank does not matter).  The groups of up to 8 distinct leaves
+// are found first and their leaders add in one atomic instruction, together with the lanes left
+// over (one each), so a wave waits for one atomic round trip.
 __global__ __launch_bounds__(256) void k_bin(int64_t n, const double *pos, const double *q, double rB, double edge,
                                              double w, int nside, int32_t *leaf, int32_t *count, int32_t *rank,
                                              int32_t *err) {
@@ -66,19 +67,27 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const double *pos, const
     }
     const int lane = (int)__lane_id();
     unsigned long long pending = __ballot(valid);
-    int r = 0;
+    int leader_of = lane, cnt = 1, off = 0;        // a lane left over is its own group of one
+    bool adds = false;
     for (int round = 0; round < 8 && pending; round++) {
         const int leader = __ffsll((long long)pending) - 1;
         const int lid = __shfl(id, leader);
         const unsigned long long same = __ballot(id == lid) & pending;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&count[lid], (int)__popcll(same));
-        base = __shfl(base, leader);
-        if ((same >> lane) & 1ull) r = base + (int)__popcll(same & ((1ull << lane) - 1ull));
+        if ((same >> lane) & 1ull) {
+            leader_of = leader;
+            off = (int)__popcll(same & ((1ull << lane) - 1ull));
+        }
+        if (lane == leader) {
+            adds = true;
+            cnt = (int)__popcll(same);
+        }
         pending &= ~same;
     }
-    if ((pending >> lane) & 1ull) r = atomicAdd(&count[id], 1);
-    if (valid) rank[i] = r;
+    if ((pending >> lane) & 1ull) adds = true;
+    int base = 0;
+    if (valid && adds) base = atomicAdd(&count[id], cnt);
+    base = __shfl(base, leader_of);
+    if (valid) rank[i] = base + off;
 }
 
 // exclusive scan of the leaf counts in one block (offs[m] = total; totals fit int32, as offs does): each thread sums
