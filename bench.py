@@ -6,10 +6,17 @@ of 96,000 rigid 3-site molecules
 (288,000 atoms, edge 142.18 A, charges + dipoles + quadrupoles), inputs
 resident in HBM.  The mixed-precision path is the headline; the FP64 path is
 timed on the same inputs and plan parameters for the speed-up and the
-accuracy of the mixed path.  The far field is ANKH-FFT by default (forward
+accuracy of the mixed path, and both are compared with the stored
+classical-Ewald oracle values.  The far field is ANKH-FFT by default (forward
 node transform, cell FFTs with the spectrum, inverse node transform); with
 --far fmm it is the multilevel chain (M2M, M2L on every level, far-image root
-operator, L2L).  The other method is timed on the same input for comparison.
+operator, L2L).  The other method is timed on the same input for comparison
+(its M2L contraction gives the matrix-core roofline).
+
+Two more workloads are timed as sub-records: the 1,000,000-ion melt (mixed
+energy + forces) and the 9,000,000-atom water box (mixed and FP64 energy +
+forces + fields in one pass, checked on its 20,000-atom cut-out against the
+oracle).
 
 Prints one JSON line.
 """
@@ -17,8 +24,8 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import platform
 import sys
 import time
 
@@ -28,38 +35,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "E+forces evals/s per atom on 1 MI355X, mixed vs FP64, rel RMS force err"
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 # Algorithmic flops of the near field per UNORDERED pair of atoms (the mutual
-# form evaluates each pair once): the pair kernel's formula for charges +
-# dipoles + quadrupoles with the energy, the force, the field at both atoms and
-# the accumulation into both atoms, counted term by term from its source
-# (FMA = 2, add / mul = 1, erfc / exp / rsqrt = 1 each).
-P2P_FLOP_PER_UNORDERED_PAIR = 300.0
+# form evaluates each pair once), counted term by term from the pair kernel's
+# formula (FMA = 2, add / mul = 1, erfc / exp / rsqrt = 1 each), keyed by
+# (moment order, forces, fields):
+#  - charges + dipoles + quadrupoles with the energy, the force and the field at
+#    both atoms: 300;
+#  - charges + dipoles with the energy and the force: 83 (r^2, 1/r, 1/r^2, r: 8;
+#    B0 and the Gaussian: 5; B1..B3: 11; dipole invariants and c0..c2: 21;
+#    energy: 6; a1, a2: 6; sum c_n B_{n+1}: 5; force: 15; into both atoms: 6).
+P2P_FLOP_PER_UNORDERED_PAIR = {(2, True, True): 300.0, (1, True, False): 83.0}
 
 # HBM traffic of one P2P launch measured with rocprofv3 counters (FETCH_SIZE and
 # WRITE_SIZE, calibrated against a copy of known size) for the kernel source
 # with the recorded SHA-256; reported only while the source is unchanged.
-P2P_COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                            "p2p_water_288000_counters.txt")
-P2P_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2212_08284_amd", "csrc",
-                          "ankh_p2p.hip")
-FFT_COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                            "fft_cells_water_288000_counters.txt")
-FFT_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2212_08284_amd", "csrc",
-                          "ankh_fft.hip")
+P2P_COUNTERS = os.path.join(ROOT, "profiles", "p2p_water_288000_counters.txt")
+P2P_SOURCE = os.path.join(ROOT, "paper_2212_08284_amd", "csrc", "ankh_p2p.hip")
+FFT_COUNTERS = os.path.join(ROOT, "profiles", "fft_cells_water_288000_counters.txt")
+FFT_SOURCE = os.path.join(ROOT, "paper_2212_08284_amd", "csrc", "ankh_fft.hip")
 
 PEAK = {  # MI355X, TFLOP/s (hbm: GB/s)
     "hbm": 8000.0,
-    "valu_fp64": 78.6,    # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
-    "valu_fp32": 78.6,    # the same issue rate: packed FP32 (157.3) is not used by this build
-    "valu_fp32_packed": 157.3,
+    "valu_fp64": 78.6,           # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+    "valu_fp32": 157.3,          # the published FP32 vector peak (packed FP32, two lanes per instruction)
+    "valu_fp32_unpacked": 78.6,  # one FP32 FMA per lane and cycle: the rate of the instructions issued here
     "mfma_fp64": 78.6,
     "mfma_fp32": 157.3,
     "mfma_bf16": 2500.0,
 }
+PREC_NAME = {0: "f64", 1: "f32", 2: "bf16x3"}
 
 
-def p2p_traffic(counters=P2P_COUNTERS, source=P2P_SOURCE, leaves=None):
+def counter_traffic(counters=P2P_COUNTERS, source=P2P_SOURCE, leaves=None):
     """Calibrated HBM bytes per launch of a kernel from its committed counter summary, or None when
     the summary is missing, the kernel source has changed since, or it was taken on another leaf grid."""
     import hashlib
@@ -89,28 +98,134 @@ def rel_rms(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
 
 
-def timed_run(plan, args_dev, steps, warmup, torch):
-    """K timed steps with hipEvents around the M2L and pair-kernel stages only (every event idles the
-    device for a few microseconds); then K more steps with an event at every stage boundary for the
+def err_stats(a, ref):
+    """relative RMS, and the per-atom relative errors |a_i - ref_i| / |ref_i| (max and median)"""
+    d = np.linalg.norm(a - ref, axis=1)
+    r = np.linalg.norm(ref, axis=1)
+    per = d / np.maximum(r, 1e-300)
+    return {"rel_rms": float(np.sqrt(np.sum(d ** 2) / np.sum(r ** 2))), "max_atom_rel": float(per.max()),
+            "median_atom_rel": float(np.median(per))}
+
+
+def golden(name):
+    path = os.path.join(GOLDEN, f"{name}.npz")
+    return np.load(path) if os.path.exists(path) else None
+
+
+def dtype_name(st):
+    near, far = PREC_NAME[st["near_precision"]], PREC_NAME[st["far_precision"]]
+    if near == far:
+        return near
+    return f"{near} near field + {far} far field ({'ANKH-FFT' if st['far_field'] == 2 else 'ANKH-FMM'})"
+
+
+def timed_run(plan, args_dev, steps, warmup, torch, fields=True):
+    """K timed steps with hipEvents around the far-field contraction and pair-kernel stages only (every event
+    idles the device for a few microseconds); then K more steps with an event at every stage boundary for the
     stage breakdown.  Returns (seconds per step, stats of the timed steps, breakdown, outputs)."""
     for _ in range(warmup):
-        plan.energy_forces(*args_dev)
+        plan.energy_forces(*args_dev, fields=fields)
     torch.cuda.synchronize()
     plan.set_timing(2)
     t0 = time.perf_counter()
     out = None
     for _ in range(steps):
-        out = plan.energy_forces(*args_dev)
+        out = plan.energy_forces(*args_dev, fields=fields)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     stats = plan.get_stats()
     plan.set_timing(1)
     for _ in range(steps):
-        plan.energy_forces(*args_dev)
+        plan.energy_forces(*args_dev, fields=fields)
     breakdown = plan.get_stats()["stage_ms"]
     plan.set_timing(0)
     plan.sync()
     return dt, stats, breakdown, out
+
+
+def p2p_roofline(st, breakdown, key, leaves=None, traffic=True):
+    """The pair kernel against the FP32 vector peak: algorithmic flops per launch over its average hipEvent
+    duration in the timed steps (and alone, in the breakdown pass)."""
+    sm = st["stage_ms"]
+    unordered = st["near_pairs"] / 2.0
+    fpp = P2P_FLOP_PER_UNORDERED_PAIR[key]
+    flops = unordered * fpp
+    peak = PEAK["valu_fp32"] if st["near_precision"] == 1 else PEAK["valu_fp64"]
+    tf = flops / (sm["p2p"] * 1e-3) / 1e12
+    alone = flops / (breakdown["p2p"] * 1e-3) / 1e12
+    rec = {"kernel": "p2p", "bound": "alu", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
+           "traffic": counter_traffic(leaves=leaves) if traffic else None,
+           "flop_per_launch": flops, "unordered_pairs": unordered, "flop_per_unordered_pair": fpp,
+           "avg_launch_ms": sm["p2p"], "alone_avg_launch_ms": breakdown["p2p"], "alone_achieved": alone,
+           "alone_frac": alone / peak}
+    if st["near_precision"] == 1:
+        rec["frac_of_unpacked_fp32"] = tf / PEAK["valu_fp32_unpacked"]
+        rec["alone_frac_of_unpacked_fp32"] = alone / PEAK["valu_fp32_unpacked"]
+        rec["note"] = ("peak = the published FP32 vector rate, 157.3 TFLOP/s (packed FP32, two lanes per "
+                       "instruction); this build issues unpacked FP32 (one FMA per lane and cycle, 78.6 TFLOP/s: "
+                       "frac_of_unpacked_fp32).  In the timed steps the far-field chain runs beside the pair kernel "
+                       "on a second stream and shares its CUs (alone_*: the breakdown pass, one stream)")
+    return rec
+
+
+def m2l_roofline(st, breakdown, mode):
+    """The ANKH-FMM M2L contraction (stage 4) against the matrix-core peak of its datatype: algorithmic flops
+    (2 * 189 * r_e^2 per cell of level e, plus the basis change of compressed levels) over the stage time."""
+    flops = st["m2l_flops"]
+    peak = PEAK["mfma_bf16"] if mode == "mixed_bf16x3" else (PEAK["mfma_fp32"] if mode == "mixed" else
+                                                            PEAK["mfma_fp64"])
+    t = st["stage_ms"]["m2l"]
+    tf = flops / (t * 1e-3) / 1e12
+    alone = flops / (breakdown["m2l"] * 1e-3) / 1e12
+    rec = {"kernel": "m2l", "bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
+           "traffic": None, "flop_per_launch": flops, "avg_launch_ms": t, "alone_avg_launch_ms": breakdown["m2l"],
+           "alone_achieved": alone, "alone_frac": alone / peak, "ranks": st.get("m2l_rank"),
+           "note": "ANKH-FMM far-field contraction, all levels with the projection / expansion of compressed levels "
+                   "(stage 4); algorithmic flops per cell of level e: 2 * 189 * r_e^2 (r_e the kept rank) + "
+                   "4 * n_u * r_e for the basis change"}
+    if mode == "mixed_bf16x3":
+        rec["issued_frac"] = 3 * tf / peak
+        rec["note"] += "; the split-precision product issues three bf16 products per algorithmic one (issued_frac)"
+    return rec
+
+
+def fft_roofline(st, breakdown):
+    """The ANKH-FFT cell transforms (stage 4) against the HBM peak: 16 B read + 16 B written of spectrum and
+    the real spectrum read per kept node frequency and leaf (algorithmic bytes)."""
+    sm = st["stage_ms"]
+    pa = 2 * st["eq_order"] - 1
+    nf = pa * pa * (pa // 2 + 1)
+    nleaf = st["leaves_per_axis"] ** 3
+    cb = 8 if st["far_precision"] == 0 else 4
+    per = 4 * cb + cb
+    nbytes = float(per * nf * nleaf)
+    gbs = nbytes / (sm["m2l"] * 1e-3) / 1e9
+    alone = nbytes / (breakdown["m2l"] * 1e-3) / 1e9
+    return {"kernel": "fft_cells", "bound": "hbm", "achieved": gbs, "peak": PEAK["hbm"], "unit": "GB/s",
+            "frac": gbs / PEAK["hbm"],
+            "traffic": counter_traffic(FFT_COUNTERS, FFT_SOURCE, st["leaves_per_axis"]),
+            "bytes_per_launch": nbytes, "avg_launch_ms": sm["m2l"], "alone_avg_launch_ms": breakdown["m2l"],
+            "alone_achieved": alone, "alone_frac": alone / PEAK["hbm"], "passes": 3 if st["fft_split"] else 1,
+            "note": f"ANKH-FFT cell transforms (stage 4): {nf} kept node frequencies x {nleaf} leaves, each read and "
+                    f"written once as a complex {'float64' if cb == 8 else 'float32'} value and multiplied by the "
+                    "real spectrum: the algorithmic bytes; traffic is the counters' sum over the stage's launches"}
+
+
+def oracle_errors(E, F, G, name):
+    """Errors of one evaluation against the stored oracle values of a workload (energy when stored; forces and
+    fields of the stored atoms)."""
+    out = {}
+    ge = golden(f"{name}_energy")
+    if ge is not None:
+        out["rel_energy_err"] = float(abs(E - float(ge["energy"])) / abs(float(ge["energy"])))
+    gs = golden(f"{name}_sites")
+    if gs is not None:
+        sel = gs["sel"]
+        out["sites"] = int(len(sel))
+        out["forces"] = err_stats(F[sel], gs["forces"])
+        if G is not None:
+            out["fields"] = err_stats(G[sel], gs["dEdmu"])
+    return out
 
 
 def induce_run(plan, args_dev, alpha, tol, torch, dev, reps=3):
@@ -146,22 +261,115 @@ def derivs_run(plan, args_dev, torch, reps=5):
                     "the atoms"}, out
 
 
-def cpu_baseline(data, eps):
-    """The classical-Ewald oracle on a bounded cut-out of the same water box."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(data, eps, single_thread_water=False):
+    """The classical-Ewald oracle timed on this host's cores: on a bounded cut-out of the benchmark box
+    (the value), and on the 1000-charge box and the 9000-atom water box in full."""
     import oracle
     import synth
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     sub_edge = (2000 / synth.WATER_DENSITY) ** (1.0 / 3.0)     # ~2000 molecules, same density
     cut = synth.water_cutout(data, sub_edge)
-    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     n = len(cut["q"])
     t0 = time.perf_counter()
     oracle.ewald(cut["pos"], cut["q"], cut["mu"], cut["theta"], edge=cut["edge"], eps=eps, nthreads=nthreads)
     dt = time.perf_counter() - t0
+    full = {}
+    d1 = synth.workload("charges_1000")
+    for nt in (nthreads, 1):
+        t0 = time.perf_counter()
+        oracle.ewald(d1["pos"], d1["q"], edge=d1["edge"], eps=1e-8, grad=True, nthreads=nt)
+        full[f"charges_1000_threads{nt}_s"] = time.perf_counter() - t0
+    d2 = synth.workload("water_9000")
+    for nt in ((nthreads, 1) if single_thread_water else (nthreads,)):
+        t0 = time.perf_counter()
+        oracle.ewald(d2["pos"], d2["q"], d2["mu"], d2["theta"], edge=d2["edge"], eps=eps, grad=True, nthreads=nt)
+        full[f"water_9000_threads{nt}_s"] = time.perf_counter() - t0
+    full["note"] = ("whole classical-Ewald solutions: the 1000-charge box (energy + forces, accuracy 1e-8) and the "
+                    f"9000-atom water box (energy + forces + fields, accuracy {eps:g}); seconds of wall time")
     return {"value": n / dt, "unit": "atoms*evals/s", "cores": nthreads, "kind": "oracle",
             "sample": f"classical-Ewald oracle, energy+forces+fields, on a periodic cut-out of {n} atoms "
                       f"(whole molecules, edge {cut['edge']:.2f} A) of the benchmark box, accuracy {eps:g}; "
                       f"{dt:.2f} s wall; Ewald cost grows as N^1.5, so per-atom throughput at 288,000 atoms "
-                      f"would be lower"}
+                      f"would be lower",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(), "full_configs": full}
+
+
+def sub_ionic(ak, args, torch, dev, T):
+    """The 1,000,000-ion melt (charges + dipoles): mixed energy + forces, the pair-kernel roofline, and the
+    errors against the stored oracle ions."""
+    import synth
+    d = synth.workload("ionic_1000000")
+    n = len(d["q"])
+    a = (T(d["pos"]), T(d["q"]), T(d["mu"]), None)
+    pl = ak.Plan(n, 0.5 * d["edge"], args.eps, 1, args.mode)
+    t, st, bd, out = timed_run(pl, a, args.steps, args.warmup, torch, fields=False)
+    E, F = out[0].item(), out[1].cpu().numpy()
+    pl.close()
+    rec = {"workload": "ionic_1000000: 1,000,000 +-1 charges with dipoles, 0.1 atoms/A^3, energy+forces",
+           "n_atoms": n, "edge_A": d["edge"], "mode": args.mode, "dtype": dtype_name(st),
+           "ms_per_step": t * 1e3, "value": n / t, "unit": "atoms*evals/s", "far_field": st["far_field"],
+           "leaves_per_axis": st["leaves_per_axis"], "order": st["order"], "stage_ms": bd,
+           "roofline": p2p_roofline(st, bd, (1, True, False), traffic=False),
+           "vs_oracle": oracle_errors(E, F, None, "ionic_1000000")}
+    del a, out
+    torch.cuda.empty_cache()
+    return rec
+
+
+def sub_water9m(ak, args, torch, dev, T):
+    """The 9,000,000-atom water box: mixed and FP64 energy + forces + fields in one pass, the speed-up, and the
+    20,000-atom corner cut-out against the stored oracle solution."""
+    import synth
+    d = synth.workload("water_9000000")
+    n = len(d["q"])
+    a = (T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
+    rec = {"workload": "water_9000000: 3,000,000 rigid 3-site molecules, q+mu+Theta, energy+forces+fields",
+           "n_atoms": n, "edge_A": d["edge"]}
+    outs = {}
+    for prec in (args.mode, "fp64"):
+        pl = ak.Plan(n, 0.5 * d["edge"], args.eps, 2, prec)
+        t, st, bd, out = timed_run(pl, a, args.steps, args.warmup, torch)
+        outs[prec] = [x.cpu().numpy() for x in out]
+        key = "mixed" if prec != "fp64" else "fp64"
+        rec[key] = {"ms_per_step": t * 1e3, "value": n / t, "dtype": dtype_name(st), "far_field": st["far_field"],
+                    "leaves_per_axis": st["leaves_per_axis"], "order": st["order"], "plan_ms": st["plan_ms"],
+                    "stage_ms": bd, "roofline": p2p_roofline(st, bd, (2, True, True), traffic=False)}
+        pl.close()
+        del out
+        torch.cuda.empty_cache()
+    rec["speedup_mixed_vs_fp64"] = rec["fp64"]["ms_per_step"] / rec["mixed"]["ms_per_step"]
+    m, f = outs[args.mode], outs["fp64"]
+    rec["mixed_vs_fp64"] = {"rel_energy_err": float(abs(m[0][0] - f[0][0]) / abs(f[0][0])),
+                            "forces": err_stats(m[1], f[1]), "fields": err_stats(m[2], f[2])}
+    del a, outs
+    torch.cuda.empty_cache()
+    g = golden("water_cutout_20k")
+    if g is not None:
+        c = synth.water_cutout(d, 58.442)
+        nc = len(c["q"])
+        ca = (T(c["pos"]), T(c["q"]), T(c["mu"]), T(c["theta"]))
+        cut = {"n_atoms": nc, "edge_A": c["edge"]}
+        for prec in (args.mode, "fp64"):
+            pl = ak.Plan(nc, 0.5 * c["edge"], args.eps, 2, prec)
+            e, F, G = pl.energy_forces(*ca)
+            pl.sync()
+            pl.close()
+            cut["mixed" if prec != "fp64" else "fp64"] = {
+                "rel_energy_err": float(abs(e.item() - float(g["energy"])) / abs(float(g["energy"]))),
+                "forces": err_stats(F.cpu().numpy(), g["forces"]), "fields": err_stats(G.cpu().numpy(), g["dEdmu"])}
+        rec["cutout_vs_oracle"] = cut
+    return rec
 
 
 def main():
@@ -172,11 +380,15 @@ def main():
     ap.add_argument("--workload", default="water_288000")
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-single-thread-water", action="store_true",
+                    help="also time the oracle on the 9000-atom water box on one thread (minutes)")
     ap.add_argument("--mixed-only", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--mode", default="mixed_bf16x3", choices=["mixed", "mixed_bf16x3"],
                     help="precision mode of the headline (mixed) path")
     ap.add_argument("--no-induce", action="store_true", help="skip the induced-dipole solve")
     ap.add_argument("--no-derivs", action="store_true", help="skip the charge / quadrupole derivative timing")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 1,000,000-ion and 9,000,000-atom sub-records")
     ap.add_argument("--induce-tol", type=float, default=1e-6)
     ap.add_argument("--far", default="fft", choices=["fmm", "fft"],
                     help="far-field method of the timed path: ANKH-FFT (the variant the paper times) or "
@@ -230,20 +442,25 @@ def main():
     log(f"mixed plan: {pm.stats}")
     t_mixed, st_mixed, bd_mixed, out_mixed = timed_run(pm, args_dev, args.steps, args.warmup, torch)
     log(f"mixed: {t_mixed * 1e3:.3f} ms/step timed stages {st_mixed['stage_ms']} breakdown {bd_mixed}")
+    Em, Fm, Gm = [x.double().cpu().numpy() for x in out_mixed]
 
     far_other = None
+    roof_m2l = None
     if not args.no_far_compare:
         alt = "fft" if args.far == "fmm" else "fmm"
         pa = ak.Plan(n, rB, args.eps, 2, args.mode, far=alt, overlap=ovl, depth=args.depth)
         t_a, st_a, bd_a, out_a = timed_run(pa, args_dev, args.steps, args.warmup, torch)
-        Em, Fm, Gm = [x.double().cpu().numpy() for x in out_mixed]
         Ea, Fa, Ga = [x.double().cpu().numpy() for x in out_a]
         far_other = {"far": alt, "ms_per_step": t_a * 1e3, "value": n / t_a, "plan_ms": st_a["plan_ms"],
-                     "depth": st_a["depth"], "eq_order": st_a["eq_order"], "stage_ms": bd_a,
+                     "depth": st_a["depth"], "eq_order": st_a["eq_order"], "dtype": dtype_name(st_a), "stage_ms": bd_a,
                      "rel_energy_diff": float(abs(Ea[0] - Em[0]) / abs(Em[0])),
                      "rel_rms_force_diff": rel_rms(Fa, Fm), "rel_rms_field_diff": rel_rms(Ga, Gm)}
+        if alt == "fmm":
+            roof_m2l = m2l_roofline(st_a, bd_a, args.mode)
         pa.close()
         log(f"{alt}: {far_other}")
+    if args.far == "fmm":
+        roof_m2l = m2l_roofline(st_mixed, bd_mixed, args.mode)
 
     derivs = None
     if not args.no_derivs:
@@ -256,6 +473,7 @@ def main():
         induce = induce_run(pm, args_dev, synth.water_polarisabilities(n // 3), args.induce_tol, torch, dev)
         log(f"induce: { {k: v for k, v in induce.items() if k != '_mu'} }")
 
+    vs_oracle = {"mixed": oracle_errors(float(Em[0]), Fm, Gm, args.workload)}
     res = {}
     if not args.mixed_only:
         pf = ak.Plan(n, rB, args.eps, 2, "fp64", far=args.far, overlap=ovl, depth=args.depth, leaves=lv)
@@ -273,69 +491,27 @@ def main():
             induce["mixed_vs_fp64_rel_rms_mu_ind"] = rel_rms(induce.pop("_mu"), ind64.pop("_mu"))
             induce.pop("_mu", None)
         log(f"fp64: {t_fp64 * 1e3:.3f} ms/step breakdown {bd_fp64}")
-        Em, Fm, Gm = [x.double().cpu().numpy() for x in out_mixed]
         Ef, Ff, Gf = [x.double().cpu().numpy() for x in out_fp64]
+        vs_oracle["fp64"] = oracle_errors(float(Ef[0]), Ff, Gf, args.workload)
         res = {
             "fp64_ms_per_step": t_fp64 * 1e3,
             "fp64_value": n / t_fp64,
+            "fp64_dtype": dtype_name(st_fp64),
             "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
             "mixed_vs_fp64": {"rel_energy_err": float(abs(Em[0] - Ef[0]) / abs(Ef[0])),
-                              "rel_rms_force_err": rel_rms(Fm, Ff), "rel_rms_field_err": rel_rms(Gm, Gf)},
+                              "rel_rms_force_err": rel_rms(Fm, Ff), "rel_rms_field_err": rel_rms(Gm, Gf),
+                              "forces": err_stats(Fm, Ff), "fields": err_stats(Gm, Gf)},
             "fp64_stage_ms": bd_fp64,
+            "fp64_roofline": p2p_roofline(st_fp64, bd_fp64, (2, True, True), traffic=False),
         }
         pf.close()
+    log(f"vs oracle: {vs_oracle}")
 
     # roofline of the dominant kernel of the timed (mixed) path, from the live hipEvent stage timings
     sm = st_mixed["stage_ms"]
-    unordered = st_mixed["near_pairs"] / 2.0
-    p2p_flops = unordered * P2P_FLOP_PER_UNORDERED_PAIR
-    p2p_tf = p2p_flops / (sm["p2p"] * 1e-3) / 1e12
-    m2l_flops = st_mixed["m2l_flops"]
-    m2l_tf = m2l_flops / (sm["m2l"] * 1e-3) / 1e12
-    m2l_peak = PEAK["mfma_bf16"] if args.mode == "mixed_bf16x3" else PEAK["mfma_fp32"]
-    p2p_alone_tf = p2p_flops / (bd_mixed["p2p"] * 1e-3) / 1e12
-    p2p_roof = {"kernel": "p2p", "bound": "alu", "achieved": p2p_tf, "peak": PEAK["valu_fp32"],
-                "unit": "TFLOP/s", "frac": p2p_tf / PEAK["valu_fp32"],
-                "traffic": p2p_traffic(leaves=st_mixed["leaves_per_axis"]),
-                "flop_per_launch": p2p_flops, "unordered_pairs": unordered,
-                "flop_per_unordered_pair": P2P_FLOP_PER_UNORDERED_PAIR, "avg_launch_ms": sm["p2p"],
-                "frac_of_packed_fp32_peak": p2p_tf / PEAK["valu_fp32_packed"],
-                "alone_avg_launch_ms": bd_mixed["p2p"], "alone_achieved": p2p_alone_tf,
-                "alone_frac": p2p_alone_tf / PEAK["valu_fp32"],
-                "note": "peak = 256 CU x 4 SIMD x 16 lanes x FMA x 2.4 GHz (unpacked FP32, as issued); in the timed "
-                        "steps the far-field chain runs beside the pair kernel on a second stream and shares its "
-                        "CUs, so avg_launch_ms is longer than the kernel alone (alone_*: the breakdown pass, one "
-                        "stream)"}
-    m2l_roof = {"kernel": "m2l", "bound": "mfma", "achieved": m2l_tf, "peak": m2l_peak, "unit": "TFLOP/s",
-                "frac": m2l_tf / m2l_peak, "traffic": None, "flop_per_launch": m2l_flops, "avg_launch_ms": sm["m2l"],
-                "note": "algorithmic flops per cell of level e: 2 * 189 * r_e^2 (r_e the kept rank of the compressed "
-                        "operators, n_u if uncompressed) + 4 * n_u * r_e for the basis change; the BF16x3 split issues 3x "
-                        "the contraction flops", "ranks": st_mixed.get("m2l_rank")}
-    if args.far == "fft":
-        # stage 4 of ANKH-FFT is the cell-transform kernel: per launch it reads and writes the half
-        # spectrum (complex float64) and reads the real spectrum, 40 B per kept node frequency and leaf
-        pa = 2 * st_mixed["eq_order"] - 1
-        nf = pa * pa * (pa // 2 + 1)
-        nleaf = st_mixed["leaves_per_axis"] ** 3
-        fft_bytes = 40.0 * nf * nleaf
-        fft_gbs = fft_bytes / (sm["m2l"] * 1e-3) / 1e9
-        m2l_roof = {"kernel": "fft_cells", "bound": "hbm", "achieved": fft_gbs, "peak": PEAK["hbm"], "unit": "GB/s",
-                    "frac": fft_gbs / PEAK["hbm"],
-                    "traffic": p2p_traffic(FFT_COUNTERS, FFT_SOURCE, st_mixed["leaves_per_axis"]),
-                    "bytes_per_launch": fft_bytes,
-                    "alone_avg_launch_ms": bd_mixed["m2l"],
-                    "alone_achieved": fft_bytes / (bd_mixed["m2l"] * 1e-3) / 1e9,
-                    "alone_frac": fft_bytes / (bd_mixed["m2l"] * 1e-3) / 1e9 / PEAK["hbm"],
-                    "avg_launch_ms": sm["m2l"],
-                    "passes": 3 if st_mixed["fft_split"] else 1,
-                    "note": f"ANKH-FFT cell transforms (stage 4): {nf} kept node frequencies x {nleaf} leaves, each "
-                            "read and written once as complex float64 and multiplied by the real spectrum (float64): "
-                            "the algorithmic bytes.  " + (
-                                "On this grid the transforms run in three passes through HBM (each value read and "
-                                "written once per pass)" if st_mixed["fft_split"] else
-                                "On this grid all cells of a node frequency sit in one block's LDS (one pass)") +
-                            "; traffic is the counters' sum over the stage's launches"}
-    roof, other = (p2p_roof, m2l_roof) if sm["p2p"] >= sm["m2l"] else (m2l_roof, p2p_roof)
+    roof_p2p = p2p_roofline(st_mixed, bd_mixed, (2, True, True), leaves=st_mixed["leaves_per_axis"])
+    roof_far = fft_roofline(st_mixed, bd_mixed) if args.far == "fft" else roof_m2l
+    roof = roof_p2p if sm["p2p"] >= sm["m2l"] else roof_far
 
     line = {
         "metric": METRIC,
@@ -348,7 +524,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.mode == "mixed" else "f32+bf16x3",
+        "dtype": dtype_name(st_mixed),
         "mode": args.mode,
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: rigid 3-site water, q+mu+Theta, energy+forces+fields",
@@ -368,9 +544,15 @@ def main():
                          "pair kernel only.  ANKH-FFT stages: m2m = forward node transform, m2l = cell transforms "
                          "with the spectrum, l2l = inverse node transform + leaf energies, periodic = none",
         "roofline": roof,
-        "roofline_" + other["kernel"]: other,
     }
+    if roof is not roof_p2p:
+        line["roofline_p2p"] = roof_p2p
+    if args.far == "fft" and roof is not roof_far:
+        line["roofline_fft_cells"] = roof_far
+    if roof_m2l is not None:
+        line["roofline_m2l"] = roof_m2l
     line.update(res)
+    line["vs_oracle"] = vs_oracle
     if far_other is not None:
         line["far_other"] = far_other
     if derivs is not None:
@@ -379,8 +561,16 @@ def main():
         induce.pop("_mu", None)
         line["induce"] = induce
     pm.close()
+    del args_dev, out_mixed
+    torch.cuda.empty_cache()
+    if not args.no_configs:
+        line["configs"] = {}
+        line["configs"]["ionic_1000000"] = sub_ionic(ak, args, torch, dev, T)
+        log(f"ionic_1000000: {line['configs']['ionic_1000000']}")
+        line["configs"]["water_9000000"] = sub_water9m(ak, args, torch, dev, T)
+        log(f"water_9000000: {line['configs']['water_9000000']}")
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(data, args.eps)
+        line["cpu_baseline"] = cpu_baseline(data, args.eps, args.cpu_single_thread_water)
     print(json.dumps(line), flush=True)
 
 

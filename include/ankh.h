@@ -1,5 +1,6 @@
 /*
- * ankh.h - C ABI of the MI355X interpolated-Ewald library (ANKH-FMM hot path).
+ * ankh.h - C ABI of the MI355X interpolated-Ewald library (ANKH hot path:
+ * ANKH-FFT far field by default, ANKH-FMM on request).
  *
  * The library evaluates the periodic electrostatic energy of point charges,
  * dipoles and quadrupoles in a cubic box,
@@ -8,17 +9,22 @@
  *     D_u = q_u + mu_u . grad + Theta_u : grad grad,            (paper, eq. 1)
  *
  * (the x = y, t = 0 term omitted, tin-foil boundary), by the interpolated
- * Ewald strategy of the paper's ANKH-FMM section: with a small splitting
- * parameter xi the reciprocal Ewald term is negligible and the real-space
- * kernel H = erfc(xi r)/r (eq. for H) is summed over a truncated cube of
- * images.  That sum is split over the leaves of a perfect octree into a near
- * field (direct pair sums between adjacent leaves) and a far field handled by
- * Chebyshev interpolation: modified charges at the leaves (Alg. 2), upward
- * M2M, M2L over the interaction lists of every level (cells of the adjacent
- * images included), one root operator for all farther images (periodicity
- * section), then the self energy (eq. for E_self) and, for non-neutral
- * cells, the neutralising background.  Forces and fields come from the
- * adjoint of the same approximation (L2L, L2P, pair gradients).
+ * Ewald strategy of the paper: with a small splitting parameter xi the
+ * reciprocal Ewald term is negligible and the real-space kernel
+ * H = erfc(xi r)/r (eq. for H) is summed over a truncated cube of images.
+ * That sum is split over a uniform grid of leaves into a near field (direct
+ * pair sums between adjacent leaves) and a far field handled by Chebyshev
+ * interpolation: modified charges at the leaves (Alg. 2), then either
+ *  - ANKH-FFT (the ANKH-FFT section, Alg. 5; the automatic choice): the leaf
+ *    grids reinterpolated onto equispaced nodes and every non-adjacent leaf
+ *    pair, far images included, through one 6D convolution applied by FFT, or
+ *  - ANKH-FMM (the ANKH-FMM section, Alg. 3): upward M2M, M2L over the
+ *    interaction lists of every octree level (cells of the adjacent images
+ *    included), one root operator for all farther images (periodicity
+ *    section), downward L2L,
+ * then the self energy (eq. for E_self) and, for non-neutral cells, the
+ * neutralising background.  Forces and fields come from the adjoint of the
+ * same approximation (the transposed far-field chain, L2P, pair gradients).
  *
  * Units: Angstrom and elementary charge, Coulomb constant 1 (eq. 1 carries no
  * prefactor); energies in e^2/Angstrom.
@@ -89,7 +95,8 @@ typedef struct {
     double m2l_tol;     /* compressed M2L (the singular-value compression of the far-field operators):
                            singular values above m2l_tol x the largest are kept; 0 = auto (0.1 x
                            rel_accuracy, orders <= 7), NEGATIVE = no compression */
-    int32_t far_field;  /* far-field method, an ankh_far_field value; 0 = auto (ANKH_FAR_FMM) */
+    int32_t far_field;  /* far-field method, an ankh_far_field value; 0 = auto: ANKH_FAR_FFT wherever its grid
+                           and orders are supported (order <= 8, the automatic leaf grid), else ANKH_FAR_FMM */
     int32_t eq_order;   /* ANKH-FFT: equispaced nodes per axis of each leaf grid, 2..10; 0 = the
                            Chebyshev order */
     int32_t leaves;     /* ANKH-FFT: leaves per axis of its single-level grid, 1..40 or a power of two up
@@ -101,6 +108,17 @@ typedef struct {
                            block, else three passes) */
     int32_t overlap;    /* far-field chain beside the pair kernel on the plan's second stream: 1 = yes,
                            2 = no (every stage in sequence on the plan's stream), 0 = auto (yes) */
+    double force_accuracy; /* target relative RMS error of the forces and fields, in [1e-12, 1e-2]; 0 = none.
+                              rel_accuracy bounds the relative energy error (the accuracy measure of the
+                              paper's numerical results); the force error follows it at a workload-dependent
+                              multiple, a few times rel_accuracy on neutral molecules and up to ~30 times on
+                              unscreened ions.  With a force target the planner chooses xi, the image radius
+                              and the order for min(rel_accuracy, force_accuracy / 30). */
+    int64_t workspace_limit; /* most device bytes the plan may hold, its transient plan-time buffers and the
+                                buffers that ankh_energy_derivs / ankh_induce add on first use included;
+                                0 = no limit.  A plan beyond it fails with ANKH_ERR_OUT_OF_MEMORY (*out
+                                untouched); a first derivative / induced-dipole call beyond it returns
+                                ANKH_ERR_OUT_OF_MEMORY before any output is written. */
 } ankh_overrides;
 
 /* Far-field methods.
@@ -149,6 +167,9 @@ typedef struct {
     int32_t fft_split;         /* ANKH-FFT: 1 if the cell transforms run in three passes */
     int32_t leaves_per_axis;   /* leaves per axis of the finest grid (2^depth; for an ANKH-FFT grid
                                   that is not a power of two, depth reads -1) */
+    int32_t near_precision;    /* arithmetic of the near-field pair terms: 0 float64, 1 float32 */
+    int32_t far_precision;     /* arithmetic of the far-field chain (P2M to L2P): 0 float64, 1 float32,
+                                  2 the ANKH-FMM contraction in split bf16 (rest float64) */
 } ankh_plan_stats;
 
 /*

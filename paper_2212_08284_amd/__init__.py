@@ -5,7 +5,8 @@ kernels behind the C ABI declared in include/ankh.h.  The functions below
 carry the C names (`ankh_plan`, `ankh_energy`, `ankh_energy_forces`,
 `ankh_energy_derivs`, `ankh_induce`, ...);
 `Plan` wraps a plan handle and `AnkhEnergy` is the autograd function whose
-backward returns -g F for the positions and g dE/dmu for the dipoles.
+backward returns -g F for the positions, g dE/dmu for the dipoles and, when
+asked for, g dE/dq and g dE/dTheta.
 
 Device memory and streams come from PyTorch (ROCm): every array argument is
 a contiguous float64 tensor on the GPU.  There is no CPU fallback: the module
@@ -47,7 +48,8 @@ class _Overrides(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("order", ctypes.c_int32), ("images", ctypes.c_int32),
                 ("xi", ctypes.c_double), ("root_order", ctypes.c_int32), ("m2l_tol", ctypes.c_double),
                 ("far_field", ctypes.c_int32), ("eq_order", ctypes.c_int32), ("leaves", ctypes.c_int32),
-                ("fft_split", ctypes.c_int32), ("overlap", ctypes.c_int32)]
+                ("fft_split", ctypes.c_int32), ("overlap", ctypes.c_int32), ("force_accuracy", ctypes.c_double),
+                ("workspace_limit", ctypes.c_int64)]
 
 
 class _Stats(ctypes.Structure):
@@ -57,7 +59,8 @@ class _Stats(ctypes.Structure):
                 ("plan_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_int64), ("m2l_flops", ctypes.c_double),
                 ("near_pairs", ctypes.c_int64), ("stage_ms", ctypes.c_double * len(STAGES)), ("timed_evals", ctypes.c_int64),
                 ("m2l_rank", ctypes.c_int32 * 8), ("far_field", ctypes.c_int32), ("eq_order", ctypes.c_int32),
-                ("overlap", ctypes.c_int32), ("fft_split", ctypes.c_int32), ("leaves_per_axis", ctypes.c_int32)]
+                ("overlap", ctypes.c_int32), ("fft_split", ctypes.c_int32), ("leaves_per_axis", ctypes.c_int32),
+                ("near_precision", ctypes.c_int32), ("far_precision", ctypes.c_int32)]
 
 
 _lib = None
@@ -133,12 +136,15 @@ def ankh_plan(n_atoms: int, box_radius: float, rel_accuracy: float, max_order: i
               precision: int = ANKH_FP64, depth: int | None = None, order: int | None = None,
               images: int | None = None, xi: float | None = None, root_order: int | None = None,
               m2l_tol: float | None = None, stream=None, far_field: int = 0, eq_order: int | None = None,
-              overlap: bool | None = None, fft_split: bool = False, leaves: int | None = None):
+              overlap: bool | None = None, fft_split: bool = False, leaves: int | None = None,
+              force_accuracy: float | None = None, workspace_limit: int | None = None):
     """Create a plan; returns the opaque handle (ctypes.c_void_p).  m2l_tol: singular-value cutoff of the
     compressed M2L (None = automatic, negative = no compression).  far_field: ANKH_FAR_FMM / ANKH_FAR_FFT
     (0 = automatic); eq_order: equispaced nodes per axis of ANKH-FFT (None = the Chebyshev order); overlap:
     far-field chain beside the pair kernel (None = automatic); fft_split: ANKH-FFT cell transforms in three
-    passes even when one block could hold them (testing); leaves: ANKH-FFT leaves per axis (None = 2^depth)."""
+    passes even when one block could hold them (testing); leaves: ANKH-FFT leaves per axis (None = 2^depth);
+    force_accuracy: target relative RMS force error (None = only the energy target); workspace_limit: most
+    device bytes the plan may hold (None = no limit)."""
     L = load_library()
     if not torch.cuda.is_available():
         raise RuntimeError("no GPU: the interpolated-Ewald library runs on the GPU only")
@@ -147,7 +153,9 @@ def ankh_plan(n_atoms: int, box_radius: float, rel_accuracy: float, max_order: i
                     0 if root_order is None else int(root_order), 0.0 if m2l_tol is None else float(m2l_tol),
                     int(far_field), 0 if eq_order is None else int(eq_order), 0 if leaves is None else int(leaves),
                     1 if fft_split else 0,
-                    0 if overlap is None else (1 if overlap else 2))
+                    0 if overlap is None else (1 if overlap else 2),
+                    0.0 if force_accuracy is None else float(force_accuracy),
+                    0 if workspace_limit is None else int(workspace_limit))
     if stream is None:
         stream = torch.cuda.current_stream()
     h = ctypes.c_void_p()
@@ -229,7 +237,8 @@ class Plan:
 
     def __init__(self, n_atoms, box_radius, rel_accuracy=1e-6, max_order=2, precision="fp64", depth=None,
                  order=None, images=None, xi=None, root_order=None, m2l_tol=None, stream=None, far="auto",
-                 eq_order=None, overlap=None, fft_split=False, leaves=None):
+                 eq_order=None, overlap=None, fft_split=False, leaves=None, force_accuracy=None,
+                 workspace_limit=None):
         prec = ({"fp64": ANKH_FP64, "mixed": ANKH_MIXED, "mixed_bf16x3": ANKH_MIXED_BF16X3}[precision]
                 if isinstance(precision, str) else int(precision))
         far_field = ({"auto": ANKH_FAR_AUTO, "fmm": ANKH_FAR_FMM, "fft": ANKH_FAR_FFT}[far]
@@ -237,7 +246,8 @@ class Plan:
         self.n = int(n_atoms)
         self.max_order = int(max_order)
         self.handle = ankh_plan(n_atoms, box_radius, rel_accuracy, max_order, prec, depth, order, images, xi,
-                                root_order, m2l_tol, stream, far_field, eq_order, overlap, fft_split, leaves)
+                                root_order, m2l_tol, stream, far_field, eq_order, overlap, fft_split, leaves,
+                                force_accuracy, workspace_limit)
         self.stats = ankh_get_stats(self.handle)
 
     def _args(self, pos, q, mu, theta):
@@ -333,24 +343,39 @@ class Plan:
 
 
 class AnkhEnergy(torch.autograd.Function):
-    """E(pos, q, mu, theta) with the hand-written adjoint: dE/dpos = -F, dE/dmu = fields."""
+    """E(pos, q, mu, theta) with the hand-written adjoint: dE/dpos = -F, dE/dmu = the fields, and, when q or
+    theta require a gradient, dE/dq (site potentials) and the traceless dE/dTheta from ankh_energy_derivs."""
 
     @staticmethod
     def forward(ctx, pos, q, mu, theta, plan: Plan):
-        e, F, G = plan.energy_forces(pos.detach(), q.detach(), None if mu is None else mu.detach(),
-                                     None if theta is None else theta.detach(), fields=mu is not None)
-        ctx.save_for_backward(F, G if G is not None else F.new_zeros(0))
+        want_q = ctx.needs_input_grad[1]
+        want_th = theta is not None and ctx.needs_input_grad[3]
         ctx.has_mu = mu is not None
+        ctx.want_q, ctx.want_th = want_q, want_th
+        args = (pos.detach(), q.detach(), None if mu is None else mu.detach(),
+                None if theta is None else theta.detach())
+        if want_q or want_th:
+            out = plan.energy_derivs(*args, fields=ctx.has_mu, potentials=want_q, theta_grad=want_th)
+            F = out["forces"]
+            G = out.get("dEdmu")
+            ctx.save_for_backward(F, G if G is not None else F.new_zeros(0),
+                                  out["dEdq"] if want_q else F.new_zeros(0),
+                                  out["dEdtheta"] if want_th else F.new_zeros(0))
+            return out["energy"][0]
+        e, F, G = plan.energy_forces(*args, fields=ctx.has_mu)
+        ctx.save_for_backward(F, G if G is not None else F.new_zeros(0), F.new_zeros(0), F.new_zeros(0))
         return e[0]
 
     @staticmethod
     def backward(ctx, g):
-        F, G = ctx.saved_tensors
+        F, G, dq, dth = ctx.saved_tensors
         dpos = -g * F
         dmu = g * G if ctx.has_mu else None
-        return dpos, None, dmu, None, None
+        return dpos, (g * dq if ctx.want_q else None), dmu, (g * dth if ctx.want_th else None), None
 
 
 def energy(pos, q, mu=None, theta=None, plan: Plan | None = None):
-    """Differentiable energy (positions and dipoles)."""
+    """Differentiable energy in the positions, charges, dipoles and quadrupoles."""
+    if plan is None:
+        raise ValueError("energy() needs a Plan")
     return AnkhEnergy.apply(pos, q, mu, theta, plan)

@@ -169,6 +169,7 @@ extern "C" ankh_status ankh_induce(ankh_plan_t pl, const double *pos, const doub
     if (!pl->d_ind) {
         void *v = nullptr;
         const size_t bytes = work_doubles(pl->n) * sizeof(double);
+        if (pl->bytes_limit && pl->bytes + bytes > pl->bytes_limit) return ANKH_ERR_OUT_OF_MEMORY;
         if (hipMalloc(&v, bytes) != hipSuccess) {
             (void)hipGetLastError();
             return ANKH_ERR_OUT_OF_MEMORY;

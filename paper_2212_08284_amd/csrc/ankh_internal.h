@@ -23,8 +23,8 @@ constexpr int kNumOff = 343;         // slots for offsets d in [-3,3]^3 (316 use
 constexpr int kNumIL = 189;          // interaction-list length of every cell
 constexpr int kRedBlocks = 1024;     // first-stage blocks of the energy reduction (the epilogue)
 constexpr int kNumStages = 11;
-constexpr int kCperSlices = 16;
-constexpr int kNumSlots = 16;       // near-field partials per atom (see the pair kernel)     // column slices of the far-image root matvec
+constexpr int kCperSlices = 16;     // column slices of the far-image root matvec
+constexpr int kNumSlots = 16;       // near-field partials per atom (see the pair kernel)
 
 // index of offset d in [-3,3]^3
 __host__ __device__ constexpr int off_index(int dx, int dy, int dz) {
@@ -129,6 +129,7 @@ struct ankh_plan_s {
     double2 *d_fftTw = nullptr;   // e^{-2 pi i k / n}: k < n/2 (radix 2) or k < n (direct DFT), three-pass path
     double *d_fftD = nullptr;
     size_t bytes = 0;
+    size_t bytes_limit = 0;       // ankh_overrides.workspace_limit (0 = none)
 
     // statistics / timing
     double plan_ms = 0;

@@ -29,6 +29,7 @@ inline void ck(hipError_t e) {
 template <typename T>
 void dalloc(ankh_plan_s *pl, T **p, size_t count) {
     if (count == 0) count = 1;
+    if (pl->bytes_limit && pl->bytes + count * sizeof(T) > pl->bytes_limit) throw std::bad_alloc();
     void *v = nullptr;
     hipError_t e = hipMalloc(&v, count * sizeof(T));
     if (e != hipSuccess) {
@@ -277,7 +278,15 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         if (ov->fft_split < 0 || ov->fft_split > 1) return ANKH_ERR_INVALID_ARG;
         if (ov->leaves < 0 || ov->leaves > 64) return ANKH_ERR_INVALID_ARG;
         if (ov->leaves > 0 && ov->far_field != ANKH_FAR_FFT) return ANKH_ERR_INVALID_ARG;
+        if (!(ov->force_accuracy == 0 || (ov->force_accuracy >= 1e-12 && ov->force_accuracy <= 1e-2)))
+            return ANKH_ERR_INVALID_ARG;
+        if (ov->workspace_limit < 0) return ANKH_ERR_INVALID_ARG;
     }
+    // the accuracy the parameters are chosen for: the energy target, or a force target over the largest
+    // measured ratio of the relative RMS force error to the relative energy error (unscreened ions)
+    const double eps_plan = (ov && ov->force_accuracy > 0) ? std::min(rel_accuracy, ov->force_accuracy / 30.0)
+                                                          : rel_accuracy;
+    if (precision != ANKH_FP64 && eps_plan < 1e-7) return ANKH_ERR_ACCURACY_UNREACHABLE;
     auto t0 = std::chrono::steady_clock::now();
     ankh_plan_s *pl = new (std::nothrow) ankh_plan_s();
     if (!pl) return ANKH_ERR_OUT_OF_MEMORY;
@@ -288,10 +297,11 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
     pl->max_order = max_order;
     pl->precision = precision;
     pl->stream = static_cast<hipStream_t>(hip_stream);
+    pl->bytes_limit = ov ? (size_t)ov->workspace_limit : 0;
 
     // splitting parameter: the largest reciprocal weight exp(-(pi/(xi edge))^2)
     // equals eps/10, so the dropped reciprocal term stays below the target
-    const double s2 = std::log(10.0 / rel_accuracy);
+    const double s2 = std::log(10.0 / eps_plan);
     pl->xi = (ov && ov->xi > 0) ? ov->xi : kPi / (pl->edge * std::sqrt(s2));
     // image radius: pairs beyond the cube Z_p are >= p * edge apart, where erfc(xi p edge) <~ eps/10
     {
@@ -299,10 +309,29 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         int p = (int)std::ceil(sr / (pl->xi * pl->edge)) + 1;
         pl->images = (ov && ov->images > 0) ? ov->images : std::max(p, 2);
     }
-    pl->order = (ov && ov->order > 0) ? ov->order : order_for(rel_accuracy);
+    pl->order = (ov && ov->order > 0) ? ov->order : order_for(eps_plan);
     pl->nu = pl->order * pl->order * pl->order;
     pl->nup = (pl->nu + 31) / 32 * 32;   // row stride: a multiple of the M2L tile step
-    pl->far_field = (ov && ov->far_field == ANKH_FAR_FFT) ? ANKH_FAR_FFT : ANKH_FAR_FMM;
+    {
+        // automatic far field: ANKH-FFT (the variant the paper times) wherever its automatic leaf grid and
+        // orders are supported, else ANKH-FMM
+        int ff = ov ? ov->far_field : ANKH_FAR_AUTO;
+        if (ff == ANKH_FAR_AUTO) {
+            ff = ANKH_FAR_FMM;
+            const bool user_grid = ov && ov->depth >= 0;
+            const int eqo = (ov && ov->eq_order > 0) ? ov->eq_order : pl->order;
+            if (!user_grid) {
+                const int g = leaves_for(n_atoms, pl->nu);
+                int e = 0;
+                while ((1 << e) < g) e++;
+                const bool pow2 = (g & (g - 1)) == 0;
+                if (pl->order <= 8 && fft_supported(pow2 ? e : 0, pl->order, eqo)) ff = ANKH_FAR_FFT;
+            } else if (pl->order <= 8 && fft_supported(ov->depth, pl->order, eqo)) {
+                ff = ANKH_FAR_FFT;
+            }
+        }
+        pl->far_field = ff;
+    }
     const bool fft = pl->far_field == ANKH_FAR_FFT;
     pl->overlap = (ov && ov->overlap) ? ov->overlap == 1 : true;
     pl->depth = (ov && ov->depth >= 0) ? ov->depth : depth_for(n_atoms, pl->nu);
@@ -483,6 +512,8 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
             // scratch: the full float64 stack of a level, and room for the compression's
             // intermediate products or the compressed float64 stack
             double *tmp = nullptr, *work = nullptr, *kc = nullptr;
+            const size_t ntmp = 1 + (compress ? 1 : 0) + (compress && precision != ANKH_FP64 ? 1 : 0);
+            if (pl->bytes_limit && pl->bytes + ntmp * kper * sizeof(double) > pl->bytes_limit) throw std::bad_alloc();
             ck(hipMalloc((void **)&tmp, kper * sizeof(double)));
             if (compress) ck(hipMalloc((void **)&work, kper * sizeof(double)));
             if (compress && precision != ANKH_FP64) ck(hipMalloc((void **)&kc, kper * sizeof(double)));
@@ -588,11 +619,11 @@ ankh_status ankh_energy_derivs(ankh_plan_t pl, const double *pos, const double *
     ankh_status st = check_inputs(pl, pos, q, mu, theta);
     if (st != ANKH_OK) return st;
     if (!energy || (dE_dtheta && pl->max_order < 2)) return ANKH_ERR_INVALID_ARG;
-    if ((st = run(pl, pos, q, mu, theta, energy, forces, dE_dmu)) != ANKH_OK) return st;
-    if (!dE_dq && !dE_dtheta) return ANKH_OK;
-    if (!pl->d_mom) {
+    if ((dE_dq || dE_dtheta) && !pl->d_mom) {
+        // before the evaluation, so that a failed allocation leaves every output untouched
         void *v = nullptr;
         const size_t bytes = (size_t)7 * pl->n * sizeof(double);
+        if (pl->bytes_limit && pl->bytes + bytes > pl->bytes_limit) return ANKH_ERR_OUT_OF_MEMORY;
         if (hipMalloc(&v, bytes) != hipSuccess) {
             (void)hipGetLastError();
             return ANKH_ERR_OUT_OF_MEMORY;
@@ -600,6 +631,8 @@ ankh_status ankh_energy_derivs(ankh_plan_t pl, const double *pos, const double *
         pl->d_mom = static_cast<double *>(v);
         pl->bytes += bytes;
     }
+    if ((st = run(pl, pos, q, mu, theta, energy, forces, dE_dmu)) != ANKH_OK) return st;
+    if (!dE_dq && !dE_dtheta) return ANKH_OK;
     const int ord = theta ? 2 : (mu ? 1 : 0);
     if (launch_p2p_moments(pl, ord, pl->d_mom) != hipSuccess) return ANKH_ERR_HIP;
     if (launch_l2p_moments(pl, ord, pl->d_mom, dE_dq, dE_dtheta) != hipSuccess) return ANKH_ERR_HIP;
@@ -656,6 +689,9 @@ ankh_status ankh_get_stats(ankh_plan_t pl, ankh_plan_stats *out) {
     out->overlap = pl->overlap ? 1 : 0;
     out->fft_split = (pl->fft_split || (pl->fft_dft && !pl->fft_single)) ? 1 : 0;
     out->eq_order = pl->far_field == ANKH_FAR_FFT ? pl->eq_order : 0;
+    out->near_precision = pl->precision == ANKH_FP64 ? 0 : 1;
+    out->far_precision = pl->precision == ANKH_FP64 || pl->far_field == ANKH_FAR_FFT ? 0
+                         : (pl->precision == ANKH_MIXED_BF16X3 ? 2 : 1);
     out->near_pairs = -1;
     if (pl->last_kind) {
         std::vector<int32_t> offs(pl->nleaf + 1);

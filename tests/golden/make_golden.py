@@ -56,7 +56,13 @@ def make(name):
     elif name == "water_288000_energy":
         d = synth.workload("water_288000")
         r = oracle.ewald(d["pos"], d["q"], d["mu"], d["theta"], edge=d["edge"], eps=1e-9, grad=False)
-        np.savez_compressed(out, energy=r["energy"], eps=1e-9)
+        np.savez_compressed(out, energy=r["energy"], e_real=r["e_real"], e_rec=r["e_rec"],
+                            e_self=r["e_self"], e_bg=r["e_bg"], eps=1e-9)
+    elif name == "ionic_1000000_energy":
+        d = synth.workload("ionic_1000000")
+        r = oracle.ewald(d["pos"], d["q"], d["mu"], d["theta"], edge=d["edge"], eps=1e-9, grad=False)
+        np.savez_compressed(out, energy=r["energy"], e_real=r["e_real"], e_rec=r["e_rec"],
+                            e_self=r["e_self"], e_bg=r["e_bg"], eps=1e-9)
     else:
         raise KeyError(name)
     print(f"{name}: {time.time() - t:.1f} s -> {out}", flush=True)

@@ -1,4 +1,5 @@
-"""GPU parity of the HIP path (called through the C ABI via the binding).
+"""GPU parity of the HIP path with the ANKH-FMM far field (called through the C ABI via the binding;
+the ANKH-FFT far field, the automatic choice, has its own file and the full-size checks).
 
 * Stage parity against the NumPy transcription of the method (oracle/ankh_ref):
   same parameters, same approximation, so energy terms, leaf multipoles,
@@ -56,6 +57,7 @@ def _system(kind, seed=7):
 
 
 def _run(ak, d, eps=1e-6, prec="fp64", **ov):
+    ov.setdefault("far", "fmm")
     pl = ak.Plan(len(d["q"]), 0.5 * d["edge"], eps, 2, prec, **ov)
     e, F, G = pl.energy_forces(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
     pl.sync()
@@ -169,7 +171,7 @@ def test_energy_only_path_matches(ak):
 
 def test_stage_timing_modes(ak):
     d = _system("qmt")
-    pl = ak.Plan(len(d["q"]), 0.5 * d["edge"], 1e-6, 2, "fp64")
+    pl = ak.Plan(len(d["q"]), 0.5 * d["edge"], 1e-6, 2, "fp64", far="fmm")
     args = (T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
     for mode in (1, 2):
         pl.set_timing(mode)
@@ -202,7 +204,7 @@ def test_charges_1000_vs_oracle(ak):
     # 1000 +-1 charges in a 24 A box, FP64, energy at accuracy 1e-8
     d = synth.workload("charges_1000")
     g = np.load(os.path.join(GOLDEN, "charges_1000.npz"))
-    pl = ak.Plan(1000, 12.0, 1e-8, 0, "fp64")
+    pl = ak.Plan(1000, 12.0, 1e-8, 0, "fp64", far="fmm")
     e = pl.energy(T(d["pos"]), T(d["q"]))
     pl.sync()
     assert abs(e.item() - float(g["energy"])) <= 1e-6 * abs(float(g["energy"]))
@@ -250,7 +252,7 @@ def _away_from_faces(pos, edge, depth, h, count, seed):
 def test_adjoint_is_gradient_of_energy(ak):
     d = synth.water(300, seed=21)
     n = len(d["q"])
-    pl = ak.Plan(n, 0.5 * d["edge"], 1e-6, 2, "fp64")
+    pl = ak.Plan(n, 0.5 * d["edge"], 1e-6, 2, "fp64", far="fmm")
     pos, q, mu, th = T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"])
     e0, F, G = pl.energy_forces(pos, q, mu, th)
     pl.sync()
@@ -279,7 +281,7 @@ def test_adjoint_is_gradient_of_energy(ak):
 
 def test_autograd_function(ak):
     d = synth.water(100, seed=4)
-    pl = ak.Plan(len(d["q"]), 0.5 * d["edge"], 1e-6, 2, "fp64")
+    pl = ak.Plan(len(d["q"]), 0.5 * d["edge"], 1e-6, 2, "fp64", far="fmm")
     pos = T(d["pos"]).requires_grad_(True)
     mu = T(d["mu"]).requires_grad_(True)
     E = ak.energy(pos, T(d["q"]), mu, T(d["theta"]), plan=pl)
@@ -313,7 +315,7 @@ def test_nonneutral_and_tiny_systems_vs_oracle(ak, far):
 def test_latched_input_errors(ak):
     d = synth.water(50, seed=9)
     n = len(d["q"])
-    pl = ak.Plan(n, 0.5 * d["edge"], 1e-5, 2, "fp64")
+    pl = ak.Plan(n, 0.5 * d["edge"], 1e-5, 2, "fp64", far="fmm")
     pos = d["pos"].copy()
     pos[3, 1] = np.nan
     pl.energy(T(pos), T(d["q"]), T(d["mu"]), T(d["theta"]))
@@ -330,7 +332,7 @@ def test_latched_input_errors(ak):
     pl.energy(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
     pl.sync()
     # host-checked: a quadrupole array on a charges-only plan
-    pq = ak.Plan(n, 0.5 * d["edge"], 1e-5, 0, "fp64")
+    pq = ak.Plan(n, 0.5 * d["edge"], 1e-5, 0, "fp64", far="fmm")
     with pytest.raises(ak.AnkhError) as ei:
         pq.energy(T(d["pos"]), T(d["q"]), None, T(d["theta"]))
     assert ei.value.status == 1
@@ -360,7 +362,7 @@ def test_water_9000000_mixed_vs_fp64(ak):
     n = len(d["q"])
     out = {}
     for prec in ("fp64", "mixed_bf16x3"):
-        pl = ak.Plan(n, 0.5 * d["edge"], 1e-5, 2, prec)
+        pl = ak.Plan(n, 0.5 * d["edge"], 1e-5, 2, prec, far="fmm")
         e, F, G = pl.energy_forces(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
         pl.sync()
         out[prec] = (e.item(), F.cpu().numpy(), G.cpu().numpy())
