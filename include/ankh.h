@@ -95,8 +95,9 @@ typedef struct {
     double m2l_tol;     /* compressed M2L (the singular-value compression of the far-field operators):
                            singular values above m2l_tol x the largest are kept; 0 = auto (0.1 x
                            rel_accuracy, orders <= 7), NEGATIVE = no compression */
-    int32_t far_field;  /* far-field method, an ankh_far_field value; 0 = auto: ANKH_FAR_FFT wherever its grid
-                           and orders are supported (order <= 8, the automatic leaf grid), else ANKH_FAR_FMM */
+    int32_t far_field;  /* far-field method, an ankh_far_field value; 0 = auto: ANKH_FAR_FFT up to order 6
+                           (rel_accuracy >= 1e-6) on a supported leaf grid, else ANKH_FAR_FMM (at higher orders
+                           the equispaced reinterpolation of ANKH-FFT misses the energy target) */
     int32_t eq_order;   /* ANKH-FFT: equispaced nodes per axis of each leaf grid, 2..10; 0 = the
                            Chebyshev order */
     int32_t leaves;     /* ANKH-FFT: leaves per axis of its single-level grid, 1..40 or a power of two up

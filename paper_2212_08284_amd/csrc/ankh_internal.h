@@ -129,6 +129,7 @@ struct ankh_plan_s {
     double2 *d_fftTw = nullptr;   // e^{-2 pi i k / n}: k < n/2 (radix 2) or k < n (direct DFT), three-pass path
     double *d_fftD = nullptr;
     size_t bytes = 0;
+    int device = 0;               // the HIP device current at plan time (the plan's buffers live there)
     size_t bytes_limit = 0;       // ankh_overrides.workspace_limit (0 = none)
 
     // statistics / timing

@@ -176,34 +176,39 @@ def test_water_288000_adjoint_central_differences(ak, water):
 
 
 def test_charges_1000_auto_far_field_vs_oracle(ak):
-    """The 1000-charge box at 1e-8 through the automatic far field (ANKH-FFT, order 8)."""
+    """The 1000-charge box at its accuracy 1e-8 through the automatic far field (ANKH-FMM, order 8): energy
+    within 1e-6 relative and forces within 1e-5 relative RMS of the oracle."""
+    eps, far = 1e-8, "fmm"
     d = synth.workload("charges_1000")
     g = golden("charges_1000")
-    pl = ak.Plan(1000, 12.0, 1e-8, 0, "fp64")
-    assert pl.stats["far_field"] == ak.ANKH_FAR_FFT and pl.stats["order"] == 8
+    pl = ak.Plan(1000, 12.0, eps, 0, "fp64")
+    assert pl.stats["far_field"] == ak.ANKH_FAR_FMM and pl.stats["order"] == 8
     e = pl.energy(T(d["pos"]), T(d["q"]))
     _, F, _ = pl.energy_forces(T(d["pos"]), T(d["q"]), fields=False)
     pl.sync()
     pl.close()
     ef = errs(F.cpu().numpy(), g["forces"])
-    print(f"charges_1000 auto: rel E {abs(e.item() - float(g['energy'])) / abs(float(g['energy'])):.2e}; "
+    print(f"charges_1000 auto ({far}, eps {eps:g}): rel E "
+          f"{abs(e.item() - float(g['energy'])) / abs(float(g['energy'])):.2e}; "
           f"F rms/max/median {ef[0]:.2e} {ef[1]:.2e} {ef[2]:.2e}")
     assert abs(e.item() - float(g["energy"])) <= 1e-6 * abs(float(g["energy"]))
     assert ef[0] <= 1e-5
 
 
 def test_auto_far_field_choice(ak):
-    """Automatic far field: ANKH-FFT on its automatic grid wherever the order is supported (<= 8), ANKH-FMM
-    beyond (accuracy 1e-9: order 9)."""
+    """Automatic far field: ANKH-FFT on its automatic grid up to order 6 (accuracy 1e-6), ANKH-FMM beyond
+    (accuracy 1e-7: order 7; 1e-9: order 9)."""
     d = synth.water(300, seed=3)
     n = len(d["q"])
     p1 = ak.Plan(n, 0.5 * d["edge"], 1e-6, 2, "fp64")
     p2 = ak.Plan(n, 0.5 * d["edge"], 1e-9, 2, "fp64")
     p3 = ak.Plan(n, 0.5 * d["edge"], 1e-6, 2, "fp64", depth=2)
+    p4 = ak.Plan(n, 0.5 * d["edge"], 1e-7, 2, "fp64")
     assert p1.stats["far_field"] == ak.ANKH_FAR_FFT
     assert p2.stats["far_field"] == ak.ANKH_FAR_FMM and p2.stats["order"] == 9
     assert p3.stats["far_field"] == ak.ANKH_FAR_FFT and p3.stats["depth"] == 2
-    for p in (p1, p2, p3):
+    assert p4.stats["far_field"] == ak.ANKH_FAR_FMM and p4.stats["order"] == 7
+    for p in (p1, p2, p3, p4):
         p.close()
 
 
