@@ -245,6 +245,28 @@ ankh_status ankh_energy_derivs(ankh_plan_t plan, const double *pos, const double
                                double *dE_dq, double *dE_dtheta);
 
 /*
+ * ankh_energy_derivs_noalloc: ankh_energy_derivs for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, same outputs, bitwise
+ * equal to ankh_energy_derivs on the same plan and inputs.  The call itself
+ * allocates nothing: the plan's buffers serve the evaluation, and the 7 n
+ * doubles of the charge and quadrupole derivatives live in a static device
+ * array of the library (28 MiB, held on every GPU the library runs on until
+ * the process ends) instead of a plan buffer.
+ *   Limit: n_atoms <= 524288 (2^19); a larger plan returns ANKH_ERR_INVALID_ARG
+ *   before anything is enqueued.
+ *   The static array is shared by every call on one GPU: calls that overlap on
+ *   one GPU (other streams, other threads, other plans) race and must be
+ *   ordered by the caller.  Each call writes every entry it reads, so nothing
+ *   of an earlier call's contents leaks into a result.
+ *   Stage timing (ankh_set_timing) is ignored for this call: its events would
+ *   be created on first use.
+ */
+ankh_status ankh_energy_derivs_noalloc(ankh_plan_t plan, const double *pos, const double *q, const double *mu,
+                                       const double *theta, double *energy, double *forces, double *dE_dmu,
+                                       double *dE_dq, double *dE_dtheta);
+
+/*
  * ankh_induce: induced dipoles of isotropic point polarisabilities, the
  * polarizable use of the method that the paper's introduction names (the
  * moments of eq. 1 extended by induced dipoles).  The induced dipoles are the

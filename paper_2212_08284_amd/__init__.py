@@ -67,7 +67,7 @@ _lib = None
 
 EXPORTS = ["ankh_plan", "ankh_energy", "ankh_energy_forces", "ankh_sync", "ankh_get_stats", "ankh_set_timing",
            "ankh_last_terms", "ankh_leaf_multipoles", "ankh_destroy", "ankh_status_string", "ankh_induce",
-           "ankh_energy_derivs"]
+           "ankh_energy_derivs", "ankh_energy_derivs_noalloc"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -88,6 +88,8 @@ def load_library(path: str = LIB_PATH):
     L.ankh_energy_forces.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp]
     L.ankh_energy_derivs.restype = ctypes.c_int
     L.ankh_energy_derivs.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+    L.ankh_energy_derivs_noalloc.restype = ctypes.c_int
+    L.ankh_energy_derivs_noalloc.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
     L.ankh_induce.restype = ctypes.c_int
     L.ankh_induce.argtypes = [vp, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int32, dp, dp, dp,
                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
@@ -175,6 +177,11 @@ def ankh_energy_forces(plan, pos, q, mu, theta, energy, forces, dE_dmu):
 def ankh_energy_derivs(plan, pos, q, mu, theta, energy, forces, dE_dmu, dE_dq, dE_dtheta):
     _check(load_library().ankh_energy_derivs(plan, pos, q, mu, theta, energy, forces, dE_dmu, dE_dq, dE_dtheta),
            "ankh_energy_derivs")
+
+
+def ankh_energy_derivs_noalloc(plan, pos, q, mu, theta, energy, forces, dE_dmu, dE_dq, dE_dtheta):
+    _check(load_library().ankh_energy_derivs_noalloc(plan, pos, q, mu, theta, energy, forces, dE_dmu, dE_dq,
+                                                      dE_dtheta), "ankh_energy_derivs_noalloc")
 
 
 def ankh_induce(plan, pos, q, mu, theta, alpha, tol, max_iter, mu_ind, energy, forces):
@@ -274,9 +281,11 @@ class Plan:
         return e, F, G
 
     def energy_derivs(self, pos, q, mu=None, theta=None, forces=True, fields=True, potentials=True,
-                      theta_grad=True):
+                      theta_grad=True, noalloc=False):
         """Energy and the requested derivatives (see ankh_energy_derivs in ankh.h): a dict with "energy"
-        and, as asked, "forces" -dE/dx, "dEdmu", "dEdq" [n] and "dEdtheta" [n][6]."""
+        and, as asked, "forces" -dE/dx, "dEdmu", "dEdq" [n] and "dEdtheta" [n][6].  noalloc: through
+        ankh_energy_derivs_noalloc (the library allocates nothing in the call; the output tensors are still
+        allocated here, by torch)."""
         keep, (pp, qp, mp, tp) = self._args(pos, q, mu, theta)
         dev = pos.device
         out = {"energy": torch.empty(1, dtype=torch.float64, device=dev)}
@@ -289,8 +298,8 @@ class Plan:
         if theta_grad:
             out["dEdtheta"] = torch.empty((self.n, 6), dtype=torch.float64, device=dev)
         ptr = lambda k: ctypes.c_void_p(out[k].data_ptr()) if k in out else None
-        ankh_energy_derivs(self.handle, pp, qp, mp, tp, ptr("energy"), ptr("forces"), ptr("dEdmu"), ptr("dEdq"),
-                           ptr("dEdtheta"))
+        fn = ankh_energy_derivs_noalloc if noalloc else ankh_energy_derivs
+        fn(self.handle, pp, qp, mp, tp, ptr("energy"), ptr("forces"), ptr("dEdmu"), ptr("dEdq"), ptr("dEdtheta"))
         return out
 
     def induce(self, pos, q, mu, theta, alpha, tol=1e-8, max_iter=100, energy=True, forces=False,

@@ -7,12 +7,20 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "ankh_internal.h"
 
 using namespace ankh;
+
+// Scratch of ankh_energy_derivs_noalloc: the near-field charge and quadrupole derivatives [7][n] of up to
+// kNoAllocMaxAtoms atoms.  Every GPU the library runs on holds one copy until the process ends.  In host
+// code `scratch` only names the symbol: its device address comes from hipGetSymbolAddress, once per
+// device (noalloc_scratch below), and only that address is handed to kernels.
+constexpr int64_t kNoAllocMaxAtoms = (int64_t)1 << 19;
+static __device__ __align__(256) double scratch[7 * kNoAllocMaxAtoms];
 
 namespace {
 
@@ -222,6 +230,31 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
     pl->last_kind = grad ? 2 : 1;
     pl->last_order = ord;
     if (ev) pl->n_timed++;
+    return ANKH_OK;
+}
+
+// device address of `scratch` on device dev, looked up with that device current on the first call for it
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+ankh_status noalloc_scratch(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return ANKH_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) return ANKH_ERR_HIP;
+        if (cur != dev && hipSetDevice(dev) != hipSuccess) return ANKH_ERR_HIP;
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev && hipSetDevice(cur) != hipSuccess) return ANKH_ERR_HIP;
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return ANKH_ERR_HIP;
+        }
+        g_scratch[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch[dev];
     return ANKH_OK;
 }
 
@@ -643,6 +676,29 @@ ankh_status ankh_energy_derivs(ankh_plan_t pl, const double *pos, const double *
     const int ord = theta ? 2 : (mu ? 1 : 0);
     if (launch_p2p_moments(pl, ord, pl->d_mom) != hipSuccess) return ANKH_ERR_HIP;
     if (launch_l2p_moments(pl, ord, pl->d_mom, dE_dq, dE_dtheta) != hipSuccess) return ANKH_ERR_HIP;
+    return ANKH_OK;
+}
+
+ankh_status ankh_energy_derivs_noalloc(ankh_plan_t pl, const double *pos, const double *q, const double *mu,
+                                       const double *theta, double *energy, double *forces, double *dE_dmu,
+                                       double *dE_dq, double *dE_dtheta) {
+    ankh_status st = check_inputs(pl, pos, q, mu, theta);
+    if (st != ANKH_OK) return st;
+    if (!energy || (dE_dtheta && pl->max_order < 2)) return ANKH_ERR_INVALID_ARG;
+    if (pl->n > kNoAllocMaxAtoms) return ANKH_ERR_INVALID_ARG;
+    double *mom = nullptr;
+    if ((dE_dq || dE_dtheta) && (st = noalloc_scratch(pl->device, &mom)) != ANKH_OK) return st;
+    // stage timing would create events on its first use: it stays off in this call
+    const int timing = pl->timing;
+    pl->timing = 0;
+    st = run(pl, pos, q, mu, theta, energy, forces, dE_dmu);
+    pl->timing = timing;
+    if (st != ANKH_OK) return st;
+    if (!dE_dq && !dE_dtheta) return ANKH_OK;
+    // the near-field pass writes every [7][n] entry that the far-field pass then reads
+    const int ord = theta ? 2 : (mu ? 1 : 0);
+    if (launch_p2p_moments(pl, ord, mom) != hipSuccess) return ANKH_ERR_HIP;
+    if (launch_l2p_moments(pl, ord, mom, dE_dq, dE_dtheta) != hipSuccess) return ANKH_ERR_HIP;
     return ANKH_OK;
 }
 

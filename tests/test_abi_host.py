@@ -126,4 +126,5 @@ def test_null_plan_and_null_outputs(lib):
     assert lib.ankh_plan(None, 10, 1.0, 1e-6, 0, 0, None, None) == 1
     assert lib.ankh_induce(None, vp(8), vp(8), None, None, vp(8), 1e-8, 10, vp(8), None, None, None, None) == 1
     assert lib.ankh_energy_derivs(None, vp(8), vp(8), None, None, vp(8), None, None, vp(8), None) == 1
+    assert lib.ankh_energy_derivs_noalloc(None, vp(8), vp(8), None, None, vp(8), None, None, vp(8), None) == 1
     lib.ankh_destroy(None)   # no-op
