@@ -24,7 +24,7 @@ constexpr int kNumIL = 189;          // interaction-list length of every cell
 constexpr int kRedBlocks = 1024;     // first-stage blocks of the energy reduction (the epilogue)
 constexpr int kNumStages = 11;
 constexpr int kCperSlices = 16;     // column slices of the far-image root matvec
-constexpr int kNumSlots = 16;       // near-field partials per atom (see the pair kernel)
+constexpr int kNumSlots = 14;       // near-field partials per atom (see the pair kernel)
 
 // index of offset d in [-3,3]^3
 __host__ __device__ constexpr int off_index(int dx, int dy, int dz) {
@@ -104,8 +104,8 @@ struct ankh_plan_s {
     double *d_U = nullptr, *d_Mc = nullptr, *d_Lc = nullptr;
     double *d_Cper = nullptr;     // far-image root operator [nup0][nup0]
     double *d_cper_part = nullptr;// its column-slice partial products [kCperSlices][nup0]
-    double *d_slot_e = nullptr;   // near-field partials per atom: energy [kNumSlots][n]
-    void *d_slot_f = nullptr;     //   forces [3][kNumSlots][n] and fields [3][kNumSlots][n], float64 or float32
+    double *d_enear = nullptr;    // near energy per leaf (the pair kernel's block of that source leaf)
+    void *d_slot_f = nullptr;     // near-field partials per atom: forces [3][kNumSlots][n] and fields [3][kNumSlots][n], float64 or float32
     void *d_slot_g = nullptr;
     double *d_eleaf = nullptr;    // far energy per leaf
     double *d_F = nullptr;        // forces in leaf order [3][n]

@@ -4,23 +4,26 @@
 // excluding an atom with itself at zero shift.
 //
 // Mutual form (the pair symmetry of the mutual-interactions section): each
-// unordered pair of adjacent leaves is one task, (t, t + d) for the 13 offsets
+// unordered pair of adjacent leaves is one task, (s - d, s) for the 13 offsets
 // d > 0 (lexicographically), and every pair of atoms in it is evaluated once:
-// the target atom takes the energy, its force and its field, the source atom
-// takes the opposite force and its own field.  The leaf with itself is a
-// fourteenth task evaluated in gather form (all ordered pairs, half energy).
+// the target atom (in s - d) takes the energy, its force and its field, the
+// source atom (in s) the opposite force and its own field.  The leaf with
+// itself is a fourteenth task, evaluated in gather form (all ordered pairs,
+// half energy).
 //
-// Blocks are formed per source leaf s: the mutual tasks (s - d, s) of one
-// block share the source atoms, staged once in LDS, and the target atoms of
-// all their target leaves form one list.  The 256 threads form 16 groups of
-// 16 lanes.  The lanes of a group hold 16 consecutive targets of the list and
-// read the same source atom (an LDS broadcast); the source's share is summed
-// over the 16 lanes with DPP row operations and added to that source's LDS
-// accumulator by the one group that owns it.  The target shares of the 16
-// groups are summed through LDS.  Every atom receives one partial per task
-// it is a target of (slot 0: its own leaf, slots 1..13: the half-shell
-// tasks) and one per block it is a source of (slots 14, 15); k_p2p_slots adds
-// the 16 slots in order.  No atomics: results are bitwise reproducible.
+// One block per source leaf s evaluates its 13 mutual tasks and its own leaf.
+// The atoms of the 13 target leaves form one list; lane l of the block owns
+// list positions l and l + 256 for the whole block (two targets per lane:
+// every source value read from LDS serves both), so a target is loaded once
+// and its partial sums stay in registers.  The source atoms of s are staged in
+// LDS in chunks of 64 and every lane walks the chunk in the same order (LDS
+// broadcasts).  A source's share of one step is summed over the 16 lanes of a
+// row with DPP and stored per row; the chunk's 16 row sums are added in row
+// order afterwards.  Every atom receives one partial per task it is a target
+// of (slots 0..12) and one for its own leaf's block (slot 13: its source
+// shares and its own-leaf pairs); k_epilogue adds the 14 slots in order.  The
+// near energy is summed per block in float64.  No atomics: results are
+// bitwise reproducible.
 //
 // Pair terms (r = x_i - x_j, D_x = q + mu.d + Th:dd on x, the mirrored
 // operator on the source): with B_0 = H, B_{n+1} = -(1/r) dB_n/dr,
@@ -41,13 +44,16 @@
 namespace ankh {
 namespace {
 
-constexpr int CH = 128;     // source atoms per LDS chunk
+constexpr int CH = 64;      // source atoms per LDS chunk (and targets per round of the own-leaf task)
 constexpr int NHALF = 13;   // half-shell neighbour offsets (mutual tasks per leaf)
-constexpr int NKIND = 2;    // blocks per source leaf
-constexpr int KMAX = 7;     // mutual tasks of a kind-0 block (kind 1: the other 6 and the leaf itself)
-constexpr int G = 16;       // lanes per group (one DPP row)
-constexpr int NG = 16;      // groups per block
-constexpr int kTList = 2048; // list positions whose target segment is tabulated per block
+constexpr int BT = 256;     // threads per block
+constexpr int NW = BT / 64; // waves per block
+constexpr int NROW = BT / 16;   // 16-lane DPP rows per block
+constexpr int TPASS = 2 * BT;   // target list positions per pass (two per lane)
+constexpr int kSlotSrc = NHALF; // slot of an atom's own-leaf block
+constexpr int G = 16;       // derivative pass: lanes per group (targets per round)
+constexpr int NG = 16;      //                  groups per block (source split)
+static_assert(kNumSlots == NHALF + 1, "one slot per mutual task of a target and one for its own leaf");
 
 // Per-launch constants of the radial functions: xi; gx, the factor that turns
 // r^2 into the argument of gauss(); pwc[n] = (2 xi^2)^n / (xi sqrt(pi)), the
@@ -64,9 +70,9 @@ template <typename R> struct P2PArgs {
     int64_t n;
     int nside, depth;
     double w, xi;
-    double *slot_e;         // [27][n] energy partials (target side)
-    void *slot_f;           // [3][27][n] force partials (R)
-    void *slot_g;           // [3][27][n] field partials (R)
+    double *enear;          // [nleaf] near energy per block (source leaf)
+    void *slot_f;           // [3][kNumSlots][n] force partials (R)
+    void *slot_g;           // [3][kNumSlots][n] field partials (R)
     Radial<R> rad;
 };
 
@@ -357,42 +363,37 @@ __device__ inline void task_offset(int k, int &dx, int &dy, int &dz) {
             }
 }
 
-// Blocks: two per source leaf s.  Kind 0 evaluates the mutual tasks (s - d, s)
-// for the first 7 half-shell offsets d, kind 1 those for the other 6 and then
-// the leaf with itself (gather form).  The target atoms of all target leaves
-// of a block form one list that streams through the 16-lane groups, so only
-// the last pass of a block is partly empty.
+// One block per source leaf s: the 13 mutual tasks (s - d, s) and the leaf with
+// itself.  Lane l owns target list positions l and l + BT of every pass (a pass
+// covers TPASS positions; more than one only for crowded half-shells).
 template <typename R, int ORD, bool GRAD, bool FIELD, int SL>
-__global__ __launch_bounds__(256) void k_p2p(P2PArgs<R> a) {
+__global__ __launch_bounds__(BT) void k_p2p(P2PArgs<R> a) {
     constexpr int NM = 1 + (ORD >= 1 ? 3 : 0) + (ORD >= 2 ? 6 : 0);   // moment components
+    constexpr bool ADJ = GRAD || FIELD;
     __shared__ double sx[CH], sy[CH], sz[CH];
     __shared__ R smo[NM][CH];
-    __shared__ R sacc[6][CH];           // source-side force (3) and field (3)
-    __shared__ double tpart[2][7][NG][G];   // target-side partials of the 16 groups (two passes)
-    __shared__ int tfirst[KMAX], tcount[KMAX], tpre[KMAX + 1];   // target leaves: first atom, atoms, prefix
-    __shared__ double tshift[KMAX][3];                            // their position shift, -d w
-    __shared__ unsigned char tseg[kTList];                        // segment of each list position
+    __shared__ R wpart[ADJ ? 6 : 1][NROW][CH];   // source shares per row and chunk atom; own-leaf partials per wave
+    __shared__ int tfirst[NHALF], tpre[NHALF + 1];   // target leaves: first atom, list prefix
+    __shared__ double tshift[NHALF][3];              // their position shift into the source leaf's frame, -d w
+    __shared__ double ered[NROW];
 
     const int tid = threadIdx.x;
-    const int grp = tid >> 4, ln = tid & 15;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int ns = a.nside;
     const int64_t nleaf = (int64_t)ns * ns * ns;
-    // XCD-aware order: each XCD receives a contiguous Morton range of source leaves
-    const int64_t nblk = nleaf * NKIND;
+    // XCD-aware order: each XCD receives a contiguous range of source leaves
     int64_t b = blockIdx.x;
-    if ((nblk & 7) == 0) b = (int64_t)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
-    const int kind = (int)(b % NKIND);
+    if ((nleaf & 7) == 0) b = (int64_t)(blockIdx.x & 7) * (nleaf >> 3) + (blockIdx.x >> 3);
     // Morton order on an octree level; on any other grid (ANKH-FFT) the lexicographic order
-    const int leaf = a.depth >= 0 ? morton_leaf(b / NKIND, a.depth, ns) : (int)(b / NKIND);
+    const int leaf = a.depth >= 0 ? morton_leaf(b, a.depth, ns) : (int)b;
     const int lx = leaf / (ns * ns), ly = (leaf / ns) % ns, lz = leaf % ns;
-    const int k_first = kind == 0 ? 1 : KMAX + 1;
-    const int ntl = kind == 0 ? KMAX : NHALF - KMAX;
-    if (tid < ntl) {
+    if (tid < NHALF) {
         int dx, dy, dz;
-        task_offset(k_first + tid, dx, dy, dz);
+        task_offset(1 + tid, dx, dy, dz);
         const int t = (((lx - dx + ns) % ns) * ns + (ly - dy + ns) % ns) * ns + (lz - dz + ns) % ns;
         tfirst[tid] = a.offs[t];
-        tcount[tid] = a.offs[t + 1] - a.offs[t];
+        tpre[tid + 1] = a.offs[t + 1] - a.offs[t];
         tshift[tid][0] = -dx * a.w;
         tshift[tid][1] = -dy * a.w;
         tshift[tid][2] = -dz * a.w;
@@ -400,101 +401,21 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs<R> a) {
     __syncthreads();
     if (tid == 0) {
         tpre[0] = 0;
-        for (int k = 0; k < ntl; k++) tpre[k + 1] = tpre[k] + tcount[k];
+        for (int k = 0; k < NHALF; k++) tpre[k + 1] += tpre[k];
     }
     __syncthreads();
-    const int ntg = tpre[ntl];
+    const int ntg = tpre[NHALF];
     const int s0 = a.offs[leaf], nsrc = a.offs[leaf + 1] - s0;
-    const int slot_src = NHALF + 1 + kind;
 
     const R *q = pick<R>(a.q, a.qf), *mu = pick<R>(a.mu, a.muf), *th = pick<R>(a.th, a.thf);
     const int64_t n = a.n;
     R *SF = static_cast<R *>(a.slot_f), *SG = static_cast<R *>(a.slot_g);
     const int64_t sstride = (int64_t)kNumSlots * n;     // component stride of the slot arrays
     const Radial<R> rc = a.rad;
+    double eacc = 0;   // this lane's near energy
 
-    // target leaf (segment of the block's list) of list position f < ntg
-    auto segment_scan = [&](int f) {
-        int s = 0;
-        while (s + 1 < ntl && f >= tpre[s + 1]) s++;
-        return s;
-    };
-    // the segment of each of the first kTList list positions, looked up once per block instead of in
-    // every pass (target loads and partial-sum stores)
-    for (int f = tid; f < min(ntg, kTList); f += 256) tseg[f] = (unsigned char)segment_scan(f);
-    __syncthreads();
-    auto segment = [&](int f) { return f < kTList ? (int)tseg[f] : segment_scan(f); };
-    // sums the 16 groups' partials of pass tp (fixed order) and stores them in
-    // the atoms' slots.  The partials alternate between two LDS buffers, so one
-    // barrier per pass suffices: a buffer is rewritten two passes later, after
-    // every thread has passed the next pass's barrier.
-    auto flush = [&](int buf, int tp, int nt_pass, bool mutual, bool first) {
-        __syncthreads();
-        if (tid < 7 * G) {
-            const int c = tid / G, l = tid % G;
-            const int f = tp + l;
-            if (f < nt_pass) {
-                double s = 0;
-                for (int g2 = 0; g2 < NG; g2++) s += tpart[buf][c][g2][l];
-                int64_t at;
-                int slot;
-                if (mutual) {
-                    const int sg = segment(f);
-                    at = tfirst[sg] + (f - tpre[sg]);
-                    slot = k_first + sg;
-                } else {
-                    at = s0 + f;
-                    slot = 0;
-                }
-                if (c == 0) {
-                    double *pe = a.slot_e + (int64_t)slot * n + at;
-                    *pe = first ? s : *pe + s;
-                } else if ((c <= 3 && GRAD) || (c >= 4 && FIELD)) {
-                    R *p = (c <= 3 ? SF + (int64_t)(c - 1) * sstride : SG + (int64_t)(c - 4) * sstride) +
-                           (int64_t)slot * n + at;
-                    *p = first ? (R)s : (R)(*p + (R)s);
-                }
-            }
-        }
-    };
-    // one lane's target atom of a pass: position (shifted into the source leaf's frame) and moments
-    struct Target {
-        double x, y, z;
-        R c, d[3], Q[6];
-    };
-    auto load_target = [&](int f, int nt_pass, bool mutual, Target &t) {
-        const bool iv = f < nt_pass;
-        int64_t ti = s0;
-        double shx = 0, shy = 0, shz = 0;
-        if (iv) {
-            if (mutual) {
-                const int sg = segment(f);
-                ti = tfirst[sg] + (f - tpre[sg]);
-                shx = tshift[sg][0];
-                shy = tshift[sg][1];
-                shz = tshift[sg][2];
-            } else {
-                ti = s0 + f;
-            }
-        }
-        // an absent target sits far away with zero moments: its pair terms vanish.  Every array is
-        // read at a 32-bit unsigned offset from a uniform base (one address add per load).
-        const unsigned u = (unsigned)ti;
-        t.x = iv ? a.x[u] + shx : 1.0e4;
-        t.y = iv ? a.y[u] + shy : 1.0e4;
-        t.z = iv ? a.z[u] + shz : 1.0e4;
-        t.c = iv ? q[u] : (R)0;
-#pragma unroll
-        for (int c = 0; c < 3; c++) t.d[c] = (ORD >= 1 && iv) ? (mu + (int64_t)c * n)[u] : (R)0;
-#pragma unroll
-        for (int c = 0; c < 6; c++) t.Q[c] = (ORD >= 2 && iv) ? (th + (int64_t)c * n)[u] : (R)0;
-    };
-    int pbuf = 0;
-
-    for (int cs = 0; cs < nsrc; cs += CH) {
-        const int chn = min(CH, nsrc - cs);
-        __syncthreads();
-        for (int f = tid; f < chn; f += 256) {
+    auto load_chunk = [&](int cs, int chn) {
+        for (int f = tid; f < chn; f += BT) {
             const int64_t sj = s0 + cs + f;
             sx[f] = a.x[sj];
             sy[f] = a.y[sj];
@@ -504,157 +425,263 @@ __global__ __launch_bounds__(256) void k_p2p(P2PArgs<R> a) {
                 for (int c = 0; c < 3; c++) smo[1 + c][f] = mu[c * n + sj];
             if (ORD >= 2)
                 for (int c = 0; c < 6; c++) smo[4 + c][f] = th[c * n + sj];
-            for (int c = 0; c < 6; c++) sacc[c][f] = 0;
         }
-        __syncthreads();
-        // mutual tasks: every target atom of the block against this chunk.  In
-        // float32 each lane keeps its share of the group's sources (at most
-        // CH / NG of them) in registers over all passes; the 16 lanes' shares
-        // are summed once per chunk.  In float64 (register-bound) the share is
-        // summed over the lanes for every pair.
-        constexpr bool RACC = sizeof(R) == 4;
-        constexpr int MS = RACC ? CH / NG : 1;
-        R psrc[MS][6];
+    };
+    // one target atom: position (in the source leaf's frame) and moments
+    struct Target {
+        double x, y, z;
+        R c, d[3], Q[6];
+    };
+    // list position f of the mutual tasks (valid if f < ntg), or atom s0 + f of the own leaf; an absent
+    // target sits far away with zero moments, so its pair terms vanish
+    auto load_target = [&](int f, bool mutual, Target &t, int &seg, int64_t &at) {
+        const bool iv = f < (mutual ? ntg : nsrc);
+        seg = 0;
+        at = 0;   // an index every array holds (the loads below may run for absent targets too)
+        double shx = 0, shy = 0, shz = 0;
+        if (iv) {
+            if (mutual) {
+                while (seg + 1 < NHALF && f >= tpre[seg + 1]) seg++;
+                at = tfirst[seg] + (f - tpre[seg]);
+                shx = tshift[seg][0];
+                shy = tshift[seg][1];
+                shz = tshift[seg][2];
+            } else {
+                at = s0 + f;
+            }
+        }
+        // every array is read at a 32-bit unsigned offset from a uniform base
+        const unsigned u = (unsigned)at;
+        t.x = iv ? a.x[u] + shx : 1.0e4;
+        t.y = iv ? a.y[u] + shy : 1.0e4;
+        t.z = iv ? a.z[u] + shz : 1.0e4;
+        t.c = iv ? q[u] : (R)0;
 #pragma unroll
-        for (int m = 0; m < MS; m++)
+        for (int c = 0; c < 3; c++) t.d[c] = (ORD >= 1 && iv) ? (mu + (int64_t)c * n)[u] : (R)0;
 #pragma unroll
-            for (int c = 0; c < 6; c++) psrc[m][c] = 0;
-        for (int tp = 0; tp < ntg; tp += G) {
-            Target tcur;
-            load_target(tp + ln, ntg, true, tcur);
-            const double xt = tcur.x, yt = tcur.y, zt = tcur.z;
-            const R ci = tcur.c;
-            const R *di = tcur.d, *Qi = tcur.Q;
-            R te = 0, tf[3] = {0, 0, 0}, tg[3] = {0, 0, 0};
-            // one pair with source j: the target's share into te / tf / tg, the source's into sf / sg
-            auto pair = [&](int j, R *sf, R *sg) {
-                const R rx = (R)(xt - sx[j]), ry = (R)(yt - sy[j]), rz = (R)(zt - sz[j]);
+        for (int c = 0; c < 6; c++) t.Q[c] = (ORD >= 2 && iv) ? (th + (int64_t)c * n)[u] : (R)0;
+    };
+    auto slot_ptr = [&](int c, int slot, int64_t at) {
+        return (c < 3 ? SF + (int64_t)c * sstride : SG + (int64_t)(c - 3) * sstride) + (int64_t)slot * n + at;
+    };
+    constexpr int c_lo = GRAD ? 0 : 3, c_hi = FIELD ? 6 : 3;   // the slot components that are written
+
+    // mutual tasks: every pass of target positions against every source chunk
+    const int npass = ntg > 0 ? (ntg + TPASS - 1) / TPASS : (nsrc > 0 ? 1 : 0);
+    for (int pass = 0; pass < npass; pass++) {
+        Target t0, t1;
+        int seg0, seg1;
+        int64_t at0, at1;
+        const int f0 = pass * TPASS + tid, f1 = f0 + BT;
+        load_target(f0, true, t0, seg0, at0);
+        load_target(f1, true, t1, seg1, at1);
+        // wave-uniform: some lane of this wave holds a second target
+        const bool two = pass * TPASS + BT + wv * 64 < ntg;
+        R tf0[3] = {0, 0, 0}, tg0[3] = {0, 0, 0}, tf1[3] = {0, 0, 0}, tg1[3] = {0, 0, 0};
+        for (int cs = 0; cs < nsrc; cs += CH) {
+            const int chn = min(CH, nsrc - cs);
+            __syncthreads();
+            load_chunk(cs, chn);
+            __syncthreads();
+            R te = 0;
+            for (int j = 0; j < chn; j++) {
+                const double xs = sx[j], ys = sy[j], zs = sz[j];
                 R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
                 if (ORD >= 1)
                     for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
                 if (ORD >= 2)
                     for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
-                pair_terms<R, ORD, GRAD, FIELD, true, SL>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, rc, (R)1, te,
-                                                           tf, tg, sf, sg);
-            };
-            if constexpr (RACC) {
-#pragma unroll
-                for (int m = 0; m < MS; m++) {
-                    const int j = grp + NG * m;
-                    if (j < chn) pair(j, &psrc[m][0], &psrc[m][3]);
-                }
-            } else {
-                for (int j = grp; j < chn; j += NG) {
-                    R sf[3] = {0, 0, 0}, sg[3] = {0, 0, 0};
-                    pair(j, sf, sg);
-                    if (GRAD || FIELD) {
-                        // the source's share, summed over the 16 targets of the group
-                        R v[6];
-#pragma unroll
-                        for (int c = 0; c < 3; c++) {
-                            v[c] = GRAD ? row16_sum(sf[c]) : (R)0;
-                            v[3 + c] = FIELD ? row16_sum(sg[c]) : (R)0;
-                        }
-                        if (ln == 0) {
-#pragma unroll
-                            for (int c = 0; c < 6; c++) sacc[c][j] += v[c];
-                        }
-                    }
-                }
-            }
-            tpart[pbuf][0][grp][ln] = (double)te;
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                tpart[pbuf][1 + c][grp][ln] = (double)tf[c];
-                tpart[pbuf][4 + c][grp][ln] = (double)tg[c];
-            }
-            flush(pbuf, tp, ntg, true, cs == 0);
-            pbuf ^= 1;
-        }
-        if constexpr (RACC) {
-            if (GRAD || FIELD) {
-#pragma unroll
-                for (int m = 0; m < MS; m++) {
-                    const int j = grp + NG * m;
+                const R ck = smo[0][j];
+                R sf[3] = {0, 0, 0}, sg[3] = {0, 0, 0};
+                pair_terms<R, ORD, GRAD, FIELD, true, SL>((R)(t0.x - xs), (R)(t0.y - ys), (R)(t0.z - zs), t0.c,
+                                                           t0.d, t0.Q, ck, dk, Qk, rc, (R)1, te, tf0, tg0, sf, sg);
+                if (two)
+                    pair_terms<R, ORD, GRAD, FIELD, true, SL>((R)(t1.x - xs), (R)(t1.y - ys), (R)(t1.z - zs),
+                                                               t1.c, t1.d, t1.Q, ck, dk, Qk, rc, (R)1, te, tf1,
+                                                               tg1, sf, sg);
+                if constexpr (ADJ) {
+                    // the source's share of this step, summed over each row of 16 lanes
                     R v[6];
 #pragma unroll
-                    for (int c = 0; c < 3; c++) {
-                        v[c] = GRAD ? row16_sum(psrc[m][c]) : (R)0;
-                        v[3 + c] = FIELD ? row16_sum(psrc[m][3 + c]) : (R)0;
-                    }
-                    if (ln == 0 && j < chn) {
+                    for (int c = c_lo; c < c_hi; c++) v[c] = row16_sum(c < 3 ? sf[c] : sg[c - 3]);
+                    if ((lane & 15) == 15) {
 #pragma unroll
-                        for (int c = 0; c < 6; c++) sacc[c][j] = v[c];
+                        for (int c = c_lo; c < c_hi; c++) wpart[c][tid >> 4][j] = v[c];
                     }
                 }
             }
-            __syncthreads();
-        }
-        // source side of this chunk
-        for (int f = tid; f < chn; f += 256) {
-            const int64_t sj = s0 + cs + f;
-            if (GRAD)
-                for (int c = 0; c < 3; c++) SF[(int64_t)c * sstride + (int64_t)slot_src * n + sj] = sacc[c][f];
-            if (FIELD)
-                for (int c = 0; c < 3; c++) SG[(int64_t)c * sstride + (int64_t)slot_src * n + sj] = sacc[3 + c][f];
-            a.slot_e[(int64_t)slot_src * n + sj] = 0.0;
-        }
-        // the leaf with itself: its atoms against this chunk, all ordered pairs, half energy
-        if (kind == 1) {
-            for (int tp = 0; tp < nsrc; tp += G) {
-                Target tcur;
-                load_target(tp + ln, nsrc, false, tcur);
-                const int i = tp + ln;
-                const double xt = tcur.x, yt = tcur.y, zt = tcur.z;
-                const R ci = tcur.c;
-                const R *di = tcur.d, *Qi = tcur.Q;
-                R te = 0, tf[3] = {0, 0, 0}, tg[3] = {0, 0, 0};
-                for (int j = grp; j < chn; j += NG) {
-                    if (j + cs == i) continue;   // an atom with itself at zero shift
-                    const R rx = (R)(xt - sx[j]), ry = (R)(yt - sy[j]), rz = (R)(zt - sz[j]);
-                    R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
-                    if (ORD >= 1)
-                        for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
-                    if (ORD >= 2)
-                        for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
-                    pair_terms<R, ORD, GRAD, FIELD, false, SL>(rx, ry, rz, ci, di, Qi, smo[0][j], dk, Qk, rc,
-                                                               (R)0.5, te, tf, tg, nullptr, nullptr);
-                }
-                tpart[pbuf][0][grp][ln] = (double)te;
+            eacc += (double)te;
+            if constexpr (ADJ) {
+                __syncthreads();
+                // the chunk atoms' source shares: the 16 row sums in row order, by the atom's owner thread
+                if (tid < chn) {
+                    const int64_t sj = s0 + cs + tid;
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    tpart[pbuf][1 + c][grp][ln] = (double)tf[c];
-                    tpart[pbuf][4 + c][grp][ln] = (double)tg[c];
+                    for (int c = c_lo; c < c_hi; c++) {
+                        R sum = 0;
+#pragma unroll
+                        for (int r = 0; r < NROW; r++) sum += wpart[c][r][tid];
+                        R *p = slot_ptr(c, kSlotSrc, sj);
+                        *p = pass == 0 ? sum : *p + sum;
+                    }
                 }
-                flush(pbuf, tp, nsrc, false, cs == 0);
-                pbuf ^= 1;
+            }
+        }
+        // the targets' partials of this block's tasks
+        if constexpr (ADJ) {
+            if (f0 < ntg) {
+#pragma unroll
+                for (int c = c_lo; c < c_hi; c++) *slot_ptr(c, seg0, at0) = c < 3 ? tf0[c] : tg0[c - 3];
+            }
+            if (f1 < ntg) {
+#pragma unroll
+                for (int c = c_lo; c < c_hi; c++) *slot_ptr(c, seg1, at1) = c < 3 ? tf1[c] : tg1[c - 3];
             }
         }
     }
-    // an empty source leaf: the target slots of the block's tasks still hold zeros
-    if (nsrc == 0) {
-        for (int f = tid; f < ntg; f += 256) {
-            const int sg = segment(f);
-            const int64_t at = tfirst[sg] + (f - tpre[sg]);
-            const int slot = k_first + sg;
-            a.slot_e[(int64_t)slot * n + at] = 0.0;
-            for (int c = 0; c < 3; c++) {
-                if (GRAD) SF[(int64_t)c * sstride + (int64_t)slot * n + at] = 0;
-                if (FIELD) SG[(int64_t)c * sstride + (int64_t)slot * n + at] = 0;
+
+    // the leaf with itself.  Up to CH atoms (the chunk still in LDS): the unordered pairs in mutual form,
+    // round robin in one wave: lane i pairs with i + k (mod m) for k = 1 .. (m - 1) / 2, its source shares
+    // accumulated in LDS (the partners of one step are distinct, so no two lanes touch one entry), and for
+    // even m the pair at distance m / 2 once from each side in gather form with half energy.
+    if (nsrc > 0 && nsrc <= CH) {
+        const int m = nsrc;
+        __syncthreads();   // the mutual phase's readers of wpart are done
+        if (wv == 0) {
+            const int i = lane;
+            const bool iv = i < m;
+            const int ii = iv ? i : 0;
+            Target t;
+            t.x = iv ? sx[ii] : 1.0e4;
+            t.y = iv ? sy[ii] : 1.0e4;
+            t.z = iv ? sz[ii] : 1.0e4;
+            t.c = iv ? smo[0][ii] : (R)0;
+#pragma unroll
+            for (int c = 0; c < 3; c++) t.d[c] = (ORD >= 1 && iv) ? smo[1 + c][ii] : (R)0;
+#pragma unroll
+            for (int c = 0; c < 6; c++) t.Q[c] = (ORD >= 2 && iv) ? smo[4 + c][ii] : (R)0;
+            R te = 0, tf[3] = {0, 0, 0}, tg[3] = {0, 0, 0};
+            if constexpr (ADJ) {
+#pragma unroll
+                for (int c = c_lo; c < c_hi; c++) wpart[c][0][i] = (R)0;
+            }
+            auto partner = [&](int j, R *dk, R *Qk) {
+                if (ORD >= 1)
+                    for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
+                if (ORD >= 2)
+                    for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
+            };
+            const int K = (m - 1) / 2;
+            for (int k = 1; k <= K; k++) {
+                int j = i + k;
+                if (j >= m) j -= m;
+                if (!iv) j = 0;
+                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0}, sf[3] = {0, 0, 0}, sg[3] = {0, 0, 0};
+                partner(j, dk, Qk);
+                pair_terms<R, ORD, GRAD, FIELD, true, SL>((R)(t.x - sx[j]), (R)(t.y - sy[j]), (R)(t.z - sz[j]), t.c,
+                                                           t.d, t.Q, smo[0][j], dk, Qk, rc, (R)1, te, tf, tg, sf, sg);
+                if constexpr (ADJ) {
+                    // LDS atomics: other lanes read and add these entries in later steps (in this wave's
+                    // instruction order); within one step every lane has its own entry
+                    if (iv) {
+#pragma unroll
+                        for (int c = c_lo; c < c_hi; c++) atomicAdd(&wpart[c][0][j], c < 3 ? sf[c] : sg[c - 3]);
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if ((m & 1) == 0) {
+                int j = i + m / 2;
+                if (j >= m) j -= m;
+                if (!iv) j = 0;
+                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
+                partner(j, dk, Qk);
+                pair_terms<R, ORD, GRAD, FIELD, false, SL>((R)(t.x - sx[j]), (R)(t.y - sy[j]), (R)(t.z - sz[j]),
+                                                            t.c, t.d, t.Q, smo[0][j], dk, Qk, rc, (R)0.5, te, tf, tg,
+                                                            nullptr, nullptr);
+            }
+            eacc += (double)te;
+            // the atom's own-leaf partials (its target side, then its source shares), added to its slot by
+            // its owner thread, which wrote the slot in the mutual phase
+            if constexpr (ADJ) {
+                if (iv) {
+                    const int64_t sj = s0 + i;
+#pragma unroll
+                    for (int c = c_lo; c < c_hi; c++) {
+                        R *p = slot_ptr(c, kSlotSrc, sj);
+                        *p = *p + ((c < 3 ? tf[c] : tg[c - 3]) + wpart[c][0][i]);
+                    }
+                }
             }
         }
+    }
+    // more than CH atoms: gather form, CH of them per round as targets (the same in every wave), the
+    // sources dealt to the waves; all ordered pairs but an atom with itself, half energy
+    for (int tc = 0; nsrc > CH && tc < nsrc; tc += CH) {
+        Target t;
+        int seg;
+        int64_t at;
+        const int i = tc + lane;
+        load_target(i, false, t, seg, at);
+        R te = 0, tf[3] = {0, 0, 0}, tg[3] = {0, 0, 0};
+        for (int cs = 0; cs < nsrc; cs += CH) {
+            const int chn = min(CH, nsrc - cs);
+            __syncthreads();
+            load_chunk(cs, chn);
+            __syncthreads();
+            for (int j = wv; j < chn; j += NW) {
+                if (cs + j == i) continue;   // an atom with itself at zero shift
+                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
+                if (ORD >= 1)
+                    for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
+                if (ORD >= 2)
+                    for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
+                pair_terms<R, ORD, GRAD, FIELD, false, SL>((R)(t.x - sx[j]), (R)(t.y - sy[j]), (R)(t.z - sz[j]),
+                                                            t.c, t.d, t.Q, smo[0][j], dk, Qk, rc, (R)0.5, te, tf, tg,
+                                                            nullptr, nullptr);
+            }
+        }
+        eacc += (double)te;
+        if constexpr (ADJ) {
+            __syncthreads();   // the last chunk's readers of wpart are done
+#pragma unroll
+            for (int c = c_lo; c < c_hi; c++) wpart[c][wv][lane] = c < 3 ? tf[c] : tg[c - 3];
+            __syncthreads();
+            // the waves' partials in wave order, added to the atom's own-leaf slot by its owner thread
+            if (tid < CH && tc + tid < nsrc) {
+                const int64_t sj = s0 + tc + tid;
+#pragma unroll
+                for (int c = c_lo; c < c_hi; c++) {
+                    R sum = 0;
+#pragma unroll
+                    for (int w = 0; w < NW; w++) sum += wpart[c][w][tid];
+                    R *p = slot_ptr(c, kSlotSrc, sj);
+                    *p = *p + sum;
+                }
+            }
+        }
+    }
+
+    // the block's near energy: the lanes' sums, rows by DPP, then the 16 rows in order
+    const double er = row16_sum(eacc);
+    if ((lane & 15) == 15) ered[tid >> 4] = er;
+    __syncthreads();
+    if (tid == 0) {
+        double e = 0;
+        for (int r = 0; r < NROW; r++) e += ered[r];
+        a.enear[leaf] = e;
     }
 }
 
 // The evaluation's epilogue, per atom in kRedBlocks blocks of contiguous leaf-order ranges:
-//  - the near energy, the sum of its energy slots (slot order);
 //  - forces and fields, the far-field part (from L2P) plus the slots, written in caller order
 //    (fields with the self-field term of the dipole);
-//  - the block's partial sums of the energy terms: near, self, total charge and the far energies of
-//    its share of the leaves (finished by k_reduce2 in block order).
+//  - the block's partial sums of the energy terms: self, total charge, and the near and far energies
+//    of its share of the leaves (finished by k_reduce2 in block order).
 template <typename R> struct EpiArgs {
     int64_t n, nleaf;
-    const double *slot_e;
+    const double *enear;
     const R *SF, *SG;
     const double *F, *G, *eleaf;
     Particles P;
@@ -675,9 +702,6 @@ __global__ __launch_bounds__(256) void k_epilogue(EpiArgs<R> a) {
     const double c0 = -xi / sqrt(3.14159265358979323846), c1 = 2 * xi * xi / 3, c2 = 8 * xi * xi * xi * xi / 5;
     double near = 0, self = 0, qs = 0, far = 0;
     for (int64_t s = a0 + t; s < a1; s += 256) {
-        double e = 0;
-        for (int k = 0; k < kNumSlots; k++) e += a.slot_e[(int64_t)k * n + s];
-        near += e;
         const double q = a.P.q[s];
         qs += q;
         double v = q * q;
@@ -710,7 +734,10 @@ __global__ __launch_bounds__(256) void k_epilogue(EpiArgs<R> a) {
             }
         }
     }
-    for (int64_t l = l0 + t; l < l1; l += 256) far += a.eleaf[l];
+    for (int64_t l = l0 + t; l < l1; l += 256) {
+        near += a.enear[l];
+        far += a.eleaf[l];
+    }
     red[0][t] = near;
     red[1][t] = self;
     red[2][t] = qs;
@@ -895,7 +922,7 @@ hipError_t launch_moments_prec(ankh_plan_s *pl, int ord, double *out) {
 template <typename R, int SL>
 hipError_t launch_t(ankh_plan_s *pl, P2PArgs<R> a, int ord, bool grad, bool fields) {
     a.rad = radial_constants<R, SL>(pl->xi);
-    dim3 g((unsigned)(pl->nleaf * NKIND)), b(256);
+    dim3 g((unsigned)pl->nleaf), b(BT);
     hipStream_t s = pl->stream;
 #define ANKH_P2P(O, GR, FL) hipLaunchKernelGGL((k_p2p<R, O, GR, FL, SL>), g, b, 0, s, a)
     if (ord == 0) {
@@ -918,7 +945,7 @@ hipError_t launch_epi_t(ankh_plan_s *pl, int ord, bool grad, bool fields, double
     EpiArgs<R> a;
     a.n = pl->n;
     a.nleaf = pl->nleaf;
-    a.slot_e = pl->d_slot_e;
+    a.enear = pl->d_enear;
     a.SF = static_cast<const R *>(pl->d_slot_f);
     a.SG = static_cast<const R *>(pl->d_slot_g);
     a.F = pl->d_F;
@@ -959,7 +986,7 @@ hipError_t launch_prec(ankh_plan_s *pl, int ord, bool grad, bool fields) {
     a.depth = pl->fft_dft ? -1 : pl->depth;
     a.w = pl->edge / pl->nside;
     a.xi = pl->xi;
-    a.slot_e = pl->d_slot_e;
+    a.enear = pl->d_enear;
     a.slot_f = pl->d_slot_f;
     a.slot_g = pl->d_slot_g;
     // largest xi r of a near pair: opposite corners of diagonally adjacent leaves

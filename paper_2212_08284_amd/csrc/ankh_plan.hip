@@ -54,7 +54,7 @@ void free_all(ankh_plan_s *pl) {
                     pl->d_M, pl->d_L, pl->d_K, pl->d_Kf, pl->d_Cper, pl->d_eleaf, pl->d_F,
                     pl->d_G, pl->d_terms, pl->d_part, pl->d_err, pl->d_tab0, pl->d_Mf, pl->d_m2l_part,
                     pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr,
-                    pl->d_Kb, pl->d_Mb, pl->d_slot_e, pl->d_slot_f, pl->d_slot_g, pl->d_cper_part,
+                    pl->d_Kb, pl->d_Mb, pl->d_enear, pl->d_slot_f, pl->d_slot_g, pl->d_cper_part,
                     pl->d_U, pl->d_Mc, pl->d_Lc, pl->d_ind, pl->d_mom, pl->d_fftB, pl->d_fftW, pl->d_fftX,
                     pl->d_fftD, pl->d_fftTw};
     for (void *p : ptrs)
@@ -506,7 +506,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
             pl->d_rootM = pl->d_M;
             pl->d_rootL = pl->d_L;
         }
-        dalloc(pl, &pl->d_slot_e, (size_t)kNumSlots * n);
+        dalloc(pl, &pl->d_enear, pl->nleaf);
         if (precision == ANKH_FP64) {
             double *f = nullptr, *g = nullptr;
             dalloc(pl, &f, (size_t)3 * kNumSlots * n);
