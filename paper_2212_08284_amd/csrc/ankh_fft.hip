@@ -48,16 +48,25 @@ namespace {
 
 constexpr double kPiF = 3.14159265358979323846;
 
+// Complex values of the working precision: float64 (double2) everywhere in the FP64 mode; float32
+// (float2) for the spectrum, the tables and the transforms of an evaluation in the mixed modes.
+template <typename R> struct CplxOf;
+template <> struct CplxOf<double> { using type = double2; };
+template <> struct CplxOf<float> { using type = float2; };
+template <typename R> using Cplx = typename CplxOf<R>::type;
+__host__ __device__ inline double2 mkc(double a, double b) { return make_double2(a, b); }
+__host__ __device__ inline float2 mkc(float a, float b) { return make_float2(a, b); }
+
 // e^{-2 pi i k / 16}, k = 0..7: the roots of unity of every cell FFT (n <= 16)
-struct Tw16 {
-    double2 w[8];
+template <typename R> struct Tw16 {
+    Cplx<R> w[8];
 };
 
-__device__ inline double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+template <typename C> __device__ inline C cmul(C a, C b) {
+    return mkc(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ inline double2 cmulc(double2 a, double2 b) {   // conj(a) * b
-    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+template <typename C> __device__ inline C cmulc(C a, C b) {   // conj(a) * b
+    return mkc(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
 // blocks are dealt to the 8 XCDs in turn: give each XCD a contiguous range of
@@ -70,8 +79,9 @@ __device__ inline int64_t xcd_leaf(int64_t b, int64_t ncell) {
 
 // radix-2 FFT of N <= 16 points in registers (decimation in time, bit-reversed
 // input order); INV uses the conjugate roots and no scaling
-template <int N, bool INV>
-__device__ inline void fft_line(double2 (&v)[N], const Tw16 &tw) {
+template <typename R, int N, bool INV>
+__device__ inline void fft_line(Cplx<R> (&v)[N], const Tw16<R> &tw) {
+    using C = Cplx<R>;
     if constexpr (N > 1) {
 #pragma unroll
         for (int i = 0; i < N; i++) {
@@ -80,7 +90,7 @@ __device__ inline void fft_line(double2 (&v)[N], const Tw16 &tw) {
             for (int b = 1, r = N >> 1; b < N; b <<= 1, r >>= 1)
                 if (i & b) j |= r;
             if (i < j) {
-                const double2 t = v[i];
+                const C t = v[i];
                 v[i] = v[j];
                 v[j] = t;
             }
@@ -91,11 +101,11 @@ __device__ inline void fft_line(double2 (&v)[N], const Tw16 &tw) {
             for (int i = 0; i < N; i += len) {
 #pragma unroll
                 for (int k = 0; k < len / 2; k++) {
-                    double2 w = tw.w[k * (16 / len)];
+                    C w = tw.w[k * (16 / len)];
                     if (INV) w.y = -w.y;
-                    const double2 u = v[i + k], t = cmul(w, v[i + k + len / 2]);
-                    v[i + k] = make_double2(u.x + t.x, u.y + t.y);
-                    v[i + k + len / 2] = make_double2(u.x - t.x, u.y - t.y);
+                    const C u = v[i + k], t = cmul(w, v[i + k + len / 2]);
+                    v[i + k] = mkc(u.x + t.x, u.y + t.y);
+                    v[i + k + len / 2] = mkc(u.x - t.x, u.y - t.y);
                 }
             }
         }
@@ -214,11 +224,13 @@ __device__ inline int cell_at(int x, int y, int z) {
     return xy * NS + (z ^ (xy & (NS - 1)));
 }
 
-template <int NS, int MODE>
-__global__ __launch_bounds__(256) void k_fft_cells(double2 *X, double *D, int64_t ncell, double scale, Tw16 tw) {
-    extern __shared__ double2 sm[];
+template <typename R, int NS, int MODE>
+__global__ __launch_bounds__(256) void k_fft_cells(Cplx<R> *X, R *D, int64_t ncell, R scale, Tw16<R> tw) {
+    using C = Cplx<R>;
+    extern __shared__ __align__(16) unsigned char smraw[];
+    C *sm = reinterpret_cast<C *>(smraw);
     const int64_t f = blockIdx.x;
-    double2 *xf = X + f * ncell;
+    C *xf = X + f * ncell;
     const int t = threadIdx.x;
     constexpr int NL = NS * NS;
     for (int i = t; i < NS * NS * NS; i += 256) {
@@ -226,12 +238,12 @@ __global__ __launch_bounds__(256) void k_fft_cells(double2 *X, double *D, int64_
         sm[cell_at<NS>(x, y, z)] = xf[i];
     }
     __syncthreads();
-    double2 v[NS];
+    C v[NS];
     if (t < NL) {                                   // z lines
         const int x = t / NS, y = t % NS;
 #pragma unroll
         for (int z = 0; z < NS; z++) v[z] = sm[cell_at<NS>(x, y, z)];
-        fft_line<NS, false>(v, tw);
+        fft_line<R, NS, false>(v, tw);
 #pragma unroll
         for (int z = 0; z < NS; z++) sm[cell_at<NS>(x, y, z)] = v[z];
     }
@@ -240,7 +252,7 @@ __global__ __launch_bounds__(256) void k_fft_cells(double2 *X, double *D, int64_
         const int x = t / NS, z = t % NS;
 #pragma unroll
         for (int y = 0; y < NS; y++) v[y] = sm[cell_at<NS>(x, y, z)];
-        fft_line<NS, false>(v, tw);
+        fft_line<R, NS, false>(v, tw);
 #pragma unroll
         for (int y = 0; y < NS; y++) sm[cell_at<NS>(x, y, z)] = v[y];
     }
@@ -249,17 +261,17 @@ __global__ __launch_bounds__(256) void k_fft_cells(double2 *X, double *D, int64_
         const int y = t / NS, z = t % NS;
 #pragma unroll
         for (int x = 0; x < NS; x++) v[x] = sm[cell_at<NS>(x, y, z)];
-        fft_line<NS, false>(v, tw);
+        fft_line<R, NS, false>(v, tw);
         if (MODE == 1) {
 #pragma unroll
             for (int x = 0; x < NS; x++) D[f * ncell + (x * NS + y) * NS + z] = v[x].x;
         } else {
 #pragma unroll
             for (int x = 0; x < NS; x++) {
-                const double d = D[f * ncell + (x * NS + y) * NS + z] * scale;
-                v[x] = make_double2(v[x].x * d, v[x].y * d);
+                const R d = D[f * ncell + (x * NS + y) * NS + z] * scale;
+                v[x] = mkc(v[x].x * d, v[x].y * d);
             }
-            fft_line<NS, true>(v, tw);
+            fft_line<R, NS, true>(v, tw);
 #pragma unroll
             for (int x = 0; x < NS; x++) sm[cell_at<NS>(x, y, z)] = v[x];
         }
@@ -270,7 +282,7 @@ __global__ __launch_bounds__(256) void k_fft_cells(double2 *X, double *D, int64_
         const int x = t / NS, z = t % NS;
 #pragma unroll
         for (int y = 0; y < NS; y++) v[y] = sm[cell_at<NS>(x, y, z)];
-        fft_line<NS, true>(v, tw);
+        fft_line<R, NS, true>(v, tw);
 #pragma unroll
         for (int y = 0; y < NS; y++) sm[cell_at<NS>(x, y, z)] = v[y];
     }
@@ -279,7 +291,7 @@ __global__ __launch_bounds__(256) void k_fft_cells(double2 *X, double *D, int64_
         const int x = t / NS, y = t % NS;
 #pragma unroll
         for (int z = 0; z < NS; z++) v[z] = sm[cell_at<NS>(x, y, z)];
-        fft_line<NS, true>(v, tw);
+        fft_line<R, NS, true>(v, tw);
 #pragma unroll
         for (int z = 0; z < NS; z++) sm[cell_at<NS>(x, y, z)] = v[z];
     }
@@ -300,13 +312,14 @@ __global__ __launch_bounds__(256) void k_fft_cells(double2 *X, double *D, int64_
 constexpr int kCB = 4;
 constexpr int kCF = 8, kFT = 512;
 
-template <int L>
-__global__ __launch_bounds__(kFT) void k_fft_nodes_fwd_t(const double *Q, int nup, const double2 *B, double2 *X,
+template <typename R, int L>
+__global__ __launch_bounds__(kFT) void k_fft_nodes_fwd_t(const double *Q, int nup, const Cplx<R> *B, Cplx<R> *X,
                                                          int64_t ncell) {
+    using C = Cplx<R>;
     constexpr int PA = 2 * L - 1, PH = L, NQ = L * L * L, NT1 = PA * L * L;
-    __shared__ double sQ[kCF][NQ];
-    __shared__ double2 T1[kCF][NT1];
-    __shared__ double2 sB[PA * L];
+    __shared__ R sQ[kCF][NQ];
+    __shared__ C T1[kCF][NT1];
+    __shared__ C sB[PA * L];
     const int64_t c0 = xcd_leaf(blockIdx.x, ncell / kCF) * kCF;
     const int t = threadIdx.x;
     for (int i = t; i < kCF * NQ; i += kFT) sQ[i / NQ][i % NQ] = Q[(c0 + i / NQ) * nup + i % NQ];
@@ -315,54 +328,55 @@ __global__ __launch_bounds__(kFT) void k_fft_nodes_fwd_t(const double *Q, int nu
     // x: thread (cell, f1, j, k): T1[f1][j][k] = sum_i B[f1][i] Q[i][j][k]
     for (int o = t; o < kCF * NT1; o += kFT) {
         const int cell = o / NT1, r = o - cell * NT1, f1 = r / (L * L), jk = r - f1 * L * L;
-        double re = 0, im = 0;
+        R re = 0, im = 0;
 #pragma unroll
         for (int i = 0; i < L; i++) {
-            const double2 b = sB[f1 * L + i];
-            const double q = sQ[cell][i * L * L + jk];
+            const C b = sB[f1 * L + i];
+            const R q = sQ[cell][i * L * L + jk];
             re += b.x * q;
             im += b.y * q;
         }
-        T1[cell][r] = make_double2(re, im);
+        T1[cell][r] = mkc(re, im);
     }
     __syncthreads();
     // y and z, half spectrum: thread (line f1 f2, cell), the kCF cells of a line adjacent lanes:
     // v[k] = sum_j B[f2][j] T1[f1][j][k], then X[f1 f2 f3] = sum_k B[f3][k] v[k]
     for (int o = t; o < kCF * PA * PA; o += kFT) {
         const int cell = o % kCF, f12 = o / kCF, f1 = f12 / PA, f2 = f12 - f1 * PA;
-        const double2 *t1 = &T1[cell][f1 * L * L];
-        double2 v[L];
+        const C *t1 = &T1[cell][f1 * L * L];
+        C v[L];
 #pragma unroll
-        for (int k = 0; k < L; k++) v[k] = make_double2(0.0, 0.0);
+        for (int k = 0; k < L; k++) v[k] = mkc((R)0, (R)0);
 #pragma unroll
         for (int j = 0; j < L; j++) {
-            const double2 b = sB[f2 * L + j];
+            const C b = sB[f2 * L + j];
 #pragma unroll
             for (int k = 0; k < L; k++) {
-                const double2 u = t1[j * L + k];
+                const C u = t1[j * L + k];
                 v[k].x += b.x * u.x - b.y * u.y;
                 v[k].y += b.x * u.y + b.y * u.x;
             }
         }
 #pragma unroll
         for (int f3 = 0; f3 < PH; f3++) {
-            double re = 0, im = 0;
+            R re = 0, im = 0;
 #pragma unroll
             for (int k = 0; k < L; k++) {
-                const double2 b = B[f3 * L + k];
+                const C b = B[f3 * L + k];
                 re += b.x * v[k].x - b.y * v[k].y;
                 im += b.x * v[k].y + b.y * v[k].x;
             }
-            X[(int64_t)(f12 * PH + f3) * ncell + c0 + cell] = make_double2(re, im);
+            X[(int64_t)(f12 * PH + f3) * ncell + c0 + cell] = mkc(re, im);
         }
     }
 }
 
-template <int L>
-__global__ __launch_bounds__(256) void k_fft_nodes_inv_t(const double2 *X, const double2 *B, double *Lam, int nup,
+template <typename R, int L>
+__global__ __launch_bounds__(256) void k_fft_nodes_inv_t(const Cplx<R> *X, const Cplx<R> *B, double *Lam, int nup,
                                                          int64_t ncell) {
+    using C = Cplx<R>;
     constexpr int PA = 2 * L - 1, PH = L, NU = PA * PA * L;
-    __shared__ double2 U[kCB][NU];
+    __shared__ C U[kCB][NU];
     const int64_t c0 = xcd_leaf(blockIdx.x, ncell / kCB) * kCB;
     const int t = threadIdx.x;
     // z: thread (line f1 f2, cell): U[f1][f2][k] = sum_f3 w(f3) conj(B[f3][k]) X[f1 f2 f3]; two lines
@@ -370,7 +384,7 @@ __global__ __launch_bounds__(256) void k_fft_nodes_inv_t(const double2 *X, const
     // last line again and is not stored)
     constexpr int NZ = kCB * PA * PA;
     for (int o0 = t; o0 < NZ; o0 += 512) {
-        double2 x[2][PH];
+        C x[2][PH];
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const int o = min(o0 + 256 * h, NZ - 1), cell = o % kCB, f12 = o / kCB;
@@ -383,15 +397,15 @@ __global__ __launch_bounds__(256) void k_fft_nodes_inv_t(const double2 *X, const
             if (o >= NZ) break;
 #pragma unroll
             for (int k = 0; k < L; k++) {
-                double re = 0, im = 0;
+                R re = 0, im = 0;
 #pragma unroll
                 for (int f3 = 0; f3 < PH; f3++) {
-                    const double w = f3 == 0 ? 1.0 : 2.0;       // pa odd: no unpaired frequency besides 0
-                    const double2 v = cmulc(B[f3 * L + k], x[h][f3]);
+                    const R w = f3 == 0 ? 1.0 : 2.0;       // pa odd: no unpaired frequency besides 0
+                    const C v = cmulc(B[f3 * L + k], x[h][f3]);
                     re += w * v.x;
                     im += w * v.y;
                 }
-                U[cell][f12 * L + k] = make_double2(re, im);
+                U[cell][f12 * L + k] = mkc(re, im);
             }
         }
     }
@@ -400,21 +414,21 @@ __global__ __launch_bounds__(256) void k_fft_nodes_inv_t(const double2 *X, const
     // Lambda[i][j][k] = Re sum_f1 conj(B[f1][i]) v[f1]
     for (int o = t; o < kCB * L * L; o += 256) {
         const int cell = o / (L * L), jk = o - cell * L * L, j = jk / L, k = jk - j * L;
-        double2 v[PA];
+        C v[PA];
 #pragma unroll
         for (int f1 = 0; f1 < PA; f1++) {
-            double re = 0, im = 0;
+            R re = 0, im = 0;
 #pragma unroll
             for (int f2 = 0; f2 < PA; f2++) {
-                const double2 u = cmulc(B[f2 * L + j], U[cell][(f1 * PA + f2) * L + k]);
+                const C u = cmulc(B[f2 * L + j], U[cell][(f1 * PA + f2) * L + k]);
                 re += u.x;
                 im += u.y;
             }
-            v[f1] = make_double2(re, im);
+            v[f1] = mkc(re, im);
         }
 #pragma unroll
         for (int i = 0; i < L; i++) {
-            double re = 0;
+            R re = 0;
 #pragma unroll
             for (int f1 = 0; f1 < PA; f1++) re += cmulc(B[f1 * L + i], v[f1]).x;
             Lam[(c0 + cell) * nup + (i * L + j) * L + k] = re;
@@ -498,8 +512,9 @@ __device__ inline int brev(int v) {
     return (int)(__brev((unsigned)v) >> (32 - bits));
 }
 
-template <int NS, bool ALONG_V, bool DIT, bool INV>
-__device__ void tile_fft(double2 *tile, const double2 *tw) {
+template <typename R, int NS, bool ALONG_V, bool DIT, bool INV>
+__device__ void tile_fft(Cplx<R> *tile, const Cplx<R> *tw) {
+    using C = Cplx<R>;
     constexpr int NB = NS * (NS / 2);
     for (int half = DIT ? 1 : NS / 2; DIT ? half < NS : half >= 1; half = DIT ? 2 * half : half / 2) {
         for (int b = threadIdx.x; b < NB; b += blockDim.x) {
@@ -507,18 +522,18 @@ __device__ void tile_fft(double2 *tile, const double2 *tw) {
             const int line = ALONG_V ? b / (NS / 2) : b % NS;
             const int k = ALONG_V ? b % (NS / 2) : b / NS;
             const int pos = k % half, i0 = (k / half) * 2 * half + pos, i1 = i0 + half;
-            double2 w = tw[pos * (NS / (2 * half))];
+            C w = tw[pos * (NS / (2 * half))];
             if (INV) w.y = -w.y;
             const int e0 = ALONG_V ? line * NS + i0 : i0 * NS + line;
             const int e1 = ALONG_V ? line * NS + i1 : i1 * NS + line;
-            const double2 u = tile[e0], v = tile[e1];
+            const C u = tile[e0], v = tile[e1];
             if (DIT) {
-                const double2 t = cmul(w, v);
-                tile[e0] = make_double2(u.x + t.x, u.y + t.y);
-                tile[e1] = make_double2(u.x - t.x, u.y - t.y);
+                const C t = cmul(w, v);
+                tile[e0] = mkc(u.x + t.x, u.y + t.y);
+                tile[e1] = mkc(u.x - t.x, u.y - t.y);
             } else {
-                tile[e0] = make_double2(u.x + v.x, u.y + v.y);
-                tile[e1] = cmul(w, make_double2(u.x - v.x, u.y - v.y));
+                tile[e0] = mkc(u.x + v.x, u.y + v.y);
+                tile[e1] = cmul(w, mkc(u.x - v.x, u.y - v.y));
             }
         }
         __syncthreads();
@@ -527,10 +542,11 @@ __device__ void tile_fft(double2 *tile, const double2 *tw) {
 
 // pass 1 / 3: block (f, x), the (y, z) plane of X[f] (contiguous): forward (DIT, natural output) or
 // inverse (DIF, written back in natural order)
-template <int NS, bool INV>
-__global__ __launch_bounds__(256) void k_fft_yz(double2 *X, const double2 *tw, int64_t ncell) {
-    __shared__ double2 tile[NS * NS];
-    double2 *p = X + (int64_t)blockIdx.x * ncell + (int64_t)blockIdx.y * NS * NS;
+template <typename R, int NS, bool INV>
+__global__ __launch_bounds__(256) void k_fft_yz(Cplx<R> *X, const Cplx<R> *tw, int64_t ncell) {
+    using C = Cplx<R>;
+    __shared__ C tile[NS * NS];
+    C *p = X + (int64_t)blockIdx.x * ncell + (int64_t)blockIdx.y * NS * NS;
     const int t = threadIdx.x;
     for (int i = t; i < NS * NS; i += 256) {
         const int y = i / NS, z = i % NS;
@@ -538,11 +554,11 @@ __global__ __launch_bounds__(256) void k_fft_yz(double2 *X, const double2 *tw, i
     }
     __syncthreads();
     if (!INV) {
-        tile_fft<NS, true, true, false>(tile, tw);
-        tile_fft<NS, false, true, false>(tile, tw);
+        tile_fft<R, NS, true, true, false>(tile, tw);
+        tile_fft<R, NS, false, true, false>(tile, tw);
     } else {
-        tile_fft<NS, true, false, true>(tile, tw);
-        tile_fft<NS, false, false, true>(tile, tw);
+        tile_fft<R, NS, true, false, true>(tile, tw);
+        tile_fft<R, NS, false, false, true>(tile, tw);
     }
     for (int i = t; i < NS * NS; i += 256) {
         const int y = i / NS, z = i % NS;
@@ -552,10 +568,11 @@ __global__ __launch_bounds__(256) void k_fft_yz(double2 *X, const double2 *tw, i
 
 // pass 2: block (f, y), the (x, z) tile of X[f]: forward along x, then MODE 0: times D * scale and the
 // inverse along x, back to X; MODE 1 (plan): the real part to D
-template <int NS, int MODE>
-__global__ __launch_bounds__(256) void k_fft_x(double2 *X, double *D, const double2 *tw, int64_t ncell,
-                                               double scale) {
-    __shared__ double2 tile[NS * NS];
+template <typename R, int NS, int MODE>
+__global__ __launch_bounds__(256) void k_fft_x(Cplx<R> *X, R *D, const Cplx<R> *tw, int64_t ncell,
+                                               R scale) {
+    using C = Cplx<R>;
+    __shared__ C tile[NS * NS];
     const int64_t f = blockIdx.x;
     const int y = blockIdx.y, t = threadIdx.x;
     for (int i = t; i < NS * NS; i += 256) {
@@ -563,7 +580,7 @@ __global__ __launch_bounds__(256) void k_fft_x(double2 *X, double *D, const doub
         tile[brev<NS>(x) * NS + z] = X[f * ncell + ((int64_t)x * NS + y) * NS + z];
     }
     __syncthreads();
-    tile_fft<NS, false, true, false>(tile, tw);
+    tile_fft<R, NS, false, true, false>(tile, tw);
     if (MODE == 1) {
         for (int i = t; i < NS * NS; i += 256) {
             const int x = i / NS, z = i % NS;
@@ -573,11 +590,11 @@ __global__ __launch_bounds__(256) void k_fft_x(double2 *X, double *D, const doub
     }
     for (int i = t; i < NS * NS; i += 256) {
         const int x = i / NS, z = i % NS;
-        const double d = D[f * ncell + ((int64_t)x * NS + y) * NS + z] * scale;
-        tile[i] = make_double2(tile[i].x * d, tile[i].y * d);
+        const R d = D[f * ncell + ((int64_t)x * NS + y) * NS + z] * scale;
+        tile[i] = mkc(tile[i].x * d, tile[i].y * d);
     }
     __syncthreads();
-    tile_fft<NS, false, false, true>(tile, tw);
+    tile_fft<R, NS, false, false, true>(tile, tw);
     for (int i = t; i < NS * NS; i += 256) {
         const int x = i / NS, z = i % NS;
         X[f * ncell + ((int64_t)x * NS + y) * NS + z] = tile[brev<NS>(x) * NS + z];
@@ -679,8 +696,9 @@ template <> struct Roots<6> {
                                      0.8660254037844386};
 };
 
-template <int N2, bool ALONG_V, bool INV, int ROW = 4 * N2>
-__device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
+template <typename R, int N2, bool ALONG_V, bool INV, int ROW = 4 * N2>
+__device__ inline void tiles_phase1(Cplx<R> *t, int ntile, const Cplx<R> *tw) {
+    using C = Cplx<R>;
     constexpr int N = 4 * N2;
     constexpr int NL = ALONG_V ? N : ROW;     // lines per tile
     // the N2-point transforms take their roots as constants, and each task reads its twiddles before
@@ -692,18 +710,18 @@ __device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
         const int r = task - tile * NL * 4;
         if (ALONG_V) { line = r / 4; n1 = r % 4; }
         else { n1 = r / NL; line = r % NL; }
-        double2 *b = t + tile * N * ROW;
-        auto at = [&](int j) -> double2 & { return b[ALONG_V ? line * ROW + j : j * ROW + line]; };
-        double2 wt[N2];                      // W^{n1 k2}, n1 k2 < N
+        C *b = t + tile * N * ROW;
+        auto at = [&](int j) -> C & { return b[ALONG_V ? line * ROW + j : j * ROW + line]; };
+        C wt[N2];                      // W^{n1 k2}, n1 k2 < N
 #pragma unroll
         for (int k2 = 0; k2 < N2; k2++) wt[k2] = tw[n1 * k2];
         if (!INV) {
-            double2 x[N2];
+            C x[N2];
 #pragma unroll
             for (int n2 = 0; n2 < N2; n2++) x[n2] = at(n1 + 4 * n2);
 #pragma unroll
             for (int k2 = 0; k2 < N2; k2++) {
-                double re = 0, im = 0;
+                R re = 0, im = 0;
 #pragma unroll
                 for (int n2 = 0; n2 < N2; n2++) {
                     if ((n2 * k2) % N2 == 0) {         // root 1
@@ -711,25 +729,25 @@ __device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
                         im += x[n2].y;
                         continue;
                     }
-                    const double wx = Roots<N2>::re[(n2 * k2) % N2], wy = Roots<N2>::im[(n2 * k2) % N2];
+                    const R wx = Roots<N2>::re[(n2 * k2) % N2], wy = Roots<N2>::im[(n2 * k2) % N2];
                     re += x[n2].x * wx - x[n2].y * wy;
                     im += x[n2].x * wy + x[n2].y * wx;
                 }
-                const double2 w = wt[k2];
-                at(n1 + 4 * k2) = k2 == 0 ? make_double2(re, im)
-                                          : make_double2(re * w.x - im * w.y, re * w.y + im * w.x);
+                const C w = wt[k2];
+                at(n1 + 4 * k2) = k2 == 0 ? mkc(re, im)
+                                          : mkc(re * w.x - im * w.y, re * w.y + im * w.x);
             }
         } else {
             // inverse of phase 1: z[n1 + 4 k2] times conj W^{n1 k2}, then the conjugate N2-point transform
-            double2 z[N2];
+            C z[N2];
 #pragma unroll
             for (int k2 = 0; k2 < N2; k2++) {
-                const double2 v = at(n1 + 4 * k2), w = wt[k2];
-                z[k2] = k2 == 0 ? v : make_double2(v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y);
+                const C v = at(n1 + 4 * k2), w = wt[k2];
+                z[k2] = k2 == 0 ? v : mkc(v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y);
             }
 #pragma unroll
             for (int n2 = 0; n2 < N2; n2++) {
-                double re = 0, im = 0;
+                R re = 0, im = 0;
 #pragma unroll
                 for (int k2 = 0; k2 < N2; k2++) {
                     if ((n2 * k2) % N2 == 0) {         // root 1
@@ -737,19 +755,20 @@ __device__ inline void tiles_phase1(double2 *t, int ntile, const double2 *tw) {
                         im += z[k2].y;
                         continue;
                     }
-                    const double wx = Roots<N2>::re[(n2 * k2) % N2], wy = Roots<N2>::im[(n2 * k2) % N2];
+                    const R wx = Roots<N2>::re[(n2 * k2) % N2], wy = Roots<N2>::im[(n2 * k2) % N2];
                     re += z[k2].x * wx + z[k2].y * wy;
                     im += z[k2].y * wx - z[k2].x * wy;
                 }
-                at(n1 + 4 * n2) = make_double2(re, im);
+                at(n1 + 4 * n2) = mkc(re, im);
             }
         }
     }
     __syncthreads();
 }
 
-template <int N2, bool ALONG_V, bool INV, int ROW = 4 * N2>
-__device__ inline void tiles_phase2(double2 *t, int ntile) {
+template <typename R, int N2, bool ALONG_V, bool INV, int ROW = 4 * N2>
+__device__ inline void tiles_phase2(Cplx<R> *t, int ntile) {
+    using C = Cplx<R>;
     constexpr int N = 4 * N2;
     constexpr int NL = ALONG_V ? N : ROW;
     for (int task = threadIdx.x; task < ntile * NL * N2; task += blockDim.x) {
@@ -758,30 +777,31 @@ __device__ inline void tiles_phase2(double2 *t, int ntile) {
         const int r = task - tile * NL * N2;
         if (ALONG_V) { line = r / N2; k2 = r % N2; }
         else { k2 = r / NL; line = r % NL; }
-        double2 *b = t + tile * N * ROW;
-        auto at = [&](int j) -> double2 & { return b[ALONG_V ? line * ROW + j : j * ROW + line]; };
-        const double2 a = at(4 * k2), bb = at(4 * k2 + 1), c = at(4 * k2 + 2), d = at(4 * k2 + 3);
-        const double2 s0 = make_double2(a.x + c.x, a.y + c.y), s1 = make_double2(a.x - c.x, a.y - c.y);
-        const double2 s2 = make_double2(bb.x + d.x, bb.y + d.y), s3 = make_double2(bb.x - d.x, bb.y - d.y);
+        C *b = t + tile * N * ROW;
+        auto at = [&](int j) -> C & { return b[ALONG_V ? line * ROW + j : j * ROW + line]; };
+        const C a = at(4 * k2), bb = at(4 * k2 + 1), c = at(4 * k2 + 2), d = at(4 * k2 + 3);
+        const C s0 = mkc(a.x + c.x, a.y + c.y), s1 = mkc(a.x - c.x, a.y - c.y);
+        const C s2 = mkc(bb.x + d.x, bb.y + d.y), s3 = mkc(bb.x - d.x, bb.y - d.y);
         // (-i)^{n1 k1} forward, i^{n1 k1} inverse
-        const double2 js3 = INV ? make_double2(-s3.y, s3.x) : make_double2(s3.y, -s3.x);
-        at(4 * k2) = make_double2(s0.x + s2.x, s0.y + s2.y);
-        at(4 * k2 + 1) = make_double2(s1.x + js3.x, s1.y + js3.y);
-        at(4 * k2 + 2) = make_double2(s0.x - s2.x, s0.y - s2.y);
-        at(4 * k2 + 3) = make_double2(s1.x - js3.x, s1.y - js3.y);
+        const C js3 = INV ? mkc(-s3.y, s3.x) : mkc(s3.y, -s3.x);
+        at(4 * k2) = mkc(s0.x + s2.x, s0.y + s2.y);
+        at(4 * k2 + 1) = mkc(s1.x + js3.x, s1.y + js3.y);
+        at(4 * k2 + 2) = mkc(s0.x - s2.x, s0.y - s2.y);
+        at(4 * k2 + 3) = mkc(s1.x - js3.x, s1.y - js3.y);
     }
     __syncthreads();
 }
 
 // one axis of every tile: forward (natural -> digit-reversed) or inverse (digit-reversed -> natural)
-template <int N2, bool ALONG_V, bool INV, int ROW = 4 * N2>
-__device__ inline void tiles_axis(double2 *t, int ntile, const double2 *tw) {
+template <typename R, int N2, bool ALONG_V, bool INV, int ROW = 4 * N2>
+__device__ inline void tiles_axis(Cplx<R> *t, int ntile, const Cplx<R> *tw) {
+    using C = Cplx<R>;
     if (!INV) {
-        tiles_phase1<N2, ALONG_V, false, ROW>(t, ntile, tw);
-        tiles_phase2<N2, ALONG_V, false, ROW>(t, ntile);
+        tiles_phase1<R, N2, ALONG_V, false, ROW>(t, ntile, tw);
+        tiles_phase2<R, N2, ALONG_V, false, ROW>(t, ntile);
     } else {
-        tiles_phase2<N2, ALONG_V, true, ROW>(t, ntile);
-        tiles_phase1<N2, ALONG_V, true, ROW>(t, ntile, tw);
+        tiles_phase2<R, N2, ALONG_V, true, ROW>(t, ntile);
+        tiles_phase1<R, N2, ALONG_V, true, ROW>(t, ntile, tw);
     }
 }
 
@@ -790,82 +810,86 @@ __device__ inline void tiles_axis(double2 *t, int ntile, const double2 *tw) {
 // then the inverse of the three axes) or its real part to D (MODE 1).  40 B of HBM per value.
 constexpr int kAllThreads = 1024;
 
-template <int N2, int MODE>
-__global__ __launch_bounds__(kAllThreads) void k_rdft_all(double2 *X, double *D, const double2 *twg, int64_t ncell,
-                                                          double scale) {
+template <typename R, int N2, int MODE>
+__global__ __launch_bounds__(kAllThreads) void k_rdft_all(Cplx<R> *X, R *D, const Cplx<R> *twg, int64_t ncell,
+                                                          R scale) {
+    using C = Cplx<R>;
     constexpr int N = 4 * N2, NN = N * N, N3 = N * N * N, T = kAllThreads;
-    extern __shared__ double2 sm[];
-    double2 *t = sm, *tw = sm + N3;
+    extern __shared__ __align__(16) unsigned char smraw[];
+    C *sm = reinterpret_cast<C *>(smraw);
+    C *t = sm, *tw = sm + N3;
     const int64_t f = blockIdx.x;
-    double2 *xf = X + f * ncell;
-    const double *df = D + f * ncell;
+    C *xf = X + f * ncell;
+    const R *df = D + f * ncell;
     for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
     // eight loads in flight per thread (indices past the slab clamped to its last value, never stored)
     for (int i0 = (int)threadIdx.x; i0 < N3; i0 += 8 * T) {
         auto ld = [&](int k) { return xf[min(i0 + k * T, N3 - 1)]; };
-        const double2 a0 = ld(0), a1 = ld(1), a2 = ld(2), a3 = ld(3), a4 = ld(4), a5 = ld(5), a6 = ld(6), a7 = ld(7);
-        auto st = [&](int k, const double2 &a) {
+        const C a0 = ld(0), a1 = ld(1), a2 = ld(2), a3 = ld(3), a4 = ld(4), a5 = ld(5), a6 = ld(6), a7 = ld(7);
+        auto st = [&](int k, const C &a) {
             if (i0 + k * T < N3) t[i0 + k * T] = a;
         };
         st(0, a0), st(1, a1), st(2, a2), st(3, a3), st(4, a4), st(5, a5), st(6, a6), st(7, a7);
     }
     __syncthreads();
-    tiles_axis<N2, true, false>(t, N, tw);          // z, in the N x-planes
-    tiles_axis<N2, false, false>(t, N, tw);         // y
-    tiles_axis<N2, false, false, NN>(t, 1, tw);     // x: one N x N^2 tile
+    tiles_axis<R, N2, true, false>(t, N, tw);          // z, in the N x-planes
+    tiles_axis<R, N2, false, false>(t, N, tw);         // y
+    tiles_axis<R, N2, false, false, NN>(t, 1, tw);     // x: one N x N^2 tile
     if (MODE == 1) {
         for (int i = threadIdx.x; i < N3; i += T) D[f * ncell + i] = t[i].x;
         return;
     }
     for (int i0 = (int)threadIdx.x; i0 < N3; i0 += 8 * T) {
         auto ld = [&](int k) { return df[min(i0 + k * T, N3 - 1)]; };
-        const double d0 = ld(0), d1 = ld(1), d2 = ld(2), d3 = ld(3), d4 = ld(4), d5 = ld(5), d6 = ld(6), d7 = ld(7);
-        auto mul = [&](int k, double d) {
+        const R d0 = ld(0), d1 = ld(1), d2 = ld(2), d3 = ld(3), d4 = ld(4), d5 = ld(5), d6 = ld(6), d7 = ld(7);
+        auto mul = [&](int k, R d) {
             const int i = i0 + k * T;
             if (i < N3) {
-                const double s = d * scale;
-                t[i] = make_double2(t[i].x * s, t[i].y * s);
+                const R s = d * scale;
+                t[i] = mkc(t[i].x * s, t[i].y * s);
             }
         };
         mul(0, d0), mul(1, d1), mul(2, d2), mul(3, d3), mul(4, d4), mul(5, d5), mul(6, d6), mul(7, d7);
     }
     __syncthreads();
-    tiles_axis<N2, false, true, NN>(t, 1, tw);
-    tiles_axis<N2, false, true>(t, N, tw);
-    tiles_axis<N2, true, true>(t, N, tw);
+    tiles_axis<R, N2, false, true, NN>(t, 1, tw);
+    tiles_axis<R, N2, false, true>(t, N, tw);
+    tiles_axis<R, N2, true, true>(t, N, tw);
     for (int i = threadIdx.x; i < N3; i += T) xf[i] = t[i];
 }
 
 // passes 1 / 3: block (f, x0 .. x0 + PB), the (y, z) planes
-template <int N1, int N2, int PB>
-__global__ __launch_bounds__(256) void k_rdft_yz(double2 *X, const double2 *twg, int64_t ncell, int inv) {
+template <typename R, int N1, int N2, int PB>
+__global__ __launch_bounds__(256) void k_rdft_yz(Cplx<R> *X, const Cplx<R> *twg, int64_t ncell, int inv) {
+    using C = Cplx<R>;
     static_assert(N1 == 4, "4 x N2 points");
     constexpr int N = N1 * N2;
-    __shared__ double2 t[PB * N * N];
-    __shared__ double2 tw[N];
+    __shared__ C t[PB * N * N];
+    __shared__ C tw[N];
     const int x0 = blockIdx.y * PB, np = min(PB, N - x0);
-    double2 *p = X + (int64_t)blockIdx.x * ncell + (int64_t)x0 * N * N;
+    C *p = X + (int64_t)blockIdx.x * ncell + (int64_t)x0 * N * N;
     for (int i = threadIdx.x; i < N; i += 256) tw[i] = twg[i];
     for (int i = threadIdx.x; i < np * N * N; i += 256) t[i] = p[i];
     __syncthreads();
     if (inv) {
-        tiles_axis<N2, false, true>(t, np, tw);    // y, then z: the reverse of the forward order
-        tiles_axis<N2, true, true>(t, np, tw);
+        tiles_axis<R, N2, false, true>(t, np, tw);    // y, then z: the reverse of the forward order
+        tiles_axis<R, N2, true, true>(t, np, tw);
     } else {
-        tiles_axis<N2, true, false>(t, np, tw);    // z
-        tiles_axis<N2, false, false>(t, np, tw);   // y
+        tiles_axis<R, N2, true, false>(t, np, tw);    // z
+        tiles_axis<R, N2, false, false>(t, np, tw);   // y
     }
     for (int i = threadIdx.x; i < np * N * N; i += 256) p[i] = t[i];
 }
 
 // pass 2: block (f, y0 .. y0 + PB), the (x, z) tiles: forward along x, then times D * scale and the
 // inverse (MODE 0), or the real part to D (MODE 1)
-template <int N1, int N2, int PB, int MODE>
-__global__ __launch_bounds__(256) void k_rdft_x(double2 *X, double *D, const double2 *twg, int64_t ncell,
-                                                double scale) {
+template <typename R, int N1, int N2, int PB, int MODE>
+__global__ __launch_bounds__(256) void k_rdft_x(Cplx<R> *X, R *D, const Cplx<R> *twg, int64_t ncell,
+                                                R scale) {
+    using C = Cplx<R>;
     constexpr int N = N1 * N2;
-    __shared__ double2 t[PB * N * N];
-    __shared__ double2 tw[N];
+    __shared__ C t[PB * N * N];
+    __shared__ C tw[N];
     const int64_t f = blockIdx.x;
     const int y0 = blockIdx.y * PB, np = min(PB, N - y0);
     for (int i = threadIdx.x; i < N; i += 256) tw[i] = twg[i];
@@ -874,16 +898,16 @@ __global__ __launch_bounds__(256) void k_rdft_x(double2 *X, double *D, const dou
         t[i] = X[f * ncell + ((int64_t)x * N + y0 + tile) * N + z];
     }
     __syncthreads();
-    tiles_axis<N2, false, false>(t, np, tw);
+    tiles_axis<R, N2, false, false>(t, np, tw);
     for (int i = threadIdx.x; i < np * N * N; i += 256) {
         const int tile = i / (N * N), r = i - tile * N * N, x = r / N, z = r - x * N;
         const int64_t g = f * ncell + ((int64_t)x * N + y0 + tile) * N + z;
         if (MODE == 1) D[g] = t[i].x;
-        else t[i] = make_double2(t[i].x * D[g] * scale, t[i].y * D[g] * scale);
+        else t[i] = mkc(t[i].x * D[g] * scale, t[i].y * D[g] * scale);
     }
     if (MODE == 1) return;
     __syncthreads();
-    tiles_axis<N2, false, true>(t, np, tw);
+    tiles_axis<R, N2, false, true>(t, np, tw);
     for (int i = threadIdx.x; i < np * N * N; i += 256) {
         const int tile = i / (N * N), r = i - tile * N * N, x = r / N, z = r - x * N;
         X[f * ncell + ((int64_t)x * N + y0 + tile) * N + z] = t[i];
@@ -988,11 +1012,11 @@ __global__ __launch_bounds__(256) void k_fft_table_sym(const double2 *W, int pa,
     }
 }
 
-Tw16 roots16() {
-    Tw16 tw;
+template <typename R> Tw16<R> roots16() {
+    Tw16<R> tw;
     for (int k = 0; k < 8; k++) {
         const long double a = -2.0L * (long double)kPiF * k / 16.0L;
-        tw.w[k] = make_double2((double)cosl(a), (double)sinl(a));
+        tw.w[k] = mkc((R)cosl(a), (R)sinl(a));
     }
     return tw;
 }
@@ -1009,25 +1033,29 @@ size_t table_sym_lds(int pa) {
     return sizeof(double2) * ((size_t)pa * pa + 2 * (size_t)pa * pa * pa) + sizeof(double) * pa * pa * pa;
 }
 
-template <int NS, int MODE>
-void split_passes(ankh_plan_s *pl, double2 *X, double *D, double scale) {
+template <int NS, int MODE, typename R>
+void split_passes(ankh_plan_s *pl, Cplx<R> *X, R *D, const Cplx<R> *tw, R scale) {
     const dim3 g((unsigned)pl->fft_nf, NS), b(256);
-    hipLaunchKernelGGL((k_fft_yz<NS, false>), g, b, 0, pl->stream, X, pl->d_fftTw, pl->nleaf);
-    hipLaunchKernelGGL((k_fft_x<NS, MODE>), g, b, 0, pl->stream, X, D, pl->d_fftTw, pl->nleaf, scale);
-    if (MODE == 0) hipLaunchKernelGGL((k_fft_yz<NS, true>), g, b, 0, pl->stream, X, pl->d_fftTw, pl->nleaf);
+    hipLaunchKernelGGL((k_fft_yz<R, NS, false>), g, b, 0, pl->stream, X, tw, pl->nleaf);
+    hipLaunchKernelGGL((k_fft_x<R, NS, MODE>), g, b, 0, pl->stream, X, D, tw, pl->nleaf, scale);
+    if (MODE == 0) hipLaunchKernelGGL((k_fft_yz<R, NS, true>), g, b, 0, pl->stream, X, tw, pl->nleaf);
 }
 
-template <int MODE>
-hipError_t cells(ankh_plan_s *pl, double2 *X, double *D, double scale) {
-    if (pl->fft_single) {
+// The cell transforms of every kept node frequency in the working precision R: the spectrum X, the
+// real spectrum D and the roots tw of that precision.  Grids that are not 12, 20, 24 or a power of
+// two (direct DFTs) exist in float64 only.
+template <int MODE, typename R>
+hipError_t cells(ankh_plan_s *pl, Cplx<R> *X, R *D, const Cplx<R> *tw, R scale) {
+    if (sizeof(R) == 8 ? pl->fft_single : pl->fft_single32) {
         // one block per node frequency with all cells in LDS
-        const size_t shm = sizeof(double2) * ((size_t)pl->nleaf + pl->nside);
+        const size_t shm = sizeof(Cplx<R>) * ((size_t)pl->nleaf + pl->nside);
+        const dim3 g((unsigned)pl->fft_nf), b(kAllThreads);
         if (pl->nside == 12)
-            hipLaunchKernelGGL((k_rdft_all<3, MODE>), dim3((unsigned)pl->fft_nf), dim3(kAllThreads), shm, pl->stream, X, D,
-                               pl->d_fftTw, pl->nleaf, scale);
+            hipLaunchKernelGGL((k_rdft_all<R, 3, MODE>), g, b, shm, pl->stream, X, D, tw, pl->nleaf, scale);
+        else if (pl->nside == 20)
+            hipLaunchKernelGGL((k_rdft_all<R, 5, MODE>), g, b, shm, pl->stream, X, D, tw, pl->nleaf, scale);
         else
-            hipLaunchKernelGGL((k_rdft_all<5, MODE>), dim3((unsigned)pl->fft_nf), dim3(kAllThreads), shm, pl->stream, X, D,
-                               pl->d_fftTw, pl->nleaf, scale);
+            hipLaunchKernelGGL((k_rdft_all<R, 6, MODE>), g, b, shm, pl->stream, X, D, tw, pl->nleaf, scale);
         return hipGetLastError();
     }
     if (pl->fft_dft && (pl->nside == 12 || pl->nside == 20 || pl->nside == 24)) {
@@ -1035,13 +1063,12 @@ hipError_t cells(ankh_plan_s *pl, double2 *X, double *D, double scale) {
         // (PB N^2 complex values + N roots within 64 KB)
         const int n = pl->nside;
         const dim3 b(256);
-#define ANKH_RDFT(A, B, PB)                                                                                        \
-        {                                                                                                          \
-            const dim3 g((unsigned)pl->fft_nf, (unsigned)((n + PB - 1) / PB));                                    \
-            hipLaunchKernelGGL((k_rdft_yz<A, B, PB>), g, b, 0, pl->stream, X, pl->d_fftTw, pl->nleaf, 0);          \
-            hipLaunchKernelGGL((k_rdft_x<A, B, PB, MODE>), g, b, 0, pl->stream, X, D, pl->d_fftTw, pl->nleaf, scale); \
-            if (MODE == 0)                                                                                          \
-                hipLaunchKernelGGL((k_rdft_yz<A, B, PB>), g, b, 0, pl->stream, X, pl->d_fftTw, pl->nleaf, 1);      \
+#define ANKH_RDFT(A, B, PB)                                                                                    \
+        {                                                                                                      \
+            const dim3 g((unsigned)pl->fft_nf, (unsigned)((n + PB - 1) / PB));                                \
+            hipLaunchKernelGGL((k_rdft_yz<R, A, B, PB>), g, b, 0, pl->stream, X, tw, pl->nleaf, 0);            \
+            hipLaunchKernelGGL((k_rdft_x<R, A, B, PB, MODE>), g, b, 0, pl->stream, X, D, tw, pl->nleaf, scale); \
+            if (MODE == 0) hipLaunchKernelGGL((k_rdft_yz<R, A, B, PB>), g, b, 0, pl->stream, X, tw, pl->nleaf, 1); \
         }
         if (n == 12) ANKH_RDFT(4, 3, 4)
         else if (n == 20) ANKH_RDFT(4, 5, 2)
@@ -1050,45 +1077,54 @@ hipError_t cells(ankh_plan_s *pl, double2 *X, double *D, double scale) {
         return hipGetLastError();
     }
     if (pl->fft_dft) {
-        const int n = pl->nside;
-        const dim3 g((unsigned)pl->fft_nf, n), b(256);
-        const size_t shm = sizeof(double2) * (2 * (size_t)n * n + n);
-        hipLaunchKernelGGL(k_dft_yz, g, b, shm, pl->stream, X, pl->d_fftTw, n, pl->nleaf, 0);
-        hipLaunchKernelGGL(k_dft_x, g, b, shm, pl->stream, X, D, pl->d_fftTw, n, pl->nleaf, scale, MODE);
-        if (MODE == 0) hipLaunchKernelGGL(k_dft_yz, g, b, shm, pl->stream, X, pl->d_fftTw, n, pl->nleaf, 1);
-        return hipGetLastError();
+        if constexpr (sizeof(R) == 8) {
+            const int n = pl->nside;
+            const dim3 g((unsigned)pl->fft_nf, n), b(256);
+            const size_t shm = sizeof(double2) * (2 * (size_t)n * n + n);
+            hipLaunchKernelGGL(k_dft_yz, g, b, shm, pl->stream, X, tw, n, pl->nleaf, 0);
+            hipLaunchKernelGGL(k_dft_x, g, b, shm, pl->stream, X, D, tw, n, pl->nleaf, (double)scale, MODE);
+            if (MODE == 0) hipLaunchKernelGGL(k_dft_yz, g, b, shm, pl->stream, X, tw, n, pl->nleaf, 1);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
     }
     if (pl->fft_split) {
         switch (pl->nside) {
-            case 2: split_passes<2, MODE>(pl, X, D, scale); break;
-            case 4: split_passes<4, MODE>(pl, X, D, scale); break;
-            case 8: split_passes<8, MODE>(pl, X, D, scale); break;
-            case 16: split_passes<16, MODE>(pl, X, D, scale); break;
-            case 32: split_passes<32, MODE>(pl, X, D, scale); break;
-            default: split_passes<64, MODE>(pl, X, D, scale); break;
+            case 2: split_passes<2, MODE, R>(pl, X, D, tw, scale); break;
+            case 4: split_passes<4, MODE, R>(pl, X, D, tw, scale); break;
+            case 8: split_passes<8, MODE, R>(pl, X, D, tw, scale); break;
+            case 16: split_passes<16, MODE, R>(pl, X, D, tw, scale); break;
+            case 32: split_passes<32, MODE, R>(pl, X, D, tw, scale); break;
+            default: split_passes<64, MODE, R>(pl, X, D, tw, scale); break;
         }
         return hipGetLastError();
     }
-    const size_t shm = sizeof(double2) * pl->nleaf;
+    const size_t shm = sizeof(Cplx<R>) * pl->nleaf;
     const dim3 g((unsigned)pl->fft_nf), b(256);
-    const Tw16 tw = roots16();
+    const Tw16<R> t16 = roots16<R>();
     switch (pl->nside) {
-        case 1: hipLaunchKernelGGL((k_fft_cells<1, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, tw); break;
-        case 2: hipLaunchKernelGGL((k_fft_cells<2, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, tw); break;
-        case 4: hipLaunchKernelGGL((k_fft_cells<4, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, tw); break;
-        case 8: hipLaunchKernelGGL((k_fft_cells<8, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, tw); break;
-        default: hipLaunchKernelGGL((k_fft_cells<16, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, tw); break;
+        case 1: hipLaunchKernelGGL((k_fft_cells<R, 1, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, t16); break;
+        case 2: hipLaunchKernelGGL((k_fft_cells<R, 2, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, t16); break;
+        case 4: hipLaunchKernelGGL((k_fft_cells<R, 4, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, t16); break;
+        case 8: hipLaunchKernelGGL((k_fft_cells<R, 8, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, t16); break;
+        default: hipLaunchKernelGGL((k_fft_cells<R, 16, MODE>), g, b, shm, pl->stream, X, D, pl->nleaf, scale, t16); break;
     }
     return hipGetLastError();
 }
 
+__global__ void k_to_f32(const double *a, float *b, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
 }  // namespace
 
-// the one-block cell transform for 12^3 and 20^3 grids, where the device grants its LDS (queried,
-// and the kernels' dynamic limit raised when above the default)
-bool fft_single_ok(int nside) {
-    if (nside != 12 && nside != 20) return false;
-    const size_t need = sizeof(double2) * ((size_t)nside * nside * nside + nside);
+// the one-block cell transform, where the device grants its LDS (queried, and the kernels' dynamic
+// limit raised when above the default): 12^3 and 20^3 grids in float64, also 24^3 in float32
+bool fft_single_ok(int nside, bool f32) {
+    if (!(nside == 12 || nside == 20 || (f32 && nside == 24))) return false;
+    const size_t need = (f32 ? sizeof(float2) : sizeof(double2)) * ((size_t)nside * nside * nside + nside);
     int device = 0, lim = 0;
     if (hipGetDevice(&device) != hipSuccess ||
         hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
@@ -1098,11 +1134,19 @@ bool fft_single_ok(int nside) {
     if (need > (size_t)lim) return false;
     if (need > 65536) {
         const int bytes = (int)need;
-        if (nside == 12) return true;
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rdft_all<5, 0>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess ||
-            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rdft_all<5, 1>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) {
+        hipError_t e = hipSuccess;
+        if (f32) {
+            const void *k0 = nside == 20 ? reinterpret_cast<const void *>(&k_rdft_all<float, 5, 0>)
+                                         : reinterpret_cast<const void *>(&k_rdft_all<float, 6, 0>);
+            e = hipFuncSetAttribute(k0, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        } else if (nside == 20) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rdft_all<double, 5, 0>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rdft_all<double, 5, 1>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        }
+        if (e != hipSuccess) {
             (void)hipGetLastError();
             return false;
         }
@@ -1179,7 +1223,14 @@ hipError_t launch_fft_build_D(ankh_plan_s *pl) {
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return cells<1>(pl, pl->d_fftX, pl->d_fftD, 1.0);
+    return cells<1, double>(pl, pl->d_fftX, pl->d_fftD, pl->d_fftTw, 1.0);
+}
+
+// the float32 copy of the real spectrum (mixed modes), from the float64 one built above
+hipError_t launch_fft_D_to_f32(ankh_plan_s *pl) {
+    hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, pl->stream, pl->d_fftD, pl->d_fftD32,
+                       (int64_t)pl->fft_nf * pl->nleaf);
+    return hipGetLastError();
 }
 
 // the register-blocked kernels for equispaced order = Chebyshev order <= 6 (four leaves per block
@@ -1187,6 +1238,13 @@ hipError_t launch_fft_build_D(ankh_plan_s *pl) {
 static bool fast_nodes(const ankh_plan_s *pl) {
     return pl->eq_order == pl->order && pl->order >= 3 && pl->order <= 6 && pl->nleaf % (8 * kCB) == 0 &&
            pl->nleaf % kCF == 0;
+}
+
+// the mixed modes run the transforms of an evaluation in float32 where every kernel of the plan has a
+// float32 form: the register-blocked node transforms and any cell transform but the direct DFTs
+bool fft_f32_ok(const ankh_plan_s *pl) {
+    const bool dft_only = pl->fft_dft && !(pl->nside == 12 || pl->nside == 20 || pl->nside == 24);
+    return fast_nodes(pl) && !dft_only;
 }
 
 #define ANKH_FFT_ORDERS(L, X) \
@@ -1202,10 +1260,19 @@ hipError_t launch_fft_forward(ankh_plan_s *pl) {
     const double *Q = pl->d_M + pl->lv[pl->depth].cell0 * pl->nup;
     if (fast_nodes(pl)) {
         const dim3 g((unsigned)(pl->nleaf / kCF)), b(kFT);
-#define ANKH_FWD(LL) \
-        hipLaunchKernelGGL(k_fft_nodes_fwd_t<LL>, g, b, 0, pl->stream, Q, pl->nup, pl->d_fftB, pl->d_fftX, pl->nleaf)
-        ANKH_FFT_ORDERS(L, ANKH_FWD)
+        if (pl->fft_f32) {
+#define ANKH_FWD(LL)                                                                                                \
+            hipLaunchKernelGGL((k_fft_nodes_fwd_t<float, LL>), g, b, 0, pl->stream, Q, pl->nup, pl->d_fftB32, pl->d_fftX32, \
+                               pl->nleaf)
+            ANKH_FFT_ORDERS(L, ANKH_FWD)
 #undef ANKH_FWD
+        } else {
+#define ANKH_FWD(LL)                                                                                                \
+            hipLaunchKernelGGL((k_fft_nodes_fwd_t<double, LL>), g, b, 0, pl->stream, Q, pl->nup, pl->d_fftB, pl->d_fftX, \
+                               pl->nleaf)
+            ANKH_FFT_ORDERS(L, ANKH_FWD)
+#undef ANKH_FWD
+        }
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_fft_nodes_fwd, dim3((unsigned)pl->nleaf), dim3(64), nodes_fwd_lds(L, pa), pl->stream, Q,
@@ -1215,7 +1282,8 @@ hipError_t launch_fft_forward(ankh_plan_s *pl) {
 
 hipError_t launch_fft_cells(ankh_plan_s *pl) {
     const double n6 = (double)pl->nleaf * pl->fft_pa * pl->fft_pa * pl->fft_pa;
-    return cells<0>(pl, pl->d_fftX, pl->d_fftD, 1.0 / n6);
+    if (pl->fft_f32) return cells<0, float>(pl, pl->d_fftX32, pl->d_fftD32, pl->d_fftTw32, (float)(1.0 / n6));
+    return cells<0, double>(pl, pl->d_fftX, pl->d_fftD, pl->d_fftTw, 1.0 / n6);
 }
 
 hipError_t launch_fft_inverse(ankh_plan_s *pl) {
@@ -1223,10 +1291,19 @@ hipError_t launch_fft_inverse(ankh_plan_s *pl) {
     double *Lam = pl->d_L + pl->lv[pl->depth].cell0 * pl->nup;
     if (fast_nodes(pl)) {
         const dim3 g((unsigned)(pl->nleaf / kCB)), b(256);
-#define ANKH_INV(LL) \
-        hipLaunchKernelGGL(k_fft_nodes_inv_t<LL>, g, b, 0, pl->stream, pl->d_fftX, pl->d_fftB, Lam, pl->nup, pl->nleaf)
-        ANKH_FFT_ORDERS(L, ANKH_INV)
+        if (pl->fft_f32) {
+#define ANKH_INV(LL)                                                                                                \
+            hipLaunchKernelGGL((k_fft_nodes_inv_t<float, LL>), g, b, 0, pl->stream, pl->d_fftX32, pl->d_fftB32, Lam, \
+                               pl->nup, pl->nleaf)
+            ANKH_FFT_ORDERS(L, ANKH_INV)
 #undef ANKH_INV
+        } else {
+#define ANKH_INV(LL)                                                                                                \
+            hipLaunchKernelGGL((k_fft_nodes_inv_t<double, LL>), g, b, 0, pl->stream, pl->d_fftX, pl->d_fftB, Lam,    \
+                               pl->nup, pl->nleaf)
+            ANKH_FFT_ORDERS(L, ANKH_INV)
+#undef ANKH_INV
+        }
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_fft_nodes_inv, dim3((unsigned)pl->nleaf), dim3(64), nodes_inv_lds(L, pa, ph), pl->stream,

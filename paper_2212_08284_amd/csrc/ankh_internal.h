@@ -128,6 +128,12 @@ struct ankh_plan_s {
     double2 *d_fftB = nullptr, *d_fftW = nullptr, *d_fftX = nullptr;
     double2 *d_fftTw = nullptr;   // e^{-2 pi i k / n}: k < n/2 (radix 2) or k < n (direct DFT), three-pass path
     double *d_fftD = nullptr;
+    // mixed modes: the spectrum, its node-transform matrix, the roots and the real spectrum in float32
+    // (the float64 X and D above are freed once D is built)
+    bool fft_f32 = false;
+    bool fft_single32 = false;    // float32 cell transforms in one block per node frequency (12, 20, 24 per axis)
+    float2 *d_fftX32 = nullptr, *d_fftB32 = nullptr, *d_fftTw32 = nullptr;
+    float *d_fftD32 = nullptr;
     size_t bytes = 0;
     int device = 0;               // the HIP device current at plan time (the plan's buffers live there)
     size_t bytes_limit = 0;       // ankh_overrides.workspace_limit (0 = none)
@@ -183,10 +189,12 @@ hipError_t launch_build_cper(ankh_plan_s *pl);
 hipError_t launch_convert_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 // ANKH-FFT (ankh_fft.hip)
 bool fft_supported(int depth, int L, int eq_order);
-bool fft_single_ok(int nside);
+bool fft_single_ok(int nside, bool f32);
 void fft_host_tables(int L, int eq_order, const double *cheb_nodes, std::vector<double2> &B, std::vector<double2> &W);
 void fft_host_roots(int nside, bool full, std::vector<double2> &tw);
 hipError_t launch_fft_build_D(ankh_plan_s *pl);    // plan time: the real spectrum D
+hipError_t launch_fft_D_to_f32(ankh_plan_s *pl);   // plan time: its float32 copy (mixed modes)
+bool fft_f32_ok(const ankh_plan_s *pl);            // every transform of the plan has a float32 form
 hipError_t launch_fft_forward(ankh_plan_s *pl);    // leaf multipoles -> half spectrum X
 hipError_t launch_fft_cells(ankh_plan_s *pl);      // cell transforms, product with D, inverse
 hipError_t launch_fft_inverse(ankh_plan_s *pl);    // X -> leaf local expansions

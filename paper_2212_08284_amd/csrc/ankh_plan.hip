@@ -56,7 +56,7 @@ void free_all(ankh_plan_s *pl) {
                     pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr,
                     pl->d_Kb, pl->d_Mb, pl->d_enear, pl->d_slot_f, pl->d_slot_g, pl->d_cper_part,
                     pl->d_U, pl->d_Mc, pl->d_Lc, pl->d_ind, pl->d_mom, pl->d_fftB, pl->d_fftW, pl->d_fftX,
-                    pl->d_fftD, pl->d_fftTw};
+                    pl->d_fftD, pl->d_fftTw, pl->d_fftX32, pl->d_fftB32, pl->d_fftTw32, pl->d_fftD32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &set : pl->evsets)
@@ -93,11 +93,15 @@ int depth_for(int64_t n, int nu) {
 
 // ANKH-FFT leaves per axis: no octree levels above the leaves, so any grid with fast cell transforms
 // (powers of two up to 64; 12, 20, 24) is a candidate.  The far field costs little against the pair
-// kernel, so the grid targets fewer atoms per leaf than the octree rule: 0.17 n_u (36 at order 6),
-// the best of 16^3, 20^3 and 24^3 on the 288,000-atom water box.
+// kernel, so the grid targets far fewer atoms per leaf than the octree rule: 0.1 n_u (22 at order 6)
+// from 100,000 atoms, 0.17 n_u below.  On the 288,000-atom water box 24^3 leaves (21 atoms each) take
+// 0.99 ms per mixed evaluation and 1.72 ms in FP64, against 1.15 / 1.91 ms on 20^3 and 1.73 / 2.86 ms
+// on 16^3, at a relative energy error of 1.8e-7.  Small boxes gain little time from small leaves and
+// lose accuracy (the far field carries more of the energy): a 600-atom water box at 1e-6 has a
+// relative energy error of 5.9e-6 on 4^3 leaves against 6e-7 on 2^3.
 int leaves_for(int64_t n, int nu) {
     static const int cand[] = {1, 2, 4, 8, 12, 16, 20, 24, 32, 64};
-    const double occ = std::max(12.0, 0.17 * nu);
+    const double occ = std::max(12.0, (n >= 100000 ? 0.1 : 0.17) * nu);
     const double target = std::cbrt(std::max(1.0, (double)n / occ));
     int best = 1;
     double bd = 1e300;
@@ -411,7 +415,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
     // DFTs along each axis on a grid that is not a power of two
     pl->fft_dft = grid != 0;
     pl->fft_split = fft && !grid && pl->nside >= 2 && (pl->nside > 16 || (ov && ov->fft_split == 1));
-    pl->fft_single = fft && grid && !(ov && ov->fft_split == 1) && fft_single_ok(grid);
+    pl->fft_single = fft && grid && !(ov && ov->fft_split == 1) && fft_single_ok(grid, false);
     pl->nleaf = (int64_t)pl->nside * pl->nside * pl->nside;
     size_t cells = 0;
     for (int e = 0; e <= pl->depth; e++) {
@@ -619,6 +623,29 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
             ck(hipMemcpy(pl->d_fftB, B.data(), B.size() * sizeof(double2), hipMemcpyHostToDevice));
             ck(hipMemcpy(pl->d_fftW, W.data(), W.size() * sizeof(double2), hipMemcpyHostToDevice));
             ck(launch_fft_build_D(pl));
+            pl->fft_f32 = precision != ANKH_FP64 && fft_f32_ok(pl);
+            pl->fft_single32 = pl->fft_f32 && grid && !(ov && ov->fft_split == 1) && fft_single_ok(grid, true);
+            if (pl->fft_f32) {
+                // mixed modes: the transforms of an evaluation in float32 (half the spectrum's bytes); the
+                // float64 spectrum and work array only served the plan-time build of D
+                const size_t nx = (size_t)pl->fft_nf * pl->nleaf;
+                std::vector<float2> B32(B.size()), tw32(tw.size());
+                for (size_t i = 0; i < B.size(); i++) B32[i] = make_float2((float)B[i].x, (float)B[i].y);
+                for (size_t i = 0; i < tw.size(); i++) tw32[i] = make_float2((float)tw[i].x, (float)tw[i].y);
+                dalloc(pl, &pl->d_fftB32, B32.size());
+                dalloc(pl, &pl->d_fftTw32, tw32.size());
+                dalloc(pl, &pl->d_fftD32, nx);
+                ck(hipMemcpy(pl->d_fftB32, B32.data(), B32.size() * sizeof(float2), hipMemcpyHostToDevice));
+                ck(hipMemcpy(pl->d_fftTw32, tw32.data(), tw32.size() * sizeof(float2), hipMemcpyHostToDevice));
+                ck(launch_fft_D_to_f32(pl));
+                ck(hipStreamSynchronize(pl->stream));
+                ck(hipFree(pl->d_fftX));
+                ck(hipFree(pl->d_fftD));
+                pl->d_fftX = nullptr;
+                pl->d_fftD = nullptr;
+                pl->bytes -= nx * (sizeof(double2) + sizeof(double));
+                dalloc(pl, &pl->d_fftX32, nx);
+            }
         } else {
             ck(launch_build_cper(pl));
         }
@@ -750,10 +777,11 @@ ankh_status ankh_get_stats(ankh_plan_t pl, ankh_plan_stats *out) {
     for (int e = 0; e < 8; e++) out->m2l_rank[e] = (e >= 1 && e <= pl->depth) ? pl->m2l_rank[e] : 0;
     out->far_field = pl->far_field;
     out->overlap = pl->overlap ? 1 : 0;
-    out->fft_split = (pl->fft_split || (pl->fft_dft && !pl->fft_single)) ? 1 : 0;
+    out->fft_split = (pl->fft_split || (pl->fft_dft && !(pl->fft_f32 ? pl->fft_single32 : pl->fft_single))) ? 1 : 0;
     out->eq_order = pl->far_field == ANKH_FAR_FFT ? pl->eq_order : 0;
     out->near_precision = pl->precision == ANKH_FP64 ? 0 : 1;
-    out->far_precision = pl->precision == ANKH_FP64 || pl->far_field == ANKH_FAR_FFT ? 0
+    out->far_precision = pl->precision == ANKH_FP64 ? 0
+                         : pl->far_field == ANKH_FAR_FFT ? (pl->fft_f32 ? 1 : 0)
                          : (pl->precision == ANKH_MIXED_BF16X3 ? 2 : 1);
     out->near_pairs = -1;
     if (pl->last_kind) {

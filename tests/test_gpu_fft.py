@@ -124,17 +124,22 @@ def test_fft_stage_parity_any_leaf_grid(ak, leaves, order, eq, kind, split):
     pl.close()
 
 
-@pytest.mark.parametrize("leaves", [16, 24])
+@pytest.mark.parametrize("leaves", [16, 20, 24])
 def test_fft_water_288000_other_grids(ak, leaves):
-    """The benchmark box on the 16^3 octree level (one-block cell transforms) and on a 24^3 grid (4 x 6
-    two-phase transforms): FP64 against ANKH-FMM at depth 4 and the stored oracle atoms; mixed
-    against FP64."""
+    """The benchmark box on the 16^3 octree level (one-block cell transforms), on a 20^3 grid (4 x 5
+    two-phase transforms, one block per node frequency) and on the planner's 24^3 grid (4 x 6, three
+    passes in float64): FP64 against ANKH-FMM at depth 4 and the stored oracle atoms; mixed against
+    FP64."""
     d = synth.workload("water_288000")
     n = len(d["q"])
     pl, e, F, G = _run(ak, d, eps=1e-6, leaves=leaves)
     assert pl.stats["leaves_per_axis"] == leaves
     pl.close()
     pm, em, Fm, Gm = _run(ak, d, eps=1e-6, prec="mixed_bf16x3", leaves=leaves)
+    # the mixed modes: float32 transforms, in one block per node frequency on 24^3 (110 KB of LDS)
+    assert pm.stats["far_precision"] == 1
+    if leaves in (20, 24):
+        assert pm.stats["fft_split"] == 0
     pm.close()
     pf = ak.Plan(n, 0.5 * d["edge"], 1e-6, 2, "fp64", far="fmm")
     ef, Ff, Gf = pf.energy_forces(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
@@ -225,14 +230,16 @@ def test_fft_adjoint_is_gradient_of_energy(ak, leaves):
 
 
 def test_fft_water_288000_full_size(ak):
-    """The benchmark box on the planner's grid (20^3 leaves, 36 atoms each: the two-phase 4 x 5 cell
-    transforms), the configuration bench.py times: FP64 ANKH-FFT against ANKH-FMM and the stored
-    oracle atoms; the mixed modes against FP64 ANKH-FFT."""
+    """The benchmark box on the planner's grid (24^3 leaves, 21 atoms each: the two-phase 4 x 6 cell
+    transforms, in one block per node frequency in float32), the configuration bench.py times: FP64
+    ANKH-FFT against ANKH-FMM and the stored oracle atoms; the mixed modes against FP64 ANKH-FFT.
+    Smaller leaves hand closer pairs to the interpolated far field, so at 24^3 the fields of the two
+    methods differ by ~3e-5 at the same order."""
     d = synth.workload("water_288000")
     out = {}
     for prec in ("fp64", "mixed", "mixed_bf16x3"):
         pl, e, F, G = _run(ak, d, eps=1e-6, prec=prec)
-        assert pl.stats["leaves_per_axis"] == 20
+        assert pl.stats["leaves_per_axis"] == 24
         out[prec] = (e, F, G)
         pl.close()
     n = len(d["q"])
@@ -244,7 +251,7 @@ def test_fft_water_288000_full_size(ak):
     e64, F64, G64 = out["fp64"]
     assert abs(e64 - ef) <= 1e-6 * abs(ef)
     assert rel_rms(F64, Ff) <= 1e-5
-    assert rel_rms(G64, Gf) <= 2e-5
+    assert rel_rms(G64, Gf) <= 5e-5
     for prec in ("mixed", "mixed_bf16x3"):
         e, F, G = out[prec]
         assert abs(e - e64) <= 1e-5 * abs(e64)
@@ -260,12 +267,12 @@ def test_fft_water_288000_full_size(ak):
 
 def test_fft_derivs_run_on_the_fft_far_field(ak):
     """ankh_energy_derivs evaluates through the same far field: its outputs agree with ANKH-FMM within
-    the approximation error."""
+    the approximation error, on the same leaves (depth 1, the octree rule's choice for this box)."""
     d = synth.water(300, seed=5)
     n = len(d["q"])
     out = {}
     for far in ("fmm", "fft"):
-        pl = ak.Plan(n, 0.5 * d["edge"], 1e-7, 2, "fp64", far=far)
+        pl = ak.Plan(n, 0.5 * d["edge"], 1e-7, 2, "fp64", far=far, depth=1)
         o = pl.energy_derivs(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
         pl.sync()
         out[far] = {k: v.cpu().numpy() for k, v in o.items()}
