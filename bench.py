@@ -446,6 +446,7 @@ def main():
 
     far_other = None
     roof_m2l = None
+    roof_m2l_f32 = None
     if not args.no_far_compare:
         alt = "fft" if args.far == "fmm" else "fmm"
         pa = ak.Plan(n, rB, args.eps, 2, args.mode, far=alt, overlap=ovl, depth=args.depth)
@@ -459,6 +460,13 @@ def main():
             roof_m2l = m2l_roofline(st_a, bd_a, args.mode)
         pa.close()
         log(f"{alt}: {far_other}")
+        if alt == "fmm" and args.mode != "mixed":
+            # the same ANKH-FMM contraction on the float32 matrix cores (ANKH_MIXED): its own peak
+            pf32 = ak.Plan(n, rB, args.eps, 2, "mixed", far="fmm", overlap=ovl, depth=args.depth)
+            t_f, st_f, bd_f, _ = timed_run(pf32, args_dev, args.steps, args.warmup, torch)
+            far_other["mixed_fp32_mfma"] = {"ms_per_step": t_f * 1e3, "value": n / t_f, "stage_ms": bd_f}
+            roof_m2l_f32 = m2l_roofline(st_f, bd_f, "mixed")
+            pf32.close()
     if args.far == "fmm":
         roof_m2l = m2l_roofline(st_mixed, bd_mixed, args.mode)
 
@@ -551,6 +559,8 @@ def main():
         line["roofline_fft_cells"] = roof_far
     if roof_m2l is not None:
         line["roofline_m2l"] = roof_m2l
+    if roof_m2l_f32 is not None:
+        line["roofline_m2l_fp32"] = roof_m2l_f32
     line.update(res)
     line["vs_oracle"] = vs_oracle
     if far_other is not None:
