@@ -56,6 +56,12 @@ def lib():
                                            ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_dtensor.restype = ctypes.c_int
         L.oracle_dtensor.argtypes = [dp, ctypes.c_double, ctypes.c_int, dp]
+        L.oracle_ewald_o3.restype = ctypes.c_int
+        L.oracle_ewald_o3.argtypes = [ctypes.c_int64, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.oracle_near_field_o3.restype = ctypes.c_int
+        L.oracle_near_field_o3.argtypes = [ctypes.c_int64, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_int, ctypes.c_int, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -89,13 +95,16 @@ def ewald_params(n: int, edge: float, eps: float = 1e-10, alpha: float | None = 
 
 
 def ewald(pos, q, mu=None, theta=None, edge=None, eps: float = 1e-10, alpha: float | None = None,
-          grad: bool = True, nthreads: int = 0, rc: float | None = None, kmax: int | None = None):
-    """Classical Ewald energy (and forces -dE/dx, fields dE/dmu when grad)."""
+          grad: bool = True, nthreads: int = 0, rc: float | None = None, kmax: int | None = None, omega=None):
+    """Classical Ewald energy (and forces -dE/dx, fields dE/dmu when grad).  omega: optional traceless
+    octupoles [n][10] as (xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz, yzz, zzz), used literally in
+    Omega : grad grad grad."""
     pos = _c64(pos, (-1, 3))
     n = pos.shape[0]
     q = _c64(q, (n,))
     mu = _c64(mu, (n, 3))
     theta = _c64(theta, (n, 6))
+    omega = _c64(omega, (n, 10))
     a, r, k = ewald_params(n, edge, eps, alpha)
     if rc is not None:
         r = rc
@@ -104,8 +113,8 @@ def ewald(pos, q, mu=None, theta=None, edge=None, eps: float = 1e-10, alpha: flo
     eo = np.zeros(5)
     F = np.zeros((n, 3)) if grad else None
     G = np.zeros((n, 3)) if grad else None
-    rcode = lib().oracle_ewald(n, _p(pos), _p(q), _p(mu), _p(theta), float(edge), float(a), float(r),
-                               int(k), int(nthreads), _p(eo), _p(F), _p(G))
+    rcode = lib().oracle_ewald_o3(n, _p(pos), _p(q), _p(mu), _p(theta), _p(omega), float(edge), float(a),
+                                  float(r), int(k), int(nthreads), _p(eo), _p(F), _p(G))
     if rcode != 0:
         raise ValueError(f"oracle_ewald failed ({rcode})")
     out = dict(energy=float(eo[4]), e_real=float(eo[0]), e_rec=float(eo[1]), e_self=float(eo[2]),

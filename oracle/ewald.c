@@ -8,7 +8,7 @@
  *
  * What it computes: the tin-foil periodic energy of eq. (1) of the paper,
  *   E = 1/2 sum_t sum_x sum_y D_x D_y 1/|x - y + t|,
- *   D_u = q_u + mu_u . grad + Theta_u : grad grad,
+ *   D_u = q_u + mu_u . grad + Theta_u : grad grad (+ Omega_u : grad grad grad),
  * (the x = y, t = 0 term omitted), split as in the Ewald summation of the
  * ANKH-FMM section (real + reciprocal + self, plus the neutralising
  * background for non-neutral cells).  The printed reciprocal term and its
@@ -18,6 +18,13 @@
  *   S(k)  = sum_j (q_j + i mu_j.k - Theta_j : k k) exp(i k . r_j).
  * Self term (eq. for E_self, valid for traceless Theta):
  *   E_self = -(a / sqrt(pi)) sum (q^2 + 2a^2/3 |mu|^2 + 8a^4/5 Theta:Theta).
+ * Octupoles (the higher multipole order the paper's operator D admits): Omega
+ * is the full symmetric traceless rank-3 tensor used literally in
+ * Omega : grad grad grad; its reciprocal factor is -i Omega : k k k and its
+ * self term -(a / sqrt(pi)) 48 a^6 / 7 Omega:Omega.  In general the moment of
+ * rank l contributes (2 a^2)^l l! / (2 l + 1) M:M: the Taylor term of order 2l
+ * of erf(a r)/r at r = 0, of which only the l! index pairings across the two
+ * traceless tensors survive.
  * Background: E_bg = -pi Q^2 / (2 V a^2), Q = sum q.
  * Theta is the full symmetric tensor used literally in Theta : grad grad.
  *
@@ -43,8 +50,8 @@
 #include <omp.h>
 #endif
 
-#define MAXRANK 5
-#define NTUPLE5 243
+#define MAXRANK 7         /* rank of the octupole-octupole force tensor */
+#define NTUPLE5 2187      /* 3^MAXRANK index tuples */
 
 /* ---- derivative-tensor term tables ----------------------------------- */
 typedef struct {
@@ -221,11 +228,30 @@ typedef struct {
     const double *q, *mu;
     double *pos;      /* wrapped copy */
     double *Th;       /* full 3x3 per atom, or NULL */
+    double *Om;       /* full 3x3x3 per atom, or NULL */
     int order;        /* highest multipole present */
     /* cell list */
     int nc, R;
     int *cell_start, *cell_atoms;
 } ctx_t;
+
+/* full symmetric 3x3x3 from (xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz, yzz, zzz) */
+static void omega_full(const double *om, double Om[27])
+{
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++)
+            for (int c = 0; c < 3; c++) {
+                int n[3] = {0, 0, 0};
+                n[a]++; n[b]++; n[c]++;
+                /* index of the sorted triple in the stored order */
+                int k;
+                if (n[0] == 3) k = 0;
+                else if (n[0] == 2) k = n[1] == 1 ? 1 : 2;
+                else if (n[0] == 1) k = n[1] == 2 ? 3 : (n[1] == 1 ? 4 : 5);
+                else k = n[1] == 3 ? 6 : (n[1] == 2 ? 7 : (n[1] == 1 ? 8 : 9));
+                Om[(a * 3 + b) * 3 + c] = om[k];
+            }
+}
 
 static void ctx_init(ctx_t *c, int64_t n, const double *pos, const double *q, const double *mu,
                      const double *theta, double L, double a, double rc, int kmax)
@@ -244,6 +270,7 @@ static void ctx_init(ctx_t *c, int64_t n, const double *pos, const double *q, co
         c->Th = (double *)malloc(sizeof(double) * 9 * (n > 0 ? n : 1));
         for (int64_t i = 0; i < n; i++) theta_full(theta + 6 * i, c->Th + 9 * i);
     }
+    c->Om = NULL;
     c->order = theta ? 2 : (mu ? 1 : 0);
     int nc = (int)floor(L / rc);
     if (nc < 1) nc = 1;
@@ -275,9 +302,73 @@ static void ctx_init(ctx_t *c, int64_t n, const double *pos, const double *q, co
     free(cid);
 }
 
+static void ctx_set_omega(ctx_t *c, const double *omega)
+{
+    if (!omega) return;
+    c->Om = (double *)malloc(sizeof(double) * 27 * (c->n > 0 ? c->n : 1));
+    for (int64_t i = 0; i < c->n; i++) omega_full(omega + 10 * i, c->Om + 27 * i);
+    c->order = 3;
+}
+
 static void ctx_free(ctx_t *c)
 {
-    free(c->pos); free(c->Th); free(c->cell_start); free(c->cell_atoms);
+    free(c->pos); free(c->Th); free(c->Om); free(c->cell_start); free(c->cell_atoms);
+}
+
+/*
+ * The pair functional on full tensors of every rank present, for moments up to
+ * octupoles:  Phi = sum_{a,b} (-1)^b M_i^a : T^(a+b) : M_j^b,  M^0 = q, M^1 = mu,
+ * M^2 = Theta, M^3 = Omega (each contracted with the first a / last b indices;
+ * the sign because grad_{x_j} = -grad_r).  grad >= 0 selects the component of the
+ * gradient (rank + 1).  The explicit functional above is the same sum for q, mu
+ * and Theta.
+ */
+static double pair_phi_gen(double T[MAXRANK + 1][NTUPLE5], int grad, const double *Mi[4], const double *Mj[4])
+{
+    double e = 0.0;
+    for (int a = 0; a < 4; a++) {
+        if (!Mi[a]) continue;
+        const int na = ipow3(a);
+        for (int b = 0; b < 4; b++) {
+            if (!Mj[b]) continue;
+            const int nb = ipow3(b), n = a + b;
+            const double sign = (b & 1) ? -1.0 : 1.0;
+            double s = 0.0;
+            for (int I = 0; I < na; I++) {
+                const double mi = Mi[a][I];
+                if (mi == 0.0) continue;
+                for (int J = 0; J < nb; J++) {
+                    const int t = I * nb + J;
+                    s += mi * Mj[b][J] * (grad < 0 ? T[n][t] : T[n + 1][t * 3 + grad]);
+                }
+            }
+            e += sign * s;
+        }
+    }
+    return e;
+}
+
+/* field on i: dPhi/dmu_i = sum_b (-1)^b T^(1+b) : M_j^b */
+static void pair_field_gen(double T[MAXRANK + 1][NTUPLE5], const double *Mj[4], double f[3])
+{
+    for (int e = 0; e < 3; e++) {
+        double s = 0.0;
+        for (int b = 0; b < 4; b++) {
+            if (!Mj[b]) continue;
+            const int nb = ipow3(b);
+            const double sign = (b & 1) ? -1.0 : 1.0;
+            for (int J = 0; J < nb; J++) s += sign * Mj[b][J] * T[1 + b][e * nb + J];
+        }
+        f[e] = s;
+    }
+}
+
+static void moments_of(const ctx_t *c, int64_t i, const double *M[4])
+{
+    M[0] = c->q + i;
+    M[1] = c->mu ? c->mu + 3 * i : NULL;
+    M[2] = c->Th ? c->Th + 9 * i : NULL;
+    M[3] = c->Om ? c->Om + 27 * i : NULL;
 }
 
 /* real-space sum for atom i: energy contribution (1/2 sum over its pairs),
@@ -324,6 +415,21 @@ static void real_atom(const ctx_t *c, int64_t i, int want_grad, double *ei, doub
             if (j == i && sh[0] == 0 && sh[1] == 0 && sh[2] == 0) continue;
             radial(r2, c->a, nmax, B);
             dtensors(r, B, nmax, T);
+            if (c->Om) {
+                const double *Mi[4], *Mj[4];
+                moments_of(c, i, Mi);
+                moments_of(c, j, Mj);
+                e += 0.5 * pair_phi_gen(T, -1, Mi, Mj);
+                if (want_grad) {
+                    for (int d = 0; d < 3; d++) f[d] -= pair_phi_gen(T, d, Mi, Mj);
+                    if (mi) {
+                        double h[3];
+                        pair_field_gen(T, Mj, h);
+                        for (int d = 0; d < 3; d++) g[d] += h[d];
+                    }
+                }
+                continue;
+            }
             const double *mj = c->mu ? c->mu + 3 * j : NULL;
             const double *Tj = c->Th ? c->Th + 9 * j : NULL;
             e += 0.5 * pair_phi(T, -1, qi, mi, Ti, c->q[j], mj, Tj);
@@ -343,6 +449,15 @@ static void real_atom(const ctx_t *c, int64_t i, int want_grad, double *ei, doub
 }
 
 /* ---- reciprocal space ------------------------------------------------ */
+/* Om : k k k */
+static double om_kkk(const double *Om, const double k[3])
+{
+    double s = 0.0;
+    for (int a = 0; a < 3; a++) for (int b = 0; b < 3; b++) for (int c = 0; c < 3; c++)
+        s += Om[(a * 3 + b) * 3 + c] * k[a] * k[b] * k[c];
+    return s;
+}
+
 typedef struct {
     int nk;
     int *m;             /* [nk][3], half space */
@@ -391,13 +506,14 @@ static void rec_build(const ctx_t *c, rec_t *rc)
         double k[3] = {2 * M_PI * m[0] / L, 2 * M_PI * m[1] / L, 2 * M_PI * m[2] / L};
         double sre = 0, sim = 0;
         for (int64_t i = 0; i < n; i++) {
-            /* a_i = q - Th:kk + i mu.k */
+            /* a_i = q - Th:kk + i (mu.k - Om:kkk) */
             double are = c->q[i], aim = 0;
             if (c->mu) aim = c->mu[3 * i] * k[0] + c->mu[3 * i + 1] * k[1] + c->mu[3 * i + 2] * k[2];
             if (c->Th) {
                 const double *T = c->Th + 9 * i;
                 for (int x = 0; x < 3; x++) for (int y = 0; y < 3; y++) are -= T[3 * x + y] * k[x] * k[y];
             }
+            if (c->Om) aim -= om_kkk(c->Om + 27 * i, k);
             double pr = 1, pi = 0;
             for (int d = 0; d < 3; d++) {
                 double er = rc->ex_re[((size_t)i * 3 + d) * W + m[d] + K];
@@ -446,6 +562,7 @@ static void rec_atom(const ctx_t *c, const rec_t *rc, int64_t i, double dr[3], d
             const double *T = c->Th + 9 * i;
             for (int x = 0; x < 3; x++) for (int y = 0; y < 3; y++) are -= T[3 * x + y] * k[x] * k[y];
         }
+        if (c->Om) aim -= om_kkk(c->Om + 27 * i, k);
         double pr = 1, pi = 0;
         for (int d = 0; d < 3; d++) {
             double er = rc->ex_re[((size_t)i * 3 + d) * W + m[d] + K];
@@ -487,6 +604,12 @@ static void self_terms(const ctx_t *c, int64_t i, double *e, double g[3])
         for (int x = 0; x < 9; x++) tt += T[x] * T[x];
         s += (8 * a * a * a * a / 5) * tt;
     }
+    if (c->Om) {
+        const double *O = c->Om + 27 * i;
+        double oo = 0;
+        for (int x = 0; x < 27; x++) oo += O[x] * O[x];
+        s += (48 * a * a * a * a * a * a / 7) * oo;
+    }
     *e = -(a / sp) * s;
 }
 
@@ -495,9 +618,9 @@ static void self_terms(const ctx_t *c, int64_t i, double *e, double g[3])
  * energy_out[0..4] = real, reciprocal, self, background, total.
  * forces, dEdmu: [n][3] or NULL.  Returns 0 on success, negative on bad input.
  */
-int oracle_ewald(int64_t n, const double *pos, const double *q, const double *mu, const double *theta,
-                 double edge, double alpha, double rcut, int kmax, int nthreads,
-                 double *energy_out, double *forces, double *dEdmu)
+int oracle_ewald_o3(int64_t n, const double *pos, const double *q, const double *mu, const double *theta,
+                    const double *omega, double edge, double alpha, double rcut, int kmax, int nthreads,
+                    double *energy_out, double *forces, double *dEdmu)
 {
     if (n <= 0 || !pos || !q || !energy_out || edge <= 0 || alpha <= 0 || rcut <= 0 || kmax < 0) return -1;
 #ifdef _OPENMP
@@ -505,6 +628,7 @@ int oracle_ewald(int64_t n, const double *pos, const double *q, const double *mu
 #endif
     ctx_t c;
     ctx_init(&c, n, pos, q, mu, theta, edge, alpha, rcut, kmax);
+    ctx_set_omega(&c, omega);
     const int want_grad = (forces || dEdmu) ? 1 : 0;
     double *ereal = (double *)malloc(sizeof(double) * n);
     double *eself = (double *)malloc(sizeof(double) * n);
@@ -542,6 +666,15 @@ int oracle_ewald(int64_t n, const double *pos, const double *q, const double *mu
     rec_free(&rc);
     ctx_free(&c);
     return 0;
+}
+
+/* the same without octupoles */
+int oracle_ewald(int64_t n, const double *pos, const double *q, const double *mu, const double *theta,
+                 double edge, double alpha, double rcut, int kmax, int nthreads,
+                 double *energy_out, double *forces, double *dEdmu)
+{
+    return oracle_ewald_o3(n, pos, q, mu, theta, NULL, edge, alpha, rcut, kmax, nthreads, energy_out, forces,
+                           dEdmu);
 }
 
 /* ---- derivatives in the charges and quadrupoles ------------------------ */
@@ -733,9 +866,9 @@ int oracle_dtensor(const double r[3], double alpha, int n, double *out)
  * eatom[i] = 1/2 sum_j pair energy; forces = -grad; dEdmu = field from the
  * pairs (no self term).  Any output may be NULL.
  */
-int oracle_near_field(int64_t n, const double *pos, const double *q, const double *mu, const double *theta,
-                      double edge, double xi, int nside, int nthreads,
-                      double *eatom, double *forces, double *dEdmu)
+int oracle_near_field_o3(int64_t n, const double *pos, const double *q, const double *mu, const double *theta,
+                         const double *omega, double edge, double xi, int nside, int nthreads,
+                         double *eatom, double *forces, double *dEdmu)
 {
     /* nside: leaves per axis (2^depth for an octree; any count for the single-level ANKH-FFT grid) */
     if (n <= 0 || !pos || !q || edge <= 0 || xi <= 0 || nside < 1 || nside > 1024) return -1;
@@ -745,6 +878,7 @@ int oracle_near_field(int64_t n, const double *pos, const double *q, const doubl
     ctx_t c;
     /* a cell list whose cells are the leaves: nc = nside, R = 1, no cutoff */
     ctx_init(&c, n, pos, q, mu, theta, edge, xi, edge, 0);
+    ctx_set_omega(&c, omega);
     free(c.cell_start); free(c.cell_atoms);
     const int nc = nside;
     const double w = edge / nc;
@@ -800,6 +934,21 @@ int oracle_near_field(int64_t n, const double *pos, const double *q, const doubl
                 double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
                 radial(r2, xi, nmax, B);
                 dtensors(r, B, nmax, T);
+                if (c.Om) {
+                    const double *Mi[4], *Mj[4];
+                    moments_of(&c, i, Mi);
+                    moments_of(&c, j, Mj);
+                    e += 0.5 * pair_phi_gen(T, -1, Mi, Mj);
+                    if (want_grad) {
+                        for (int d = 0; d < 3; d++) f[d] -= pair_phi_gen(T, d, Mi, Mj);
+                        if (mi) {
+                            double h[3];
+                            pair_field_gen(T, Mj, h);
+                            for (int d = 0; d < 3; d++) g[d] += h[d];
+                        }
+                    }
+                    continue;
+                }
                 const double *mj = c.mu ? c.mu + 3 * j : NULL;
                 const double *Tj = c.Th ? c.Th + 9 * j : NULL;
                 e += 0.5 * pair_phi(T, -1, q[i], mi, Ti, q[j], mj, Tj);
@@ -821,4 +970,12 @@ int oracle_near_field(int64_t n, const double *pos, const double *q, const doubl
     c.cell_start = NULL; c.cell_atoms = NULL;
     ctx_free(&c);
     return 0;
+}
+
+/* the same without octupoles */
+int oracle_near_field(int64_t n, const double *pos, const double *q, const double *mu, const double *theta,
+                      double edge, double xi, int nside, int nthreads,
+                      double *eatom, double *forces, double *dEdmu)
+{
+    return oracle_near_field_o3(n, pos, q, mu, theta, NULL, edge, xi, nside, nthreads, eatom, forces, dEdmu);
 }

@@ -64,6 +64,24 @@ def random_traceless_theta(rng: np.random.Generator, n: int, sigma: float) -> np
     return np.stack([xx, xy, xz, yy, yz, zz], axis=1)
 
 
+def random_traceless_omega(rng: np.random.Generator, n: int, sigma: float) -> np.ndarray:
+    """Traceless symmetric octupoles [n][10] in the order (xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz, yzz,
+    zzz): xxx, xxy, xxz, xyy, xyz, yyy, yyz ~ N(0, sigma), and the three traces zero,
+    xzz = -xxx - xyy, yzz = -xxy - yyy, zzz = -xxz - yyz."""
+    o = np.zeros((n, 10))
+    free = [0, 1, 2, 3, 4, 6, 7]
+    o[:, free] = rng.normal(0.0, sigma, (n, 7))
+    o[:, 5] = -o[:, 0] - o[:, 3]
+    o[:, 8] = -o[:, 1] - o[:, 6]
+    o[:, 9] = -o[:, 2] - o[:, 7]
+    return o
+
+
+def water_octupoles(n_mol: int, seed: int = 2, sigma: float = 0.05) -> np.ndarray:
+    """Octupoles for a water box of n_mol molecules (3 n_mol atoms), seeded apart from the box itself."""
+    return random_traceless_omega(np.random.default_rng(1000 + seed), 3 * n_mol, sigma)
+
+
 def charges(n: int = 1000, edge: float = 24.0, seed: int = 1) -> dict:
     """n point charges, uniform in the box, half +1 and half -1 (neutral for even n)."""
     rng = np.random.default_rng(seed)

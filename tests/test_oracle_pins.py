@@ -292,3 +292,103 @@ def test_derivative_tensors(oracle_lib, n):
         r2 = r @ r
         ref = (3 * np.outer(r, r) - r2 * np.eye(3)) / r2 ** 2.5
         np.testing.assert_allclose(T, ref, rtol=1e-7)
+
+
+# ---- octupoles (the next multipole order of the operator D) ------------------------------------------
+
+def _octupole_system(seed, n=24, edge=9.0):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(-0.5 * edge, 0.5 * edge, (n, 3))
+    q = rng.normal(0.0, 0.5, n)
+    q -= q.mean()
+    mu = rng.normal(0.0, 0.2, (n, 3))
+    th = synth.random_traceless_theta(rng, n, 0.2)
+    om = synth.random_traceless_omega(rng, n, 0.2)
+    return pos, q, mu, th, om, edge
+
+
+def test_octupole_alpha_independence():
+    """The splitting parameter cancels exactly with octupoles present: the reciprocal factor -i Omega:kkk
+    and the self term 48 a^6/7 Omega:Omega balance the real-space octupole terms (energy, forces, fields)."""
+    import oracle
+    pos, q, mu, th, om, L = _octupole_system(5)
+    a0 = oracle.ewald_params(len(q), L, 1e-14)[0]
+    res = [oracle.ewald(pos, q, mu, th, edge=L, eps=1e-14, alpha=f * a0, omega=om) for f in (0.75, 1.0, 1.5)]
+    E = [r["energy"] for r in res]
+    assert max(abs(e - E[1]) for e in E) <= 1e-10 * abs(E[1])
+    for r in res:
+        assert np.abs(r["forces"] - res[1]["forces"]).max() <= 1e-9 * np.abs(res[1]["forces"]).max()
+        assert np.abs(r["dEdmu"] - res[1]["dEdmu"]).max() <= 1e-9 * np.abs(res[1]["dEdmu"]).max()
+    # and the octupoles matter: without them the energy differs
+    e0 = oracle.ewald(pos, q, mu, th, edge=L, eps=1e-14, grad=False)["energy"]
+    assert abs(e0 - E[1]) > 1e-3 * abs(E[1])
+
+
+def test_octupole_translation_invariance():
+    import oracle
+    pos, q, mu, th, om, L = _octupole_system(6)
+    e1 = oracle.ewald(pos, q, mu, th, edge=L, eps=1e-14, omega=om, grad=False)["energy"]
+    e2 = oracle.ewald(pos + np.array([1.3, -2.2, 0.7]), q, mu, th, edge=L, eps=1e-14, omega=om,
+                      grad=False)["energy"]
+    assert abs(e1 - e2) <= 1e-12 * abs(e1)
+
+
+def test_octupole_is_the_limit_of_a_charge_cube():
+    """A point octupole with Omega_xyz = w (and its permutations; traceless) is the limit of eight charges
+    s_x s_y s_z 6 w / d^3 at the corners (+-d/2)^3 of a cube around it: the third Taylor term of the
+    cluster's potential is d^3 (6w/d^3) d_x d_y d_z = Omega : grad^3.  The cube has no rank-4 moment, and
+    its rank-5 moment acts as d_x d_y d_z (Laplacian), which vanishes on the Coulomb potential, so the
+    first correction is O(d^4).  The interaction energy with a neutral charge pair, Richardson-
+    extrapolated in d^4, matches the oracle's octupole (normalisation Omega : grad grad grad used
+    literally, sign, reciprocal factor -i Omega:kkk)."""
+    import oracle
+    L, w = 14.0, 0.3
+    P = np.array([0.4, -0.3, 0.2])
+    pair_pos = np.array([[2.9, 1.1, -1.6], [-2.2, 2.4, 1.3]])
+    pair_q = np.array([1.0, -1.0])
+    om = np.zeros((1, 10))
+    om[0, 4] = w          # xyz
+
+    def E(pos, q, omega=None):
+        return oracle.ewald(pos, q, edge=L, eps=1e-14, grad=False,
+                            mu=np.zeros((len(q), 3)) if omega is not None else None,
+                            theta=np.zeros((len(q), 6)) if omega is not None else None, omega=omega)["energy"]
+
+    # interaction of the point octupole with the pair
+    e_oct = (E(np.vstack([P, pair_pos]), np.array([0.0, 1.0, -1.0]), np.vstack([om, np.zeros((2, 10))]))
+             - E(P[None], np.array([0.0]), om) - E(pair_pos, pair_q))
+
+    def e_cube(d):
+        corners = np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], float)
+        qc = corners.prod(axis=1) * 6 * w / d ** 3
+        pc = P + 0.5 * d * corners
+        return E(np.vstack([pc, pair_pos]), np.concatenate([qc, pair_q])) - E(pc, qc) - E(pair_pos, pair_q)
+
+    d = 0.4
+    e1, e2 = e_cube(d), e_cube(d / 2)
+    rich = (16 * e2 - e1) / 15
+    assert abs(e_oct) > 1e-3
+    assert abs(e1 - e_oct) <= 1e-4 * abs(e_oct)          # the cube itself: O(d^4)
+    assert abs(rich - e_oct) <= 1e-6 * abs(e_oct), (rich, e_oct, e1, e2)
+
+
+def test_octupole_forces_and_fields_are_derivatives():
+    """Central differences of the octupole system's energy in positions and dipoles."""
+    import oracle
+    pos, q, mu, th, om, L = _octupole_system(7, n=12)
+    r = oracle.ewald(pos, q, mu, th, edge=L, eps=1e-14, omega=om)
+    h = 1e-5
+    for i in (0, 5, 11):
+        for c in range(3):
+            p1, p2 = pos.copy(), pos.copy()
+            p1[i, c] += h
+            p2[i, c] -= h
+            fd = -(oracle.ewald(p1, q, mu, th, edge=L, eps=1e-14, omega=om, grad=False)["energy"]
+                   - oracle.ewald(p2, q, mu, th, edge=L, eps=1e-14, omega=om, grad=False)["energy"]) / (2 * h)
+            assert fd == pytest.approx(r["forces"][i, c], rel=1e-6, abs=1e-7 * np.abs(r["forces"]).max())
+            m1, m2 = mu.copy(), mu.copy()
+            m1[i, c] += h
+            m2[i, c] -= h
+            fd = (oracle.ewald(pos, q, m1, th, edge=L, eps=1e-14, omega=om, grad=False)["energy"]
+                  - oracle.ewald(pos, q, m2, th, edge=L, eps=1e-14, omega=om, grad=False)["energy"]) / (2 * h)
+            assert fd == pytest.approx(r["dEdmu"][i, c], rel=1e-6, abs=1e-7 * np.abs(r["dEdmu"]).max())
