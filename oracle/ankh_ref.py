@@ -301,9 +301,17 @@ def m2l_projector(w: float, L: int, xi: float, rank: int) -> np.ndarray:
     return U @ U.T
 
 
+# octupoles: stored components (xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz, yzz, zzz), their derivative orders
+# (a, b, c) per axis and their multiplicities in the full symmetric tensor
+OMEGA_ABC = [(3, 0, 0), (2, 1, 0), (2, 0, 1), (1, 2, 0), (1, 1, 1), (1, 0, 2), (0, 3, 0), (0, 2, 1), (0, 1, 2),
+             (0, 0, 3)]
+OMEGA_MULT = [1, 3, 3, 3, 6, 3, 1, 3, 3, 1]
+
+
 def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, p: int,
              grad: bool = True, nthreads: int = 0, keep: bool = False, root_order: int | None = None,
-             m2l_ranks=None, far: str = "fmm", eq_order: int | None = None, leaves: int | None = None) -> dict:
+             m2l_ranks=None, far: str = "fmm", eq_order: int | None = None, leaves: int | None = None,
+             omega=None) -> dict:
     """root_order: Chebyshev order of the root grid that carries the far
     images (depth >= 1); defaults to `order`.  m2l_ranks: optional rank per
     level (index e = 1..depth; a rank >= L^3 or 0 leaves the level
@@ -318,6 +326,7 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
     q = _c64(q, (N,))
     mu = _c64(mu, (N, 3))
     theta = _c64(theta, (N, 6))
+    omega = _c64(omega, (N, 10))
     L = order
     nu = L ** 3
     E = depth
@@ -332,7 +341,7 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
     yhat = (pos - ctr) / h
 
     # step 2: modified charges (Alg. 2), derivatives up to 2 (3 for forces)
-    nd = 3 if grad else 2
+    nd = (3 if grad else 2) + (1 if omega is not None else 0)
     S = lagrange_derivs(yhat, L, nd, h)          # [N, 3, nd+1, L]
     Sx, Sy, Sz = S[:, 0], S[:, 1], S[:, 2]
 
@@ -348,6 +357,10 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
         xx, xy, xz, yy, yz, zz = [theta[:, c, None, None, None] for c in range(6)]
         contrib += xx * tens(2, 0, 0) + 2 * xy * tens(1, 1, 0) + 2 * xz * tens(1, 0, 1)
         contrib += yy * tens(0, 2, 0) + 2 * yz * tens(0, 1, 1) + zz * tens(0, 0, 2)
+    if omega is not None:
+        # Omega : grad^3 S_k, every stored component with its multiplicity
+        for c, (a, b, cc) in enumerate(OMEGA_ABC):
+            contrib += OMEGA_MULT[c] * omega[:, c, None, None, None] * tens(a, b, cc)
     Q = np.zeros((nleaf_ax ** 3, L, L, L))
     np.add.at(Q, leaf, contrib)
 
@@ -401,8 +414,8 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
     eatom = np.zeros(N)
     Fn = np.zeros((N, 3)) if grad else None
     Gn = np.zeros((N, 3)) if grad else None
-    rc = _oracle_lib().oracle_near_field(N, _p(pos), _p(q), _p(mu), _p(theta), float(edge), float(xi),
-                                         int(nleaf_ax), int(nthreads), _p(eatom), _p(Fn), _p(Gn))
+    rc = _oracle_lib().oracle_near_field_o3(N, _p(pos), _p(q), _p(mu), _p(theta), _p(omega), float(edge),
+                                            float(xi), int(nleaf_ax), int(nthreads), _p(eatom), _p(Fn), _p(Gn))
     if rc != 0:
         raise ValueError("oracle_near_field failed")
     e_near = float(np.sum(eatom))
@@ -415,6 +428,9 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
         tt = theta[:, 0] ** 2 + theta[:, 3] ** 2 + theta[:, 5] ** 2 + 2 * (
             theta[:, 1] ** 2 + theta[:, 2] ** 2 + theta[:, 4] ** 2)
         s = s + (8 * xi ** 4 / 5) * tt
+    if omega is not None:
+        oo = np.sum(np.array(OMEGA_MULT)[None, :] * omega ** 2, axis=1)      # Omega : Omega
+        s = s + (48 * xi ** 6 / 7) * oo
     e_self = float(-(xi / math.sqrt(math.pi)) * np.sum(s))
     Qtot = float(np.sum(q))
     e_bg = -math.pi * Qtot ** 2 / (2 * edge ** 3 * xi ** 2)
@@ -438,11 +454,11 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
                     dv[:, bx, :, by, :, bz] += np.einsum("ai,bj,ck,xyzabc->xyzijk", Vp[bx], Vp[by], Vp[bz], par)
                 Lam = down.reshape(n, n, n, nu) + Lloc[e]
         Lam_leaf = Lam.reshape(-1, L, L, L)[leaf]          # [N, L, L, L]
-        # L2P: derivatives of phi(y) = sum_k Lam_k S_k(y) up to order 3
+        # L2P: derivatives of phi(y) = sum_k Lam_k S_k(y) up to order 3 (4 with octupoles)
         phi = {}
-        for a in range(4):
-            for b in range(4 - a):
-                for c in range(4 - a - b):
+        for a in range(nd + 1):
+            for b in range(nd + 1 - a):
+                for c in range(nd + 1 - a - b):
                     phi[(a, b, c)] = np.einsum("nijk,ni,nj,nk->n", Lam_leaf, Sx[:, a], Sy[:, b], Sz[:, c])
 
         def dphi(*axes):
@@ -468,6 +484,11 @@ def evaluate(pos, q, mu, theta, edge: float, depth: int, order: int, xi: float, 
                 for a in range(3):
                     for b in range(3):
                         g = g + Th[:, a, b] * dphi(a, b, x)
+            if omega is not None:
+                for c, (a, b, cc) in enumerate(OMEGA_ABC):
+                    cnt = [a, b, cc]
+                    cnt[x] += 1
+                    g = g + OMEGA_MULT[c] * omega[:, c] * phi[tuple(cnt)]
             Ff[:, x] = -g
             Gf[:, x] = dphi(x)
         # equals sum(e_far_levels) + e_per: the leaf form of the same quadratic form

@@ -256,3 +256,76 @@ def test_fft_far_field_converges_to_ewald():
                     leaves=3)
     assert abs(r3["energy"] - ex["energy"]) < 2e-6 * abs(ex["energy"])
     assert np.sqrt(np.sum((r3["forces"] - ex["forces"]) ** 2) / np.sum(ex["forces"] ** 2)) < 2e-5
+
+
+# ---- octupoles -------------------------------------------------------------------------------------------
+
+def test_p2m_reproduces_octupole_moment():
+    """Interpolation of order L >= 4 reproduces cubic polynomials, so the third moment of the leaf's modified
+    charges is sum (q x_a x_b x_c + mu-, Theta- terms + 6 Omega_abc): the octupole enters P2M through
+    Omega : grad^3 with the right normalisation."""
+    rng = np.random.default_rng(11)
+    edge, E, L = 10.0, 0, 5
+    n = 10
+    pos = rng.uniform(-5, 5, (n, 3))
+    q = np.zeros(n)
+    om = synth.random_traceless_omega(rng, n, 0.3)
+    out = R.evaluate(pos, q, np.zeros((n, 3)), np.zeros((n, 6)), edge, E, L, 0.1, 2, grad=False, keep=True,
+                     omega=om)
+    Q = out["Q"].reshape(-1)
+    nodes = R.nodes3d(L) * 0.5 * edge
+    m3 = np.einsum("ka,kb,kc,k->abc", nodes, nodes, nodes, Q)
+    full = np.zeros((n, 3, 3, 3))
+    for c, (a, b, cc) in enumerate(R.OMEGA_ABC):
+        idx = [0] * a + [1] * b + [2] * cc
+        for perm in set(itertools.permutations(idx)):
+            full[:, perm[0], perm[1], perm[2]] = om[:, c]
+    np.testing.assert_allclose(m3, 6 * full.sum(0), atol=1e-10)
+    # no lower moments from pure octupoles
+    assert abs(Q.sum()) < 1e-11
+
+
+@pytest.mark.parametrize("far", ["fmm", "fft"])
+def test_octupole_gradient_is_exact(far):
+    """With octupoles, forces and fields of the transcription are central differences of its own energy
+    (P2M with the third derivatives of the basis, L2P with the fourth)."""
+    d = synth.water(30, seed=4)
+    om = synth.water_octupoles(30, seed=4)
+    edge = d["edge"]
+    E, L, xi, p = 1, 4, 0.08, 3
+    kw = dict(far=far, eq_order=4, omega=om)
+    base = R.evaluate(d["pos"], d["q"], d["mu"], d["theta"], edge, E, L, xi, p, grad=True, **kw)
+    h = 1e-5
+    for i in (3, 41):
+        for c in range(3):
+            vals = []
+            for s in (1, -1):
+                pp = d["pos"].copy()
+                pp[i, c] += s * h
+                vals.append(R.evaluate(pp, d["q"], d["mu"], d["theta"], edge, E, L, xi, p, grad=False, **kw)["energy"])
+            assert -(vals[0] - vals[1]) / (2 * h) == pytest.approx(base["forces"][i, c], rel=1e-6, abs=1e-7)
+            vals = []
+            for s in (1, -1):
+                mm = d["mu"].copy()
+                mm[i, c] += s * h
+                vals.append(R.evaluate(d["pos"], d["q"], mm, d["theta"], edge, E, L, xi, p, grad=False, **kw)["energy"])
+            assert (vals[0] - vals[1]) / (2 * h) == pytest.approx(base["dEdmu"][i, c], rel=1e-6, abs=1e-7)
+
+
+def test_octupole_convergence_to_ewald():
+    """With octupoles on every atom, the interpolated energy and forces approach the classical-Ewald oracle
+    as the order grows."""
+    d = synth.water(100, seed=9)
+    om = synth.water_octupoles(100, seed=9)
+    edge = d["edge"]
+    ex = oracle.ewald(d["pos"], d["q"], d["mu"], d["theta"], edge=edge, eps=1e-13, omega=om)
+    s2 = math.log(10 / 1e-7)
+    xi = math.pi / (edge * math.sqrt(s2))
+    p = int(math.ceil(math.sqrt(s2) / (xi * edge))) + 1
+    errs = []
+    for L in (4, 6, 8):
+        r = R.evaluate(d["pos"], d["q"], d["mu"], d["theta"], edge, 1, L, xi, p, grad=True, omega=om)
+        errs.append((abs(r["energy"] - ex["energy"]) / abs(ex["energy"]),
+                     np.sqrt(np.sum((r["forces"] - ex["forces"]) ** 2) / np.sum(ex["forces"] ** 2))))
+    assert errs[0][1] > errs[1][1] > errs[2][1]
+    assert errs[2][0] < 1e-6 and errs[2][1] < 1e-5, errs
