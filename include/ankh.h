@@ -65,7 +65,8 @@ typedef enum {
     ANKH_OK = 0,
     ANKH_ERR_INVALID_ARG = 1,          /* null pointer, n mismatch, box_radius <= 0, accuracy out of range ... */
     ANKH_ERR_NONFINITE_INPUT = 2,      /* latched: NaN/Inf in positions or moments */
-    ANKH_ERR_THETA_NOT_TRACELESS = 3,  /* latched: |trace Theta| > 1e-6 (max |Theta_ii| + 1) */
+    ANKH_ERR_THETA_NOT_TRACELESS = 3,  /* latched: |trace Theta| > 1e-6 (max |Theta_ii| + 1), or an octupole
+                                          trace Omega_aab above 1e-6 (max |Omega_abc| + 1) */
     ANKH_ERR_LEAF_OVERFLOW = 4,        /* reserved: no kernel has a per-leaf capacity limit */
     ANKH_ERR_ACCURACY_UNREACHABLE = 5, /* plan: accuracy below what the precision mode can reach */
     ANKH_ERR_OUT_OF_MEMORY = 6,        /* plan: device allocation failed */
@@ -183,8 +184,9 @@ typedef struct {
  *                 sets xi (reciprocal term below the target), the image
  *                 radius p and the interpolation order L (convergence in L
  *                 is geometric, numerical-results section).
- *   max_order     0 charges, 1 + dipoles, 2 + quadrupoles; later calls may
- *                 pass NULL for the moments above this order.
+ *   max_order     0 charges, 1 + dipoles, 2 + quadrupoles, 3 + octupoles
+ *                 (ankh_energy_octupole); later calls may pass NULL for the
+ *                 moments above this order.
  *   precision     an ankh_precision value.
  *   ov            NULL or overrides of depth / order / images / xi.
  *   hip_stream    hipStream_t (as void *) all work is enqueued on; NULL = default.
@@ -216,6 +218,34 @@ ankh_status ankh_energy(ankh_plan_t plan, const double *pos, const double *q, co
  */
 ankh_status ankh_energy_forces(ankh_plan_t plan, const double *pos, const double *q, const double *mu,
                                const double *theta, double *energy, double *forces, double *dE_dmu);
+
+/*
+ * ankh_energy_octupole: energy, forces and fields with octupoles, the next
+ * order of the operator of eq. 1,
+ *
+ *     D_u = q_u + mu_u . grad + Theta_u : grad grad + Omega_u : grad grad grad,
+ *
+ * the extension to any multipole order that the paper's introduction and its
+ * first conclusion name.  Every stage takes the third derivative order: P2M
+ * anterpolates Omega : grad^3 S_k (Alg. 2 with the third power of the
+ * differentiation matrix), the pair terms use the rank-3 moments, L2P the
+ * fourth basis derivatives, and the self energy gains -(48/7) xi^7/sqrt(pi)
+ * Omega : Omega per atom.
+ *   omega  [n][10] device, traceless symmetric octupoles as (xxx, xxy, xxz,
+ *                  xyy, xyz, xzz, yyy, yyz, yzz, zzz), used literally in
+ *                  Omega : grad^3 (no 1/6 or 1/15 factor; the full
+ *                  contraction weights the components 1, 3, 3, 3, 6, 3, 1,
+ *                  3, 3, 1); not NULL.  A trace Omega_aab (a summed) that
+ *                  does not vanish is latched as ANKH_ERR_THETA_NOT_TRACELESS.
+ *   pos, q, mu, theta, energy  as for ankh_energy (mu, theta may be NULL).
+ *   forces [n][3]  device output or NULL (energy only, or fields only).
+ *   dE_dmu [n][3]  device output or NULL: dE/dmu.
+ * Needs a plan with max_order 3 (which then also serves ankh_energy and the
+ * other calls for lower moments).  Both precision modes and both far fields.
+ */
+ankh_status ankh_energy_octupole(ankh_plan_t plan, const double *pos, const double *q, const double *mu,
+                                 const double *theta, const double *omega, double *energy, double *forces,
+                                 double *dE_dmu);
 
 /*
  * ankh_energy_derivs: the energy with any of its derivatives in the atoms'

@@ -3,7 +3,7 @@
 Argument marshalling only: every step of an evaluation runs in the HIP
 kernels behind the C ABI declared in include/ankh.h.  The functions below
 carry the C names (`ankh_plan`, `ankh_energy`, `ankh_energy_forces`,
-`ankh_energy_derivs`, `ankh_induce`, ...);
+`ankh_energy_derivs`, `ankh_energy_octupole`, `ankh_induce`, ...);
 `Plan` wraps a plan handle and `AnkhEnergy` is the autograd function whose
 backward returns -g F for the positions, g dE/dmu for the dipoles and, when
 asked for, g dE/dq and g dE/dTheta.
@@ -30,7 +30,7 @@ ANKH_FAR_FMM = 1
 ANKH_FAR_FFT = 2
 
 STATUS = {
-    0: "ok", 1: "invalid argument", 2: "non-finite input", 3: "quadrupole not traceless",
+    0: "ok", 1: "invalid argument", 2: "non-finite input", 3: "quadrupole or octupole not traceless",
     4: "leaf overflow", 5: "accuracy unreachable in this precision", 6: "out of device memory",
     7: "HIP runtime error", 8: "induced dipoles not converged",
 }
@@ -67,7 +67,7 @@ _lib = None
 
 EXPORTS = ["ankh_plan", "ankh_energy", "ankh_energy_forces", "ankh_sync", "ankh_get_stats", "ankh_set_timing",
            "ankh_last_terms", "ankh_leaf_multipoles", "ankh_destroy", "ankh_status_string", "ankh_induce",
-           "ankh_energy_derivs", "ankh_energy_derivs_noalloc"]
+           "ankh_energy_derivs", "ankh_energy_derivs_noalloc", "ankh_energy_octupole"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -90,6 +90,8 @@ def load_library(path: str = LIB_PATH):
     L.ankh_energy_derivs.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
     L.ankh_energy_derivs_noalloc.restype = ctypes.c_int
     L.ankh_energy_derivs_noalloc.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+    L.ankh_energy_octupole.restype = ctypes.c_int
+    L.ankh_energy_octupole.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp]
     L.ankh_induce.restype = ctypes.c_int
     L.ankh_induce.argtypes = [vp, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int32, dp, dp, dp,
                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
@@ -182,6 +184,11 @@ def ankh_energy_derivs(plan, pos, q, mu, theta, energy, forces, dE_dmu, dE_dq, d
 def ankh_energy_derivs_noalloc(plan, pos, q, mu, theta, energy, forces, dE_dmu, dE_dq, dE_dtheta):
     _check(load_library().ankh_energy_derivs_noalloc(plan, pos, q, mu, theta, energy, forces, dE_dmu, dE_dq,
                                                       dE_dtheta), "ankh_energy_derivs_noalloc")
+
+
+def ankh_energy_octupole(plan, pos, q, mu, theta, omega, energy, forces, dE_dmu):
+    _check(load_library().ankh_energy_octupole(plan, pos, q, mu, theta, omega, energy, forces, dE_dmu),
+           "ankh_energy_octupole")
 
 
 def ankh_induce(plan, pos, q, mu, theta, alpha, tol, max_iter, mu_ind, energy, forces):
@@ -278,6 +285,20 @@ class Plan:
         G = torch.empty((self.n, 3), dtype=torch.float64, device=pos.device) if fields else None
         ankh_energy_forces(self.handle, pp, qp, mp, tp, ctypes.c_void_p(e.data_ptr()),
                            ctypes.c_void_p(F.data_ptr()), None if G is None else ctypes.c_void_p(G.data_ptr()))
+        return e, F, G
+
+    def energy_octupole(self, pos, q, mu, theta, omega, forces=True, fields=True):
+        """Energy (and forces / fields) with octupoles omega [n][10] (xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz,
+        yzz, zzz); the plan needs max_order 3.  Returns (energy [1], forces or None, dE/dmu or None)."""
+        keep, (pp, qp, mp, tp) = self._args(pos, q, mu, theta)
+        omega, op = _dev(omega, 10, self.n, "omega")
+        dev = pos.device
+        e = torch.empty(1, dtype=torch.float64, device=dev)
+        F = torch.empty((self.n, 3), dtype=torch.float64, device=dev) if forces else None
+        G = torch.empty((self.n, 3), dtype=torch.float64, device=dev) if fields else None
+        ankh_energy_octupole(self.handle, pp, qp, mp, tp, op, ctypes.c_void_p(e.data_ptr()),
+                             None if F is None else ctypes.c_void_p(F.data_ptr()),
+                             None if G is None else ctypes.c_void_p(G.data_ptr()))
         return e, F, G
 
     def energy_derivs(self, pos, q, mu=None, theta=None, forces=True, fields=True, potentials=True,

@@ -40,7 +40,8 @@ struct Particles {
     double *q;
     double *mu;      // [3][n]
     double *th;      // [6][n] (xx, xy, xz, yy, yz, zz)
-    float *qf, *muf, *thf;
+    double *om;      // [10][n] (xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz, yzz, zzz)
+    float *qf, *muf, *thf, *omf;
 };
 
 struct Level {
@@ -157,7 +158,7 @@ hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 hipError_t launch_sort(ankh_plan_s *pl, const double *pos, const double *q, const double *mu,
                        const double *th);
 hipError_t launch_gather(ankh_plan_s *pl, const double *pos, const double *q, const double *mu,
-                         const double *th);
+                         const double *th, const double *om);
 hipError_t launch_p2m(ankh_plan_s *pl, int ord);
 hipError_t launch_m2m(ankh_plan_s *pl, int e_parent);
 hipError_t launch_l2l(ankh_plan_s *pl, int e_child);

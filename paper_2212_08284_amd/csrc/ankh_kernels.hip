@@ -165,8 +165,9 @@ __global__ __launch_bounds__(256) void k_segsort(const int32_t *offs, const int3
 
 // leaf-order particle arrays: local coordinates (relative to the leaf centre)
 __global__ void k_gather(int64_t n, const int32_t *perm, const int32_t *leaf, const double *pos,
-                         const double *q, const double *mu, const double *th, double rB, double edge,
-                         double w, int nside, Particles P, int planned_order, int mixed, int32_t *err) {
+                         const double *q, const double *mu, const double *th, const double *om, double rB,
+                         double edge, double w, int nside, Particles P, int planned_order, int mixed,
+                         int32_t *err) {
     int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int i = perm[s];
@@ -206,6 +207,21 @@ __global__ void k_gather(int64_t n, const int32_t *perm, const int32_t *leaf, co
         const double tr = t[0] + t[3] + t[5], mx = fmax(fabs(t[0]), fmax(fabs(t[3]), fabs(t[5])));
         if (fabs(tr) > 1e-6 * (1.0 + mx)) err[1] = 1;
     }
+    if (planned_order >= 3) {
+        double o[10];
+        for (int d = 0; d < 10; d++) {
+            double v = om ? om[10 * (int64_t)i + d] : 0.0;
+            fin = fin && isfinite(v);
+            o[d] = v;
+            P.om[d * n + s] = v;
+            if (mixed) P.omf[d * n + s] = (float)v;
+        }
+        // the three traces Omega_aab (b = x, y, z) must vanish
+        double mx = 0;
+        for (int d = 0; d < 10; d++) mx = fmax(mx, fabs(o[d]));
+        const double tx = o[0] + o[3] + o[5], ty = o[1] + o[6] + o[8], tz = o[2] + o[7] + o[9];
+        if (fmax(fabs(tx), fmax(fabs(ty), fabs(tz))) > 1e-6 * (1.0 + mx)) err[1] = 1;
+    }
     if (!fin) err[0] = 1;
 }
 
@@ -244,20 +260,25 @@ __device__ inline void cheb_basis(double xh, double hinv, const double *sH, doub
 
 // ---- P2M: modified charges of every leaf (Alg. 2) --------------------------
 // Q[i][j][k] = sum_atoms sum_(a,b,c) m_abc S^(a)_i(x) S^(b)_j(y) S^(c)_k(z), the
-// ten (a,b,c) of q, mu and Theta (off-diagonal Theta doubled).  Grouped by the
-// x order a, the sum is sum_a S^(a)_i(x) w_a(j, k) with
-//   w_0 = q y0 z0 + mu_y y1 z0 + mu_z y0 z1 + Th_yy y2 z0 + 2 Th_yz y1 z1 + Th_zz y0 z2,
-//   w_1 = mu_x y0 z0 + 2 Th_xy y1 z0 + 2 Th_xz y0 z1,   w_2 = Th_xx y0 z0,
+// (a,b,c) of q, mu, Theta and Omega, each component of a symmetric tensor
+// weighted by its multiplicity (off-diagonal Theta doubled; Omega 1, 3 or 6).
+// Grouped by the x order a, the sum is sum_a S^(a)_i(x) w_a(j, k) with
+//   w_0 = q y0 z0 + mu_y y1 z0 + mu_z y0 z1 + Th_yy y2 z0 + 2 Th_yz y1 z1 + Th_zz y0 z2
+//         + Om_yyy y3 z0 + 3 Om_yyz y2 z1 + 3 Om_yzz y1 z2 + Om_zzz y0 z3,
+//   w_1 = mu_x y0 z0 + 2 Th_xy y1 z0 + 2 Th_xz y0 z1 + 3 Om_xyy y2 z0 + 6 Om_xyz y1 z1 + 3 Om_xzz y0 z2,
+//   w_2 = Th_xx y0 z0 + 3 Om_xxy y1 z0 + 3 Om_xxz y0 z1,   w_3 = Om_xxx y0 z0,
 // so a thread owns one (j, k) line of L nodes and a slice of the leaf's atoms;
 // the slices' lines are summed in slice order at the end.
 template <int L, int ORD>
 __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, const double *tab, int nu, int nup,
                                              double hinv, double *Q, int64_t n) {
     constexpr int ND = ORD + 1;
-    constexpr int CH = 64;                 // atoms per LDS chunk (a leaf of the planned grids: one chunk)
+    // atoms per LDS chunk (a leaf of the planned grids: one chunk); 32 with octupoles, whose four basis
+    // derivatives per axis would not fit 64 atoms into the static LDS at order 10
+    constexpr int CH = ORD >= 3 ? 32 : 64;
     constexpr int NJK = L * L;
     constexpr int NSL = 256 / NJK;         // atom slices
-    constexpr int NMO = ORD == 0 ? 1 : (ORD == 1 ? 4 : 10);
+    constexpr int NMO = ORD == 0 ? 1 : (ORD == 1 ? 4 : (ORD == 2 ? 10 : 20));
     constexpr int NS = CH * 3 * ND * L, NR = NSL * L * L * L;
     __shared__ double sH[L * L];
     __shared__ double sBuf[NS > NR ? NS : NR];   // the chunk's 1D bases, then the slices' partial lines
@@ -299,6 +320,11 @@ __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, c
                 mo[8] = 2 * P.th[4 * n + slot];     // 2 yz
                 mo[9] = P.th[5 * n + slot];         // zz
             }
+            if (ORD >= 3) {
+                constexpr double mult[10] = {1, 3, 3, 3, 6, 3, 1, 3, 3, 1};
+#pragma unroll
+                for (int c = 0; c < 10; c++) mo[10 + c] = mult[c] * P.om[c * n + slot];
+            }
         }
         __syncthreads();
         if (sl < NSL) {
@@ -312,10 +338,17 @@ __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, c
                     w[0] += mo[2] * y1 * z0 + mo[3] * y0 * z1;
                     w[1] = mo[1] * y0 * z0;
                     if constexpr (ORD >= 2) {
-                        const double y2 = sS[a][1][ND - 1][j], z2 = sS[a][2][ND - 1][k];
+                        const double y2 = sS[a][1][2][j], z2 = sS[a][2][2][k];
                         w[0] += mo[7] * y2 * z0 + mo[8] * y1 * z1 + mo[9] * y0 * z2;
                         w[1] += mo[5] * y1 * z0 + mo[6] * y0 * z1;
-                        w[ND - 1] = mo[4] * y0 * z0;
+                        w[2] = mo[4] * y0 * z0;
+                        if constexpr (ORD >= 3) {
+                            const double y3 = sS[a][1][3][j], z3 = sS[a][2][3][k];
+                            w[0] += mo[16] * y3 * z0 + mo[17] * y2 * z1 + mo[18] * y1 * z2 + mo[19] * y0 * z3;
+                            w[1] += mo[13] * y2 * z0 + mo[14] * y1 * z1 + mo[15] * y0 * z2;
+                            w[2] += mo[11] * y1 * z0 + mo[12] * y0 * z1;
+                            w[3] = mo[10] * y0 * z0;
+                        }
                     }
                 }
 #pragma unroll
@@ -556,7 +589,8 @@ __global__ __launch_bounds__(256) void k_leafdot(const double *Q, const double *
 }
 
 // ---- L2P: far-field forces and fields at the atoms (adjoint of P2M) --------
-// phi(y) = sum_k Lambda_k S_k(y); F = -(q grad phi + mu_a grad d_a phi + Th_ab grad d_a d_b phi),
+// phi(y) = sum_k Lambda_k S_k(y); F = -(q grad phi + mu_a grad d_a phi + Th_ab grad d_a d_b phi
+// + Om_abc grad d_a d_b d_c phi),
 // dE/dmu = grad phi.  One thread per atom (leaf order): its 1D bases in
 // registers, the leaf's expansion contracted along z, then y, then x.
 template <int L, int ORD, bool FIELD>
@@ -631,6 +665,15 @@ __global__ __launch_bounds__(256, L <= 6 ? 2 : 1) void k_l2p(Particles P, const 
                 v += xx * phi[2 + ex][ey][ez] + yy * phi[ex][2 + ey][ez] + zz * phi[ex][ey][2 + ez] +
                      2 * xy * phi[1 + ex][1 + ey][ez] + 2 * xz * phi[1 + ex][ey][1 + ez] +
                      2 * yz * phi[ex][1 + ey][1 + ez];
+            }
+            if (ORD >= 3) {
+                // Omega : grad^3 d_c phi, each stored component with its multiplicity
+                const double *o = P.om + slot;
+                v += o[0] * phi[3 + ex][ey][ez] + 3 * o[n] * phi[2 + ex][1 + ey][ez] +
+                     3 * o[2 * n] * phi[2 + ex][ey][1 + ez] + 3 * o[3 * n] * phi[1 + ex][2 + ey][ez] +
+                     6 * o[4 * n] * phi[1 + ex][1 + ey][1 + ez] + 3 * o[5 * n] * phi[1 + ex][ey][2 + ez] +
+                     o[6 * n] * phi[ex][3 + ey][ez] + 3 * o[7 * n] * phi[ex][2 + ey][1 + ez] +
+                     3 * o[8 * n] * phi[ex][1 + ey][2 + ez] + o[9 * n] * phi[ex][ey][3 + ez];
             }
             f[c] = -v;
         }
@@ -847,10 +890,11 @@ hipError_t launch_sort(ankh_plan_s *pl, const double *pos, const double *q, cons
     return hipGetLastError();
 }
 
-hipError_t launch_gather(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th) {
+hipError_t launch_gather(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th,
+                         const double *om) {
     const double w = pl->edge / pl->nside;
     hipLaunchKernelGGL(k_gather, dim3(nblk(pl->n, 256)), dim3(256), 0, pl->stream, pl->n, pl->d_perm, pl->d_leaf,
-                       pos, q, mu, th, pl->rB, pl->edge, w, pl->nside, pl->P, pl->max_order,
+                       pos, q, mu, th, om, pl->rB, pl->edge, w, pl->nside, pl->P, pl->max_order,
                        is_mixed(pl) ? 1 : 0, pl->d_err);
     return hipGetLastError();
 }
@@ -881,8 +925,11 @@ hipError_t launch_p2m(ankh_plan_s *pl, int ord) {
     else if (ord == 1)                                                                                            \
         hipLaunchKernelGGL((k_p2m<LL, 1>), g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, pl->nu, pl->nup, \
                            hinv, Q, pl->n);                                                                       \
-    else                                                                                                          \
+    else if (ord == 2)                                                                                            \
         hipLaunchKernelGGL((k_p2m<LL, 2>), g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, pl->nu, pl->nup, \
+                           hinv, Q, pl->n);                                                                       \
+    else                                                                                                          \
+        hipLaunchKernelGGL((k_p2m<LL, 3>), g, b, shm, pl->stream, pl->P, pl->d_offs, pl->d_tab, pl->nu, pl->nup, \
                            hinv, Q, pl->n);
     ANKH_FOR_ORDER(L, ANKH_P2M)
 #undef ANKH_P2M
@@ -953,7 +1000,8 @@ hipError_t launch_l2p(ankh_plan_s *pl, int ord, bool fields) {
 #define ANKH_L2P(LL)                                                                         \
     if (ord == 0) { if (fields) ANKH_L2P3(LL, 0, true); else ANKH_L2P3(LL, 0, false); }     \
     else if (ord == 1) { if (fields) ANKH_L2P3(LL, 1, true); else ANKH_L2P3(LL, 1, false); } \
-    else { if (fields) ANKH_L2P3(LL, 2, true); else ANKH_L2P3(LL, 2, false); }
+    else if (ord == 2) { if (fields) ANKH_L2P3(LL, 2, true); else ANKH_L2P3(LL, 2, false); } \
+    else { if (fields) ANKH_L2P3(LL, 3, true); else ANKH_L2P3(LL, 3, false); }
     ANKH_FOR_ORDER(L, ANKH_L2P)
 #undef ANKH_L2P3
 #undef ANKH_L2P

@@ -25,7 +25,7 @@
 // near energy is summed per block in float64.  No atomics: results are
 // bitwise reproducible.
 //
-// Pair terms (r = x_i - x_j, D_x = q + mu.d + Th:dd on x, the mirrored
+// Pair terms (r = x_i - x_j, D_x = q + mu.d + Th:dd on x (+ Om:ddd, see pair_terms), the mirrored
 // operator on the source): with B_0 = H, B_{n+1} = -(1/r) dB_n/dr,
 //   E_ij = c0 B0 + c1 B1 + c2 B2 + c3 B3 + c4 B4,
 //   c0 = qi qk
@@ -59,13 +59,13 @@ static_assert(kNumSlots == NHALF + 1, "one slot per mutual task of a target and 
 // r^2 into the argument of gauss(); pwc[n] = (2 xi^2)^n / (xi sqrt(pi)), the
 // Gaussian's weight in B_n.
 template <typename R> struct Radial {
-    R xi, xi2, c_erf, gx, pwc[6];   // c_erf = (2/sqrt(pi)) xi
+    R xi, xi2, c_erf, gx, pwc[8];   // c_erf = (2/sqrt(pi)) xi
 };
 
 template <typename R> struct P2PArgs {
     const double *x, *y, *z;
-    const double *q, *mu, *th;
-    const float *qf, *muf, *thf;
+    const double *q, *mu, *th, *om;
+    const float *qf, *muf, *thf, *omf;
     const int32_t *offs;
     int64_t n;
     int nside, depth;
@@ -179,6 +179,32 @@ template <typename R> __device__ inline void symv_acc(const R *Q, const R *v, R 
     o[1] += Q[1] * v[0] + Q[3] * v[1] + Q[4] * v[2];
     o[2] += Q[2] * v[0] + Q[4] * v[1] + Q[5] * v[2];
 }
+// A : B of two symmetric matrices (xx, xy, xz, yy, yz, zz)
+template <typename R> __device__ inline R sym_dot(const R *A, const R *B) {
+    return A[0] * B[0] + A[3] * B[3] + A[5] * B[5] + 2 * (A[1] * B[1] + A[2] * B[2] + A[4] * B[4]);
+}
+// Octupoles O = (xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz, yzz, zzz).  M = O r, the symmetric matrix
+// M_ab = O_abc r_c
+template <typename R> __device__ inline void oct_r(const R *O, R rx, R ry, R rz, R *M) {
+    M[0] = O[0] * rx + O[1] * ry + O[2] * rz;
+    M[1] = O[1] * rx + O[3] * ry + O[4] * rz;
+    M[2] = O[2] * rx + O[4] * ry + O[5] * rz;
+    M[3] = O[3] * rx + O[6] * ry + O[7] * rz;
+    M[4] = O[4] * rx + O[7] * ry + O[8] * rz;
+    M[5] = O[5] * rx + O[8] * ry + O[9] * rz;
+}
+// o_c += O_abc M_ab for a symmetric matrix M
+template <typename R> __device__ inline void oct_mat_acc(const R *O, const R *M, R *o) {
+    o[0] += O[0] * M[0] + O[3] * M[3] + O[5] * M[5] + 2 * (O[1] * M[1] + O[2] * M[2] + O[4] * M[4]);
+    o[1] += O[1] * M[0] + O[6] * M[3] + O[8] * M[5] + 2 * (O[3] * M[1] + O[4] * M[2] + O[7] * M[4]);
+    o[2] += O[2] * M[0] + O[7] * M[3] + O[9] * M[5] + 2 * (O[4] * M[1] + O[5] * M[2] + O[8] * M[4]);
+}
+// full contraction of two octupoles: every stored component with its multiplicity
+template <typename R> __device__ inline R oct_dot(const R *A, const R *B) {
+    return A[0] * B[0] + A[6] * B[6] + A[9] * B[9] +
+           3 * (A[1] * B[1] + A[2] * B[2] + A[3] * B[3] + A[5] * B[5] + A[7] * B[7] + A[8] * B[8]) +
+           6 * A[4] * B[4];
+}
 
 template <typename R, int SL> Radial<R> radial_constants(double xi) {
     Radial<R> c;
@@ -189,7 +215,7 @@ template <typename R, int SL> Radial<R> radial_constants(double xi) {
     c.gx = (R)(sizeof(R) == 4 && SL > 0 ? -xi * xi * 1.4426950408889634074 : xi * xi);
     double p = 1.0 / (xi * 1.7724538509055160273);
     c.pwc[0] = (R)p;
-    for (int k = 1; k < 6; k++) {
+    for (int k = 1; k < 8; k++) {
         p *= 2.0 * xi * xi;
         c.pwc[k] = (R)p;
     }
@@ -217,9 +243,24 @@ template <> __device__ inline double gauss<double, 2>(double v) { return exp_nea
 //   a3 = 2 (qi B2 - (di.r) B3 + (r.Qi.r) B4),  a4 = 2 (qk B2 + (dk.r) B3 + (r.Qk.r) B4),
 // and the fields reuse a1, a2:  dE/d(di) = B1 dk + 2 B2 Qk r + a1 r,
 // dE/d(dk) = B1 di - 2 B2 Qi r + a2 r.
+// Octupoles (ORD = 3) add to c3 .. c6 the terms of the rank-3 moments (the general rule: for traceless
+// moments A of rank a on the target and C of rank b on the source, the pair term is
+//   sum_j (-1)^(a-j) C(a,j) C(b,j) j! B_(a+b-j) <A r^(a-j), C r^(b-j)>_j,
+// j indices of A contracted with j of C and the rest with r; the quadrupole c_n above are its a, b <= 2
+// cases).  With Oi r (matrix), Oi r r (vector) and oi = Oi r r r (scalar), likewise for Ok:
+//   c3 += -qk oi + qi ok + 3 (Oi r r.dk + di.Ok r r) + 6 (Qi:Ok r - Oi r:Qk + Oi:Ok)
+//   c4 += -oi (dk.r) - (di.r) ok + 6 (Oi r r.Qk r - Qi r.Ok r r) - 18 Oi r:Ok r
+//   c5  = -oi (r.Qk.r) + (r.Qi.r) ok + 9 Oi r r.Ok r r,   c6 = -oi ok.
+// Their gradient adds -ok B4 to a1, -oi B4 to a2, -2 oi B5 to a3, 2 ok B5 to a4, 6 B4 Oi r r to the
+// vector multiplied by Qk, -6 B4 Ok r r to the one multiplied by Qi, and
+//   -3 (qk B3 + (dk.r) B4 + (r.Qk.r) B5 + ok B6) Oi r r + 3 (qi B3 - (di.r) B4 + (r.Qi.r) B5 - oi B6) Ok r r
+//   + (Oi r)(6 B3 dk + 12 B4 Qk r + 18 B5 Ok r r) + (Ok r)(6 B3 di - 12 B4 Qi r + 18 B5 Oi r r)
+//   + Oi:(-6 B3 Qk - 18 B4 Ok r) + Ok:(6 B3 Qi - 18 B4 Oi r),
+// with (O:M)_c = O_abc M_ab; the fields add 3 B3 Ok r r (target) and 3 B3 Oi r r (source).
 template <typename R, int ORD, bool GRAD, bool FIELD, bool SRC, int SL>
-__device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *Qi, R ck, const R *dk,
-                                  const R *Qk, const Radial<R> &rc, R ew, R &te, R *tf, R *tg, R *sf, R *sg) {
+__device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *Qi, const R *Oi, R ck, const R *dk,
+                                  const R *Qk, const R *Ok, const Radial<R> &rc, R ew, R &te, R *tf, R *tg, R *sf,
+                                  R *sg) {
     constexpr int NB = 2 * ORD + 1 + (GRAD ? 1 : 0);
     const R r2 = rx * rx + ry * ry + rz * rz;
     const R rinv = dev_rsqrt<R>(r2);
@@ -241,9 +282,10 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
         for (int n = 2; n < NB; n++) B[n] = ((R)(2 * n - 1) * B[n - 1] + rc.pwc[n] * ex) * rinv2;
     }
     const R rv[3] = {rx, ry, rz};
-    R c0 = ci * ck, c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+    R c0 = ci * ck, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0;
     R dir = 0, dkr = 0;
     R Qir[3] = {0, 0, 0}, Qkr[3] = {0, 0, 0}, qirr = 0, qkrr = 0;
+    R Oi1[6], Ok1[6], Oi2[3] = {0, 0, 0}, Ok2[3] = {0, 0, 0}, oi3 = 0, ok3 = 0;
     if constexpr (ORD >= 1) {
         dir = di[0] * rx + di[1] * ry + di[2] * rz;
         dkr = dk[0] * rx + dk[1] * ry + dk[2] * rz;
@@ -265,15 +307,34 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
         c3 = -dir * qkrr + dkr * qirr - 4 * QirQkr;
         c4 = qirr * qkrr;
     }
+    if constexpr (ORD >= 3) {
+        oct_r(Oi, rx, ry, rz, Oi1);
+        oct_r(Ok, rx, ry, rz, Ok1);
+        symv(Oi1, rx, ry, rz, Oi2[0], Oi2[1], Oi2[2]);
+        symv(Ok1, rx, ry, rz, Ok2[0], Ok2[1], Ok2[2]);
+        oi3 = Oi2[0] * rx + Oi2[1] * ry + Oi2[2] * rz;
+        ok3 = Ok2[0] * rx + Ok2[1] * ry + Ok2[2] * rz;
+        const R Oi2dk = Oi2[0] * dk[0] + Oi2[1] * dk[1] + Oi2[2] * dk[2];
+        const R diOk2 = di[0] * Ok2[0] + di[1] * Ok2[1] + di[2] * Ok2[2];
+        const R Oi2Qkr = Oi2[0] * Qkr[0] + Oi2[1] * Qkr[1] + Oi2[2] * Qkr[2];
+        const R QirOk2 = Qir[0] * Ok2[0] + Qir[1] * Ok2[1] + Qir[2] * Ok2[2];
+        const R Oi2Ok2 = Oi2[0] * Ok2[0] + Oi2[1] * Ok2[1] + Oi2[2] * Ok2[2];
+        c3 += ci * ok3 - ck * oi3 + 3 * (Oi2dk + diOk2) + 6 * (sym_dot(Qi, Ok1) - sym_dot(Oi1, Qk) + oct_dot(Oi, Ok));
+        c4 += -oi3 * dkr - dir * ok3 + 6 * (Oi2Qkr - QirOk2) - 18 * sym_dot(Oi1, Ok1);
+        c5 = -oi3 * qkrr + qirr * ok3 + 9 * Oi2Ok2;
+        c6 = -oi3 * ok3;
+    }
     if constexpr (SRC) {
         // ew = 1: the terms go straight into the accumulator
         te += c0 * B[0];
         if constexpr (ORD >= 1) te += c1 * B[1] + c2 * B[2];
         if constexpr (ORD >= 2) te += c3 * B[3] + c4 * B[4];
+        if constexpr (ORD >= 3) te += c5 * B[5] + c6 * B[6];
     } else {
         R E = c0 * B[0];
         if constexpr (ORD >= 1) E += c1 * B[1] + c2 * B[2];
         if constexpr (ORD >= 2) E += c3 * B[3] + c4 * B[4];
+        if constexpr (ORD >= 3) E += c5 * B[5] + c6 * B[6];
         te += ew * E;
     }
     if constexpr (!GRAD && !FIELD) return;
@@ -286,11 +347,16 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
             a1 -= qkrr * B[3];
             a2 += qirr * B[3];
         }
+        if constexpr (ORD >= 3) {
+            a1 -= ok3 * B[4];
+            a2 -= oi3 * B[4];
+        }
     }
     if constexpr (GRAD) {
         R sn = c0 * B[1];
         if constexpr (ORD >= 1) sn += c1 * B[2] + c2 * B[3];
         if constexpr (ORD >= 2) sn += c3 * B[4] + c4 * B[5];
+        if constexpr (ORD >= 3) sn += c5 * B[6] + c6 * B[7];
         R gr[3];
 #pragma unroll
         for (int a = 0; a < 3; a++) gr[a] = -sn * rv[a];
@@ -299,8 +365,12 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
             for (int a = 0; a < 3; a++) gr[a] += a1 * di[a] + a2 * dk[a];
         }
         if constexpr (ORD >= 2) {
-            const R a3 = 2 * (ci * B[2] - dir * B[3] + qirr * B[4]);
-            const R a4 = 2 * (ck * B[2] + dkr * B[3] + qkrr * B[4]);
+            R a3 = 2 * (ci * B[2] - dir * B[3] + qirr * B[4]);
+            R a4 = 2 * (ck * B[2] + dkr * B[3] + qkrr * B[4]);
+            if constexpr (ORD >= 3) {
+                a3 -= 2 * oi3 * B[5];
+                a4 += 2 * ok3 * B[5];
+            }
             // b2 (Qk di - Qi dk) + b3 (Qi Qk r + Qk Qi r) = Qk (b2 di + b3 Qi r) + Qi (b3 Qk r - b2 dk):
             // two products with a quadrupole instead of four
             const R b2 = 2 * B[2], b3 = -4 * B[3];
@@ -310,6 +380,30 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
                 gr[a] += a3 * Qkr[a] + a4 * Qir[a];
                 w1[a] = b2 * di[a] + b3 * Qir[a];
                 w2[a] = b3 * Qkr[a] - b2 * dk[a];
+            }
+            if constexpr (ORD >= 3) {
+                const R b4 = 6 * B[4];
+                const R gi = -3 * (ck * B[3] + dkr * B[4] + qkrr * B[5] + ok3 * B[6]);
+                const R gk = 3 * (ci * B[3] - dir * B[4] + qirr * B[5] - oi3 * B[6]);
+                const R e3 = 6 * B[3], e4 = 12 * B[4], e5 = 18 * B[5], f4 = 18 * B[4];
+                R u1[3], u2[3], M1[6], M2[6];
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    w1[a] += b4 * Oi2[a];
+                    w2[a] -= b4 * Ok2[a];
+                    gr[a] += gi * Oi2[a] + gk * Ok2[a];
+                    u1[a] = e3 * dk[a] + e4 * Qkr[a] + e5 * Ok2[a];
+                    u2[a] = e3 * di[a] - e4 * Qir[a] + e5 * Oi2[a];
+                }
+#pragma unroll
+                for (int c = 0; c < 6; c++) {
+                    M1[c] = -e3 * Qk[c] - f4 * Ok1[c];
+                    M2[c] = e3 * Qi[c] - f4 * Oi1[c];
+                }
+                symv_acc(Oi1, u1, gr);
+                symv_acc(Ok1, u2, gr);
+                oct_mat_acc(Oi, M1, gr);
+                oct_mat_acc(Ok, M2, gr);
             }
             symv_acc(Qk, w1, gr);
             symv_acc(Qi, w2, gr);
@@ -327,10 +421,12 @@ __device__ inline void pair_terms(R rx, R ry, R rz, R ci, const R *di, const R *
             tg[a] += B[1] * dk[a];
             tg[a] += a1 * rv[a];
             if constexpr (ORD >= 2) tg[a] += b2 * Qkr[a];
+            if constexpr (ORD >= 3) tg[a] += 3 * B[3] * Ok2[a];
             if constexpr (SRC) {
                 sg[a] += B[1] * di[a];
                 sg[a] += a2 * rv[a];
                 if constexpr (ORD >= 2) sg[a] -= b2 * Qir[a];
+                if constexpr (ORD >= 3) sg[a] += 3 * B[3] * Oi2[a];
             }
         }
     }
@@ -368,7 +464,7 @@ __device__ inline void task_offset(int k, int &dx, int &dy, int &dz) {
 // covers TPASS positions; more than one only for crowded half-shells).
 template <typename R, int ORD, bool GRAD, bool FIELD, int SL>
 __global__ __launch_bounds__(BT) void k_p2p(P2PArgs<R> a) {
-    constexpr int NM = 1 + (ORD >= 1 ? 3 : 0) + (ORD >= 2 ? 6 : 0);   // moment components
+    constexpr int NM = 1 + (ORD >= 1 ? 3 : 0) + (ORD >= 2 ? 6 : 0) + (ORD >= 3 ? 10 : 0);   // moment components
     constexpr bool ADJ = GRAD || FIELD;
     __shared__ double sx[CH], sy[CH], sz[CH];
     __shared__ R smo[NM][CH];
@@ -408,6 +504,7 @@ __global__ __launch_bounds__(BT) void k_p2p(P2PArgs<R> a) {
     const int s0 = a.offs[leaf], nsrc = a.offs[leaf + 1] - s0;
 
     const R *q = pick<R>(a.q, a.qf), *mu = pick<R>(a.mu, a.muf), *th = pick<R>(a.th, a.thf);
+    const R *om = pick<R>(a.om, a.omf);
     const int64_t n = a.n;
     R *SF = static_cast<R *>(a.slot_f), *SG = static_cast<R *>(a.slot_g);
     const int64_t sstride = (int64_t)kNumSlots * n;     // component stride of the slot arrays
@@ -425,12 +522,14 @@ __global__ __launch_bounds__(BT) void k_p2p(P2PArgs<R> a) {
                 for (int c = 0; c < 3; c++) smo[1 + c][f] = mu[c * n + sj];
             if (ORD >= 2)
                 for (int c = 0; c < 6; c++) smo[4 + c][f] = th[c * n + sj];
+            if (ORD >= 3)
+                for (int c = 0; c < 10; c++) smo[10 + c][f] = om[c * n + sj];
         }
     };
     // one target atom: position (in the source leaf's frame) and moments
     struct Target {
         double x, y, z;
-        R c, d[3], Q[6];
+        R c, d[3], Q[6], O[ORD >= 3 ? 10 : 1];
     };
     // list position f of the mutual tasks (valid if f < ntg), or atom s0 + f of the own leaf; an absent
     // target sits far away with zero moments, so its pair terms vanish
@@ -460,11 +559,24 @@ __global__ __launch_bounds__(BT) void k_p2p(P2PArgs<R> a) {
         for (int c = 0; c < 3; c++) t.d[c] = (ORD >= 1 && iv) ? (mu + (int64_t)c * n)[u] : (R)0;
 #pragma unroll
         for (int c = 0; c < 6; c++) t.Q[c] = (ORD >= 2 && iv) ? (th + (int64_t)c * n)[u] : (R)0;
+        if constexpr (ORD >= 3) {
+#pragma unroll
+            for (int c = 0; c < 10; c++) t.O[c] = iv ? (om + (int64_t)c * n)[u] : (R)0;
+        }
     };
     auto slot_ptr = [&](int c, int slot, int64_t at) {
         return (c < 3 ? SF + (int64_t)c * sstride : SG + (int64_t)(c - 3) * sstride) + (int64_t)slot * n + at;
     };
     constexpr int c_lo = GRAD ? 0 : 3, c_hi = FIELD ? 6 : 3;   // the slot components that are written
+    // the higher moments of chunk atom j
+    auto partner = [&](int j, R *dk, R *Qk, R *Ok) {
+        if (ORD >= 1)
+            for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
+        if (ORD >= 2)
+            for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
+        if (ORD >= 3)
+            for (int c = 0; c < 10; c++) Ok[c] = smo[10 + c][j];
+    };
 
     // mutual tasks: every pass of target positions against every source chunk
     const int npass = ntg > 0 ? (ntg + TPASS - 1) / TPASS : (nsrc > 0 ? 1 : 0);
@@ -486,19 +598,17 @@ __global__ __launch_bounds__(BT) void k_p2p(P2PArgs<R> a) {
             R te = 0;
             for (int j = 0; j < chn; j++) {
                 const double xs = sx[j], ys = sy[j], zs = sz[j];
-                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
-                if (ORD >= 1)
-                    for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
-                if (ORD >= 2)
-                    for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
+                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0}, Ok[ORD >= 3 ? 10 : 1];
+                partner(j, dk, Qk, Ok);
                 const R ck = smo[0][j];
                 R sf[3] = {0, 0, 0}, sg[3] = {0, 0, 0};
                 pair_terms<R, ORD, GRAD, FIELD, true, SL>((R)(t0.x - xs), (R)(t0.y - ys), (R)(t0.z - zs), t0.c,
-                                                           t0.d, t0.Q, ck, dk, Qk, rc, (R)1, te, tf0, tg0, sf, sg);
+                                                           t0.d, t0.Q, t0.O, ck, dk, Qk, Ok, rc, (R)1, te, tf0, tg0,
+                                                           sf, sg);
                 if (two)
                     pair_terms<R, ORD, GRAD, FIELD, true, SL>((R)(t1.x - xs), (R)(t1.y - ys), (R)(t1.z - zs),
-                                                               t1.c, t1.d, t1.Q, ck, dk, Qk, rc, (R)1, te, tf1,
-                                                               tg1, sf, sg);
+                                                               t1.c, t1.d, t1.Q, t1.O, ck, dk, Qk, Ok, rc, (R)1, te,
+                                                               tf1, tg1, sf, sg);
                 if constexpr (ADJ) {
                     // the source's share of this step, summed over each row of 16 lanes
                     R v[6];
@@ -560,26 +670,26 @@ __global__ __launch_bounds__(BT) void k_p2p(P2PArgs<R> a) {
             for (int c = 0; c < 3; c++) t.d[c] = (ORD >= 1 && iv) ? smo[1 + c][ii] : (R)0;
 #pragma unroll
             for (int c = 0; c < 6; c++) t.Q[c] = (ORD >= 2 && iv) ? smo[4 + c][ii] : (R)0;
+            if constexpr (ORD >= 3) {
+#pragma unroll
+                for (int c = 0; c < 10; c++) t.O[c] = iv ? smo[10 + c][ii] : (R)0;
+            }
             R te = 0, tf[3] = {0, 0, 0}, tg[3] = {0, 0, 0};
             if constexpr (ADJ) {
 #pragma unroll
                 for (int c = c_lo; c < c_hi; c++) wpart[c][0][i] = (R)0;
             }
-            auto partner = [&](int j, R *dk, R *Qk) {
-                if (ORD >= 1)
-                    for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
-                if (ORD >= 2)
-                    for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
-            };
             const int K = (m - 1) / 2;
             for (int k = 1; k <= K; k++) {
                 int j = i + k;
                 if (j >= m) j -= m;
                 if (!iv) j = 0;
-                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0}, sf[3] = {0, 0, 0}, sg[3] = {0, 0, 0};
-                partner(j, dk, Qk);
+                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0}, Ok[ORD >= 3 ? 10 : 1], sf[3] = {0, 0, 0},
+                  sg[3] = {0, 0, 0};
+                partner(j, dk, Qk, Ok);
                 pair_terms<R, ORD, GRAD, FIELD, true, SL>((R)(t.x - sx[j]), (R)(t.y - sy[j]), (R)(t.z - sz[j]), t.c,
-                                                           t.d, t.Q, smo[0][j], dk, Qk, rc, (R)1, te, tf, tg, sf, sg);
+                                                           t.d, t.Q, t.O, smo[0][j], dk, Qk, Ok, rc, (R)1, te, tf, tg,
+                                                           sf, sg);
                 if constexpr (ADJ) {
                     // LDS atomics: other lanes read and add these entries in later steps (in this wave's
                     // instruction order); within one step every lane has its own entry
@@ -595,11 +705,11 @@ __global__ __launch_bounds__(BT) void k_p2p(P2PArgs<R> a) {
                 int j = i + m / 2;
                 if (j >= m) j -= m;
                 if (!iv) j = 0;
-                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
-                partner(j, dk, Qk);
+                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0}, Ok[ORD >= 3 ? 10 : 1];
+                partner(j, dk, Qk, Ok);
                 pair_terms<R, ORD, GRAD, FIELD, false, SL>((R)(t.x - sx[j]), (R)(t.y - sy[j]), (R)(t.z - sz[j]),
-                                                            t.c, t.d, t.Q, smo[0][j], dk, Qk, rc, (R)0.5, te, tf, tg,
-                                                            nullptr, nullptr);
+                                                            t.c, t.d, t.Q, t.O, smo[0][j], dk, Qk, Ok, rc, (R)0.5, te,
+                                                            tf, tg, nullptr, nullptr);
             }
             eacc += (double)te;
             // the atom's own-leaf partials (its target side, then its source shares), added to its slot by
@@ -632,14 +742,11 @@ __global__ __launch_bounds__(BT) void k_p2p(P2PArgs<R> a) {
             __syncthreads();
             for (int j = wv; j < chn; j += NW) {
                 if (cs + j == i) continue;   // an atom with itself at zero shift
-                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0};
-                if (ORD >= 1)
-                    for (int c = 0; c < 3; c++) dk[c] = smo[1 + c][j];
-                if (ORD >= 2)
-                    for (int c = 0; c < 6; c++) Qk[c] = smo[4 + c][j];
+                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0}, Ok[ORD >= 3 ? 10 : 1];
+                partner(j, dk, Qk, Ok);
                 pair_terms<R, ORD, GRAD, FIELD, false, SL>((R)(t.x - sx[j]), (R)(t.y - sy[j]), (R)(t.z - sz[j]),
-                                                            t.c, t.d, t.Q, smo[0][j], dk, Qk, rc, (R)0.5, te, tf, tg,
-                                                            nullptr, nullptr);
+                                                            t.c, t.d, t.Q, t.O, smo[0][j], dk, Qk, Ok, rc, (R)0.5, te,
+                                                            tf, tg, nullptr, nullptr);
             }
         }
         eacc += (double)te;
@@ -700,6 +807,7 @@ __global__ __launch_bounds__(256) void k_epilogue(EpiArgs<R> a) {
     const int64_t l0 = a.nleaf * b / kRedBlocks, l1 = a.nleaf * (b + 1) / kRedBlocks;
     const double xi = a.xi;
     const double c0 = -xi / sqrt(3.14159265358979323846), c1 = 2 * xi * xi / 3, c2 = 8 * xi * xi * xi * xi / 5;
+    const double c3 = 48 * xi * xi * xi * xi * xi * xi / 7;
     double near = 0, self = 0, qs = 0, far = 0;
     for (int64_t s = a0 + t; s < a1; s += 256) {
         const double q = a.P.q[s];
@@ -713,6 +821,16 @@ __global__ __launch_bounds__(256) void k_epilogue(EpiArgs<R> a) {
             const double xx = a.P.th[s], xy = a.P.th[n + s], xz = a.P.th[2 * n + s];
             const double yy = a.P.th[3 * n + s], yz = a.P.th[4 * n + s], zz = a.P.th[5 * n + s];
             v += c2 * (xx * xx + yy * yy + zz * zz + 2 * (xy * xy + xz * xz + yz * yz));
+        }
+        if (a.ord >= 3) {
+            // Omega : Omega, each stored component with its multiplicity
+            constexpr double mult[10] = {1, 3, 3, 3, 6, 3, 1, 3, 3, 1};
+            double oo = 0;
+            for (int c = 0; c < 10; c++) {
+                const double o = a.P.om[c * n + s];
+                oo += mult[c] * o * o;
+            }
+            v += c3 * oo;
         }
         self += c0 * v;
         const int64_t i = a.perm[s];
@@ -931,10 +1049,15 @@ hipError_t launch_t(ankh_plan_s *pl, P2PArgs<R> a, int ord, bool grad, bool fiel
         if (grad) { if (fields) ANKH_P2P(1, true, true); else ANKH_P2P(1, true, false); }
         else if (fields) ANKH_P2P(1, false, true);
         else ANKH_P2P(1, false, false);
-    } else {
+    } else if (ord == 2) {
         if (grad) { if (fields) ANKH_P2P(2, true, true); else ANKH_P2P(2, true, false); }
         else if (fields) ANKH_P2P(2, false, true);
         else ANKH_P2P(2, false, false);
+    } else {
+        // octupoles: a fields-only evaluation also writes the force partials (three variants, not four)
+        if (fields) ANKH_P2P(3, true, true);
+        else if (grad) ANKH_P2P(3, true, false);
+        else ANKH_P2P(3, false, false);
     }
 #undef ANKH_P2P
     return hipGetLastError();
@@ -980,6 +1103,8 @@ hipError_t launch_prec(ankh_plan_s *pl, int ord, bool grad, bool fields) {
     a.qf = pl->P.qf;
     a.muf = pl->P.muf;
     a.thf = pl->P.thf;
+    a.om = pl->P.om;
+    a.omf = pl->P.omf;
     a.offs = pl->d_offs;
     a.n = pl->n;
     a.nside = pl->nside;

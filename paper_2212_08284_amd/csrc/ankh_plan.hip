@@ -51,6 +51,7 @@ void dalloc(ankh_plan_s *pl, T **p, size_t count) {
 void free_all(ankh_plan_s *pl) {
     void *ptrs[] = {pl->d_tab, pl->d_leaf, pl->d_count, pl->d_offs, pl->d_rank, pl->d_perm, pl->d_tmp,
                     pl->P.x, pl->P.y, pl->P.z, pl->P.q, pl->P.mu, pl->P.th, pl->P.qf, pl->P.muf, pl->P.thf,
+                    pl->P.om, pl->P.omf,
                     pl->d_M, pl->d_L, pl->d_K, pl->d_Kf, pl->d_Cper, pl->d_eleaf, pl->d_F,
                     pl->d_G, pl->d_terms, pl->d_part, pl->d_err, pl->d_tab0, pl->d_Mf, pl->d_m2l_part,
                     pl->root_owned ? pl->d_rootM : nullptr, pl->root_owned ? pl->d_rootL : nullptr,
@@ -152,11 +153,11 @@ void build_tables(ankh_plan_s *pl) {
 bool stage_recorded(int mode, int stage) { return mode == 1 || (mode == 2 && (stage == 4 || stage == 8)); }
 
 ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th,
-                double *energy, double *forces, double *dEdmu) {
+                double *energy, double *forces, double *dEdmu, const double *om = nullptr) {
     // forces and / or fields (dE/dmu); a null forces pointer with fields asked for is the fields-only
     // evaluation of the induced-dipole iteration (the pair kernel then skips the force arithmetic)
     const bool grad = forces != nullptr;
-    const int ord = th ? 2 : (mu ? 1 : 0);
+    const int ord = om ? 3 : (th ? 2 : (mu ? 1 : 0));
     const bool fields = dEdmu && ord >= 1;
     const bool adj = grad || fields;
     hipStream_t s = pl->stream;
@@ -183,7 +184,7 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
         mark(0);
         ck(launch_sort(pl, pos, q, mu, th));
         mark(1);
-        ck(launch_gather(pl, pos, q, mu, th));
+        ck(launch_gather(pl, pos, q, mu, th, om));
         mark(2);
         if (overlap) {
             ck(hipEventRecord(pl->ev_fork, s));
@@ -283,7 +284,7 @@ const char *ankh_status_string(ankh_status st) {
         case ANKH_OK: return "ok";
         case ANKH_ERR_INVALID_ARG: return "invalid argument";
         case ANKH_ERR_NONFINITE_INPUT: return "non-finite input";
-        case ANKH_ERR_THETA_NOT_TRACELESS: return "quadrupole not traceless";
+        case ANKH_ERR_THETA_NOT_TRACELESS: return "quadrupole or octupole not traceless";
         case ANKH_ERR_LEAF_OVERFLOW: return "leaf overflow";
         case ANKH_ERR_ACCURACY_UNREACHABLE: return "accuracy unreachable in this precision";
         case ANKH_ERR_OUT_OF_MEMORY: return "out of device memory";
@@ -299,7 +300,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
     if (n_atoms < 1 || n_atoms > (int64_t)0x7fffffff) return ANKH_ERR_INVALID_ARG;
     if (!(box_radius > 0) || !std::isfinite(box_radius)) return ANKH_ERR_INVALID_ARG;
     if (!(rel_accuracy >= 1e-12 && rel_accuracy <= 1e-2)) return ANKH_ERR_INVALID_ARG;
-    if (max_order < 0 || max_order > 2) return ANKH_ERR_INVALID_ARG;
+    if (max_order < 0 || max_order > 3) return ANKH_ERR_INVALID_ARG;
     if (precision != ANKH_FP64 && precision != ANKH_MIXED && precision != ANKH_MIXED_BF16X3) return ANKH_ERR_INVALID_ARG;
     if (precision != ANKH_FP64 && rel_accuracy < 1e-7) return ANKH_ERR_ACCURACY_UNREACHABLE;
     if (ov) {
@@ -492,10 +493,12 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         dalloc(pl, &pl->P.q, n);
         if (max_order >= 1) dalloc(pl, &pl->P.mu, 3 * n);
         if (max_order >= 2) dalloc(pl, &pl->P.th, 6 * n);
+        if (max_order >= 3) dalloc(pl, &pl->P.om, 10 * n);
         if (precision != ANKH_FP64) {
             dalloc(pl, &pl->P.qf, n);
             if (max_order >= 1) dalloc(pl, &pl->P.muf, 3 * n);
             if (max_order >= 2) dalloc(pl, &pl->P.thf, 6 * n);
+            if (max_order >= 3) dalloc(pl, &pl->P.omf, 10 * n);
         }
         dalloc(pl, &pl->d_M, cells * pl->nup);
         dalloc(pl, &pl->d_L, cells * pl->nup);
@@ -678,6 +681,15 @@ ankh_status ankh_energy_forces(ankh_plan_t pl, const double *pos, const double *
     if (st != ANKH_OK) return st;
     if (!energy || !forces) return ANKH_ERR_INVALID_ARG;
     return run(pl, pos, q, mu, theta, energy, forces, dE_dmu);
+}
+
+ankh_status ankh_energy_octupole(ankh_plan_t pl, const double *pos, const double *q, const double *mu,
+                                 const double *theta, const double *omega, double *energy, double *forces,
+                                 double *dE_dmu) {
+    ankh_status st = check_inputs(pl, pos, q, mu, theta);
+    if (st != ANKH_OK) return st;
+    if (!energy || !omega || pl->max_order < 3) return ANKH_ERR_INVALID_ARG;
+    return run(pl, pos, q, mu, theta, energy, forces, dE_dmu, omega);
 }
 
 ankh_status ankh_energy_derivs(ankh_plan_t pl, const double *pos, const double *q, const double *mu,

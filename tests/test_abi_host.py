@@ -60,7 +60,7 @@ def _plan(lib, n=100, rb=10.0, eps=1e-6, order=2, prec=0, ov=None):
 
 
 @pytest.mark.parametrize("kw", [dict(n=0), dict(n=-5), dict(rb=0.0), dict(rb=-1.0), dict(rb=float("nan")),
-                                dict(eps=1e-13), dict(eps=0.5), dict(order=3), dict(order=-1), dict(prec=7)])
+                                dict(eps=1e-13), dict(eps=0.5), dict(order=4), dict(order=-1), dict(prec=7)])
 def test_plan_rejects_invalid_arguments(lib, kw):
     st, h = _plan(lib, **kw)
     assert st == 1          # ANKH_ERR_INVALID_ARG
@@ -127,4 +127,5 @@ def test_null_plan_and_null_outputs(lib):
     assert lib.ankh_induce(None, vp(8), vp(8), None, None, vp(8), 1e-8, 10, vp(8), None, None, None, None) == 1
     assert lib.ankh_energy_derivs(None, vp(8), vp(8), None, None, vp(8), None, None, vp(8), None) == 1
     assert lib.ankh_energy_derivs_noalloc(None, vp(8), vp(8), None, None, vp(8), None, None, vp(8), None) == 1
+    assert lib.ankh_energy_octupole(None, vp(8), vp(8), None, None, vp(8), vp(8), None, None) == 1
     lib.ankh_destroy(None)   # no-op
