@@ -8,8 +8,9 @@
 // d > 0 (lexicographically), and every pair of atoms in it is evaluated once:
 // the target atom (in s - d) takes the energy, its force and its field, the
 // source atom (in s) the opposite force and its own field.  The leaf with
-// itself is a fourteenth task, evaluated in gather form (all ordered pairs,
-// half energy).
+// itself is a fourteenth task: up to 64 atoms in mutual form by a round robin
+// in lane groups of one wave, more in gather form (all ordered pairs, half
+// energy).
 //
 // One block per source leaf s evaluates its 13 mutual tasks and its own leaf.
 // The atoms of the 13 target leaves form one list; lane l of the block owns
@@ -468,7 +469,8 @@ __global__ __launch_bounds__(BT) void k_p2p(P2PArgs<R> a) {
     constexpr bool ADJ = GRAD || FIELD;
     __shared__ double sx[CH], sy[CH], sz[CH];
     __shared__ R smo[NM][CH];
-    __shared__ R wpart[ADJ ? 6 : 1][NROW][CH];   // source shares per row and chunk atom; own-leaf partials per wave
+    __shared__ R wpart[ADJ ? 6 : 1][NROW][CH];   // source shares per row and chunk atom; own-leaf partials per
+                                                 // lane group; gather-form partials per wave
     __shared__ int tfirst[NHALF], tpre[NHALF + 1];   // target leaves: first atom, list prefix
     __shared__ double tshift[NHALF][3];              // their position shift into the source leaf's frame, -d w
     __shared__ double ered[NROW];
@@ -651,76 +653,84 @@ __global__ __launch_bounds__(BT) void k_p2p(P2PArgs<R> a) {
     }
 
     // the leaf with itself.  Up to CH atoms (the chunk still in LDS): the unordered pairs in mutual form,
-    // round robin in one wave: lane i pairs with i + k (mod m) for k = 1 .. (m - 1) / 2, its source shares
-    // accumulated in LDS (the partners of one step are distinct, so no two lanes touch one entry), and for
-    // even m the pair at distance m / 2 once from each side in gather form with half energy.
+    // round robin in one wave.  Step k pairs atom i with i + k (mod m), k = 1 .. (m - 1) / 2, and for even m
+    // the atoms i < m / 2 with i + m / 2 (each pair once).  The wave holds G = min(64 / m, 8) groups of m
+    // lanes (lane g m + i is atom i of group g), and group g takes steps g, g + G, ...: a G-th of the steps
+    // per wave instead of all of them on m lanes.  Each group adds its source shares into its own LDS row
+    // (the partners of one step are distinct, so no two lanes of an instruction touch one entry; the adds
+    // to an entry follow the wave's instruction order), then the groups' target partials and source rows
+    // are summed per atom in group order.
     if (nsrc > 0 && nsrc <= CH) {
         const int m = nsrc;
         __syncthreads();   // the mutual phase's readers of wpart are done
         if (wv == 0) {
-            const int i = lane;
-            const bool iv = i < m;
-            const int ii = iv ? i : 0;
+            const int K = (m - 1) / 2, U = K + ((m & 1) == 0 ? 1 : 0);   // steps
+            const int G = max(1, min(min(64 / m, 8), U));
+            const int g = lane / m, i = lane - g * m;
+            const bool inl = g < G;
+            const int ii = inl ? i : 0;
             Target t;
-            t.x = iv ? sx[ii] : 1.0e4;
-            t.y = iv ? sy[ii] : 1.0e4;
-            t.z = iv ? sz[ii] : 1.0e4;
-            t.c = iv ? smo[0][ii] : (R)0;
+            t.x = sx[ii];
+            t.y = sy[ii];
+            t.z = sz[ii];
+            t.c = smo[0][ii];
 #pragma unroll
-            for (int c = 0; c < 3; c++) t.d[c] = (ORD >= 1 && iv) ? smo[1 + c][ii] : (R)0;
+            for (int c = 0; c < 3; c++) t.d[c] = ORD >= 1 ? smo[1 + c][ii] : (R)0;
 #pragma unroll
-            for (int c = 0; c < 6; c++) t.Q[c] = (ORD >= 2 && iv) ? smo[4 + c][ii] : (R)0;
+            for (int c = 0; c < 6; c++) t.Q[c] = ORD >= 2 ? smo[4 + c][ii] : (R)0;
             if constexpr (ORD >= 3) {
 #pragma unroll
-                for (int c = 0; c < 10; c++) t.O[c] = iv ? smo[10 + c][ii] : (R)0;
+                for (int c = 0; c < 10; c++) t.O[c] = smo[10 + c][ii];
             }
             R te = 0, tf[3] = {0, 0, 0}, tg[3] = {0, 0, 0};
             if constexpr (ADJ) {
+                if (inl) {
 #pragma unroll
-                for (int c = c_lo; c < c_hi; c++) wpart[c][0][i] = (R)0;
+                    for (int c = c_lo; c < c_hi; c++) wpart[c][g][i] = (R)0;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
             }
-            const int K = (m - 1) / 2;
-            for (int k = 1; k <= K; k++) {
-                int j = i + k;
-                if (j >= m) j -= m;
-                if (!iv) j = 0;
-                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0}, Ok[ORD >= 3 ? 10 : 1], sf[3] = {0, 0, 0},
-                  sg[3] = {0, 0, 0};
-                partner(j, dk, Qk, Ok);
-                pair_terms<R, ORD, GRAD, FIELD, true, SL>((R)(t.x - sx[j]), (R)(t.y - sy[j]), (R)(t.z - sz[j]), t.c,
-                                                           t.d, t.Q, t.O, smo[0][j], dk, Qk, Ok, rc, (R)1, te, tf, tg,
-                                                           sf, sg);
-                if constexpr (ADJ) {
-                    // LDS atomics: other lanes read and add these entries in later steps (in this wave's
-                    // instruction order); within one step every lane has its own entry
-                    if (iv) {
+            for (int u0 = 0; u0 < U; u0 += G) {
+                const int u = u0 + g;
+                const int k = u < K ? u + 1 : m / 2;
+                // lanes without a pair in this step sit it out (masked: the step costs the wave one pair)
+                if (inl && u < U && (u < K || i < m / 2)) {
+                    int j = i + k;
+                    if (j >= m) j -= m;
+                    R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0}, Ok[ORD >= 3 ? 10 : 1], sf[3] = {0, 0, 0},
+                      sg[3] = {0, 0, 0};
+                    partner(j, dk, Qk, Ok);
+                    pair_terms<R, ORD, GRAD, FIELD, true, SL>((R)(t.x - sx[j]), (R)(t.y - sy[j]), (R)(t.z - sz[j]),
+                                                               t.c, t.d, t.Q, t.O, smo[0][j], dk, Qk, Ok, rc, (R)1, te,
+                                                               tf, tg, sf, sg);
+                    if constexpr (ADJ) {
 #pragma unroll
-                        for (int c = c_lo; c < c_hi; c++) atomicAdd(&wpart[c][0][j], c < 3 ? sf[c] : sg[c - 3]);
+                        for (int c = c_lo; c < c_hi; c++) atomicAdd(&wpart[c][g][j], c < 3 ? sf[c] : sg[c - 3]);
                     }
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            if ((m & 1) == 0) {
-                int j = i + m / 2;
-                if (j >= m) j -= m;
-                if (!iv) j = 0;
-                R dk[3] = {0, 0, 0}, Qk[6] = {0, 0, 0, 0, 0, 0}, Ok[ORD >= 3 ? 10 : 1];
-                partner(j, dk, Qk, Ok);
-                pair_terms<R, ORD, GRAD, FIELD, false, SL>((R)(t.x - sx[j]), (R)(t.y - sy[j]), (R)(t.z - sz[j]),
-                                                            t.c, t.d, t.Q, t.O, smo[0][j], dk, Qk, Ok, rc, (R)0.5, te,
-                                                            tf, tg, nullptr, nullptr);
-            }
             eacc += (double)te;
-            // the atom's own-leaf partials (its target side, then its source shares), added to its slot by
-            // its owner thread, which wrote the slot in the mutual phase
             if constexpr (ADJ) {
-                if (iv) {
+                // the groups' target partials into rows G .. 2G - 1, then per atom, by its owner thread (lane
+                // i of group 0, which wrote the slot in the mutual phase): the target partials and source
+                // rows of the groups in group order
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                if (inl) {
+#pragma unroll
+                    for (int c = c_lo; c < c_hi; c++) wpart[c][G + g][i] = c < 3 ? tf[c] : tg[c - 3];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                if (g == 0) {
                     const int64_t sj = s0 + i;
 #pragma unroll
                     for (int c = c_lo; c < c_hi; c++) {
+                        R sum = 0;
+                        for (int gg = 0; gg < G; gg++) sum += wpart[c][G + gg][i] + wpart[c][gg][i];
                         R *p = slot_ptr(c, kSlotSrc, sj);
-                        *p = *p + ((c < 3 ? tf[c] : tg[c - 3]) + wpart[c][0][i]);
+                        *p = *p + sum;
                     }
                 }
             }
