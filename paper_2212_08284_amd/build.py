@@ -15,7 +15,7 @@ SOURCES = ["ankh_plan.hip", "ankh_kernels.hip", "ankh_m2l.hip", "ankh_p2p.hip", 
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
     # packed FP32 instructions stay disabled (the compiler would otherwise form
     # them from ordinary float code)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -35,6 +35,10 @@ def build(verbose: bool = False) -> str:
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+        # compiler warnings are reported (the host pass's note on the disabled packed-FP32 feature is not)
+        warn = [ln for ln in r.stderr.splitlines() if "warning:" in ln and "packed-fp32-ops" not in ln]
+        if warn:
+            print("\n".join(warn), file=sys.stderr, flush=True)
         return obj
 
     with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:

@@ -795,7 +795,6 @@ __device__ inline void tiles_phase2(Cplx<R> *t, int ntile) {
 // one axis of every tile: forward (natural -> digit-reversed) or inverse (digit-reversed -> natural)
 template <typename R, int N2, bool ALONG_V, bool INV, int ROW = 4 * N2>
 __device__ inline void tiles_axis(Cplx<R> *t, int ntile, const Cplx<R> *tw) {
-    using C = Cplx<R>;
     if (!INV) {
         tiles_phase1<R, N2, ALONG_V, false, ROW>(t, ntile, tw);
         tiles_phase2<R, N2, ALONG_V, false, ROW>(t, ntile);

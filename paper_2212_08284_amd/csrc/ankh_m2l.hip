@@ -692,7 +692,6 @@ hipError_t launch_m2l(ankh_plan_s *pl, int e) {
     // levels before the first contraction), L = L' U^T (after the last)
     double *Msrc = comp ? pl->d_Mc + pl->c_off[e] : const_cast<double *>(M);
     double *Ldst = comp ? pl->d_Lc + pl->c_off[e] : L;
-    hipError_t err;
     double *out = nsplit > 1 ? pl->d_m2l_part : Ldst;
     // this level's multipoles in the working precision of the contraction
     if (pl->precision == ANKH_MIXED_BF16X3)

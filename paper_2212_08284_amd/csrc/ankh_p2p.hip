@@ -80,9 +80,6 @@ template <typename R> struct P2PArgs {
 template <typename R> __device__ inline R dev_erfc(R v);
 template <> __device__ inline double dev_erfc<double>(double v) { return erfc(v); }
 template <> __device__ inline float dev_erfc<float>(float v) { return erfcf(v); }
-template <typename R> __device__ inline R dev_exp(R v);
-template <> __device__ inline double dev_exp<double>(double v) { return exp(v); }
-template <> __device__ inline float dev_exp<float>(float v) { return expf(v); }
 // 1/sqrt(v) for v = r^2 of a near pair (never denormal, never zero): the
 // hardware reciprocal square root (float32, ~1 ulp), refined in float64 by two
 // Newton steps y <- y (3/2 - v y^2 / 2), each squaring the relative error.
@@ -146,8 +143,8 @@ __device__ inline double row16_sum(double v) {
 // 13 / 8 in float64; exp 14 / 9 terms in float64 (float32 takes the hardware
 // exponential).
 template <typename R, int SL> struct NearSeries;
-template <> struct NearSeries<float, 1> { static constexpr int NE = 7, NX = 8; };
-template <> struct NearSeries<float, 2> { static constexpr int NE = 4, NX = 5; };
+template <> struct NearSeries<float, 1> { static constexpr int NE = 7; };
+template <> struct NearSeries<float, 2> { static constexpr int NE = 4; };
 template <> struct NearSeries<double, 1> { static constexpr int NE = 13, NX = 14; };
 template <> struct NearSeries<double, 2> { static constexpr int NE = 8, NX = 9; };
 // sum_n (-u)^n / (n! (2n+1)) at u = x^2, so that erfc(x) = 1 - (2/sqrt(pi)) x erf_series(u)
@@ -979,9 +976,15 @@ __global__ __launch_bounds__(256) void k_p2p_moments(MomArgs<R> a) {
                     R sv = ck * B[2];
                     if (ORD >= 1) sv += dkr * B[3];
                     if (ORD >= 2) sv += qkrr * B[4];
-                    R v[3];
+                    R v[3] = {0, 0, 0};
+                    if constexpr (ORD >= 1) {
 #pragma unroll
-                    for (int c = 0; c < 3; c++) v[c] = B[2] * dk[c] + 2 * B[3] * Qkr[c];
+                        for (int c = 0; c < 3; c++) v[c] = B[2] * dk[c];
+                    }
+                    if constexpr (ORD >= 2) {
+#pragma unroll
+                        for (int c = 0; c < 3; c++) v[c] += 2 * B[3] * Qkr[c];
+                    }
                     // (xx, xy, xz, yy, yz, zz)
                     constexpr int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll

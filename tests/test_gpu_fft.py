@@ -335,3 +335,29 @@ def test_fft_planning_errors(ak):
     pl = ak.Plan(2_000_000, 100.0, 1e-6, 2, "mixed", far="fft")
     assert pl.stats["depth"] == 5 and pl.stats["far_field"] == ak.ANKH_FAR_FFT and pl.stats["fft_split"] == 1
     pl.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fft_overlap_matches_one_stream(ak, prec):
+    """The far-field chain on the plan's second stream beside the pair kernel gives bitwise the result of
+    the one-stream schedule (every kernel writes its own outputs; the sums run in a fixed order).  Stage
+    timing mode 2 keeps the overlap and times the cell transforms and the pair kernel."""
+    d = synth.workload("water_9000")
+    n = len(d["q"])
+    outs = []
+    for overlap in (True, False):
+        pl = ak.Plan(n, 0.5 * d["edge"], 1e-6, 2, prec, far="fft", leaves=16, overlap=overlap)
+        assert pl.stats["overlap"] == int(overlap) and pl.stats["leaves_per_axis"] == 16
+        e, F, G = pl.energy_forces(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
+        pl.sync()
+        outs.append((e.item(), F.cpu().numpy(), G.cpu().numpy()))
+        if overlap:
+            pl.set_timing(2)
+            for _ in range(3):
+                pl.energy_forces(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
+            st = pl.get_stats()
+            assert st["timed_evals"] == 3
+            assert 0 < st["stage_ms"]["p2p"] < 50 and 0 < st["stage_ms"]["m2l"] < 50
+        pl.close()
+    assert outs[0][0] == outs[1][0]
+    assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[0][2], outs[1][2])
