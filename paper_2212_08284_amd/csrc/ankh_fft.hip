@@ -857,6 +857,163 @@ __global__ __launch_bounds__(kAllThreads) void k_rdft_all(Cplx<R> *X, R *D, cons
     for (int i = threadIdx.x; i < N3; i += T) xf[i] = t[i];
 }
 
+// The evaluation form of k_rdft_all (MODE 0): a persistent grid of one block per CU walks the node
+// frequencies f = blockIdx.x, + gridDim.x, ...  The HBM traffic of frequency f + gridDim.x is issued
+// while f is transformed: its spectrum values go straight into registers in the order of the first z
+// phase (each thread holds the N2 inputs of its z tasks, ZK of them) and its D values in the order of
+// the x products (XK tasks of 4 values); barriers wait for LDS operations only, so these loads stay in
+// flight across the transform.  Three stages work outside LDS:
+//   - the first z phase reads its inputs from those registers (no load pass through LDS);
+//   - the second x phase, the product with D and the first inverse x phase are one step per task (the
+//     4-point transforms of the same four values around the product);
+//   - the last inverse z phase writes its outputs straight to X.
+// Every value is read and written once per frequency, and D read once: 40 B (float32: 20 B) per kept
+// node frequency and leaf, as in k_rdft_all, whose arithmetic and order of operations it keeps.
+template <typename R, int N2>
+__global__ __launch_bounds__(kAllThreads) void k_rdft_pf(Cplx<R> *X, const R *D, const Cplx<R> *twg,
+                                                         int64_t ncell, R scale, int64_t nf) {
+    using C = Cplx<R>;
+    constexpr int N = 4 * N2, NN = N * N, N3 = N * N * N, T = kAllThreads;
+    constexpr int ZT = 4 * NN, ZK = (ZT + T - 1) / T;         // z tasks (line, n1) and per thread
+    constexpr int XT = N2 * NN, XK = (XT + T - 1) / T;        // x tasks (k2, line) and per thread
+    extern __shared__ __align__(16) unsigned char smraw[];
+    C *sm = reinterpret_cast<C *>(smraw);
+    C *t = sm, *tw = sm + N3;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N; i += T) tw[i] = twg[i];
+    C zin[ZK][N2];
+    R dv[XK][4];
+    auto load_z = [&](int64_t f) {
+        const C *xf = X + f * ncell;
+#pragma unroll
+        for (int k = 0; k < ZK; k++) {
+            const int task = tid + k * T;
+            if (task < ZT) {
+                const int line = task >> 2, n1 = task & 3;
+#pragma unroll
+                for (int n2 = 0; n2 < N2; n2++) zin[k][n2] = xf[line * N + n1 + 4 * n2];
+            }
+        }
+    };
+    auto load_d = [&](int64_t f) {
+        const R *df = D + f * ncell;
+#pragma unroll
+        for (int k = 0; k < XK; k++) {
+            const int task = tid + k * T;
+            if (task < XT) {
+                const int k2 = task / NN, line = task - k2 * NN;
+#pragma unroll
+                for (int k1 = 0; k1 < 4; k1++) dv[k][k1] = df[(4 * k2 + k1) * NN + line];
+            }
+        }
+    };
+    int64_t f = blockIdx.x;
+    if (f < nf) {
+        load_z(f);
+        load_d(f);
+    }
+    __syncthreads();   // the roots
+    for (; f < nf; f += gridDim.x) {
+        const int64_t fn = f + gridDim.x;
+        // z, phase 1 (forward), from the registers into LDS
+#pragma unroll
+        for (int k = 0; k < ZK; k++) {
+            const int task = tid + k * T;
+            if (task < ZT) {
+                const int line = task >> 2, n1 = task & 3;
+                C *b = t + line * N;
+#pragma unroll
+                for (int k2 = 0; k2 < N2; k2++) {
+                    R re = 0, im = 0;
+#pragma unroll
+                    for (int n2 = 0; n2 < N2; n2++) {
+                        const C x = zin[k][n2];
+                        if ((n2 * k2) % N2 == 0) {
+                            re += x.x;
+                            im += x.y;
+                            continue;
+                        }
+                        const R wx = Roots<N2>::re[(n2 * k2) % N2], wy = Roots<N2>::im[(n2 * k2) % N2];
+                        re += x.x * wx - x.y * wy;
+                        im += x.x * wy + x.y * wx;
+                    }
+                    const C w = tw[n1 * k2];
+                    b[n1 + 4 * k2] = k2 == 0 ? mkc(re, im) : mkc(re * w.x - im * w.y, re * w.y + im * w.x);
+                }
+            }
+        }
+        if (fn < nf) load_z(fn);
+        __syncthreads();
+        tiles_phase2<R, N2, true, false>(t, N);                // z, phase 2
+        tiles_axis<R, N2, false, false>(t, N, tw);             // y
+        tiles_phase1<R, N2, false, false, NN>(t, 1, tw);       // x, phase 1
+        // x: phase 2, the product with D * scale, and the inverse phase 2, per task
+#pragma unroll
+        for (int k = 0; k < XK; k++) {
+            const int task = tid + k * T;
+            if (task < XT) {
+                const int k2 = task / NN, line = task - k2 * NN;
+                C *b = t + line;
+                const C a = b[(4 * k2) * NN], bb = b[(4 * k2 + 1) * NN], c = b[(4 * k2 + 2) * NN],
+                        d = b[(4 * k2 + 3) * NN];
+                const C s0 = mkc(a.x + c.x, a.y + c.y), s1 = mkc(a.x - c.x, a.y - c.y);
+                const C s2 = mkc(bb.x + d.x, bb.y + d.y), s3 = mkc(bb.x - d.x, bb.y - d.y);
+                const C js3 = mkc(s3.y, -s3.x);
+                const R e0 = dv[k][0] * scale, e1 = dv[k][1] * scale, e2 = dv[k][2] * scale, e3 = dv[k][3] * scale;
+                const C o0 = mkc((s0.x + s2.x) * e0, (s0.y + s2.y) * e0);
+                const C o1 = mkc((s1.x + js3.x) * e1, (s1.y + js3.y) * e1);
+                const C o2 = mkc((s0.x - s2.x) * e2, (s0.y - s2.y) * e2);
+                const C o3 = mkc((s1.x - js3.x) * e3, (s1.y - js3.y) * e3);
+                const C u0 = mkc(o0.x + o2.x, o0.y + o2.y), u1 = mkc(o0.x - o2.x, o0.y - o2.y);
+                const C u2 = mkc(o1.x + o3.x, o1.y + o3.y), u3 = mkc(o1.x - o3.x, o1.y - o3.y);
+                const C ju3 = mkc(-u3.y, u3.x);
+                b[(4 * k2) * NN] = mkc(u0.x + u2.x, u0.y + u2.y);
+                b[(4 * k2 + 1) * NN] = mkc(u1.x + ju3.x, u1.y + ju3.y);
+                b[(4 * k2 + 2) * NN] = mkc(u0.x - u2.x, u0.y - u2.y);
+                b[(4 * k2 + 3) * NN] = mkc(u1.x - ju3.x, u1.y - ju3.y);
+            }
+        }
+        if (fn < nf) load_d(fn);
+        __syncthreads();
+        tiles_phase1<R, N2, false, true, NN>(t, 1, tw);        // x, inverse phase 1
+        tiles_axis<R, N2, false, true>(t, N, tw);              // y, inverse
+        tiles_phase2<R, N2, true, true>(t, N);                 // z, inverse phase 2
+        // z, inverse phase 1, from LDS straight to X
+        C *xf = X + f * ncell;
+#pragma unroll
+        for (int k = 0; k < ZK; k++) {
+            const int task = tid + k * T;
+            if (task < ZT) {
+                const int line = task >> 2, n1 = task & 3;
+                const C *b = t + line * N;
+                C z[N2];
+#pragma unroll
+                for (int k2 = 0; k2 < N2; k2++) {
+                    const C v = b[n1 + 4 * k2], w = tw[n1 * k2];
+                    z[k2] = k2 == 0 ? v : mkc(v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y);
+                }
+#pragma unroll
+                for (int n2 = 0; n2 < N2; n2++) {
+                    R re = 0, im = 0;
+#pragma unroll
+                    for (int k2 = 0; k2 < N2; k2++) {
+                        if ((n2 * k2) % N2 == 0) {
+                            re += z[k2].x;
+                            im += z[k2].y;
+                            continue;
+                        }
+                        const R wx = Roots<N2>::re[(n2 * k2) % N2], wy = Roots<N2>::im[(n2 * k2) % N2];
+                        re += z[k2].x * wx + z[k2].y * wy;
+                        im += z[k2].y * wx - z[k2].x * wy;
+                    }
+                    xf[line * N + n1 + 4 * n2] = mkc(re, im);
+                }
+            }
+        }
+        __syncthreads();   // this frequency's LDS reads are done before the next one's writes
+    }
+}
+
 // passes 1 / 3: block (f, x0 .. x0 + PB), the (y, z) planes
 template <typename R, int N1, int N2, int PB>
 __global__ __launch_bounds__(256) void k_rdft_yz(Cplx<R> *X, const Cplx<R> *twg, int64_t ncell, int inv) {
@@ -1049,6 +1206,19 @@ hipError_t cells(ankh_plan_s *pl, Cplx<R> *X, R *D, const Cplx<R> *tw, R scale) 
         // one block per node frequency with all cells in LDS
         const size_t shm = sizeof(Cplx<R>) * ((size_t)pl->nleaf + pl->nside);
         const dim3 g((unsigned)pl->fft_nf), b(kAllThreads);
+        if constexpr (MODE == 0 && sizeof(R) == 4) {
+            // evaluation in float32: the persistent, prefetching form, one block per CU (in float64 its
+            // registers would spill)
+            const int64_t nf = pl->fft_nf;
+            const dim3 gp((unsigned)std::min<int64_t>(nf, pl->num_cu));
+            if (pl->nside == 12)
+                hipLaunchKernelGGL((k_rdft_pf<R, 3>), gp, b, shm, pl->stream, X, D, tw, pl->nleaf, scale, nf);
+            else if (pl->nside == 20)
+                hipLaunchKernelGGL((k_rdft_pf<R, 5>), gp, b, shm, pl->stream, X, D, tw, pl->nleaf, scale, nf);
+            else
+                hipLaunchKernelGGL((k_rdft_pf<R, 6>), gp, b, shm, pl->stream, X, D, tw, pl->nleaf, scale, nf);
+            return hipGetLastError();
+        }
         if (pl->nside == 12)
             hipLaunchKernelGGL((k_rdft_all<R, 3, MODE>), g, b, shm, pl->stream, X, D, tw, pl->nleaf, scale);
         else if (pl->nside == 20)
@@ -1137,7 +1307,10 @@ bool fft_single_ok(int nside, bool f32) {
         if (f32) {
             const void *k0 = nside == 20 ? reinterpret_cast<const void *>(&k_rdft_all<float, 5, 0>)
                                          : reinterpret_cast<const void *>(&k_rdft_all<float, 6, 0>);
+            const void *k1 = nside == 20 ? reinterpret_cast<const void *>(&k_rdft_pf<float, 5>)
+                                         : reinterpret_cast<const void *>(&k_rdft_pf<float, 6>);
             e = hipFuncSetAttribute(k0, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+            if (e == hipSuccess) e = hipFuncSetAttribute(k1, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         } else if (nside == 20) {
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rdft_all<double, 5, 0>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);

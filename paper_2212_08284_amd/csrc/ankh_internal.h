@@ -137,6 +137,7 @@ struct ankh_plan_s {
     float *d_fftD32 = nullptr;
     size_t bytes = 0;
     int device = 0;               // the HIP device current at plan time (the plan's buffers live there)
+    int num_cu = 256;             // its compute units (the persistent grid of the one-block cell transforms)
     size_t bytes_limit = 0;       // ankh_overrides.workspace_limit (0 = none)
 
     // statistics / timing

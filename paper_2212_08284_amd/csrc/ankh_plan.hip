@@ -340,6 +340,13 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         (void)hipGetLastError();
         pl->device = 0;
     }
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pl->device) == hipSuccess && ncu > 0)
+            pl->num_cu = ncu;
+        else
+            (void)hipGetLastError();
+    }
     pl->bytes_limit = ov ? (size_t)ov->workspace_limit : 0;
 
     // splitting parameter: the largest reciprocal weight exp(-(pi/(xi edge))^2)
