@@ -269,6 +269,57 @@ __device__ inline void cheb_basis(double xh, double hinv, const double *sH, doub
 //   w_2 = Th_xx y0 z0 + 3 Om_xxy y1 z0 + 3 Om_xxz y0 z1,   w_3 = Om_xxx y0 z0,
 // so a thread owns one (j, k) line of L nodes and a slice of the leaf's atoms;
 // the slices' lines are summed in slice order at the end.
+// the moments of atom `slot` in the order the line weights take them (off-diagonal components of a
+// symmetric tensor times their multiplicity)
+template <int ORD>
+__device__ inline void p2m_moments(const Particles &P, int64_t slot, int64_t n, double *mo) {
+    mo[0] = P.q[slot];
+    if (ORD >= 1) {
+        mo[1] = P.mu[slot];
+        mo[2] = P.mu[n + slot];
+        mo[3] = P.mu[2 * n + slot];
+    }
+    if (ORD >= 2) {
+        mo[4] = P.th[slot];                 // xx
+        mo[5] = 2 * P.th[n + slot];         // 2 xy
+        mo[6] = 2 * P.th[2 * n + slot];     // 2 xz
+        mo[7] = P.th[3 * n + slot];         // yy
+        mo[8] = 2 * P.th[4 * n + slot];     // 2 yz
+        mo[9] = P.th[5 * n + slot];         // zz
+    }
+    if (ORD >= 3) {
+        constexpr double mult[10] = {1, 3, 3, 3, 6, 3, 1, 3, 3, 1};
+#pragma unroll
+        for (int c = 0; c < 10; c++) mo[10 + c] = mult[c] * P.om[c * n + slot];
+    }
+}
+
+// w_a(j, k) of one atom (see k_p2m), from its moments and its y and z bases Sy[d][j], Sz[d][k]
+template <int ORD, int ND, int L>
+__device__ inline void p2m_weights(const double *mo, const double (*Sy)[L], const double (*Sz)[L], int j, int k,
+                                   double *w) {
+    const double y0 = Sy[0][j], z0 = Sz[0][k];
+    w[0] = mo[0] * y0 * z0;
+    if constexpr (ORD >= 1) {
+        const double y1 = Sy[1][j], z1 = Sz[1][k];
+        w[0] += mo[2] * y1 * z0 + mo[3] * y0 * z1;
+        w[1] = mo[1] * y0 * z0;
+        if constexpr (ORD >= 2) {
+            const double y2 = Sy[2][j], z2 = Sz[2][k];
+            w[0] += mo[7] * y2 * z0 + mo[8] * y1 * z1 + mo[9] * y0 * z2;
+            w[1] += mo[5] * y1 * z0 + mo[6] * y0 * z1;
+            w[2] = mo[4] * y0 * z0;
+            if constexpr (ORD >= 3) {
+                const double y3 = Sy[3][j], z3 = Sz[3][k];
+                w[0] += mo[16] * y3 * z0 + mo[17] * y2 * z1 + mo[18] * y1 * z2 + mo[19] * y0 * z3;
+                w[1] += mo[13] * y2 * z0 + mo[14] * y1 * z1 + mo[15] * y0 * z2;
+                w[2] += mo[11] * y1 * z0 + mo[12] * y0 * z1;
+                w[3] = mo[10] * y0 * z0;
+            }
+        }
+    }
+}
+
 template <int L, int ORD>
 __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, const double *tab, int nu, int nup,
                                              double hinv, double *Q, int64_t n) {
@@ -304,53 +355,13 @@ __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, c
             cheb_basis<ND, L>(xl * hinv, hinv, sH, &sS[a][ax][0][0], L);
         } else if (tid >= 3 * CH && tid < 3 * CH + m) {
             const int a = tid - 3 * CH;
-            const int64_t slot = s0 + c0 + a;
-            double *mo = sMom[a];
-            mo[0] = P.q[slot];
-            if (ORD >= 1) {
-                mo[1] = P.mu[slot];
-                mo[2] = P.mu[n + slot];
-                mo[3] = P.mu[2 * n + slot];
-            }
-            if (ORD >= 2) {
-                mo[4] = P.th[slot];                 // xx
-                mo[5] = 2 * P.th[n + slot];         // 2 xy
-                mo[6] = 2 * P.th[2 * n + slot];     // 2 xz
-                mo[7] = P.th[3 * n + slot];         // yy
-                mo[8] = 2 * P.th[4 * n + slot];     // 2 yz
-                mo[9] = P.th[5 * n + slot];         // zz
-            }
-            if (ORD >= 3) {
-                constexpr double mult[10] = {1, 3, 3, 3, 6, 3, 1, 3, 3, 1};
-#pragma unroll
-                for (int c = 0; c < 10; c++) mo[10 + c] = mult[c] * P.om[c * n + slot];
-            }
+            p2m_moments<ORD>(P, s0 + c0 + a, n, sMom[a]);
         }
         __syncthreads();
         if (sl < NSL) {
             for (int a = sl; a < m; a += NSL) {
-                const double *mo = sMom[a];
-                const double y0 = sS[a][1][0][j], z0 = sS[a][2][0][k];
                 double w[ND];
-                w[0] = mo[0] * y0 * z0;
-                if constexpr (ORD >= 1) {
-                    const double y1 = sS[a][1][1][j], z1 = sS[a][2][1][k];
-                    w[0] += mo[2] * y1 * z0 + mo[3] * y0 * z1;
-                    w[1] = mo[1] * y0 * z0;
-                    if constexpr (ORD >= 2) {
-                        const double y2 = sS[a][1][2][j], z2 = sS[a][2][2][k];
-                        w[0] += mo[7] * y2 * z0 + mo[8] * y1 * z1 + mo[9] * y0 * z2;
-                        w[1] += mo[5] * y1 * z0 + mo[6] * y0 * z1;
-                        w[2] = mo[4] * y0 * z0;
-                        if constexpr (ORD >= 3) {
-                            const double y3 = sS[a][1][3][j], z3 = sS[a][2][3][k];
-                            w[0] += mo[16] * y3 * z0 + mo[17] * y2 * z1 + mo[18] * y1 * z2 + mo[19] * y0 * z3;
-                            w[1] += mo[13] * y2 * z0 + mo[14] * y1 * z1 + mo[15] * y0 * z2;
-                            w[2] += mo[11] * y1 * z0 + mo[12] * y0 * z1;
-                            w[3] = mo[10] * y0 * z0;
-                        }
-                    }
-                }
+                p2m_weights<ORD, ND, L>(sMom[a], sS[a][1], sS[a][2], j, k, w);
 #pragma unroll
                 for (int i = 0; i < L; i++) {
                     double v = acc[i];
