@@ -371,12 +371,16 @@ __global__ __launch_bounds__(kFT) void k_fft_nodes_fwd_t(const double *Q, int nu
     }
 }
 
+// In float32 it also gives the leaf's far energy 1/2 Q_c . Lambda_c with Lambda_c (each thread's L
+// products, then the L^2 threads of a leaf in order), which otherwise k_leafdot computes (in float64
+// the extra registers would spill).
 template <typename R, int L>
-__global__ __launch_bounds__(256) void k_fft_nodes_inv_t(const Cplx<R> *X, const Cplx<R> *B, double *Lam, int nup,
-                                                         int64_t ncell) {
+__global__ __launch_bounds__(256) void k_fft_nodes_inv_t(const Cplx<R> *X, const Cplx<R> *B, double *Lam,
+                                                         const double *Q, double *eleaf, int nup, int64_t ncell) {
     using C = Cplx<R>;
     constexpr int PA = 2 * L - 1, PH = L, NU = PA * PA * L;
     __shared__ C U[kCB][NU];
+    __shared__ double part[sizeof(R) == 4 ? kCB : 1][sizeof(R) == 4 ? L * L : 1];
     const int64_t c0 = xcd_leaf(blockIdx.x, ncell / kCB) * kCB;
     const int t = threadIdx.x;
     // z: thread (line f1 f2, cell): U[f1][f2][k] = sum_f3 w(f3) conj(B[f3][k]) X[f1 f2 f3]; two lines
@@ -426,12 +430,24 @@ __global__ __launch_bounds__(256) void k_fft_nodes_inv_t(const Cplx<R> *X, const
             }
             v[f1] = mkc(re, im);
         }
+        double e = 0;
 #pragma unroll
         for (int i = 0; i < L; i++) {
             R re = 0;
 #pragma unroll
             for (int f1 = 0; f1 < PA; f1++) re += cmulc(B[f1 * L + i], v[f1]).x;
-            Lam[(c0 + cell) * nup + (i * L + j) * L + k] = re;
+            const int64_t at = (c0 + cell) * nup + (i * L + j) * L + k;
+            Lam[at] = re;
+            if constexpr (sizeof(R) == 4) e += Q[at] * (double)re;
+        }
+        if constexpr (sizeof(R) == 4) part[cell][jk] = e;
+    }
+    if constexpr (sizeof(R) == 4) {
+        __syncthreads();
+        if (t < kCB) {
+            double e = 0;
+            for (int jk = 0; jk < L * L; jk++) e += part[t][jk];
+            eleaf[c0 + t] = 0.5 * e;
         }
     }
 }
@@ -1458,21 +1474,24 @@ hipError_t launch_fft_cells(ankh_plan_s *pl) {
     return cells<0, double>(pl, pl->d_fftX, pl->d_fftD, pl->d_fftTw, 1.0 / n6);
 }
 
+bool fft_inverse_leaf_energies(const ankh_plan_s *pl) { return fast_nodes(pl) && pl->fft_f32; }
+
 hipError_t launch_fft_inverse(ankh_plan_s *pl) {
     const int L = pl->order, pa = pl->fft_pa, ph = pl->fft_ph;
     double *Lam = pl->d_L + pl->lv[pl->depth].cell0 * pl->nup;
+    const double *Q = pl->d_M + pl->lv[pl->depth].cell0 * pl->nup;
     if (fast_nodes(pl)) {
         const dim3 g((unsigned)(pl->nleaf / kCB)), b(256);
         if (pl->fft_f32) {
 #define ANKH_INV(LL)                                                                                                \
             hipLaunchKernelGGL((k_fft_nodes_inv_t<float, LL>), g, b, 0, pl->stream, pl->d_fftX32, pl->d_fftB32, Lam, \
-                               pl->nup, pl->nleaf)
+                               Q, pl->d_eleaf, pl->nup, pl->nleaf)
             ANKH_FFT_ORDERS(L, ANKH_INV)
 #undef ANKH_INV
         } else {
 #define ANKH_INV(LL)                                                                                                \
             hipLaunchKernelGGL((k_fft_nodes_inv_t<double, LL>), g, b, 0, pl->stream, pl->d_fftX, pl->d_fftB, Lam,    \
-                               pl->nup, pl->nleaf)
+                               Q, pl->d_eleaf, pl->nup, pl->nleaf)
             ANKH_FFT_ORDERS(L, ANKH_INV)
 #undef ANKH_INV
         }

@@ -200,5 +200,6 @@ bool fft_f32_ok(const ankh_plan_s *pl);            // every transform of the pla
 hipError_t launch_fft_forward(ankh_plan_s *pl);    // leaf multipoles -> half spectrum X
 hipError_t launch_fft_cells(ankh_plan_s *pl);      // cell transforms, product with D, inverse
 hipError_t launch_fft_inverse(ankh_plan_s *pl);    // X -> leaf local expansions
+bool fft_inverse_leaf_energies(const ankh_plan_s *pl);   // launch_fft_inverse also writes the leaf far energies
 
 }  // namespace ankh

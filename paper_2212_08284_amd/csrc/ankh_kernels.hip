@@ -90,53 +90,62 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const double *pos, const
     if (valid) rank[i] = base + off;
 }
 
-// exclusive scan of the leaf counts in one block (offs[m] = total; totals fit int32, as offs does): each thread sums
-// a contiguous run of counts (eight loads in flight), the runs are scanned within each wave by shuffles
-// and across the 16 waves by the first wave
+// exclusive scan of the leaf counts in one block (offs[m] = total; totals fit int32, as offs does), in
+// chunks of 8192 counts: a coalesced load into LDS (eight per thread, all in flight), each thread's eight
+// consecutive counts summed, the sums scanned within each wave by shuffles and across the 16 waves by the
+// first wave, the offsets written back through LDS (coalesced), the chunk total carried to the next
 __global__ __launch_bounds__(1024) void k_scan(const int32_t *count, int32_t *offs, int64_t m) {
+    constexpr int T = 1024, C = 8 * T;
+    __shared__ int buf[C];
     __shared__ int wsum[16];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int64_t per = (m + 1023) / 1024;
-    const int64_t b = t * per < m ? t * per : m, e = b + per < m ? b + per : m;
-    int s = 0;
-    for (int64_t i0 = b; i0 < e; i0 += 8) {
-        int c[8];
+    int carry = 0;
+    for (int64_t c0 = 0; c0 < m; c0 += C) {
+        const int cn = (int)((m - c0) < C ? (m - c0) : C);
+        int v[8];
 #pragma unroll
-        for (int u = 0; u < 8; u++) c[u] = count[i0 + u < e ? i0 + u : e - 1];
+        for (int u = 0; u < 8; u++) v[u] = t + u * T < cn ? count[c0 + t + u * T] : 0;
 #pragma unroll
-        for (int u = 0; u < 8; u++) s += i0 + u < e ? c[u] : 0;
-    }
-    int v = s;                              // inclusive scan over the wave
+        for (int u = 0; u < 8; u++) buf[t + u * T] = v[u];
+        __syncthreads();
+        int e[8], s = 0;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(v, off, 64);
-        if (lane >= off) v += y;
-    }
-    if (lane == 63) wsum[w] = v;
-    __syncthreads();
-    if (w == 0) {
-        int x = lane < 16 ? wsum[lane] : 0;
+        for (int u = 0; u < 8; u++) {
+            e[u] = buf[8 * t + u];
+            s += e[u];
+        }
+        int x = s;                          // inclusive scan over the wave
 #pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
+        for (int off = 1; off < 64; off <<= 1) {
             const int y = __shfl_up(x, off, 64);
             if (lane >= off) x += y;
         }
-        if (lane < 16) wsum[lane] = x;     // inclusive totals of the waves
-    }
-    __syncthreads();
-    int base = v - s + (w > 0 ? wsum[w - 1] : 0);
-    for (int64_t i0 = b; i0 < e; i0 += 8) {
-        int c[8];
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        if (w == 0) {
+            int z = lane < 16 ? wsum[lane] : 0;
 #pragma unroll
-        for (int u = 0; u < 8; u++) c[u] = count[i0 + u < e ? i0 + u : e - 1];
+            for (int off = 1; off < 16; off <<= 1) {
+                const int y = __shfl_up(z, off, 64);
+                if (lane >= off) z += y;
+            }
+            if (lane < 16) wsum[lane] = z;  // inclusive totals of the waves
+        }
+        __syncthreads();
+        int base = carry + x - s + (w > 0 ? wsum[w - 1] : 0);
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            buf[8 * t + u] = base;
+            base += e[u];
+        }
+        carry += wsum[15];
+        __syncthreads();
 #pragma unroll
         for (int u = 0; u < 8; u++)
-            if (i0 + u < e) {
-                offs[i0 + u] = base;
-                base += c[u];
-            }
+            if (t + u * T < cn) offs[c0 + t + u * T] = buf[t + u * T];
+        __syncthreads();                    // buf and wsum are free for the next chunk
     }
-    if (t == 1023) offs[m] = wsum[15];
+    if (t == 0) offs[m] = carry;
 }
 
 __global__ void k_scatter(int64_t n, const int32_t *leaf, const int32_t *offs, const int32_t *rank, int32_t *perm) {
@@ -145,20 +154,27 @@ __global__ void k_scatter(int64_t n, const int32_t *leaf, const int32_t *offs, c
     perm[offs[leaf[i]] + rank[i]] = (int32_t)i;
 }
 
-// order the atoms of each leaf by input index (rank sort), so that every
-// later sum runs in an order independent of the scatter's atomics
-__global__ __launch_bounds__(256) void k_segsort(const int32_t *offs, const int32_t *perm, int32_t *out) {
-    __shared__ int32_t seg[2048];
-    const int64_t leaf = blockIdx.x;
+// order the atoms of each leaf by input index (rank sort), so that every later sum runs in an order
+// independent of the scatter's atomics.  One wave per leaf, four leaves per block (a leaf holds a few
+// tens of atoms); a leaf of up to 512 atoms is staged in LDS.
+__global__ __launch_bounds__(256) void k_segsort(const int32_t *offs, const int32_t *perm, int32_t *out,
+                                                 int64_t nleaf) {
+    __shared__ int32_t seg[4][512];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t leaf = (int64_t)blockIdx.x * 4 + wv;
+    if (leaf >= nleaf) return;   // the waves synchronise among themselves only
     const int s0 = offs[leaf], cnt = offs[leaf + 1] - s0;
-    const bool cached = cnt <= 2048;
+    const bool cached = cnt <= 512;
+    int32_t *sg = seg[wv];
     if (cached)
-        for (int e = threadIdx.x; e < cnt; e += blockDim.x) seg[e] = perm[s0 + e];
-    __syncthreads();
-    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-        const int v = cached ? seg[e] : perm[s0 + e];
+        for (int e = lane; e < cnt; e += 64) sg[e] = perm[s0 + e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int e = lane; e < cnt; e += 64) {
+        const int v = cached ? sg[e] : perm[s0 + e];
         int rank = 0;
-        for (int j = 0; j < cnt; j++) rank += ((cached ? seg[j] : perm[s0 + j]) < v);
+        for (int j = 0; j < cnt; j++) rank += ((cached ? sg[j] : perm[s0 + j]) < v);
         out[s0 + rank] = v;
     }
 }
@@ -897,7 +913,8 @@ hipError_t launch_sort(ankh_plan_s *pl, const double *pos, const double *q, cons
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, pl->d_count, pl->d_offs, pl->nleaf);
     hipLaunchKernelGGL(k_scatter, dim3(nblk(pl->n, 256)), dim3(256), 0, s, pl->n, pl->d_leaf, pl->d_offs,
                        pl->d_rank, pl->d_tmp);
-    hipLaunchKernelGGL(k_segsort, dim3((unsigned)pl->nleaf), dim3(256), 0, s, pl->d_offs, pl->d_tmp, pl->d_perm);
+    hipLaunchKernelGGL(k_segsort, dim3((unsigned)((pl->nleaf + 3) / 4)), dim3(256), 0, s, pl->d_offs, pl->d_tmp,
+                       pl->d_perm, pl->nleaf);
     return hipGetLastError();
 }
 

@@ -213,7 +213,7 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
             mark(6);
             for (int e = 1; e <= pl->depth; e++) ck(launch_l2l(pl, e));
         }
-        ck(launch_leafdot(pl));
+        if (!(pl->far_field == ANKH_FAR_FFT && fft_inverse_leaf_energies(pl))) ck(launch_leafdot(pl));
         mark(7);
         if (adj) ck(launch_l2p(pl, ord, fields));
         if (overlap) {
