@@ -163,8 +163,7 @@ def p2p_roofline(st, breakdown, key, leaves=None, traffic=True):
         rec["alone_frac_of_unpacked_fp32"] = alone / PEAK["valu_fp32_unpacked"]
         rec["note"] = ("peak = the published FP32 vector rate, 157.3 TFLOP/s (packed FP32, two lanes per "
                        "instruction); this build issues unpacked FP32 (one FMA per lane and cycle, 78.6 TFLOP/s: "
-                       "frac_of_unpacked_fp32).  In the timed steps the far-field chain runs beside the pair kernel "
-                       "on a second stream and shares its CUs (alone_*: the breakdown pass, one stream)")
+                       "frac_of_unpacked_fp32).  alone_*: the breakdown pass (an event at every stage boundary)")
     return rec
 
 
@@ -547,9 +546,9 @@ def main():
         "ns_per_day_equiv_dt2fs": 86400.0 / t_mixed * 2e-6,
         "stage_ms": bd_mixed,
         "stage_ms_note": "a separate pass of the same number of steps with an event at every stage boundary and the "
-                         "stages in sequence on one stream; the timed steps overlap the far-field chain with the pair "
-                         "kernel and carry events around stage 4 (the M2L, or the cell transforms of ANKH-FFT) and the "
-                         "pair kernel only.  ANKH-FFT stages: m2m = forward node transform, m2l = cell transforms "
+                         "stages in sequence on one stream; the timed steps carry events around stage 4 (the M2L, "
+                         "or the cell transforms of ANKH-FFT) and the pair kernel only (and the far-field chain on a "
+                         "second stream beside the pair kernel with --overlap on).  ANKH-FFT stages: m2m = forward node transform, m2l = cell transforms "
                          "with the spectrum, l2l = inverse node transform + leaf energies, periodic = none",
         "roofline": roof,
     }

@@ -37,12 +37,12 @@
  *
  * Streams: all work of a plan is ordered on the HIP stream given to
  * ankh_plan (NULL = the default stream) and is asynchronous; outputs are
- * valid after that stream is synchronised or after ankh_sync.  Within an
- * evaluation the far-field chain may run on a second stream that the plan
- * owns (ankh_overrides.overlap), forked from that stream after the particles
- * are sorted and joined back before the pair results are summed, beside the
- * pair kernel.  Work enqueued on the plan's stream is therefore ordered as if
- * everything ran on it.
+ * valid after that stream is synchronised or after ankh_sync.  On request
+ * (ankh_overrides.overlap) the far-field chain of an evaluation runs on a
+ * second stream that the plan owns, forked from that stream after the
+ * particles are sorted and joined back before the pair results are summed,
+ * beside the pair kernel.  Work enqueued on the plan's stream is ordered as
+ * if everything ran on it either way.
  * A plan is not thread-safe; use one plan per stream.
  *
  * Errors: host-checkable errors return at once with outputs untouched.
@@ -109,7 +109,9 @@ typedef struct {
                            (12 and 20 leaves per axis: one block if the device grants 128 KB of LDS per
                            block, else three passes) */
     int32_t overlap;    /* far-field chain beside the pair kernel on the plan's second stream: 1 = yes,
-                           2 = no (every stage in sequence on the plan's stream), 0 = auto (yes) */
+                           2 = no (every stage in sequence on the plan's stream), 0 = auto (no: the pair
+                           kernel fills every SIMD's registers and issues at the VALU limit, so the
+                           evaluation takes the sum of its stages either way) */
     double force_accuracy; /* target relative RMS error of the forces and fields, in [1e-12, 1e-2]; 0 = none.
                               rel_accuracy bounds the relative energy error (the accuracy measure of the
                               paper's numerical results); the force error follows it at a workload-dependent

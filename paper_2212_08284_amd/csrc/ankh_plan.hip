@@ -385,7 +385,11 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
         pl->far_field = ff;
     }
     const bool fft = pl->far_field == ANKH_FAR_FFT;
-    pl->overlap = (ov && ov->overlap) ? ov->overlap == 1 : true;
+    // the far-field chain on the second stream beside the pair kernel only on request: the pair kernel
+    // holds every VGPR of every SIMD and issues at the VALU limit, so a far-field block beside it slows it
+    // by about its own duration, and the evaluation takes the sum of its stages either way (on the 288k
+    // water box 0.907 against 0.904 ms mixed, 1.636 against 1.615 ms FP64)
+    pl->overlap = (ov && ov->overlap) ? ov->overlap == 1 : false;
     pl->depth = (ov && ov->depth >= 0) ? ov->depth : depth_for(n_atoms, pl->nu);
     // ANKH-FFT's grid of leaves per axis: a power of two is the octree depth; any other count (up to
     // kMaxFftDft) is a single level, kept as level 0
