@@ -531,26 +531,73 @@ __device__ inline int brev(int v) {
 template <typename R, int NS, bool ALONG_V, bool DIT, bool INV>
 __device__ void tile_fft(Cplx<R> *tile, const Cplx<R> *tw) {
     using C = Cplx<R>;
-    constexpr int NB = NS * (NS / 2);
-    for (int half = DIT ? 1 : NS / 2; DIT ? half < NS : half >= 1; half = DIT ? 2 * half : half / 2) {
-        for (int b = threadIdx.x; b < NB; b += blockDim.x) {
-            // consecutive threads take consecutive elements of the line direction that is contiguous
-            const int line = ALONG_V ? b / (NS / 2) : b % NS;
-            const int k = ALONG_V ? b % (NS / 2) : b / NS;
-            const int pos = k % half, i0 = (k / half) * 2 * half + pos, i1 = i0 + half;
-            C w = tw[pos * (NS / (2 * half))];
-            if (INV) w.y = -w.y;
-            const int e0 = ALONG_V ? line * NS + i0 : i0 * NS + line;
-            const int e1 = ALONG_V ? line * NS + i1 : i1 * NS + line;
-            const C u = tile[e0], v = tile[e1];
-            if (DIT) {
-                const C t = cmul(w, v);
-                tile[e0] = mkc(u.x + t.x, u.y + t.y);
-                tile[e1] = mkc(u.x - t.x, u.y - t.y);
-            } else {
-                tile[e0] = mkc(u.x + v.x, u.y + v.y);
-                tile[e1] = cmul(w, mkc(u.x - v.x, u.y - v.y));
+    constexpr int Q4 = NS >= 4 ? NS / 4 : 1;   // pairs of stages exist from 4 points on
+    constexpr int NB = NS * (NS / 2), NQ = NS * Q4;
+    auto twid = [&](int pos, int h) {           // W_{2h}^pos (conjugated for INV)
+        C w = tw[pos * (NS / (2 * h))];
+        if (INV) w.y = -w.y;
+        return w;
+    };
+    auto at = [&](int line, int i) -> C & { return tile[ALONG_V ? line * NS + i : i * NS + line]; };
+    // Two radix-2 stages at a time where two remain (the butterflies of both stages on the four values
+    // p, p + h, p + 2h, p + 3h in one thread, operation for operation as in two stages), one barrier per
+    // pair of stages; a single radix-2 stage where one remains.
+    // DIT: half 1, 2, 4, ... (stages h and 2h together); DIF: half NS/2, NS/4, ... (h and h/2).
+    int half = DIT ? 1 : NS / 2;
+    while (DIT ? half < NS : half >= 1) {
+        const bool pair = NS >= 4 && (DIT ? 2 * half < NS : half >= 2);
+        if (pair) {
+            const int hq = DIT ? half : half / 2;   // the smaller half of the two stages
+            for (int b = threadIdx.x; b < NQ; b += blockDim.x) {
+                const int line = ALONG_V ? b / Q4 : b % NS;
+                const int k = ALONG_V ? b % Q4 : b / NS;
+                const int pos = k % hq, p = (k / hq) * 4 * hq + pos;
+                C x0 = at(line, p), x1 = at(line, p + hq), x2 = at(line, p + 2 * hq), x3 = at(line, p + 3 * hq);
+                if (DIT) {
+                    // stage hq: (p, p + hq), (p + 2hq, p + 3hq) with W_{2hq}^pos
+                    const C w1 = twid(pos, hq);
+                    const C t1 = cmul(w1, x1), t3 = cmul(w1, x3);
+                    const C u0 = mkc(x0.x + t1.x, x0.y + t1.y), u1 = mkc(x0.x - t1.x, x0.y - t1.y);
+                    const C u2 = mkc(x2.x + t3.x, x2.y + t3.y), u3 = mkc(x2.x - t3.x, x2.y - t3.y);
+                    // stage 2hq: (p, p + 2hq) with W_{4hq}^pos, (p + hq, p + 3hq) with W_{4hq}^(pos + hq)
+                    const C w2 = twid(pos, 2 * hq), w3 = twid(pos + hq, 2 * hq);
+                    const C t2 = cmul(w2, u2), t4 = cmul(w3, u3);
+                    at(line, p) = mkc(u0.x + t2.x, u0.y + t2.y);
+                    at(line, p + 2 * hq) = mkc(u0.x - t2.x, u0.y - t2.y);
+                    at(line, p + hq) = mkc(u1.x + t4.x, u1.y + t4.y);
+                    at(line, p + 3 * hq) = mkc(u1.x - t4.x, u1.y - t4.y);
+                } else {
+                    // stage 2hq: (p, p + 2hq) with W_{4hq}^pos, (p + hq, p + 3hq) with W_{4hq}^(pos + hq)
+                    const C w2 = twid(pos, 2 * hq), w3 = twid(pos + hq, 2 * hq);
+                    const C u0 = mkc(x0.x + x2.x, x0.y + x2.y), u2 = cmul(w2, mkc(x0.x - x2.x, x0.y - x2.y));
+                    const C u1 = mkc(x1.x + x3.x, x1.y + x3.y), u3 = cmul(w3, mkc(x1.x - x3.x, x1.y - x3.y));
+                    // stage hq: (p, p + hq), (p + 2hq, p + 3hq) with W_{2hq}^pos
+                    const C w1 = twid(pos, hq);
+                    at(line, p) = mkc(u0.x + u1.x, u0.y + u1.y);
+                    at(line, p + hq) = cmul(w1, mkc(u0.x - u1.x, u0.y - u1.y));
+                    at(line, p + 2 * hq) = mkc(u2.x + u3.x, u2.y + u3.y);
+                    at(line, p + 3 * hq) = cmul(w1, mkc(u2.x - u3.x, u2.y - u3.y));
+                }
             }
+            half = DIT ? 4 * half : half / 4;
+        } else {
+            for (int b = threadIdx.x; b < NB; b += blockDim.x) {
+                // consecutive threads take consecutive elements of the line direction that is contiguous
+                const int line = ALONG_V ? b / (NS / 2) : b % NS;
+                const int k = ALONG_V ? b % (NS / 2) : b / NS;
+                const int pos = k % half, i0 = (k / half) * 2 * half + pos, i1 = i0 + half;
+                const C w = twid(pos, half);
+                const C u = at(line, i0), v = at(line, i1);
+                if (DIT) {
+                    const C t = cmul(w, v);
+                    at(line, i0) = mkc(u.x + t.x, u.y + t.y);
+                    at(line, i1) = mkc(u.x - t.x, u.y - t.y);
+                } else {
+                    at(line, i0) = mkc(u.x + v.x, u.y + v.y);
+                    at(line, i1) = cmul(w, mkc(u.x - v.x, u.y - v.y));
+                }
+            }
+            half = DIT ? 2 * half : half / 2;
         }
         __syncthreads();
     }
@@ -562,19 +609,21 @@ template <typename R, int NS, bool INV>
 __global__ __launch_bounds__(256) void k_fft_yz(Cplx<R> *X, const Cplx<R> *tw, int64_t ncell) {
     using C = Cplx<R>;
     __shared__ C tile[NS * NS];
+    __shared__ C stw[NS / 2];
     C *p = X + (int64_t)blockIdx.x * ncell + (int64_t)blockIdx.y * NS * NS;
     const int t = threadIdx.x;
+    for (int i = t; i < NS / 2; i += 256) stw[i] = tw[i];
     for (int i = t; i < NS * NS; i += 256) {
         const int y = i / NS, z = i % NS;
         tile[INV ? i : brev<NS>(y) * NS + brev<NS>(z)] = p[i];
     }
     __syncthreads();
     if (!INV) {
-        tile_fft<R, NS, true, true, false>(tile, tw);
-        tile_fft<R, NS, false, true, false>(tile, tw);
+        tile_fft<R, NS, true, true, false>(tile, stw);
+        tile_fft<R, NS, false, true, false>(tile, stw);
     } else {
-        tile_fft<R, NS, true, false, true>(tile, tw);
-        tile_fft<R, NS, false, false, true>(tile, tw);
+        tile_fft<R, NS, true, false, true>(tile, stw);
+        tile_fft<R, NS, false, false, true>(tile, stw);
     }
     for (int i = t; i < NS * NS; i += 256) {
         const int y = i / NS, z = i % NS;
@@ -589,14 +638,16 @@ __global__ __launch_bounds__(256) void k_fft_x(Cplx<R> *X, R *D, const Cplx<R> *
                                                R scale) {
     using C = Cplx<R>;
     __shared__ C tile[NS * NS];
+    __shared__ C stw[NS / 2];
     const int64_t f = blockIdx.x;
     const int y = blockIdx.y, t = threadIdx.x;
+    for (int i = t; i < NS / 2; i += 256) stw[i] = tw[i];
     for (int i = t; i < NS * NS; i += 256) {
         const int x = i / NS, z = i % NS;
         tile[brev<NS>(x) * NS + z] = X[f * ncell + ((int64_t)x * NS + y) * NS + z];
     }
     __syncthreads();
-    tile_fft<R, NS, false, true, false>(tile, tw);
+    tile_fft<R, NS, false, true, false>(tile, stw);
     if (MODE == 1) {
         for (int i = t; i < NS * NS; i += 256) {
             const int x = i / NS, z = i % NS;
@@ -610,7 +661,7 @@ __global__ __launch_bounds__(256) void k_fft_x(Cplx<R> *X, R *D, const Cplx<R> *
         tile[i] = mkc(tile[i].x * d, tile[i].y * d);
     }
     __syncthreads();
-    tile_fft<R, NS, false, false, true>(tile, tw);
+    tile_fft<R, NS, false, false, true>(tile, stw);
     for (int i = t; i < NS * NS; i += 256) {
         const int x = i / NS, z = i % NS;
         X[f * ncell + ((int64_t)x * NS + y) * NS + z] = tile[brev<NS>(x) * NS + z];
