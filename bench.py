@@ -326,6 +326,43 @@ def sub_ionic(ak, args, torch, dev, T):
     return rec
 
 
+def sub_octupole(ak, args, torch, dev, T, data):
+    """The benchmark box with a traceless octupole on every atom as well (ankh_energy_octupole, the next
+    order of the operator D): mixed and FP64 energy + forces + fields, and the mixed path against FP64.
+    (Parity with the oracle's octupoles is a test: classical Ewald with octupoles is too slow at this size.)"""
+    import synth
+    n = len(data["q"])
+    om = synth.water_octupoles(n // 3, seed=5)
+    a = (T(data["pos"]), T(data["q"]), T(data["mu"]), T(data["theta"]), T(om))
+    rec = {"workload": "water_288000 with octupoles: q+mu+Theta+Omega, energy+forces+fields", "n_atoms": n}
+    outs = {}
+    for key, mode in (("mixed", args.mode), ("fp64", "fp64")):
+        pl = ak.Plan(n, 0.5 * data["edge"], args.eps, 3, mode)
+        for _ in range(args.warmup):
+            pl.energy_octupole(*a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = pl.energy_octupole(*a)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        pl.set_timing(1)
+        for _ in range(args.steps):
+            pl.energy_octupole(*a)
+        st = pl.get_stats()
+        pl.close()
+        rec[key] = {"ms_per_step": t * 1e3, "value": n / t, "unit": "atoms*evals/s", "dtype": dtype_name(st),
+                    "stage_ms": st["stage_ms"]}
+        outs[key] = (out[0].item(), out[1].cpu().numpy(), out[2].cpu().numpy())
+    (e0, F0, G0), (e1, F1, G1) = outs["fp64"], outs["mixed"]
+    rec["speedup_mixed_vs_fp64"] = rec["fp64"]["ms_per_step"] / rec["mixed"]["ms_per_step"]
+    rec["mixed_vs_fp64"] = {"rel_energy_err": abs(e1 - e0) / abs(e0), "rel_rms_force_err": rel_rms(F1, F0),
+                            "rel_rms_field_err": rel_rms(G1, G0)}
+    del a
+    torch.cuda.empty_cache()
+    return rec
+
+
 def sub_water9m(ak, args, torch, dev, T):
     """The 9,000,000-atom water box: mixed and FP64 energy + forces + fields in one pass, the speed-up, and the
     20,000-atom corner cut-out against the stored oracle solution."""
@@ -387,7 +424,7 @@ def main():
     ap.add_argument("--no-induce", action="store_true", help="skip the induced-dipole solve")
     ap.add_argument("--no-derivs", action="store_true", help="skip the charge / quadrupole derivative timing")
     ap.add_argument("--no-configs", action="store_true",
-                    help="skip the 1,000,000-ion and 9,000,000-atom sub-records")
+                    help="skip the 1,000,000-ion, 9,000,000-atom and octupole sub-records")
     ap.add_argument("--induce-tol", type=float, default=1e-6)
     ap.add_argument("--far", default="fft", choices=["fmm", "fft"],
                     help="far-field method of the timed path: ANKH-FFT (the variant the paper times) or "
@@ -578,6 +615,9 @@ def main():
         log(f"ionic_1000000: {line['configs']['ionic_1000000']}")
         line["configs"]["water_9000000"] = sub_water9m(ak, args, torch, dev, T)
         log(f"water_9000000: {line['configs']['water_9000000']}")
+        if data.get("theta") is not None:
+            line["configs"]["water_288000_octupoles"] = sub_octupole(ak, args, torch, dev, T, data)
+            log(f"octupoles: {line['configs']['water_288000_octupoles']}")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(data, args.eps, not args.no_cpu_single_thread_water)
     print(json.dumps(line), flush=True)
