@@ -216,7 +216,9 @@ ankh_status ankh_energy(ankh_plan_t plan, const double *pos, const double *q, co
  * ankh_energy_forces: energy, forces F_i = -dE/dx_i and fields dE/dmu_i of the
  * same approximation (the exact gradient of the approximate energy).
  *   forces [n][3]  device output, not NULL.
- *   dE_dmu [n][3]  device output or NULL; zeros when no dipoles are passed.
+ *   dE_dmu [n][3]  device output or NULL: the field dE/dmu at each atom when the call passes
+ *                  dipoles or quadrupoles (mu may then be NULL: the field at mu = 0); zeros for
+ *                  a charges-only call.
  */
 ankh_status ankh_energy_forces(ankh_plan_t plan, const double *pos, const double *q, const double *mu,
                                const double *theta, double *energy, double *forces, double *dE_dmu);

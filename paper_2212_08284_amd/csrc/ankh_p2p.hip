@@ -841,21 +841,38 @@ __global__ __launch_bounds__(256) void k_epilogue(EpiArgs<R> a) {
         }
         self += c0 * v;
         const int64_t i = a.perm[s];
-        if (GRAD && a.forces)
+        // every slot of the atom is loaded before the first sum (all loads in flight at once), then the
+        // slots are added in slot order
+        if (GRAD && a.forces) {
+            R vf[3][kNumSlots];
+#pragma unroll
+            for (int c = 0; c < 3; c++)
+#pragma unroll
+                for (int k = 0; k < kNumSlots; k++) vf[c][k] = a.SF[c * st + (int64_t)k * n + s];
+#pragma unroll
             for (int c = 0; c < 3; c++) {
                 double w = 0;
-                for (int k = 0; k < kNumSlots; k++) w += (double)a.SF[c * st + (int64_t)k * n + s];
+#pragma unroll
+                for (int k = 0; k < kNumSlots; k++) w += (double)vf[c][k];
                 a.forces[3 * i + c] = a.F[c * n + s] + w;
             }
+        }
         if (a.dEdmu) {
-            for (int c = 0; c < 3; c++) {
-                double g = 0;
-                if (FIELD) {
+            if (FIELD) {
+                R vg[3][kNumSlots];
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+#pragma unroll
+                    for (int k = 0; k < kNumSlots; k++) vg[c][k] = a.SG[c * st + (int64_t)k * n + s];
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
                     double w = 0;
-                    for (int k = 0; k < kNumSlots; k++) w += (double)a.SG[c * st + (int64_t)k * n + s];
-                    g = (a.G[c * n + s] + w) + a.fself * a.P.mu[c * n + s];
+#pragma unroll
+                    for (int k = 0; k < kNumSlots; k++) w += (double)vg[c][k];
+                    a.dEdmu[3 * i + c] = (a.G[c * n + s] + w) + a.fself * a.P.mu[c * n + s];
                 }
-                a.dEdmu[3 * i + c] = g;
+            } else {
+                for (int c = 0; c < 3; c++) a.dEdmu[3 * i + c] = 0.0;
             }
         }
     }

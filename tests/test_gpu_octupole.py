@@ -163,6 +163,24 @@ def test_octupole_bitwise_reproducible(ak):
     pl.close()
 
 
+def test_octupole_with_charges_only(ak):
+    """Charges and octupoles without dipoles or quadrupoles (mu, theta NULL): the gather fills zero
+    moments, and the field dE/dmu is the one at mu = 0."""
+    d = _water()
+    n = len(d["q"])
+    pl = ak.Plan(n, 0.5 * d["edge"], 1e-6, 3, "fp64", far="fmm", depth=2, order=5, images=4, m2l_tol=-1.0)
+    e, F, G = pl.energy_octupole(T(d["pos"]), T(d["q"]), None, None, T(d["omega"]))
+    pl.sync()
+    st = pl.stats
+    r = ankh_ref.evaluate(d["pos"], d["q"], np.zeros((n, 3)), None, d["edge"], st["depth"], st["order"], st["xi"],
+                          st["images"], grad=True, root_order=st["root_order"], omega=d["omega"])
+    scale = abs(r["e_near"]) + abs(r["e_self"]) + 1.0
+    assert abs(e.item() - r["energy"]) <= 1e-12 * scale
+    assert rel_rms(F.cpu().numpy(), r["forces"]) <= 1e-11
+    assert rel_rms(G.cpu().numpy(), r["dEdmu"]) <= 1e-11
+    pl.close()
+
+
 def test_octupole_errors(ak):
     d = _water(100)
     n = len(d["q"])
