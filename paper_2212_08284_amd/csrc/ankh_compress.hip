@@ -151,104 +151,95 @@ struct BasisLevel {
     const double *A;
     const double *B;
     double *C;
+    __bf16 *hi, *lo;   // projection in the split-bf16 mode: C also as bf16 hi / lo parts (same layout), else null
     int lda, ldb, ldc, rows, N, K, ntn, tile0;
 };
 constexpr int kMaxBasisLevels = 8;
 struct BasisJob {
     BasisLevel lv[kMaxBasisLevels];
-    int nlv, ntiles, per_xcd;
+    int nlv, ntiles;
 };
-constexpr int BT = 32, BKC = 16, BW = 4;   // tile, chunk, waves per block
+constexpr int BT = 32, BKC = 16;   // column tile, contraction chunk
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// One wave per 16 x 32 output tile (two 16 x 16 fragments of v_mfma_f64_16x16x4),
+// the whole contraction, operands loaded straight from memory one chunk of 16
+// ahead; 4 waves (consecutive tiles, mostly of one row band) per block.  Lane
+// (r, q) = (lane % 16, lane / 16) supplies A(m0 + r, k) and B(k, n0 + r) of the
+// products; within a chunk k0 the 4 sub-steps j take k = k0 + 4 q + j, so each
+// lane reads 4 consecutive k of its row of A (the sum over k is the same, in a
+// different order).  Result element v of lane (r, q) is C(m0 + q + 4 v, n0 + r).
 template <bool NT>
 __global__ __launch_bounds__(256) void k_basis(BasisJob job) {
-    // per wave: A chunk [16][33] and B chunk [16][33]; reused for the final sum [4][32][33]
-    __shared__ double lds[BW * 2 * BKC * (BT + 1)];
-    const int b = blockIdx.x;
-    const int v = (b % 8) * job.per_xcd + b / 8;
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, r = ln & 15, q = ln >> 4;
+    const int v = blockIdx.x * 4 + wv;
     if (v >= job.ntiles) return;
     int li = 0;
     while (li + 1 < job.nlv && v >= job.lv[li + 1].tile0) li++;
     const BasisLevel L = job.lv[li];
     const int tl = v - L.tile0;
-    const int m0 = (tl / L.ntn) * BT, n0 = (tl % L.ntn) * BT;
-    const int wv = threadIdx.x / 64, ln = threadIdx.x % 64, tx = ln % 8, ty = ln / 8;
-    double(*As)[BT + 1] = reinterpret_cast<double(*)[BT + 1]>(lds + wv * 2 * BKC * (BT + 1));
-    double(*Bs)[BT + 1] = reinterpret_cast<double(*)[BT + 1]>(lds + (wv * 2 + 1) * BKC * (BT + 1));
-    // K and N are multiples of the chunk and tile widths (host-checked); rows of A beyond the level
-    // are clamped to its last row and their results dropped.  A wave past the last chunk loads zeros.
-    const int nchunk = L.K / BKC, steps = (nchunk + BW - 1) / BW;
-    double2 ra[4], rb[4];
-    auto load = [&](int c) {
-        const bool ok = c < nchunk;
-        const int k0 = c * BKC;
+    const int m0 = (tl / L.ntn) * 16, n0 = (tl % L.ntn) * BT;
+    // rows of A past the level are clamped to its last row; their results are dropped
+    const double *Ar = L.A + (int64_t)min(m0 + r, L.rows - 1) * L.lda + 4 * q;
+    const double *B0 = NT ? L.B + (int64_t)(n0 + r) * L.ldb + 4 * q : L.B + (int64_t)(4 * q) * L.ldb + n0 + r;
+    const int64_t b16 = NT ? 16 * (int64_t)L.ldb : 16;   // column n0 + 16 + r
+    struct Op {
+        double a[4], b0[4], b1[4];
+    };
+    auto load = [&](int k0, Op &o) {
+        const double2 a01 = *reinterpret_cast<const double2 *>(Ar + k0);
+        const double2 a23 = *reinterpret_cast<const double2 *>(Ar + k0 + 2);
+        o.a[0] = a01.x, o.a[1] = a01.y, o.a[2] = a23.x, o.a[3] = a23.y;
+        if (NT) {
+            const double2 p01 = *reinterpret_cast<const double2 *>(B0 + k0);
+            const double2 p23 = *reinterpret_cast<const double2 *>(B0 + k0 + 2);
+            const double2 s01 = *reinterpret_cast<const double2 *>(B0 + b16 + k0);
+            const double2 s23 = *reinterpret_cast<const double2 *>(B0 + b16 + k0 + 2);
+            o.b0[0] = p01.x, o.b0[1] = p01.y, o.b0[2] = p23.x, o.b0[3] = p23.y;
+            o.b1[0] = s01.x, o.b1[1] = s01.y, o.b1[2] = s23.x, o.b1[3] = s23.y;
+        } else {
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const int idx = ln + 64 * q;
-            const int r = idx / 8, p = 2 * (idx % 8);          // A and B (NT): 32 rows x 8 pairs
-            const int m = min(m0 + r, L.rows - 1);
-            ra[q] = ok ? *reinterpret_cast<const double2 *>(L.A + (int64_t)m * L.lda + k0 + p) : double2{0.0, 0.0};
-            if (NT) {
-                rb[q] = ok ? *reinterpret_cast<const double2 *>(L.B + (int64_t)(n0 + r) * L.ldb + k0 + p)
-                           : double2{0.0, 0.0};
-            } else {
-                const int rk = idx / 16, pn = 2 * (idx % 16);   // B (TN): 16 rows of K x 16 pairs along N
-                rb[q] = ok ? *reinterpret_cast<const double2 *>(L.B + (int64_t)(k0 + rk) * L.ldb + n0 + pn)
-                           : double2{0.0, 0.0};
+            for (int j = 0; j < 4; j++) {
+                o.b0[j] = B0[(int64_t)(k0 + j) * L.ldb];
+                o.b1[j] = B0[(int64_t)(k0 + j) * L.ldb + b16];
             }
         }
     };
-    auto store = [&]() {
+    f64x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+    auto mma = [&](const Op &o) {
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const int idx = ln + 64 * q;
-            const int r = idx / 8, p = 2 * (idx % 8);
-            As[p][r] = ra[q].x;
-            As[p + 1][r] = ra[q].y;
-            if (NT) {
-                Bs[p][r] = rb[q].x;
-                Bs[p + 1][r] = rb[q].y;
-            } else {
-                const int rk = idx / 16, pn = 2 * (idx % 16);
-                Bs[rk][pn] = rb[q].x;
-                Bs[rk][pn + 1] = rb[q].y;
-            }
+        for (int j = 0; j < 4; j++) {
+            c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[j], o.b0[j], c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[j], o.b1[j], c1, 0, 0, 0);
         }
     };
-    double acc[4][4] = {};
-    load(wv);
-    for (int t = 0; t < steps; t++) {
-        __syncthreads();   // the previous chunk's reads are done
-        store();
-        __syncthreads();
-        if (t + 1 < steps) load(wv + BW * (t + 1));
-#pragma unroll
-        for (int kk = 0; kk < BKC; kk++) {
-            double a[4], bb[4];
-#pragma unroll
-            for (int i = 0; i < 4; i++) a[i] = As[kk][ty + 8 * i];
-#pragma unroll
-            for (int j = 0; j < 4; j++) bb[j] = Bs[kk][tx + 8 * j];
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-#pragma unroll
-                for (int j = 0; j < 4; j++) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
-        }
+    // chunks alternate register sets P0 / P1; loads past the last chunk repeat it
+    const int nks = L.K / BKC;
+    Op P0, P1;
+    load(0, P0);
+    for (int s = 0; s < nks; s += 2) {
+        load(min(s + 1, nks - 1) * BKC, P1);
+        mma(P0);
+        load(min(s + 2, nks - 1) * BKC, P0);
+        if (s + 1 < nks) mma(P1);
     }
-    // the 4 waves' partial tiles, summed in wave order
-    __syncthreads();
-    double(*red)[BT][BT + 1] = reinterpret_cast<double(*)[BT][BT + 1]>(lds);
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+    for (int e = 0; e < 4; e++) {
+        const int m = m0 + q + 4 * e;
+        if (m >= L.rows) continue;
 #pragma unroll
-        for (int j = 0; j < 4; j++) red[wv][ty + 8 * i][tx + 8 * j] = acc[i][j];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const int o = threadIdx.x + 256 * q, r = o / BT, c = o % BT;
-        const int m = m0 + r;
-        const double sum = (red[0][r][c] + red[1][r][c]) + (red[2][r][c] + red[3][r][c]);
-        if (m < L.rows) L.C[(int64_t)m * L.ldc + n0 + c] = sum;
+        for (int h = 0; h < 2; h++) {
+            const int64_t o = (int64_t)m * L.ldc + n0 + 16 * h + r;
+            const double sum = h ? c1[e] : c0[e];
+            L.C[o] = sum;
+            if (L.hi) {   // the contraction's operand: hi = bf16(x), lo = bf16(x - hi), x = float(sum)
+                const float x = (float)sum;
+                const __bf16 a = (__bf16)x;
+                L.hi[o] = a;
+                L.lo[o] = (__bf16)(x - (float)a);
+            }
+        }
     }
 }
 
@@ -272,6 +263,10 @@ hipError_t launch_m2l_basis(ankh_plan_s *pl, bool expand) {
         if (!expand) {
             b.A = M, b.lda = pl->nup, b.K = pl->nup;
             b.C = Mc, b.ldc = rp, b.N = rp;
+            if (pl->precision == ANKH_MIXED_BF16X3) {
+                b.hi = pl->d_Mb + pl->mb_off[e];
+                b.lo = pl->d_Mb + pl->mb_total + pl->mb_off[e];
+            }
         } else {
             b.A = Lc, b.lda = rp, b.K = rp;
             b.C = Lf, b.ldc = pl->nup, b.N = pl->nup;
@@ -279,12 +274,11 @@ hipError_t launch_m2l_basis(ankh_plan_s *pl, bool expand) {
         if (b.K % BKC || b.N % BT || b.rows < 1) return hipErrorInvalidValue;
         b.ntn = b.N / BT;
         b.tile0 = nt;
-        nt += ((b.rows + BT - 1) / BT) * b.ntn;
+        nt += ((b.rows + 15) / 16) * b.ntn;
     }
     if (job.nlv == 0) return hipSuccess;
     job.ntiles = nt;
-    job.per_xcd = (nt + 7) / 8;
-    const dim3 grid((unsigned)(8 * job.per_xcd));
+    const dim3 grid((unsigned)((nt + 3) / 4));
     if (expand)
         hipLaunchKernelGGL(k_basis<true>, grid, dim3(256), 0, pl->stream, job);
     else

@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
 // and the product is accumulated in float32 as hi*hi + hi*lo + lo*hi (the
 // lo*lo term is below the float32 rounding of the sum).  K_d is stored tiled,
 // [d][l / 32][k][l % 32], so the A tile of one 32-wide contraction step is one
-// contiguous run; the multipoles of the level are split once per launch.
+// contiguous run; the multipoles of all levels are split once per evaluation.
 // Lane l of v_mfma_f32_16x16x32_bf16 supplies A[l % 16][8 (l / 16) .. +8] and
 // B[8 (l / 16) .. +8][l % 16]; result element v sits at row 4 (l / 16) + v,
 // column l % 16.  LDS rows are 32 bf16 (four 16-byte chunks); chunk c of row r
@@ -280,12 +280,52 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
 // banks without padding.
 __device__ inline int swz(int r, int c) { return r * 32 + 8 * (c ^ (((r >> 1) ^ (r >> 3)) & 3)); }
 
-template <int RF>
+// Writes a wave's 16 RF x 16 NB result tile: rows r0 + 16 i + 4 (lane / 16) + v,
+// columns (class cells) c0 + 16 j + lane % 16; rows past n_up and cells past the
+// class are dropped.  Split-K: float32 into slice `split` of `part`; else float64
+// into `dst`.
+template <int RF, int NB>
+__device__ inline void m2l_write_tile(const f32x4 (&acc)[RF][NB], float *part, double *dst, int split,
+                                      int64_t part_stride, int r0, int c0, int lr, int lk, int h, int px, int py,
+                                      int pz, int nside, int nup, int nsplit) {
+    const int ncls = h * h * h;
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        const int cl = c0 + j * 16 + lr;
+        if (cl >= ncls) continue;
+        const size_t cell = (size_t)((2 * (cl / (h * h)) + px) * nside + 2 * ((cl / h) % h) + py) * nside +
+                            2 * (cl % h) + pz;
+#pragma unroll
+        for (int i = 0; i < RF; i++) {
+            const int rb = r0 + i * 16;   // 16-row block, entirely inside or outside n_up
+            if (rb >= nup) continue;
+            if (nsplit > 1) {
+                float *P = part + (size_t)split * part_stride + cell * nup + rb + 4 * lk;
+                *reinterpret_cast<f32x4 *>(P) = acc[i][j];
+            } else {
+                double *Lc = dst + cell * nup + rb + 4 * lk;
+#pragma unroll
+                for (int v = 0; v < 4; v++) Lc[v] = (double)acc[i][j][v];
+            }
+        }
+    }
+}
+
+// Block tile: 32 RF output nodes x 32 NB cells; the 4 waves form a 2 x 2 grid of
+// 16 RF x 16 NB sub-tiles, so one step's fragment reads (RF + NB pairs of
+// 16-byte loads per lane) feed 3 RF NB products.  The three products of a step
+// are issued as three sweeps over the RF x NB accumulators (each accumulator
+// still sums lo*hi, hi*lo, hi*hi in that order), so consecutive matrix-core
+// instructions never wait on each other's result.  A split-K block writes its
+// float32 tile to its slice of `part` (summed in float64 by k_m2l_reduce); an
+// unsplit level writes float64 to `dst`.
+template <int RF, int NB>
 __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ Kh, const __bf16 *__restrict__ Kl,
                                                     const __bf16 *__restrict__ Mh, const __bf16 *__restrict__ Ml,
-                                                    double *__restrict__ out, int nside, int nup, int nsplit,
-                                                    int64_t out_stride) {
-    constexpr int BM = 32 * RF, BK = 32;
+                                                    float *__restrict__ part, double *__restrict__ dst, int nside,
+                                                    int nup, int nsplit, int64_t part_stride) {
+    constexpr int BM = 32 * RF, BN = 32 * NB, BK = 32;
+    static_assert(NB % 2 == 0, "one or more whole 16-byte B chunks per thread");
     __shared__ __attribute__((aligned(16))) __bf16 Ash[2][BM * BK];
     __shared__ __attribute__((aligned(16))) __bf16 Asl[2][BM * BK];
     __shared__ __attribute__((aligned(16))) __bf16 Bsh[2][BN * BK];
@@ -302,76 +342,89 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ K
     const int *il = c_il.v[tile.cls];
     const int o_begin = kNumIL * tile.split / nsplit, o_end = kNumIL * (tile.split + 1) / nsplit;
 
-    // A loader: 16-byte chunks (8 bf16 of the contraction) of hi and of lo, LA per thread
+    // Loaders.  Every load and LDS store is unconditional and addressed by 32-bit
+    // element offsets from the operand base, which keeps the per-step address work
+    // to a few instructions.  A: 16-byte chunks (8 bf16 of the contraction) of hi and
+    // of lo, LA per thread; the thread slots past the tile's NCA chunks repeat chunk
+    // p - NCA (same data, same LDS address), and rows past n_up (a padded row tile)
+    // load the last row.  B: LB chunks per thread (cell p / 4, chunk p % 4 for
+    // p = tid + 256 u); cells past the class load the last cell.  Such rows and
+    // cells only reach outputs that are never written.
     constexpr int NCA = BM * 4, LA = (NCA + NTHR - 1) / NTHR;
-    // B loader: one chunk of hi and of lo per thread
-    const int b_col = tid >> 2, b_c = tid & 3;
-    const int tcell = col0 + b_col;
-    const bool b_ok = tcell < ncls;
-    int gx = 0, gy = 0, gz = 0;
-    if (b_ok) {
-        gx = 2 * (tcell / (h * h)) + px;
-        gy = 2 * ((tcell / h) % h) + py;
-        gz = 2 * (tcell % h) + pz;
+    static_assert(LA * NTHR <= 2 * NCA, "a repeated slot maps onto a real chunk");
+    constexpr int LB = NB / 2;
+    int a_off[LA], a_lds[LA], b_lds[LB], bx[LB], by[LB], bz[LB];
+#pragma unroll
+    for (int u = 0; u < LA; u++) {
+        const int p0 = tid + NTHR * u, p = p0 < NCA ? p0 : p0 - NCA;
+        a_off[u] = min(row0 + (p >> 2), nup - 1) * BK + 8 * (p & 3);
+        a_lds[u] = swz(p >> 2, p & 3);
     }
+    const int b_c = tid & 3;
+#pragma unroll
+    for (int u = 0; u < LB; u++) {
+        const int col = (tid + NTHR * u) >> 2, tcell = min(col0 + col, ncls - 1);
+        bx[u] = 2 * (tcell / (h * h)) + px;
+        by[u] = 2 * ((tcell / h) % h) + py;
+        bz[u] = 2 * (tcell % h) + pz;
+        b_lds[u] = swz(col, b_c);
+    }
+    const int mask = nside - 1;   // the level's side is a power of two
     const int nk = nup / BK;
     const int niter = (o_end - o_begin) * nk;
-    bf16x8 rah[LA], ral[LA], rbh, rbl;
-    const bf16x8 zero4 = {};
-    auto load = [&](int it) {
-        const int di = il[o_begin + it / nk], kb = it % nk;
-        const size_t base = ((size_t)di * nk + kb) * nup * BK;
+    bf16x8 rah[LA], ral[LA], rbh[LB], rbl[LB];
+    // step (o, kb): offset il[o], contraction block kb
+    auto load = [&](int o, int kb) {
+        const int di = il[o];
+        const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
+        const __bf16 *kh = Kh + ((size_t)di * nk + kb) * nup * BK, *kl = Kl + ((size_t)di * nk + kb) * nup * BK;
 #pragma unroll
         for (int u = 0; u < LA; u++) {
-            const int p = tid + NTHR * u;
-            const int r = p >> 2, c = p & 3;
-            if (p < NCA && row0 + r < nup) {
-                const size_t off = base + (size_t)(row0 + r) * BK + 8 * c;
-                rah[u] = *reinterpret_cast<const bf16x8 *>(Kh + off);
-                ral[u] = *reinterpret_cast<const bf16x8 *>(Kl + off);
-            } else {
-                rah[u] = zero4;
-                ral[u] = zero4;
-            }
+            rah[u] = *reinterpret_cast<const bf16x8 *>(kh + a_off[u]);
+            ral[u] = *reinterpret_cast<const bf16x8 *>(kl + a_off[u]);
         }
-        if (b_ok) {
-            const size_t off = source_cell(gx, gy, gz, di, nside) * nup + kb * BK + 8 * b_c;
-            rbh = *reinterpret_cast<const bf16x8 *>(Mh + off);
-            rbl = *reinterpret_cast<const bf16x8 *>(Ml + off);
-        } else {
-            rbh = zero4;
-            rbl = zero4;
+        const int kc = kb * BK + 8 * b_c;
+#pragma unroll
+        for (int u = 0; u < LB; u++) {
+            const int cell = (((bx[u] + dx) & mask) * nside + ((by[u] + dy) & mask)) * nside + ((bz[u] + dz) & mask);
+            const int off = cell * nup + kc;
+            rbh[u] = *reinterpret_cast<const bf16x8 *>(Mh + off);
+            rbl[u] = *reinterpret_cast<const bf16x8 *>(Ml + off);
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < LA; u++) {
-            const int p = tid + NTHR * u;
-            if (p < NCA) {
-                const int r = p >> 2, c = p & 3;
-                *reinterpret_cast<bf16x8 *>(&Ash[buf][swz(r, c)]) = rah[u];
-                *reinterpret_cast<bf16x8 *>(&Asl[buf][swz(r, c)]) = ral[u];
-            }
+            *reinterpret_cast<bf16x8 *>(&Ash[buf][a_lds[u]]) = rah[u];
+            *reinterpret_cast<bf16x8 *>(&Asl[buf][a_lds[u]]) = ral[u];
         }
-        *reinterpret_cast<bf16x8 *>(&Bsh[buf][swz(b_col, b_c)]) = rbh;
-        *reinterpret_cast<bf16x8 *>(&Bsl[buf][swz(b_col, b_c)]) = rbl;
+#pragma unroll
+        for (int u = 0; u < LB; u++) {
+            *reinterpret_cast<bf16x8 *>(&Bsh[buf][b_lds[u]]) = rbh[u];
+            *reinterpret_cast<bf16x8 *>(&Bsl[buf][b_lds[u]]) = rbl[u];
+        }
     };
 
-    f32x4 acc[RF][2];
+    f32x4 acc[RF][NB];
 #pragma unroll
     for (int i = 0; i < RF; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0, 0, 0, 0};
+        for (int j = 0; j < NB; j++) acc[i][j] = f32x4{0, 0, 0, 0};
     if (niter > 0) {
-        load(0);
+        load(o_begin, 0);
         store(0);
     }
     __syncthreads();
     const int lr = lane & 15, lk = lane >> 4;
+    int on = o_begin, kn = 0;   // the step loaded next
     for (int it = 0; it < niter; it++) {
         const int cur = it & 1;
-        if (it + 1 < niter) load(it + 1);
-        bf16x8 ah[RF], al[RF], bh[2], bl[2];
+        if (++kn == nk) {
+            kn = 0;
+            on++;
+        }
+        if (it + 1 < niter) load(on, kn);
+        bf16x8 ah[RF], al[RF], bh[NB], bl[NB];
 #pragma unroll
         for (int i = 0; i < RF; i++) {
             const int r = wr * 16 * RF + i * 16 + lr;
@@ -379,37 +432,31 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ K
             al[i] = *reinterpret_cast<const bf16x8 *>(&Asl[cur][swz(r, lk)]);
         }
 #pragma unroll
-        for (int j = 0; j < 2; j++) {
-            const int cl = wc * 32 + j * 16 + lr;
+        for (int j = 0; j < NB; j++) {
+            const int cl = wc * 16 * NB + j * 16 + lr;
             bh[j] = *reinterpret_cast<const bf16x8 *>(&Bsh[cur][swz(cl, lk)]);
             bl[j] = *reinterpret_cast<const bf16x8 *>(&Bsl[cur][swz(cl, lk)]);
         }
 #pragma unroll
         for (int i = 0; i < RF; i++)
 #pragma unroll
-            for (int j = 0; j < 2; j++) {
+            for (int j = 0; j < NB; j++)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < RF; i++)
+#pragma unroll
+            for (int j = 0; j < NB; j++)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < RF; i++)
+#pragma unroll
+            for (int j = 0; j < NB; j++)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-            }
         if (it + 1 < niter) store(cur ^ 1);
         __syncthreads();
     }
-    double *o = out + (size_t)tile.split * out_stride;
-#pragma unroll
-    for (int j = 0; j < 2; j++) {
-        const int cl = col0 + wc * 32 + j * 16 + lr;
-        if (cl >= ncls) continue;
-        const int cx = 2 * (cl / (h * h)) + px, cy = 2 * ((cl / h) % h) + py, cz = 2 * (cl % h) + pz;
-        double *Lc = o + ((size_t)(cx * nside + cy) * nside + cz) * nup;
-#pragma unroll
-        for (int i = 0; i < RF; i++) {
-            const int rb = row0 + wr * 16 * RF + i * 16;
-            if (rb >= nup) continue;
-#pragma unroll
-            for (int v = 0; v < 4; v++) Lc[rb + 4 * lk + v] = (double)acc[i][j][v];
-        }
-    }
+    m2l_write_tile<RF, NB>(acc, part, dst, tile.split, part_stride, row0 + wr * 16 * RF, col0 + wc * 16 * NB, lr,
+                           lk, h, px, py, pz, nside, nup, nsplit);
 }
 
 // ---- coarse levels (at most 64 cells): all cells in one column tile ---------
@@ -422,8 +469,8 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ K
 template <int RF>
 __global__ __launch_bounds__(256) void k_m2l_bf16x3_all(const __bf16 *__restrict__ Kh, const __bf16 *__restrict__ Kl,
                                                         const __bf16 *__restrict__ Mh, const __bf16 *__restrict__ Ml,
-                                                        double *__restrict__ out, int nside, int nup, int nsplit,
-                                                        int64_t out_stride) {
+                                                        float *__restrict__ part, int nside, int nup, int nsplit,
+                                                        int64_t part_stride) {
     constexpr int BM = 32 * RF, BK = 32;
     __shared__ __attribute__((aligned(16))) __bf16 Ash[2][BM * BK];
     __shared__ __attribute__((aligned(16))) __bf16 Asl[2][BM * BK];
@@ -526,31 +573,40 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3_all(const __bf16 *__restrict
         if (it + 1 < niter) store(cur ^ 1);
         __syncthreads();
     }
-    double *o = out + (size_t)split * out_stride;
+    float *o = part + (size_t)split * part_stride;
 #pragma unroll
     for (int j = 0; j < 2; j++) {
         const int cl = wc * 32 + j * 16 + lr;
         if (cl >= ncell) continue;
-        double *Lc = o + (size_t)cl * nup;
+        float *Lc = o + (size_t)cl * nup;
 #pragma unroll
         for (int i = 0; i < RF; i++) {
             const int rb = row0 + wr * 16 * RF + i * 16;
             if (rb >= nup) continue;
-#pragma unroll
-            for (int v = 0; v < 4; v++) Lc[rb + 4 * lk + v] = (double)acc[i][j][v];
+            *reinterpret_cast<f32x4 *>(Lc + rb + 4 * lk) = acc[i][j];
         }
     }
 }
 
-// hi / lo bf16 split of a float64 array (via float32)
-__global__ void k_split_bf16(const double *__restrict__ s, __bf16 *__restrict__ hi, __bf16 *__restrict__ lo,
-                             int64_t n) {
+// hi / lo bf16 split (via float32) of the source multipoles of several levels in
+// one launch: level li's n[li] values (packed at off[li] of the launch's range)
+// from src[li] go to hi / lo + dst[li]
+struct SplitJob {
+    const double *src[kMaxDepth + 1];
+    int64_t n[kMaxDepth + 1], off[kMaxDepth + 1], dst[kMaxDepth + 1];
+    int nlv;
+    int64_t total;
+};
+__global__ void k_split_bf16(SplitJob job, __bf16 *__restrict__ hi, __bf16 *__restrict__ lo) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float x = (float)s[i];
+    if (i >= job.total) return;
+    int li = 0;
+    while (li + 1 < job.nlv && i >= job.off[li + 1]) li++;
+    const int64_t k = i - job.off[li];
+    const float x = (float)job.src[li][k];
     const __bf16 a = (__bf16)x;
-    hi[i] = a;
-    lo[i] = (__bf16)(x - (float)a);
+    hi[job.dst[li] + k] = a;
+    lo[job.dst[li] + k] = (__bf16)(x - (float)a);
 }
 
 // plan time: K_d for the BF16 x 3 kernel from the [d][l][k] float64 stack
@@ -570,25 +626,78 @@ __global__ void k_split_K_bf16(const double *__restrict__ K, __bf16 *__restrict_
     lo[i] = (__bf16)(x - (float)a);
 }
 
-// L = sum over the split-K partials in a fixed order: NR interleaved runs of
-// the slices (slice k in run k mod NR), each added in slice order, then the
-// NR run sums in run order.  256 threads = NR runs x (256 / NR) elements.
-template <int NR>
-__global__ __launch_bounds__(256) void k_m2l_reduce(const double *__restrict__ part, double *__restrict__ L,
-                                                    int64_t n, int nsplit) {
+// L = sum over the split-K partials (float64, or the float32 tiles of the split
+// bf16 kernels) in a fixed order: NR interleaved runs of the slices (slice k in
+// run k mod NR), each added in float64 in slice order, then the NR run sums in
+// run order.  256 threads = NR runs x (256 / NR) elements.
+template <int NR, typename P>
+__global__ __launch_bounds__(256) void k_m2l_reduce(const P *__restrict__ part, double *__restrict__ L, int64_t n,
+                                                    int nsplit) {
     constexpr int NE = 256 / NR;
     __shared__ double red[NR][NE];
     const int w = threadIdx.x / NE, r = threadIdx.x % NE;
     const int64_t i = blockIdx.x * (int64_t)NE + r;
     double s = 0;
-    if (i < n)
-        for (int k = w; k < nsplit; k += NR) s += part[k * n + i];
+    if (i < n) {
+        int k = w;
+        for (; k + 3 * NR < nsplit; k += 4 * NR) {   // four loads in flight, added in slice order
+            const double a0 = part[k * n + i], a1 = part[(k + NR) * n + i], a2 = part[(k + 2 * NR) * n + i],
+                         a3 = part[(k + 3 * NR) * n + i];
+            s += a0;
+            s += a1;
+            s += a2;
+            s += a3;
+        }
+        for (; k < nsplit; k += NR) s += (double)part[k * n + i];
+    }
     red[w][r] = s;
     __syncthreads();
     if (w == 0 && i < n) {
         double t = red[0][r];
         for (int k = 1; k < NR; k++) t += red[k][r];
         L[i] = t;
+    }
+}
+
+// The split-bf16 mode's reductions of all split levels in one launch: level li's
+// blocks start at block blk0[li]; a block is nr[li] runs x (256 / nr[li])
+// elements and sums as k_m2l_reduce<nr> (16 runs for the many-slice coarse
+// levels, 4 otherwise).
+struct ReduceJob {
+    const float *part[kMaxDepth + 1];
+    double *L[kMaxDepth + 1];
+    int64_t n[kMaxDepth + 1], blk0[kMaxDepth + 1];
+    int nsplit[kMaxDepth + 1], nr[kMaxDepth + 1];
+    int nlv;
+};
+__global__ __launch_bounds__(256) void k_m2l_reduce_levels(ReduceJob job) {
+    __shared__ double red[256];
+    int li = 0;
+    while (li + 1 < job.nlv && (int64_t)blockIdx.x >= job.blk0[li + 1]) li++;
+    const float *part = job.part[li];
+    const int64_t n = job.n[li];
+    const int nsplit = job.nsplit[li], NR = job.nr[li], NE = 256 / NR;
+    const int w = threadIdx.x / NE, r = threadIdx.x % NE;
+    const int64_t i = ((int64_t)blockIdx.x - job.blk0[li]) * NE + r;
+    double s = 0;
+    if (i < n) {
+        int k = w;
+        for (; k + 3 * NR < nsplit; k += 4 * NR) {   // four loads in flight, added in slice order
+            const double a0 = part[k * n + i], a1 = part[(k + NR) * n + i], a2 = part[(k + 2 * NR) * n + i],
+                         a3 = part[(k + 3 * NR) * n + i];
+            s += a0;
+            s += a1;
+            s += a2;
+            s += a3;
+        }
+        for (; k < nsplit; k += NR) s += (double)part[k * n + i];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (w == 0 && i < n) {
+        double t = red[r];
+        for (int k = 1; k < NR; k++) t += red[k * NE + r];
+        job.L[li][i] = t;
     }
 }
 
@@ -628,49 +737,107 @@ bool m2l_all_cells(const ankh_plan_s *pl, int e) {
     return pl->precision == ANKH_MIXED_BF16X3 && pl->lv[e].ncell <= BN;
 }
 
-// Number of offset slices (split-K).  A level with >= 2048 block tiles runs
-// unsplit.  Otherwise a multiple of 8 (the XCD-aware block order then gives
-// every XCD whole slices), raised until the level launches >= 1024 blocks,
-// while the partial tiles stay within 32768 cells x 224 values and every slice
-// keeps at least one offset.
+// Columns of the block tile, 32 NB cells.  The split-precision kernel takes 128
+// cells (NB = 4) where a parity class has at least 128 cells and the row tile is
+// at most 160 nodes (taller tiles would not fit two waves per SIMD); everything
+// else takes 64.
+int m2l_col_frags(const ankh_plan_s *pl, int e) {
+    const int h = pl->lv[e].nside / 2;
+    const bool wide = pl->precision == ANKH_MIXED_BF16X3 && !m2l_all_cells(pl, e) && h * h * h >= 128 &&
+                      m2l_row_frags(pl->rpad[e]) <= 5;
+    return wide ? 4 : 2;
+}
+
+// Number of offset slices (split-K).  Split-precision mode: a multiple of 8 (the
+// XCD-aware block order then gives every XCD whole slices), raised until the
+// level launches >= 512 blocks, while the float32 partial tiles stay within
+// 64 MiB and every slice keeps at least one offset.  The float32 / float64
+// kernels: a level with >= 2048 block tiles runs unsplit, else as above with
+// >= 1024 blocks and float64 partials within 32768 cells x 224 values.
 int m2l_splits(const ankh_plan_s *pl, int e) {
     const int h = pl->lv[e].nside / 2;
     const int n = pl->rpad[e];
-    const int bm = 32 * m2l_row_frags(n);
-    const int64_t tiles = (int64_t)((n + bm - 1) / bm) * ((h * h * h + BN - 1) / BN) * 8;
+    const int bm = 32 * m2l_row_frags(n), bn = 32 * m2l_col_frags(pl, e);
+    const int64_t tiles = (int64_t)((n + bm - 1) / bm) * ((h * h * h + bn - 1) / bn) * 8;
     const int64_t ncell = pl->lv[e].ncell;
     if (m2l_all_cells(pl, e)) return kNumFar;
-    if (tiles >= 2048) return 1;
+    const bool bf = pl->precision == ANKH_MIXED_BF16X3;
+    const int64_t want = bf ? 512 : 1024;
+    if (tiles >= 2 * want) return 1;
     int s = 8;
-    while (tiles * s < 1024 && (s + 8) * ncell * n <= (int64_t)32768 * 224 && s + 8 <= kNumIL) s += 8;
+    if (bf)
+        while (tiles * s < want && (s + 8) * ncell * n * (int64_t)sizeof(float) <= ((int64_t)64 << 20) &&
+               s + 8 <= kNumIL)
+            s += 8;
+    else
+        while (tiles * s < want && (s + 8) * ncell * n <= (int64_t)32768 * 224 && s + 8 <= kNumIL) s += 8;
     return s;
+}
+
+// Bytes of the split-K partial tiles of level e (0 when it runs unsplit).
+size_t m2l_part_bytes(const ankh_plan_s *pl, int e) {
+    const int sp = m2l_splits(pl, e);
+    if (sp <= 1) return 0;
+    const size_t nv = (size_t)pl->lv[e].ncell * pl->rpad[e];
+    return sp * nv * (pl->precision == ANKH_MIXED_BF16X3 ? sizeof(float) : sizeof(double));
+}
+
+// Split-precision mode, once per evaluation before the contractions: every
+// level's source multipoles as bf16 hi / lo at d_Mb + mb_off[e] and d_Mb +
+// mb_total + mb_off[e].  The projection of the compressed levels writes theirs;
+// this splits the uncompressed ones (one launch, packed).
+hipError_t launch_m2l_prepare(ankh_plan_s *pl) {
+    if (pl->precision != ANKH_MIXED_BF16X3 || pl->depth < 1) return hipSuccess;
+    SplitJob job{};
+    int64_t total = 0;
+    for (int e = 1; e <= pl->depth; e++) {
+        if (pl->rpad[e] < pl->nup) continue;
+        job.src[job.nlv] = pl->d_M + pl->lv[e].cell0 * pl->nup;
+        job.n[job.nlv] = pl->lv[e].ncell * pl->rpad[e];
+        job.off[job.nlv] = total;
+        job.dst[job.nlv] = (int64_t)pl->mb_off[e];
+        total += job.n[job.nlv];
+        job.nlv++;
+    }
+    if (total == 0) return hipSuccess;
+    job.total = total;
+    hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, pl->stream, job,
+                       pl->d_Mb, pl->d_Mb + pl->mb_total);
+    return hipGetLastError();
 }
 
 namespace {
 // one level's contraction: operand size n (rows and contraction per offset), source
 // multipoles M [cells][n] (float64), K stack of the level at its slot
 template <int RF>
-void launch_rf(ankh_plan_s *pl, int e, dim3 grid, int n, const double *Msrc, double *out, int nsplit,
+void launch_rf(ankh_plan_s *pl, int e, dim3 grid, int n, const double *Msrc, double *Ldst, int nsplit,
                int64_t nval) {
     const ankh::Level &lv = pl->lv[e];
     const size_t kper = (size_t)kNumOff * pl->nup * pl->nup;
     const size_t koff = (size_t)(e - 1) * kper;
     if (pl->precision == ANKH_MIXED_BF16X3) {
-        const __bf16 *Mh = pl->d_Mb, *Ml = pl->d_Mb + nval;
+        const __bf16 *Mh = pl->d_Mb + pl->mb_off[e], *Ml = pl->d_Mb + pl->mb_total + pl->mb_off[e];
         const size_t kall = (size_t)pl->depth * kper;
+        float *part = reinterpret_cast<float *>(pl->d_m2l_part) + pl->m2l_part_off[e];
         if (m2l_all_cells(pl, e))
             hipLaunchKernelGGL(k_m2l_bf16x3_all<RF>, dim3((unsigned)(((n + 32 * RF - 1) / (32 * RF)) * nsplit)),
-                               dim3(NTHR), 0, pl->stream, pl->d_Kb + koff, pl->d_Kb + kall + koff, Mh, Ml, out,
+                               dim3(NTHR), 0, pl->stream, pl->d_Kb + koff, pl->d_Kb + kall + koff, Mh, Ml, part,
+                               lv.nside, n, nsplit, nval);
+        else if (m2l_col_frags(pl, e) == 4) {
+            if constexpr (RF <= 5)
+                hipLaunchKernelGGL((k_m2l_bf16x3<RF, 4>), grid, dim3(NTHR), 0, pl->stream, pl->d_Kb + koff,
+                                   pl->d_Kb + kall + koff, Mh, Ml, part, Ldst, lv.nside, n, nsplit, nval);
+        } else
+            hipLaunchKernelGGL((k_m2l_bf16x3<RF, 2>), grid, dim3(NTHR), 0, pl->stream, pl->d_Kb + koff,
+                               pl->d_Kb + kall + koff, Mh, Ml, part, Ldst, lv.nside, n, nsplit, nval);
+    } else {
+        double *out = nsplit > 1 ? pl->d_m2l_part : Ldst;
+        if (pl->precision == ANKH_MIXED)
+            hipLaunchKernelGGL((k_m2l<float, RF>), grid, dim3(NTHR), 0, pl->stream, pl->d_Kf + koff, pl->d_Mf, out,
                                lv.nside, n, nsplit, nval);
         else
-            hipLaunchKernelGGL(k_m2l_bf16x3<RF>, grid, dim3(NTHR), 0, pl->stream, pl->d_Kb + koff,
-                               pl->d_Kb + kall + koff, Mh, Ml, out, lv.nside, n, nsplit, nval);
-    } else if (pl->precision == ANKH_MIXED) {
-        hipLaunchKernelGGL((k_m2l<float, RF>), grid, dim3(NTHR), 0, pl->stream, pl->d_Kf + koff, pl->d_Mf, out,
-                           lv.nside, n, nsplit, nval);
-    } else {
-        hipLaunchKernelGGL((k_m2l<double, RF>), grid, dim3(NTHR), 0, pl->stream, pl->d_K + koff, Msrc, out,
-                           lv.nside, n, nsplit, nval);
+            hipLaunchKernelGGL((k_m2l<double, RF>), grid, dim3(NTHR), 0, pl->stream, pl->d_K + koff, Msrc, out,
+                               lv.nside, n, nsplit, nval);
     }
 }
 }  // namespace
@@ -682,9 +849,9 @@ hipError_t launch_m2l(ankh_plan_s *pl, int e) {
     const int n = pl->rpad[e];
     const bool comp = n < pl->nup;
     const int nsplit = m2l_splits(pl, e);
-    const int rf = m2l_row_frags(n);
-    const int bm = 32 * rf;
-    dim3 grid((unsigned)(((n + bm - 1) / bm) * ((ncls + BN - 1) / BN) * 8 * nsplit));
+    const int rf = m2l_all_cells(pl, e) ? 2 : m2l_row_frags(n);
+    const int bm = 32 * rf, bn = 32 * m2l_col_frags(pl, e);
+    dim3 grid((unsigned)(((n + bm - 1) / bm) * ((ncls + bn - 1) / bn) * 8 * nsplit));
     const int64_t nval = lv.ncell * n;
     double *L = pl->d_L + lv.cell0 * pl->nup;
     const double *M = pl->d_M + lv.cell0 * pl->nup;
@@ -692,29 +859,57 @@ hipError_t launch_m2l(ankh_plan_s *pl, int e) {
     // levels before the first contraction), L = L' U^T (after the last)
     double *Msrc = comp ? pl->d_Mc + pl->c_off[e] : const_cast<double *>(M);
     double *Ldst = comp ? pl->d_Lc + pl->c_off[e] : L;
-    double *out = nsplit > 1 ? pl->d_m2l_part : Ldst;
-    // this level's multipoles in the working precision of the contraction
-    if (pl->precision == ANKH_MIXED_BF16X3)
-        hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream, Msrc,
-                           pl->d_Mb, pl->d_Mb + nval, nval);
-    else if (pl->precision == ANKH_MIXED)
+    // this level's multipoles in the working precision of the float32 contraction
+    // (the split-precision mode splits all levels in launch_m2l_prepare)
+    if (pl->precision == ANKH_MIXED)
         hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream, Msrc,
                            pl->d_Mf, nval);
     switch (rf) {
-        case 2: launch_rf<2>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
-        case 3: launch_rf<3>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
-        case 4: launch_rf<4>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
-        case 5: launch_rf<5>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
-        case 6: launch_rf<6>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
-        case 7: launch_rf<7>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
-        default: launch_rf<8>(pl, e, grid, n, Msrc, out, nsplit, nval); break;
+        case 2: launch_rf<2>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
+        case 3: launch_rf<3>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
+        case 4: launch_rf<4>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
+        case 5: launch_rf<5>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
+        case 6: launch_rf<6>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
+        case 7: launch_rf<7>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
+        default: launch_rf<8>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
     }
-    if (nsplit > 64)
-        hipLaunchKernelGGL(k_m2l_reduce<16>, dim3((unsigned)((nval + 15) / 16)), dim3(256), 0, pl->stream,
-                           pl->d_m2l_part, Ldst, nval, nsplit);
-    else if (nsplit > 1)
-        hipLaunchKernelGGL(k_m2l_reduce<4>, dim3((unsigned)((nval + 63) / 64)), dim3(256), 0, pl->stream,
-                           pl->d_m2l_part, Ldst, nval, nsplit);
+    // split levels of the float32 / float64 kernels are summed here (they share one
+    // partial buffer); the split-bf16 mode's levels in launch_m2l_finish
+    if (nsplit > 1 && pl->precision != ANKH_MIXED_BF16X3) {
+        const double *pd = pl->d_m2l_part;
+        if (nsplit > 64)
+            hipLaunchKernelGGL((k_m2l_reduce<16, double>), dim3((unsigned)((nval + 15) / 16)), dim3(256), 0,
+                               pl->stream, pd, Ldst, nval, nsplit);
+        else
+            hipLaunchKernelGGL((k_m2l_reduce<4, double>), dim3((unsigned)((nval + 63) / 64)), dim3(256), 0,
+                               pl->stream, pd, Ldst, nval, nsplit);
+    }
+    return hipGetLastError();
+}
+
+// Split-bf16 mode, after the last contraction: the partial tiles of every split
+// level (each level has its own region) summed into its local expansions.
+hipError_t launch_m2l_finish(ankh_plan_s *pl) {
+    if (pl->precision != ANKH_MIXED_BF16X3 || pl->depth < 1) return hipSuccess;
+    ReduceJob job{};
+    int64_t blocks = 0;
+    for (int e = 1; e <= pl->depth; e++) {
+        const int nsplit = m2l_splits(pl, e);
+        if (nsplit <= 1) continue;
+        const ankh::Level &lv = pl->lv[e];
+        const int n = pl->rpad[e];
+        job.part[job.nlv] = reinterpret_cast<const float *>(pl->d_m2l_part) + pl->m2l_part_off[e];
+        job.L[job.nlv] = n < pl->nup ? pl->d_Lc + pl->c_off[e] : pl->d_L + lv.cell0 * pl->nup;
+        job.n[job.nlv] = lv.ncell * n;
+        job.nsplit[job.nlv] = nsplit;
+        job.nr[job.nlv] = nsplit > 64 ? 16 : 4;
+        job.blk0[job.nlv] = blocks;
+        const int ne = 256 / job.nr[job.nlv];
+        blocks += (job.n[job.nlv] + ne - 1) / ne;
+        job.nlv++;
+    }
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_m2l_reduce_levels, dim3((unsigned)blocks), dim3(256), 0, pl->stream, job);
     return hipGetLastError();
 }
 

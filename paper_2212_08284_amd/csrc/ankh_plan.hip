@@ -205,8 +205,10 @@ ankh_status run(ankh_plan_s *pl, const double *pos, const double *q, const doubl
         } else {
             for (int e = pl->depth - 1; e >= 0; e--) ck(launch_m2m(pl, e));
             mark(4);
+            ck(launch_m2l_prepare(pl));
             ck(launch_m2l_project(pl));
             for (int e = 1; e <= pl->depth; e++) ck(launch_m2l(pl, e));
+            ck(launch_m2l_finish(pl));
             ck(launch_m2l_expand(pl));
             mark(5);
             ck(launch_cper(pl));
@@ -609,17 +611,24 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
                 dalloc(pl, &pl->d_Mc, coff);
                 dalloc(pl, &pl->d_Lc, coff);
             }
-            // M2L scratch: split-K partials and one level's multipoles in the working precision
+            // M2L scratch: split-K partials of one level, and the multipoles in the working
+            // precision (one level in float32; all levels in split bf16)
             size_t part = 0, mlev = 0;
             for (int e = 1; e <= pl->depth; e++) {
                 const size_t nv = (size_t)pl->lv[e].ncell * pl->rpad[e];
-                const int sp = m2l_splits(pl, e);
-                if (sp > 1) part = std::max(part, (size_t)sp * nv);
+                if (bf) {   // every split level its own float32 region (256-byte aligned)
+                    pl->m2l_part_off[e] = part / sizeof(float);
+                    part += (m2l_part_bytes(pl, e) + 255) / 256 * 256;
+                } else {
+                    part = std::max(part, m2l_part_bytes(pl, e));
+                }
                 mlev = std::max(mlev, nv);
+                pl->mb_off[e] = pl->mb_total;
+                pl->mb_total += nv;
             }
-            if (part) dalloc(pl, &pl->d_m2l_part, part);
+            if (part) dalloc(pl, &pl->d_m2l_part, (part + sizeof(double) - 1) / sizeof(double));
             if (precision == ANKH_MIXED) dalloc(pl, &pl->d_Mf, mlev);
-            if (bf) dalloc(pl, &pl->d_Mb, 2 * mlev);
+            if (bf) dalloc(pl, &pl->d_Mb, 2 * pl->mb_total);
         }
         if (fft) {
             // the 6D spectrum: node transforms of the reinterpolation (B) and of the generating
