@@ -55,6 +55,8 @@ P2P_COUNTERS = os.path.join(ROOT, "profiles", "p2p_water_288000_counters.txt")
 P2P_SOURCE = os.path.join(ROOT, "paper_2212_08284_amd", "csrc", "ankh_p2p.hip")
 FFT_COUNTERS = os.path.join(ROOT, "profiles", "fft_cells_water_288000_counters.txt")
 FFT_SOURCE = os.path.join(ROOT, "paper_2212_08284_amd", "csrc", "ankh_fft.hip")
+M2L_COUNTERS = os.path.join(ROOT, "profiles", "m2l_water_288000_counters.txt")
+M2L_SOURCES = [os.path.join(ROOT, "paper_2212_08284_amd", "csrc", f) for f in ("ankh_m2l.hip", "ankh_compress.hip")]
 
 PEAK = {  # MI355X, TFLOP/s (hbm: GB/s)
     "hbm": 8000.0,
@@ -69,8 +71,9 @@ PREC_NAME = {0: "f64", 1: "f32", 2: "bf16x3"}
 
 
 def counter_traffic(counters=P2P_COUNTERS, source=P2P_SOURCE, leaves=None):
-    """Calibrated HBM bytes per launch of a kernel from its committed counter summary, or None when
-    the summary is missing, the kernel source has changed since, or it was taken on another leaf grid."""
+    """Calibrated HBM bytes per launch of a kernel (or stage) from its committed counter summary, or None
+    when the summary is missing, the kernel source (one file, or several hashed in order as one stream)
+    has changed since, or it was taken on another leaf grid."""
     import hashlib
     try:
         rec = {}
@@ -79,8 +82,11 @@ def counter_traffic(counters=P2P_COUNTERS, source=P2P_SOURCE, leaves=None):
                 if "=" in ln and not ln.lstrip().startswith("#"):
                     k, v = ln.split("=", 1)
                     rec[k.strip()] = v.strip()
-        with open(source, "rb") as fh:
-            sha = hashlib.sha256(fh.read()).hexdigest()
+        h = hashlib.sha256()
+        for src in ([source] if isinstance(source, str) else source):
+            with open(src, "rb") as fh:
+                h.update(fh.read())
+        sha = h.hexdigest()
         if rec.get("kernel_source_sha256") != sha:
             return None
         if leaves is not None and rec.get("leaves_per_axis") != str(leaves):
@@ -176,15 +182,18 @@ def m2l_roofline(st, breakdown, mode):
     t = st["stage_ms"]["m2l"]
     tf = flops / (t * 1e-3) / 1e12
     alone = flops / (breakdown["m2l"] * 1e-3) / 1e12
+    traffic = (counter_traffic(M2L_COUNTERS, M2L_SOURCES, st.get("leaves_per_axis"))
+               if mode == "mixed_bf16x3" else None)
     rec = {"kernel": "m2l", "bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
-           "traffic": None, "flop_per_launch": flops, "avg_launch_ms": t, "alone_avg_launch_ms": breakdown["m2l"],
+           "traffic": traffic, "flop_per_launch": flops, "avg_launch_ms": t, "alone_avg_launch_ms": breakdown["m2l"],
            "alone_achieved": alone, "alone_frac": alone / peak, "ranks": st.get("m2l_rank"),
            "note": "ANKH-FMM far-field contraction, all levels with the projection / expansion of compressed levels "
                    "(stage 4); algorithmic flops per cell of level e: 2 * 189 * r_e^2 (r_e the kept rank) + "
                    "4 * n_u * r_e for the basis change"}
     if mode == "mixed_bf16x3":
         rec["issued_frac"] = 3 * tf / peak
-        rec["note"] += "; the split-precision product issues three bf16 products per algorithmic one (issued_frac)"
+        rec["note"] += ("; the split-precision product issues three bf16 products per algorithmic one (issued_frac)"
+                        "; traffic: the counters' HBM bytes summed over the stage's launches")
     return rec
 
 
