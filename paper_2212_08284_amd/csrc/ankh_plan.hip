@@ -611,8 +611,10 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
                 dalloc(pl, &pl->d_Mc, coff);
                 dalloc(pl, &pl->d_Lc, coff);
             }
-            // M2L scratch: split-K partials of one level, and the multipoles in the working
-            // precision (one level in float32; all levels in split bf16)
+            // M2L scratch: split-K partials (the largest level's in float64, reused level by level;
+            // in split bf16 every split level's float32 tiles side by side, summed in one launch),
+            // and the multipoles in the working precision (one level in float32; all levels in
+            // split bf16)
             size_t part = 0, mlev = 0;
             for (int e = 1; e <= pl->depth; e++) {
                 const size_t nv = (size_t)pl->lv[e].ncell * pl->rpad[e];
