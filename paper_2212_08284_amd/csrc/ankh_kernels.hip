@@ -245,7 +245,7 @@ __global__ void k_gather(int64_t n, const int32_t *perm, const int32_t *leaf, co
 // T_m and its derivatives up to order ND-1 by the differentiated three-term
 // recurrence (identical to D^n T with the differentiation matrix D), then
 // S^(n)_k = (1/h)^n sum_m H[k][m] T^(n)_m.
-template <int ND, int L>
+template <int ND, int L, bool ROLLED = false>
 __device__ inline void cheb_basis(double xh, double hinv, const double *sH, double *out /* [ND][L] */,
                                   int stride_n) {
     double T[ND][L > 2 ? L : 2];
@@ -260,15 +260,27 @@ __device__ inline void cheb_basis(double xh, double hinv, const double *sH, doub
 #pragma unroll
         for (int n = 1; n < ND; n++) T[n][m + 1] = 2 * n * T[n - 1][m] + 2 * xh * T[n][m] - T[n][m - 1];
     }
+    // ROLLED (an output in LDS): the loop over k stays a loop, which keeps the L^2 entries of sH out of
+    // registers; an output in registers needs it unrolled (constant indices)
     double sc = 1.0;
 #pragma unroll
     for (int n = 0; n < ND; n++) {
+        if constexpr (ROLLED) {
+#pragma unroll 1
+            for (int k = 0; k < L; k++) {
+                double s = 0;
 #pragma unroll
-        for (int k = 0; k < L; k++) {
-            double s = 0;
+                for (int m = 0; m < L; m++) s += sH[k * L + m] * T[n][m];
+                out[n * stride_n + k] = s * sc;
+            }
+        } else {
 #pragma unroll
-            for (int m = 0; m < L; m++) s += sH[k * L + m] * T[n][m];
-            out[n * stride_n + k] = s * sc;
+            for (int k = 0; k < L; k++) {
+                double s = 0;
+#pragma unroll
+                for (int m = 0; m < L; m++) s += sH[k * L + m] * T[n][m];
+                out[n * stride_n + k] = s * sc;
+            }
         }
         sc *= hinv;
     }
@@ -337,12 +349,12 @@ __device__ inline void p2m_weights(const double *mo, const double (*Sy)[L], cons
 }
 
 template <int L, int ORD>
-__global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, const double *tab, int nu, int nup,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_p2m(Particles P, const int32_t *offs, const double *tab, int nu, int nup,
                                              double hinv, double *Q, int64_t n) {
     constexpr int ND = ORD + 1;
-    // atoms per LDS chunk (a leaf of the planned grids: one chunk); 32 with octupoles, whose four basis
-    // derivatives per axis would not fit 64 atoms into the static LDS at order 10
-    constexpr int CH = ORD >= 3 ? 32 : 64;
+    // atoms per LDS chunk (a leaf of the planned ANKH-FFT grids: one chunk): 32 keeps the block's LDS
+    // at 17 KB (order 6, quadrupoles), so that eight blocks of 60 VGPRs share a CU
+    constexpr int CH = 32;
     constexpr int NJK = L * L;
     constexpr int NSL = 256 / NJK;         // atom slices
     constexpr int NMO = ORD == 0 ? 1 : (ORD == 1 ? 4 : (ORD == 2 ? 10 : 20));
@@ -368,13 +380,14 @@ __global__ __launch_bounds__(256) void k_p2m(Particles P, const int32_t *offs, c
             const int a = tid / 3, ax = tid % 3;
             const int64_t slot = s0 + c0 + a;
             const double xl = ax == 0 ? P.x[slot] : (ax == 1 ? P.y[slot] : P.z[slot]);
-            cheb_basis<ND, L>(xl * hinv, hinv, sH, &sS[a][ax][0][0], L);
+            cheb_basis<ND, L, true>(xl * hinv, hinv, sH, &sS[a][ax][0][0], L);
         } else if (tid >= 3 * CH && tid < 3 * CH + m) {
             const int a = tid - 3 * CH;
             p2m_moments<ORD>(P, s0 + c0 + a, n, sMom[a]);
         }
         __syncthreads();
         if (sl < NSL) {
+#pragma unroll 1
             for (int a = sl; a < m; a += NSL) {
                 double w[ND];
                 p2m_weights<ORD, ND, L>(sMom[a], sS[a][1], sS[a][2], j, k, w);
