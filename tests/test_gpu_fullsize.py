@@ -10,6 +10,8 @@ times, through the C ABI (the binding only marshals arguments).
 * Planner: the automatic far field is ANKH-FFT; a force-accuracy target raises the order; the workspace
   limit turns into ANKH_ERR_OUT_OF_MEMORY with every output untouched.
 * Autograd through the charges and quadrupoles.
+* ANKH-FMM at depth 6 (3,000,000 atoms, ~11 per leaf): the finest level's contraction runs unsplit in every
+  precision, the mixed modes within the tile-shape bars of the FP64 path.
 """
 import ctypes
 import os
@@ -290,3 +292,30 @@ def test_autograd_charges_and_quadrupoles(ak):
     assert torch.equal(q.grad, ref["dEdq"])
     assert torch.equal(th.grad, ref["dEdtheta"])
     pl.close()
+
+
+@pytest.mark.parametrize("mode", ["mixed", "mixed_bf16x3"])
+def test_fmm_depth6_unsplit_finest_level(ak, mode):
+    """ANKH-FMM at depth 6 on a 1,000,000-molecule water box: the 262,144 cells of the finest level fill
+    enough block tiles (2048 and more per level) that its contraction is not split over the interaction
+    list, so the kernels write their float64 locals directly (the float32 / float64 matrix-core kernel,
+    and the split-bf16 kernel with 128-cell tiles); shallower trees only take the split path.  The mixed
+    modes stay within 1e-5 (energy) and 1e-4 (RMS forces and fields) of the FP64 path, the bars of the
+    tile-shape test (measured: 7.5e-8 / 5.6e-7 / 3.9e-7 with float32 matrix cores, 1.5e-6 / 5.7e-7 /
+    4.7e-7 in split bf16)."""
+    d = synth.water(1000000, seed=3)
+    args = (T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
+
+    def run(prec):
+        pl = ak.Plan(len(d["q"]), 0.5 * d["edge"], 1e-6, 2, prec, far="fmm", depth=6)
+        e, F, G = pl.energy_forces(*args)
+        pl.sync()
+        out = (e.item(), F.cpu().numpy(), G.cpu().numpy())
+        pl.close()
+        return out
+
+    e64, F64, G64 = run("fp64")
+    e, F, G = run(mode)
+    assert abs(e - e64) <= 1e-5 * abs(e64)
+    assert errs(F, F64)[0] <= 1e-4
+    assert errs(G, G64)[0] <= 1e-4
