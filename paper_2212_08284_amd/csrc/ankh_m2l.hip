@@ -14,11 +14,13 @@
 // run on the matrix cores (v_mfma 16x16x4 f64 / f32, or 16x16x32 bf16 in the
 // split-precision mode).  A block owns a tile of up to 256 output nodes (all
 // n_u of them for the usual orders, so the gathered multipoles are read once
-// per tile) x 64 cells and a slice of the 189 offsets; K_d and the gathered
-// multipoles stream through double-buffered LDS.  Slices of the offset list
-// (split-K) give the launch enough blocks to fill the chip at every level;
-// their partial tiles are summed in a fixed order by k_m2l_reduce, so results
-// do not depend on scheduling.
+// per tile) x 64 cells (128 on the finest levels in split precision) and a
+// slice of the 189 offsets; K_d and the gathered multipoles stream through
+// double-buffered LDS.  Slices of the offset list (split-K) give the launch
+// enough blocks to fill the chip at every level; their partial tiles are
+// summed in a fixed order (k_m2l_reduce, or k_m2l_reduce_levels for all split
+// levels of the split-precision mode at once), so results do not depend on
+// scheduling.
 #include <algorithm>
 #include <cmath>
 
