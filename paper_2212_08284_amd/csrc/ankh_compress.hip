@@ -152,6 +152,7 @@ struct BasisLevel {
     const double *B;
     double *C;
     __bf16 *hi, *lo;   // projection in the split-bf16 mode: C also as bf16 hi / lo parts (same layout), else null
+    float *f32;        // projection in the float32 mode: C also in float32 (same layout), else null
     int lda, ldb, ldc, rows, N, K, ntn, tile0;
 };
 constexpr int kMaxBasisLevels = 8;
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(256) void k_basis(BasisJob job) {
                 L.hi[o] = a;
                 L.lo[o] = (__bf16)(x - (float)a);
             }
+            if (L.f32) L.f32[o] = (float)sum;
         }
     }
 }
@@ -266,6 +268,8 @@ hipError_t launch_m2l_basis(ankh_plan_s *pl, bool expand) {
             if (pl->precision == ANKH_MIXED_BF16X3) {
                 b.hi = pl->d_Mb + pl->mb_off[e];
                 b.lo = pl->d_Mb + pl->mb_total + pl->mb_off[e];
+            } else if (pl->precision == ANKH_MIXED) {
+                b.f32 = pl->d_Mf + pl->mb_off[e];
             }
         } else {
             b.A = Lc, b.lda = rp, b.K = rp;

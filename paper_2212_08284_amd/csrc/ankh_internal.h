@@ -92,12 +92,12 @@ struct ankh_plan_s {
     double *d_L = nullptr;        // local expansions, all levels [cells][nup]
     double *d_K = nullptr;        // fp64 M2L matrices: level e>=1 at (e-1) * 343 * nup * nup, [d][l][k]
     float *d_Kf = nullptr;        // fp32 copy for the mixed mode
-    float *d_Mf = nullptr;        // fp32 multipoles of one level (mixed mode M2L operand)
+    float *d_Mf = nullptr;        // fp32 multipoles of all levels (mixed mode M2L operand), level e at mb_off[e]
     __bf16 *d_Kb = nullptr;       // bf16 hi parts of all levels' K (row-major K_d[k][l]), then the lo parts
     __bf16 *d_Mb = nullptr;       // bf16 hi parts of all levels' source multipoles (level e at mb_off[e]), then the lo parts
     size_t mb_off[ankh::kMaxDepth + 1] = {}, mb_total = 0;
-    double *d_m2l_part = nullptr; // split-K partial local expansions: one level's (float64), or in the split-bf16
-                                  // mode every split level's float32 tiles, level e at m2l_part_off[e] floats
+    double *d_m2l_part = nullptr; // split-K partial tiles of every split level (float64 in FP64, float32 in the
+                                  // mixed modes), level e at byte m2l_part_off[e]
     size_t m2l_part_off[ankh::kMaxDepth + 1] = {};
     // compressed M2L, per level e >= 1: kept rank, padded rank (n_up when the level is
     // uncompressed), basis U [n_up][rpad] at d_U + u_off[e], compressed multipoles and
@@ -175,8 +175,8 @@ int m2l_splits(const ankh_plan_s *pl, int e);
 int m2l_row_frags(int nup);
 int m2l_col_frags(const ankh_plan_s *pl, int e);
 size_t m2l_part_bytes(const ankh_plan_s *pl, int e);
-hipError_t launch_m2l_prepare(ankh_plan_s *pl);     // split-bf16 mode: uncompressed levels' multipoles as bf16 hi / lo
-hipError_t launch_m2l_finish(ankh_plan_s *pl);      // split-bf16 mode: sums of the split levels' partial tiles
+hipError_t launch_m2l_prepare(ankh_plan_s *pl);     // mixed modes: uncompressed levels' multipoles in the working precision
+hipError_t launch_m2l_finish(ankh_plan_s *pl);      // sums of the split levels' partial tiles
 hipError_t launch_split_K_bf16(ankh_plan_s *pl, const double *K, __bf16 *hi, __bf16 *lo, int nr);
 hipError_t compress_level(ankh_plan_s *pl, int e, const double *K, double *Kc, double *work, double tol);
 hipError_t launch_m2l_basis(ankh_plan_s *pl, bool expand);

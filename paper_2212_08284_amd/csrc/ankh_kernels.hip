@@ -349,7 +349,7 @@ __device__ inline void p2m_weights(const double *mo, const double (*Sy)[L], cons
 }
 
 template <int L, int ORD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_p2m(Particles P, const int32_t *offs, const double *tab, int nu, int nup,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(L <= 7 && ORD <= 2 ? 8 : 1))) void k_p2m(Particles P, const int32_t *offs, const double *tab, int nu, int nup,
                                              double hinv, double *Q, int64_t n) {
     constexpr int ND = ORD + 1;
     // atoms per LDS chunk (a leaf of the planned ANKH-FFT grids: one chunk): 32 keeps the block's LDS

@@ -137,10 +137,10 @@ __device__ inline size_t source_cell(int gx, int gy, int gz, int di, int nside) 
 // (f64) or 16 (f32): 64 bytes of contraction per row and step.  Row strides
 // of the LDS tiles are BM + 16 and BN + 16 elements, which puts the four
 // 16-lane groups of a fragment read on disjoint banks.
-template <typename T, int RF>
-__global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *__restrict__ M,
-                                             double *__restrict__ out, int nside, int nup, int nsplit,
-                                             int64_t out_stride) {
+template <typename T, int RF, bool ALL>
+__global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *__restrict__ M, T *__restrict__ part,
+                                             double *__restrict__ dst, int nside, int nup, int nsplit,
+                                             int64_t part_stride) {
     using Acc = typename Mma<T>::acc;
     constexpr int BM = 32 * RF;
     constexpr int BK = 64 / (int)sizeof(T);
@@ -152,12 +152,28 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
     const int lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int h = nside >> 1;
-    const int ncls = h * h * h;
-    const M2LTile tile = m2l_tile((nup + BM - 1) / BM, (ncls + BN - 1) / BN, nsplit);
-    const int px = tile.cls >> 2, py = (tile.cls >> 1) & 1, pz = tile.cls & 1;
-    const int row0 = tile.rt * BM, col0 = tile.ct * BN;
-    const int *il = c_il.v[tile.cls];
-    const int o_begin = kNumIL * tile.split / nsplit, o_end = kNumIL * (tile.split + 1) / nsplit;
+    const int nrt = (nup + BM - 1) / BM;
+    // block -> (row tile, column tile, parity class, offset slice).  ALL (a coarse level of at most 64
+    // cells): the level's cells in natural order in one column tile, contracted over the 316 offsets of
+    // the union of the class lists; a cell reads zero multipoles for the offsets outside its own list.
+    int rt, ct = 0, cls = 0, split, ncol, nil;
+    const int *il;
+    if constexpr (ALL) {
+        rt = blockIdx.x % nrt;
+        split = blockIdx.x / nrt;
+        ncol = nside * nside * nside;
+        il = c_far.v;
+        nil = kNumFar;
+    } else {
+        ncol = h * h * h;
+        const M2LTile tile = m2l_tile(nrt, (ncol + BN - 1) / BN, nsplit);
+        rt = tile.rt, ct = tile.ct, cls = tile.cls, split = tile.split;
+        il = c_il.v[cls];
+        nil = kNumIL;
+    }
+    const int px = cls >> 2, py = (cls >> 1) & 1, pz = cls & 1;
+    const int row0 = rt * BM, col0 = ct * BN;
+    const int o_begin = nil * split / nsplit, o_end = nil * (split + 1) / nsplit;
 
     // A loader: pairs of adjacent rows; LA pairs per thread
     constexpr int NPA = BK * BM / 2, LA = (NPA + NTHR - 1) / NTHR;
@@ -166,12 +182,16 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
     static_assert(BK * BN == PB * NTHR, "B tile must be one 16-byte load per thread");
     const int b_col = tid / (BK / PB), b_k = (tid % (BK / PB)) * PB;
     const int tcell = col0 + b_col;
-    const bool b_ok = tcell < ncls;
+    const bool b_ok = tcell < ncol;
     int gx = 0, gy = 0, gz = 0;
     if (b_ok) {
-        gx = 2 * (tcell / (h * h)) + px;
-        gy = 2 * ((tcell / h) % h) + py;
-        gz = 2 * (tcell % h) + pz;
+        if constexpr (ALL) {
+            gx = tcell / (nside * nside), gy = (tcell / nside) % nside, gz = tcell % nside;
+        } else {
+            gx = 2 * (tcell / (h * h)) + px;
+            gy = 2 * ((tcell / h) % h) + py;
+            gz = 2 * (tcell % h) + pz;
+        }
     }
 
     const int nk = nup / BK;
@@ -193,7 +213,12 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
                 ra[u][1] = (T)0;
             }
         }
-        if (b_ok) {
+        bool use = b_ok;
+        if constexpr (ALL) {
+            const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
+            use = use && in_list_1d(dx, gx & 1) && in_list_1d(dy, gy & 1) && in_list_1d(dz, gz & 1);
+        }
+        if (use) {
             const T *src = M + source_cell(gx, gy, gz, di, nside) * nup + k0 + b_k;
             const uint4 v = *reinterpret_cast<const uint4 *>(src);
             const T *pv = reinterpret_cast<const T *>(&v);
@@ -249,20 +274,28 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
         __syncthreads();
     }
 
-    // scatter each 16 x 16 result block (rows per Mma<T>::row, column lane % 16)
-    double *o = out + (size_t)tile.split * out_stride;
+    // scatter each 16 x 16 result block (rows per Mma<T>::row, column lane % 16): split-K, the
+    // accumulators as they are (type T) into slice `split` of `part`; else float64 into `dst`
 #pragma unroll
     for (int j = 0; j < 2; j++) {
         const int cl = col0 + wc * 32 + j * 16 + lr;
-        if (cl >= ncls) continue;
-        const int cx = 2 * (cl / (h * h)) + px, cy = 2 * ((cl / h) % h) + py, cz = 2 * (cl % h) + pz;
-        double *Lc = o + ((size_t)(cx * nside + cy) * nside + cz) * nup;
+        if (cl >= ncol) continue;
+        size_t cell = cl;
+        if constexpr (!ALL)
+            cell = ((size_t)(2 * (cl / (h * h)) + px) * nside + 2 * ((cl / h) % h) + py) * nside + 2 * (cl % h) + pz;
 #pragma unroll
         for (int i = 0; i < RF; i++) {
             const int rb = row0 + wr * 16 * RF + i * 16;   // 16-row block, entirely inside or outside nup
             if (rb >= nup) continue;
+            if (nsplit > 1) {
+                T *Pc = part + (size_t)split * part_stride + cell * nup + rb;
 #pragma unroll
-            for (int v = 0; v < 4; v++) Lc[rb + Mma<T>::row(lk, v)] = (double)acc[i][j][v];
+                for (int v = 0; v < 4; v++) Pc[Mma<T>::row(lk, v)] = acc[i][j][v];
+            } else {
+                double *Lc = dst + cell * nup + rb;
+#pragma unroll
+                for (int v = 0; v < 4; v++) Lc[Mma<T>::row(lk, v)] = (double)acc[i][j][v];
+            }
         }
     }
 }
@@ -590,25 +623,36 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3_all(const __bf16 *__restrict
     }
 }
 
-// hi / lo bf16 split (via float32) of the source multipoles of several levels in
-// one launch: level li's n[li] values (packed at off[li] of the launch's range)
-// from src[li] go to hi / lo + dst[li]
+// The source multipoles of several levels in one launch, in the working precision of the
+// contraction: level li's n[li] values (packed at off[li] of the launch's range) from src[li] go to
+// position dst[li] of the output: bf16 hi / lo parts (via float32), or float32.
 struct SplitJob {
     const double *src[kMaxDepth + 1];
     int64_t n[kMaxDepth + 1], off[kMaxDepth + 1], dst[kMaxDepth + 1];
     int nlv;
     int64_t total;
 };
+__device__ inline int64_t split_job_index(const SplitJob &job, int64_t i, int &li) {
+    li = 0;
+    while (li + 1 < job.nlv && i >= job.off[li + 1]) li++;
+    return i - job.off[li];
+}
 __global__ void k_split_bf16(SplitJob job, __bf16 *__restrict__ hi, __bf16 *__restrict__ lo) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= job.total) return;
-    int li = 0;
-    while (li + 1 < job.nlv && i >= job.off[li + 1]) li++;
-    const int64_t k = i - job.off[li];
+    int li;
+    const int64_t k = split_job_index(job, i, li);
     const float x = (float)job.src[li][k];
     const __bf16 a = (__bf16)x;
     hi[job.dst[li] + k] = a;
     lo[job.dst[li] + k] = (__bf16)(x - (float)a);
+}
+__global__ void k_to_f32_levels(SplitJob job, float *__restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= job.total) return;
+    int li;
+    const int64_t k = split_job_index(job, i, li);
+    out[job.dst[li] + k] = (float)job.src[li][k];
 }
 
 // plan time: K_d for the BF16 x 3 kernel from the [d][l][k] float64 stack
@@ -628,55 +672,25 @@ __global__ void k_split_K_bf16(const double *__restrict__ K, __bf16 *__restrict_
     lo[i] = (__bf16)(x - (float)a);
 }
 
-// L = sum over the split-K partials (float64, or the float32 tiles of the split
-// bf16 kernels) in a fixed order: NR interleaved runs of the slices (slice k in
-// run k mod NR), each added in float64 in slice order, then the NR run sums in
-// run order.  256 threads = NR runs x (256 / NR) elements.
-template <int NR, typename P>
-__global__ __launch_bounds__(256) void k_m2l_reduce(const P *__restrict__ part, double *__restrict__ L, int64_t n,
-                                                    int nsplit) {
-    constexpr int NE = 256 / NR;
-    __shared__ double red[NR][NE];
-    const int w = threadIdx.x / NE, r = threadIdx.x % NE;
-    const int64_t i = blockIdx.x * (int64_t)NE + r;
-    double s = 0;
-    if (i < n) {
-        int k = w;
-        for (; k + 3 * NR < nsplit; k += 4 * NR) {   // four loads in flight, added in slice order
-            const double a0 = part[k * n + i], a1 = part[(k + NR) * n + i], a2 = part[(k + 2 * NR) * n + i],
-                         a3 = part[(k + 3 * NR) * n + i];
-            s += a0;
-            s += a1;
-            s += a2;
-            s += a3;
-        }
-        for (; k < nsplit; k += NR) s += (double)part[k * n + i];
-    }
-    red[w][r] = s;
-    __syncthreads();
-    if (w == 0 && i < n) {
-        double t = red[0][r];
-        for (int k = 1; k < NR; k++) t += red[k][r];
-        L[i] = t;
-    }
-}
-
-// The split-bf16 mode's reductions of all split levels in one launch: level li's
-// blocks start at block blk0[li]; a block is nr[li] runs x (256 / nr[li])
-// elements and sums as k_m2l_reduce<nr> (16 runs for the many-slice coarse
-// levels, 4 otherwise).
+// The reductions of all split levels in one launch, after the last contraction: L = sum over the
+// level's partial tiles (float64, or the float32 accumulator tiles of the mixed modes, added in
+// float64) in a fixed order.  Level li's blocks start at block blk0[li]; a block is nr[li] runs x
+// (256 / nr[li]) elements (16 runs for the many-slice coarse levels, 4 otherwise): slice k goes to run
+// k mod nr, each run adds its slices in slice order, then the runs are added in run order.
+template <typename P>
 struct ReduceJob {
-    const float *part[kMaxDepth + 1];
+    const P *part[kMaxDepth + 1];
     double *L[kMaxDepth + 1];
     int64_t n[kMaxDepth + 1], blk0[kMaxDepth + 1];
     int nsplit[kMaxDepth + 1], nr[kMaxDepth + 1];
     int nlv;
 };
-__global__ __launch_bounds__(256) void k_m2l_reduce_levels(ReduceJob job) {
+template <typename P>
+__global__ __launch_bounds__(256) void k_m2l_reduce_levels(ReduceJob<P> job) {
     __shared__ double red[256];
     int li = 0;
     while (li + 1 < job.nlv && (int64_t)blockIdx.x >= job.blk0[li + 1]) li++;
-    const float *part = job.part[li];
+    const P *part = job.part[li];
     const int64_t n = job.n[li];
     const int nsplit = job.nsplit[li], NR = job.nr[li], NE = 256 / NR;
     const int w = threadIdx.x / NE, r = threadIdx.x % NE;
@@ -701,11 +715,6 @@ __global__ __launch_bounds__(256) void k_m2l_reduce_levels(ReduceJob job) {
         for (int k = 1; k < NR; k++) t += red[k * NE + r];
         job.L[li][i] = t;
     }
-}
-
-__global__ void k_f64_to_f32(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) d[i] = (float)s[i];
 }
 
 }  // namespace
@@ -733,16 +742,15 @@ int m2l_row_frags(int n) {
     return best;
 }
 
-// Coarse levels of the split-precision mode (at most 64 cells) run all cells in
-// one column tile over the 316 offsets, one offset per slice.
-bool m2l_all_cells(const ankh_plan_s *pl, int e) {
-    return pl->precision == ANKH_MIXED_BF16X3 && pl->lv[e].ncell <= BN;
-}
+// Coarse levels (at most 64 cells) run all cells in one column tile over the 316 offsets, one
+// offset per slice.
+bool m2l_all_cells(const ankh_plan_s *pl, int e) { return pl->lv[e].ncell <= BN; }
 
 // Columns of the block tile, 32 NB cells.  The split-precision kernel takes 128
 // cells (NB = 4) where a parity class has at least 128 cells and the row tile is
 // at most 160 nodes (taller tiles would not fit two waves per SIMD); everything
-// else takes 64.
+// else takes 64 (128-cell tiles were slower in float32: 459 against 442 us on
+// the finest level of the 288k box).
 int m2l_col_frags(const ankh_plan_s *pl, int e) {
     const int h = pl->lv[e].nside / 2;
     const bool wide = pl->precision == ANKH_MIXED_BF16X3 && !m2l_all_cells(pl, e) && h * h * h >= 128 &&
@@ -750,29 +758,28 @@ int m2l_col_frags(const ankh_plan_s *pl, int e) {
     return wide ? 4 : 2;
 }
 
-// Number of offset slices (split-K).  Split-precision mode: a multiple of 8 (the
-// XCD-aware block order then gives every XCD whole slices), raised until the
-// level launches >= 512 blocks, while the float32 partial tiles stay within
-// 64 MiB and every slice keeps at least one offset.  The float32 / float64
-// kernels: a level with >= 2048 block tiles runs unsplit, else as above with
-// >= 1024 blocks and float64 partials within 32768 cells x 224 values.
+// bytes per partial value: the float32 accumulators of the mixed modes, float64 in FP64
+static size_t m2l_part_elem(const ankh_plan_s *pl) {
+    return pl->precision == ANKH_FP64 ? sizeof(double) : sizeof(float);
+}
+
+// Number of offset slices (split-K).  A multiple of 8 (the XCD-aware block order then gives
+// every XCD whole slices), raised until the level launches >= 512 blocks (split bf16) or
+// >= 1024 (the float32 / float64 kernels), while the level's partial tiles stay within
+// 64 MiB and every slice keeps at least one offset; a level with twice that many block
+// tiles runs unsplit.
 int m2l_splits(const ankh_plan_s *pl, int e) {
+    if (m2l_all_cells(pl, e)) return kNumFar;
     const int h = pl->lv[e].nside / 2;
     const int n = pl->rpad[e];
     const int bm = 32 * m2l_row_frags(n), bn = 32 * m2l_col_frags(pl, e);
     const int64_t tiles = (int64_t)((n + bm - 1) / bm) * ((h * h * h + bn - 1) / bn) * 8;
     const int64_t ncell = pl->lv[e].ncell;
-    if (m2l_all_cells(pl, e)) return kNumFar;
-    const bool bf = pl->precision == ANKH_MIXED_BF16X3;
-    const int64_t want = bf ? 512 : 1024;
+    const int64_t want = pl->precision == ANKH_MIXED_BF16X3 ? 512 : 1024;
     if (tiles >= 2 * want) return 1;
+    const int64_t elem = (int64_t)m2l_part_elem(pl);
     int s = 8;
-    if (bf)
-        while (tiles * s < want && (s + 8) * ncell * n * (int64_t)sizeof(float) <= ((int64_t)64 << 20) &&
-               s + 8 <= kNumIL)
-            s += 8;
-    else
-        while (tiles * s < want && (s + 8) * ncell * n <= (int64_t)32768 * 224 && s + 8 <= kNumIL) s += 8;
+    while (tiles * s < want && (s + 8) * ncell * n * elem <= ((int64_t)64 << 20) && s + 8 <= kNumIL) s += 8;
     return s;
 }
 
@@ -781,15 +788,15 @@ size_t m2l_part_bytes(const ankh_plan_s *pl, int e) {
     const int sp = m2l_splits(pl, e);
     if (sp <= 1) return 0;
     const size_t nv = (size_t)pl->lv[e].ncell * pl->rpad[e];
-    return sp * nv * (pl->precision == ANKH_MIXED_BF16X3 ? sizeof(float) : sizeof(double));
+    return sp * nv * m2l_part_elem(pl);
 }
 
-// Split-precision mode, once per evaluation before the contractions: every
-// level's source multipoles as bf16 hi / lo at d_Mb + mb_off[e] and d_Mb +
-// mb_total + mb_off[e].  The projection of the compressed levels writes theirs;
-// this splits the uncompressed ones (one launch, packed).
+// Mixed modes, once per evaluation before the contractions: every level's source multipoles
+// in the contraction's working precision, at offset mb_off[e] (split bf16: d_Mb hi parts,
+// then the lo parts at + mb_total; float32: d_Mf).  The projection of the compressed levels
+// writes theirs; this converts the uncompressed ones (one launch, packed).
 hipError_t launch_m2l_prepare(ankh_plan_s *pl) {
-    if (pl->precision != ANKH_MIXED_BF16X3 || pl->depth < 1) return hipSuccess;
+    if (pl->precision == ANKH_FP64 || pl->depth < 1) return hipSuccess;
     SplitJob job{};
     int64_t total = 0;
     for (int e = 1; e <= pl->depth; e++) {
@@ -803,8 +810,11 @@ hipError_t launch_m2l_prepare(ankh_plan_s *pl) {
     }
     if (total == 0) return hipSuccess;
     job.total = total;
-    hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, pl->stream, job,
-                       pl->d_Mb, pl->d_Mb + pl->mb_total);
+    const dim3 g((unsigned)((total + 255) / 256));
+    if (pl->precision == ANKH_MIXED_BF16X3)
+        hipLaunchKernelGGL(k_split_bf16, g, dim3(256), 0, pl->stream, job, pl->d_Mb, pl->d_Mb + pl->mb_total);
+    else
+        hipLaunchKernelGGL(k_to_f32_levels, g, dim3(256), 0, pl->stream, job, pl->d_Mf);
     return hipGetLastError();
 }
 
@@ -817,90 +827,53 @@ void launch_rf(ankh_plan_s *pl, int e, dim3 grid, int n, const double *Msrc, dou
     const ankh::Level &lv = pl->lv[e];
     const size_t kper = (size_t)kNumOff * pl->nup * pl->nup;
     const size_t koff = (size_t)(e - 1) * kper;
+    const bool all = m2l_all_cells(pl, e);
+    char *part = reinterpret_cast<char *>(pl->d_m2l_part) + pl->m2l_part_off[e];
     if (pl->precision == ANKH_MIXED_BF16X3) {
         const __bf16 *Mh = pl->d_Mb + pl->mb_off[e], *Ml = pl->d_Mb + pl->mb_total + pl->mb_off[e];
         const size_t kall = (size_t)pl->depth * kper;
-        float *part = reinterpret_cast<float *>(pl->d_m2l_part) + pl->m2l_part_off[e];
-        if (m2l_all_cells(pl, e))
-            hipLaunchKernelGGL(k_m2l_bf16x3_all<RF>, dim3((unsigned)(((n + 32 * RF - 1) / (32 * RF)) * nsplit)),
-                               dim3(NTHR), 0, pl->stream, pl->d_Kb + koff, pl->d_Kb + kall + koff, Mh, Ml, part,
-                               lv.nside, n, nsplit, nval);
+        float *pf = reinterpret_cast<float *>(part);
+        if (all)
+            hipLaunchKernelGGL(k_m2l_bf16x3_all<RF>, grid, dim3(NTHR), 0, pl->stream, pl->d_Kb + koff,
+                               pl->d_Kb + kall + koff, Mh, Ml, pf, lv.nside, n, nsplit, nval);
         else if (m2l_col_frags(pl, e) == 4) {
             if constexpr (RF <= 5)
                 hipLaunchKernelGGL((k_m2l_bf16x3<RF, 4>), grid, dim3(NTHR), 0, pl->stream, pl->d_Kb + koff,
-                                   pl->d_Kb + kall + koff, Mh, Ml, part, Ldst, lv.nside, n, nsplit, nval);
+                                   pl->d_Kb + kall + koff, Mh, Ml, pf, Ldst, lv.nside, n, nsplit, nval);
         } else
             hipLaunchKernelGGL((k_m2l_bf16x3<RF, 2>), grid, dim3(NTHR), 0, pl->stream, pl->d_Kb + koff,
-                               pl->d_Kb + kall + koff, Mh, Ml, part, Ldst, lv.nside, n, nsplit, nval);
+                               pl->d_Kb + kall + koff, Mh, Ml, pf, Ldst, lv.nside, n, nsplit, nval);
+    } else if (pl->precision == ANKH_MIXED) {
+        const float *Mf = pl->d_Mf + pl->mb_off[e];
+        float *pf = reinterpret_cast<float *>(part);
+        if (all)
+            hipLaunchKernelGGL((k_m2l<float, RF, true>), grid, dim3(NTHR), 0, pl->stream, pl->d_Kf + koff, Mf, pf,
+                               Ldst, lv.nside, n, nsplit, nval);
+        else
+            hipLaunchKernelGGL((k_m2l<float, RF, false>), grid, dim3(NTHR), 0, pl->stream, pl->d_Kf + koff, Mf, pf,
+                               Ldst, lv.nside, n, nsplit, nval);
     } else {
-        double *out = nsplit > 1 ? pl->d_m2l_part : Ldst;
-        if (pl->precision == ANKH_MIXED)
-            hipLaunchKernelGGL((k_m2l<float, RF>), grid, dim3(NTHR), 0, pl->stream, pl->d_Kf + koff, pl->d_Mf, out,
-                               lv.nside, n, nsplit, nval);
+        double *pd = reinterpret_cast<double *>(part);
+        if (all)
+            hipLaunchKernelGGL((k_m2l<double, RF, true>), grid, dim3(NTHR), 0, pl->stream, pl->d_K + koff, Msrc,
+                               pd, Ldst, lv.nside, n, nsplit, nval);
         else
-            hipLaunchKernelGGL((k_m2l<double, RF>), grid, dim3(NTHR), 0, pl->stream, pl->d_K + koff, Msrc, out,
-                               lv.nside, n, nsplit, nval);
+            hipLaunchKernelGGL((k_m2l<double, RF, false>), grid, dim3(NTHR), 0, pl->stream, pl->d_K + koff, Msrc,
+                               pd, Ldst, lv.nside, n, nsplit, nval);
     }
 }
-}  // namespace
 
-hipError_t launch_m2l(ankh_plan_s *pl, int e) {
-    const ankh::Level &lv = pl->lv[e];
-    const int h = lv.nside / 2;
-    const int ncls = h * h * h;
-    const int n = pl->rpad[e];
-    const bool comp = n < pl->nup;
-    const int nsplit = m2l_splits(pl, e);
-    const int rf = m2l_all_cells(pl, e) ? 2 : m2l_row_frags(n);
-    const int bm = 32 * rf, bn = 32 * m2l_col_frags(pl, e);
-    dim3 grid((unsigned)(((n + bm - 1) / bm) * ((ncls + bn - 1) / bn) * 8 * nsplit));
-    const int64_t nval = lv.ncell * n;
-    double *L = pl->d_L + lv.cell0 * pl->nup;
-    const double *M = pl->d_M + lv.cell0 * pl->nup;
-    // compressed levels contract in the rank-n basis: M' = M U (projected for all
-    // levels before the first contraction), L = L' U^T (after the last)
-    double *Msrc = comp ? pl->d_Mc + pl->c_off[e] : const_cast<double *>(M);
-    double *Ldst = comp ? pl->d_Lc + pl->c_off[e] : L;
-    // this level's multipoles in the working precision of the float32 contraction
-    // (the split-precision mode splits all levels in launch_m2l_prepare)
-    if (pl->precision == ANKH_MIXED)
-        hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, pl->stream, Msrc,
-                           pl->d_Mf, nval);
-    switch (rf) {
-        case 2: launch_rf<2>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
-        case 3: launch_rf<3>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
-        case 4: launch_rf<4>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
-        case 5: launch_rf<5>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
-        case 6: launch_rf<6>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
-        case 7: launch_rf<7>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
-        default: launch_rf<8>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
-    }
-    // split levels of the float32 / float64 kernels are summed here (they share one
-    // partial buffer); the split-bf16 mode's levels in launch_m2l_finish
-    if (nsplit > 1 && pl->precision != ANKH_MIXED_BF16X3) {
-        const double *pd = pl->d_m2l_part;
-        if (nsplit > 64)
-            hipLaunchKernelGGL((k_m2l_reduce<16, double>), dim3((unsigned)((nval + 15) / 16)), dim3(256), 0,
-                               pl->stream, pd, Ldst, nval, nsplit);
-        else
-            hipLaunchKernelGGL((k_m2l_reduce<4, double>), dim3((unsigned)((nval + 63) / 64)), dim3(256), 0,
-                               pl->stream, pd, Ldst, nval, nsplit);
-    }
-    return hipGetLastError();
-}
-
-// Split-bf16 mode, after the last contraction: the partial tiles of every split
-// level (each level has its own region) summed into its local expansions.
-hipError_t launch_m2l_finish(ankh_plan_s *pl) {
-    if (pl->precision != ANKH_MIXED_BF16X3 || pl->depth < 1) return hipSuccess;
-    ReduceJob job{};
+template <typename P>
+hipError_t reduce_levels(ankh_plan_s *pl) {
+    ReduceJob<P> job{};
     int64_t blocks = 0;
     for (int e = 1; e <= pl->depth; e++) {
         const int nsplit = m2l_splits(pl, e);
         if (nsplit <= 1) continue;
         const ankh::Level &lv = pl->lv[e];
         const int n = pl->rpad[e];
-        job.part[job.nlv] = reinterpret_cast<const float *>(pl->d_m2l_part) + pl->m2l_part_off[e];
+        job.part[job.nlv] = reinterpret_cast<const P *>(reinterpret_cast<const char *>(pl->d_m2l_part) +
+                                                        pl->m2l_part_off[e]);
         job.L[job.nlv] = n < pl->nup ? pl->d_Lc + pl->c_off[e] : pl->d_L + lv.cell0 * pl->nup;
         job.n[job.nlv] = lv.ncell * n;
         job.nsplit[job.nlv] = nsplit;
@@ -911,8 +884,47 @@ hipError_t launch_m2l_finish(ankh_plan_s *pl) {
         job.nlv++;
     }
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_m2l_reduce_levels, dim3((unsigned)blocks), dim3(256), 0, pl->stream, job);
+    hipLaunchKernelGGL(k_m2l_reduce_levels<P>, dim3((unsigned)blocks), dim3(256), 0, pl->stream, job);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_m2l(ankh_plan_s *pl, int e) {
+    const ankh::Level &lv = pl->lv[e];
+    const int h = lv.nside / 2;
+    const int ncls = h * h * h;
+    const int n = pl->rpad[e];
+    const bool comp = n < pl->nup;
+    const bool all = m2l_all_cells(pl, e);
+    const int nsplit = m2l_splits(pl, e);
+    const int rf = all ? 2 : m2l_row_frags(n);   // coarse levels: 64-row tiles, more blocks for the operator stream
+    const int bm = 32 * rf, bn = 32 * m2l_col_frags(pl, e);
+    const int nrt = (n + bm - 1) / bm;
+    const dim3 grid((unsigned)(all ? nrt * nsplit : nrt * ((ncls + bn - 1) / bn) * 8 * nsplit));
+    const int64_t nval = lv.ncell * n;
+    double *L = pl->d_L + lv.cell0 * pl->nup;
+    const double *M = pl->d_M + lv.cell0 * pl->nup;
+    // compressed levels contract in the rank-n basis: M' = M U (projected for all
+    // levels before the first contraction), L = L' U^T (after the last)
+    const double *Msrc = comp ? pl->d_Mc + pl->c_off[e] : M;
+    double *Ldst = comp ? pl->d_Lc + pl->c_off[e] : L;
+    switch (rf) {
+        case 2: launch_rf<2>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
+        case 3: launch_rf<3>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
+        case 4: launch_rf<4>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
+        case 5: launch_rf<5>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
+        case 6: launch_rf<6>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
+        case 7: launch_rf<7>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
+        default: launch_rf<8>(pl, e, grid, n, Msrc, Ldst, nsplit, nval); break;
+    }
+    return hipGetLastError();
+}
+
+// After the last contraction: the partial tiles of every split level (each level has its
+// own region) summed into its local expansions, one launch.
+hipError_t launch_m2l_finish(ankh_plan_s *pl) {
+    if (pl->depth < 1) return hipSuccess;
+    return pl->precision == ANKH_FP64 ? reduce_levels<double>(pl) : reduce_levels<float>(pl);
 }
 
 }  // namespace ankh

@@ -611,25 +611,20 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
                 dalloc(pl, &pl->d_Mc, coff);
                 dalloc(pl, &pl->d_Lc, coff);
             }
-            // M2L scratch: split-K partials (the largest level's in float64, reused level by level;
-            // in split bf16 every split level's float32 tiles side by side, summed in one launch),
-            // and the multipoles in the working precision (one level in float32; all levels in
-            // split bf16)
-            size_t part = 0, mlev = 0;
+            // M2L scratch: the split-K partial tiles of every split level side by side (level e at
+            // byte m2l_part_off[e], 256-byte aligned; float64 in FP64, the float32 accumulators in the
+            // mixed modes), summed in one launch after the last contraction; and in the mixed modes
+            // every level's multipoles in the contraction's working precision (level e at mb_off[e])
+            size_t part = 0;
             for (int e = 1; e <= pl->depth; e++) {
                 const size_t nv = (size_t)pl->lv[e].ncell * pl->rpad[e];
-                if (bf) {   // every split level its own float32 region (256-byte aligned)
-                    pl->m2l_part_off[e] = part / sizeof(float);
-                    part += (m2l_part_bytes(pl, e) + 255) / 256 * 256;
-                } else {
-                    part = std::max(part, m2l_part_bytes(pl, e));
-                }
-                mlev = std::max(mlev, nv);
+                pl->m2l_part_off[e] = part;
+                part += (m2l_part_bytes(pl, e) + 255) / 256 * 256;
                 pl->mb_off[e] = pl->mb_total;
                 pl->mb_total += nv;
             }
             if (part) dalloc(pl, &pl->d_m2l_part, (part + sizeof(double) - 1) / sizeof(double));
-            if (precision == ANKH_MIXED) dalloc(pl, &pl->d_Mf, mlev);
+            if (precision == ANKH_MIXED) dalloc(pl, &pl->d_Mf, pl->mb_total);
             if (bf) dalloc(pl, &pl->d_Mb, 2 * pl->mb_total);
         }
         if (fft) {
