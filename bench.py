@@ -70,7 +70,7 @@ PEAK = {  # MI355X, TFLOP/s (hbm: GB/s)
 PREC_NAME = {0: "f64", 1: "f32", 2: "bf16x3"}
 
 
-def counter_traffic(counters=P2P_COUNTERS, source=P2P_SOURCE, leaves=None):
+def counter_traffic(counters=P2P_COUNTERS, source=P2P_SOURCE, leaves=None, suffix=""):
     """Calibrated HBM bytes per launch of a kernel (or stage) from its committed counter summary, or None
     when the summary is missing, the kernel source (one file, or several hashed in order as one stream)
     has changed since, or it was taken on another leaf grid."""
@@ -91,7 +91,7 @@ def counter_traffic(counters=P2P_COUNTERS, source=P2P_SOURCE, leaves=None):
             return None
         if leaves is not None and rec.get("leaves_per_axis") != str(leaves):
             return None
-        return float(rec["fetch_bytes_per_launch"]) + float(rec["write_bytes_per_launch"])
+        return float(rec["fetch_bytes_per_launch" + suffix]) + float(rec["write_bytes_per_launch" + suffix])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -182,8 +182,9 @@ def m2l_roofline(st, breakdown, mode):
     t = st["stage_ms"]["m2l"]
     tf = flops / (t * 1e-3) / 1e12
     alone = flops / (breakdown["m2l"] * 1e-3) / 1e12
-    traffic = (counter_traffic(M2L_COUNTERS, M2L_SOURCES, st.get("leaves_per_axis"))
-               if mode == "mixed_bf16x3" else None)
+    traffic = (counter_traffic(M2L_COUNTERS, M2L_SOURCES, st.get("leaves_per_axis"),
+                               "" if mode == "mixed_bf16x3" else "_f32")
+               if mode in ("mixed_bf16x3", "mixed") else None)
     rec = {"kernel": "m2l", "bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
            "traffic": traffic, "flop_per_launch": flops, "avg_launch_ms": t, "alone_avg_launch_ms": breakdown["m2l"],
            "alone_achieved": alone, "alone_frac": alone / peak, "ranks": st.get("m2l_rank"),
@@ -192,8 +193,9 @@ def m2l_roofline(st, breakdown, mode):
                    "4 * n_u * r_e for the basis change"}
     if mode == "mixed_bf16x3":
         rec["issued_frac"] = 3 * tf / peak
-        rec["note"] += ("; the split-precision product issues three bf16 products per algorithmic one (issued_frac)"
-                        "; traffic: the counters' HBM bytes summed over the stage's launches")
+        rec["note"] += "; the split-precision product issues three bf16 products per algorithmic one (issued_frac)"
+    if mode in ("mixed_bf16x3", "mixed"):
+        rec["note"] += "; traffic: the counters' HBM bytes summed over the stage's launches"
     return rec
 
 
