@@ -175,72 +175,65 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
     const int row0 = rt * BM, col0 = ct * BN;
     const int o_begin = nil * split / nsplit, o_end = nil * (split + 1) / nsplit;
 
-    // A loader: pairs of adjacent rows; LA pairs per thread
+    // Loaders, unconditional and addressed by 32-bit element offsets (a few instructions per step).
+    // A: pairs of adjacent rows, LA pairs per thread; the slots past the tile's NPA pairs repeat pair
+    // p - NPA (same data, same LDS place), rows past n_up (a padded row tile) read the last pair of rows,
+    // whose products are never written out.
     constexpr int NPA = BK * BM / 2, LA = (NPA + NTHR - 1) / NTHR;
-    // B loader: 16 bytes (PB contraction values) of one cell's multipoles per thread
+    static_assert(LA * NTHR <= 2 * NPA, "a repeated slot maps onto a real pair");
+    int a_off[LA], a_k[LA], a_r[LA];
+#pragma unroll
+    for (int u = 0; u < LA; u++) {
+        const int p0 = tid + NTHR * u, p = p0 < NPA ? p0 : p0 - NPA;
+        a_k[u] = p / (BM / 2), a_r[u] = (p % (BM / 2)) * 2;
+        a_off[u] = a_k[u] * nup + min(row0 + a_r[u], nup - 2);
+    }
+    // B: 16 bytes (PB contraction values) of one cell's multipoles per thread; a cell past the level's
+    // columns reads the last one (its products are never written out)
     constexpr int PB = 16 / (int)sizeof(T);
     static_assert(BK * BN == PB * NTHR, "B tile must be one 16-byte load per thread");
     const int b_col = tid / (BK / PB), b_k = (tid % (BK / PB)) * PB;
-    const int tcell = col0 + b_col;
-    const bool b_ok = tcell < ncol;
-    int gx = 0, gy = 0, gz = 0;
-    if (b_ok) {
-        if constexpr (ALL) {
-            gx = tcell / (nside * nside), gy = (tcell / nside) % nside, gz = tcell % nside;
-        } else {
-            gx = 2 * (tcell / (h * h)) + px;
-            gy = 2 * ((tcell / h) % h) + py;
-            gz = 2 * (tcell % h) + pz;
-        }
+    const int tcell = min(col0 + b_col, ncol - 1);
+    int gx, gy, gz;
+    if constexpr (ALL) {
+        gx = tcell / (nside * nside), gy = (tcell / nside) % nside, gz = tcell % nside;
+    } else {
+        gx = 2 * (tcell / (h * h)) + px;
+        gy = 2 * ((tcell / h) % h) + py;
+        gz = 2 * (tcell % h) + pz;
     }
+    const int mask = nside - 1;   // the level's side is a power of two
 
     const int nk = nup / BK;
     const int niter = (o_end - o_begin) * nk;
     T ra[LA][2], rb[PB];
-    auto load = [&](int it) {
-        const int di = il[o_begin + it / nk], k0 = (it % nk) * BK;
-        const T *Kd = K + (size_t)di * nup * nup + (size_t)k0 * nup + row0;
+    // step (o, kb): offset il[o], contraction block kb
+    auto load = [&](int o, int kb) {
+        const int di = il[o], k0 = kb * BK;
+        const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
+        const T *Kd = K + ((size_t)di * nup + k0) * nup;
 #pragma unroll
         for (int u = 0; u < LA; u++) {
-            const int p = tid + NTHR * u;
-            const int k = p / (BM / 2), r = (p % (BM / 2)) * 2;
-            if (p < NPA && row0 + r < nup) {
-                const T *src = Kd + (size_t)k * nup + r;
-                ra[u][0] = src[0];
-                ra[u][1] = src[1];
-            } else {
-                ra[u][0] = (T)0;
-                ra[u][1] = (T)0;
-            }
+            ra[u][0] = Kd[a_off[u]];
+            ra[u][1] = Kd[a_off[u] + 1];
         }
-        bool use = b_ok;
-        if constexpr (ALL) {
-            const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
-            use = use && in_list_1d(dx, gx & 1) && in_list_1d(dy, gy & 1) && in_list_1d(dz, gz & 1);
-        }
-        if (use) {
-            const T *src = M + source_cell(gx, gy, gz, di, nside) * nup + k0 + b_k;
-            const uint4 v = *reinterpret_cast<const uint4 *>(src);
-            const T *pv = reinterpret_cast<const T *>(&v);
+        const int cell = (((gx + dx) & mask) * nside + ((gy + dy) & mask)) * nside + ((gz + dz) & mask);
+        const uint4 v = *reinterpret_cast<const uint4 *>(M + (cell * nup + k0 + b_k));
+        const T *pv = reinterpret_cast<const T *>(&v);
+        bool use = true;
+        if constexpr (ALL)
+            use = in_list_1d(dx, gx & 1) && in_list_1d(dy, gy & 1) && in_list_1d(dz, gz & 1);
 #pragma unroll
-            for (int u = 0; u < PB; u++) rb[u] = pv[u];
-        } else {
-#pragma unroll
-            for (int u = 0; u < PB; u++) rb[u] = (T)0;
-        }
+        for (int q = 0; q < PB; q++) rb[q] = use ? pv[q] : (T)0;
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < LA; u++) {
-            const int p = tid + NTHR * u;
-            if (p < NPA) {
-                const int k = p / (BM / 2), r = (p % (BM / 2)) * 2;
-                As[buf][k][r] = ra[u][0];
-                As[buf][k][r + 1] = ra[u][1];
-            }
+            As[buf][a_k[u]][a_r[u]] = ra[u][0];
+            As[buf][a_k[u]][a_r[u] + 1] = ra[u][1];
         }
 #pragma unroll
-        for (int u = 0; u < PB; u++) Bs[buf][b_k + u][b_col] = rb[u];
+        for (int q = 0; q < PB; q++) Bs[buf][b_k + q][b_col] = rb[q];
     };
 
     Acc acc[RF][2];
@@ -250,14 +243,19 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
         for (int j = 0; j < 2; j++) acc[i][j] = Acc{0, 0, 0, 0};
 
     if (niter > 0) {
-        load(0);
+        load(o_begin, 0);
         store(0);
     }
     __syncthreads();
     const int lr = lane & 15, lk = lane >> 4;
+    int on = o_begin, kn = 0;   // the step loaded next
     for (int it = 0; it < niter; it++) {
         const int cur = it & 1;
-        if (it + 1 < niter) load(it + 1);
+        if (++kn == nk) {
+            kn = 0;
+            on++;
+        }
+        if (it + 1 < niter) load(on, kn);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             T av[RF], bv[2];
