@@ -173,7 +173,8 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
     }
     const int px = cls >> 2, py = (cls >> 1) & 1, pz = cls & 1;
     const int row0 = rt * BM, col0 = ct * BN;
-    const int o_begin = nil * split / nsplit, o_end = nil * (split + 1) / nsplit;
+    // this block's run of the (offset, contraction block) steps: slice `split` of the nil x nk steps
+    // (a slice may begin and end inside an offset's blocks)
 
     // Loaders, unconditional and addressed by 32-bit element offsets (a few instructions per step).
     // A: pairs of adjacent rows, LA pairs per thread; the slots past the tile's NPA pairs repeat pair
@@ -205,7 +206,8 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
     const int mask = nside - 1;   // the level's side is a power of two
 
     const int nk = nup / BK;
-    const int niter = (o_end - o_begin) * nk;
+    const int it0 = (int)((int64_t)nil * nk * split / nsplit), it1 = (int)((int64_t)nil * nk * (split + 1) / nsplit);
+    const int niter = it1 - it0;
     T ra[LA][2], rb[PB];
     // step (o, kb): offset il[o], contraction block kb
     auto load = [&](int o, int kb) {
@@ -242,13 +244,13 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ K, const T *_
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = Acc{0, 0, 0, 0};
 
+    int on = it0 / nk, kn = it0 % nk;   // the step loaded next
     if (niter > 0) {
-        load(o_begin, 0);
+        load(on, kn);
         store(0);
     }
     __syncthreads();
     const int lr = lane & 15, lk = lane >> 4;
-    int on = o_begin, kn = 0;   // the step loaded next
     for (int it = 0; it < niter; it++) {
         const int cur = it & 1;
         if (++kn == nk) {
@@ -740,8 +742,7 @@ int m2l_row_frags(int n) {
     return best;
 }
 
-// Coarse levels (at most 64 cells) run all cells in one column tile over the 316 offsets, one
-// offset per slice.
+// Coarse levels (at most 64 cells) run all cells in one column tile over the 316 offsets.
 bool m2l_all_cells(const ankh_plan_s *pl, int e) { return pl->lv[e].ncell <= BN; }
 
 // Columns of the block tile, 32 NB cells.  The split-precision kernel takes 128
@@ -767,7 +768,10 @@ static size_t m2l_part_elem(const ankh_plan_s *pl) {
 // 64 MiB and every slice keeps at least one offset; a level with twice that many block
 // tiles runs unsplit.
 int m2l_splits(const ankh_plan_s *pl, int e) {
-    if (m2l_all_cells(pl, e)) return kNumFar;
+    // coarse levels: one offset per slice; in float32 half an offset's contraction blocks per slice
+    // (its 16-wide blocks make twice as many steps as split bf16's; float64 pays more for the
+    // doubled float64 partial tiles than it gains)
+    if (m2l_all_cells(pl, e)) return pl->precision == ANKH_MIXED ? 2 * kNumFar : kNumFar;
     const int h = pl->lv[e].nside / 2;
     const int n = pl->rpad[e];
     const int bm = 32 * m2l_row_frags(n), bn = 32 * m2l_col_frags(pl, e);
