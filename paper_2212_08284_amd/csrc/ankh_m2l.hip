@@ -768,10 +768,9 @@ static size_t m2l_part_elem(const ankh_plan_s *pl) {
 // 64 MiB and every slice keeps at least one offset; a level with twice that many block
 // tiles runs unsplit.
 int m2l_splits(const ankh_plan_s *pl, int e) {
-    // coarse levels: one offset per slice; in float32 half an offset's contraction blocks per slice
-    // (its 16-wide blocks make twice as many steps as split bf16's; float64 pays more for the
-    // doubled float64 partial tiles than it gains)
-    if (m2l_all_cells(pl, e)) return pl->precision == ANKH_MIXED ? 2 * kNumFar : kNumFar;
+    // coarse levels: one offset per slice (two per offset in float32, 632 slices, gained nothing in
+    // the contraction and cost 5 us in the reduction)
+    if (m2l_all_cells(pl, e)) return kNumFar;
     const int h = pl->lv[e].nside / 2;
     const int n = pl->rpad[e];
     const int bm = 32 * m2l_row_frags(n), bn = 32 * m2l_col_frags(pl, e);
