@@ -16,11 +16,13 @@
 // n_u of them for the usual orders, so the gathered multipoles are read once
 // per tile) x 64 cells (128 on the finest levels in split precision) and a
 // slice of the 189 offsets; K_d and the gathered multipoles stream through
-// double-buffered LDS.  Slices of the offset list (split-K) give the launch
-// enough blocks to fill the chip at every level; their partial tiles are
-// summed in a fixed order (k_m2l_reduce, or k_m2l_reduce_levels for all split
-// levels of the split-precision mode at once), so results do not depend on
-// scheduling.
+// double-buffered LDS.  A coarse level of at most one tile of cells runs as one
+// all-cell tile over the union of the eight parity classes' offsets (316 of
+// them), multipoles of cells outside a class's list read as zero.  Slices of
+// the offset list (split-K) give the launch enough blocks to fill the chip at
+// every level; their partial tiles are summed in a fixed order by one
+// k_m2l_reduce_levels launch for all split levels, so results do not depend
+// on scheduling.
 #include <algorithm>
 #include <cmath>
 
@@ -352,7 +354,7 @@ __device__ inline void m2l_write_tile(const f32x4 (&acc)[RF][NB], float *part, d
 // are issued as three sweeps over the RF x NB accumulators (each accumulator
 // still sums lo*hi, hi*lo, hi*hi in that order), so consecutive matrix-core
 // instructions never wait on each other's result.  A split-K block writes its
-// float32 tile to its slice of `part` (summed in float64 by k_m2l_reduce); an
+// float32 tile to its slice of `part` (summed by k_m2l_reduce_levels); an
 // unsplit level writes float64 to `dst`.
 template <int RF, int NB>
 __global__ __launch_bounds__(256) void k_m2l_bf16x3(const __bf16 *__restrict__ Kh, const __bf16 *__restrict__ Kl,
