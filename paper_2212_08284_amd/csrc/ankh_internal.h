@@ -193,7 +193,10 @@ hipError_t launch_l2p_moments(ankh_plan_s *pl, int ord, const double *near, doub
 // forces == nullptr with dEdmu != nullptr is a fields-only evaluation
 ankh_status evaluate(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th,
                      double *energy, double *forces, double *dEdmu);
-hipError_t launch_build_m2l(ankh_plan_s *pl, int e, double *K);
+// the M2L stack of level e into K (kNumOff x nup x nup), from the operators of the 16 classes of the
+// cube's symmetries built into reps (m2l_reps_elems doubles)
+size_t m2l_reps_elems(const ankh_plan_s *pl);
+hipError_t launch_build_m2l(ankh_plan_s *pl, int e, double *K, double *reps);
 hipError_t launch_build_cper(ankh_plan_s *pl);
 hipError_t launch_convert_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 // ANKH-FFT (ankh_fft.hip)

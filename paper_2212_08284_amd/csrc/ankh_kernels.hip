@@ -6,6 +6,7 @@
 // stored cell-major with a row stride nup >= L^3 (a multiple of 64, zero padded).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "ankh_internal.h"
 
@@ -757,29 +758,102 @@ __global__ __launch_bounds__(kRedBlocks) void k_reduce2(const double *part, doub
 
 
 // ---- plan-time builders ------------------------------------------------------
-// K_d[k][l] = H(w (1/2 (r_k - r_l) - d)) stored as [d][l][k]; zero for the
-// 27 adjacent offsets and for padded rows / columns.
-__global__ void k_build_m2l(double *K, const double *tab, int L, int nu, int nup, double w, double xi) {
-    const int64_t tot = (int64_t)kNumOff * nup * nup;
-    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// K_d[k][l] = H(w (1/2 (r_k - r_l) - d)) stored as [d][l][k]; zero for the 27 adjacent offsets and
+// for padded rows / columns.
+//
+// Only one operator per class of the cube's symmetries is evaluated, as the paper's precomputation
+// of its M2L approximations does (ANKH-FMM, mutual interactions).  A symmetry g of the cube permutes
+// the axes and reflects some of them, (g v)_c = s_c v_{p_c}; it maps the 316 far offsets onto
+// themselves in 16 classes, one representative r per class with 3 >= r_x >= r_y >= r_z >= 0 and
+// r_x >= 2.  The Chebyshev nodes are symmetric about the cell centre (r_{L-1-i} = -r_i), so for
+// d = g r the node pair (k, l) sees the distance of the representative's pair (k~, l~) with
+// k~_{p_c} = k_c where s_c = +1 and L-1-k_c where s_c = -1; H depends on the distance only, hence
+// K_d[k][l] = K_r[k~][l~].  The representatives are built by the formula above, then every
+// offset's operator is read from its representative with the node indices moved.
+constexpr int kNumCls = 16;
+struct SymTable {
+    int cls[kNumOff];            // class of each offset slot, -1 for the 27 adjacent offsets
+    unsigned char perm[kNumOff]; // p_0 | p_1 << 2 | p_2 << 4
+    unsigned char refl[kNumOff]; // bit c set: s_c = -1
+    signed char rep[kNumCls][3]; // the representatives
+};
+
+SymTable make_sym_table() {
+    SymTable T{};
+    int nc = 0;
+    for (int x = 2; x <= 3; x++)
+        for (int y = 0; y <= x; y++)
+            for (int z = 0; z <= y; z++) {
+                T.rep[nc][0] = (signed char)x;
+                T.rep[nc][1] = (signed char)y;
+                T.rep[nc][2] = (signed char)z;
+                nc++;
+            }
+    for (int di = 0; di < kNumOff; di++) {
+        const int d[3] = {di / 49 - 3, (di / 7) % 7 - 3, di % 7 - 3};
+        const int a[3] = {std::abs(d[0]), std::abs(d[1]), std::abs(d[2])};
+        T.cls[di] = -1;
+        if (std::max(a[0], std::max(a[1], a[2])) < 2) continue;
+        // the axes ordered by |d_c|, largest first (ties in axis order): axis c goes to position p_c
+        int ord[3] = {0, 1, 2};
+        std::stable_sort(ord, ord + 3, [&](int u, int v) { return a[u] > a[v]; });
+        int p[3];
+        for (int j = 0; j < 3; j++) p[ord[j]] = j;
+        const int r[3] = {a[ord[0]], a[ord[1]], a[ord[2]]};
+        for (int c = 0; c < kNumCls; c++)
+            if (T.rep[c][0] == r[0] && T.rep[c][1] == r[1] && T.rep[c][2] == r[2]) T.cls[di] = c;
+        T.perm[di] = (unsigned char)(p[0] | p[1] << 2 | p[2] << 4);
+        T.refl[di] = (unsigned char)((d[0] < 0) | (d[1] < 0) << 1 | (d[2] < 0) << 2);
+    }
+    return T;
+}
+
+// the class representatives, R[c][l][k] (kNumCls x nup x nup)
+__global__ void k_build_m2l_reps(double *R, const double *tab, int L, int nu, int nup, double w, double xi,
+                                 SymTable T) {
+    const int64_t tot = (int64_t)kNumCls * nup * nup;
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx >= tot) return;
     const int k = (int)(idx % nup);
     const int l = (int)((idx / nup) % nup);
-    const int di = (int)(idx / ((int64_t)nup * nup));
-    const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
-    const int am = max(abs(dx), max(abs(dy), abs(dz)));
+    const int c = (int)(idx / ((int64_t)nup * nup));
     double v = 0;
-    if (am >= 2 && k < nu && l < nu) {
+    if (k < nu && l < nu) {
         const int ki[3] = {k / (L * L), (k / L) % L, k % L};
         const int li[3] = {l / (L * L), (l / L) % L, l % L};
-        const int dd[3] = {dx, dy, dz};
         double r2 = 0;
-        for (int c = 0; c < 3; c++) {
-            const double u = w * (0.5 * (tab[ki[c]] - tab[li[c]]) - dd[c]);
+        for (int a = 0; a < 3; a++) {
+            const double u = w * (0.5 * (tab[ki[a]] - tab[li[a]]) - T.rep[c][a]);
             r2 += u * u;
         }
         const double r = sqrt(r2);
         v = erfc(xi * r) / r;
+    }
+    R[idx] = v;
+}
+
+// every offset's operator from its class representative
+__global__ void k_expand_m2l(double *K, const double *R, int L, int nu, int nup, SymTable T) {
+    const int64_t tot = (int64_t)kNumOff * nup * nup;
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= tot) return;
+    const int k = (int)(idx % nup);
+    const int l = (int)((idx / nup) % nup);
+    const int di = (int)(idx / ((int64_t)nup * nup));
+    const int c = T.cls[di];
+    double v = 0;
+    if (c >= 0 && k < nu && l < nu) {
+        const int ki[3] = {k / (L * L), (k / L) % L, k % L};
+        const int li[3] = {l / (L * L), (l / L) % L, l % L};
+        int kt[3], lt[3];
+        for (int a = 0; a < 3; a++) {
+            const int pa = (T.perm[di] >> (2 * a)) & 3;
+            const bool m = (T.refl[di] >> a) & 1;
+            kt[pa] = m ? L - 1 - ki[a] : ki[a];
+            lt[pa] = m ? L - 1 - li[a] : li[a];
+        }
+        const int kk = (kt[0] * L + kt[1]) * L + kt[2], ll = (lt[0] * L + lt[1]) * L + lt[2];
+        v = R[((int64_t)c * nup + ll) * nup + kk];
     }
     K[idx] = v;
 }
@@ -1069,10 +1143,15 @@ hipError_t launch_reduce(ankh_plan_s *pl, double *energy_out) {
     return hipGetLastError();
 }
 
-hipError_t launch_build_m2l(ankh_plan_s *pl, int e, double *K) {
-    const int64_t tot = (int64_t)kNumOff * pl->nup * pl->nup;
-    hipLaunchKernelGGL(k_build_m2l, dim3(nblk(tot, 256)), dim3(256), 0, pl->stream, K, pl->d_tab, pl->order, pl->nu,
-                       pl->nup, pl->lv[e].width, pl->xi);
+size_t m2l_reps_elems(const ankh_plan_s *pl) { return (size_t)kNumCls * pl->nup * pl->nup; }
+
+hipError_t launch_build_m2l(ankh_plan_s *pl, int e, double *K, double *reps) {
+    static const SymTable T = make_sym_table();
+    const int64_t nr = (int64_t)m2l_reps_elems(pl), tot = (int64_t)kNumOff * pl->nup * pl->nup;
+    hipLaunchKernelGGL(k_build_m2l_reps, dim3(nblk(nr, 256)), dim3(256), 0, pl->stream, reps, pl->d_tab, pl->order,
+                       pl->nu, pl->nup, pl->lv[e].width, pl->xi, T);
+    hipLaunchKernelGGL(k_expand_m2l, dim3(nblk(tot, 256)), dim3(256), 0, pl->stream, K, reps, pl->order, pl->nu,
+                       pl->nup, T);
     return hipGetLastError();
 }
 

@@ -569,17 +569,20 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
                 dalloc(pl, &pl->d_U, (size_t)pl->depth * pl->nup * pl->nup);
                 for (int e = 1; e <= pl->depth; e++) pl->u_off[e] = (size_t)(e - 1) * pl->nup * pl->nup;
             }
-            // scratch: the full float64 stack of a level, and room for the compression's
-            // intermediate products or the compressed float64 stack
-            double *tmp = nullptr, *work = nullptr, *kc = nullptr;
+            // scratch: the operators of the 16 symmetry classes and the full float64 stack of a level,
+            // and room for the compression's intermediate products or the compressed float64 stack
+            double *tmp = nullptr, *work = nullptr, *kc = nullptr, *reps = nullptr;
             const size_t ntmp = 1 + (compress ? 1 : 0) + (compress && precision != ANKH_FP64 ? 1 : 0);
-            if (pl->bytes_limit && pl->bytes + ntmp * kper * sizeof(double) > pl->bytes_limit) throw std::bad_alloc();
+            const size_t nreps = m2l_reps_elems(pl);
+            if (pl->bytes_limit && pl->bytes + (ntmp * kper + nreps) * sizeof(double) > pl->bytes_limit)
+                throw std::bad_alloc();
             ck(hipMalloc((void **)&tmp, kper * sizeof(double)));
+            ck(hipMalloc((void **)&reps, nreps * sizeof(double)));
             if (compress) ck(hipMalloc((void **)&work, kper * sizeof(double)));
             if (compress && precision != ANKH_FP64) ck(hipMalloc((void **)&kc, kper * sizeof(double)));
             for (int e = 1; e <= pl->depth; e++) {
                 const size_t slot = (size_t)(e - 1) * kper;
-                ck(launch_build_m2l(pl, e, tmp));
+                ck(launch_build_m2l(pl, e, tmp, reps));
                 const double *full = tmp;
                 if (compress) {
                     double *dst = precision == ANKH_FP64 ? pl->d_K + slot : kc;
@@ -599,6 +602,7 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
                 ck(hipStreamSynchronize(pl->stream));
             }
             ck(hipFree(tmp));
+            ck(hipFree(reps));
             if (work) ck(hipFree(work));
             if (kc) ck(hipFree(kc));
             // compressed multipoles / locals of the compressed levels

@@ -8,6 +8,8 @@ facts fixed by the mathematics, not by the transcription itself:
   sum(q x x^T + mu x^T + x mu^T + 2 Theta);
 * M2M preserves those moments from children to parent;
 * the far-image root operator equals a direct image sum of the kernel;
+* the 316 M2L operators of a level are those of 16 classes of the cube's
+  symmetries with the node indices moved;
 * forces and fields are the exact gradient of the approximate energy
   (central finite differences);
 * the approximation converges geometrically in L to the classical-Ewald
@@ -188,6 +190,42 @@ def test_m2l_projector_pins():
     # K_-d = K_d^T: the projected stack of transposes loses the same
     At = np.hstack([R.m2l_matrix(d, w, L, xi).T for d in offs])
     assert abs(np.linalg.norm(At - P @ At, 2) - s[r]) <= 1e-8 * s[0]
+
+
+def test_m2l_cube_symmetry_classes():
+    """The library evaluates one M2L operator per class of the cube's 48 symmetries and moves the node
+    indices for the rest.  Pinned here on the oracle's operators: the 316 far offsets fall into 16
+    classes (representatives 3 >= r_x >= r_y >= r_z >= 0, r_x >= 2, each class one orbit of the 48
+    axis permutations with reflections); for d = g r, (g v)_c = s_c v_{p_c}, node k maps to k~ with
+    k~_{p_c} = k_c (s_c = +1) or L-1-k_c (s_c = -1), and K_d[k, l] = K_r[k~, l~]."""
+    L, w, xi = 4, 0.7, 1.3
+    offs = R.interaction_offsets()
+    reps = sorted({tuple(sorted((abs(c) for c in d), reverse=True)) for d in offs})
+    assert len(offs) == 316 and len(reps) == 16
+    assert all(r[0] >= 2 and r[0] >= r[1] >= r[2] >= 0 for r in reps)
+    group = [(perm, sg) for perm in itertools.permutations(range(3))
+             for sg in itertools.product((1, -1), repeat=3)]
+    assert len(group) == 48
+    for r in reps:   # each class is the orbit of its representative
+        orbit = {tuple(sg[c] * r[perm[c]] for c in range(3)) for perm, sg in group}
+        assert orbit == {d for d in offs if tuple(sorted((abs(c) for c in d), reverse=True)) == r}
+    Kr = {r: R.m2l_matrix(r, w, L, xi) for r in reps}
+    idx = np.array(list(itertools.product(range(L), repeat=3)))   # node k -> (k_x, k_y, k_z)
+    worst = 0.0
+    for d in offs:
+        a = [abs(c) for c in d]
+        order = sorted(range(3), key=lambda c: -a[c])      # axes by |d_c|, largest first (stable)
+        p = [0] * 3
+        for j, c in enumerate(order):
+            p[c] = j
+        r = tuple(a[c] for c in order)
+        moved = np.empty_like(idx)
+        for c in range(3):
+            moved[:, p[c]] = L - 1 - idx[:, c] if d[c] < 0 else idx[:, c]
+        kt = (moved[:, 0] * L + moved[:, 1]) * L + moved[:, 2]
+        Kd = R.m2l_matrix(d, w, L, xi)
+        worst = max(worst, np.max(np.abs(Kd - Kr[r][np.ix_(kt, kt)])) / np.max(np.abs(Kd)))
+    assert worst < 1e-14
 
 
 @pytest.mark.parametrize("L,Le", [(6, 4), (5, 5), (4, 6)])
