@@ -83,7 +83,9 @@ typedef enum {
                                reduction in float64 */
     ANKH_MIXED_BF16X3 = 2   /* as ANKH_MIXED, with the far-field contraction on the bf16
                                matrix cores in split precision (hi*hi + hi*lo + lo*hi,
-                               float32 accumulation) */
+                               float32 accumulation).  This applies to the ANKH-FMM M2L; the
+                               ANKH-FFT transforms have no matrix-core form, so with that far
+                               field both mixed modes run the same float32 path */
 } ankh_precision;
 
 /* Optional overrides of the planner's choices: depth < 0 and any other field <= 0 mean "auto". */
