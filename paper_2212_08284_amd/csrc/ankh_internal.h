@@ -82,7 +82,8 @@ struct ankh_plan_s {
     double *d_rootL = nullptr;    // depth >= 1, else the level-0 rows of d_M / d_L
     bool root_owned = false;
     int32_t *d_leaf = nullptr;    // leaf id per input atom
-    int32_t *d_count = nullptr;   // atoms per leaf
+    int32_t *d_count = nullptr;   // atoms per leaf (zero between evaluations: the scan clears it)
+    bool count_dirty = true;      // d_count must be cleared before the next binning
     int32_t *d_offs = nullptr;    // CSR offsets [nleaf + 1]
     int32_t *d_rank = nullptr;    // arrival rank of each input atom in its leaf [n]
     int32_t *d_perm = nullptr;    // leaf-order slot -> input atom

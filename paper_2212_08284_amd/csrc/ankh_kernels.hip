@@ -94,8 +94,9 @@ __global__ __launch_bounds__(256) void k_bin(int64_t n, const double *pos, const
 // exclusive scan of the leaf counts in one block (offs[m] = total; totals fit int32, as offs does), in
 // chunks of 8192 counts: a coalesced load into LDS (eight per thread, all in flight), each thread's eight
 // consecutive counts summed, the sums scanned within each wave by shuffles and across the 16 waves by the
-// first wave, the offsets written back through LDS (coalesced), the chunk total carried to the next
-__global__ __launch_bounds__(1024) void k_scan(const int32_t *count, int32_t *offs, int64_t m) {
+// first wave, the offsets written back through LDS (coalesced), the chunk total carried to the next.
+// The counts are set back to zero once read, ready for the next binning.
+__global__ __launch_bounds__(1024) void k_scan(int32_t *count, int32_t *offs, int64_t m) {
     constexpr int T = 1024, C = 8 * T;
     __shared__ int buf[C];
     __shared__ int wsum[16];
@@ -106,6 +107,9 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *count, int32_t *of
         int v[8];
 #pragma unroll
         for (int u = 0; u < 8; u++) v[u] = t + u * T < cn ? count[c0 + t + u * T] : 0;
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            if (t + u * T < cn) count[c0 + t + u * T] = 0;
 #pragma unroll
         for (int u = 0; u < 8; u++) buf[t + u * T] = v[u];
         __syncthreads();
@@ -180,58 +184,62 @@ __global__ __launch_bounds__(256) void k_segsort(const int32_t *offs, const int3
     }
 }
 
-// leaf-order particle arrays: local coordinates (relative to the leaf centre)
-__global__ void k_gather(int64_t n, const int32_t *perm, const int32_t *leaf, const double *pos,
-                         const double *q, const double *mu, const double *th, const double *om, double rB,
-                         double edge, double w, int nside, Particles P, int planned_order, int mixed,
-                         int32_t *err) {
-    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// leaf-order particle arrays: local coordinates (relative to the leaf centre).  Every input of an atom
+// is loaded before the first store (the inputs are read-only and do not alias the outputs), so a
+// thread waits for one round trip of its scattered reads instead of one per moment.  The leaf
+// coordinates are recomputed from the positions exactly as the binning computed them.
+template <int ORD, bool MIXED>
+__global__ __launch_bounds__(256) void k_gather(int64_t n, const int32_t *__restrict__ perm,
+                                                const double *__restrict__ pos, const double *__restrict__ q,
+                                                const double *__restrict__ mu, const double *__restrict__ th,
+                                                const double *__restrict__ om, double rB, double edge, double w,
+                                                int nside, Particles P, int32_t *err) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
-    const int i = perm[s];
-    const int id = leaf[i];
-    const int ix[3] = {id / (nside * nside), (id / nside) % nside, id % nside};
+    const int64_t i = perm[s];
+    double p[3], m[3], t[6], o[10];
+    for (int d = 0; d < 3; d++) p[d] = pos[3 * i + d];
+    const double qi = q[i];
+    if constexpr (ORD >= 1)
+        for (int d = 0; d < 3; d++) m[d] = mu ? mu[3 * i + d] : 0.0;
+    if constexpr (ORD >= 2)
+        for (int d = 0; d < 6; d++) t[d] = th ? th[6 * i + d] : 0.0;
+    if constexpr (ORD >= 3)
+        for (int d = 0; d < 10; d++) o[d] = om ? om[10 * i + d] : 0.0;
     double loc[3];
     for (int d = 0; d < 3; d++) {
-        double v = pos[3 * (int64_t)i + d], xw = 0;
-        if (isfinite(v)) leaf_coord(v, rB, edge, w, nside, &xw);
-        else xw = v;
-        loc[d] = xw - (-rB + (ix[d] + 0.5) * w);
+        const double v = p[d];
+        double xw = v;
+        const int ix = isfinite(v) ? leaf_coord(v, rB, edge, w, nside, &xw) : 0;
+        loc[d] = xw - (-rB + (ix + 0.5) * w);
     }
     P.x[s] = loc[0];
     P.y[s] = loc[1];
     P.z[s] = loc[2];
-    const double qi = q[i];
     P.q[s] = qi;
-    if (mixed) P.qf[s] = (float)qi;
+    if constexpr (MIXED) P.qf[s] = (float)qi;
     bool fin = true;
-    if (planned_order >= 1) {
+    if constexpr (ORD >= 1) {
         for (int d = 0; d < 3; d++) {
-            double v = mu ? mu[3 * (int64_t)i + d] : 0.0;
-            fin = fin && isfinite(v);
-            P.mu[d * n + s] = v;
-            if (mixed) P.muf[d * n + s] = (float)v;
+            fin = fin && isfinite(m[d]);
+            P.mu[d * n + s] = m[d];
+            if constexpr (MIXED) P.muf[d * n + s] = (float)m[d];
         }
     }
-    if (planned_order >= 2) {
-        double t[6];
+    if constexpr (ORD >= 2) {
         for (int d = 0; d < 6; d++) {
-            double v = th ? th[6 * (int64_t)i + d] : 0.0;
-            fin = fin && isfinite(v);
-            t[d] = v;
-            P.th[d * n + s] = v;
-            if (mixed) P.thf[d * n + s] = (float)v;
+            fin = fin && isfinite(t[d]);
+            P.th[d * n + s] = t[d];
+            if constexpr (MIXED) P.thf[d * n + s] = (float)t[d];
         }
         const double tr = t[0] + t[3] + t[5], mx = fmax(fabs(t[0]), fmax(fabs(t[3]), fabs(t[5])));
         if (fabs(tr) > 1e-6 * (1.0 + mx)) err[1] = 1;
     }
-    if (planned_order >= 3) {
-        double o[10];
+    if constexpr (ORD >= 3) {
         for (int d = 0; d < 10; d++) {
-            double v = om ? om[10 * (int64_t)i + d] : 0.0;
-            fin = fin && isfinite(v);
-            o[d] = v;
-            P.om[d * n + s] = v;
-            if (mixed) P.omf[d * n + s] = (float)v;
+            fin = fin && isfinite(o[d]);
+            P.om[d * n + s] = o[d];
+            if constexpr (MIXED) P.omf[d * n + s] = (float)o[d];
         }
         // the three traces Omega_aab (b = x, y, z) must vanish
         double mx = 0;
@@ -994,7 +1002,12 @@ hipError_t launch_sort(ankh_plan_s *pl, const double *pos, const double *q, cons
     hipStream_t s = pl->stream;
     const double w = pl->edge / pl->nside;
     hipError_t e;
-    if ((e = launch_zero_i32(pl->d_count, pl->nleaf, s)) != hipSuccess) return e;
+    // the scan leaves the counts at zero; they are cleared here only at the first binning of a plan or
+    // after a binning whose launches failed
+    if (pl->count_dirty) {
+        if ((e = launch_zero_i32(pl->d_count, pl->nleaf, s)) != hipSuccess) return e;
+        pl->count_dirty = false;
+    }
     hipLaunchKernelGGL(k_bin, dim3(nblk(pl->n, 256)), dim3(256), 0, s, pl->n, pos, q, pl->rB, pl->edge, w,
                        pl->nside, pl->d_leaf, pl->d_count, pl->d_rank, pl->d_err);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, pl->d_count, pl->d_offs, pl->nleaf);
@@ -1002,15 +1015,25 @@ hipError_t launch_sort(ankh_plan_s *pl, const double *pos, const double *q, cons
                        pl->d_rank, pl->d_tmp);
     hipLaunchKernelGGL(k_segsort, dim3((unsigned)((pl->nleaf + 3) / 4)), dim3(256), 0, s, pl->d_offs, pl->d_tmp,
                        pl->d_perm, pl->nleaf);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) pl->count_dirty = true;
+    return e;
 }
 
 hipError_t launch_gather(ankh_plan_s *pl, const double *pos, const double *q, const double *mu, const double *th,
                          const double *om) {
     const double w = pl->edge / pl->nside;
-    hipLaunchKernelGGL(k_gather, dim3(nblk(pl->n, 256)), dim3(256), 0, pl->stream, pl->n, pl->d_perm, pl->d_leaf,
-                       pos, q, mu, th, om, pl->rB, pl->edge, w, pl->nside, pl->P, pl->max_order,
-                       is_mixed(pl) ? 1 : 0, pl->d_err);
+    const bool mixed = is_mixed(pl);
+#define ANKH_GATHER(O, M)                                                                                           \
+    hipLaunchKernelGGL((k_gather<O, M>), dim3(nblk(pl->n, 256)), dim3(256), 0, pl->stream, pl->n, pl->d_perm, pos, \
+                       q, mu, th, om, pl->rB, pl->edge, w, pl->nside, pl->P, pl->d_err)
+    switch (pl->max_order) {
+        case 0: if (mixed) ANKH_GATHER(0, true); else ANKH_GATHER(0, false); break;
+        case 1: if (mixed) ANKH_GATHER(1, true); else ANKH_GATHER(1, false); break;
+        case 2: if (mixed) ANKH_GATHER(2, true); else ANKH_GATHER(2, false); break;
+        default: if (mixed) ANKH_GATHER(3, true); else ANKH_GATHER(3, false); break;
+    }
+#undef ANKH_GATHER
     return hipGetLastError();
 }
 
