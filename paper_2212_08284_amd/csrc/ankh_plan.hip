@@ -48,6 +48,28 @@ void dalloc(ankh_plan_s *pl, T **p, size_t count) {
     pl->bytes += count * sizeof(T);
 }
 
+// plan-time device scratch (not counted in the plan's bytes): released explicitly, or when a failure
+// unwinds the plan's construction
+struct Scratch {
+    double *p = nullptr;
+    void alloc(size_t count) {
+        if (hipMalloc((void **)&p, count * sizeof(double)) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            throw std::bad_alloc();
+        }
+    }
+    void release() {
+        if (!p) return;
+        const hipError_t e = hipFree(p);
+        p = nullptr;
+        ck(e);
+    }
+    ~Scratch() {
+        if (p) (void)hipFree(p);
+    }
+};
+
 void free_all(ankh_plan_s *pl) {
     void *ptrs[] = {pl->d_tab, pl->d_leaf, pl->d_count, pl->d_offs, pl->d_rank, pl->d_perm, pl->d_tmp,
                     pl->P.x, pl->P.y, pl->P.z, pl->P.q, pl->P.mu, pl->P.th, pl->P.qf, pl->P.muf, pl->P.thf,
@@ -571,15 +593,16 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
             }
             // scratch: the operators of the 16 symmetry classes and the full float64 stack of a level,
             // and room for the compression's intermediate products or the compressed float64 stack
-            double *tmp = nullptr, *work = nullptr, *kc = nullptr, *reps = nullptr;
+            Scratch s_tmp, s_work, s_kc, s_reps;
             const size_t ntmp = 1 + (compress ? 1 : 0) + (compress && precision != ANKH_FP64 ? 1 : 0);
             const size_t nreps = m2l_reps_elems(pl);
             if (pl->bytes_limit && pl->bytes + (ntmp * kper + nreps) * sizeof(double) > pl->bytes_limit)
                 throw std::bad_alloc();
-            ck(hipMalloc((void **)&tmp, kper * sizeof(double)));
-            ck(hipMalloc((void **)&reps, nreps * sizeof(double)));
-            if (compress) ck(hipMalloc((void **)&work, kper * sizeof(double)));
-            if (compress && precision != ANKH_FP64) ck(hipMalloc((void **)&kc, kper * sizeof(double)));
+            s_tmp.alloc(kper);
+            s_reps.alloc(nreps);
+            if (compress) s_work.alloc(kper);
+            if (compress && precision != ANKH_FP64) s_kc.alloc(kper);
+            double *tmp = s_tmp.p, *work = s_work.p, *kc = s_kc.p, *reps = s_reps.p;
             for (int e = 1; e <= pl->depth; e++) {
                 const size_t slot = (size_t)(e - 1) * kper;
                 ck(launch_build_m2l(pl, e, tmp, reps));
@@ -601,10 +624,10 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
                 }
                 ck(hipStreamSynchronize(pl->stream));
             }
-            ck(hipFree(tmp));
-            ck(hipFree(reps));
-            if (work) ck(hipFree(work));
-            if (kc) ck(hipFree(kc));
+            s_tmp.release();
+            s_reps.release();
+            s_work.release();
+            s_kc.release();
             // compressed multipoles / locals of the compressed levels
             size_t coff = 0;
             for (int e = 1; e <= pl->depth; e++) {
@@ -663,11 +686,12 @@ ankh_status ankh_plan(ankh_plan_t *out, int64_t n_atoms, double box_radius, doub
                 ck(hipMemcpy(pl->d_fftTw32, tw32.data(), tw32.size() * sizeof(float2), hipMemcpyHostToDevice));
                 ck(launch_fft_D_to_f32(pl));
                 ck(hipStreamSynchronize(pl->stream));
-                ck(hipFree(pl->d_fftX));
-                ck(hipFree(pl->d_fftD));
-                pl->d_fftX = nullptr;
+                const hipError_t ex = hipFree(pl->d_fftX), ed = hipFree(pl->d_fftD);
+                pl->d_fftX = nullptr;   // never freed twice, even when a free reports an error
                 pl->d_fftD = nullptr;
                 pl->bytes -= nx * (sizeof(double2) + sizeof(double));
+                ck(ex);
+                ck(ed);
                 dalloc(pl, &pl->d_fftX32, nx);
             }
         } else {
