@@ -328,9 +328,15 @@ def test_latched_input_errors(ak):
     with pytest.raises(ak.AnkhError) as ei:
         pl.sync()
     assert ei.value.status == 3
-    # the latch is cleared: a clean call syncs fine
-    pl.energy(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
+    # the latch is cleared: a clean call syncs fine, and nothing of the failed calls (the leaf counts
+    # of the binning included) is left in the plan: it gives a fresh plan's energy bit for bit
+    e_reused = pl.energy(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
     pl.sync()
+    fresh = ak.Plan(n, 0.5 * d["edge"], 1e-5, 2, "fp64", far="fmm")
+    e_fresh = fresh.energy(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
+    fresh.sync()
+    assert e_reused.item() == e_fresh.item()
+    fresh.close()
     # host-checked: a quadrupole array on a charges-only plan
     pq = ak.Plan(n, 0.5 * d["edge"], 1e-5, 0, "fp64", far="fmm")
     with pytest.raises(ak.AnkhError) as ei:
@@ -338,6 +344,32 @@ def test_latched_input_errors(ak):
     assert ei.value.status == 1
     pl.close()
     pq.close()
+
+
+@pytest.mark.parametrize("far,prec", [("fft", "mixed_bf16x3"), ("fft", "fp64"), ("fmm", "mixed")])
+def test_plan_reuse_after_nonfinite_input(ak, far, prec):
+    """An evaluation with a non-finite position bins that atom into leaf 0 and reports the error; the
+    next clean evaluation on the same plan equals a fresh plan's, energy, forces and fields, bit for
+    bit (the binning's leaf counts are cleared by every evaluation, failed ones included)."""
+    d = synth.water(300, seed=21)
+    n = len(d["q"])
+    args = (n, 0.5 * d["edge"], 1e-6, 2, prec)
+    pl = ak.Plan(*args, far=far)
+    pos = d["pos"].copy()
+    pos[7, 2] = np.inf
+    pl.energy_forces(T(pos), T(d["q"]), T(d["mu"]), T(d["theta"]))
+    with pytest.raises(ak.AnkhError) as ei:
+        pl.sync()
+    assert ei.value.status == 2
+    e1, F1, G1 = pl.energy_forces(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
+    pl.sync()
+    fresh = ak.Plan(*args, far=far)
+    e2, F2, G2 = fresh.energy_forces(T(d["pos"]), T(d["q"]), T(d["mu"]), T(d["theta"]))
+    fresh.sync()
+    assert e1.item() == e2.item()
+    assert torch.equal(F1, F2) and torch.equal(G1, G2)
+    pl.close()
+    fresh.close()
 
 
 def test_water_288000_sampled_vs_oracle(ak):
